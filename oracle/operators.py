@@ -1,0 +1,141 @@
+"""Oracle: graph -> walk operators (H, Lindblad rates, superoperator), dense.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import this file.
+
+Everything here is plain dense numpy in float64/complex128, written to be
+checked against the paper by eye:
+
+* ``transition_matrix``   - eq. generator_matrix (Section 2.2): M_ij = -gamma G_ij
+  for i != j, M_jj = gamma OutDeg(j), OutDeg(v_j) = sum_i G_ij (eq. out_degree).
+* ``undirected``          - G^u_ij = max(G_ij, G_ji) (Section 2.1).
+* ``walk_operators``      - H and the Lindblad operators of the L-QSW
+  (Section 2.4.1, eq. lindblad): L_k = sqrt(|M_ij|) |v_i><v_j|.
+* ``lindblad_ops``        - the explicit list of L_k matrices.
+* ``superop_kron``        - the vectorised generator of eq. qsw built literally
+  from the Kronecker mappings of eq. vec_mappings with column stacking
+  (vec(XYZ) = (Z^T kron X) vec(Y)), one explicit L_k at a time.
+
+Conventions (readings of the paper, listed in the design notes):
+* G[i, j] is the weight of the arc j -> i (row = target, column = source).
+* ``h_mode``: "laplacian" -> H = transition matrix of G^u (= weighted graph
+  Laplacian for gamma = 1); "adjacency" -> H = G^u (used by the paper's
+  three-vertex example, which passes H = GU).
+* ``r_mode``: "transition" -> L_k = sqrt(gamma G_ij) |i><j| for every arc;
+  "colnorm" -> the column-normalised transition matrix, L_k = sqrt(G_ij /
+  OutDeg(j)) |i><j| (eq. markov_chain rates).
+* ``dephasing``: also keep the diagonal L_k = sqrt(|M_jj|) |j><j| that the
+  sum over all N^2 indices k of eq. qsw contains.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def undirected(G: np.ndarray) -> np.ndarray:
+    return np.maximum(G, G.T)
+
+
+def out_degree(G: np.ndarray) -> np.ndarray:
+    """OutDeg(v_j) = sum over i of G_ij (column sums)."""
+    return G.sum(axis=0)
+
+
+def transition_matrix(gamma: float, G: np.ndarray) -> np.ndarray:
+    """eq. generator_matrix: off-diagonal -gamma G_ij, diagonal gamma OutDeg(j)."""
+    N = G.shape[0]
+    M = -gamma * G.astype(np.float64)
+    M[np.arange(N), np.arange(N)] = gamma * out_degree(G)
+    return M
+
+
+def colnorm_transition_matrix(G: np.ndarray) -> np.ndarray:
+    """CTRW transition matrix with unit total outflow from every vertex that
+    has out-arcs: off-diagonal -G_ij / OutDeg(j), diagonal 1 (0 for sinks)."""
+    N = G.shape[0]
+    od = out_degree(G)
+    M = np.zeros((N, N))
+    for j in range(N):
+        if od[j] > 0:
+            M[:, j] = -G[:, j] / od[j]
+            M[j, j] = 1.0
+    return M
+
+
+def walk_operators(G: np.ndarray, h_mode: str = "laplacian",
+                   r_mode: str = "transition", dephasing: bool = False,
+                   gamma: float = 1.0):
+    """Return (H, ML) with H real symmetric N x N and ML the condensed
+    Lindblad matrix (eq. condensed_lindblads): ML_ij = sqrt(|M_ij|) for every
+    (i, j) that carries an L_k."""
+    G = np.asarray(G, dtype=np.float64)
+    N = G.shape[0]
+    if np.any(np.diag(G) != 0):
+        raise ValueError("simple graphs only (Tr G = 0)")
+    if np.any(G < 0):
+        raise ValueError("weights must be positive")
+    Gu = undirected(G)
+    if h_mode == "laplacian":
+        H = transition_matrix(gamma, Gu)
+    elif h_mode == "adjacency":
+        H = Gu.copy()
+    else:
+        raise ValueError(h_mode)
+    if r_mode == "transition":
+        M = transition_matrix(gamma, G)
+    elif r_mode == "colnorm":
+        M = colnorm_transition_matrix(G)
+    else:
+        raise ValueError(r_mode)
+    ML = np.sqrt(np.abs(M))
+    if not dephasing:
+        ML[np.arange(N), np.arange(N)] = 0.0
+    return H, ML
+
+
+def lindblad_ops(ML: np.ndarray):
+    """The explicit list of L_k = ML_ij |v_i><v_j| for every nonzero ML_ij,
+    k = N(j-1)+i order (column-major over (i, j))."""
+    N = ML.shape[0]
+    ops = []
+    for j in range(N):
+        for i in range(N):
+            if ML[i, j] != 0:
+                L = np.zeros((N, N), np.complex128)
+                L[i, j] = ML[i, j]
+                ops.append(L)
+    return ops
+
+
+def superop_kron(H: np.ndarray, ML: np.ndarray, omega: float) -> np.ndarray:
+    """Dense N^2 x N^2 generator of eq. qsw acting on the COLUMN-STACKED
+    vec(rho) (index i + N j <-> rho_ij), from eq. vec_mappings:
+
+      -i(1-omega) (I kron H - H^T kron I)
+      + omega sum_k [ conj(L_k) kron L_k
+                      - 1/2 (I kron L_k^dag L_k + (L_k^dag L_k)^T kron I) ]
+    """
+    N = H.shape[0]
+    I = np.eye(N)
+    Hc = np.asarray(H, dtype=np.complex128)
+    S = -1j * (1.0 - omega) * (np.kron(I, Hc) - np.kron(Hc.T, I))
+    for L in lindblad_ops(ML):
+        LdL = L.conj().T @ L
+        S = S + omega * (np.kron(L.conj(), L)
+                         - 0.5 * (np.kron(I, LdL) + np.kron(LdL.T, I)))
+    return S
+
+
+def colstack_to_rowmajor(N: int) -> np.ndarray:
+    """perm[r] = column-stacked index of the row-major index r = a N + b,
+    i.e. rho_ab: rowmajor a N + b  <->  colstack a + N b."""
+    r = np.arange(N * N)
+    a, b = r // N, r % N
+    return a + N * b
+
+
+def superop_kron_rowmajor(H, ML, omega) -> np.ndarray:
+    """superop_kron permuted to act on the row-major vec(rho) (index a N + b)."""
+    N = H.shape[0]
+    S = superop_kron(H, ML, omega)
+    p = colstack_to_rowmajor(N)
+    return S[np.ix_(p, p)]
