@@ -1,0 +1,206 @@
+/*
+ * qsw.h - C ABI of libqsw: L-QSW (locally interacting quantum stochastic
+ * walk) propagation on one AMD MI355X (gfx950) GPU.
+ *
+ * The library builds the vectorised Lindblad superoperator L of a walk on a
+ * graph (Section 2.4.1 eq. qsw, vectorised by eq. vec_mappings) as a
+ * complex128 CSR matrix in device memory, and evaluates
+ *     rho(t_k) = unvec( exp(t_k L) vec(rho0) ),  t_k = t0 + k dt,
+ * by the truncated-Taylor method with scaling and early termination that the
+ * paper adopts (Section 3.1: Al-Mohy and Higham's single-time algorithm,
+ * `step`, and time-series algorithm, `series`), without balancing or shift.
+ *
+ * Conventions
+ *   - Graphs: CSR of the N x N adjacency G with G[i][j] = weight of the arc
+ *     from source vertex j to target vertex i (row = target, column =
+ *     source), weights > 0, no diagonal (simple graphs, Section 2.1).
+ *   - Density matrices are complex128 (interleaved re, im doubles), N x N,
+ *     ROW-MAJOR: element (a, b) at index a*N + b.  The superoperator acts on
+ *     this row-major vec.  (The paper stacks columns; the two orders differ
+ *     by a fixed permutation and give the same rho.)
+ *   - Every pointer documented "device" must be memory of the device that
+ *     was current when the handle was built; "host" pointers are ordinary
+ *     CPU memory.  Host arrays are only read during the call.
+ *   - `hip_stream` is a hipStream_t (NULL = the default stream).  All device
+ *     work of a call is enqueued on it; calls return before it completes
+ *     unless stated otherwise.  Caller-owned device buffers must stay alive
+ *     until the stream has finished the call's work.
+ *   - Errors are returned as qsw_status_t; nothing aborts or throws across
+ *     the ABI.  Argument and graph checks are synchronous.  Device faults and
+ *     non-finite values surface through qsw_last_stats.
+ */
+#ifndef QSW_H
+#define QSW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qsw_superop_s *qsw_superop_t;
+
+typedef enum {
+    QSW_OK = 0,
+    QSW_ERR_ARG = 1,        /* bad argument (null pointer, omega outside [0,1], sizes) */
+    QSW_ERR_GRAPH = 2,      /* malformed graph CSR (self-loop, w <= 0, unsorted, duplicate, out of range) */
+    QSW_ERR_OOM = 3,        /* device allocation failed */
+    QSW_ERR_DEVICE = 4,     /* HIP runtime error (launch, copy, no device) */
+    QSW_ERR_NONFINITE = 5,  /* a norm or value was NaN or infinite */
+    QSW_ERR_STATE = 6,      /* handle used on another device, or workspace too small */
+    QSW_ERR_SIZE = 7        /* N*N does not fit the 32-bit column index (N > 46340) */
+} qsw_status_t;
+
+/* Build flags (bitwise OR). */
+enum {
+    QSW_H_LAPLACIAN = 0,    /* H = transition matrix of G^u (eq. generator_matrix on the
+                               undirected companion, Section 2.4.1): the weighted Laplacian for gamma = 1 */
+    QSW_H_ADJACENCY = 1,    /* H = G^u itself (the paper's three-vertex example passes H = GU) */
+    QSW_R_TRANSITION = 0,   /* L_k = sqrt(gamma G_ij)|i><j| for every arc (eq. lindblad) */
+    QSW_R_COLNORM = 2,      /* L_k = sqrt(G_ij / OutDeg(j))|i><j| (column-normalised rates) */
+    QSW_DEPHASING = 4       /* also the diagonal L_k = sqrt(|M_jj|)|j><j| that eq. qsw sums over */
+};
+
+/* Precision of the tolerance used for theta_m and the stopping test. */
+enum { QSW_PREC_DOUBLE = 0 /* u = 2^-53 */, QSW_PREC_SINGLE = 1 /* u = 2^-24 */ };
+
+typedef struct {
+    int32_t N;           /* graph order */
+    int64_t n;           /* superoperator dimension N*N */
+    int64_t nnz;         /* stored entries of L (explicit zeros kept: pattern independent of omega) */
+    double omega;
+    double norm1;        /* ||L||_1, exact (max column sum) */
+    double d[10];        /* d[p] = estimate of ||L^p||_1^(1/p), p = 2..9 (d[0] = d[1] = norm1) */
+    int64_t d_index[10]; /* column e_j whose image attains the estimate of ||L^p||_1, or -1 when
+                            the estimate came from the first (non-unit) probe block */
+    int32_t d_probe[10]; /* for d_index == -1: which probe column (0 = all-ones/n, 1 = +-1/n) */
+    int32_t norm_products; /* sparse products spent on the estimates */
+    double build_ms;     /* host wall time of the build call, including device sync */
+} qsw_info_t;
+
+typedef struct {
+    int32_t branch;      /* 0: one single-time application per interval (q <= s);
+                            1: time-series blocks with stored powers (q > s) */
+    int32_t m;           /* Taylor degree used for each interval (branch 0) or block (branch 1) */
+    int32_t s;           /* scaling steps per interval (branch 0) or for the whole span (branch 1) */
+    int32_t m0, s0;      /* parameters of the exp(t0 L) start, 0/1 when t0 = 0 */
+    int64_t launched;    /* sparse-product kernels enqueued */
+    int64_t products;    /* sparse products actually computed (early termination skips the rest) */
+    int32_t nonfinite;   /* 1 if any norm in the run was NaN or infinite */
+    double ms;           /* device time of the last propagate call (events on its stream) */
+    double bytes;        /* algorithmic HBM bytes of the computed products (see design notes) */
+} qsw_stats_t;
+
+/* ---------------------------------------------------------------- build */
+
+/*
+ * Build the L-QSW superoperator of a graph (Section 2.4.1; H from G^u,
+ * L_k from the CTRW transition matrix of G, eq. generator_matrix and eq.
+ * lindblad), assemble it in device CSR (int64 row_ptr, int32 columns sorted
+ * within each row, complex128 values), compute ||L||_1 exactly and estimate
+ * ||L^p||_1, p = 2..9 (the 1-norm series the paper computes at construction,
+ * Section 4 footnote).
+ *
+ *   N, row_ptr[N+1], col_idx[nnz], w[nnz]: host CSR of G (see Conventions).
+ *   omega in [0, 1]; gamma > 0 (system-wide transition rate).
+ *   flags: QSW_H_*, QSW_R_*, QSW_DEPHASING.
+ *   *out receives a handle owning the device CSR; free with qsw_superop_destroy.
+ * Synchronises `hip_stream` before returning.
+ */
+qsw_status_t qsw_superop_build(int32_t N, const int64_t *row_ptr, const int32_t *col_idx,
+                               const double *w, double omega, double gamma, uint32_t flags,
+                               void *hip_stream, qsw_superop_t *out);
+
+/*
+ * Build from explicit operators, as the paper's LQSW(omega, H, M_L) does
+ * (Section 4): H is a Hermitian N x N host CSR (complex128 values,
+ * interleaved; it may hold a diagonal; its pattern must be symmetric), M_L
+ * the condensed Lindblad matrix (eq. condensed_lindblads) as a real host CSR:
+ * each entry (i, j) is one L_k = M_L[i][j] |i><j| (rates |M_L[i][j]|^2;
+ * diagonal entries are dephasing channels).  Columns sorted, no duplicates.
+ * flags: 0.  Synchronises `hip_stream`.
+ */
+qsw_status_t qsw_superop_build_ops(int32_t N,
+                                   const int64_t *h_row_ptr, const int32_t *h_col,
+                                   const double *h_val,
+                                   const int64_t *l_row_ptr, const int32_t *l_col,
+                                   const double *l_val,
+                                   double omega, uint32_t flags, void *hip_stream,
+                                   qsw_superop_t *out);
+
+void qsw_superop_destroy(qsw_superop_t h);
+
+qsw_status_t qsw_superop_info(qsw_superop_t h, qsw_info_t *info);
+
+/* Copy the device CSR to caller host buffers (row_ptr[n+1], col[nnz],
+ * val[2*nnz] doubles).  Any pointer may be NULL to skip it.  Synchronous. */
+qsw_status_t qsw_superop_copy_csr(qsw_superop_t h, int64_t *row_ptr, int32_t *col,
+                                  double *val);
+
+/* ------------------------------------------------------------ propagate */
+
+/* Device workspace (bytes) that qsw_propagate needs for these arguments. */
+size_t qsw_propagate_workspace_bytes(qsw_superop_t h, double t0, double dt, int32_t n_steps);
+
+/*
+ * out[k] = rho(t0 + k dt) = unvec(exp((t0 + k dt) L) vec(rho0)), k = 0..n_steps
+ * (the paper's `series(t1 = t0, tq = t0 + n_steps dt, steps = n_steps)`;
+ * n_steps = 1, t0 = 0 is its `step(dt)`).
+ *
+ *   rho0: device, N*N complex128, row-major; read only.
+ *   out:  device, (n_steps+1) * N*N complex128; out[0] = exp(t0 L) rho0.
+ *         Must not overlap rho0.
+ *   workspace: device, >= qsw_propagate_workspace_bytes(...) bytes, 256-byte
+ *         aligned; its contents on entry are ignored.
+ *   n_steps >= 0; dt and t0 finite.
+ * Enqueues everything on `hip_stream` and returns; no device memory is
+ * allocated.  Concurrent calls on one handle need distinct workspaces and
+ * outputs; qsw_last_stats then reports whichever call finished last.
+ */
+qsw_status_t qsw_propagate(qsw_superop_t h, const void *rho0, double t0, double dt,
+                           int32_t n_steps, void *out, void *workspace, size_t ws_bytes,
+                           void *hip_stream);
+
+/* Statistics of the last qsw_propagate on this handle (waits for it). */
+qsw_status_t qsw_last_stats(qsw_superop_t h, qsw_stats_t *st);
+
+/* ------------------------------------------------------------- helpers */
+
+/* y = L x (device complex128 vectors of length n).  Enqueued on the stream. */
+qsw_status_t qsw_apply(qsw_superop_t h, const void *x, void *y, void *hip_stream);
+
+/* pops[k*N + a] = Re rho_k[a][a] for k < count (the paper's
+ * gather_populations).  rho: device count*N*N complex128; pops: device
+ * count*N doubles.  Enqueued on the stream. */
+qsw_status_t qsw_populations(qsw_superop_t h, const void *rho, int32_t count, void *pops,
+                             void *hip_stream);
+
+/* ------------------------------------------- host-only (no GPU needed) */
+
+/* theta_m (1 <= m <= 55) of the truncated-Taylor backward-error bound,
+ * computed by the library from its definition; prec = QSW_PREC_*.
+ * Returns a negative value for a bad argument. */
+double qsw_theta(int32_t m, int32_t prec);
+
+/*
+ * Taylor degree m and scaling s for exp(t L) from ||L||_1 and d[p], p = 2..9
+ * (d may be NULL: the 1-norm alone is used), n0 right-hand sides, tolerance
+ * prec.  The rule is Al-Mohy and Higham's (cited in Section 3.1): the 1-norm
+ * choice when ||tL||_1 is small, else the minimum of m * ceil(alpha_p / theta_m)
+ * over 2 <= p <= 8, p(p-1)-1 <= m <= 55, alpha_p = t max(d_p, d_{p+1});
+ * smallest m on ties; t||L||_1 = 0 gives m = 0, s = 1.
+ */
+qsw_status_t qsw_select_params(double norm1, const double *d, double t, int32_t n0,
+                               int32_t prec, int32_t *m, int32_t *s);
+
+const char *qsw_status_str(qsw_status_t s);
+
+/* Library version string. */
+const char *qsw_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QSW_H */

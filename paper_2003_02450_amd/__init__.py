@@ -1,0 +1,250 @@
+"""L-QSW propagation on one MI355X: thin Python binding of libqsw.
+
+Every step of the walk runs in the HIP kernels of ``libqsw.so`` (built from
+``csrc/`` by ``python -m paper_2003_02450_amd.build``); this module only
+marshals arguments.  PyTorch provides the device memory (complex128 tensors)
+and the stream.
+
+    op = Superop.from_graph(N, row_ptr, col_idx, w, omega=0.5)
+    rho = op.propagate(rho0, t0=0.0, dt=1.0, n_steps=50)   # [51, N, N]
+
+mirrors the paper's ``LQSW(omega, H, M_L)`` + ``series`` (Section 4);
+``step(rho0, t)`` is ``step``; ``populations(rho)`` is
+``gather_populations``.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import QswError  # noqa: F401
+
+__all__ = ["Superop", "QswError", "theta", "select_params", "library_path"]
+
+library_path = _lib.LIB_PATH
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream(device):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def theta(m: int, single: bool = False) -> float:
+    """theta_m of the Taylor backward-error bound (host-only library call)."""
+    return float(_lib.load().qsw_theta(int(m), _lib.QSW_PREC_SINGLE if single else
+                                       _lib.QSW_PREC_DOUBLE))
+
+
+def select_params(norm1: float, d=None, t: float = 1.0, n0: int = 1, single: bool = False):
+    """(m, s) for exp(t L) from ||L||_1 and d[p] = ||L^p||_1^(1/p), p = 2..9
+    (host-only library call; ``d`` indexable by p, or None)."""
+    L = _lib.load()
+    darr = None
+    if d is not None:
+        darr = np.zeros(10, np.float64)
+        for p in range(2, 10):
+            darr[p] = float(d[p])
+    m, s = ctypes.c_int32(), ctypes.c_int32()
+    st = L.qsw_select_params(float(norm1), None if darr is None else _ptr(darr), float(t),
+                             int(n0), _lib.QSW_PREC_SINGLE if single else _lib.QSW_PREC_DOUBLE,
+                             ctypes.byref(m), ctypes.byref(s))
+    _lib.check(st, "qsw_select_params")
+    return m.value, s.value
+
+
+class Superop:
+    """Device-resident L-QSW superoperator (CSR) plus its 1-norm series."""
+
+    def __init__(self, handle, device):
+        self._h = handle
+        self.device = device
+        info = _lib.Info()
+        _lib.check(_lib.load().qsw_superop_info(self._h, ctypes.byref(info)), "qsw_superop_info")
+        self.N = info.N
+        self.n = info.n
+        self.nnz = info.nnz
+        self.omega = info.omega
+        self._info = info
+
+    # ------------------------------------------------------------ builders
+    @classmethod
+    def from_graph(cls, N, row_ptr, col_idx, w, omega, gamma=1.0, h_mode="laplacian",
+                   r_mode="transition", dephasing=False, device=None):
+        """Graph CSR (row = target, column = source, w > 0) -> superoperator."""
+        torch = _torch()
+        L = _lib.load()
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        flags = 0
+        if h_mode == "adjacency":
+            flags |= _lib.QSW_H_ADJACENCY
+        elif h_mode != "laplacian":
+            raise ValueError(h_mode)
+        if r_mode == "colnorm":
+            flags |= _lib.QSW_R_COLNORM
+        elif r_mode != "transition":
+            raise ValueError(r_mode)
+        if dephasing:
+            flags |= _lib.QSW_DEPHASING
+        rp = np.ascontiguousarray(row_ptr, np.int64)
+        ci = np.ascontiguousarray(col_idx, np.int32)
+        ww = np.ascontiguousarray(w, np.float64)
+        if rp.shape != (int(N) + 1,):
+            raise ValueError("row_ptr must have N+1 entries")
+        h = ctypes.c_void_p()
+        with torch.cuda.device(dev):
+            st = L.qsw_superop_build(int(N), _ptr(rp), _ptr(ci), _ptr(ww), float(omega),
+                                     float(gamma), flags, _stream(dev), ctypes.byref(h))
+        _lib.check(st, "qsw_superop_build")
+        return cls(h, dev)
+
+    @classmethod
+    def from_workload_graph(cls, graph, omega, **kw):
+        return cls.from_graph(graph.N, graph.row_ptr, graph.col_idx, graph.w, omega, **kw)
+
+    @classmethod
+    def from_operators(cls, H, ML, omega, device=None):
+        """The paper's LQSW(omega, H, M_L): Hermitian H and condensed Lindblad
+        matrix M_L (each entry one L_k), given as scipy sparse or dense."""
+        torch = _torch()
+        import scipy.sparse as sp
+        L = _lib.load()
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        Hc = sp.csr_matrix(H, dtype=np.complex128)
+        Hc.sort_indices()
+        Mc = sp.csr_matrix(ML, dtype=np.float64)
+        Mc.sort_indices()
+        N = Hc.shape[0]
+        hp = np.ascontiguousarray(Hc.indptr, np.int64)
+        hc = np.ascontiguousarray(Hc.indices, np.int32)
+        hv = np.ascontiguousarray(Hc.data, np.complex128).view(np.float64)
+        lp = np.ascontiguousarray(Mc.indptr, np.int64)
+        lc = np.ascontiguousarray(Mc.indices, np.int32)
+        lv = np.ascontiguousarray(Mc.data, np.float64)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(dev):
+            st = L.qsw_superop_build_ops(int(N), _ptr(hp), _ptr(hc), _ptr(hv), _ptr(lp), _ptr(lc),
+                                         _ptr(lv), float(omega), 0, _stream(dev), ctypes.byref(h))
+        _lib.check(st, "qsw_superop_build_ops")
+        return cls(h, dev)
+
+    # ------------------------------------------------------------- queries
+    def info(self) -> dict:
+        i = self._info
+        return {"N": i.N, "n": i.n, "nnz": i.nnz, "omega": i.omega, "norm1": i.norm1,
+                "d": {p: i.d[p] for p in range(2, 10)},
+                "d_index": {p: i.d_index[p] for p in range(2, 10)},
+                "d_probe": {p: i.d_probe[p] for p in range(2, 10)},
+                "norm_products": i.norm_products, "build_ms": i.build_ms}
+
+    def csr(self):
+        """Host copies (row_ptr int64, col int32, val complex128)."""
+        rp = np.empty(self.n + 1, np.int64)
+        col = np.empty(self.nnz, np.int32)
+        val = np.empty(self.nnz, np.complex128)
+        st = _lib.load().qsw_superop_copy_csr(self._h, _ptr(rp), _ptr(col),
+                                              _ptr(val.view(np.float64)))
+        _lib.check(st, "qsw_superop_copy_csr")
+        return rp, col, val
+
+    def workspace_bytes(self, t0, dt, n_steps) -> int:
+        return int(_lib.load().qsw_propagate_workspace_bytes(self._h, float(t0), float(dt),
+                                                             int(n_steps)))
+
+    # ---------------------------------------------------------- evolution
+    def _as_device_state(self, rho0):
+        torch = _torch()
+        if not torch.is_tensor(rho0):
+            rho0 = torch.from_numpy(np.ascontiguousarray(rho0, np.complex128))
+        rho0 = rho0.to(device=self.device, dtype=torch.complex128).contiguous()
+        if tuple(rho0.shape) not in ((self.N, self.N), (self.n,)):
+            raise ValueError(f"rho0 must be {self.N} x {self.N}")
+        return rho0
+
+    def propagate(self, rho0, t0=0.0, dt=1.0, n_steps=1, out=None, workspace=None):
+        """rho(t0 + k dt), k = 0..n_steps, as a [n_steps+1, N, N] complex128
+        tensor on the device (enqueued on the current stream)."""
+        torch = _torch()
+        L = _lib.load()
+        rho0 = self._as_device_state(rho0)
+        if out is None:
+            out = torch.empty((n_steps + 1, self.N, self.N), dtype=torch.complex128,
+                              device=self.device)
+        if out.dtype != torch.complex128 or not out.is_contiguous() or \
+                out.numel() < (n_steps + 1) * self.n:
+            raise ValueError("out must be a contiguous complex128 tensor of "
+                             "(n_steps+1) N^2 elements")
+        ws = self.workspace_bytes(t0, dt, n_steps)
+        if ws == 0:
+            raise QswError(1, "qsw_propagate_workspace_bytes")
+        if workspace is None or workspace.numel() < ws + 256:
+            workspace = torch.empty(ws + 256, dtype=torch.uint8, device=self.device)
+        base = workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        with torch.cuda.device(self.device):
+            st = L.qsw_propagate(self._h, ctypes.c_void_p(rho0.data_ptr()), float(t0), float(dt),
+                                 int(n_steps), ctypes.c_void_p(out.data_ptr()),
+                                 ctypes.c_void_p(aligned), ws, _stream(self.device))
+        _lib.check(st, "qsw_propagate")
+        self._keep = (rho0, workspace)  # alive until the stream has used them
+        return out
+
+    def step(self, rho0, t):
+        """rho(t) = exp(t L) rho0 (the paper's `step`)."""
+        return self.propagate(rho0, 0.0, float(t), 1)[1]
+
+    def last_stats(self) -> dict:
+        s = _lib.Stats()
+        st = _lib.load().qsw_last_stats(self._h, ctypes.byref(s))
+        if st not in (0, 5):
+            _lib.check(st, "qsw_last_stats")
+        return {"branch": s.branch, "m": s.m, "s": s.s, "m0": s.m0, "s0": s.s0,
+                "launched": s.launched, "products": s.products, "nonfinite": bool(s.nonfinite),
+                "ms": s.ms, "bytes": s.bytes}
+
+    def apply(self, x, out=None):
+        """y = L x for a length-n complex128 device vector."""
+        torch = _torch()
+        x = x.to(device=self.device, dtype=torch.complex128).contiguous().reshape(-1)
+        if x.numel() != self.n:
+            raise ValueError("x must have N^2 elements")
+        y = torch.empty_like(x) if out is None else out
+        with torch.cuda.device(self.device):
+            st = _lib.load().qsw_apply(self._h, ctypes.c_void_p(x.data_ptr()),
+                                       ctypes.c_void_p(y.data_ptr()), _stream(self.device))
+        _lib.check(st, "qsw_apply")
+        return y
+
+    def populations(self, rho):
+        """Diagonals Re rho_k[a, a] of a [count, N, N] device series."""
+        torch = _torch()
+        rho = rho.contiguous()
+        count = rho.numel() // self.n
+        pops = torch.empty((count, self.N), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            st = _lib.load().qsw_populations(self._h, ctypes.c_void_p(rho.data_ptr()), count,
+                                             ctypes.c_void_p(pops.data_ptr()),
+                                             _stream(self.device))
+        _lib.check(st, "qsw_populations")
+        return pops
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().qsw_superop_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,106 @@
+"""ctypes declarations of libqsw (include/qsw.h).  Argument marshalling only."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqsw.so")
+
+QSW_OK = 0
+STATUS_NAMES = {0: "QSW_OK", 1: "QSW_ERR_ARG", 2: "QSW_ERR_GRAPH", 3: "QSW_ERR_OOM",
+                4: "QSW_ERR_DEVICE", 5: "QSW_ERR_NONFINITE", 6: "QSW_ERR_STATE",
+                7: "QSW_ERR_SIZE"}
+
+QSW_H_LAPLACIAN = 0
+QSW_H_ADJACENCY = 1
+QSW_R_TRANSITION = 0
+QSW_R_COLNORM = 2
+QSW_DEPHASING = 4
+QSW_PREC_DOUBLE = 0
+QSW_PREC_SINGLE = 1
+
+# Every function the header declares, for the export check.
+EXPORTED = ("qsw_superop_build", "qsw_superop_build_ops", "qsw_superop_destroy",
+            "qsw_superop_info", "qsw_superop_copy_csr", "qsw_propagate_workspace_bytes",
+            "qsw_propagate", "qsw_last_stats", "qsw_apply", "qsw_populations", "qsw_theta",
+            "qsw_select_params", "qsw_status_str", "qsw_version")
+
+
+class QswError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {STATUS_NAMES.get(status, status)}")
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("n", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("omega", ctypes.c_double), ("norm1", ctypes.c_double),
+                ("d", ctypes.c_double * 10), ("d_index", ctypes.c_int64 * 10),
+                ("d_probe", ctypes.c_int32 * 10), ("norm_products", ctypes.c_int32),
+                ("build_ms", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("branch", ctypes.c_int32), ("m", ctypes.c_int32), ("s", ctypes.c_int32),
+                ("m0", ctypes.c_int32), ("s0", ctypes.c_int32), ("launched", ctypes.c_int64),
+                ("products", ctypes.c_int64), ("nonfinite", ctypes.c_int32),
+                ("ms", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+_lib = None
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_dbl = ctypes.c_double
+_u32 = ctypes.c_uint32
+
+
+def load() -> ctypes.CDLL:
+    """Load the in-tree libqsw.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2003_02450_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    L.qsw_superop_build.restype = _i32
+    L.qsw_superop_build.argtypes = [_i32, _vp, _vp, _vp, _dbl, _dbl, _u32, _vp,
+                                    ctypes.POINTER(_vp)]
+    L.qsw_superop_build_ops.restype = _i32
+    L.qsw_superop_build_ops.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _dbl, _u32, _vp,
+                                        ctypes.POINTER(_vp)]
+    L.qsw_superop_destroy.restype = None
+    L.qsw_superop_destroy.argtypes = [_vp]
+    L.qsw_superop_info.restype = _i32
+    L.qsw_superop_info.argtypes = [_vp, ctypes.POINTER(Info)]
+    L.qsw_superop_copy_csr.restype = _i32
+    L.qsw_superop_copy_csr.argtypes = [_vp, _vp, _vp, _vp]
+    L.qsw_propagate_workspace_bytes.restype = ctypes.c_size_t
+    L.qsw_propagate_workspace_bytes.argtypes = [_vp, _dbl, _dbl, _i32]
+    L.qsw_propagate.restype = _i32
+    L.qsw_propagate.argtypes = [_vp, _vp, _dbl, _dbl, _i32, _vp, _vp, ctypes.c_size_t, _vp]
+    L.qsw_last_stats.restype = _i32
+    L.qsw_last_stats.argtypes = [_vp, ctypes.POINTER(Stats)]
+    L.qsw_apply.restype = _i32
+    L.qsw_apply.argtypes = [_vp, _vp, _vp, _vp]
+    L.qsw_populations.restype = _i32
+    L.qsw_populations.argtypes = [_vp, _vp, _i32, _vp, _vp]
+    L.qsw_theta.restype = _dbl
+    L.qsw_theta.argtypes = [_i32, _i32]
+    L.qsw_select_params.restype = _i32
+    L.qsw_select_params.argtypes = [_dbl, _vp, _dbl, _i32, _i32, ctypes.POINTER(_i32),
+                                    ctypes.POINTER(_i32)]
+    L.qsw_status_str.restype = ctypes.c_char_p
+    L.qsw_status_str.argtypes = [_i32]
+    L.qsw_version.restype = ctypes.c_char_p
+    L.qsw_version.argtypes = []
+    _lib = L
+    return L
+
+
+def check(status: int, what: str):
+    if status != QSW_OK:
+        raise QswError(status, what)

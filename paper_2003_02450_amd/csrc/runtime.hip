@@ -1,0 +1,934 @@
+// Host runtime and C ABI of libqsw (declared in include/qsw.h).
+//
+// Build: graph -> H, rates R, K on the host (O(N + E)), device assembly of
+// the superoperator L and of its adjoint, exact ||L||_1 from the adjoint's
+// row sums, block 1-norm estimates of ||L^p||_1 (p = 2..9), adjoint freed.
+// Propagate: FP64 parameter selection on the host, then launch chains of the
+// fused Taylor-term kernel whose stopping test runs on the device, so the
+// host never waits inside the loop.
+#include "qsw_impl.h"
+#include "params.h"
+#include "../../include/qsw.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <limits>
+#include <mutex>
+#include <new>
+#include <vector>
+
+using namespace qsw;
+
+namespace {
+
+// ---------------------------------------------------------------- helpers
+
+#define HIP_TRY(expr)                                  \
+  do {                                                 \
+    hipError_t _e = (expr);                            \
+    if (_e != hipSuccess) return status_of(_e);        \
+  } while (0)
+
+qsw_status_t status_of(hipError_t e) {
+  if (e == hipSuccess) return QSW_OK;
+  if (e == hipErrorOutOfMemory) return QSW_ERR_OOM;
+  return QSW_ERR_DEVICE;
+}
+
+template <class T>
+hipError_t dalloc(T **p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc((void **)p, count * sizeof(T));
+}
+
+template <class T>
+void dfree(T *&p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+// Save and restore the caller's current device around an API call.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (dev >= 0 && dev != prev) ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+int env_int(const char *name, int dflt) {
+  const char *v = std::getenv(name);
+  if (!v || !*v) return dflt;
+  return std::atoi(v);
+}
+
+// Host-side operator data before upload.
+struct HostOps {
+  int32_t N = 0;
+  std::vector<int64_t> hp;      // off-diagonal H CSR
+  std::vector<int32_t> hc;
+  std::vector<double> hv;       // interleaved complex
+  std::vector<double> hdiag;
+  std::vector<int64_t> rp;      // off-diagonal rates CSR (row = target)
+  std::vector<int32_t> rc;
+  std::vector<double> rv;
+  std::vector<double> rdiag;
+  std::vector<double> K;
+};
+
+// Check a host CSR: row_ptr monotone from 0, columns in range, strictly
+// increasing within each row.
+qsw_status_t check_csr(int32_t N, const int64_t *rp, const int32_t *ci, bool allow_diag) {
+  if (rp[0] != 0) return QSW_ERR_GRAPH;
+  for (int32_t i = 0; i < N; ++i) {
+    if (rp[i + 1] < rp[i]) return QSW_ERR_GRAPH;
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+      const int32_t c = ci[e];
+      if (c < 0 || c >= N) return QSW_ERR_GRAPH;
+      if (!allow_diag && c == i) return QSW_ERR_GRAPH;
+      if (e > rp[i] && ci[e - 1] >= c) return QSW_ERR_GRAPH;
+    }
+  }
+  return QSW_OK;
+}
+
+// Transpose of an N x N CSR (row-sorted output).
+void transpose_csr(int32_t N, const std::vector<int64_t> &rp, const std::vector<int32_t> &ci,
+                   const std::vector<double> &v, int width, std::vector<int64_t> &tp,
+                   std::vector<int32_t> &tc, std::vector<double> &tv) {
+  const int64_t nnz = rp[N];
+  tp.assign(N + 1, 0);
+  for (int64_t e = 0; e < nnz; ++e) tp[ci[e] + 1]++;
+  for (int32_t i = 0; i < N; ++i) tp[i + 1] += tp[i];
+  tc.resize(nnz);
+  tv.resize(nnz * width);
+  std::vector<int64_t> pos(tp.begin(), tp.end() - 1);
+  for (int32_t i = 0; i < N; ++i)
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+      const int64_t o = pos[ci[e]]++;
+      tc[o] = i;
+      for (int w = 0; w < width; ++w) tv[o * width + w] = v[e * width + w];
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ handle
+
+struct qsw_superop_s {
+  int device = -1;
+  int32_t N = 0;
+  int64_t n = 0, nnz = 0;
+  double omega = 0.0;
+  int64_t *row_ptr = nullptr;
+  int32_t *col = nullptr;
+  double2 *val = nullptr;
+  qsw_info_t info{};
+  // launch shape of the product kernels
+  int lpr = 8;
+  int grid = 2048;
+  int64_t rows_per_block = 0;
+  // last propagate
+  hipEvent_t ev_start = nullptr, ev_end = nullptr;
+  unsigned long long *stats_dev = nullptr;  // [products, nonfinite]
+  qsw_stats_t last{};
+  bool have_last = false;
+};
+
+namespace {
+
+void choose_launch(qsw_superop_s *h) {
+  const double avg = h->n ? (double)h->nnz / (double)h->n : 1.0;
+  int lpr = avg <= 12 ? 4 : avg <= 48 ? 8 : avg <= 160 ? 16 : avg <= 600 ? 32 : 64;
+  lpr = env_int("QSW_LPR", lpr);
+  if (lpr != 4 && lpr != 8 && lpr != 16 && lpr != 32 && lpr != 64) lpr = 8;
+  const int rpi = 256 / lpr;
+  int target = env_int("QSW_GRID", 2048);
+  if (target < 1) target = 2048;
+  int64_t rpb = (h->n + target - 1) / target;
+  rpb = std::max<int64_t>(rpi, (rpb + rpi - 1) / rpi * rpi);
+  h->lpr = lpr;
+  h->rows_per_block = rpb;
+  h->grid = (int)((h->n + rpb - 1) / rpb);
+}
+
+// Device copies of one operator set plus the assembled matrix.
+struct DeviceOps {
+  int64_t *hp = nullptr;
+  int32_t *hc = nullptr;
+  double2 *hv = nullptr;
+  double *hdiag = nullptr;
+  int64_t *rp = nullptr;
+  int32_t *rc = nullptr;
+  double *rv = nullptr;
+  double *rdiag = nullptr;
+  double *K = nullptr;
+  int64_t *PH = nullptr;
+  int64_t *PR = nullptr;
+  void release() {
+    dfree(hp); dfree(hc); dfree(hv); dfree(hdiag); dfree(rp); dfree(rc); dfree(rv);
+    dfree(rdiag); dfree(K); dfree(PH); dfree(PR);
+  }
+};
+
+template <class T>
+hipError_t upload(T **dst, const std::vector<T> &src, hipStream_t s) {
+  hipError_t e = dalloc(dst, src.size());
+  if (e != hipSuccess) return e;
+  if (src.empty()) return hipSuccess;
+  return hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+// Assemble sigma = +1 (L, rates as given) or -1 (L^dagger, rates transposed)
+// into freshly allocated (row_ptr, col, val).
+qsw_status_t assemble(const HostOps &op, bool adjoint, double omega, hipStream_t s,
+                      int64_t **rp_out, int32_t **col_out, double2 **val_out, int64_t *nnz_out) {
+  const int32_t N = op.N;
+  const int64_t n = (int64_t)N * N;
+  std::vector<int64_t> rtp;
+  std::vector<int32_t> rtc;
+  std::vector<double> rtv;
+  const std::vector<int64_t> *rp = &op.rp;
+  const std::vector<int32_t> *rc = &op.rc;
+  const std::vector<double> *rv = &op.rv;
+  if (adjoint) {
+    transpose_csr(N, op.rp, op.rc, op.rv, 1, rtp, rtc, rtv);
+    rp = &rtp;
+    rc = &rtc;
+    rv = &rtv;
+  }
+  std::vector<int64_t> PH(N + 1, 0), PR(N + 1, 0);
+  for (int32_t i = 0; i < N; ++i) {
+    PH[i + 1] = PH[i] + (op.hp[i + 1] - op.hp[i]);
+    PR[i + 1] = PR[i] + ((*rp)[i + 1] - (*rp)[i]);
+  }
+  const int64_t EH = PH[N];
+  const int64_t nnz = 2 * (int64_t)N * EH + n + PR[N];
+  DeviceOps d;
+  std::vector<double> hvec = op.hv;
+  qsw_status_t st = QSW_OK;
+  hipError_t e;
+  int64_t *drp = nullptr;
+  int32_t *dcol = nullptr;
+  double2 *dval = nullptr;
+  do {
+    if ((e = upload(&d.hp, op.hp, s)) != hipSuccess) break;
+    if ((e = upload(&d.hc, op.hc, s)) != hipSuccess) break;
+    if ((e = dalloc(&d.hv, op.hc.size())) != hipSuccess) break;
+    if (!op.hc.empty() &&
+        (e = hipMemcpyAsync(d.hv, hvec.data(), hvec.size() * sizeof(double),
+                            hipMemcpyHostToDevice, s)) != hipSuccess)
+      break;
+    if ((e = upload(&d.hdiag, op.hdiag, s)) != hipSuccess) break;
+    if ((e = upload(&d.rp, *rp, s)) != hipSuccess) break;
+    if ((e = upload(&d.rc, *rc, s)) != hipSuccess) break;
+    if ((e = upload(&d.rv, *rv, s)) != hipSuccess) break;
+    if ((e = upload(&d.rdiag, op.rdiag, s)) != hipSuccess) break;
+    if ((e = upload(&d.K, op.K, s)) != hipSuccess) break;
+    if ((e = upload(&d.PH, PH, s)) != hipSuccess) break;
+    if ((e = upload(&d.PR, PR, s)) != hipSuccess) break;
+    if ((e = dalloc(&drp, (size_t)n + 1)) != hipSuccess) break;
+    if ((e = dalloc(&dcol, (size_t)nnz)) != hipSuccess) break;
+    if ((e = dalloc(&dval, (size_t)nnz)) != hipSuccess) break;
+    AssembleArgs A;
+    A.N = N;
+    A.hp = d.hp; A.hc = d.hc; A.hv = d.hv; A.hdiag = d.hdiag;
+    A.rp = d.rp; A.rc = d.rc; A.rv = d.rv; A.rdiag = d.rdiag;
+    A.K = d.K; A.PH = d.PH; A.PR = d.PR; A.EH = EH;
+    A.omega = omega;
+    A.sigma = adjoint ? -1.0 : 1.0;
+    A.row_ptr = drp; A.col = dcol; A.val = dval;
+    if ((e = launch_assemble(A, n, s)) != hipSuccess) break;
+    e = hipStreamSynchronize(s);  // host vectors above must outlive the copies
+  } while (false);
+  d.release();
+  if (e != hipSuccess) {
+    dfree(drp); dfree(dcol); dfree(dval);
+    st = status_of(e);
+    return st;
+  }
+  *rp_out = drp;
+  *col_out = dcol;
+  *val_out = dval;
+  *nnz_out = nnz;
+  return QSW_OK;
+}
+
+// SplitMix64 (Steele, Lea and Flood, 2014): the sign pattern of the second
+// probe column of the 1-norm estimator.
+uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+// Block 1-norm estimator (Higham and Tisseur's algorithm, two columns,
+// complex case, at most five iterations) applied to A^p, with the products
+// formed by p sparse products on the device.  Returns the estimate and the
+// unit column (or probe column) that attains it.
+struct Estimator {
+  int64_t n;
+  hipStream_t s;
+  const int64_t *rp; const int32_t *col; const double2 *val;      // A
+  const int64_t *arp; const int32_t *acol; const double2 *aval;   // A^dagger
+  double2 *X, *Y, *W0, *W1, *S;  // n x 2 interleaved blocks
+  double *h, *part, *sums;
+  int grid, nb;
+  int products = 0;
+
+  // out = (A or A^dagger)^p in; intermediates alternate between W0 and W1,
+  // the epilogue `mode` runs on the last product only.
+  hipError_t power(bool adj, const double2 *in, double2 *out, int p, int mode) {
+    const double2 *src = in;
+    for (int i = 1; i <= p; ++i) {
+      double2 *dst = (i == p) ? out : ((i & 1) ? W0 : W1);
+      hipError_t e = launch_spmm2(n, adj ? arp : rp, adj ? acol : col, adj ? aval : val, src, dst,
+                                  i == p ? mode : 0, part, S, h, grid, s);
+      if (e != hipSuccess) return e;
+      ++products;
+      src = dst;
+    }
+    return hipSuccess;
+  }
+
+  hipError_t estimate(int p, double *est_out, int64_t *index_out, int *probe_out) {
+    const int t = n >= 2 ? 2 : 1;
+    std::vector<double> hx(4 * (size_t)n, 0.0);  // two interleaved complex columns
+    const double inv = 1.0 / (double)n;
+    bool all_plus = true;
+    for (int64_t i = 0; i < n; ++i) {
+      hx[4 * i] = inv;
+      const double sg = (splitmix64(0x51A7E5ull + (uint64_t)i) >> 63) ? -1.0 : 1.0;
+      hx[4 * i + 2] = sg * inv;
+      if (sg < 0) all_plus = false;
+    }
+    if (all_plus && n >= 2) hx[4 * (n - 1) + 2] = -inv;  // keep the probes independent
+    if (t == 1)
+      for (int64_t i = 0; i < n; ++i) hx[4 * i + 2] = 0.0;
+    hipError_t e = hipMemcpyAsync(X, hx.data(), hx.size() * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    double est_old = 0.0, est = 0.0;
+    int64_t ind_best = -1;
+    int probe_best = 0;
+    int64_t ind[2] = {-1, -1};
+    std::vector<int64_t> hist;
+    std::vector<double> hh((size_t)n);
+    const int itmax = 5;
+    for (int k = 1;; ++k) {
+      // Y = A^p X, column 1-norms and S = sign(Y)
+      e = power(false, X, Y, p, 1);
+      if (e != hipSuccess) return e;
+      e = launch_sum_partials(part, nb, sums, s);
+      if (e != hipSuccess) return e;
+      double cs[2] = {0.0, 0.0};
+      e = hipMemcpyAsync(cs, sums, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+      if (e != hipSuccess) return e;
+      e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return e;
+      int jbest = 0;
+      est = cs[0];
+      if (t == 2 && cs[1] > est) {
+        est = cs[1];
+        jbest = 1;
+      }
+      if (est > est_old || k == 2) {
+        if (k == 1) {
+          ind_best = -1;
+          probe_best = jbest;
+        } else {
+          ind_best = ind[jbest];
+        }
+      }
+      if (k >= 2 && est <= est_old) {
+        est = est_old;
+        break;
+      }
+      est_old = est;
+      if (k > itmax) break;
+      // Z = (A^dagger)^p S, h_i = max_j |Z_ij|
+      e = power(true, S, Y, p, 2);
+      if (e != hipSuccess) return e;
+      e = hipMemcpyAsync(hh.data(), h, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, s);
+      if (e != hipSuccess) return e;
+      e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return e;
+      double hmax = 0.0;
+      for (int64_t i = 0; i < n; ++i) hmax = std::max(hmax, hh[i]);
+      if (k >= 2 && ind_best >= 0 && hmax == hh[ind_best]) break;
+      // indices by decreasing h (ties: smaller index first); only the first
+      // t + |hist| of that order can matter
+      const size_t want = std::min<size_t>((size_t)n, (size_t)t + hist.size());
+      std::vector<int64_t> top;
+      top.reserve(want + 1);
+      auto better = [&](int64_t a, int64_t b) {
+        return hh[a] > hh[b] || (hh[a] == hh[b] && a < b);
+      };
+      for (int64_t i = 0; i < n; ++i) {
+        if (top.size() < want) {
+          top.push_back(i);
+          std::push_heap(top.begin(), top.end(), better);
+        } else if (better(i, top.front())) {
+          std::pop_heap(top.begin(), top.end(), better);
+          top.back() = i;
+          std::push_heap(top.begin(), top.end(), better);
+        }
+      }
+      std::sort(top.begin(), top.end(), better);
+      auto in_hist = [&](int64_t i) { return std::find(hist.begin(), hist.end(), i) != hist.end(); };
+      if (t > 1) {
+        bool all_seen = true;
+        for (int j = 0; j < t && j < (int)top.size(); ++j)
+          if (!in_hist(top[j])) all_seen = false;
+        if (all_seen) break;
+      }
+      int got = 0;
+      for (size_t q = 0; q < top.size() && got < t; ++q)
+        if (!in_hist(top[q])) ind[got++] = top[q];
+      if (got < t) break;
+      std::fill(hx.begin(), hx.end(), 0.0);
+      for (int j = 0; j < t; ++j) {
+        hx[4 * ind[j] + 2 * j] = 1.0;
+        hist.push_back(ind[j]);
+      }
+      e = hipMemcpyAsync(X, hx.data(), hx.size() * sizeof(double), hipMemcpyHostToDevice, s);
+      if (e != hipSuccess) return e;
+    }
+    e = hipStreamSynchronize(s);  // hx must outlive the last upload
+    if (e != hipSuccess) return e;
+    *est_out = est;
+    *index_out = ind_best;
+    *probe_out = probe_best;
+    return hipSuccess;
+  }
+};
+
+qsw_status_t build_common(HostOps &op, double omega, hipStream_t s, qsw_superop_t *out) {
+  auto t_start = std::chrono::steady_clock::now();
+  const int32_t N = op.N;
+  const int64_t n = (int64_t)N * N;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  qsw_superop_s *h = new (std::nothrow) qsw_superop_s();
+  if (!h) return QSW_ERR_OOM;
+  h->device = dev;
+  h->N = N;
+  h->n = n;
+  h->omega = omega;
+  auto fail = [&](qsw_status_t st) {
+    qsw_superop_destroy(h);
+    return st;
+  };
+  // K_j = sum_i R_ij over the rates as given (diagonal included)
+  op.K.assign(N, 0.0);
+  for (int32_t i = 0; i < N; ++i) {
+    for (int64_t e = op.rp[i]; e < op.rp[i + 1]; ++e) op.K[op.rc[e]] += op.rv[e];
+    op.K[i] += op.rdiag[i];
+  }
+  qsw_status_t st = assemble(op, false, omega, s, &h->row_ptr, &h->col, &h->val, &h->nnz);
+  if (st != QSW_OK) return fail(st);
+  choose_launch(h);
+  // adjoint for ||L||_1 and the estimator
+  int64_t *arp = nullptr;
+  int32_t *acol = nullptr;
+  double2 *aval = nullptr;
+  int64_t annz = 0;
+  st = assemble(op, true, omega, s, &arp, &acol, &aval, &annz);
+  if (st != QSW_OK) return fail(st);
+  unsigned long long *nbits = nullptr;
+  Estimator E{};
+  hipError_t e = hipSuccess;
+  double norm1 = 0.0;
+  do {
+    if ((e = dalloc(&nbits, 1)) != hipSuccess) break;
+    if ((e = launch_zero(nbits, sizeof(unsigned long long), s)) != hipSuccess) break;
+    if ((e = launch_row_abs_max(n, arp, aval, nbits, s)) != hipSuccess) break;
+    unsigned long long bits = 0;
+    if ((e = hipMemcpyAsync(&bits, nbits, sizeof(bits), hipMemcpyDeviceToHost, s)) != hipSuccess) break;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) break;
+    std::memcpy(&norm1, &bits, sizeof(double));
+    h->info.norm1 = norm1;
+    h->info.d[0] = h->info.d[1] = norm1;
+    for (int p = 0; p < 10; ++p) {
+      h->info.d_index[p] = -1;
+      h->info.d_probe[p] = 0;
+    }
+    E.n = n;
+    E.s = s;
+    E.rp = h->row_ptr; E.col = h->col; E.val = h->val;
+    E.arp = arp; E.acol = acol; E.aval = aval;
+    E.grid = 2048;
+    E.nb = spmm2_blocks(n, E.grid);
+    if ((e = dalloc(&E.X, 2 * (size_t)n)) != hipSuccess) break;
+    if ((e = dalloc(&E.Y, 2 * (size_t)n)) != hipSuccess) break;
+    if ((e = dalloc(&E.W0, 2 * (size_t)n)) != hipSuccess) break;
+    if ((e = dalloc(&E.W1, 2 * (size_t)n)) != hipSuccess) break;
+    if ((e = dalloc(&E.S, 2 * (size_t)n)) != hipSuccess) break;
+    if ((e = dalloc(&E.h, (size_t)n)) != hipSuccess) break;
+    if ((e = dalloc(&E.part, 2 * (size_t)E.nb)) != hipSuccess) break;
+    if ((e = dalloc(&E.sums, 2)) != hipSuccess) break;
+    for (int p = 2; p <= kPMax + 1 && norm1 > 0.0; ++p) {
+      double est = 0.0;
+      int64_t idx = -1;
+      int probe = 0;
+      if ((e = E.estimate(p, &est, &idx, &probe)) != hipSuccess) break;
+      h->info.d[p] = std::pow(est, 1.0 / p);
+      h->info.d_index[p] = idx;
+      h->info.d_probe[p] = probe;
+    }
+  } while (false);
+  dfree(nbits);
+  dfree(E.X); dfree(E.Y); dfree(E.W0); dfree(E.W1); dfree(E.S); dfree(E.h); dfree(E.part); dfree(E.sums);
+  dfree(arp); dfree(acol); dfree(aval);
+  if (e != hipSuccess) return fail(status_of(e));
+  if (!std::isfinite(norm1)) return fail(QSW_ERR_NONFINITE);
+  h->info.N = N;
+  h->info.n = n;
+  h->info.nnz = h->nnz;
+  h->info.omega = omega;
+  h->info.norm_products = E.products;
+  if (hipEventCreate(&h->ev_start) != hipSuccess || hipEventCreate(&h->ev_end) != hipSuccess)
+    return fail(QSW_ERR_DEVICE);
+  if (dalloc(&h->stats_dev, 2) != hipSuccess) return fail(QSW_ERR_OOM);
+  auto t_end = std::chrono::steady_clock::now();
+  h->info.build_ms = std::chrono::duration<double, std::milli>(t_end - t_start).count();
+  *out = h;
+  return QSW_OK;
+}
+
+// ------------------------------------------------------------ propagate plan
+
+struct Plan {
+  int branch = 0;
+  int m = 0, s = 1;      // per interval (branch 0) or for the span (branch 1)
+  int m0 = 0, s0 = 1;    // exp(t0 L) start
+  int d = 0, j = 0, r = 0;
+  size_t off_state = 0, off_pts = 0, off_B = 0, off_F = 0, off_K = 0, total = 0;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+qsw_status_t make_plan(const qsw_superop_s *h, double t0, double dt, int32_t n_steps, Plan &P) {
+  if (!std::isfinite(t0) || !std::isfinite(dt) || n_steps < 0) return QSW_ERR_ARG;
+  const double *d = h->info.d;
+  qsw_status_t st;
+  if (t0 != 0.0) {
+    st = select_params_impl(h->info.norm1, d, t0, 1, QSW_PREC_DOUBLE, &P.m0, &P.s0);
+    if (st != QSW_OK) return st;
+  }
+  const size_t vec = (size_t)h->n * sizeof(double2);
+  P.off_state = 0;
+  size_t off = align256(sizeof(DeviceState));
+  if (n_steps > 0) {
+    int mS = 0, sS = 1;
+    st = select_params_impl(h->info.norm1, d, (double)n_steps * dt, 1, QSW_PREC_DOUBLE, &mS, &sS);
+    if (st != QSW_OK) return st;
+    if (n_steps <= sS || mS == 0) {
+      P.branch = 0;
+      st = select_params_impl(h->info.norm1, d, dt, 1, QSW_PREC_DOUBLE, &P.m, &P.s);
+      if (st != QSW_OK) return st;
+    } else {
+      P.branch = 1;
+      P.m = mS;
+      P.s = sS;
+      P.d = n_steps / sS;
+      P.j = n_steps / P.d;
+      P.r = n_steps - P.d * P.j;
+    }
+  }
+  P.off_pts = off;
+  if (P.branch == 1) off += align256(sizeof(PointSlots) * (size_t)P.d);
+  P.off_B = off;
+  off += 2 * align256(vec);
+  P.off_F = off;
+  off += 2 * align256(vec);
+  P.off_K = off;
+  if (P.branch == 1) off += (size_t)P.m * align256(vec);
+  P.total = off;
+  return QSW_OK;
+}
+
+struct Runner {
+  qsw_superop_s *h;
+  hipStream_t s;
+  DeviceState *st;
+  double2 *B[2];
+  double2 *F[2];
+  int64_t gstep = 0;
+  int64_t launched = 0;
+  double tol;
+
+  SpmvArgs base_args() const {
+    SpmvArgs a{};
+    a.n = h->n;
+    a.rp = h->row_ptr;
+    a.col = h->col;
+    a.val = h->val;
+    a.tol = tol;
+    a.st = st;
+    a.rows_per_block = h->rows_per_block;
+    return a;
+  }
+
+  // x_out = T_m(t L / s)^s x_in with the early-termination test on the device.
+  hipError_t alg32(const double2 *x_in, double2 *x_out, double t, int m, int s_steps) {
+    if (m == 0) return launch_copy(x_out, x_in, h->n, s);
+    const double2 *Fsrc = x_in;
+    for (int i = 0; i < s_steps; ++i) {
+      const int par = (int)(gstep & 1);
+      ++gstep;
+      double2 *Fdst = (i == s_steps - 1) ? x_out : F[i & 1];
+      for (int j = 1; j <= m; ++j) {
+        SpmvArgs a = base_args();
+        a.x = (j == 1) ? Fsrc : B[(j - 1) & 1];
+        a.y = B[j & 1];
+        a.fin = (j == 1) ? Fsrc : Fdst;
+        a.fout = Fdst;
+        a.alpha = t / ((double)s_steps * (double)j);
+        a.par = par;
+        a.j = j;
+        hipError_t e = launch_taylor_term(a, h->lpr, h->grid, s);
+        if (e != hipSuccess) return e;
+        ++launched;
+      }
+      Fsrc = Fdst;
+    }
+    return hipSuccess;
+  }
+};
+
+}  // namespace
+
+// ================================================================== C ABI
+
+extern "C" {
+
+const char *qsw_status_str(qsw_status_t s) {
+  switch (s) {
+    case QSW_OK: return "ok";
+    case QSW_ERR_ARG: return "invalid argument";
+    case QSW_ERR_GRAPH: return "malformed graph or operator CSR";
+    case QSW_ERR_OOM: return "device out of memory";
+    case QSW_ERR_DEVICE: return "HIP runtime error";
+    case QSW_ERR_NONFINITE: return "non-finite value";
+    case QSW_ERR_STATE: return "bad state (device, workspace)";
+    case QSW_ERR_SIZE: return "N*N exceeds the 32-bit column index";
+  }
+  return "unknown status";
+}
+
+const char *qsw_version(void) { return "qsw 0.1 gfx950"; }
+
+qsw_status_t qsw_superop_build(int32_t N, const int64_t *row_ptr, const int32_t *col_idx,
+                               const double *w, double omega, double gamma, uint32_t flags,
+                               void *hip_stream, qsw_superop_t *out) {
+  if (!out || !row_ptr || N < 1) return QSW_ERR_ARG;
+  *out = nullptr;
+  if (!(omega >= 0.0 && omega <= 1.0) || !(gamma > 0.0) || !std::isfinite(gamma)) return QSW_ERR_ARG;
+  if (flags & ~(uint32_t)(QSW_H_ADJACENCY | QSW_R_COLNORM | QSW_DEPHASING)) return QSW_ERR_ARG;
+  if ((int64_t)N * N > (int64_t)std::numeric_limits<int32_t>::max()) return QSW_ERR_SIZE;
+  const int64_t E = row_ptr[N];
+  if (E > 0 && (!col_idx || !w)) return QSW_ERR_ARG;
+  qsw_status_t st = check_csr(N, row_ptr, col_idx, false);
+  if (st != QSW_OK) return st;
+  for (int64_t e = 0; e < E; ++e)
+    if (!(w[e] > 0.0) || !std::isfinite(w[e])) return QSW_ERR_GRAPH;
+  // G^u = max(G, G^T) by merging each row of G with the same row of G^T
+  std::vector<int64_t> gp(row_ptr, row_ptr + N + 1), tp;
+  std::vector<int32_t> gc(col_idx, col_idx + E), tc;
+  std::vector<double> gw(w, w + E), tw;
+  transpose_csr(N, gp, gc, gw, 1, tp, tc, tw);
+  HostOps op;
+  op.N = N;
+  op.hp.assign(N + 1, 0);
+  op.hdiag.assign(N, 0.0);
+  std::vector<int32_t> uc;
+  std::vector<double> uw;
+  uc.reserve(2 * E);
+  uw.reserve(2 * E);
+  for (int32_t i = 0; i < N; ++i) {
+    int64_t a = gp[i], b = tp[i];
+    while (a < gp[i + 1] || b < tp[i + 1]) {
+      const int32_t ca = a < gp[i + 1] ? gc[a] : INT32_MAX;
+      const int32_t cb = b < tp[i + 1] ? tc[b] : INT32_MAX;
+      if (ca == cb) {
+        uc.push_back(ca);
+        uw.push_back(std::max(gw[a], tw[b]));
+        ++a;
+        ++b;
+      } else if (ca < cb) {
+        uc.push_back(ca);
+        uw.push_back(gw[a++]);
+      } else {
+        uc.push_back(cb);
+        uw.push_back(tw[b++]);
+      }
+    }
+    op.hp[i + 1] = (int64_t)uc.size();
+  }
+  const bool laplacian = !(flags & QSW_H_ADJACENCY);
+  op.hc = uc;
+  op.hv.assign(2 * uc.size(), 0.0);
+  for (int32_t i = 0; i < N; ++i) {
+    double deg = 0.0;
+    for (int64_t e = op.hp[i]; e < op.hp[i + 1]; ++e) {
+      deg += uw[e];
+      op.hv[2 * e] = laplacian ? -gamma * uw[e] : uw[e];
+    }
+    op.hdiag[i] = laplacian ? gamma * deg : 0.0;
+  }
+  // rates: R_ij for each arc j -> i (row i of G), plus optional dephasing
+  std::vector<double> outdeg(N, 0.0);
+  for (int64_t e = 0; e < E; ++e) outdeg[gc[e]] += gw[e];
+  const bool colnorm = (flags & QSW_R_COLNORM) != 0;
+  op.rp = gp;
+  op.rc = gc;
+  op.rv.resize(E);
+  for (int64_t e = 0; e < E; ++e) op.rv[e] = colnorm ? gw[e] / outdeg[gc[e]] : gamma * gw[e];
+  op.rdiag.assign(N, 0.0);
+  if (flags & QSW_DEPHASING)
+    for (int32_t j = 0; j < N; ++j)
+      op.rdiag[j] = colnorm ? (outdeg[j] > 0.0 ? 1.0 : 0.0) : gamma * outdeg[j];
+  return build_common(op, omega, (hipStream_t)hip_stream, out);
+}
+
+qsw_status_t qsw_superop_build_ops(int32_t N, const int64_t *h_row_ptr, const int32_t *h_col,
+                                   const double *h_val, const int64_t *l_row_ptr,
+                                   const int32_t *l_col, const double *l_val, double omega,
+                                   uint32_t flags, void *hip_stream, qsw_superop_t *out) {
+  if (!out || !h_row_ptr || !l_row_ptr || N < 1) return QSW_ERR_ARG;
+  *out = nullptr;
+  if (!(omega >= 0.0 && omega <= 1.0) || flags != 0) return QSW_ERR_ARG;
+  if ((int64_t)N * N > (int64_t)std::numeric_limits<int32_t>::max()) return QSW_ERR_SIZE;
+  const int64_t EH = h_row_ptr[N], EL = l_row_ptr[N];
+  if ((EH > 0 && (!h_col || !h_val)) || (EL > 0 && (!l_col || !l_val))) return QSW_ERR_ARG;
+  qsw_status_t st = check_csr(N, h_row_ptr, h_col, true);
+  if (st != QSW_OK) return st;
+  st = check_csr(N, l_row_ptr, l_col, true);
+  if (st != QSW_OK) return st;
+  HostOps op;
+  op.N = N;
+  op.hp.assign(N + 1, 0);
+  op.hdiag.assign(N, 0.0);
+  for (int32_t i = 0; i < N; ++i) {
+    for (int64_t e = h_row_ptr[i]; e < h_row_ptr[i + 1]; ++e) {
+      const double re = h_val[2 * e], im = h_val[2 * e + 1];
+      if (!std::isfinite(re) || !std::isfinite(im)) return QSW_ERR_GRAPH;
+      if (h_col[e] == i) {
+        if (std::fabs(im) > 1e-14 * (1.0 + std::fabs(re))) return QSW_ERR_GRAPH;  // not Hermitian
+        op.hdiag[i] = re;
+      } else {
+        op.hc.push_back(h_col[e]);
+        op.hv.push_back(re);
+        op.hv.push_back(im);
+      }
+    }
+    op.hp[i + 1] = (int64_t)op.hc.size();
+  }
+  // Hermitian pattern and values: H_ji = conj(H_ij)
+  for (int32_t i = 0; i < N; ++i)
+    for (int64_t e = op.hp[i]; e < op.hp[i + 1]; ++e) {
+      const int32_t j = op.hc[e];
+      const auto b = op.hc.begin() + op.hp[j], en = op.hc.begin() + op.hp[j + 1];
+      const auto it = std::lower_bound(b, en, i);
+      if (it == en || *it != i) return QSW_ERR_GRAPH;
+      const int64_t f = it - op.hc.begin();
+      const double tolh = 1e-14 * (1.0 + std::fabs(op.hv[2 * e]) + std::fabs(op.hv[2 * e + 1]));
+      if (std::fabs(op.hv[2 * f] - op.hv[2 * e]) > tolh ||
+          std::fabs(op.hv[2 * f + 1] + op.hv[2 * e + 1]) > tolh)
+        return QSW_ERR_GRAPH;
+    }
+  op.rp.assign(N + 1, 0);
+  op.rdiag.assign(N, 0.0);
+  for (int32_t i = 0; i < N; ++i) {
+    for (int64_t e = l_row_ptr[i]; e < l_row_ptr[i + 1]; ++e) {
+      const double v = l_val[e];
+      if (!std::isfinite(v)) return QSW_ERR_GRAPH;
+      if (l_col[e] == i) {
+        op.rdiag[i] = v * v;
+      } else if (v != 0.0) {
+        op.rc.push_back(l_col[e]);
+        op.rv.push_back(v * v);
+      }
+    }
+    op.rp[i + 1] = (int64_t)op.rc.size();
+  }
+  return build_common(op, omega, (hipStream_t)hip_stream, out);
+}
+
+void qsw_superop_destroy(qsw_superop_t h) {
+  if (!h) return;
+  DeviceGuard g(h->device);
+  dfree(h->row_ptr);
+  dfree(h->col);
+  dfree(h->val);
+  dfree(h->stats_dev);
+  if (h->ev_start) (void)hipEventDestroy(h->ev_start);
+  if (h->ev_end) (void)hipEventDestroy(h->ev_end);
+  delete h;
+}
+
+qsw_status_t qsw_superop_info(qsw_superop_t h, qsw_info_t *info) {
+  if (!h || !info) return QSW_ERR_ARG;
+  *info = h->info;
+  return QSW_OK;
+}
+
+qsw_status_t qsw_superop_copy_csr(qsw_superop_t h, int64_t *row_ptr, int32_t *col, double *val) {
+  if (!h) return QSW_ERR_ARG;
+  DeviceGuard g(h->device);
+  if (!g.ok) return QSW_ERR_DEVICE;
+  if (row_ptr)
+    HIP_TRY(hipMemcpy(row_ptr, h->row_ptr, ((size_t)h->n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+  if (col) HIP_TRY(hipMemcpy(col, h->col, (size_t)h->nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (val) HIP_TRY(hipMemcpy(val, h->val, (size_t)h->nnz * sizeof(double2), hipMemcpyDeviceToHost));
+  return QSW_OK;
+}
+
+size_t qsw_propagate_workspace_bytes(qsw_superop_t h, double t0, double dt, int32_t n_steps) {
+  if (!h) return 0;
+  Plan P;
+  if (make_plan(h, t0, dt, n_steps, P) != QSW_OK) return 0;
+  return P.total;
+}
+
+qsw_status_t qsw_propagate(qsw_superop_t h, const void *rho0, double t0, double dt,
+                           int32_t n_steps, void *out, void *workspace, size_t ws_bytes,
+                           void *hip_stream) {
+  if (!h || !rho0 || !out || !workspace) return QSW_ERR_ARG;
+  Plan P;
+  qsw_status_t st = make_plan(h, t0, dt, n_steps, P);
+  if (st != QSW_OK) return st;
+  if (ws_bytes < P.total || ((uintptr_t)workspace & 255)) return QSW_ERR_STATE;
+  const size_t vbytes = (size_t)h->n * sizeof(double2);
+  const char *o = (const char *)out;
+  const char *r0 = (const char *)rho0;
+  if (r0 < o + vbytes * ((size_t)n_steps + 1) && o < r0 + vbytes) return QSW_ERR_ARG;
+  DeviceGuard g(h->device);
+  if (!g.ok) return QSW_ERR_DEVICE;
+  hipStream_t s = (hipStream_t)hip_stream;
+  char *ws = (char *)workspace;
+  const size_t vec = align256(vbytes);
+  Runner R;
+  R.h = h;
+  R.s = s;
+  R.st = (DeviceState *)(ws + P.off_state);
+  R.B[0] = (double2 *)(ws + P.off_B);
+  R.B[1] = (double2 *)(ws + P.off_B + vec);
+  R.F[0] = (double2 *)(ws + P.off_F);
+  R.F[1] = (double2 *)(ws + P.off_F + vec);
+  R.tol = tol_of(QSW_PREC_DOUBLE);
+  double2 *outv = (double2 *)out;
+  const int64_t n = h->n;
+  auto slot = [&](int64_t k) { return outv + k * n; };
+  HIP_TRY(hipEventRecord(h->ev_start, s));
+  HIP_TRY(launch_zero(R.st, sizeof(DeviceState), s));
+  // out[0] = exp(t0 L) rho0
+  if (t0 != 0.0)
+    HIP_TRY(R.alg32((const double2 *)rho0, slot(0), t0, P.m0, P.s0));
+  else
+    HIP_TRY(launch_copy(slot(0), (const double2 *)rho0, n, s));
+  if (n_steps > 0 && P.branch == 0) {
+    for (int32_t k = 0; k < n_steps; ++k) HIP_TRY(R.alg32(slot(k), slot(k + 1), dt, P.m, P.s));
+  } else if (n_steps > 0) {
+    // time-series blocks: K_0 = Z (block start), K_p in the workspace
+    PointSlots *pts = (PointSlots *)(ws + P.off_pts);
+    std::vector<double2 *> Kp(P.m + 1);
+    for (int p = 1; p <= P.m; ++p) Kp[p] = (double2 *)(ws + P.off_K + (size_t)(p - 1) * vec);
+    int64_t zi = 0;
+    for (int i = 1; i <= P.j + 1; ++i) {
+      const int dd = (i <= P.j) ? P.d : P.r;
+      if (dd == 0) break;
+      const double2 *Z = slot(zi);
+      Kp[0] = (double2 *)Z;
+      HIP_TRY(launch_series_init(R.st, pts, dd, Z, n, 1024, s));
+      for (int k = 1; k <= dd; ++k) {
+        double2 *Fk = slot(zi + k);
+        PointSlots *pt = pts + (k - 1);
+        for (int p = 1; p <= P.m; ++p) {
+          SpmvArgs a = R.base_args();
+          a.x = Kp[p - 1];
+          a.y = Kp[p];
+          a.alpha = dt / (double)p;
+          HIP_TRY(launch_series_power(a, pt, k, p, h->lpr, h->grid, s));
+          HIP_TRY(launch_series_accum(R.st, pt, k, p, Kp[p], Z, Fk, n, R.tol, 2048, s));
+          R.launched += 1;
+        }
+      }
+      zi += dd;
+    }
+  }
+  HIP_TRY(hipMemcpyAsync(h->stats_dev, &R.st->products, sizeof(unsigned long long),
+                         hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(h->stats_dev + 1, &R.st->nonfinite, sizeof(int), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipEventRecord(h->ev_end, s));
+  h->last = qsw_stats_t{};
+  h->last.branch = P.branch;
+  h->last.m = P.m;
+  h->last.s = P.s;
+  h->last.m0 = P.m0;
+  h->last.s0 = P.s0;
+  h->last.launched = R.launched;
+  h->have_last = true;
+  return QSW_OK;
+}
+
+qsw_status_t qsw_last_stats(qsw_superop_t h, qsw_stats_t *st) {
+  if (!h || !st) return QSW_ERR_ARG;
+  if (!h->have_last) return QSW_ERR_STATE;
+  DeviceGuard g(h->device);
+  if (!g.ok) return QSW_ERR_DEVICE;
+  HIP_TRY(hipEventSynchronize(h->ev_end));
+  unsigned long long buf[2] = {0, 0};
+  HIP_TRY(hipMemcpy(buf, h->stats_dev, sizeof(buf), hipMemcpyDeviceToHost));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, h->ev_start, h->ev_end));
+  h->last.products = (int64_t)buf[0];
+  h->last.nonfinite = (int)(buf[1] & 0xffffffffu) != 0;
+  h->last.ms = ms;
+  h->last.bytes = (double)h->last.products *
+                  (20.0 * (double)h->nnz + 8.0 * (double)(h->n + 1) + 64.0 * (double)h->n);
+  *st = h->last;
+  return h->last.nonfinite ? QSW_ERR_NONFINITE : QSW_OK;
+}
+
+qsw_status_t qsw_apply(qsw_superop_t h, const void *x, void *y, void *hip_stream) {
+  if (!h || !x || !y || x == y) return QSW_ERR_ARG;
+  DeviceGuard g(h->device);
+  if (!g.ok) return QSW_ERR_DEVICE;
+  SpmvArgs a{};
+  a.n = h->n;
+  a.rp = h->row_ptr;
+  a.col = h->col;
+  a.val = h->val;
+  a.x = (const double2 *)x;
+  a.y = (double2 *)y;
+  a.alpha = 1.0;
+  a.rows_per_block = h->rows_per_block;
+  HIP_TRY(launch_spmv(a, h->lpr, h->grid, (hipStream_t)hip_stream));
+  return QSW_OK;
+}
+
+qsw_status_t qsw_populations(qsw_superop_t h, const void *rho, int32_t count, void *pops,
+                             void *hip_stream) {
+  if (!h || !rho || !pops || count < 0) return QSW_ERR_ARG;
+  if (count == 0) return QSW_OK;
+  DeviceGuard g(h->device);
+  if (!g.ok) return QSW_ERR_DEVICE;
+  HIP_TRY(launch_populations((const double2 *)rho, h->N, count, (double *)pops,
+                             (hipStream_t)hip_stream));
+  return QSW_OK;
+}
+
+}  // extern "C"

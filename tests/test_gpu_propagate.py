@@ -1,0 +1,219 @@
+"""GPU propagation (single-time and time-series branches) against the oracle,
+through the C ABI.  Parity bar: max |rho_gpu - rho_oracle| <= 1e-10 (the
+bound the paper reports against an independent implementation, Section 5);
+GPU-vs-GPU reruns are bitwise identical."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle import expmv, native
+from tests.gpu_util import build_gpu, gpu_run, oracle_superop, random_workload
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _check_density(rho, pure=False):
+    assert abs(np.trace(rho) - 1) < 1e-12
+    assert np.abs(rho - rho.conj().T).max() < 1e-13
+    assert np.linalg.eigvalsh(0.5 * (rho + rho.conj().T)).min() > -1e-12
+    if pure:
+        assert abs(np.trace(rho @ rho).real - 1) < 1e-12
+
+
+def test_cycle16_series_branch_matches_oracle():
+    wl = workloads.cycle16()
+    got, op = gpu_run(wl)
+    st = op.last_stats()
+    assert st["branch"] == 1, st          # q = 10 > s: stored powers
+    ref, _ = oracle.run_workload(wl)
+    assert np.abs(got - ref).max() <= TOL
+    for k in range(wl.n_steps + 1):
+        _check_density(got[k])
+    op.close()
+
+
+def test_cycle16_step_branch_matches_oracle():
+    wl = workloads.cycle16()
+    wl.n_steps, wl.dt = 2, 5.0              # q = 2 <= s: one application per interval
+    got, op = gpu_run(wl)
+    assert op.last_stats()["branch"] == 0
+    ref, _ = oracle.run_workload(wl)
+    assert np.abs(got - ref).max() <= TOL
+    op.close()
+
+
+@pytest.mark.parametrize("omega", [0.0, 0.2, 0.5, 0.93, 1.0])
+@pytest.mark.parametrize("r_mode,dephasing", [("transition", False), ("colnorm", True)])
+def test_random_digraphs_match_oracle(omega, r_mode, dephasing):
+    for N, k, seed in ((7, 2, 11), (23, 3, 12)):
+        wl = random_workload(N, k, omega, seed, r_mode=r_mode, dephasing=dephasing,
+                             n_steps=6, dt=0.8)
+        got, op = gpu_run(wl)
+        ref, _ = oracle.run_workload(wl)
+        assert np.abs(got - ref).max() <= TOL, (N, omega)
+        for j in range(wl.n_steps + 1):
+            _check_density(got[j])
+        op.close()
+
+
+def test_ragged_size_and_start_time():
+    # n = 41^2 = 1681 rows: not a multiple of any row-block size; t0 != 0
+    wl = random_workload(41, 4, 0.45, 21, n_steps=4, dt=0.6, t0=1.3)
+    got, op = gpu_run(wl)
+    ref, _ = oracle.run_workload(wl)
+    assert np.abs(got - ref).max() <= TOL
+    assert op.last_stats()["m0"] > 0
+    op.close()
+
+
+def test_negative_time_step():
+    wl = random_workload(9, 2, 0.0, 3, n_steps=3, dt=-0.5)
+    got, op = gpu_run(wl)
+    ref, _ = oracle.run_workload(wl)
+    assert np.abs(got - ref).max() <= TOL
+    op.close()
+
+
+def test_er256_matches_oracle_sampled():
+    """ER N=256 workload: the first 8 grid points in full against the oracle,
+    every later point by one oracle interval from the GPU's previous point,
+    invariants on every point."""
+    wl = workloads.er256()
+    got, op = gpu_run(wl)
+    st = op.last_stats()
+    assert st["branch"] == 0
+    A = oracle_superop(wl)
+    ref, info = expmv.propagate(A, wl.rho0, 0.0, wl.dt, 8)
+    assert np.abs(got[:9] - ref).max() <= TOL
+    for k in (37, 100):
+        one, _, _ = expmv.expmv(A, got[k - 1].reshape(-1), wl.dt, norm1=info["norm1"])
+        assert np.abs(got[k].reshape(-1) - one).max() <= TOL
+    for k in range(0, wl.n_steps + 1, 5):
+        _check_density(got[k], pure=False)
+    op.close()
+
+
+def test_outdeg1024_matches_oracle_sampled():
+    """The benchmark workload at full size (N = 1024, 51 points), in the
+    launch configuration the benchmark uses: points 1-2 in full against the
+    oracle, point 50 by one oracle interval from the GPU's point 49, and the
+    trace and Hermiticity of every point."""
+    wl = workloads.outdeg1024()
+    got, op = gpu_run(wl)
+    A = oracle_superop(wl)
+    ref, info = expmv.propagate(A, wl.rho0, 0.0, wl.dt, 2)
+    assert np.abs(got[:3] - ref).max() <= TOL
+    one, _, _ = expmv.expmv(A, got[49].reshape(-1), wl.dt, norm1=info["norm1"])
+    assert np.abs(got[50].reshape(-1) - one).max() <= TOL
+    for k in range(wl.n_steps + 1):
+        assert abs(np.trace(got[k]) - 1) < 1e-12
+        assert np.abs(got[k] - got[k].conj().T).max() < 1e-13
+    op.close()
+
+
+def test_three_vertex_example_through_gpu():
+    """Section 4: L-QSW with H = GU, M_L = G, rho0 = diag(1,0,0), t = 100."""
+    import paper_2003_02450_amd as qsw
+    import scipy.sparse as sp
+    spec = json.load(open(os.path.join(GOLDEN, "three_vertex_example.json")))
+    t = spec["t"]
+    G, Gu = workloads.two_sources_one_sink()
+    for omega, closed in ((0.0, [math.cos(t / math.sqrt(2)) ** 4,
+                                 math.sin(t / math.sqrt(2)) ** 4,
+                                 0.5 * math.sin(math.sqrt(2) * t) ** 2]),
+                          (1.0, [math.exp(-t), 0.0, 1 - math.exp(-t)])):
+        op = qsw.Superop.from_operators(sp.csr_matrix(Gu.dense()), sp.csr_matrix(G.dense()),
+                                        omega)
+        rho = op.step(workloads.basis_state(3), t)
+        p = op.populations(rho.reshape(1, 3, 3)).cpu().numpy()[0]
+        assert np.abs(p - np.array(closed)).max() <= 1e-12
+        key = "omega_0" if omega == 0.0 else "omega_1"
+        assert np.abs(p - np.array(spec["printed_populations"][key])).max() <= 5e-9
+        op.close()
+
+
+def test_step_vs_series_agree():
+    """Section 5: step and series agree to 1e-14 or below."""
+    import torch
+    wl = workloads.cycle16()
+    op = build_gpu(wl)
+    ser = op.propagate(wl.rho0, 0.0, 1.0, 10).cpu().numpy()
+    rho = torch.from_numpy(wl.rho0).cuda()
+    for k in range(1, 11):
+        rho = op.step(rho, 1.0)
+        assert np.abs(rho.cpu().numpy() - ser[k]).max() <= 1e-13
+    op.close()
+
+
+def test_resume_equals_uninterrupted():
+    wl = random_workload(15, 3, 0.6, 31, n_steps=8, dt=0.5)
+    got, op = gpu_run(wl)
+    tail = op.propagate(got[4], 0.0, 0.5, 4).cpu().numpy()
+    assert np.abs(tail - got[4:]).max() <= 1e-13
+    op.close()
+
+
+def test_rerun_is_bitwise_identical():
+    for wl in (workloads.cycle16(), random_workload(31, 3, 0.7, 41, n_steps=3)):
+        a, op = gpu_run(wl)
+        b, _ = gpu_run(wl, op)
+        assert np.array_equal(a, b)
+        op.close()
+
+
+def test_maximally_mixed_fixed_point_on_cycle():
+    g = workloads.cycle_graph(24)
+    wl = workloads.Workload("c24", g, 0.6, "laplacian", "transition", False,
+                            workloads.maximally_mixed(24), 0.0, 5.0, 4)
+    got, op = gpu_run(wl)
+    assert np.abs(got - np.eye(24) / 24).max() <= 1e-14
+    op.close()
+
+
+def test_zero_steps_zero_dt_and_empty_graph():
+    import paper_2003_02450_amd as qsw
+    wl = random_workload(6, 2, 0.5, 2, n_steps=0)
+    got, op = gpu_run(wl)
+    assert got.shape == (1, 6, 6) and np.array_equal(got[0], wl.rho0)
+    wl.n_steps, wl.dt = 3, 0.0
+    got, _ = gpu_run(wl, op)
+    for k in range(4):
+        assert np.array_equal(got[k], wl.rho0)
+    op.close()
+    op = qsw.Superop.from_graph(5, np.zeros(6, np.int64), np.array([], np.int32),
+                                np.array([], np.float64), 0.5)
+    rho0 = workloads.uniform_superposition(5)
+    out = op.propagate(rho0, 0.0, 1.0, 3).cpu().numpy()
+    for k in range(4):
+        assert np.array_equal(out[k], rho0)
+    op.close()
+
+
+def test_nonfinite_input_is_reported():
+    wl = random_workload(6, 2, 0.5, 2, n_steps=2)
+    wl.rho0 = wl.rho0.copy()
+    wl.rho0[1, 2] = np.nan
+    got, op = gpu_run(wl)
+    assert op.last_stats()["nonfinite"]
+    op.close()
+
+
+def test_populations_are_diagonals():
+    wl = random_workload(12, 3, 0.4, 5, n_steps=3)
+    import torch
+    op = build_gpu(wl)
+    out = op.propagate(wl.rho0, 0.0, wl.dt, wl.n_steps)
+    pops = op.populations(out).cpu().numpy()
+    torch.cuda.synchronize()
+    host = out.cpu().numpy()
+    for k in range(4):
+        assert np.array_equal(pops[k], np.diag(host[k]).real)
+    op.close()
