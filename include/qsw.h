@@ -97,8 +97,11 @@ typedef struct {
 /*
  * Build the L-QSW superoperator of a graph (Section 2.4.1; H from G^u,
  * L_k from the CTRW transition matrix of G, eq. generator_matrix and eq.
- * lindblad), assemble it in device CSR (int64 row_ptr, int32 columns sorted
- * within each row, complex128 values), compute ||L||_1 exactly and estimate
+ * lindblad), assemble it in device CSR (int64 row_ptr, int32 columns,
+ * complex128 values; each row in structural order: the H rho entries by
+ * ascending c (column c N + b of row a N + b), the diagonal, the rho H
+ * entries by ascending c (column a N + c), then the population-transfer
+ * entries (column j (N + 1)); no column repeats), compute ||L||_1 exactly and estimate
  * ||L^p||_1, p = 2..9 (the 1-norm series the paper computes at construction,
  * Section 4 footnote).
  *
@@ -134,7 +137,8 @@ void qsw_superop_destroy(qsw_superop_t h);
 qsw_status_t qsw_superop_info(qsw_superop_t h, qsw_info_t *info);
 
 /* Copy the device CSR to caller host buffers (row_ptr[n+1], col[nnz],
- * val[2*nnz] doubles).  Any pointer may be NULL to skip it.  Synchronous. */
+ * val[2*nnz] doubles), rows in the structural order described at
+ * qsw_superop_build.  Any pointer may be NULL to skip it.  Synchronous. */
 qsw_status_t qsw_superop_copy_csr(qsw_superop_t h, int64_t *row_ptr, int32_t *col,
                                   double *val);
 

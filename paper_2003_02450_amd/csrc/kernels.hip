@@ -2,11 +2,22 @@
 // complex128 CSR product with the fused Taylor-term epilogue, the
 // time-series kernels and the block 1-norm estimation helpers.
 //
-// All maxima of non-negative doubles travel as IEEE bit patterns in 64-bit
+// Two row engines compute the CSR product; both feed the same epilogues.
+//  * stream: a workgroup takes row blocks of at most kCap entries, streams
+//    their values and column indices with fully coalesced loads (a wave
+//    reads 64 consecutive entries per instruction, several loads in flight
+//    per lane), gathers x, stages the products in LDS and then reduces each
+//    row with a power-of-two group of lanes in a fixed order.  Contiguous
+//    runs of blocks are given to the workgroups of one XCD.
+//  * vector: LPR lanes per row stride through the row (kept for tuning and
+//    for comparison).
+// Every reduction order is fixed by the matrix, so results are bitwise
+// reproducible.
+//
+// Maxima of non-negative doubles travel as IEEE bit patterns in 64-bit
 // unsigned integers: their unsigned order is the numeric order, so a plain
-// integer atomicMax merges them and the result does not depend on the order
-// in which workgroups finish.  NaN (after fabs) sorts above +inf, so a
-// non-finite value reaches the norm slots and is reported.
+// integer atomicMax merges them independently of workgroup order, and NaN
+// (after fabs) sorts above +inf, so a non-finite value reaches the slots.
 #include "qsw_impl.h"
 
 #include <hip/hip_runtime.h>
@@ -17,6 +28,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
+constexpr int kUnroll = 8;  // independent entries in flight per lane (stream engine)
 
 __device__ __forceinline__ unsigned long long abs_bits(double v) {
   return (unsigned long long)__double_as_longlong(fabs(v));
@@ -36,11 +48,11 @@ __device__ __forceinline__ unsigned long long wave_umax(unsigned long long v) {
   return v;
 }
 
-// Reduce NV maxima over the workgroup and merge them into dst[] with one
-// atomic per value.  Every thread of the workgroup must call it.
-// A maximum at or above the bit pattern of +inf flags *nonfinite.
 constexpr unsigned long long kInfBits = 0x7FF0000000000000ull;
 
+// Reduce NV maxima over the workgroup and merge them into dst[] with one
+// atomic each; a maximum at or above +inf sets *nonfinite.  Every thread of
+// the workgroup must call it.
 template <int NV>
 __device__ __forceinline__ void block_umax_to(unsigned long long (&v)[NV],
                                               unsigned long long *const (&dst)[NV],
@@ -64,45 +76,392 @@ __device__ __forceinline__ void block_umax_to(unsigned long long (&v)[NV],
 
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 
-// Streaming load of a matrix value: read once per product, so it is marked
-// non-temporal to leave the caches to the gathered vector.
+// Matrix entries are read once per product: non-temporal loads leave the
+// caches to the gathered vector.
 __device__ __forceinline__ double2 load_stream(const double2 *p) {
   const dvec2 v = __builtin_nontemporal_load(reinterpret_cast<const dvec2 *>(p));
   return make_double2(v.x, v.y);
 }
+__device__ __forceinline__ int load_stream(const int32_t *p) {
+  return __builtin_nontemporal_load(p);
+}
 
-// Complex multiply-accumulate acc += v * x.
 __device__ __forceinline__ void cmac(double &ax, double &ay, double2 v, double2 x) {
   ax = fma(v.x, x.x, ax);
   ax = fma(-v.y, x.y, ax);
   ay = fma(v.x, x.y, ay);
   ay = fma(v.y, x.x, ay);
 }
+__device__ __forceinline__ double2 cmul(double2 v, double2 x) {
+  return make_double2(fma(v.x, x.x, -v.y * x.y), fma(v.x, x.y, v.y * x.x));
+}
 
-// Row product of LPR lanes: lanes stride through the row, then a butterfly
-// over the LPR lanes leaves the full sum in every lane of the group.
-template <int LPR>
-__device__ __forceinline__ double2 row_dot(const int64_t *__restrict__ rp,
-                                           const int32_t *__restrict__ col,
-                                           const double2 *__restrict__ val,
-                                           const double2 *__restrict__ x, int64_t row,
-                                           bool valid, int lane) {
-  double ax = 0.0, ay = 0.0;
-  if (valid) {
-    const int64_t e0 = rp[row], e1 = rp[row + 1];
-    for (int64_t e = e0 + lane; e < e1; e += LPR) {
-      const int c = __builtin_nontemporal_load(col + e);
-      const double2 v = load_stream(val + e);
-      cmac(ax, ay, v, x[c]);
+// --------------------------------------------------------------------------
+// Row engines.  `epi(row, acc)` receives the complex sums of row `row` for
+// NRHS right-hand sides (acc[2 r] = real, acc[2 r + 1] = imaginary part).
+// --------------------------------------------------------------------------
+
+// Logical workgroup index: the dispatcher deals workgroups to the 8 XCDs in
+// turn, so regrouping gives each XCD one contiguous run of row blocks and
+// keeps the vector slices those rows gather in that XCD's L2.
+__device__ __forceinline__ int xcd_contiguous_index() {
+  const int G = gridDim.x, w = blockIdx.x;
+  if (G & 7) return w;
+  return (w & 7) * (G >> 3) + (w >> 3);
+}
+
+// One row block of the stream engine.
+struct BlockDesc {
+  int64_t r0, r1;  // rows r0..r1-1
+  int64_t e0;      // first entry
+  int cnt;         // entries (valid when fits)
+  bool fits;       // cnt <= stage capacity
+};
+
+__device__ __forceinline__ BlockDesc block_desc(const SpmvArgs &a, int64_t k, int cap) {
+  BlockDesc d;
+  d.r0 = a.blk[k];
+  d.r1 = a.blk[k + 1];
+  d.e0 = a.rp[d.r0];
+  const int64_t c = a.rp[d.r1] - d.e0;
+  d.fits = c <= cap && d.r1 - d.r0 <= cap;
+  d.cnt = d.fits ? (int)c : 0;
+  return d;
+}
+
+// Software-pipelined over the workgroup's run of blocks: while block k is
+// reduced out of LDS, the column indices and values of block k+1 are
+// already in flight.  Loads the reduction needs (row offsets, the
+// epilogue's inputs) are issued before that prefetch, so waiting for them
+// does not wait for it.
+template <int NRHS, class Epi>
+__device__ __forceinline__ void stream_engine(const SpmvArgs &a, Epi &epi) {
+  constexpr int CAP = kCap / NRHS;  // entries staged per block
+  static_assert(CAP <= kBlock * kUnroll, "one unrolled pass must cover a block");
+  static_assert(kCap < 65536, "row offsets are stored in 16 bits");
+  __shared__ double2 prod[kCap];
+  __shared__ unsigned short rofs[kCap + 1];  // row starts of the block, relative to e0 (<= kCap)
+  const int tid = threadIdx.x;
+  int64_t k = (int64_t)xcd_contiguous_index() * a.blocks_per_wg;
+  const int64_t kend = min((int64_t)a.nblk, k + a.blocks_per_wg);
+  if (k >= kend) return;
+  int c[kUnroll];
+  double2 v[kUnroll];
+  auto issue = [&](const BlockDesc &d) {
+    const int32_t *cb = a.col + d.e0;
+    const double2 *vb = a.val + d.e0;
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int i = tid + u * kBlock;
+      if (i < d.cnt) {
+        c[u] = load_stream(cb + i);
+        v[u] = load_stream(vb + i);
+      }
+    }
+  };
+  BlockDesc cur = block_desc(a, k, CAP);
+  if (cur.fits) issue(cur);
+  while (k < kend) {
+    if (cur.fits) {
+      // descriptor of the next block first: its latency overlaps the gathers
+      BlockDesc nxt{};
+      nxt.fits = false;
+      if (k + 1 < kend) nxt = block_desc(a, k + 1, CAP);
+      // products of the staged block (x gathered) into LDS
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int i = tid + u * kBlock;
+        if (i < cur.cnt) {
+#pragma unroll
+          for (int r = 0; r < NRHS; ++r)
+            prod[i * NRHS + r] = cmul(v[u], a.x[(int64_t)c[u] * NRHS + r]);
+        }
+      }
+      const int nr = (int)(cur.r1 - cur.r0);
+      for (int i = tid; i <= nr; i += kBlock)
+        rofs[i] = (unsigned short)(a.rp[cur.r0 + i] - cur.e0);
+      int L = 64;
+      while (L > 1 && nr * L > kBlock) L >>= 1;
+      const int rpp = kBlock / L;
+      const int g = tid / L, lane = tid & (L - 1);
+      typename Epi::Pre pre{};
+      if (g < nr && lane == 0) pre = epi.pre(cur.r0 + g);
+      // next block's entries, in flight during this block's reduction
+      if (nxt.fits) issue(nxt);
+      __syncthreads();
+      for (int base = 0; base < nr; base += rpp) {
+        const int ri = base + g;
+        double acc[2 * NRHS];
+#pragma unroll
+        for (int q = 0; q < 2 * NRHS; ++q) acc[q] = 0.0;
+        if (ri < nr) {
+          const int s = rofs[ri], t = rofs[ri + 1];
+          for (int q = s + lane; q < t; q += L) {
+#pragma unroll
+            for (int r = 0; r < NRHS; ++r) {
+              const double2 pv = prod[q * NRHS + r];
+              acc[2 * r] += pv.x;
+              acc[2 * r + 1] += pv.y;
+            }
+          }
+        }
+        for (int off = L >> 1; off > 0; off >>= 1) {
+#pragma unroll
+          for (int q = 0; q < 2 * NRHS; ++q) acc[q] += __shfl_xor(acc[q], off, L);
+        }
+        if (ri < nr && lane == 0) {
+          if (base == 0) epi(cur.r0 + ri, acc, pre);
+          else epi(cur.r0 + ri, acc, epi.pre(cur.r0 + ri));
+        }
+      }
+      __syncthreads();
+      cur = nxt;
+      ++k;
+    } else {
+      // a block whose rows exceed the LDS stage: one row at a time, the
+      // whole workgroup strides through it, fixed tree reduction
+      double *red = reinterpret_cast<double *>(prod);
+      for (int64_t row = cur.r0; row < cur.r1; ++row) {
+        double acc[2 * NRHS];
+#pragma unroll
+        for (int q = 0; q < 2 * NRHS; ++q) acc[q] = 0.0;
+        for (int64_t e = a.rp[row] + tid; e < a.rp[row + 1]; e += kBlock) {
+          const double2 vv = a.val[e];
+          const int64_t cc = a.col[e];
+#pragma unroll
+          for (int r = 0; r < NRHS; ++r)
+            cmac(acc[2 * r], acc[2 * r + 1], vv, a.x[cc * NRHS + r]);
+        }
+#pragma unroll
+        for (int q = 0; q < 2 * NRHS; ++q) red[q * kBlock + tid] = acc[q];
+        __syncthreads();
+        for (int w2 = kBlock / 2; w2 > 0; w2 >>= 1) {
+          if (tid < w2) {
+#pragma unroll
+            for (int q = 0; q < 2 * NRHS; ++q) red[q * kBlock + tid] += red[q * kBlock + tid + w2];
+          }
+          __syncthreads();
+        }
+        if (tid == 0) {
+#pragma unroll
+          for (int q = 0; q < 2 * NRHS; ++q) acc[q] = red[q * kBlock];
+          epi(row, acc, epi.pre(row));
+        }
+        __syncthreads();
+      }
+      ++k;
+      if (k < kend) {
+        cur = block_desc(a, k, CAP);
+        if (cur.fits) issue(cur);
+      }
     }
   }
-#pragma unroll
-  for (int off = LPR / 2; off > 0; off >>= 1) {
-    ax += __shfl_xor(ax, off, LPR);
-    ay += __shfl_xor(ay, off, LPR);
-  }
-  return make_double2(ax, ay);
 }
+
+// Jagged engine.  Stage: the block's entries stream in memory order (a wave
+// reads 64 consecutive entries per instruction); in the position-major
+// layout consecutive lanes hold the same position of rows ranked next to
+// each other, so the leading H rho entries of rows of one rho-row gather x
+// at consecutive addresses.  Products go to LDS.  Reduce: L lanes per row
+// walk its positions (reading consecutive LDS words across rows), then a
+// butterfly; the epilogue runs for the row's original index.  Workgroups take
+// blocks k = blockIdx.x, blockIdx.x + gridDim.x, ... so the whole device
+// sweeps the matrix front to back together.
+template <class Epi>
+__device__ __forceinline__ void jagged_engine(const SpmvArgs &a, Epi &epi) {
+  __shared__ double2 prod[kCap];
+  __shared__ unsigned short spos[kCap + 1];
+  const int tid = threadIdx.x;
+  for (int64_t k = blockIdx.x; k < a.njag; k += gridDim.x) {
+    const JagRec R = a.jrec[k];
+    if (R.flags & kJagLong) {
+      // rows longer than the stage: CSR order, one row at a time
+      double *red = reinterpret_cast<double *>(prod);
+      for (int64_t row = R.r0; row < R.r0 + R.nr; ++row) {
+        double acc[2] = {0.0, 0.0};
+        for (int64_t e = a.rp[row] + tid; e < a.rp[row + 1]; e += kBlock)
+          cmac(acc[0], acc[1], a.jval[e], a.x[a.jcol[e]]);
+        red[tid] = acc[0];
+        red[kBlock + tid] = acc[1];
+        __syncthreads();
+        for (int w2 = kBlock / 2; w2 > 0; w2 >>= 1) {
+          if (tid < w2) {
+            red[tid] += red[tid + w2];
+            red[kBlock + tid] += red[kBlock + tid + w2];
+          }
+          __syncthreads();
+        }
+        if (tid == 0) {
+          acc[0] = red[0];
+          acc[1] = red[kBlock];
+          epi(row, acc, epi.pre(row));
+        }
+        __syncthreads();
+      }
+      continue;
+    }
+    int c[kUnroll];
+    double2 v[kUnroll];
+    const int32_t *cb = a.jcol + R.e0;
+    const double2 *vb = a.jval + R.e0;
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int i = tid + u * kBlock;
+      if (i < R.cnt) {
+        c[u] = load_stream(cb + i);
+        v[u] = load_stream(vb + i);
+      }
+    }
+    for (int i = tid; i <= R.maxlen; i += kBlock) spos[i] = a.jps[R.pso + i];
+    int L = 64;
+    while (L > 1 && R.nr * L > kBlock) L >>= 1;
+    const int g = tid / L, lane = tid & (L - 1);
+    int orow = 0;
+    typename Epi::Pre pre{};
+    if (g < R.nr && lane == 0) {
+      orow = a.jperm[R.r0 + g];
+      pre = epi.pre(R.r0 + orow);
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int i = tid + u * kBlock;
+      if (i < R.cnt) prod[i] = cmul(v[u], a.x[c[u]]);
+    }
+    __syncthreads();
+    const int rpp = kBlock / L;
+    for (int base = 0; base < R.nr; base += rpp) {
+      const int r = base + g;
+      double acc[2] = {0.0, 0.0};
+      if (r < R.nr) {
+        for (int p = lane; p < R.maxlen; p += L) {
+          const int s0 = spos[p], s1 = spos[p + 1];
+          if (r >= s1 - s0) break;  // rows are ranked by length: no later position either
+          const double2 q = prod[s0 + r];
+          acc[0] += q.x;
+          acc[1] += q.y;
+        }
+      }
+      for (int off = L >> 1; off > 0; off >>= 1) {
+        acc[0] += __shfl_xor(acc[0], off, L);
+        acc[1] += __shfl_xor(acc[1], off, L);
+      }
+      if (r < R.nr && lane == 0) {
+        if (base == 0) {
+          epi(R.r0 + orow, acc, pre);
+        } else {
+          const int o2 = a.jperm[R.r0 + r];
+          epi(R.r0 + o2, acc, epi.pre(R.r0 + o2));
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int LPR, class Epi>
+__device__ __forceinline__ void vector_engine(const SpmvArgs &a, Epi &epi) {
+  constexpr int RPI = kBlock / LPR;
+  const int g = threadIdx.x / LPR, lane = threadIdx.x % LPR;
+  const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_block;
+  const int64_t r1 = min(a.n, r0 + a.rows_per_block);
+  for (int64_t base = r0; base < r1; base += RPI) {
+    const int64_t row = base + g;
+    double acc[2] = {0.0, 0.0};
+    if (row < r1) {
+      for (int64_t e = a.rp[row] + lane; e < a.rp[row + 1]; e += LPR)
+        cmac(acc[0], acc[1], load_stream(a.val + e), a.x[load_stream(a.col + e)]);
+    }
+#pragma unroll
+    for (int off = LPR / 2; off > 0; off >>= 1) {
+      acc[0] += __shfl_xor(acc[0], off, LPR);
+      acc[1] += __shfl_xor(acc[1], off, LPR);
+    }
+    if (row < r1 && lane == 0) epi(row, acc, epi.pre(row));
+  }
+}
+
+// Engines: 0 = jagged layout, 3 = CSR stream, 4..64 = vector with that many
+// lanes per row.
+template <int ENGINE, class Epi>
+__device__ __forceinline__ void run_engine(const SpmvArgs &a, Epi &epi) {
+  if constexpr (ENGINE == 0)
+    jagged_engine(a, epi);
+  else if constexpr (ENGINE == 3)
+    stream_engine<1>(a, epi);
+  else
+    vector_engine<ENGINE>(a, epi);
+}
+
+// ---------------------------------------------------------------- epilogues
+
+// Each epilogue names what it reads per row (Pre) so the engine can fetch it
+// ahead of the reduction.
+struct NoPre {};
+
+struct TaylorEpi {  // y = alpha A x ; F_out = F_in + y ; norms
+  const SpmvArgs &a;
+  unsigned long long mb = 0, mf = 0, mb0 = 0;
+  typedef double2 Pre;
+  __device__ explicit TaylorEpi(const SpmvArgs &args) : a(args) {}
+  __device__ __forceinline__ Pre pre(int64_t row) const { return a.fin[row]; }
+  __device__ __forceinline__ void operator()(int64_t row, const double *acc, Pre f) {
+    const double2 y = make_double2(a.alpha * acc[0], a.alpha * acc[1]);
+    a.y[row] = y;
+    if (a.j == 1) mb0 = umax(mb0, abs_bits(cabs2(f)));
+    f.x += y.x;
+    f.y += y.y;
+    a.fout[row] = f;
+    mb = umax(mb, abs_bits(cabs2(y)));
+    mf = umax(mf, abs_bits(cabs2(f)));
+  }
+};
+
+struct PlainEpi {  // y = alpha A x
+  const SpmvArgs &a;
+  typedef NoPre Pre;
+  __device__ explicit PlainEpi(const SpmvArgs &args) : a(args) {}
+  __device__ __forceinline__ Pre pre(int64_t) const { return Pre{}; }
+  __device__ __forceinline__ void operator()(int64_t row, const double *acc, Pre) {
+    a.y[row] = make_double2(a.alpha * acc[0], a.alpha * acc[1]);
+  }
+};
+
+struct PowerEpi {  // y = alpha A x ; max |y|
+  const SpmvArgs &a;
+  unsigned long long mk = 0;
+  typedef NoPre Pre;
+  __device__ explicit PowerEpi(const SpmvArgs &args) : a(args) {}
+  __device__ __forceinline__ Pre pre(int64_t) const { return Pre{}; }
+  __device__ __forceinline__ void operator()(int64_t row, const double *acc, Pre) {
+    const double2 y = make_double2(a.alpha * acc[0], a.alpha * acc[1]);
+    a.y[row] = y;
+    mk = umax(mk, abs_bits(cabs2(y)));
+  }
+};
+
+struct Spmm2Epi {  // two right-hand sides for the 1-norm estimator
+  double2 *Y;
+  int mode;
+  double2 *sgn;
+  double *h;
+  double s0 = 0.0, s1 = 0.0;
+  typedef NoPre Pre;
+  __device__ __forceinline__ Pre pre(int64_t) const { return Pre{}; }
+  __device__ __forceinline__ void operator()(int64_t row, const double *acc, Pre) {
+    const double2 y0 = make_double2(acc[0], acc[1]), y1 = make_double2(acc[2], acc[3]);
+    Y[2 * row] = y0;
+    Y[2 * row + 1] = y1;
+    const double m0 = cabs2(y0), m1 = cabs2(y1);
+    if (mode == 1) {
+      s0 += m0;
+      s1 += m1;
+      sgn[2 * row] = m0 > 0.0 ? make_double2(y0.x / m0, y0.y / m0) : make_double2(1.0, 0.0);
+      sgn[2 * row + 1] = m1 > 0.0 ? make_double2(y1.x / m1, y1.y / m1) : make_double2(1.0, 0.0);
+    } else if (mode == 2) {
+      h[row] = m0 > m1 ? m0 : m1;
+    }
+  }
+};
 
 // --------------------------------------------------------------------------
 // Superoperator assembly: one thread per row r = a*N + b.
@@ -131,44 +490,124 @@ __global__ __launch_bounds__(kBlock) void assemble_kernel(AssembleArgs A, int64_
   const double2 dval =
       make_double2(-0.5 * w * (A.K[a] + A.K[b]) + (a == b ? w * A.rdiag[a] : 0.0),
                    -ch * (A.hdiag[a] - A.hdiag[b]));
-  const int64_t INF = INT64_MAX;
-  int64_t i1 = ha0, i2 = hb0;
-  int64_t i3 = (a == b) ? ra0 : 0, e3 = (a == b) ? ra1 : 0;
-  bool diag_done = false;
+  // Each row is written in structural order: the H rho entries (column
+  // c N + b, ascending c), the diagonal, the rho H entries (column a N + c,
+  // ascending c), then the population-transfer entries (column j (N + 1),
+  // ascending j).  Rows of one rho-row a then share the column offsets c N of
+  // their leading entries, which the product kernels use to coalesce gathers.
   int64_t o = start;
-  for (;;) {
-    // S1: rho_cb terms, column c N + b, value sigma(-i)(1-w) H_ac
-    const int64_t k1 = i1 < ha1 ? (int64_t)A.hc[i1] * N + b : INF;
-    // S2: rho_ac terms, column a N + c, value sigma(+i)(1-w) conj(H_bc), and the diagonal
-    const int64_t kh = i2 < hb1 ? a * N + A.hc[i2] : INF;
-    const int64_t kd = diag_done ? INF : a * N + b;
-    const int64_t k2 = kh < kd ? kh : kd;
-    // S3: population transfer rho_jj, column j (N + 1), value w R_aj
-    const int64_t k3 = i3 < e3 ? (int64_t)A.rc[i3] * (N + 1) : INF;
-    if (k1 == INF && k2 == INF && k3 == INF) break;
-    int64_t key;
-    double2 v;
-    if (k1 < k2 && k1 < k3) {
-      const double2 h = A.hv[i1++];
-      key = k1;
-      v = make_double2(ch * h.y, -ch * h.x);
-    } else if (k2 < k3) {
-      key = k2;
-      if (kd < kh) {
-        v = dval;
-        diag_done = true;
-      } else {
-        const double2 h = A.hv[i2++];
-        v = make_double2(ch * h.y, ch * h.x);
-      }
-    } else {
-      key = k3;
-      v = make_double2(w * A.rv[i3++], 0.0);
-    }
-    A.col[o] = (int32_t)key;
-    A.val[o] = v;
-    ++o;
+  // sigma(-i)(1-w) H_ac on rho_cb
+  for (int64_t i = ha0; i < ha1; ++i, ++o) {
+    const double2 h = A.hv[i];
+    A.col[o] = (int32_t)((int64_t)A.hc[i] * N + b);
+    A.val[o] = make_double2(ch * h.y, -ch * h.x);
   }
+  A.col[o] = (int32_t)(a * N + b);
+  A.val[o] = dval;
+  ++o;
+  // sigma(+i)(1-w) conj(H_bc) on rho_ac
+  for (int64_t i = hb0; i < hb1; ++i, ++o) {
+    const double2 h = A.hv[i];
+    A.col[o] = (int32_t)(a * N + A.hc[i]);
+    A.val[o] = make_double2(ch * h.y, ch * h.x);
+  }
+  // w R_aj on rho_jj
+  if (a == b) {
+    for (int64_t i = ra0; i < ra1; ++i, ++o) {
+      A.col[o] = (int32_t)((int64_t)A.rc[i] * (N + 1));
+      A.val[o] = make_double2(w * A.rv[i], 0.0);
+    }
+  }
+}
+
+// Row blocks of the stream engine: block k starts at the first row whose
+// first entry index is >= k B.
+__global__ void row_blocks_kernel(const int64_t *rp, int64_t n, int64_t B, int32_t *blk,
+                                  int64_t nblk) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > nblk) return;
+  if (k == nblk) {
+    blk[k] = (int32_t)n;
+    return;
+  }
+  const int64_t target = k * B;
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (rp[mid] < target) lo = mid + 1;
+    else hi = mid;
+  }
+  blk[k] = (int32_t)lo;
+}
+
+// Longest row of each row block.
+__global__ void jag_measure_kernel(const int64_t *rp, const int32_t *blk, int64_t nblk,
+                                   int32_t *maxlen) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nblk) return;
+  int64_t m = 0;
+  for (int64_t r = blk[k]; r < blk[k + 1]; ++r) m = max(m, rp[r + 1] - rp[r]);
+  maxlen[k] = (int32_t)m;
+}
+
+// One workgroup per row block: rank rows by length (longest first, ties by
+// row), count rows per position, scatter the entries position-major.
+__global__ __launch_bounds__(kBlock) void jag_build_kernel(
+    const int64_t *rp, const int32_t *col, const double2 *val, const int32_t *blk,
+    const int32_t *maxlen_arr, const int32_t *pso_arr, JagRec *rec, int32_t *jcol,
+    double2 *jval, unsigned short *jperm, unsigned short *jps) {
+  __shared__ int lens[kCap];
+  __shared__ unsigned short rank[kCap];
+  __shared__ int ps[kCap + 1];
+  const int64_t k = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int64_t r0 = blk[k], r1 = blk[k + 1];
+  const int64_t e0 = rp[r0];
+  const int64_t cnt = rp[r1] - e0;
+  const int64_t nr = r1 - r0;
+  const int maxlen = maxlen_arr[k];
+  const bool fits = cnt <= kCap && nr <= kCap;
+  if (!fits) {
+    for (int64_t e = e0 + tid; e < e0 + cnt; e += kBlock) {
+      jcol[e] = col[e];
+      jval[e] = val[e];
+    }
+    for (int64_t i = tid; i < nr; i += kBlock) jperm[r0 + i] = (unsigned short)(i & 0xffff);
+    if (tid == 0) rec[k] = JagRec{e0, (int32_t)r0, (int32_t)cnt, (int32_t)nr, maxlen, pso_arr[k], kJagLong};
+    return;
+  }
+  const int inr = (int)nr;
+  for (int i = tid; i < inr; i += kBlock) lens[i] = (int)(rp[r0 + i + 1] - rp[r0 + i]);
+  __syncthreads();
+  for (int i = tid; i < inr; i += kBlock) {
+    const int li = lens[i];
+    int rk = 0;
+    for (int j = 0; j < inr; ++j) rk += (lens[j] > li) || (lens[j] == li && j < i);
+    rank[i] = (unsigned short)rk;
+    jperm[r0 + rk] = (unsigned short)i;
+  }
+  for (int p = tid; p < maxlen; p += kBlock) {
+    int cp = 0;
+    for (int i = 0; i < inr; ++i) cp += lens[i] > p;
+    ps[p + 1] = cp;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    ps[0] = 0;
+    for (int p = 1; p <= maxlen; ++p) ps[p] += ps[p - 1];
+  }
+  __syncthreads();
+  for (int p = tid; p <= maxlen; p += kBlock) jps[pso_arr[k] + p] = (unsigned short)ps[p];
+  for (int i = tid; i < inr; i += kBlock) {
+    const int rk = rank[i];
+    const int64_t src = rp[r0 + i];
+    for (int q = 0; q < lens[i]; ++q) {
+      const int64_t dst = e0 + ps[q] + rk;
+      jcol[dst] = col[src + q];
+      jval[dst] = val[src + q];
+    }
+  }
+  if (tid == 0) rec[k] = JagRec{e0, (int32_t)r0, (int32_t)cnt, (int32_t)nr, maxlen, pso_arr[k], 0};
 }
 
 // max over rows of sum_e |val[e]|  (on the adjoint this is ||L||_1).
@@ -201,55 +640,45 @@ __global__ void copy_kernel(double2 *dst, const double2 *src, int64_t n) {
 // --------------------------------------------------------------------------
 // Term j of one scaling step of the single-time algorithm.
 // --------------------------------------------------------------------------
-template <int LPR, bool TAYLOR>
+
+// Returns true when the step already passed the two-term test (then every
+// workgroup of this launch returns at once).  Evaluated identically by every
+// workgroup from values written by earlier launches.
+__device__ __forceinline__ bool taylor_prologue(const SpmvArgs &a) {
+  StepSlots *S = &a.st->step[a.par];
+  if (a.j >= 2) {
+    if (*(volatile int *)&S->stop) return true;
+    const double c1 = bits_to_d(a.j == 2 ? S->b0 : S->b[a.j - 2]);
+    const double c2 = bits_to_d(S->b[a.j - 1]);
+    const double f = bits_to_d(S->f[a.j - 1]);
+    if (c1 + c2 <= a.tol * f) {
+      if (threadIdx.x == 0) *(volatile int *)&S->stop = 1;
+      return true;
+    }
+  } else if (blockIdx.x == 0) {
+    // first term of a step: clear the other parity for the next step
+    unsigned int *o = (unsigned int *)&a.st->step[a.par ^ 1];
+    for (int i = threadIdx.x; i < (int)(sizeof(StepSlots) / 4); i += kBlock) o[i] = 0u;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&a.st->products, 1ull);
+  return false;
+}
+
+template <int ENGINE>
 __global__ __launch_bounds__(kBlock) void term_kernel(SpmvArgs a) {
-  StepSlots *S = nullptr;
-  if (TAYLOR) {
-    S = &a.st->step[a.par];
-    if (a.j >= 2) {
-      if (*(volatile int *)&S->stop) return;
-      const double c1 = bits_to_d(a.j == 2 ? S->b0 : S->b[a.j - 2]);
-      const double c2 = bits_to_d(S->b[a.j - 1]);
-      const double f = bits_to_d(S->f[a.j - 1]);
-      if (c1 + c2 <= a.tol * f) {
-        if (threadIdx.x == 0) *(volatile int *)&S->stop = 1;
-        return;
-      }
-    } else if (blockIdx.x == 0) {
-      // first term of a step: clear the other parity for the next step
-      unsigned int *o = (unsigned int *)&a.st->step[a.par ^ 1];
-      for (int i = threadIdx.x; i < (int)(sizeof(StepSlots) / 4); i += kBlock) o[i] = 0u;
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&a.st->products, 1ull);
-  }
-  constexpr int RPI = kBlock / LPR;
-  const int g = threadIdx.x / LPR, lane = threadIdx.x % LPR;
-  const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_block;
-  const int64_t r1 = min(a.n, r0 + a.rows_per_block);
-  unsigned long long mb = 0, mf = 0, mb0 = 0;
-  for (int64_t base = r0; base < r1; base += RPI) {
-    const int64_t row = base + g;
-    const bool valid = row < r1;
-    const double2 acc = row_dot<LPR>(a.rp, a.col, a.val, a.x, row, valid, lane);
-    if (valid && lane == 0) {
-      const double2 y = make_double2(a.alpha * acc.x, a.alpha * acc.y);
-      a.y[row] = y;
-      if (TAYLOR) {
-        double2 f = a.fin[row];
-        if (a.j == 1) mb0 = umax(mb0, abs_bits(cabs2(f)));
-        f.x += y.x;
-        f.y += y.y;
-        a.fout[row] = f;
-        mb = umax(mb, abs_bits(cabs2(y)));
-        mf = umax(mf, abs_bits(cabs2(f)));
-      }
-    }
-  }
-  if (TAYLOR) {
-    unsigned long long v[3] = {mb, mf, mb0};
-    unsigned long long *const dst[3] = {&S->b[a.j], &S->f[a.j], a.j == 1 ? &S->b0 : nullptr};
-    block_umax_to<3>(v, dst, &a.st->nonfinite);
-  }
+  if (taylor_prologue(a)) return;
+  TaylorEpi epi(a);
+  run_engine<ENGINE>(a, epi);
+  StepSlots *S = &a.st->step[a.par];
+  unsigned long long v[3] = {epi.mb, epi.mf, epi.mb0};
+  unsigned long long *const dst[3] = {&S->b[a.j], &S->f[a.j], a.j == 1 ? &S->b0 : nullptr};
+  block_umax_to<3>(v, dst, &a.st->nonfinite);
+}
+
+template <int ENGINE>
+__global__ __launch_bounds__(kBlock) void plain_kernel(SpmvArgs a) {
+  PlainEpi epi(a);
+  run_engine<ENGINE>(a, epi);
 }
 
 // --------------------------------------------------------------------------
@@ -284,28 +713,15 @@ __device__ __forceinline__ bool point_done(const DeviceState *st, PointSlots *pt
   return false;
 }
 
-template <int LPR>
+template <int ENGINE>
 __global__ __launch_bounds__(kBlock) void series_power_kernel(SpmvArgs a, PointSlots *pt, int k,
                                                               int p) {
   if (point_done(a.st, pt, k, p, a.tol)) return;
   if (p <= *(volatile int *)&a.st->series.mhat) return;  // K_p already formed
   if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&a.st->products, 1ull);
-  constexpr int RPI = kBlock / LPR;
-  const int g = threadIdx.x / LPR, lane = threadIdx.x % LPR;
-  const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_block;
-  const int64_t r1 = min(a.n, r0 + a.rows_per_block);
-  unsigned long long mk = 0;
-  for (int64_t base = r0; base < r1; base += RPI) {
-    const int64_t row = base + g;
-    const bool valid = row < r1;
-    const double2 acc = row_dot<LPR>(a.rp, a.col, a.val, a.x, row, valid, lane);
-    if (valid && lane == 0) {
-      const double2 y = make_double2(a.alpha * acc.x, a.alpha * acc.y);
-      a.y[row] = y;
-      mk = umax(mk, abs_bits(cabs2(y)));
-    }
-  }
-  unsigned long long v[1] = {mk};
+  PowerEpi epi(a);
+  run_engine<ENGINE>(a, epi);
+  unsigned long long v[1] = {epi.mk};
   unsigned long long *const dst[1] = {&a.st->series.kn[p]};
   block_umax_to<1>(v, dst, &a.st->nonfinite);
 }
@@ -317,7 +733,7 @@ __global__ __launch_bounds__(kBlock) void series_accum_kernel(DeviceState *st, P
   if (*(volatile int *)&pt->stop) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(&st->series.mhat, p);
   const double kp = pow((double)k, (double)p);
-  unsigned long long mf = 0;
+  unsigned long long mf[1] = {0};
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kBlock) {
     const double2 kv = Kp[i];
@@ -325,67 +741,24 @@ __global__ __launch_bounds__(kBlock) void series_accum_kernel(DeviceState *st, P
     f.x = fma(kp, kv.x, f.x);
     f.y = fma(kp, kv.y, f.y);
     F[i] = f;
-    mf = umax(mf, abs_bits(cabs2(f)));
+    mf[0] = umax(mf[0], abs_bits(cabs2(f)));
   }
-  unsigned long long v[1] = {mf};
   unsigned long long *const dst[1] = {&pt->f[p]};
-  block_umax_to<1>(v, dst, &st->nonfinite);
+  block_umax_to<1>(mf, dst, &st->nonfinite);
 }
 
 // --------------------------------------------------------------------------
-// Two right-hand sides (block 1-norm estimation).
+// Two right-hand sides (block 1-norm estimation), stream engine.
 // --------------------------------------------------------------------------
-template <int LPR>
-__global__ __launch_bounds__(kBlock) void spmm2_kernel(int64_t n, const int64_t *__restrict__ rp,
-                                                       const int32_t *__restrict__ col,
-                                                       const double2 *__restrict__ val,
-                                                       const double2 *__restrict__ X,
-                                                       double2 *__restrict__ Y, int mode,
-                                                       double *part, double2 *sgn, double *h,
-                                                       int64_t rows_per_block) {
-  constexpr int RPI = kBlock / LPR;
-  const int g = threadIdx.x / LPR, lane = threadIdx.x % LPR;
-  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
-  const int64_t r1 = min(n, r0 + rows_per_block);
-  double s0 = 0.0, s1 = 0.0;
-  for (int64_t base = r0; base < r1; base += RPI) {
-    const int64_t row = base + g;
-    double a0x = 0, a0y = 0, a1x = 0, a1y = 0;
-    if (row < r1) {
-      for (int64_t e = rp[row] + lane; e < rp[row + 1]; e += LPR) {
-        const int c = col[e];
-        const double2 v = val[e];
-        cmac(a0x, a0y, v, X[2 * (int64_t)c]);
-        cmac(a1x, a1y, v, X[2 * (int64_t)c + 1]);
-      }
-    }
-#pragma unroll
-    for (int off = LPR / 2; off > 0; off >>= 1) {
-      a0x += __shfl_xor(a0x, off, LPR);
-      a0y += __shfl_xor(a0y, off, LPR);
-      a1x += __shfl_xor(a1x, off, LPR);
-      a1y += __shfl_xor(a1y, off, LPR);
-    }
-    if (row < r1 && lane == 0) {
-      const double2 y0 = make_double2(a0x, a0y), y1 = make_double2(a1x, a1y);
-      Y[2 * row] = y0;
-      Y[2 * row + 1] = y1;
-      const double m0 = cabs2(y0), m1 = cabs2(y1);
-      if (mode == 1) {
-        s0 += m0;
-        s1 += m1;
-        sgn[2 * row] = m0 > 0.0 ? make_double2(y0.x / m0, y0.y / m0) : make_double2(1.0, 0.0);
-        sgn[2 * row + 1] = m1 > 0.0 ? make_double2(y1.x / m1, y1.y / m1) : make_double2(1.0, 0.0);
-      } else if (mode == 2) {
-        h[row] = m0 > m1 ? m0 : m1;
-      }
-    }
-  }
+__global__ __launch_bounds__(kBlock) void spmm2_kernel(SpmvArgs a, int mode, double *part,
+                                                       double2 *sgn, double *h) {
+  Spmm2Epi epi{a.y, mode, sgn, h};
+  stream_engine<2>(a, epi);
   if (mode == 1) {
-    // deterministic per-block column sums: fixed tree over the workgroup
+    // deterministic per-workgroup column sums: fixed tree over the threads
     __shared__ double sm0[kBlock], sm1[kBlock];
-    sm0[threadIdx.x] = s0;
-    sm1[threadIdx.x] = s1;
+    sm0[threadIdx.x] = epi.s0;
+    sm1[threadIdx.x] = epi.s1;
     __syncthreads();
     for (int w = kBlock / 2; w > 0; w >>= 1) {
       if ((int)threadIdx.x < w) {
@@ -438,20 +811,36 @@ inline int blocks_for(int64_t n, int per = kBlock) {
   return (int)(b < 1 ? 1 : b);
 }
 
-template <int LPR>
-hipError_t term_dispatch(const SpmvArgs &a, int grid, hipStream_t s, bool taylor) {
-  if (taylor)
-    hipLaunchKernelGGL((term_kernel<LPR, true>), dim3(grid), dim3(kBlock), 0, s, a);
-  else
-    hipLaunchKernelGGL((term_kernel<LPR, false>), dim3(grid), dim3(kBlock), 0, s, a);
-  return hipGetLastError();
-}
-
 }  // namespace
+
+// ------------------------------------------------------------------ launchers
 
 hipError_t launch_assemble(const AssembleArgs &a, int64_t n, hipStream_t s) {
   const int64_t nb = (n + kBlock - 1) / kBlock;
   hipLaunchKernelGGL(assemble_kernel, dim3((unsigned)nb), dim3(kBlock), 0, s, a, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_blocks(const int64_t *rp, int64_t n, int64_t B, int32_t *blk, int64_t nblk,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(row_blocks_kernel, dim3(blocks_for(nblk + 1)), dim3(kBlock), 0, s, rp, n, B,
+                     blk, nblk);
+  return hipGetLastError();
+}
+
+hipError_t launch_jag_measure(const int64_t *rp, const int32_t *blk, int64_t nblk, int32_t *maxlen,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(jag_measure_kernel, dim3(blocks_for(nblk)), dim3(kBlock), 0, s, rp, blk, nblk,
+                     maxlen);
+  return hipGetLastError();
+}
+
+hipError_t launch_jag_build(const int64_t *rp, const int32_t *col, const double2 *val,
+                            const int32_t *blk, int64_t nblk, const int32_t *maxlen,
+                            const int32_t *pso, JagRec *rec, int32_t *jcol, double2 *jval,
+                            unsigned short *jperm, unsigned short *jps, hipStream_t s) {
+  hipLaunchKernelGGL(jag_build_kernel, dim3((unsigned)nblk), dim3(kBlock), 0, s, rp, col, val, blk,
+                     maxlen, pso, rec, jcol, jval, jperm, jps);
   return hipGetLastError();
 }
 
@@ -478,26 +867,30 @@ hipError_t launch_copy(double2 *dst, const double2 *src, int64_t n, hipStream_t 
   return hipGetLastError();
 }
 
-hipError_t launch_taylor_term(const SpmvArgs &a, int lpr, int grid, hipStream_t s) {
-  switch (lpr) {
-    case 4: return term_dispatch<4>(a, grid, s, true);
-    case 8: return term_dispatch<8>(a, grid, s, true);
-    case 16: return term_dispatch<16>(a, grid, s, true);
-    case 32: return term_dispatch<32>(a, grid, s, true);
-    case 64: return term_dispatch<64>(a, grid, s, true);
-    default: return hipErrorInvalidValue;
+#define QSW_ENGINE_SWITCH(ENG, CALL)      \
+  switch (ENG) {                          \
+    case 0: CALL(0); break;               \
+    case 3: CALL(3); break;               \
+    case 4: CALL(4); break;               \
+    case 8: CALL(8); break;               \
+    case 16: CALL(16); break;             \
+    case 32: CALL(32); break;             \
+    case 64: CALL(64); break;             \
+    default: return hipErrorInvalidValue; \
   }
+
+hipError_t launch_taylor_term(const SpmvArgs &a, int engine, int grid, hipStream_t s) {
+#define QSW_L(E) hipLaunchKernelGGL(term_kernel<E>, dim3(grid), dim3(kBlock), 0, s, a)
+  QSW_ENGINE_SWITCH(engine, QSW_L)
+#undef QSW_L
+  return hipGetLastError();
 }
 
-hipError_t launch_spmv(const SpmvArgs &a, int lpr, int grid, hipStream_t s) {
-  switch (lpr) {
-    case 4: return term_dispatch<4>(a, grid, s, false);
-    case 8: return term_dispatch<8>(a, grid, s, false);
-    case 16: return term_dispatch<16>(a, grid, s, false);
-    case 32: return term_dispatch<32>(a, grid, s, false);
-    case 64: return term_dispatch<64>(a, grid, s, false);
-    default: return hipErrorInvalidValue;
-  }
+hipError_t launch_spmv(const SpmvArgs &a, int engine, int grid, hipStream_t s) {
+#define QSW_L(E) hipLaunchKernelGGL(plain_kernel<E>, dim3(grid), dim3(kBlock), 0, s, a)
+  QSW_ENGINE_SWITCH(engine, QSW_L)
+#undef QSW_L
+  return hipGetLastError();
 }
 
 hipError_t launch_series_init(DeviceState *st, PointSlots *pts, int npts, const double2 *Z,
@@ -510,26 +903,12 @@ hipError_t launch_series_init(DeviceState *st, PointSlots *pts, int npts, const 
   return hipGetLastError();
 }
 
-hipError_t launch_series_power(const SpmvArgs &a, PointSlots *pt, int k, int p, int lpr,
+hipError_t launch_series_power(const SpmvArgs &a, PointSlots *pt, int k, int p, int engine,
                                int grid, hipStream_t s) {
-  switch (lpr) {
-    case 4:
-      hipLaunchKernelGGL(series_power_kernel<4>, dim3(grid), dim3(kBlock), 0, s, a, pt, k, p);
-      break;
-    case 8:
-      hipLaunchKernelGGL(series_power_kernel<8>, dim3(grid), dim3(kBlock), 0, s, a, pt, k, p);
-      break;
-    case 16:
-      hipLaunchKernelGGL(series_power_kernel<16>, dim3(grid), dim3(kBlock), 0, s, a, pt, k, p);
-      break;
-    case 32:
-      hipLaunchKernelGGL(series_power_kernel<32>, dim3(grid), dim3(kBlock), 0, s, a, pt, k, p);
-      break;
-    case 64:
-      hipLaunchKernelGGL(series_power_kernel<64>, dim3(grid), dim3(kBlock), 0, s, a, pt, k, p);
-      break;
-    default: return hipErrorInvalidValue;
-  }
+#define QSW_L(E) \
+  hipLaunchKernelGGL(series_power_kernel<E>, dim3(grid), dim3(kBlock), 0, s, a, pt, k, p)
+  QSW_ENGINE_SWITCH(engine, QSW_L)
+#undef QSW_L
   return hipGetLastError();
 }
 
@@ -541,23 +920,9 @@ hipError_t launch_series_accum(DeviceState *st, PointSlots *pt, int k, int p, co
   return hipGetLastError();
 }
 
-int spmm2_blocks(int64_t n, int grid) {
-  constexpr int RPI = kBlock / 8;
-  int64_t rpb = (n + grid - 1) / grid;
-  rpb = (rpb + RPI - 1) / RPI * RPI;
-  return (int)((n + rpb - 1) / rpb);
-}
-
-hipError_t launch_spmm2(int64_t n, const int64_t *rp, const int32_t *col, const double2 *val,
-                        const double2 *X, double2 *Y, int mode, double *part, double2 *sgn,
-                        double *h, int grid, hipStream_t s) {
-  constexpr int LPR = 8;
-  constexpr int RPI = kBlock / LPR;
-  int64_t rpb = (n + grid - 1) / grid;
-  rpb = (rpb + RPI - 1) / RPI * RPI;
-  const int g = (int)((n + rpb - 1) / rpb);
-  hipLaunchKernelGGL(spmm2_kernel<LPR>, dim3(g), dim3(kBlock), 0, s, n, rp, col, val, X, Y, mode,
-                     part, sgn, h, rpb);
+hipError_t launch_spmm2(const SpmvArgs &a, int mode, double *part, double2 *sgn, double *h,
+                        int grid, hipStream_t s) {
+  hipLaunchKernelGGL(spmm2_kernel, dim3(grid), dim3(kBlock), 0, s, a, mode, part, sgn, h);
   return hipGetLastError();
 }
 
@@ -572,6 +937,20 @@ hipError_t launch_populations(const double2 *rho, int32_t N, int32_t count, doub
   hipLaunchKernelGGL(populations_kernel, dim3(blocks_for(total)), dim3(kBlock), 0, s, rho, N,
                      count, pops);
   return hipGetLastError();
+}
+
+int resident_workgroups(int which) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  hipError_t e;
+  if (which == 1)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, spmm2_kernel, kBlock, 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, term_kernel<0>, kBlock, 0);
+  if (e != hipSuccess || per < 1) per = 1;
+  return cus * per;
 }
 
 }  // namespace qsw

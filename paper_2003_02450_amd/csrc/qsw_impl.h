@@ -8,7 +8,7 @@ namespace qsw {
 
 constexpr int kMMax = 55;   // largest Taylor degree
 constexpr int kPMax = 8;    // largest p in alpha_p = max(d_p, d_{p+1})
-constexpr int kMaxBlockPoints = 4096;  // time-series block length handled per launch chain
+constexpr int kCap = 2048;  // LDS product slots per workgroup of the stream engine
 
 // Norm slots of one scaling step of the single-time algorithm.  Maxima of
 // non-negative doubles are kept as their IEEE bit patterns, whose unsigned
@@ -64,12 +64,41 @@ struct AssembleArgs {
   double2 *val;
 };
 
+// Jagged-block execution layout: the rows of each block are ranked by
+// length (longest first) and the block's entries stored position-major:
+// entry p of the row of rank r sits at e0 + ps[pso + p] + r.  Blocks whose
+// entries exceed the LDS stage keep the CSR order (kJagLong).
+constexpr int kJagLong = 1;
+struct JagRec {
+  int64_t e0;      // first entry (same as the CSR row pointer of r0)
+  int32_t r0;      // first row
+  int32_t cnt;     // entries
+  int32_t nr;      // rows
+  int32_t maxlen;  // longest row
+  int32_t pso;     // offset of the block's position starts in ps[]
+  int32_t flags;
+};
+
 struct SpmvArgs {
   int64_t n;
   const int64_t *rp;
   const int32_t *col;
   const double2 *val;
-  const double2 *x;      // gathered vector
+  // stream engine: row blocks blk[0..nblk] (block k = rows blk[k]..blk[k+1]-1),
+  // each workgroup takes blocks_per_wg consecutive blocks
+  const int32_t *blk;
+  int32_t nblk;
+  int32_t blocks_per_wg;
+  // vector engine: contiguous rows per workgroup
+  int64_t rows_per_block;
+  // jagged engine
+  const JagRec *jrec;
+  int32_t njag;
+  const int32_t *jcol;
+  const double2 *jval;
+  const unsigned short *jperm;   // jperm[r0 + rank] = local row of that rank
+  const unsigned short *jps;
+  const double2 *x;      // gathered vector (NRHS interleaved columns for the estimator)
   const double2 *fin;    // accumulator in (Taylor mode)
   double2 *fout;         // accumulator out (may equal fin)
   double2 *y;            // output term
@@ -78,7 +107,6 @@ struct SpmvArgs {
   DeviceState *st;
   int par;               // scaling-step parity
   int j;                 // term index (1-based)
-  int64_t rows_per_block;// contiguous rows handled by one workgroup
 };
 
 // ---- launchers (kernels.hip) ----
@@ -88,34 +116,50 @@ hipError_t launch_row_abs_max(int64_t n, const int64_t *rp, const double2 *val,
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_copy(double2 *dst, const double2 *src, int64_t n, hipStream_t s);
 
+// Stream-engine row blocks: block k starts at the first row whose first
+// entry index is >= k B; blk has nblk + 1 entries.
+hipError_t launch_row_blocks(const int64_t *rp, int64_t n, int64_t B, int32_t *blk, int64_t nblk,
+                             hipStream_t s);
+
+// Jagged layout from the CSR and its row blocks: maxlen per block first,
+// then (with pso[] = exclusive prefix of maxlen + 1) the permuted arrays.
+hipError_t launch_jag_measure(const int64_t *rp, const int32_t *blk, int64_t nblk, int32_t *maxlen,
+                              hipStream_t s);
+hipError_t launch_jag_build(const int64_t *rp, const int32_t *col, const double2 *val,
+                            const int32_t *blk, int64_t nblk, const int32_t *maxlen,
+                            const int32_t *pso, JagRec *rec, int32_t *jcol, double2 *jval,
+                            unsigned short *jperm, unsigned short *jps, hipStream_t s);
+
+// Engine: 0 = jagged, 3 = CSR stream, 4/8/16/32/64 = vector with that many
+// lanes per row.
 // Single-time algorithm term j: y = alpha A x; F_out = F_in + y; norms into
 // st->step[par]; early exit when the previous terms already passed the test.
-hipError_t launch_taylor_term(const SpmvArgs &a, int lpr, int grid, hipStream_t s);
+hipError_t launch_taylor_term(const SpmvArgs &a, int engine, int grid, hipStream_t s);
 
 // y = alpha A x (no accumulation, no norms).
-hipError_t launch_spmv(const SpmvArgs &a, int lpr, int grid, hipStream_t s);
+hipError_t launch_spmv(const SpmvArgs &a, int engine, int grid, hipStream_t s);
 
 // Time-series branch.
 hipError_t launch_series_init(DeviceState *st, PointSlots *pts, int npts,
                               const double2 *Z, int64_t n, int grid, hipStream_t s);
 hipError_t launch_series_power(const SpmvArgs &a, PointSlots *pt, int k, int p,
-                               int lpr, int grid, hipStream_t s);
+                               int engine, int grid, hipStream_t s);
 hipError_t launch_series_accum(DeviceState *st, PointSlots *pt, int k, int p,
                                const double2 *Kp, const double2 *Z, double2 *F,
                                int64_t n, double tol, int grid, hipStream_t s);
 
-// Block 1-norm estimation helpers (two right-hand sides, interleaved rows).
-// mode 0: Y = A X; mode 1: Y = A X, column |.|_1 partials per block into
-// part[2*block + c] and S = sign(Y) into sgn; mode 2: Y = A X and
-// h[i] = max_c |Y[i][c]|.
-hipError_t launch_spmm2(int64_t n, const int64_t *rp, const int32_t *col,
-                        const double2 *val, const double2 *X, double2 *Y, int mode,
-                        double *part, double2 *sgn, double *h, int grid,
-                        hipStream_t s);
-// Number of workgroups launch_spmm2 uses for (n, grid): the length of part[]/2.
-int spmm2_blocks(int64_t n, int grid);
+// Block 1-norm estimation helpers: Y = A X for two interleaved right-hand
+// sides (stream engine; a.x = X, a.y = Y).  mode 0: product only; mode 1:
+// also column |.|_1 partial sums per workgroup into part[2*wg + c] and
+// S = sign(Y) into sgn; mode 2: also h[i] = max_c |Y[i][c]|.
+hipError_t launch_spmm2(const SpmvArgs &a, int mode, double *part, double2 *sgn, double *h,
+                        int grid, hipStream_t s);
 hipError_t launch_sum_partials(const double *part, int nblocks, double *out2,
                                hipStream_t s);
+
+// Workgroups of the stream kernels that fit on the device at once
+// (which = 0: single right-hand side, 1: two).
+int resident_workgroups(int which);
 
 hipError_t launch_populations(const double2 *rho, int32_t N, int32_t count, double *pops,
                               hipStream_t s);

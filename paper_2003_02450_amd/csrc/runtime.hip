@@ -136,9 +136,19 @@ struct qsw_superop_s {
   double2 *val = nullptr;
   qsw_info_t info{};
   // launch shape of the product kernels
-  int lpr = 8;
-  int grid = 2048;
-  int64_t rows_per_block = 0;
+  int engine = 0;                 // 0: stream engine; 4..64: vector engine lanes per row
+  int grid = 0;                   // workgroups of a product launch
+  int64_t rows_per_block = 0;     // vector engine
+  int32_t *blk = nullptr;         // stream engine row blocks
+  int32_t nblk = 0;
+  int32_t blocks_per_wg = 0;
+  // jagged layout (the propagation kernels' copy of the matrix)
+  JagRec *jrec = nullptr;
+  int32_t *jcol = nullptr;
+  double2 *jval = nullptr;
+  unsigned short *jperm = nullptr;
+  unsigned short *jps = nullptr;
+  int32_t njag = 0;
   // last propagate
   hipEvent_t ev_start = nullptr, ev_end = nullptr;
   unsigned long long *stats_dev = nullptr;  // [products, nonfinite]
@@ -148,19 +158,62 @@ struct qsw_superop_s {
 
 namespace {
 
-void choose_launch(qsw_superop_s *h) {
-  const double avg = h->n ? (double)h->nnz / (double)h->n : 1.0;
-  int lpr = avg <= 12 ? 4 : avg <= 48 ? 8 : avg <= 160 ? 16 : avg <= 600 ? 32 : 64;
-  lpr = env_int("QSW_LPR", lpr);
-  if (lpr != 4 && lpr != 8 && lpr != 16 && lpr != 32 && lpr != 64) lpr = 8;
+// Row blocks of the stream engine for one CSR: block budget B entries so that
+// a block (whose rows start before the next multiple of B) never exceeds the
+// LDS stage of `cap` entries when the longest row is at most cap/2; workgroup count from the
+// device's resident capacity, a multiple of 8 so that runs of blocks map to
+// one XCD each.
+struct Layout {
+  int32_t *blk = nullptr;
+  int32_t nblk = 0;
+  int32_t bpw = 0;
+  int grid = 0;
+};
+
+hipError_t make_layout(const int64_t *rp, int64_t n, int64_t nnz, int64_t maxrow, int cap,
+                       int resident, hipStream_t s, Layout &L) {
+  const int64_t B = (maxrow <= cap / 2) ? cap - maxrow : cap / 2;
+  const int64_t nblk = std::max<int64_t>(1, (nnz + B - 1) / B);
+  hipError_t e = dalloc(&L.blk, (size_t)nblk + 1);
+  if (e != hipSuccess) return e;
+  e = launch_row_blocks(rp, n, B, L.blk, nblk, s);
+  if (e != hipSuccess) return e;
+  int64_t G = std::max(8, resident / 8 * 8);
+  G = std::min<int64_t>(G, env_int("QSW_GRID", (int)G));
+  if (G > nblk) G = nblk;
+  if (G < 1) G = 1;
+  const int64_t bpw = (nblk + G - 1) / G;
+  int64_t g2 = (nblk + bpw - 1) / bpw;
+  if (g2 >= 8) g2 = (g2 + 7) / 8 * 8;
+  L.nblk = (int32_t)nblk;
+  L.bpw = (int32_t)bpw;
+  L.grid = (int)g2;
+  return hipSuccess;
+}
+
+void choose_vector_launch(qsw_superop_s *h, int lpr) {
   const int rpi = 256 / lpr;
-  int target = env_int("QSW_GRID", 2048);
-  if (target < 1) target = 2048;
+  const int target = 2048;
   int64_t rpb = (h->n + target - 1) / target;
   rpb = std::max<int64_t>(rpi, (rpb + rpi - 1) / rpi * rpi);
-  h->lpr = lpr;
+  h->engine = lpr;
   h->rows_per_block = rpb;
   h->grid = (int)((h->n + rpb - 1) / rpb);
+}
+
+// Upper bound of the longest row of L and of its adjoint: row (a, b) holds
+// deg_H(a) + deg_H(b) + 1 entries, plus the population-transfer entries when
+// a == b (rates of row a, or of column a for the adjoint).
+int64_t max_row_bound(const HostOps &op) {
+  int64_t dh = 0, dr = 0;
+  std::vector<int64_t> indeg(op.N, 0);
+  for (int32_t i = 0; i < op.N; ++i) {
+    dh = std::max<int64_t>(dh, op.hp[i + 1] - op.hp[i]);
+    dr = std::max<int64_t>(dr, op.rp[i + 1] - op.rp[i]);
+    for (int64_t e = op.rp[i]; e < op.rp[i + 1]; ++e) indeg[op.rc[e]]++;
+  }
+  for (int32_t i = 0; i < op.N; ++i) dr = std::max(dr, indeg[i]);
+  return 2 * dh + 1 + dr;
 }
 
 // Device copies of one operator set plus the assembled matrix.
@@ -281,21 +334,24 @@ uint64_t splitmix64(uint64_t x) {
 struct Estimator {
   int64_t n;
   hipStream_t s;
-  const int64_t *rp; const int32_t *col; const double2 *val;      // A
-  const int64_t *arp; const int32_t *acol; const double2 *aval;   // A^dagger
+  SpmvArgs fwd{}, adj{};          // A and A^dagger with their row blocks
+  int fwd_grid = 0, adj_grid = 0;
   double2 *X, *Y, *W0, *W1, *S;  // n x 2 interleaved blocks
   double *h, *part, *sums;
-  int grid, nb;
+  int nb;                         // partial sums per column (= fwd_grid)
   int products = 0;
 
   // out = (A or A^dagger)^p in; intermediates alternate between W0 and W1,
   // the epilogue `mode` runs on the last product only.
-  hipError_t power(bool adj, const double2 *in, double2 *out, int p, int mode) {
+  hipError_t power(bool adjoint, const double2 *in, double2 *out, int p, int mode) {
     const double2 *src = in;
     for (int i = 1; i <= p; ++i) {
       double2 *dst = (i == p) ? out : ((i & 1) ? W0 : W1);
-      hipError_t e = launch_spmm2(n, adj ? arp : rp, adj ? acol : col, adj ? aval : val, src, dst,
-                                  i == p ? mode : 0, part, S, h, grid, s);
+      SpmvArgs a = adjoint ? adj : fwd;
+      a.x = src;
+      a.y = dst;
+      hipError_t e = launch_spmm2(a, i == p ? mode : 0, part, S, h,
+                                  adjoint ? adj_grid : fwd_grid, s);
       if (e != hipSuccess) return e;
       ++products;
       src = dst;
@@ -414,6 +470,50 @@ struct Estimator {
   }
 };
 
+// Jagged layout of the handle's CSR over its row blocks (see JagRec).
+qsw_status_t build_jagged(qsw_superop_s *h, hipStream_t s) {
+  const int64_t nblk = h->nblk;
+  int32_t *dmax = nullptr, *dpso = nullptr;
+  std::vector<int32_t> hmax((size_t)nblk), hpso((size_t)nblk + 1);
+  hipError_t e;
+  do {
+    if ((e = dalloc(&dmax, (size_t)nblk)) != hipSuccess) break;
+    if ((e = launch_jag_measure(h->row_ptr, h->blk, nblk, dmax, s)) != hipSuccess) break;
+    if ((e = hipMemcpyAsync(hmax.data(), dmax, (size_t)nblk * sizeof(int32_t),
+                            hipMemcpyDeviceToHost, s)) != hipSuccess)
+      break;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) break;
+    hpso[0] = 0;
+    for (int64_t k = 0; k < nblk; ++k) {
+      const int64_t next = (int64_t)hpso[k] + hmax[k] + 1;
+      if (next > std::numeric_limits<int32_t>::max()) {
+        e = hipErrorInvalidValue;
+        break;
+      }
+      hpso[k + 1] = (int32_t)next;
+    }
+    if (e != hipSuccess) break;
+    if ((e = dalloc(&dpso, (size_t)nblk + 1)) != hipSuccess) break;
+    if ((e = hipMemcpyAsync(dpso, hpso.data(), ((size_t)nblk + 1) * sizeof(int32_t),
+                            hipMemcpyHostToDevice, s)) != hipSuccess)
+      break;
+    if ((e = dalloc(&h->jrec, (size_t)nblk)) != hipSuccess) break;
+    if ((e = dalloc(&h->jcol, (size_t)h->nnz)) != hipSuccess) break;
+    if ((e = dalloc(&h->jval, (size_t)h->nnz)) != hipSuccess) break;
+    if ((e = dalloc(&h->jperm, (size_t)h->n)) != hipSuccess) break;
+    if ((e = dalloc(&h->jps, (size_t)hpso[nblk])) != hipSuccess) break;
+    if ((e = launch_jag_build(h->row_ptr, h->col, h->val, h->blk, nblk, dmax, dpso, h->jrec,
+                              h->jcol, h->jval, h->jperm, h->jps, s)) != hipSuccess)
+      break;
+    e = hipStreamSynchronize(s);  // host arrays above must outlive the copies
+  } while (false);
+  dfree(dmax);
+  dfree(dpso);
+  if (e != hipSuccess) return status_of(e);
+  h->njag = (int32_t)nblk;
+  return QSW_OK;
+}
+
 qsw_status_t build_common(HostOps &op, double omega, hipStream_t s, qsw_superop_t *out) {
   auto t_start = std::chrono::steady_clock::now();
   const int32_t N = op.N;
@@ -438,7 +538,33 @@ qsw_status_t build_common(HostOps &op, double omega, hipStream_t s, qsw_superop_
   }
   qsw_status_t st = assemble(op, false, omega, s, &h->row_ptr, &h->col, &h->val, &h->nnz);
   if (st != QSW_OK) return fail(st);
-  choose_launch(h);
+  // product-kernel layout of L (stream engine unless QSW_ENGINE selects the
+  // vector engine with that many lanes per row)
+  const int64_t maxrow = max_row_bound(op);
+  const int resident1 = resident_workgroups(0);
+  {
+    Layout L;
+    hipError_t le = make_layout(h->row_ptr, n, h->nnz, maxrow, kCap, resident1, s, L);
+    if (le != hipSuccess) {
+      dfree(L.blk);
+      return fail(status_of(le));
+    }
+    h->blk = L.blk;
+    h->nblk = L.nblk;
+    h->blocks_per_wg = L.bpw;
+    // jagged layout over the same row blocks
+    st = build_jagged(h, s);
+    if (st != QSW_OK) return fail(st);
+    const int eng = env_int("QSW_ENGINE", 0);
+    h->engine = 0;
+    h->grid = std::max(1, std::min<int>(resident1, h->njag));
+    if (eng == 3) {
+      h->engine = 3;
+      h->grid = L.grid;
+    } else if (eng == 4 || eng == 8 || eng == 16 || eng == 32 || eng == 64) {
+      choose_vector_launch(h, eng);
+    }
+  }
   // adjoint for ||L||_1 and the estimator
   int64_t *arp = nullptr;
   int32_t *acol = nullptr;
@@ -448,6 +574,7 @@ qsw_status_t build_common(HostOps &op, double omega, hipStream_t s, qsw_superop_
   if (st != QSW_OK) return fail(st);
   unsigned long long *nbits = nullptr;
   Estimator E{};
+  Layout LF, LA;
   hipError_t e = hipSuccess;
   double norm1 = 0.0;
   do {
@@ -464,12 +591,18 @@ qsw_status_t build_common(HostOps &op, double omega, hipStream_t s, qsw_superop_
       h->info.d_index[p] = -1;
       h->info.d_probe[p] = 0;
     }
+    const int resident2 = resident_workgroups(1);
+    if ((e = make_layout(h->row_ptr, n, h->nnz, maxrow, kCap / 2, resident2, s, LF)) != hipSuccess) break;
+    if ((e = make_layout(arp, n, annz, maxrow, kCap / 2, resident2, s, LA)) != hipSuccess) break;
     E.n = n;
     E.s = s;
-    E.rp = h->row_ptr; E.col = h->col; E.val = h->val;
-    E.arp = arp; E.acol = acol; E.aval = aval;
-    E.grid = 2048;
-    E.nb = spmm2_blocks(n, E.grid);
+    E.fwd.n = n; E.fwd.rp = h->row_ptr; E.fwd.col = h->col; E.fwd.val = h->val;
+    E.fwd.blk = LF.blk; E.fwd.nblk = LF.nblk; E.fwd.blocks_per_wg = LF.bpw;
+    E.adj.n = n; E.adj.rp = arp; E.adj.col = acol; E.adj.val = aval;
+    E.adj.blk = LA.blk; E.adj.nblk = LA.nblk; E.adj.blocks_per_wg = LA.bpw;
+    E.fwd_grid = LF.grid;
+    E.adj_grid = LA.grid;
+    E.nb = LF.grid;
     if ((e = dalloc(&E.X, 2 * (size_t)n)) != hipSuccess) break;
     if ((e = dalloc(&E.Y, 2 * (size_t)n)) != hipSuccess) break;
     if ((e = dalloc(&E.W0, 2 * (size_t)n)) != hipSuccess) break;
@@ -489,6 +622,8 @@ qsw_status_t build_common(HostOps &op, double omega, hipStream_t s, qsw_superop_
     }
   } while (false);
   dfree(nbits);
+  dfree(LF.blk);
+  dfree(LA.blk);
   dfree(E.X); dfree(E.Y); dfree(E.W0); dfree(E.W1); dfree(E.S); dfree(E.h); dfree(E.part); dfree(E.sums);
   dfree(arp); dfree(acol); dfree(aval);
   if (e != hipSuccess) return fail(status_of(e));
@@ -578,6 +713,15 @@ struct Runner {
     a.tol = tol;
     a.st = st;
     a.rows_per_block = h->rows_per_block;
+    a.blk = h->blk;
+    a.nblk = h->nblk;
+    a.blocks_per_wg = h->blocks_per_wg;
+    a.jrec = h->jrec;
+    a.njag = h->njag;
+    a.jcol = h->jcol;
+    a.jval = h->jval;
+    a.jperm = h->jperm;
+    a.jps = h->jps;
     return a;
   }
 
@@ -598,7 +742,7 @@ struct Runner {
         a.alpha = t / ((double)s_steps * (double)j);
         a.par = par;
         a.j = j;
-        hipError_t e = launch_taylor_term(a, h->lpr, h->grid, s);
+        hipError_t e = launch_taylor_term(a, h->engine, h->grid, s);
         if (e != hipSuccess) return e;
         ++launched;
       }
@@ -774,6 +918,12 @@ void qsw_superop_destroy(qsw_superop_t h) {
   dfree(h->col);
   dfree(h->val);
   dfree(h->stats_dev);
+  dfree(h->blk);
+  dfree(h->jrec);
+  dfree(h->jcol);
+  dfree(h->jval);
+  dfree(h->jperm);
+  dfree(h->jps);
   if (h->ev_start) (void)hipEventDestroy(h->ev_start);
   if (h->ev_end) (void)hipEventDestroy(h->ev_end);
   delete h;
@@ -861,7 +1011,7 @@ qsw_status_t qsw_propagate(qsw_superop_t h, const void *rho0, double t0, double 
           a.x = Kp[p - 1];
           a.y = Kp[p];
           a.alpha = dt / (double)p;
-          HIP_TRY(launch_series_power(a, pt, k, p, h->lpr, h->grid, s));
+          HIP_TRY(launch_series_power(a, pt, k, p, h->engine, h->grid, s));
           HIP_TRY(launch_series_accum(R.st, pt, k, p, Kp[p], Z, Fk, n, R.tol, 2048, s));
           R.launched += 1;
         }
@@ -916,7 +1066,16 @@ qsw_status_t qsw_apply(qsw_superop_t h, const void *x, void *y, void *hip_stream
   a.y = (double2 *)y;
   a.alpha = 1.0;
   a.rows_per_block = h->rows_per_block;
-  HIP_TRY(launch_spmv(a, h->lpr, h->grid, (hipStream_t)hip_stream));
+  a.blk = h->blk;
+  a.nblk = h->nblk;
+  a.blocks_per_wg = h->blocks_per_wg;
+  a.jrec = h->jrec;
+  a.njag = h->njag;
+  a.jcol = h->jcol;
+  a.jval = h->jval;
+  a.jperm = h->jperm;
+  a.jps = h->jps;
+  HIP_TRY(launch_spmv(a, h->engine, h->grid, (hipStream_t)hip_stream));
   return QSW_OK;
 }
 

@@ -12,10 +12,25 @@ from tests.gpu_util import build_gpu, oracle_superop, random_workload
 pytestmark = pytest.mark.gpu
 
 
+def canonical_rows(rp, col, val):
+    """Sort the entries of every row by column (the device keeps rows in
+    structural order; the oracle's rows are sorted)."""
+    rows = np.repeat(np.arange(rp.size - 1), np.diff(rp))
+    order = np.lexsort((col, rows))
+    return col[order], val[order]
+
+
+def test_canonical_rows_helper():
+    rp = np.array([0, 3, 5])
+    col, val = canonical_rows(rp, np.array([5, 1, 3, 2, 0]), np.arange(5.0))
+    assert col.tolist() == [1, 3, 5, 0, 2] and val.tolist() == [1, 2, 0, 4, 3]
+
+
 def _compare_csr(op, A, val_tol=0.0):
     rp, col, val = op.csr()
     assert op.n == A.n and op.nnz == A.nnz
     assert np.array_equal(rp, A.row_ptr)
+    col, val = canonical_rows(rp, col, val)
     assert np.array_equal(col, A.col)
     scale = max(1.0, float(np.abs(A.val).max()) if A.nnz else 1.0)
     assert float(np.abs(val - A.val).max() if A.nnz else 0.0) <= val_tol * scale
