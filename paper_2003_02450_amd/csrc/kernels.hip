@@ -267,7 +267,7 @@ __device__ __forceinline__ void stream_engine(const SpmvArgs &a, Epi &epi) {
 // butterfly; the epilogue runs for the row's original index.  Workgroups take
 // blocks k = blockIdx.x, blockIdx.x + gridDim.x, ... so the whole device
 // sweeps the matrix front to back together.
-template <class Epi>
+template <int NRHS, class Epi>
 __device__ __forceinline__ void jagged_engine(const SpmvArgs &a, Epi &epi) {
   __shared__ double2 prod[kCap];
   __shared__ unsigned short spos[kCap + 1];
@@ -278,22 +278,28 @@ __device__ __forceinline__ void jagged_engine(const SpmvArgs &a, Epi &epi) {
       // rows longer than the stage: CSR order, one row at a time
       double *red = reinterpret_cast<double *>(prod);
       for (int64_t row = R.r0; row < R.r0 + R.nr; ++row) {
-        double acc[2] = {0.0, 0.0};
-        for (int64_t e = a.rp[row] + tid; e < a.rp[row + 1]; e += kBlock)
-          cmac(acc[0], acc[1], a.jval[e], a.x[a.jcol[e]]);
-        red[tid] = acc[0];
-        red[kBlock + tid] = acc[1];
+        double acc[2 * NRHS];
+#pragma unroll
+        for (int q = 0; q < 2 * NRHS; ++q) acc[q] = 0.0;
+        for (int64_t e = a.rp[row] + tid; e < a.rp[row + 1]; e += kBlock) {
+          const double2 vv = a.jval[e];
+          const int64_t cc = a.jcol[e];
+#pragma unroll
+          for (int r = 0; r < NRHS; ++r) cmac(acc[2 * r], acc[2 * r + 1], vv, a.x[cc * NRHS + r]);
+        }
+#pragma unroll
+        for (int q = 0; q < 2 * NRHS; ++q) red[q * kBlock + tid] = acc[q];
         __syncthreads();
         for (int w2 = kBlock / 2; w2 > 0; w2 >>= 1) {
           if (tid < w2) {
-            red[tid] += red[tid + w2];
-            red[kBlock + tid] += red[kBlock + tid + w2];
+#pragma unroll
+            for (int q = 0; q < 2 * NRHS; ++q) red[q * kBlock + tid] += red[q * kBlock + tid + w2];
           }
           __syncthreads();
         }
         if (tid == 0) {
-          acc[0] = red[0];
-          acc[1] = red[kBlock];
+#pragma unroll
+          for (int q = 0; q < 2 * NRHS; ++q) acc[q] = red[q * kBlock];
           epi(row, acc, epi.pre(row));
         }
         __syncthreads();
@@ -316,45 +322,90 @@ __device__ __forceinline__ void jagged_engine(const SpmvArgs &a, Epi &epi) {
     int L = 64;
     while (L > 1 && R.nr * L > kBlock) L >>= 1;
     const int g = tid / L, lane = tid & (L - 1);
+    const int rpp = kBlock / L;
     int orow = 0;
     typename Epi::Pre pre{};
     if (g < R.nr && lane == 0) {
       orow = a.jperm[R.r0 + g];
       pre = epi.pre(R.r0 + orow);
     }
+    if constexpr (NRHS == 1) {
+      // products once, then reduction passes over the ranks (one pass
+      // unless the block holds more than 256 / L rows)
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const int i = tid + u * kBlock;
-      if (i < R.cnt) prod[i] = cmul(v[u], a.x[c[u]]);
-    }
-    __syncthreads();
-    const int rpp = kBlock / L;
-    for (int base = 0; base < R.nr; base += rpp) {
-      const int r = base + g;
-      double acc[2] = {0.0, 0.0};
-      if (r < R.nr) {
-        for (int p = lane; p < R.maxlen; p += L) {
-          const int s0 = spos[p], s1 = spos[p + 1];
-          if (r >= s1 - s0) break;  // rows are ranked by length: no later position either
-          const double2 q = prod[s0 + r];
-          acc[0] += q.x;
-          acc[1] += q.y;
+      for (int u = 0; u < kUnroll; ++u) {
+        const int i = tid + u * kBlock;
+        if (i < R.cnt) prod[i] = cmul(v[u], a.x[c[u]]);
+      }
+      __syncthreads();
+      for (int base = 0; base < R.nr; base += rpp) {
+        const int r = base + g;
+        double acc[2] = {0.0, 0.0};
+        if (r < R.nr) {
+          for (int p = lane; p < R.maxlen; p += L) {
+            const int s0 = spos[p], s1 = spos[p + 1];
+            if (r >= s1 - s0) break;  // rows are ranked by length: no later position either
+            const double2 q = prod[s0 + r];
+            acc[0] += q.x;
+            acc[1] += q.y;
+          }
+        }
+        for (int off = L >> 1; off > 0; off >>= 1) {
+          acc[0] += __shfl_xor(acc[0], off, L);
+          acc[1] += __shfl_xor(acc[1], off, L);
+        }
+        if (r < R.nr && lane == 0) {
+          if (base == 0) {
+            epi(R.r0 + orow, acc, pre);
+          } else {
+            const int o2 = a.jperm[R.r0 + r];
+            epi(R.r0 + o2, acc, epi.pre(R.r0 + o2));
+          }
         }
       }
-      for (int off = L >> 1; off > 0; off >>= 1) {
-        acc[0] += __shfl_xor(acc[0], off, L);
-        acc[1] += __shfl_xor(acc[1], off, L);
-      }
-      if (r < R.nr && lane == 0) {
-        if (base == 0) {
-          epi(R.r0 + orow, acc, pre);
-        } else {
-          const int o2 = a.jperm[R.r0 + r];
-          epi(R.r0 + o2, acc, epi.pre(R.r0 + o2));
+      __syncthreads();
+    } else {
+      // several right-hand sides: staged one at a time so the LDS stage
+      // stays kCap products (the matrix entries stay in registers)
+      for (int base = 0; base < R.nr; base += rpp) {
+        const int r = base + g;
+        double acc[2 * NRHS];
+#pragma unroll
+        for (int rh = 0; rh < NRHS; ++rh) {
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+            const int i = tid + u * kBlock;
+            if (i < R.cnt) prod[i] = cmul(v[u], a.x[(int64_t)c[u] * NRHS + rh]);
+          }
+          __syncthreads();
+          double sx = 0.0, sy = 0.0;
+          if (r < R.nr) {
+            for (int p = lane; p < R.maxlen; p += L) {
+              const int s0 = spos[p], s1 = spos[p + 1];
+              if (r >= s1 - s0) break;
+              const double2 q = prod[s0 + r];
+              sx += q.x;
+              sy += q.y;
+            }
+          }
+          for (int off = L >> 1; off > 0; off >>= 1) {
+            sx += __shfl_xor(sx, off, L);
+            sy += __shfl_xor(sy, off, L);
+          }
+          acc[2 * rh] = sx;
+          acc[2 * rh + 1] = sy;
+          __syncthreads();
+        }
+        if (r < R.nr && lane == 0) {
+          if (base == 0) {
+            epi(R.r0 + orow, acc, pre);
+          } else {
+            const int o2 = a.jperm[R.r0 + r];
+            epi(R.r0 + o2, acc, epi.pre(R.r0 + o2));
+          }
         }
       }
     }
-    __syncthreads();
   }
 }
 
@@ -385,7 +436,7 @@ __device__ __forceinline__ void vector_engine(const SpmvArgs &a, Epi &epi) {
 template <int ENGINE, class Epi>
 __device__ __forceinline__ void run_engine(const SpmvArgs &a, Epi &epi) {
   if constexpr (ENGINE == 0)
-    jagged_engine(a, epi);
+    jagged_engine<1>(a, epi);
   else if constexpr (ENGINE == 3)
     stream_engine<1>(a, epi);
   else
@@ -753,7 +804,7 @@ __global__ __launch_bounds__(kBlock) void series_accum_kernel(DeviceState *st, P
 __global__ __launch_bounds__(kBlock) void spmm2_kernel(SpmvArgs a, int mode, double *part,
                                                        double2 *sgn, double *h) {
   Spmm2Epi epi{a.y, mode, sgn, h};
-  stream_engine<2>(a, epi);
+  jagged_engine<2>(a, epi);
   if (mode == 1) {
     // deterministic per-workgroup column sums: fixed tree over the threads
     __shared__ double sm0[kBlock], sm1[kBlock];
@@ -795,6 +846,121 @@ __global__ __launch_bounds__(kBlock) void sum_partials_kernel(const double *part
   if (threadIdx.x == 0) {
     out2[0] = sm0[0];
     out2[1] = sm1[0];
+  }
+}
+
+// Probe block of the 1-norm estimator: column 0 = 1/n, column 1 = s_i / n
+// with s_0 = -1 and s_i (i > 0) the sign of the top bit of SplitMix64
+// (Steele, Lea and Flood, 2014) of 0x51A7E5 + i; column 1 is zero when t = 1.
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+__global__ void probe_init_kernel(double2 *X, int64_t n, int t) {
+  const double inv = 1.0 / (double)n;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    X[2 * i] = make_double2(inv, 0.0);
+    double sg = (splitmix64(0x51A7E5ull + (unsigned long long)i) >> 63) ? -1.0 : 1.0;
+    if (i == 0) sg = -1.0;
+    X[2 * i + 1] = make_double2(t == 2 ? sg * inv : 0.0, 0.0);
+  }
+}
+
+// X = [e_i0, e_i1] (i1 < 0: second column zero).
+__global__ void unit_cols_kernel(double2 *X, int64_t n, int64_t i0, int64_t i1) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    X[2 * i] = make_double2(i == i0 ? 1.0 : 0.0, 0.0);
+    X[2 * i + 1] = make_double2(i == i1 ? 1.0 : 0.0, 0.0);
+  }
+}
+
+// Total order of the estimator's candidates: larger h first, then smaller index.
+__device__ __forceinline__ bool cand_better(double va, int64_t ia, double vb, int64_t ib) {
+  return va > vb || (va == vb && ia < ib);
+}
+
+// Block argmax of (value, index) pairs by cand_better; every thread gets the
+// winner.  red_v / red_i hold kBlock entries.
+__device__ __forceinline__ void block_best(double &v, int64_t &i, double *red_v, int64_t *red_i) {
+  red_v[threadIdx.x] = v;
+  red_i[threadIdx.x] = i;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      const double ov = red_v[threadIdx.x + w];
+      const int64_t oi = red_i[threadIdx.x + w];
+      if (cand_better(ov, oi, red_v[threadIdx.x], red_i[threadIdx.x])) {
+        red_v[threadIdx.x] = ov;
+        red_i[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  v = red_v[0];
+  i = red_i[0];
+  __syncthreads();
+}
+
+// Top K of h[0..n) under cand_better, per workgroup over a strided share:
+// K rounds, each excluding the winners of earlier rounds.
+__global__ __launch_bounds__(kBlock) void topk_partial_kernel(const double *h, int64_t n, int K,
+                                                              double *cand_v, int64_t *cand_i) {
+  __shared__ double red_v[kBlock];
+  __shared__ int64_t red_i[kBlock];
+  __shared__ int64_t chosen[kTopKMax];
+  for (int r = 0; r < K; ++r) {
+    double bv = -1.0;
+    int64_t bi = INT64_MAX;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+      bool taken = false;
+      for (int q = 0; q < r; ++q) taken |= chosen[q] == i;
+      if (!taken && cand_better(h[i], i, bv, bi)) {
+        bv = h[i];
+        bi = i;
+      }
+    }
+    block_best(bv, bi, red_v, red_i);
+    if (threadIdx.x == 0) {
+      chosen[r] = bi;
+      cand_v[(int64_t)blockIdx.x * K + r] = bv;
+      cand_i[(int64_t)blockIdx.x * K + r] = bi;
+    }
+    __syncthreads();
+  }
+}
+
+// Merge the per-workgroup candidates into the global top K (one workgroup).
+__global__ __launch_bounds__(kBlock) void topk_merge_kernel(const double *cand_v,
+                                                            const int64_t *cand_i, int64_t m, int K,
+                                                            double *out_v, int64_t *out_i) {
+  __shared__ double red_v[kBlock];
+  __shared__ int64_t red_i[kBlock];
+  __shared__ int64_t chosen[kTopKMax];
+  for (int r = 0; r < K; ++r) {
+    double bv = -1.0;
+    int64_t bi = INT64_MAX;
+    for (int64_t j = threadIdx.x; j < m; j += kBlock) {
+      const int64_t i = cand_i[j];
+      bool taken = false;
+      for (int q = 0; q < r; ++q) taken |= chosen[q] == i;
+      if (!taken && cand_better(cand_v[j], i, bv, bi)) {
+        bv = cand_v[j];
+        bi = i;
+      }
+    }
+    block_best(bv, bi, red_v, red_i);
+    if (threadIdx.x == 0) {
+      chosen[r] = bi;
+      out_v[r] = bv;
+      out_i[r] = bi;
+    }
+    __syncthreads();
   }
 }
 
@@ -928,6 +1094,31 @@ hipError_t launch_spmm2(const SpmvArgs &a, int mode, double *part, double2 *sgn,
 
 hipError_t launch_sum_partials(const double *part, int nblocks, double *out2, hipStream_t s) {
   hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(kBlock), 0, s, part, nblocks, out2);
+  return hipGetLastError();
+}
+
+hipError_t launch_probe_init(double2 *X, int64_t n, int t, hipStream_t s) {
+  int grid = blocks_for(n);
+  if (grid > 4096) grid = 4096;
+  hipLaunchKernelGGL(probe_init_kernel, dim3(grid), dim3(kBlock), 0, s, X, n, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_unit_cols(double2 *X, int64_t n, int64_t i0, int64_t i1, hipStream_t s) {
+  int grid = blocks_for(n);
+  if (grid > 4096) grid = 4096;
+  hipLaunchKernelGGL(unit_cols_kernel, dim3(grid), dim3(kBlock), 0, s, X, n, i0, i1);
+  return hipGetLastError();
+}
+
+hipError_t launch_topk(const double *h, int64_t n, int K, int grid, double *cand_v, int64_t *cand_i,
+                       double *out_v, int64_t *out_i, hipStream_t s) {
+  if (K < 1 || K > kTopKMax) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(topk_partial_kernel, dim3(grid), dim3(kBlock), 0, s, h, n, K, cand_v, cand_i);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(topk_merge_kernel, dim3(1), dim3(kBlock), 0, s, cand_v, cand_i,
+                     (int64_t)grid * K, K, out_v, out_i);
   return hipGetLastError();
 }
 

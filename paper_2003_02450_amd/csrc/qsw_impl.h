@@ -9,6 +9,7 @@ namespace qsw {
 constexpr int kMMax = 55;   // largest Taylor degree
 constexpr int kPMax = 8;    // largest p in alpha_p = max(d_p, d_{p+1})
 constexpr int kCap = 2048;  // LDS product slots per workgroup of the stream engine
+constexpr int kTopKMax = 16;  // candidates the 1-norm estimator ranks at once
 
 // Norm slots of one scaling step of the single-time algorithm.  Maxima of
 // non-negative doubles are kept as their IEEE bit patterns, whose unsigned
@@ -149,13 +150,20 @@ hipError_t launch_series_accum(DeviceState *st, PointSlots *pt, int k, int p,
                                int64_t n, double tol, int grid, hipStream_t s);
 
 // Block 1-norm estimation helpers: Y = A X for two interleaved right-hand
-// sides (stream engine; a.x = X, a.y = Y).  mode 0: product only; mode 1:
+// sides (jagged engine; a.x = X, a.y = Y).  mode 0: product only; mode 1:
 // also column |.|_1 partial sums per workgroup into part[2*wg + c] and
 // S = sign(Y) into sgn; mode 2: also h[i] = max_c |Y[i][c]|.
 hipError_t launch_spmm2(const SpmvArgs &a, int mode, double *part, double2 *sgn, double *h,
                         int grid, hipStream_t s);
 hipError_t launch_sum_partials(const double *part, int nblocks, double *out2,
                                hipStream_t s);
+// Estimator probe block (column 0 = 1/n, column 1 = signed 1/n; t = 1 zeroes
+// column 1), unit columns [e_i0, e_i1] (i1 < 0: zero), and the top K <= 16
+// of h by (larger value, then smaller index) through grid * K candidates.
+hipError_t launch_probe_init(double2 *X, int64_t n, int t, hipStream_t s);
+hipError_t launch_unit_cols(double2 *X, int64_t n, int64_t i0, int64_t i1, hipStream_t s);
+hipError_t launch_topk(const double *h, int64_t n, int K, int grid, double *cand_v, int64_t *cand_i,
+                       double *out_v, int64_t *out_i, hipStream_t s);
 
 // Workgroups of the stream kernels that fit on the device at once
 // (which = 0: single right-hand side, 1: two).

@@ -318,27 +318,25 @@ qsw_status_t assemble(const HostOps &op, bool adjoint, double omega, hipStream_t
   return QSW_OK;
 }
 
-// SplitMix64 (Steele, Lea and Flood, 2014): the sign pattern of the second
-// probe column of the 1-norm estimator.
-uint64_t splitmix64(uint64_t x) {
-  x += 0x9E3779B97F4A7C15ull;
-  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
-  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
-  return x ^ (x >> 31);
-}
-
 // Block 1-norm estimator (Higham and Tisseur's algorithm, two columns,
 // complex case, at most five iterations) applied to A^p, with the products
 // formed by p sparse products on the device.  Returns the estimate and the
 // unit column (or probe column) that attains it.
+// Block 1-norm estimator (Higham and Tisseur's algorithm, two columns,
+// complex case, at most five iterations) applied to A^p, with the products
+// formed by p sparse products on the device and the ranking of the
+// candidate columns done on the device; the host reads back a few scalars
+// per iteration.  Returns the estimate and the unit column (or probe column)
+// that attains it.
 struct Estimator {
   int64_t n;
   hipStream_t s;
-  SpmvArgs fwd{}, adj{};          // A and A^dagger with their row blocks
-  int fwd_grid = 0, adj_grid = 0;
+  SpmvArgs fwd{}, adj{};          // A and A^dagger (jagged layouts)
+  int grid = 0;                   // workgroups of a product (= partial sums per column)
   double2 *X, *Y, *W0, *W1, *S;  // n x 2 interleaved blocks
   double *h, *part, *sums;
-  int nb;                         // partial sums per column (= fwd_grid)
+  double *cand_v, *top_v;
+  int64_t *cand_i, *top_i;
   int products = 0;
 
   // out = (A or A^dagger)^p in; intermediates alternate between W0 and W1,
@@ -350,8 +348,7 @@ struct Estimator {
       SpmvArgs a = adjoint ? adj : fwd;
       a.x = src;
       a.y = dst;
-      hipError_t e = launch_spmm2(a, i == p ? mode : 0, part, S, h,
-                                  adjoint ? adj_grid : fwd_grid, s);
+      hipError_t e = launch_spmm2(a, i == p ? mode : 0, part, S, h, grid, s);
       if (e != hipSuccess) return e;
       ++products;
       src = dst;
@@ -361,32 +358,19 @@ struct Estimator {
 
   hipError_t estimate(int p, double *est_out, int64_t *index_out, int *probe_out) {
     const int t = n >= 2 ? 2 : 1;
-    std::vector<double> hx(4 * (size_t)n, 0.0);  // two interleaved complex columns
-    const double inv = 1.0 / (double)n;
-    bool all_plus = true;
-    for (int64_t i = 0; i < n; ++i) {
-      hx[4 * i] = inv;
-      const double sg = (splitmix64(0x51A7E5ull + (uint64_t)i) >> 63) ? -1.0 : 1.0;
-      hx[4 * i + 2] = sg * inv;
-      if (sg < 0) all_plus = false;
-    }
-    if (all_plus && n >= 2) hx[4 * (n - 1) + 2] = -inv;  // keep the probes independent
-    if (t == 1)
-      for (int64_t i = 0; i < n; ++i) hx[4 * i + 2] = 0.0;
-    hipError_t e = hipMemcpyAsync(X, hx.data(), hx.size() * sizeof(double), hipMemcpyHostToDevice, s);
+    hipError_t e = launch_probe_init(X, n, t, s);
     if (e != hipSuccess) return e;
     double est_old = 0.0, est = 0.0;
     int64_t ind_best = -1;
     int probe_best = 0;
     int64_t ind[2] = {-1, -1};
     std::vector<int64_t> hist;
-    std::vector<double> hh((size_t)n);
     const int itmax = 5;
     for (int k = 1;; ++k) {
       // Y = A^p X, column 1-norms and S = sign(Y)
       e = power(false, X, Y, p, 1);
       if (e != hipSuccess) return e;
-      e = launch_sum_partials(part, nb, sums, s);
+      e = launch_sum_partials(part, grid, sums, s);
       if (e != hipSuccess) return e;
       double cs[2] = {0.0, 0.0};
       e = hipMemcpyAsync(cs, sums, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
@@ -413,56 +397,42 @@ struct Estimator {
       }
       est_old = est;
       if (k > itmax) break;
-      // Z = (A^dagger)^p S, h_i = max_j |Z_ij|
+      // Z = (A^dagger)^p S, h_i = max_j |Z_ij|; the first t + |hist| indices
+      // by decreasing h (ties: smaller index) decide the next columns
       e = power(true, S, Y, p, 2);
       if (e != hipSuccess) return e;
-      e = hipMemcpyAsync(hh.data(), h, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, s);
+      const int want = (int)std::min<int64_t>(n, (int64_t)t + (int64_t)hist.size());
+      e = launch_topk(h, n, want, grid, cand_v, cand_i, top_v, top_i, s);
       if (e != hipSuccess) return e;
+      double tv[kTopKMax];
+      int64_t ti[kTopKMax];
+      double hb = 0.0;
+      e = hipMemcpyAsync(tv, top_v, want * sizeof(double), hipMemcpyDeviceToHost, s);
+      if (e != hipSuccess) return e;
+      e = hipMemcpyAsync(ti, top_i, want * sizeof(int64_t), hipMemcpyDeviceToHost, s);
+      if (e != hipSuccess) return e;
+      if (k >= 2 && ind_best >= 0) {
+        e = hipMemcpyAsync(&hb, h + ind_best, sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return e;
+      }
       e = hipStreamSynchronize(s);
       if (e != hipSuccess) return e;
-      double hmax = 0.0;
-      for (int64_t i = 0; i < n; ++i) hmax = std::max(hmax, hh[i]);
-      if (k >= 2 && ind_best >= 0 && hmax == hh[ind_best]) break;
-      // indices by decreasing h (ties: smaller index first); only the first
-      // t + |hist| of that order can matter
-      const size_t want = std::min<size_t>((size_t)n, (size_t)t + hist.size());
-      std::vector<int64_t> top;
-      top.reserve(want + 1);
-      auto better = [&](int64_t a, int64_t b) {
-        return hh[a] > hh[b] || (hh[a] == hh[b] && a < b);
-      };
-      for (int64_t i = 0; i < n; ++i) {
-        if (top.size() < want) {
-          top.push_back(i);
-          std::push_heap(top.begin(), top.end(), better);
-        } else if (better(i, top.front())) {
-          std::pop_heap(top.begin(), top.end(), better);
-          top.back() = i;
-          std::push_heap(top.begin(), top.end(), better);
-        }
-      }
-      std::sort(top.begin(), top.end(), better);
+      if (k >= 2 && ind_best >= 0 && tv[0] == hb) break;
       auto in_hist = [&](int64_t i) { return std::find(hist.begin(), hist.end(), i) != hist.end(); };
       if (t > 1) {
         bool all_seen = true;
-        for (int j = 0; j < t && j < (int)top.size(); ++j)
-          if (!in_hist(top[j])) all_seen = false;
+        for (int j = 0; j < t && j < want; ++j)
+          if (!in_hist(ti[j])) all_seen = false;
         if (all_seen) break;
       }
       int got = 0;
-      for (size_t q = 0; q < top.size() && got < t; ++q)
-        if (!in_hist(top[q])) ind[got++] = top[q];
+      for (int q = 0; q < want && got < t; ++q)
+        if (!in_hist(ti[q])) ind[got++] = ti[q];
       if (got < t) break;
-      std::fill(hx.begin(), hx.end(), 0.0);
-      for (int j = 0; j < t; ++j) {
-        hx[4 * ind[j] + 2 * j] = 1.0;
-        hist.push_back(ind[j]);
-      }
-      e = hipMemcpyAsync(X, hx.data(), hx.size() * sizeof(double), hipMemcpyHostToDevice, s);
+      for (int j = 0; j < t; ++j) hist.push_back(ind[j]);
+      e = launch_unit_cols(X, n, ind[0], t == 2 ? ind[1] : -1, s);
       if (e != hipSuccess) return e;
     }
-    e = hipStreamSynchronize(s);  // hx must outlive the last upload
-    if (e != hipSuccess) return e;
     *est_out = est;
     *index_out = ind_best;
     *probe_out = probe_best;
@@ -470,15 +440,32 @@ struct Estimator {
   }
 };
 
-// Jagged layout of the handle's CSR over its row blocks (see JagRec).
-qsw_status_t build_jagged(qsw_superop_s *h, hipStream_t s) {
-  const int64_t nblk = h->nblk;
+// Jagged execution layout (see JagRec) of one CSR over its row blocks.
+struct JagLayout {
+  JagRec *rec = nullptr;
+  int32_t *col = nullptr;
+  double2 *val = nullptr;
+  unsigned short *perm = nullptr;
+  unsigned short *ps = nullptr;
+  int32_t n = 0;  // blocks
+  void release() {
+    dfree(rec);
+    dfree(col);
+    dfree(val);
+    dfree(perm);
+    dfree(ps);
+  }
+};
+
+hipError_t build_jag_layout(const int64_t *rp, const int32_t *col, const double2 *val,
+                            const int32_t *blk, int64_t nblk, int64_t n, int64_t nnz,
+                            hipStream_t s, JagLayout &J) {
   int32_t *dmax = nullptr, *dpso = nullptr;
   std::vector<int32_t> hmax((size_t)nblk), hpso((size_t)nblk + 1);
   hipError_t e;
   do {
     if ((e = dalloc(&dmax, (size_t)nblk)) != hipSuccess) break;
-    if ((e = launch_jag_measure(h->row_ptr, h->blk, nblk, dmax, s)) != hipSuccess) break;
+    if ((e = launch_jag_measure(rp, blk, nblk, dmax, s)) != hipSuccess) break;
     if ((e = hipMemcpyAsync(hmax.data(), dmax, (size_t)nblk * sizeof(int32_t),
                             hipMemcpyDeviceToHost, s)) != hipSuccess)
       break;
@@ -497,21 +484,42 @@ qsw_status_t build_jagged(qsw_superop_s *h, hipStream_t s) {
     if ((e = hipMemcpyAsync(dpso, hpso.data(), ((size_t)nblk + 1) * sizeof(int32_t),
                             hipMemcpyHostToDevice, s)) != hipSuccess)
       break;
-    if ((e = dalloc(&h->jrec, (size_t)nblk)) != hipSuccess) break;
-    if ((e = dalloc(&h->jcol, (size_t)h->nnz)) != hipSuccess) break;
-    if ((e = dalloc(&h->jval, (size_t)h->nnz)) != hipSuccess) break;
-    if ((e = dalloc(&h->jperm, (size_t)h->n)) != hipSuccess) break;
-    if ((e = dalloc(&h->jps, (size_t)hpso[nblk])) != hipSuccess) break;
-    if ((e = launch_jag_build(h->row_ptr, h->col, h->val, h->blk, nblk, dmax, dpso, h->jrec,
-                              h->jcol, h->jval, h->jperm, h->jps, s)) != hipSuccess)
+    if ((e = dalloc(&J.rec, (size_t)nblk)) != hipSuccess) break;
+    if ((e = dalloc(&J.col, (size_t)nnz)) != hipSuccess) break;
+    if ((e = dalloc(&J.val, (size_t)nnz)) != hipSuccess) break;
+    if ((e = dalloc(&J.perm, (size_t)n)) != hipSuccess) break;
+    if ((e = dalloc(&J.ps, (size_t)hpso[nblk])) != hipSuccess) break;
+    if ((e = launch_jag_build(rp, col, val, blk, nblk, dmax, dpso, J.rec, J.col, J.val, J.perm,
+                              J.ps, s)) != hipSuccess)
       break;
     e = hipStreamSynchronize(s);  // host arrays above must outlive the copies
   } while (false);
   dfree(dmax);
   dfree(dpso);
+  if (e == hipSuccess) J.n = (int32_t)nblk;
+  return e;
+}
+
+qsw_status_t build_jagged(qsw_superop_s *h, hipStream_t s) {
+  JagLayout J;
+  hipError_t e = build_jag_layout(h->row_ptr, h->col, h->val, h->blk, h->nblk, h->n, h->nnz, s, J);
+  h->jrec = J.rec;
+  h->jcol = J.col;
+  h->jval = J.val;
+  h->jperm = J.perm;
+  h->jps = J.ps;
   if (e != hipSuccess) return status_of(e);
-  h->njag = (int32_t)nblk;
+  h->njag = J.n;
   return QSW_OK;
+}
+
+void set_jagged(SpmvArgs &a, const JagLayout &J) {
+  a.jrec = J.rec;
+  a.njag = J.n;
+  a.jcol = J.col;
+  a.jval = J.val;
+  a.jperm = J.perm;
+  a.jps = J.ps;
 }
 
 qsw_status_t build_common(HostOps &op, double omega, hipStream_t s, qsw_superop_t *out) {
@@ -574,7 +582,8 @@ qsw_status_t build_common(HostOps &op, double omega, hipStream_t s, qsw_superop_
   if (st != QSW_OK) return fail(st);
   unsigned long long *nbits = nullptr;
   Estimator E{};
-  Layout LF, LA;
+  Layout LA;
+  JagLayout JA;
   hipError_t e = hipSuccess;
   double norm1 = 0.0;
   do {
@@ -591,27 +600,31 @@ qsw_status_t build_common(HostOps &op, double omega, hipStream_t s, qsw_superop_
       h->info.d_index[p] = -1;
       h->info.d_probe[p] = 0;
     }
-    const int resident2 = resident_workgroups(1);
-    if ((e = make_layout(h->row_ptr, n, h->nnz, maxrow, kCap / 2, resident2, s, LF)) != hipSuccess) break;
-    if ((e = make_layout(arp, n, annz, maxrow, kCap / 2, resident2, s, LA)) != hipSuccess) break;
+    if (!(norm1 > 0.0)) break;  // L = 0: every d_p is 0
+    // adjoint row blocks and jagged layout (transient)
+    if ((e = make_layout(arp, n, annz, maxrow, kCap, resident1, s, LA)) != hipSuccess) break;
+    if ((e = build_jag_layout(arp, acol, aval, LA.blk, LA.nblk, n, annz, s, JA)) != hipSuccess) break;
     E.n = n;
     E.s = s;
     E.fwd.n = n; E.fwd.rp = h->row_ptr; E.fwd.col = h->col; E.fwd.val = h->val;
-    E.fwd.blk = LF.blk; E.fwd.nblk = LF.nblk; E.fwd.blocks_per_wg = LF.bpw;
+    E.fwd.jrec = h->jrec; E.fwd.njag = h->njag; E.fwd.jcol = h->jcol; E.fwd.jval = h->jval;
+    E.fwd.jperm = h->jperm; E.fwd.jps = h->jps;
     E.adj.n = n; E.adj.rp = arp; E.adj.col = acol; E.adj.val = aval;
-    E.adj.blk = LA.blk; E.adj.nblk = LA.nblk; E.adj.blocks_per_wg = LA.bpw;
-    E.fwd_grid = LF.grid;
-    E.adj_grid = LA.grid;
-    E.nb = LF.grid;
+    set_jagged(E.adj, JA);
+    E.grid = std::max(1, std::min(resident_workgroups(1), std::max(h->njag, JA.n)));
     if ((e = dalloc(&E.X, 2 * (size_t)n)) != hipSuccess) break;
     if ((e = dalloc(&E.Y, 2 * (size_t)n)) != hipSuccess) break;
     if ((e = dalloc(&E.W0, 2 * (size_t)n)) != hipSuccess) break;
     if ((e = dalloc(&E.W1, 2 * (size_t)n)) != hipSuccess) break;
     if ((e = dalloc(&E.S, 2 * (size_t)n)) != hipSuccess) break;
     if ((e = dalloc(&E.h, (size_t)n)) != hipSuccess) break;
-    if ((e = dalloc(&E.part, 2 * (size_t)E.nb)) != hipSuccess) break;
+    if ((e = dalloc(&E.part, 2 * (size_t)E.grid)) != hipSuccess) break;
     if ((e = dalloc(&E.sums, 2)) != hipSuccess) break;
-    for (int p = 2; p <= kPMax + 1 && norm1 > 0.0; ++p) {
+    if ((e = dalloc(&E.cand_v, (size_t)E.grid * kTopKMax)) != hipSuccess) break;
+    if ((e = dalloc(&E.cand_i, (size_t)E.grid * kTopKMax)) != hipSuccess) break;
+    if ((e = dalloc(&E.top_v, kTopKMax)) != hipSuccess) break;
+    if ((e = dalloc(&E.top_i, kTopKMax)) != hipSuccess) break;
+    for (int p = 2; p <= kPMax + 1; ++p) {
       double est = 0.0;
       int64_t idx = -1;
       int probe = 0;
@@ -621,10 +634,12 @@ qsw_status_t build_common(HostOps &op, double omega, hipStream_t s, qsw_superop_
       h->info.d_probe[p] = probe;
     }
   } while (false);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
   dfree(nbits);
-  dfree(LF.blk);
   dfree(LA.blk);
+  JA.release();
   dfree(E.X); dfree(E.Y); dfree(E.W0); dfree(E.W1); dfree(E.S); dfree(E.h); dfree(E.part); dfree(E.sums);
+  dfree(E.cand_v); dfree(E.cand_i); dfree(E.top_v); dfree(E.top_i);
   dfree(arp); dfree(acol); dfree(aval);
   if (e != hipSuccess) return fail(status_of(e));
   if (!std::isfinite(norm1)) return fail(QSW_ERR_NONFINITE);

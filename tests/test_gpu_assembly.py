@@ -82,8 +82,8 @@ def _apply_power(A, v, p):
 
 
 def _probe(n, which):
-    """The estimator's deterministic probe columns: all ones / n, and +-1/n
-    with signs from the top bit of SplitMix64(0x51A7E5 + i)."""
+    """The estimator's deterministic probe columns: all ones / n, and s_i / n
+    with s_0 = -1 and s_i the sign of the top bit of SplitMix64(0x51A7E5 + i)."""
     if which == 0:
         return np.full(n, 1.0 / n, np.complex128)
     out = np.empty(n, np.complex128)
@@ -94,8 +94,7 @@ def _probe(n, which):
         x = ((x ^ (x >> 27)) * 0x94D049BB133111EB) & mask
         x = x ^ (x >> 31)
         out[i] = (-1.0 if (x >> 63) else 1.0) / n
-    if np.all(out.real > 0):
-        out[-1] = -1.0 / n
+    out[0] = -1.0 / n
     return out
 
 
