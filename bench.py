@@ -28,6 +28,28 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_term_kernel_outdeg1024.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2003_02450_amd", "csrc", "kernels.hip")
+
+
+def measured_traffic():
+    """HBM bytes per computing Taylor-term product from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE runs, or None when the kernel source
+    has changed since those counters were taken."""
+    import hashlib
+    try:
+        fields = {}
+        for line in open(TRAFFIC_FILE):
+            if line.startswith("#") or ":" not in line:
+                continue
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+        h = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+        if fields.get("kernels_sha256_16") != h:
+            return None
+        return float(fields["traffic_bytes_per_product"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def term_bytes(n: int, nnz: int) -> float:
@@ -150,7 +172,7 @@ def main() -> int:
                    "term_launches_per_step": launched // args.steps},
         "roofline": {"bound": "hbm", "kernel": "term_kernel (CSR product + Taylor epilogue)",
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(),
                      "bytes_per_product": term_bytes(n, nnz),
                      "avg_launch_us": 1e3 * prop_ms / max(launched, 1),
                      "avg_product_us": 1e3 * prop_ms / max(products, 1)},
