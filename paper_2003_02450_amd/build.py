@@ -15,11 +15,12 @@ LIB = os.path.join(HERE, "libqsw.so")
 SOURCES = ["kernels.hip", "runtime.hip"]   # HIP (device + host)
 HOST_SOURCES = ["params.cpp"]               # plain C++, host only
 ARCH = os.environ.get("QSW_OFFLOAD_ARCH", "gfx950")
+BLOCK = int(os.environ.get("QSW_BLOCK", "256"))  # threads per product workgroup
 
 # Packed FP32 instructions are disabled for all device code.
 HIPCC_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-               "-Wall", "-Wno-unused-function"]
+               "-Wall", "-Wno-unused-function", f"-DQSW_BLOCK={BLOCK}"]
 
 
 def hipcc() -> str:

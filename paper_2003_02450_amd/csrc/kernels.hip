@@ -26,7 +26,7 @@ namespace qsw {
 
 namespace {
 
-constexpr int kBlock = 256;
+constexpr int kBlock = kBlockThreads;
 constexpr int kWaves = kBlock / 64;
 constexpr int kUnroll = 8;  // independent entries in flight per lane (stream engine)
 
@@ -258,154 +258,64 @@ __device__ __forceinline__ void stream_engine(const SpmvArgs &a, Epi &epi) {
   }
 }
 
-// Jagged engine.  Stage: the block's entries stream in memory order (a wave
-// reads 64 consecutive entries per instruction); in the position-major
-// layout consecutive lanes hold the same position of rows ranked next to
-// each other, so the leading H rho entries of rows of one rho-row gather x
-// at consecutive addresses.  Products go to LDS.  Reduce: L lanes per row
-// walk its positions (reading consecutive LDS words across rows), then a
-// butterfly; the epilogue runs for the row's original index.  Workgroups take
-// blocks k = blockIdx.x, blockIdx.x + gridDim.x, ... so the whole device
-// sweeps the matrix front to back together.
+// Wave-jagged engine.  Each wavefront owns one block of 64 rows; lane r
+// takes the row of rank r (rows ranked by length, longest first).  At entry
+// position p the rows still running are exactly ranks 0..cnt_p-1, with
+// cnt_p = popcount(ballot(len > p)), and their entries sit next to each other,
+// so every load instruction reads consecutive entries.  The leading entries
+// of the rows of one rho-row (the H rho part, columns c N + b) share c at
+// each position, so their x gathers fall on a few cache lines.  No LDS, no
+// barriers; kWaveUnroll positions are in flight per lane.  Each lane sums its
+// row in position order, so the result is bitwise reproducible.
+constexpr int kWaveUnroll = 6;
+
 template <int NRHS, class Epi>
-__device__ __forceinline__ void jagged_engine(const SpmvArgs &a, Epi &epi) {
-  __shared__ double2 prod[kCap];
-  __shared__ unsigned short spos[kCap + 1];
-  const int tid = threadIdx.x;
-  for (int64_t k = blockIdx.x; k < a.njag; k += gridDim.x) {
-    const JagRec R = a.jrec[k];
-    if (R.flags & kJagLong) {
-      // rows longer than the stage: CSR order, one row at a time
-      double *red = reinterpret_cast<double *>(prod);
-      for (int64_t row = R.r0; row < R.r0 + R.nr; ++row) {
-        double acc[2 * NRHS];
-#pragma unroll
-        for (int q = 0; q < 2 * NRHS; ++q) acc[q] = 0.0;
-        for (int64_t e = a.rp[row] + tid; e < a.rp[row + 1]; e += kBlock) {
-          const double2 vv = a.jval[e];
-          const int64_t cc = a.jcol[e];
-#pragma unroll
-          for (int r = 0; r < NRHS; ++r) cmac(acc[2 * r], acc[2 * r + 1], vv, a.x[cc * NRHS + r]);
-        }
-#pragma unroll
-        for (int q = 0; q < 2 * NRHS; ++q) red[q * kBlock + tid] = acc[q];
-        __syncthreads();
-        for (int w2 = kBlock / 2; w2 > 0; w2 >>= 1) {
-          if (tid < w2) {
-#pragma unroll
-            for (int q = 0; q < 2 * NRHS; ++q) red[q * kBlock + tid] += red[q * kBlock + tid + w2];
-          }
-          __syncthreads();
-        }
-        if (tid == 0) {
-#pragma unroll
-          for (int q = 0; q < 2 * NRHS; ++q) acc[q] = red[q * kBlock];
-          epi(row, acc, epi.pre(row));
-        }
-        __syncthreads();
-      }
-      continue;
-    }
-    int c[kUnroll];
-    double2 v[kUnroll];
-    const int32_t *cb = a.jcol + R.e0;
-    const double2 *vb = a.jval + R.e0;
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const int i = tid + u * kBlock;
-      if (i < R.cnt) {
-        c[u] = load_stream(cb + i);
-        v[u] = load_stream(vb + i);
-      }
-    }
-    for (int i = tid; i <= R.maxlen; i += kBlock) spos[i] = a.jps[R.pso + i];
-    int L = 64;
-    while (L > 1 && R.nr * L > kBlock) L >>= 1;
-    const int g = tid / L, lane = tid & (L - 1);
-    const int rpp = kBlock / L;
-    int orow = 0;
+__device__ __forceinline__ void wave_engine(const SpmvArgs &a, Epi &epi) {
+  constexpr int WPB = kBlock / 64;  // wavefronts per workgroup
+  const int lane = threadIdx.x & 63;
+  const int64_t nw = (int64_t)gridDim.x * WPB;
+  for (int64_t k = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6); k < a.nwb; k += nw) {
+    const int64_t r0 = k * kWaveRows;
+    const int nr = (int)min((int64_t)kWaveRows, a.n - r0);
+    const int64_t e0 = a.rp[r0];
+    const int len = lane < nr ? a.wlen[r0 + lane] : 0;
+    const int orow = lane < nr ? (int)a.wperm[r0 + lane] : 0;
     typename Epi::Pre pre{};
-    if (g < R.nr && lane == 0) {
-      orow = a.jperm[R.r0 + g];
-      pre = epi.pre(R.r0 + orow);
-    }
-    if constexpr (NRHS == 1) {
-      // products once, then reduction passes over the ranks (one pass
-      // unless the block holds more than 256 / L rows)
+    if (lane < nr) pre = epi.pre(r0 + orow);
+    const int maxlen = __shfl(len, 0, 64);  // rank 0 is the longest row
+    int ps = 0;
+    double acc[2 * NRHS];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int i = tid + u * kBlock;
-        if (i < R.cnt) prod[i] = cmul(v[u], a.x[c[u]]);
+    for (int q = 0; q < 2 * NRHS; ++q) acc[q] = 0.0;
+    for (int p0 = 0; p0 < maxlen; p0 += kWaveUnroll) {
+      int off[kWaveUnroll];
+      bool ok[kWaveUnroll];
+#pragma unroll
+      for (int u = 0; u < kWaveUnroll; ++u) {
+        const int cnt = __popcll(__ballot(len > p0 + u));
+        ok[u] = lane < cnt;
+        off[u] = ps + lane;
+        ps += cnt;
       }
-      __syncthreads();
-      for (int base = 0; base < R.nr; base += rpp) {
-        const int r = base + g;
-        double acc[2] = {0.0, 0.0};
-        if (r < R.nr) {
-          for (int p = lane; p < R.maxlen; p += L) {
-            const int s0 = spos[p], s1 = spos[p + 1];
-            if (r >= s1 - s0) break;  // rows are ranked by length: no later position either
-            const double2 q = prod[s0 + r];
-            acc[0] += q.x;
-            acc[1] += q.y;
-          }
-        }
-        for (int off = L >> 1; off > 0; off >>= 1) {
-          acc[0] += __shfl_xor(acc[0], off, L);
-          acc[1] += __shfl_xor(acc[1], off, L);
-        }
-        if (r < R.nr && lane == 0) {
-          if (base == 0) {
-            epi(R.r0 + orow, acc, pre);
-          } else {
-            const int o2 = a.jperm[R.r0 + r];
-            epi(R.r0 + o2, acc, epi.pre(R.r0 + o2));
-          }
+      int c[kWaveUnroll];
+      double2 v[kWaveUnroll];
+#pragma unroll
+      for (int u = 0; u < kWaveUnroll; ++u) {
+        if (ok[u]) {
+          c[u] = load_stream(a.wcol + e0 + off[u]);
+          v[u] = load_stream(a.wval + e0 + off[u]);
         }
       }
-      __syncthreads();
-    } else {
-      // several right-hand sides: staged one at a time so the LDS stage
-      // stays kCap products (the matrix entries stay in registers)
-      for (int base = 0; base < R.nr; base += rpp) {
-        const int r = base + g;
-        double acc[2 * NRHS];
 #pragma unroll
-        for (int rh = 0; rh < NRHS; ++rh) {
+      for (int u = 0; u < kWaveUnroll; ++u) {
+        if (ok[u]) {
 #pragma unroll
-          for (int u = 0; u < kUnroll; ++u) {
-            const int i = tid + u * kBlock;
-            if (i < R.cnt) prod[i] = cmul(v[u], a.x[(int64_t)c[u] * NRHS + rh]);
-          }
-          __syncthreads();
-          double sx = 0.0, sy = 0.0;
-          if (r < R.nr) {
-            for (int p = lane; p < R.maxlen; p += L) {
-              const int s0 = spos[p], s1 = spos[p + 1];
-              if (r >= s1 - s0) break;
-              const double2 q = prod[s0 + r];
-              sx += q.x;
-              sy += q.y;
-            }
-          }
-          for (int off = L >> 1; off > 0; off >>= 1) {
-            sx += __shfl_xor(sx, off, L);
-            sy += __shfl_xor(sy, off, L);
-          }
-          acc[2 * rh] = sx;
-          acc[2 * rh + 1] = sy;
-          __syncthreads();
-        }
-        if (r < R.nr && lane == 0) {
-          if (base == 0) {
-            epi(R.r0 + orow, acc, pre);
-          } else {
-            const int o2 = a.jperm[R.r0 + r];
-            epi(R.r0 + o2, acc, epi.pre(R.r0 + o2));
-          }
+          for (int r = 0; r < NRHS; ++r)
+            cmac(acc[2 * r], acc[2 * r + 1], v[u], a.x[(int64_t)c[u] * NRHS + r]);
         }
       }
     }
+    if (lane < nr) epi(r0 + orow, acc, pre);
   }
 }
 
@@ -431,12 +341,12 @@ __device__ __forceinline__ void vector_engine(const SpmvArgs &a, Epi &epi) {
   }
 }
 
-// Engines: 0 = jagged layout, 3 = CSR stream, 4..64 = vector with that many
-// lanes per row.
+// Engines: 0 = wave-jagged layout, 3 = CSR stream, 4..64 = vector with that
+// many lanes per row.
 template <int ENGINE, class Epi>
 __device__ __forceinline__ void run_engine(const SpmvArgs &a, Epi &epi) {
   if constexpr (ENGINE == 0)
-    jagged_engine<1>(a, epi);
+    wave_engine<1>(a, epi);
   else if constexpr (ENGINE == 3)
     stream_engine<1>(a, epi);
   else
@@ -591,74 +501,43 @@ __global__ void row_blocks_kernel(const int64_t *rp, int64_t n, int64_t B, int32
   blk[k] = (int32_t)lo;
 }
 
-// Longest row of each row block.
-__global__ void jag_measure_kernel(const int64_t *rp, const int32_t *blk, int64_t nblk,
-                                   int32_t *maxlen) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= nblk) return;
-  int64_t m = 0;
-  for (int64_t r = blk[k]; r < blk[k + 1]; ++r) m = max(m, rp[r + 1] - rp[r]);
-  maxlen[k] = (int32_t)m;
-}
-
-// One workgroup per row block: rank rows by length (longest first, ties by
-// row), count rows per position, scatter the entries position-major.
-__global__ __launch_bounds__(kBlock) void jag_build_kernel(
-    const int64_t *rp, const int32_t *col, const double2 *val, const int32_t *blk,
-    const int32_t *maxlen_arr, const int32_t *pso_arr, JagRec *rec, int32_t *jcol,
-    double2 *jval, unsigned short *jperm, unsigned short *jps) {
-  __shared__ int lens[kCap];
-  __shared__ unsigned short rank[kCap];
-  __shared__ int ps[kCap + 1];
-  const int64_t k = blockIdx.x;
-  const int tid = threadIdx.x;
-  const int64_t r0 = blk[k], r1 = blk[k + 1];
+// Wave-jagged layout, one wavefront per 64-row block: rank the rows by
+// length (longest first, ties by row), then scatter the entries
+// position-major (entry p of rank r at e0 + entries of positions < p + r).
+__global__ __launch_bounds__(kBlock) void wjag_build_kernel(const int64_t *rp, const int32_t *col,
+                                                            const double2 *val, int64_t n,
+                                                            int64_t nwb, int32_t *wcol,
+                                                            double2 *wval, int32_t *wlen,
+                                                            unsigned char *wperm) {
+  const int lane = threadIdx.x & 63;
+  const int64_t k = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  if (k >= nwb) return;  // the whole wavefront leaves together
+  const int64_t r0 = k * kWaveRows;
+  const int nr = (int)min((int64_t)kWaveRows, n - r0);
   const int64_t e0 = rp[r0];
-  const int64_t cnt = rp[r1] - e0;
-  const int64_t nr = r1 - r0;
-  const int maxlen = maxlen_arr[k];
-  const bool fits = cnt <= kCap && nr <= kCap;
-  if (!fits) {
-    for (int64_t e = e0 + tid; e < e0 + cnt; e += kBlock) {
-      jcol[e] = col[e];
-      jval[e] = val[e];
+  const int64_t src0 = lane < nr ? rp[r0 + lane] : 0;
+  const int len = lane < nr ? (int)(rp[r0 + lane + 1] - src0) : -1;  // padding lanes rank last
+  int rank = 0;
+  int maxlen = 0;
+  for (int j = 0; j < 64; ++j) {
+    const int lj = __shfl(len, j, 64);
+    rank += (lj > len) || (lj == len && j < lane);
+    maxlen = lj > maxlen ? lj : maxlen;
+  }
+  if (lane < nr) {
+    wlen[r0 + rank] = len;
+    wperm[r0 + rank] = (unsigned char)lane;
+  }
+  int ps = 0;
+  for (int p = 0; p < maxlen; ++p) {
+    const int cnt = __popcll(__ballot(len > p));
+    if (len > p) {
+      const int64_t dst = e0 + ps + rank;
+      wcol[dst] = col[src0 + p];
+      wval[dst] = val[src0 + p];
     }
-    for (int64_t i = tid; i < nr; i += kBlock) jperm[r0 + i] = (unsigned short)(i & 0xffff);
-    if (tid == 0) rec[k] = JagRec{e0, (int32_t)r0, (int32_t)cnt, (int32_t)nr, maxlen, pso_arr[k], kJagLong};
-    return;
+    ps += cnt;
   }
-  const int inr = (int)nr;
-  for (int i = tid; i < inr; i += kBlock) lens[i] = (int)(rp[r0 + i + 1] - rp[r0 + i]);
-  __syncthreads();
-  for (int i = tid; i < inr; i += kBlock) {
-    const int li = lens[i];
-    int rk = 0;
-    for (int j = 0; j < inr; ++j) rk += (lens[j] > li) || (lens[j] == li && j < i);
-    rank[i] = (unsigned short)rk;
-    jperm[r0 + rk] = (unsigned short)i;
-  }
-  for (int p = tid; p < maxlen; p += kBlock) {
-    int cp = 0;
-    for (int i = 0; i < inr; ++i) cp += lens[i] > p;
-    ps[p + 1] = cp;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    ps[0] = 0;
-    for (int p = 1; p <= maxlen; ++p) ps[p] += ps[p - 1];
-  }
-  __syncthreads();
-  for (int p = tid; p <= maxlen; p += kBlock) jps[pso_arr[k] + p] = (unsigned short)ps[p];
-  for (int i = tid; i < inr; i += kBlock) {
-    const int rk = rank[i];
-    const int64_t src = rp[r0 + i];
-    for (int q = 0; q < lens[i]; ++q) {
-      const int64_t dst = e0 + ps[q] + rk;
-      jcol[dst] = col[src + q];
-      jval[dst] = val[src + q];
-    }
-  }
-  if (tid == 0) rec[k] = JagRec{e0, (int32_t)r0, (int32_t)cnt, (int32_t)nr, maxlen, pso_arr[k], 0};
 }
 
 // max over rows of sum_e |val[e]|  (on the adjoint this is ||L||_1).
@@ -716,7 +595,7 @@ __device__ __forceinline__ bool taylor_prologue(const SpmvArgs &a) {
 }
 
 template <int ENGINE>
-__global__ __launch_bounds__(kBlock) void term_kernel(SpmvArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void term_kernel(SpmvArgs a) {
   if (taylor_prologue(a)) return;
   TaylorEpi epi(a);
   run_engine<ENGINE>(a, epi);
@@ -727,7 +606,7 @@ __global__ __launch_bounds__(kBlock) void term_kernel(SpmvArgs a) {
 }
 
 template <int ENGINE>
-__global__ __launch_bounds__(kBlock) void plain_kernel(SpmvArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void plain_kernel(SpmvArgs a) {
   PlainEpi epi(a);
   run_engine<ENGINE>(a, epi);
 }
@@ -765,7 +644,7 @@ __device__ __forceinline__ bool point_done(const DeviceState *st, PointSlots *pt
 }
 
 template <int ENGINE>
-__global__ __launch_bounds__(kBlock) void series_power_kernel(SpmvArgs a, PointSlots *pt, int k,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void series_power_kernel(SpmvArgs a, PointSlots *pt, int k,
                                                               int p) {
   if (point_done(a.st, pt, k, p, a.tol)) return;
   if (p <= *(volatile int *)&a.st->series.mhat) return;  // K_p already formed
@@ -804,7 +683,7 @@ __global__ __launch_bounds__(kBlock) void series_accum_kernel(DeviceState *st, P
 __global__ __launch_bounds__(kBlock) void spmm2_kernel(SpmvArgs a, int mode, double *part,
                                                        double2 *sgn, double *h) {
   Spmm2Epi epi{a.y, mode, sgn, h};
-  jagged_engine<2>(a, epi);
+  wave_engine<2>(a, epi);
   if (mode == 1) {
     // deterministic per-workgroup column sums: fixed tree over the threads
     __shared__ double sm0[kBlock], sm1[kBlock];
@@ -994,19 +873,13 @@ hipError_t launch_row_blocks(const int64_t *rp, int64_t n, int64_t B, int32_t *b
   return hipGetLastError();
 }
 
-hipError_t launch_jag_measure(const int64_t *rp, const int32_t *blk, int64_t nblk, int32_t *maxlen,
-                              hipStream_t s) {
-  hipLaunchKernelGGL(jag_measure_kernel, dim3(blocks_for(nblk)), dim3(kBlock), 0, s, rp, blk, nblk,
-                     maxlen);
-  return hipGetLastError();
-}
-
-hipError_t launch_jag_build(const int64_t *rp, const int32_t *col, const double2 *val,
-                            const int32_t *blk, int64_t nblk, const int32_t *maxlen,
-                            const int32_t *pso, JagRec *rec, int32_t *jcol, double2 *jval,
-                            unsigned short *jperm, unsigned short *jps, hipStream_t s) {
-  hipLaunchKernelGGL(jag_build_kernel, dim3((unsigned)nblk), dim3(kBlock), 0, s, rp, col, val, blk,
-                     maxlen, pso, rec, jcol, jval, jperm, jps);
+hipError_t launch_wjag_build(const int64_t *rp, const int32_t *col, const double2 *val, int64_t n,
+                             int32_t *wcol, double2 *wval, int32_t *wlen, unsigned char *wperm,
+                             hipStream_t s) {
+  const int64_t nwb = (n + kWaveRows - 1) / kWaveRows;
+  const int64_t grid = (nwb + kBlock / 64 - 1) / (kBlock / 64);
+  hipLaunchKernelGGL(wjag_build_kernel, dim3((unsigned)grid), dim3(kBlock), 0, s, rp, col, val, n,
+                     nwb, wcol, wval, wlen, wperm);
   return hipGetLastError();
 }
 

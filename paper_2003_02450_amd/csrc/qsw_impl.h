@@ -8,7 +8,11 @@ namespace qsw {
 
 constexpr int kMMax = 55;   // largest Taylor degree
 constexpr int kPMax = 8;    // largest p in alpha_p = max(d_p, d_{p+1})
-constexpr int kCap = 2048;  // LDS product slots per workgroup of the stream engine
+#ifndef QSW_BLOCK
+#define QSW_BLOCK 256
+#endif
+constexpr int kBlockThreads = QSW_BLOCK;  // threads per workgroup of the product kernels
+constexpr int kCap = QSW_BLOCK * 8;       // LDS product slots per workgroup (8 entries per lane)
 constexpr int kTopKMax = 16;  // candidates the 1-norm estimator ranks at once
 
 // Norm slots of one scaling step of the single-time algorithm.  Maxima of
@@ -65,20 +69,12 @@ struct AssembleArgs {
   double2 *val;
 };
 
-// Jagged-block execution layout: the rows of each block are ranked by
-// length (longest first) and the block's entries stored position-major:
-// entry p of the row of rank r sits at e0 + ps[pso + p] + r.  Blocks whose
-// entries exceed the LDS stage keep the CSR order (kJagLong).
-constexpr int kJagLong = 1;
-struct JagRec {
-  int64_t e0;      // first entry (same as the CSR row pointer of r0)
-  int32_t r0;      // first row
-  int32_t cnt;     // entries
-  int32_t nr;      // rows
-  int32_t maxlen;  // longest row
-  int32_t pso;     // offset of the block's position starts in ps[]
-  int32_t flags;
-};
+// Wave-jagged execution layout: rows in blocks of 64 (one wavefront each).
+// Inside a block the rows are ranked by length (longest first, ties by row)
+// and the entries stored position-major: entry p of the row of rank r sits at
+// rp[64 k] + (entries of positions < p) + r.  wlen[64 k + r] is the length of
+// the row of rank r and wperm[64 k + r] its index within the block.
+constexpr int kWaveRows = 64;
 
 struct SpmvArgs {
   int64_t n;
@@ -92,13 +88,12 @@ struct SpmvArgs {
   int32_t blocks_per_wg;
   // vector engine: contiguous rows per workgroup
   int64_t rows_per_block;
-  // jagged engine
-  const JagRec *jrec;
-  int32_t njag;
-  const int32_t *jcol;
-  const double2 *jval;
-  const unsigned short *jperm;   // jperm[r0 + rank] = local row of that rank
-  const unsigned short *jps;
+  // wave-jagged engine
+  int64_t nwb;           // blocks of 64 rows
+  const int32_t *wcol;
+  const double2 *wval;
+  const int32_t *wlen;
+  const unsigned char *wperm;
   const double2 *x;      // gathered vector (NRHS interleaved columns for the estimator)
   const double2 *fin;    // accumulator in (Taylor mode)
   double2 *fout;         // accumulator out (may equal fin)
@@ -122,17 +117,13 @@ hipError_t launch_copy(double2 *dst, const double2 *src, int64_t n, hipStream_t 
 hipError_t launch_row_blocks(const int64_t *rp, int64_t n, int64_t B, int32_t *blk, int64_t nblk,
                              hipStream_t s);
 
-// Jagged layout from the CSR and its row blocks: maxlen per block first,
-// then (with pso[] = exclusive prefix of maxlen + 1) the permuted arrays.
-hipError_t launch_jag_measure(const int64_t *rp, const int32_t *blk, int64_t nblk, int32_t *maxlen,
-                              hipStream_t s);
-hipError_t launch_jag_build(const int64_t *rp, const int32_t *col, const double2 *val,
-                            const int32_t *blk, int64_t nblk, const int32_t *maxlen,
-                            const int32_t *pso, JagRec *rec, int32_t *jcol, double2 *jval,
-                            unsigned short *jperm, unsigned short *jps, hipStream_t s);
+// Wave-jagged layout of a CSR (n rows): one wavefront per 64-row block.
+hipError_t launch_wjag_build(const int64_t *rp, const int32_t *col, const double2 *val, int64_t n,
+                             int32_t *wcol, double2 *wval, int32_t *wlen, unsigned char *wperm,
+                             hipStream_t s);
 
-// Engine: 0 = jagged, 3 = CSR stream, 4/8/16/32/64 = vector with that many
-// lanes per row.
+// Engine: 0 = wave-jagged, 3 = CSR stream, 4/8/16/32/64 = vector with that
+// many lanes per row.
 // Single-time algorithm term j: y = alpha A x; F_out = F_in + y; norms into
 // st->step[par]; early exit when the previous terms already passed the test.
 hipError_t launch_taylor_term(const SpmvArgs &a, int engine, int grid, hipStream_t s);
@@ -150,7 +141,7 @@ hipError_t launch_series_accum(DeviceState *st, PointSlots *pt, int k, int p,
                                int64_t n, double tol, int grid, hipStream_t s);
 
 // Block 1-norm estimation helpers: Y = A X for two interleaved right-hand
-// sides (jagged engine; a.x = X, a.y = Y).  mode 0: product only; mode 1:
+// sides (wave-jagged engine; a.x = X, a.y = Y).  mode 0: product only; mode 1:
 // also column |.|_1 partial sums per workgroup into part[2*wg + c] and
 // S = sign(Y) into sgn; mode 2: also h[i] = max_c |Y[i][c]|.
 hipError_t launch_spmm2(const SpmvArgs &a, int mode, double *part, double2 *sgn, double *h,

@@ -142,13 +142,12 @@ struct qsw_superop_s {
   int32_t *blk = nullptr;         // stream engine row blocks
   int32_t nblk = 0;
   int32_t blocks_per_wg = 0;
-  // jagged layout (the propagation kernels' copy of the matrix)
-  JagRec *jrec = nullptr;
-  int32_t *jcol = nullptr;
-  double2 *jval = nullptr;
-  unsigned short *jperm = nullptr;
-  unsigned short *jps = nullptr;
-  int32_t njag = 0;
+  // wave-jagged layout (the product kernels' copy of the matrix)
+  int32_t *wcol = nullptr;
+  double2 *wval = nullptr;
+  int32_t *wlen = nullptr;
+  unsigned char *wperm = nullptr;
+  int64_t nwb = 0;
   // last propagate
   hipEvent_t ev_start = nullptr, ev_end = nullptr;
   unsigned long long *stats_dev = nullptr;  // [products, nonfinite]
@@ -192,7 +191,7 @@ hipError_t make_layout(const int64_t *rp, int64_t n, int64_t nnz, int64_t maxrow
 }
 
 void choose_vector_launch(qsw_superop_s *h, int lpr) {
-  const int rpi = 256 / lpr;
+  const int rpi = kBlockThreads / lpr;
   const int target = 2048;
   int64_t rpb = (h->n + target - 1) / target;
   rpb = std::max<int64_t>(rpi, (rpb + rpi - 1) / rpi * rpi);
@@ -440,86 +439,57 @@ struct Estimator {
   }
 };
 
-// Jagged execution layout (see JagRec) of one CSR over its row blocks.
-struct JagLayout {
-  JagRec *rec = nullptr;
+// Wave-jagged execution layout (see kWaveRows) of one CSR.
+struct WaveLayout {
   int32_t *col = nullptr;
   double2 *val = nullptr;
-  unsigned short *perm = nullptr;
-  unsigned short *ps = nullptr;
-  int32_t n = 0;  // blocks
+  int32_t *len = nullptr;
+  unsigned char *perm = nullptr;
+  int64_t nwb = 0;
   void release() {
-    dfree(rec);
     dfree(col);
     dfree(val);
+    dfree(len);
     dfree(perm);
-    dfree(ps);
   }
 };
 
-hipError_t build_jag_layout(const int64_t *rp, const int32_t *col, const double2 *val,
-                            const int32_t *blk, int64_t nblk, int64_t n, int64_t nnz,
-                            hipStream_t s, JagLayout &J) {
-  int32_t *dmax = nullptr, *dpso = nullptr;
-  std::vector<int32_t> hmax((size_t)nblk), hpso((size_t)nblk + 1);
+hipError_t build_wave_layout(const int64_t *rp, const int32_t *col, const double2 *val, int64_t n,
+                             int64_t nnz, hipStream_t s, WaveLayout &W) {
   hipError_t e;
-  do {
-    if ((e = dalloc(&dmax, (size_t)nblk)) != hipSuccess) break;
-    if ((e = launch_jag_measure(rp, blk, nblk, dmax, s)) != hipSuccess) break;
-    if ((e = hipMemcpyAsync(hmax.data(), dmax, (size_t)nblk * sizeof(int32_t),
-                            hipMemcpyDeviceToHost, s)) != hipSuccess)
-      break;
-    if ((e = hipStreamSynchronize(s)) != hipSuccess) break;
-    hpso[0] = 0;
-    for (int64_t k = 0; k < nblk; ++k) {
-      const int64_t next = (int64_t)hpso[k] + hmax[k] + 1;
-      if (next > std::numeric_limits<int32_t>::max()) {
-        e = hipErrorInvalidValue;
-        break;
-      }
-      hpso[k + 1] = (int32_t)next;
-    }
-    if (e != hipSuccess) break;
-    if ((e = dalloc(&dpso, (size_t)nblk + 1)) != hipSuccess) break;
-    if ((e = hipMemcpyAsync(dpso, hpso.data(), ((size_t)nblk + 1) * sizeof(int32_t),
-                            hipMemcpyHostToDevice, s)) != hipSuccess)
-      break;
-    if ((e = dalloc(&J.rec, (size_t)nblk)) != hipSuccess) break;
-    if ((e = dalloc(&J.col, (size_t)nnz)) != hipSuccess) break;
-    if ((e = dalloc(&J.val, (size_t)nnz)) != hipSuccess) break;
-    if ((e = dalloc(&J.perm, (size_t)n)) != hipSuccess) break;
-    if ((e = dalloc(&J.ps, (size_t)hpso[nblk])) != hipSuccess) break;
-    if ((e = launch_jag_build(rp, col, val, blk, nblk, dmax, dpso, J.rec, J.col, J.val, J.perm,
-                              J.ps, s)) != hipSuccess)
-      break;
-    e = hipStreamSynchronize(s);  // host arrays above must outlive the copies
-  } while (false);
-  dfree(dmax);
-  dfree(dpso);
-  if (e == hipSuccess) J.n = (int32_t)nblk;
-  return e;
+  if ((e = dalloc(&W.col, (size_t)nnz)) != hipSuccess) return e;
+  if ((e = dalloc(&W.val, (size_t)nnz)) != hipSuccess) return e;
+  if ((e = dalloc(&W.len, (size_t)n)) != hipSuccess) return e;
+  if ((e = dalloc(&W.perm, (size_t)n)) != hipSuccess) return e;
+  if ((e = launch_wjag_build(rp, col, val, n, W.col, W.val, W.len, W.perm, s)) != hipSuccess)
+    return e;
+  W.nwb = (n + kWaveRows - 1) / kWaveRows;
+  return hipSuccess;
 }
 
-qsw_status_t build_jagged(qsw_superop_s *h, hipStream_t s) {
-  JagLayout J;
-  hipError_t e = build_jag_layout(h->row_ptr, h->col, h->val, h->blk, h->nblk, h->n, h->nnz, s, J);
-  h->jrec = J.rec;
-  h->jcol = J.col;
-  h->jval = J.val;
-  h->jperm = J.perm;
-  h->jps = J.ps;
-  if (e != hipSuccess) return status_of(e);
-  h->njag = J.n;
-  return QSW_OK;
+void set_wave(SpmvArgs &a, const WaveLayout &W) {
+  a.nwb = W.nwb;
+  a.wcol = W.col;
+  a.wval = W.val;
+  a.wlen = W.len;
+  a.wperm = W.perm;
 }
 
-void set_jagged(SpmvArgs &a, const JagLayout &J) {
-  a.jrec = J.rec;
-  a.njag = J.n;
-  a.jcol = J.col;
-  a.jval = J.val;
-  a.jperm = J.perm;
-  a.jps = J.ps;
+void set_wave(SpmvArgs &a, const qsw_superop_s *h) {
+  a.nwb = h->nwb;
+  a.wcol = h->wcol;
+  a.wval = h->wval;
+  a.wlen = h->wlen;
+  a.wperm = h->wperm;
+}
+
+// Workgroups of a wave-jagged launch: one wavefront per block up to four
+// times the resident capacity, then blocks per wavefront grow.
+int wave_grid(int64_t nwb, int resident) {
+  const int64_t wgs = (nwb + kBlockThreads / 64 - 1) / (kBlockThreads / 64);
+  int64_t cap = 4 * (int64_t)std::max(resident, 1);
+  cap = env_int("QSW_GRID", (int)cap);
+  return (int)std::max<int64_t>(1, std::min(wgs, cap));
 }
 
 qsw_status_t build_common(HostOps &op, double omega, hipStream_t s, qsw_superop_t *out) {
@@ -560,12 +530,18 @@ qsw_status_t build_common(HostOps &op, double omega, hipStream_t s, qsw_superop_
     h->blk = L.blk;
     h->nblk = L.nblk;
     h->blocks_per_wg = L.bpw;
-    // jagged layout over the same row blocks
-    st = build_jagged(h, s);
-    if (st != QSW_OK) return fail(st);
+    // wave-jagged copy for the product kernels
+    WaveLayout W;
+    hipError_t we = build_wave_layout(h->row_ptr, h->col, h->val, h->n, h->nnz, s, W);
+    h->wcol = W.col;
+    h->wval = W.val;
+    h->wlen = W.len;
+    h->wperm = W.perm;
+    if (we != hipSuccess) return fail(status_of(we));
+    h->nwb = W.nwb;
     const int eng = env_int("QSW_ENGINE", 0);
     h->engine = 0;
-    h->grid = std::max(1, std::min<int>(resident1, h->njag));
+    h->grid = wave_grid(h->nwb, resident1);
     if (eng == 3) {
       h->engine = 3;
       h->grid = L.grid;
@@ -582,8 +558,7 @@ qsw_status_t build_common(HostOps &op, double omega, hipStream_t s, qsw_superop_
   if (st != QSW_OK) return fail(st);
   unsigned long long *nbits = nullptr;
   Estimator E{};
-  Layout LA;
-  JagLayout JA;
+  WaveLayout WA;
   hipError_t e = hipSuccess;
   double norm1 = 0.0;
   do {
@@ -601,17 +576,15 @@ qsw_status_t build_common(HostOps &op, double omega, hipStream_t s, qsw_superop_
       h->info.d_probe[p] = 0;
     }
     if (!(norm1 > 0.0)) break;  // L = 0: every d_p is 0
-    // adjoint row blocks and jagged layout (transient)
-    if ((e = make_layout(arp, n, annz, maxrow, kCap, resident1, s, LA)) != hipSuccess) break;
-    if ((e = build_jag_layout(arp, acol, aval, LA.blk, LA.nblk, n, annz, s, JA)) != hipSuccess) break;
+    // adjoint wave-jagged layout (transient)
+    if ((e = build_wave_layout(arp, acol, aval, n, annz, s, WA)) != hipSuccess) break;
     E.n = n;
     E.s = s;
     E.fwd.n = n; E.fwd.rp = h->row_ptr; E.fwd.col = h->col; E.fwd.val = h->val;
-    E.fwd.jrec = h->jrec; E.fwd.njag = h->njag; E.fwd.jcol = h->jcol; E.fwd.jval = h->jval;
-    E.fwd.jperm = h->jperm; E.fwd.jps = h->jps;
+    set_wave(E.fwd, h);
     E.adj.n = n; E.adj.rp = arp; E.adj.col = acol; E.adj.val = aval;
-    set_jagged(E.adj, JA);
-    E.grid = std::max(1, std::min(resident_workgroups(1), std::max(h->njag, JA.n)));
+    set_wave(E.adj, WA);
+    E.grid = wave_grid(h->nwb, resident_workgroups(1));
     if ((e = dalloc(&E.X, 2 * (size_t)n)) != hipSuccess) break;
     if ((e = dalloc(&E.Y, 2 * (size_t)n)) != hipSuccess) break;
     if ((e = dalloc(&E.W0, 2 * (size_t)n)) != hipSuccess) break;
@@ -636,8 +609,7 @@ qsw_status_t build_common(HostOps &op, double omega, hipStream_t s, qsw_superop_
   } while (false);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   dfree(nbits);
-  dfree(LA.blk);
-  JA.release();
+  WA.release();
   dfree(E.X); dfree(E.Y); dfree(E.W0); dfree(E.W1); dfree(E.S); dfree(E.h); dfree(E.part); dfree(E.sums);
   dfree(E.cand_v); dfree(E.cand_i); dfree(E.top_v); dfree(E.top_i);
   dfree(arp); dfree(acol); dfree(aval);
@@ -731,12 +703,7 @@ struct Runner {
     a.blk = h->blk;
     a.nblk = h->nblk;
     a.blocks_per_wg = h->blocks_per_wg;
-    a.jrec = h->jrec;
-    a.njag = h->njag;
-    a.jcol = h->jcol;
-    a.jval = h->jval;
-    a.jperm = h->jperm;
-    a.jps = h->jps;
+    set_wave(a, h);
     return a;
   }
 
@@ -934,11 +901,10 @@ void qsw_superop_destroy(qsw_superop_t h) {
   dfree(h->val);
   dfree(h->stats_dev);
   dfree(h->blk);
-  dfree(h->jrec);
-  dfree(h->jcol);
-  dfree(h->jval);
-  dfree(h->jperm);
-  dfree(h->jps);
+  dfree(h->wcol);
+  dfree(h->wval);
+  dfree(h->wlen);
+  dfree(h->wperm);
   if (h->ev_start) (void)hipEventDestroy(h->ev_start);
   if (h->ev_end) (void)hipEventDestroy(h->ev_end);
   delete h;
@@ -1084,12 +1050,7 @@ qsw_status_t qsw_apply(qsw_superop_t h, const void *x, void *y, void *hip_stream
   a.blk = h->blk;
   a.nblk = h->nblk;
   a.blocks_per_wg = h->blocks_per_wg;
-  a.jrec = h->jrec;
-  a.njag = h->njag;
-  a.jcol = h->jcol;
-  a.jval = h->jval;
-  a.jperm = h->jperm;
-  a.jps = h->jps;
+  set_wave(a, h);
   HIP_TRY(launch_spmv(a, h->engine, h->grid, (hipStream_t)hip_stream));
   return QSW_OK;
 }
