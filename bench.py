@@ -12,8 +12,11 @@ Prints one JSON line.  `value` is rho(t) grid steps per second of the whole
 pass.  `roofline` rates the fused Taylor-term product kernel: algorithmic
 bytes of the products it computed (20 nnz + 8 (n+1) + 64 n per product)
 over the device time of the timed propagate calls, measured with HIP events
-on the stream the kernels run on.  `cpu_baseline` times the CPU oracle on a
-bounded sample of the same workload.
+on the stream the kernels run on.  `single_values` repeats the pass with
+the superoperator values stored as complex64 and the 2^-24 tolerance
+(vectors and sums stay double) and reports its rate, its product kernel's
+bandwidth and its largest deviation from the double pass.  `cpu_baseline`
+times the CPU oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -52,11 +55,13 @@ def measured_traffic():
         return None
 
 
-def term_bytes(n: int, nnz: int) -> float:
+def term_bytes(n: int, nnz: int, value_bytes: int = 16, series: bool = False) -> float:
     """Algorithmic HBM bytes of one Taylor-term product: values and column
-    indices (16 + 4 per entry), row pointers, x gathered once, the new term
-    written, the accumulator read and written."""
-    return 20.0 * nnz + 8.0 * (n + 1) + 64.0 * n
+    indices (16 + 4 per entry, 8 + 4 with complex64 values), row pointers, x
+    gathered once, the new term written, the accumulator read and written
+    (the time-series branch writes the power and accumulates in a second
+    pass: 16 n more)."""
+    return (value_bytes + 4.0) * nnz + 8.0 * (n + 1) + (80.0 if series else 64.0) * n
 
 
 def cpu_baseline(wl, sample_steps: int) -> dict:
@@ -82,6 +87,41 @@ def cpu_baseline(wl, sample_steps: int) -> dict:
                        f"rate = {wl.n_steps} / (build + {wl.n_steps} x mean interval)")}
 
 
+def single_leg(args, one_pass, out64, torch, n, nnz, q, wl) -> dict:
+    """The same pass with complex64 superoperator values and the 2^-24
+    tolerance (vectors and sums in double), timed the same way, and its
+    largest element difference from the double pass over all 51 points."""
+    out32 = torch.empty_like(out64)
+    for _ in range(args.warmup):
+        one_pass(True, out32)
+    torch.cuda.synchronize()
+    stats = []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        stats.append(one_pass(True, out32))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    prop_ms = sum(s["ms"] for s, _ in stats)
+    products = sum(s["products"] for s, _ in stats)
+    launched = sum(s["launched"] for s, _ in stats)
+    st0, info0 = stats[0]
+    per = term_bytes(n, nnz, 8, st0["branch"] == 1)
+    achieved = products * per / (prop_ms * 1e-3) / 1e9
+    diff = float((out32 - out64).abs().max().item())
+    bound = 2.0 * 2.0 ** -24 * (q * wl.dt) * info0["norm1"] * float(abs(wl.rho0).sum())
+    return {"value": args.steps * q / elapsed, "unit": "steps/s",
+            "ms_per_step": 1e3 * elapsed / args.steps, "dtype": "c64 values, f64 vectors",
+            "m": st0["m"], "s": st0["s"],
+            "branch": "single-time per interval" if st0["branch"] == 0 else "series",
+            "propagate_ms": round(prop_ms / args.steps, 3),
+            "products_per_step": products // args.steps,
+            "term_launches_per_step": launched // args.steps,
+            "achieved": achieved, "frac": achieved / HBM_PEAK_GBPS,
+            "bytes_per_product": per,
+            "avg_product_us": 1e3 * prop_ms / max(products, 1),
+            "max_abs_diff_vs_double": diff, "first_order_bound_t50": bound}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +129,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-sample-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-single", action="store_true",
+                    help="skip the complex64-values leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the batched and "
@@ -122,9 +164,11 @@ def main() -> int:
     n, nnz = probe.n, probe.nnz
     probe.close()
 
-    def one_pass():
+    def one_pass(single=False, dst=out):
         op = build()
-        op.propagate(rho0, wl.t0, wl.dt, q, out=out, workspace=ws)
+        if single:
+            op.set_precision(True)
+        op.propagate(rho0, wl.t0, wl.dt, q, out=dst, workspace=ws)
         st = op.last_stats()        # waits for the pass on the library stream
         info = op.info()
         op.close()
@@ -170,13 +214,15 @@ def main() -> int:
                    "propagate_ms": round(prop_ms / args.steps, 3),
                    "products_per_step": products // args.steps,
                    "term_launches_per_step": launched // args.steps},
-        "roofline": {"bound": "hbm", "kernel": "term_kernel (CSR product + Taylor epilogue)",
+        "roofline": {"bound": "hbm", "kernel": "term_kernel<100> (CSR product + Taylor epilogue)",
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(),
                      "bytes_per_product": term_bytes(n, nnz),
                      "avg_launch_us": 1e3 * prop_ms / max(launched, 1),
                      "avg_product_us": 1e3 * prop_ms / max(products, 1)},
     }
+    if not args.no_single:
+        result["single_values"] = single_leg(args, one_pass, out, torch, n, nnz, q, wl)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_steps)
     print(json.dumps(result), flush=True)

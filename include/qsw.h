@@ -89,7 +89,10 @@ typedef struct {
     int64_t products;    /* sparse products actually computed (early termination skips the rest) */
     int32_t nonfinite;   /* 1 if any norm in the run was NaN or infinite */
     double ms;           /* device time of the last propagate call (events on its stream) */
-    double bytes;        /* algorithmic HBM bytes of the computed products (see design notes) */
+    double bytes;        /* algorithmic HBM bytes of the computed products: per product
+                            (20 or 12) nnz + 8 (n+1) + (64 or 80) n for double or single
+                            values and branch 0 or 1 (branch 1 adds the accumulation pass) */
+    int32_t prec;        /* QSW_PREC_* the call ran with */
 } qsw_stats_t;
 
 /* ---------------------------------------------------------------- build */
@@ -135,6 +138,25 @@ qsw_status_t qsw_superop_build_ops(int32_t N,
 void qsw_superop_destroy(qsw_superop_t h);
 
 qsw_status_t qsw_superop_info(qsw_superop_t h, qsw_info_t *info);
+
+/*
+ * Precision of later qsw_propagate calls on this handle (default
+ * QSW_PREC_DOUBLE).
+ *   QSW_PREC_SINGLE: the product kernels read a complex64 copy of the
+ *     superoperator values (each component rounded to nearest; made here, 8
+ *     bytes per entry of device memory, kept until QSW_PREC_DOUBLE is set or
+ *     the handle is destroyed), theta_m and the stopping test use
+ *     u = 2^-24 (Al-Mohy and Higham's single-precision choice), and vectors,
+ *     products, sums and norms stay complex128 / double.  rho(t) then carries
+ *     a backward error of at most about 2 u ||L||_1 per unit time (value
+ *     rounding plus truncation) instead of u = 2^-53.
+ *   ||L||_1, the d_p and the parameter choice always come from the complex128
+ *   values; qsw_apply and qsw_superop_copy_csr always use them.
+ * Returns QSW_ERR_STATE when the handle runs a product engine other than the
+ * default one (the copy exists for its layout only), QSW_ERR_OOM when the copy
+ * does not fit.  Synchronous; changes the workspace size a plan needs.
+ */
+qsw_status_t qsw_superop_set_precision(qsw_superop_t h, int32_t prec);
 
 /* Copy the device CSR to caller host buffers (row_ptr[n+1], col[nnz],
  * val[2*nnz] doubles), rows in the structural order described at

@@ -157,6 +157,15 @@ class Superop:
         _lib.check(st, "qsw_superop_copy_csr")
         return rp, col, val
 
+    def set_precision(self, single: bool):
+        """single=True: later propagate calls read complex64 superoperator
+        values and use the 2^-24 tolerance; vectors and sums stay complex128."""
+        torch = _torch()
+        with torch.cuda.device(self.device):
+            st = _lib.load().qsw_superop_set_precision(
+                self._h, _lib.QSW_PREC_SINGLE if single else _lib.QSW_PREC_DOUBLE)
+        _lib.check(st, "qsw_superop_set_precision")
+
     def workspace_bytes(self, t0, dt, n_steps) -> int:
         return int(_lib.load().qsw_propagate_workspace_bytes(self._h, float(t0), float(dt),
                                                              int(n_steps)))
@@ -210,7 +219,8 @@ class Superop:
             _lib.check(st, "qsw_last_stats")
         return {"branch": s.branch, "m": s.m, "s": s.s, "m0": s.m0, "s0": s.s0,
                 "launched": s.launched, "products": s.products, "nonfinite": bool(s.nonfinite),
-                "ms": s.ms, "bytes": s.bytes}
+                "ms": s.ms, "bytes": s.bytes,
+                "prec": "single" if s.prec == _lib.QSW_PREC_SINGLE else "double"}
 
     def apply(self, x, out=None):
         """y = L x for a length-n complex128 device vector."""

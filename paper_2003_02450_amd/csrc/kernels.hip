@@ -86,6 +86,14 @@ __device__ __forceinline__ int load_stream(const int32_t *p) {
   return __builtin_nontemporal_load(p);
 }
 
+typedef float fvec2 __attribute__((ext_vector_type(2)));
+
+// A complex64 entry widened to complex128 (exact).
+__device__ __forceinline__ double2 load_stream(const float2 *p) {
+  const fvec2 v = __builtin_nontemporal_load(reinterpret_cast<const fvec2 *>(p));
+  return make_double2((double)v.x, (double)v.y);
+}
+
 __device__ __forceinline__ void cmac(double &ax, double &ay, double2 v, double2 x) {
   ax = fma(v.x, x.x, ax);
   ax = fma(-v.y, x.y, ax);
@@ -264,17 +272,40 @@ __device__ __forceinline__ void stream_engine(const SpmvArgs &a, Epi &epi) {
 // cnt_p = popcount(ballot(len > p)), and their entries sit next to each other,
 // so every load instruction reads consecutive entries.  The leading entries
 // of the rows of one rho-row (the H rho part, columns c N + b) share c at
-// each position, so their x gathers fall on a few cache lines.  No LDS, no
-// barriers; kWaveUnroll positions are in flight per lane.  Each lane sums its
-// row in position order, so the result is bitwise reproducible.
+// each position, so their x gathers fall on a few cache lines.  No barriers
+// between the waves of a workgroup unless STAGE; kWaveUnroll positions are in
+// flight per lane.  Each lane sums its row in position order, so the result
+// is bitwise reproducible and independent of F32 / STAGE choices other than
+// the value type.
+//
+// F32: read the complex64 copy of the values (wval32) instead of wval; every
+// product and sum stays in double precision.
+// STAGE: the rho H entries of row (a, b) gather x[a N + c] for the neighbours
+// c of b, scattered over the whole rho-row a, which misses the L1 and moves a
+// 128-byte line per 16-byte element.  The workgroup's four blocks (256
+// consecutive rows) share a unless they straddle a rho-row, so the workgroup
+// copies x[a N .. a N + N) of its first row into LDS once and every column in
+// that range is read from there (any row may use it: the test is on the
+// column).  Needs N * 16 bytes of dynamic LDS.
 constexpr int kWaveUnroll = 6;
 
-template <int NRHS, class Epi>
+template <int NRHS, bool F32, bool STAGE, class Epi>
 __device__ __forceinline__ void wave_engine(const SpmvArgs &a, Epi &epi) {
   constexpr int WPB = kBlock / 64;  // wavefronts per workgroup
   const int lane = threadIdx.x & 63;
   const int64_t nw = (int64_t)gridDim.x * WPB;
-  for (int64_t k = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6); k < a.nwb; k += nw) {
+  extern __shared__ double2 xs[];
+  static_assert(!STAGE || NRHS == 1, "staging holds one right-hand side");
+  for (int64_t kb = (int64_t)blockIdx.x * WPB; kb < a.nwb; kb += nw) {
+    int64_t base = 0;
+    if constexpr (STAGE) {
+      base = (kb * kWaveRows) / a.N * a.N;
+      __syncthreads();  // the previous blocks are done with xs
+      for (int i = threadIdx.x; i < a.N; i += kBlock) xs[i] = a.x[base + i];
+      __syncthreads();
+    }
+    const int64_t k = kb + (threadIdx.x >> 6);
+    if (k >= a.nwb) continue;
     const int64_t r0 = k * kWaveRows;
     const int nr = (int)min((int64_t)kWaveRows, a.n - r0);
     const int64_t e0 = a.rp[r0];
@@ -283,35 +314,51 @@ __device__ __forceinline__ void wave_engine(const SpmvArgs &a, Epi &epi) {
     typename Epi::Pre pre{};
     if (lane < nr) pre = epi.pre(r0 + orow);
     const int maxlen = __shfl(len, 0, 64);  // rank 0 is the longest row
-    int ps = 0;
     double acc[2 * NRHS];
 #pragma unroll
     for (int q = 0; q < 2 * NRHS; ++q) acc[q] = 0.0;
+    // Branch-free body.  Position p's entries start at the wave-uniform
+    // offset ps_p, so lane l reads entry e0 + ps_p + l whether or not its row
+    // is still running (entries past the row belong to other rows, the next
+    // block or the zero padding after the arrays: always a valid column) and
+    // discards the product when it is not.  With no branch around them,
+    // every load of an iteration is issued before the first wait.
+    const int32_t *cb = a.wcol + e0;
+    int ps = 0;
     for (int p0 = 0; p0 < maxlen; p0 += kWaveUnroll) {
-      int off[kWaveUnroll];
+      int bcur[kWaveUnroll];
       bool ok[kWaveUnroll];
 #pragma unroll
       for (int u = 0; u < kWaveUnroll; ++u) {
         const int cnt = __popcll(__ballot(len > p0 + u));
         ok[u] = lane < cnt;
-        off[u] = ps + lane;
+        bcur[u] = ps + lane;
         ps += cnt;
       }
       int c[kWaveUnroll];
+#pragma unroll
+      for (int u = 0; u < kWaveUnroll; ++u) c[u] = load_stream(cb + bcur[u]);
       double2 v[kWaveUnroll];
 #pragma unroll
       for (int u = 0; u < kWaveUnroll; ++u) {
-        if (ok[u]) {
-          c[u] = load_stream(a.wcol + e0 + off[u]);
-          v[u] = load_stream(a.wval + e0 + off[u]);
-        }
+        if constexpr (F32)
+          v[u] = load_stream(a.wval32 + e0 + bcur[u]);
+        else
+          v[u] = load_stream(a.wval + e0 + bcur[u]);
       }
 #pragma unroll
       for (int u = 0; u < kWaveUnroll; ++u) {
-        if (ok[u]) {
+        const double2 vz = ok[u] ? v[u] : make_double2(0.0, 0.0);
+        if constexpr (STAGE) {
+          const uint64_t o = (uint64_t)((int64_t)c[u] - base);
+          const bool in_row = o < (uint64_t)a.N;
+          const double2 xl = xs[in_row ? o : 0];
+          const double2 xg = a.x[in_row ? base : (int64_t)c[u]];
+          cmac(acc[0], acc[1], vz, in_row ? xl : xg);
+        } else {
 #pragma unroll
           for (int r = 0; r < NRHS; ++r)
-            cmac(acc[2 * r], acc[2 * r + 1], v[u], a.x[(int64_t)c[u] * NRHS + r]);
+            cmac(acc[2 * r], acc[2 * r + 1], vz, a.x[(int64_t)c[u] * NRHS + r]);
         }
       }
     }
@@ -341,12 +388,19 @@ __device__ __forceinline__ void vector_engine(const SpmvArgs &a, Epi &epi) {
   }
 }
 
-// Engines: 0 = wave-jagged layout, 3 = CSR stream, 4..64 = vector with that
-// many lanes per row.
+// Engines: 0 = wave-jagged layout, 1 = the same with complex64 values,
+// 100 / 101 = the same with the rho-row staged in LDS, 3 = CSR stream,
+// 4..64 = vector with that many lanes per row.
 template <int ENGINE, class Epi>
 __device__ __forceinline__ void run_engine(const SpmvArgs &a, Epi &epi) {
   if constexpr (ENGINE == 0)
-    wave_engine<1>(a, epi);
+    wave_engine<1, false, false>(a, epi);
+  else if constexpr (ENGINE == 1)
+    wave_engine<1, true, false>(a, epi);
+  else if constexpr (ENGINE == 100)
+    wave_engine<1, false, true>(a, epi);
+  else if constexpr (ENGINE == 101)
+    wave_engine<1, true, true>(a, epi);
   else if constexpr (ENGINE == 3)
     stream_engine<1>(a, epi);
   else
@@ -561,6 +615,15 @@ __global__ void zero_kernel(unsigned int *p, size_t words) {
     p[i] = 0u;
 }
 
+// Round complex128 values to complex64 (to nearest, per component).
+__global__ void to_c64_kernel(float2 *dst, const double2 *src, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double2 v = src[i];
+    dst[i] = make_float2((float)v.x, (float)v.y);
+  }
+}
+
 __global__ void copy_kernel(double2 *dst, const double2 *src, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -683,7 +746,7 @@ __global__ __launch_bounds__(kBlock) void series_accum_kernel(DeviceState *st, P
 __global__ __launch_bounds__(kBlock) void spmm2_kernel(SpmvArgs a, int mode, double *part,
                                                        double2 *sgn, double *h) {
   Spmm2Epi epi{a.y, mode, sgn, h};
-  wave_engine<2>(a, epi);
+  wave_engine<2, false, false>(a, epi);
   if (mode == 1) {
     // deterministic per-workgroup column sums: fixed tree over the threads
     __shared__ double sm0[kBlock], sm1[kBlock];
@@ -906,9 +969,20 @@ hipError_t launch_copy(double2 *dst, const double2 *src, int64_t n, hipStream_t 
   return hipGetLastError();
 }
 
+hipError_t launch_to_c64(float2 *dst, const double2 *src, int64_t n, hipStream_t s) {
+  int grid = blocks_for(n);
+  if (grid > 8192) grid = 8192;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(to_c64_kernel, dim3(grid), dim3(kBlock), 0, s, dst, src, n);
+  return hipGetLastError();
+}
+
 #define QSW_ENGINE_SWITCH(ENG, CALL)      \
   switch (ENG) {                          \
     case 0: CALL(0); break;               \
+    case 1: CALL(1); break;               \
+    case 100: CALL(100); break;           \
+    case 101: CALL(101); break;           \
     case 3: CALL(3); break;               \
     case 4: CALL(4); break;               \
     case 8: CALL(8); break;               \
@@ -918,15 +992,22 @@ hipError_t launch_copy(double2 *dst, const double2 *src, int64_t n, hipStream_t 
     default: return hipErrorInvalidValue; \
   }
 
+// Dynamic LDS of a product launch: the staged rho-row for engines 100/101.
+inline size_t stage_bytes(int engine, const SpmvArgs &a) {
+  return engine >= 100 ? (size_t)a.N * sizeof(double2) : 0;
+}
+
 hipError_t launch_taylor_term(const SpmvArgs &a, int engine, int grid, hipStream_t s) {
-#define QSW_L(E) hipLaunchKernelGGL(term_kernel<E>, dim3(grid), dim3(kBlock), 0, s, a)
+#define QSW_L(E) \
+  hipLaunchKernelGGL(term_kernel<E>, dim3(grid), dim3(kBlock), stage_bytes(E, a), s, a)
   QSW_ENGINE_SWITCH(engine, QSW_L)
 #undef QSW_L
   return hipGetLastError();
 }
 
 hipError_t launch_spmv(const SpmvArgs &a, int engine, int grid, hipStream_t s) {
-#define QSW_L(E) hipLaunchKernelGGL(plain_kernel<E>, dim3(grid), dim3(kBlock), 0, s, a)
+#define QSW_L(E) \
+  hipLaunchKernelGGL(plain_kernel<E>, dim3(grid), dim3(kBlock), stage_bytes(E, a), s, a)
   QSW_ENGINE_SWITCH(engine, QSW_L)
 #undef QSW_L
   return hipGetLastError();
@@ -945,7 +1026,8 @@ hipError_t launch_series_init(DeviceState *st, PointSlots *pts, int npts, const 
 hipError_t launch_series_power(const SpmvArgs &a, PointSlots *pt, int k, int p, int engine,
                                int grid, hipStream_t s) {
 #define QSW_L(E) \
-  hipLaunchKernelGGL(series_power_kernel<E>, dim3(grid), dim3(kBlock), 0, s, a, pt, k, p)
+  hipLaunchKernelGGL(series_power_kernel<E>, dim3(grid), dim3(kBlock), stage_bytes(E, a), s, a, \
+                     pt, k, p)
   QSW_ENGINE_SWITCH(engine, QSW_L)
 #undef QSW_L
   return hipGetLastError();

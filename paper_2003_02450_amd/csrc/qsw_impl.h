@@ -75,6 +75,8 @@ struct AssembleArgs {
 // rp[64 k] + (entries of positions < p) + r.  wlen[64 k + r] is the length of
 // the row of rank r and wperm[64 k + r] its index within the block.
 constexpr int kWaveRows = 64;
+constexpr int kWavePad = 64;  // zero entries after the wave-jagged arrays (reads past a block's end)
+constexpr size_t kStageMaxBytes = 32768;  // largest LDS-staged rho-row (N <= 2048)
 
 struct SpmvArgs {
   int64_t n;
@@ -89,9 +91,11 @@ struct SpmvArgs {
   // vector engine: contiguous rows per workgroup
   int64_t rows_per_block;
   // wave-jagged engine
+  int32_t N;             // graph order (rho-row length for the staged engines)
   int64_t nwb;           // blocks of 64 rows
   const int32_t *wcol;
   const double2 *wval;
+  const float2 *wval32;  // complex64 copy of wval (engine 1), or null
   const int32_t *wlen;
   const unsigned char *wperm;
   const double2 *x;      // gathered vector (NRHS interleaved columns for the estimator)
@@ -111,6 +115,7 @@ hipError_t launch_row_abs_max(int64_t n, const int64_t *rp, const double2 *val,
                               unsigned long long *out_bits, hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_copy(double2 *dst, const double2 *src, int64_t n, hipStream_t s);
+hipError_t launch_to_c64(float2 *dst, const double2 *src, int64_t n, hipStream_t s);
 
 // Stream-engine row blocks: block k starts at the first row whose first
 // entry index is >= k B; blk has nblk + 1 entries.

@@ -136,7 +136,8 @@ struct qsw_superop_s {
   double2 *val = nullptr;
   qsw_info_t info{};
   // launch shape of the product kernels
-  int engine = 0;                 // 0: stream engine; 4..64: vector engine lanes per row
+  int engine = 0;                 // 0 / 100: wave-jagged (100: rho-row staged in LDS);
+                                  // 3: CSR stream; 4..64: vector engine lanes per row
   int grid = 0;                   // workgroups of a product launch
   int64_t rows_per_block = 0;     // vector engine
   int32_t *blk = nullptr;         // stream engine row blocks
@@ -145,6 +146,8 @@ struct qsw_superop_s {
   // wave-jagged layout (the product kernels' copy of the matrix)
   int32_t *wcol = nullptr;
   double2 *wval = nullptr;
+  float2 *wval32 = nullptr;       // complex64 values for QSW_PREC_SINGLE propagation
+  int prec = QSW_PREC_DOUBLE;     // precision of qsw_propagate
   int32_t *wlen = nullptr;
   unsigned char *wperm = nullptr;
   int64_t nwb = 0;
@@ -457,8 +460,12 @@ struct WaveLayout {
 hipError_t build_wave_layout(const int64_t *rp, const int32_t *col, const double2 *val, int64_t n,
                              int64_t nnz, hipStream_t s, WaveLayout &W) {
   hipError_t e;
-  if ((e = dalloc(&W.col, (size_t)nnz)) != hipSuccess) return e;
-  if ((e = dalloc(&W.val, (size_t)nnz)) != hipSuccess) return e;
+  // kWavePad zero entries (column 0, value 0) after the last one: the
+  // product loops read up to 63 entries past a block's end
+  if ((e = dalloc(&W.col, (size_t)nnz + kWavePad)) != hipSuccess) return e;
+  if ((e = dalloc(&W.val, (size_t)nnz + kWavePad)) != hipSuccess) return e;
+  if ((e = launch_zero(W.col + nnz, kWavePad * sizeof(int32_t), s)) != hipSuccess) return e;
+  if ((e = launch_zero(W.val + nnz, kWavePad * sizeof(double2), s)) != hipSuccess) return e;
   if ((e = dalloc(&W.len, (size_t)n)) != hipSuccess) return e;
   if ((e = dalloc(&W.perm, (size_t)n)) != hipSuccess) return e;
   if ((e = launch_wjag_build(rp, col, val, n, W.col, W.val, W.len, W.perm, s)) != hipSuccess)
@@ -477,8 +484,10 @@ void set_wave(SpmvArgs &a, const WaveLayout &W) {
 
 void set_wave(SpmvArgs &a, const qsw_superop_s *h) {
   a.nwb = h->nwb;
+  a.N = h->N;
   a.wcol = h->wcol;
   a.wval = h->wval;
+  a.wval32 = h->wval32;
   a.wlen = h->wlen;
   a.wperm = h->wperm;
 }
@@ -540,7 +549,10 @@ qsw_status_t build_common(HostOps &op, double omega, hipStream_t s, qsw_superop_
     if (we != hipSuccess) return fail(status_of(we));
     h->nwb = W.nwb;
     const int eng = env_int("QSW_ENGINE", 0);
-    h->engine = 0;
+    // stage the rho-row in LDS when it is small enough to leave the
+    // occupancy alone (QSW_STAGE=0 turns it off)
+    const bool stage = (size_t)N * sizeof(double2) <= kStageMaxBytes && env_int("QSW_STAGE", 1) != 0;
+    h->engine = stage ? 100 : 0;
     h->grid = wave_grid(h->nwb, resident1);
     if (eng == 3) {
       h->engine = 3;
@@ -646,7 +658,7 @@ qsw_status_t make_plan(const qsw_superop_s *h, double t0, double dt, int32_t n_s
   const double *d = h->info.d;
   qsw_status_t st;
   if (t0 != 0.0) {
-    st = select_params_impl(h->info.norm1, d, t0, 1, QSW_PREC_DOUBLE, &P.m0, &P.s0);
+    st = select_params_impl(h->info.norm1, d, t0, 1, h->prec, &P.m0, &P.s0);
     if (st != QSW_OK) return st;
   }
   const size_t vec = (size_t)h->n * sizeof(double2);
@@ -654,11 +666,11 @@ qsw_status_t make_plan(const qsw_superop_s *h, double t0, double dt, int32_t n_s
   size_t off = align256(sizeof(DeviceState));
   if (n_steps > 0) {
     int mS = 0, sS = 1;
-    st = select_params_impl(h->info.norm1, d, (double)n_steps * dt, 1, QSW_PREC_DOUBLE, &mS, &sS);
+    st = select_params_impl(h->info.norm1, d, (double)n_steps * dt, 1, h->prec, &mS, &sS);
     if (st != QSW_OK) return st;
     if (n_steps <= sS || mS == 0) {
       P.branch = 0;
-      st = select_params_impl(h->info.norm1, d, dt, 1, QSW_PREC_DOUBLE, &P.m, &P.s);
+      st = select_params_impl(h->info.norm1, d, dt, 1, h->prec, &P.m, &P.s);
       if (st != QSW_OK) return st;
     } else {
       P.branch = 1;
@@ -690,6 +702,7 @@ struct Runner {
   int64_t gstep = 0;
   int64_t launched = 0;
   double tol;
+  int engine;  // product engine of this call (1 for complex64 values)
 
   SpmvArgs base_args() const {
     SpmvArgs a{};
@@ -724,7 +737,7 @@ struct Runner {
         a.alpha = t / ((double)s_steps * (double)j);
         a.par = par;
         a.j = j;
-        hipError_t e = launch_taylor_term(a, h->engine, h->grid, s);
+        hipError_t e = launch_taylor_term(a, engine, h->grid, s);
         if (e != hipSuccess) return e;
         ++launched;
       }
@@ -903,11 +916,33 @@ void qsw_superop_destroy(qsw_superop_t h) {
   dfree(h->blk);
   dfree(h->wcol);
   dfree(h->wval);
+  dfree(h->wval32);
   dfree(h->wlen);
   dfree(h->wperm);
   if (h->ev_start) (void)hipEventDestroy(h->ev_start);
   if (h->ev_end) (void)hipEventDestroy(h->ev_end);
   delete h;
+}
+
+qsw_status_t qsw_superop_set_precision(qsw_superop_t h, int32_t prec) {
+  if (!h || (prec != QSW_PREC_DOUBLE && prec != QSW_PREC_SINGLE)) return QSW_ERR_ARG;
+  DeviceGuard g(h->device);
+  if (!g.ok) return QSW_ERR_DEVICE;
+  if (prec == QSW_PREC_SINGLE && !h->wval32) {
+    if (h->engine != 0 && h->engine != 100)
+      return QSW_ERR_STATE;  // the complex64 copy exists for the wave layout only
+    // the padding converts to zeros as well
+    HIP_TRY(dalloc(&h->wval32, (size_t)h->nnz + kWavePad));
+    hipStream_t s = nullptr;
+    HIP_TRY(launch_to_c64(h->wval32, h->wval, h->nnz + kWavePad, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  } else if (prec == QSW_PREC_DOUBLE && h->wval32) {
+    HIP_TRY(hipDeviceSynchronize());  // earlier calls may still read the copy
+    dfree(h->wval32);
+    h->wval32 = nullptr;
+  }
+  h->prec = prec;
+  return QSW_OK;
 }
 
 qsw_status_t qsw_superop_info(qsw_superop_t h, qsw_info_t *info) {
@@ -959,7 +994,8 @@ qsw_status_t qsw_propagate(qsw_superop_t h, const void *rho0, double t0, double 
   R.B[1] = (double2 *)(ws + P.off_B + vec);
   R.F[0] = (double2 *)(ws + P.off_F);
   R.F[1] = (double2 *)(ws + P.off_F + vec);
-  R.tol = tol_of(QSW_PREC_DOUBLE);
+  R.tol = tol_of(h->prec);
+  R.engine = h->prec == QSW_PREC_SINGLE ? h->engine + 1 : h->engine;
   double2 *outv = (double2 *)out;
   const int64_t n = h->n;
   auto slot = [&](int64_t k) { return outv + k * n; };
@@ -992,7 +1028,7 @@ qsw_status_t qsw_propagate(qsw_superop_t h, const void *rho0, double t0, double 
           a.x = Kp[p - 1];
           a.y = Kp[p];
           a.alpha = dt / (double)p;
-          HIP_TRY(launch_series_power(a, pt, k, p, h->engine, h->grid, s));
+          HIP_TRY(launch_series_power(a, pt, k, p, R.engine, h->grid, s));
           HIP_TRY(launch_series_accum(R.st, pt, k, p, Kp[p], Z, Fk, n, R.tol, 2048, s));
           R.launched += 1;
         }
@@ -1011,6 +1047,7 @@ qsw_status_t qsw_propagate(qsw_superop_t h, const void *rho0, double t0, double 
   h->last.m0 = P.m0;
   h->last.s0 = P.s0;
   h->last.launched = R.launched;
+  h->last.prec = h->prec;
   h->have_last = true;
   return QSW_OK;
 }
@@ -1028,8 +1065,10 @@ qsw_status_t qsw_last_stats(qsw_superop_t h, qsw_stats_t *st) {
   h->last.products = (int64_t)buf[0];
   h->last.nonfinite = (int)(buf[1] & 0xffffffffu) != 0;
   h->last.ms = ms;
+  const double entry = h->last.prec == QSW_PREC_SINGLE ? 12.0 : 20.0;
+  const double vec = h->last.branch == 1 ? 80.0 : 64.0;  // power + separate accumulation
   h->last.bytes = (double)h->last.products *
-                  (20.0 * (double)h->nnz + 8.0 * (double)(h->n + 1) + 64.0 * (double)h->n);
+                  (entry * (double)h->nnz + 8.0 * (double)(h->n + 1) + vec * (double)h->n);
   *st = h->last;
   return h->last.nonfinite ? QSW_ERR_NONFINITE : QSW_OK;
 }

@@ -1,0 +1,134 @@
+"""Complex64-stored superoperator values (QSW_PREC_SINGLE) on the GPU.
+
+Each result is checked against the FP64 oracle twice: within the derived
+first-order bound 2 u |t| ||L||_1 ||vec rho0||_1 (u = 2^-24: value rounding
+plus truncation at the single tolerance), and within ten times the error of
+the oracle's own complex64-values variant (same rounded values, same
+tolerance) on the same input, so that the GPU path is no less accurate than
+the method it implements."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle import expmv
+from tests.gpu_util import build_gpu, oracle_superop, random_workload
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(op, wl):
+    import torch
+    out = op.propagate(wl.rho0, wl.t0, wl.dt, wl.n_steps)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def _check(wl, n_points=None):
+    q = wl.n_steps if n_points is None else n_points
+    A = oracle_superop(wl)
+    ref64, info = expmv.propagate(A, wl.rho0, wl.t0, wl.dt, q)
+    ref32, _ = expmv.propagate_single_values(A, wl.rho0, wl.t0, wl.dt, q)
+    op = build_gpu(wl)
+    op.set_precision(True)
+    got = _run(op, wl)
+    st = op.last_stats()
+    assert st["prec"] == "single"
+    emul = np.abs(ref32 - ref64).max()
+    err_all = 0.0
+    for k in range(q + 1):
+        t = wl.t0 + k * wl.dt
+        err = np.abs(got[k] - ref64[k]).max()
+        bound = expmv.single_values_bound(info["norm1"], t, wl.rho0)
+        assert err <= max(bound, 1e-15), (wl.name, k, err, bound)
+        assert abs(np.trace(got[k]) - 1) <= max(bound, 1e-15)
+        err_all = max(err_all, err)
+    assert err_all <= 10 * emul + 1e-11, (wl.name, err_all, emul)
+    return op, got, st, err_all
+
+
+def test_cycle16_both_branches():
+    wl = workloads.cycle16()
+    op, _, st, _ = _check(wl)
+    assert st["branch"] == 1
+    op.close()
+    wl.n_steps, wl.dt = 2, 5.0
+    op, _, st, _ = _check(wl)
+    assert st["branch"] == 0
+    op.close()
+
+
+@pytest.mark.parametrize("omega", [0.0, 0.5, 1.0])
+@pytest.mark.parametrize("r_mode,dephasing", [("transition", False), ("colnorm", True)])
+def test_random_digraphs(omega, r_mode, dephasing):
+    for N, k, seed in ((7, 2, 41), (23, 3, 42)):
+        wl = random_workload(N, k, omega, seed, r_mode=r_mode, dephasing=dephasing,
+                             n_steps=6, dt=0.8)
+        op, _, _, _ = _check(wl)
+        op.close()
+
+
+def test_ragged_size_start_time_and_negative_step():
+    wl = random_workload(41, 4, 0.45, 43, n_steps=4, dt=0.6, t0=1.3)
+    op, _, st, _ = _check(wl)
+    assert st["m0"] > 0
+    op.close()
+    wl = random_workload(9, 2, 0.3, 44, n_steps=3, dt=-0.5)
+    op, _, _, _ = _check(wl)
+    op.close()
+
+
+def test_er256_first_points():
+    wl = workloads.er256()
+    wl.n_steps = 12
+    op, _, st, _ = _check(wl)
+    assert st["branch"] == 0
+    op.close()
+
+
+def test_fewer_products_than_double_and_parameters():
+    import paper_2003_02450_amd as qsw
+    wl = workloads.er256()
+    wl.n_steps = 5
+    op = build_gpu(wl)
+    d64 = _run(op, wl)
+    s64 = op.last_stats()
+    op.set_precision(True)
+    _run(op, wl)
+    s32 = op.last_stats()
+    inf = op.info()
+    d = [inf["norm1"], inf["norm1"]] + [inf["d"][p] for p in range(2, 10)]
+    assert (s32["m"], s32["s"]) == qsw.select_params(inf["norm1"], d, wl.dt, single=True)
+    assert s32["products"] < s64["products"]
+    assert s32["bytes"] < s64["bytes"]
+    op.set_precision(False)
+    again = _run(op, wl)
+    assert op.last_stats()["prec"] == "double"
+    assert np.array_equal(again, d64)   # the double path is untouched
+    op.close()
+
+
+def test_outdeg1024_sampled():
+    """The benchmark workload at full size: points 0-2 in full against both
+    oracles, point 50 by one interval of the oracle's variant from the GPU's
+    point 49, trace and Hermiticity of every point."""
+    wl = workloads.outdeg1024()
+    A = oracle_superop(wl)
+    ref64, info = expmv.propagate(A, wl.rho0, 0.0, wl.dt, 2)
+    ref32, _ = expmv.propagate_single_values(A, wl.rho0, 0.0, wl.dt, 2)
+    op = build_gpu(wl)
+    op.set_precision(True)
+    got = _run(op, wl)
+    emul = np.abs(ref32 - ref64).max()
+    for k in range(3):
+        err = np.abs(got[k] - ref64[k]).max()
+        assert err <= expmv.single_values_bound(info["norm1"], k * wl.dt, wl.rho0) + 1e-15
+        assert err <= 10 * emul + 1e-11, (k, err, emul)
+    one, _ = expmv.propagate_single_values(A, got[49], 0.0, wl.dt, 1)
+    b = expmv.single_values_bound(info["norm1"], wl.dt, got[49])
+    assert np.abs(got[50] - one[1]).max() <= b
+    for k in range(wl.n_steps + 1):
+        bk = expmv.single_values_bound(info["norm1"], k * wl.dt, wl.rho0)
+        assert abs(np.trace(got[k]) - 1) <= bk + 1e-15
+        assert np.abs(got[k] - got[k].conj().T).max() <= bk + 1e-15
+    op.close()

@@ -266,3 +266,54 @@ def test_select_params_alpha_never_worse_than_norm1():
         m, s = expmv.select_params(nrm, d, t)
         m1, s1 = expmv.select_params_norm1(t * nrm)
         assert m * s <= m1 * s1
+
+
+# ------------------------------------------- complex64-stored values variant
+
+def test_single_values_rounding_is_componentwise_nearest():
+    rng = np.random.Generator(np.random.PCG64(31))
+    g = workloads.er_undirected(10, 0.5, rng, 0.5, 1.5)
+    A = oracle.walk_superop(g.dense(), 0.37)
+    A32 = expmv.round_values_c64(A)
+    assert (A32.row_ptr == A.row_ptr).all() and (A32.col == A.col).all()
+    for part in (np.real, np.imag):
+        d = np.abs(part(A32.val) - part(A.val))
+        assert (d <= 2.0 ** -24 * np.abs(part(A.val))).all()
+        assert (part(A32.val) == part(A32.val).astype(np.float32)).all()
+    assert (A32.val != A.val).any()
+
+
+def test_single_values_exact_storage_reduces_to_truncation_error():
+    """The 16-cycle with unit weights, rates equal to the weights and
+    omega = 0.5 has only dyadic superoperator entries, so complex64 storage
+    is exact and the variant differs from exp(tA) (scipy's dense expm) only
+    by the 2^-24 truncation: at most u |t| ||A||_1 ||vec rho0||_1."""
+    wl = _cycle_wl(0.5, r_mode="transition")
+    A = oracle.walk_superop(wl.graph.dense(), wl.omega, wl.h_mode, wl.r_mode,
+                            wl.dephasing, wl.gamma)
+    assert (expmv.round_values_c64(A).val == A.val).all()
+    out, info = expmv.propagate_single_values(A, wl.rho0, 0.0, wl.dt, wl.n_steps)
+    S = A.dense()
+    v0 = wl.rho0.reshape(-1)
+    for k in (1, 4, 10):
+        ref = scipy.linalg.expm(k * wl.dt * S) @ v0
+        err = np.abs(out[k].reshape(-1) - ref).max()
+        assert err <= 2.0 ** -24 * k * wl.dt * info["norm1"] * np.abs(v0).sum()
+    _, info64 = expmv.propagate(A, wl.rho0, 0.0, wl.dt, wl.n_steps)
+    assert info["m"] < info64["m"]   # theta_m at 2^-24 is larger
+
+
+@pytest.mark.parametrize("omega,t0", [(0.0, 0.0), (0.4, 0.0), (0.9, 0.6)])
+def test_single_values_within_first_order_bound(omega, t0):
+    rng = np.random.Generator(np.random.PCG64(32))
+    g = workloads.random_out_degree(14, 3, rng)
+    A = oracle.walk_superop(g.dense(), omega)
+    rho0 = workloads.random_density(14, rng, rank=2)
+    out, info = expmv.propagate_single_values(A, rho0, t0, 0.9, 4)
+    S = A.dense()
+    for k in range(5):
+        t = t0 + 0.9 * k
+        ref = scipy.linalg.expm(t * S) @ rho0.reshape(-1)
+        err = np.abs(out[k].reshape(-1) - ref).max()
+        assert err <= max(expmv.single_values_bound(info["norm1"], t, rho0), 1e-15), (k, err)
+        assert err > 1e-12 or t == 0.0   # the rounding is really there
