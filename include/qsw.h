@@ -191,6 +191,86 @@ qsw_status_t qsw_propagate(qsw_superop_t h, const void *rho0, double t0, double 
 /* Statistics of the last qsw_propagate on this handle (waits for it). */
 qsw_status_t qsw_last_stats(qsw_superop_t h, qsw_stats_t *st);
 
+/* -------------------------------------------------------- batched walks */
+
+/*
+ * A walk: one superoperator, n0 <= 4 initial density matrices propagated
+ * together (each exactly as qsw_propagate would propagate it alone: same
+ * parameters, same terms, same stopping decisions, bitwise the same result),
+ * and its own time grid t0 + k dt, k = 0..n_steps.  Many walks advance
+ * together in one engine, so small operators share launches and each
+ * operator's values are read once per product for all n0 right-hand sides.
+ *
+ *   op:    built handle, on the engine's device; its precision applies.  It
+ *          must stay alive until the walk has finished.
+ *   rho0:  device, n0 consecutive N*N complex128 row-major matrices.
+ *   out:   device, (n_steps+1) x n0 x N*N complex128 (point-major), or NULL.
+ *   pops:  device, (n_steps+1) x n0 x N doubles (Re rho_aa), or NULL.
+ */
+typedef struct {
+    qsw_superop_t op;
+    int32_t n0;
+    const void *rho0;
+    double t0, dt;
+    int32_t n_steps;
+    void *out;
+    void *pops;
+} qsw_walk_t;
+
+typedef struct qsw_engine_s *qsw_engine_t;
+
+typedef struct {
+    int64_t cycles;      /* control + work launch pairs so far */
+    int64_t products;    /* sparse products of the finished walks */
+    int32_t live;        /* walks admitted and not finished */
+    int32_t nonfinite;   /* 1 once any norm was NaN or infinite */
+    double ms;           /* device time of the last qsw_engine_run */
+} qsw_engine_stats_t;
+
+/* Device bytes one walk takes in an engine with `rhs` (1, 2 or 4)
+ * right-hand sides: six work vectors of n*rhs complex128, plus m stored
+ * powers in the time-series branch.  0 for a bad walk. */
+size_t qsw_walk_bytes(const qsw_walk_t *walk, int32_t rhs);
+
+/* Bytes the engine's own tables take at the start of its arena.  The engine
+ * also keeps a map of the running walks' 64-row blocks: about
+ * arena_bytes / (768 rhs) + 8 (max_walks + 1) bytes after the tables. */
+size_t qsw_engine_table_bytes(int32_t max_walks);
+
+/*
+ * An engine over a caller-owned device arena (256-byte aligned, at least
+ * qsw_engine_table_bytes(max_walks)); it allocates no device memory.  The
+ * rest of the arena holds the walks' vectors.  All work goes to hip_stream.
+ */
+qsw_status_t qsw_engine_create(int32_t max_walks, int32_t rhs, void *arena, size_t arena_bytes,
+                               void *hip_stream, qsw_engine_t *out);
+
+/* Admit a walk: QSW_OK and a ticket, or QSW_ERR_OOM when no slot or not
+ * enough free arena is available now (admission control: try again after
+ * walks have finished).  Synchronises the engine's stream. */
+qsw_status_t qsw_engine_submit(qsw_engine_t e, const qsw_walk_t *walk, int64_t *ticket);
+
+/* Run up to max_cycles cycles, or until every admitted walk has finished;
+ * *live receives the number still running.  Synchronous. */
+qsw_status_t qsw_engine_run(qsw_engine_t e, int32_t max_cycles, int32_t *live);
+
+/* Tickets of walks finished since the last poll (their outputs are complete
+ * and their arena space is free again). */
+qsw_status_t qsw_engine_poll(qsw_engine_t e, int64_t *tickets, int32_t capacity, int32_t *count);
+
+qsw_status_t qsw_engine_stats(qsw_engine_t e, qsw_engine_stats_t *st);
+
+void qsw_engine_destroy(qsw_engine_t e);
+
+/* Workspace for qsw_batch_propagate: tables plus every walk's bytes. */
+size_t qsw_batch_workspace_bytes(const qsw_walk_t *walks, int32_t count, int32_t rhs);
+
+/* All walks to completion in one engine on `workspace` (synchronous; no
+ * device allocation). */
+qsw_status_t qsw_batch_propagate(const qsw_walk_t *walks, int32_t count, int32_t rhs,
+                                 void *workspace, size_t ws_bytes, void *hip_stream,
+                                 qsw_engine_stats_t *stats);
+
 /* ------------------------------------------------------------- helpers */
 
 /* y = L x (device complex128 vectors of length n).  Enqueued on the stream. */

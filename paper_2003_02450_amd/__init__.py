@@ -21,7 +21,8 @@ import numpy as np
 from . import _lib
 from ._lib import QswError  # noqa: F401
 
-__all__ = ["Superop", "QswError", "theta", "select_params", "library_path"]
+__all__ = ["Superop", "Engine", "batch_propagate", "QswError", "theta", "select_params",
+           "library_path"]
 
 library_path = _lib.LIB_PATH
 
@@ -258,3 +259,139 @@ class Superop:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------ batched walks
+
+def _walk_struct(op, rho0, t0, dt, n_steps, out, pops):
+    torch = _torch()
+    rho0 = rho0.to(device=op.device, dtype=torch.complex128).contiguous()
+    if rho0.dim() == 2:
+        rho0 = rho0.unsqueeze(0)
+    n0 = rho0.shape[0]
+    if tuple(rho0.shape[1:]) != (op.N, op.N):
+        raise ValueError("rho0 must be [n0, N, N]")
+    for t, shape, dtype in ((out, (n_steps + 1, n0, op.N, op.N), torch.complex128),
+                            (pops, (n_steps + 1, n0, op.N), torch.float64)):
+        if t is not None and (tuple(t.shape) != shape or t.dtype != dtype or
+                              not t.is_contiguous() or t.device != rho0.device):
+            raise ValueError(f"output must be a contiguous {dtype} tensor of shape {shape}")
+    w = _lib.Walk(op._h, n0, rho0.data_ptr(), float(t0), float(dt), int(n_steps),
+                  out.data_ptr() if out is not None else None,
+                  pops.data_ptr() if pops is not None else None)
+    return w, rho0
+
+
+class Engine:
+    """Many walks advancing together on one device (qsw_engine_*).
+
+    The arena is one device tensor; a walk is admitted (``submit`` returns a
+    ticket) only while its vectors fit, and its space returns when it ends.
+    """
+
+    def __init__(self, max_walks: int, rhs: int, arena_bytes: int, device=None):
+        torch = _torch()
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None
+                                   else device)
+        self.rhs = int(rhs)
+        self._arena = torch.empty(int(arena_bytes) + 256, dtype=torch.uint8, device=self.device)
+        base = (self._arena.data_ptr() + 255) & ~255
+        self._e = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            st = _lib.load().qsw_engine_create(int(max_walks), self.rhs, ctypes.c_void_p(base),
+                                               int(arena_bytes), _stream(self.device),
+                                               ctypes.byref(self._e))
+        _lib.check(st, "qsw_engine_create")
+        self._held = {}
+
+    @staticmethod
+    def walk_bytes(op, n0, t0, dt, n_steps, rhs) -> int:
+        w = _lib.Walk(op._h, int(n0), 1, float(t0), float(dt), int(n_steps), None, None)
+        return int(_lib.load().qsw_walk_bytes(ctypes.byref(w), int(rhs)))
+
+    def submit(self, op, rho0, t0, dt, n_steps, out=None, pops=None):
+        """Ticket of the admitted walk, or None when it does not fit now."""
+        torch = _torch()
+        w, rho0 = _walk_struct(op, rho0, t0, dt, n_steps, out, pops)
+        t = ctypes.c_int64()
+        with torch.cuda.device(self.device):
+            st = _lib.load().qsw_engine_submit(self._e, ctypes.byref(w), ctypes.byref(t))
+        if st == 3:  # QSW_ERR_OOM: not admitted
+            return None
+        _lib.check(st, "qsw_engine_submit")
+        self._held[t.value] = (op, rho0, out, pops)
+        return t.value
+
+    def run(self, max_cycles: int = 2 ** 31 - 1) -> int:
+        torch = _torch()
+        live = ctypes.c_int32()
+        with torch.cuda.device(self.device):
+            st = _lib.load().qsw_engine_run(self._e, int(max_cycles), ctypes.byref(live))
+        if st != 5:
+            _lib.check(st, "qsw_engine_run")
+        return live.value
+
+    def poll(self):
+        buf = (ctypes.c_int64 * 4096)()
+        cnt = ctypes.c_int32()
+        done = []
+        while True:
+            _lib.check(_lib.load().qsw_engine_poll(self._e, buf, 4096, ctypes.byref(cnt)),
+                       "qsw_engine_poll")
+            done.extend(buf[i] for i in range(cnt.value))
+            if cnt.value < 4096:
+                break
+        for t in done:
+            self._held.pop(t, None)
+        return done
+
+    def stats(self) -> dict:
+        s = _lib.EngineStats()
+        _lib.check(_lib.load().qsw_engine_stats(self._e, ctypes.byref(s)), "qsw_engine_stats")
+        return {"cycles": s.cycles, "products": s.products, "live": s.live,
+                "nonfinite": bool(s.nonfinite), "ms": s.ms}
+
+    def close(self):
+        if getattr(self, "_e", None):
+            _lib.load().qsw_engine_destroy(self._e)
+            self._e = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_propagate(walks, rhs=None, workspace=None):
+    """Propagate walks together: each item is (op, rho0[n0, N, N], t0, dt,
+    n_steps, out, pops) with out / pops device tensors or None.  Returns the
+    engine statistics; results land in the given tensors."""
+    torch = _torch()
+    if not walks:
+        return {}
+    structs, keep = [], []
+    for (op, rho0, t0, dt, n_steps, out, pops) in walks:
+        w, r = _walk_struct(op, rho0, t0, dt, n_steps, out, pops)
+        structs.append(w)
+        keep.append(r)
+    if rhs is None:
+        m = max(w.n0 for w in structs)
+        rhs = 1 if m == 1 else (2 if m == 2 else 4)
+    arr = (_lib.Walk * len(structs))(*structs)
+    L = _lib.load()
+    need = int(L.qsw_batch_workspace_bytes(arr, len(structs), int(rhs)))
+    if need == 0:
+        raise QswError(1, "qsw_batch_workspace_bytes")
+    dev = walks[0][0].device
+    if workspace is None or workspace.numel() < need + 256:
+        workspace = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+    base = (workspace.data_ptr() + 255) & ~255
+    st_out = _lib.EngineStats()
+    with torch.cuda.device(dev):
+        st = L.qsw_batch_propagate(arr, len(structs), int(rhs), ctypes.c_void_p(base), need,
+                                   _stream(dev), ctypes.byref(st_out))
+    if st != 5:
+        _lib.check(st, "qsw_batch_propagate")
+    return {"cycles": st_out.cycles, "products": st_out.products, "live": st_out.live,
+            "nonfinite": bool(st_out.nonfinite), "ms": st_out.ms, "workspace_bytes": need}

@@ -24,7 +24,10 @@ QSW_PREC_SINGLE = 1
 EXPORTED = ("qsw_superop_build", "qsw_superop_build_ops", "qsw_superop_destroy",
             "qsw_superop_info", "qsw_superop_set_precision", "qsw_superop_copy_csr", "qsw_propagate_workspace_bytes",
             "qsw_propagate", "qsw_last_stats", "qsw_apply", "qsw_populations", "qsw_theta",
-            "qsw_select_params", "qsw_status_str", "qsw_version")
+            "qsw_select_params", "qsw_status_str", "qsw_version", "qsw_walk_bytes",
+            "qsw_engine_table_bytes", "qsw_engine_create", "qsw_engine_submit", "qsw_engine_run",
+            "qsw_engine_poll", "qsw_engine_stats", "qsw_engine_destroy",
+            "qsw_batch_workspace_bytes", "qsw_batch_propagate")
 
 
 class QswError(RuntimeError):
@@ -46,6 +49,17 @@ class Stats(ctypes.Structure):
                 ("m0", ctypes.c_int32), ("s0", ctypes.c_int32), ("launched", ctypes.c_int64),
                 ("products", ctypes.c_int64), ("nonfinite", ctypes.c_int32),
                 ("ms", ctypes.c_double), ("bytes", ctypes.c_double), ("prec", ctypes.c_int32)]
+
+
+class Walk(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_void_p), ("n0", ctypes.c_int32), ("rho0", ctypes.c_void_p),
+                ("t0", ctypes.c_double), ("dt", ctypes.c_double), ("n_steps", ctypes.c_int32),
+                ("out", ctypes.c_void_p), ("pops", ctypes.c_void_p)]
+
+
+class EngineStats(ctypes.Structure):
+    _fields_ = [("cycles", ctypes.c_int64), ("products", ctypes.c_int64),
+                ("live", ctypes.c_int32), ("nonfinite", ctypes.c_int32), ("ms", ctypes.c_double)]
 
 
 _lib = None
@@ -95,6 +109,27 @@ def load() -> ctypes.CDLL:
     L.qsw_select_params.restype = _i32
     L.qsw_select_params.argtypes = [_dbl, _vp, _dbl, _i32, _i32, ctypes.POINTER(_i32),
                                     ctypes.POINTER(_i32)]
+    L.qsw_walk_bytes.restype = ctypes.c_size_t
+    L.qsw_walk_bytes.argtypes = [ctypes.POINTER(Walk), _i32]
+    L.qsw_engine_table_bytes.restype = ctypes.c_size_t
+    L.qsw_engine_table_bytes.argtypes = [_i32]
+    L.qsw_engine_create.restype = _i32
+    L.qsw_engine_create.argtypes = [_i32, _i32, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]
+    L.qsw_engine_submit.restype = _i32
+    L.qsw_engine_submit.argtypes = [_vp, ctypes.POINTER(Walk), ctypes.POINTER(_i64)]
+    L.qsw_engine_run.restype = _i32
+    L.qsw_engine_run.argtypes = [_vp, _i32, ctypes.POINTER(_i32)]
+    L.qsw_engine_poll.restype = _i32
+    L.qsw_engine_poll.argtypes = [_vp, _vp, _i32, ctypes.POINTER(_i32)]
+    L.qsw_engine_stats.restype = _i32
+    L.qsw_engine_stats.argtypes = [_vp, ctypes.POINTER(EngineStats)]
+    L.qsw_engine_destroy.restype = None
+    L.qsw_engine_destroy.argtypes = [_vp]
+    L.qsw_batch_workspace_bytes.restype = ctypes.c_size_t
+    L.qsw_batch_workspace_bytes.argtypes = [ctypes.POINTER(Walk), _i32, _i32]
+    L.qsw_batch_propagate.restype = _i32
+    L.qsw_batch_propagate.argtypes = [ctypes.POINTER(Walk), _i32, _i32, _vp, ctypes.c_size_t, _vp,
+                                      ctypes.POINTER(EngineStats)]
     L.qsw_status_str.restype = ctypes.c_char_p
     L.qsw_status_str.argtypes = [_i32]
     L.qsw_version.restype = ctypes.c_char_p

@@ -287,25 +287,20 @@ __device__ __forceinline__ void stream_engine(const SpmvArgs &a, Epi &epi) {
 // copies x[a N .. a N + N) of its first row into LDS once and every column in
 // that range is read from there (any row may use it: the test is on the
 // column).  Needs N * 16 bytes of dynamic LDS.
-constexpr int kWaveUnroll = 6;
+// Positions in flight per lane: six for one or two right-hand sides, three
+// for four (each gathered element then takes 16 registers).
+template <int NRHS>
+constexpr int wave_unroll() { return NRHS <= 2 ? 6 : 3; }
 
+// Block k (64 rows) of the wave-jagged layout: epi(row, acc, pre) receives
+// the NRHS complex sums of each row.  With STAGE, xs holds x[base ..
+// base + N).  Called by a whole wavefront.
 template <int NRHS, bool F32, bool STAGE, class Epi>
-__device__ __forceinline__ void wave_engine(const SpmvArgs &a, Epi &epi) {
-  constexpr int WPB = kBlock / 64;  // wavefronts per workgroup
+__device__ __forceinline__ void wave_block(const SpmvArgs &a, int64_t k, Epi &epi,
+                                           const double2 *xs, int64_t base) {
+  constexpr int kWaveUnroll = wave_unroll<NRHS>();
   const int lane = threadIdx.x & 63;
-  const int64_t nw = (int64_t)gridDim.x * WPB;
-  extern __shared__ double2 xs[];
-  static_assert(!STAGE || NRHS == 1, "staging holds one right-hand side");
-  for (int64_t kb = (int64_t)blockIdx.x * WPB; kb < a.nwb; kb += nw) {
-    int64_t base = 0;
-    if constexpr (STAGE) {
-      base = (kb * kWaveRows) / a.N * a.N;
-      __syncthreads();  // the previous blocks are done with xs
-      for (int i = threadIdx.x; i < a.N; i += kBlock) xs[i] = a.x[base + i];
-      __syncthreads();
-    }
-    const int64_t k = kb + (threadIdx.x >> 6);
-    if (k >= a.nwb) continue;
+  {
     const int64_t r0 = k * kWaveRows;
     const int nr = (int)min((int64_t)kWaveRows, a.n - r0);
     const int64_t e0 = a.rp[r0];
@@ -363,6 +358,25 @@ __device__ __forceinline__ void wave_engine(const SpmvArgs &a, Epi &epi) {
       }
     }
     if (lane < nr) epi(r0 + orow, acc, pre);
+  }
+}
+
+template <int NRHS, bool F32, bool STAGE, class Epi>
+__device__ __forceinline__ void wave_engine(const SpmvArgs &a, Epi &epi) {
+  constexpr int WPB = kBlock / 64;  // wavefronts per workgroup
+  const int64_t nw = (int64_t)gridDim.x * WPB;
+  extern __shared__ double2 xs[];
+  static_assert(!STAGE || NRHS == 1, "staging holds one right-hand side");
+  for (int64_t kb = (int64_t)blockIdx.x * WPB; kb < a.nwb; kb += nw) {
+    int64_t base = 0;
+    if constexpr (STAGE) {
+      base = (kb * kWaveRows) / a.N * a.N;
+      __syncthreads();  // the previous blocks are done with xs
+      for (int i = threadIdx.x; i < a.N; i += kBlock) xs[i] = a.x[base + i];
+      __syncthreads();
+    }
+    const int64_t k = kb + (threadIdx.x >> 6);
+    if (k < a.nwb) wave_block<NRHS, F32, STAGE>(a, k, epi, xs, base);
   }
 }
 
@@ -921,6 +935,442 @@ inline int blocks_for(int64_t n, int per = kBlock) {
 
 }  // namespace
 
+// --------------------------------------------------------------------------
+// Batched propagation.  Each cycle is one launch of batch_control_kernel
+// (one thread per walk: take in the maxima of the op that just ran, apply
+// the stopping tests, choose the walk's next op) and one launch of
+// batch_work_kernel (every wave block of every active walk carries out its
+// walk's op).  Each column of a walk goes through exactly the operations of
+// qsw_propagate on that column alone: same terms, same sums in the same
+// order, same tests.
+// --------------------------------------------------------------------------
+enum BatchPc : int32_t {
+  PC_LOAD = 0,
+  PC_START,
+  PC_TERMS,
+  PC_EMIT,
+  PC_AFTER_EMIT,
+  PC_SBLOCK,
+  PC_SPOINT0,
+  PC_SPOINT,
+  PC_SAFTER_EMIT
+};
+
+__device__ void batch_issue_term(const BatchInst &I, const BatchCtl &C, BatchOp &O) {
+  const int i = C.i, j = C.j, s = C.sseg;
+  const double2 *src = (i == 0) ? I.V[C.cur] : I.F[(i - 1) & 1];
+  double2 *dst = (i == s - 1) ? I.V[C.cur ^ 1] : I.F[i & 1];
+  O.type = BOP_TERM;
+  O.active = C.active;
+  O.first = (j == 1);
+  O.alpha = C.tseg / ((double)s * (double)j);
+  O.x = (j == 1) ? src : I.B[(j - 1) & 1];
+  O.y = I.B[j & 1];
+  O.fin = (j == 1) ? src : dst;
+  O.fout = dst;
+}
+
+__device__ void batch_issue_series(const BatchInst &I, const BatchCtl &C, BatchOp &O) {
+  const double2 *Z = I.V[C.cur];
+  double2 *Fk = I.V[C.cur ^ 1];
+  double2 *Kp = I.K + (int64_t)(C.p - 1) * I.vlen;
+  O.active = C.active;
+  O.first = (C.p == 1);
+  O.kpow = pow((double)C.kk, (double)C.p);
+  O.fin = (C.p == 1) ? Z : Fk;
+  O.fout = Fk;
+  if (C.p > C.mhat) {
+    O.type = BOP_POWACC;
+    O.x = (C.p == 1) ? Z : I.K + (int64_t)(C.p - 2) * I.vlen;
+    O.y = Kp;
+    O.alpha = I.dt / (double)C.p;
+  } else {
+    O.type = BOP_ACC;
+    O.x = Kp;
+    O.y = nullptr;
+  }
+}
+
+__device__ void batch_start_segment(BatchCtl &C, int seg, double t, int m, int s, uint32_t all) {
+  C.seg = seg;
+  C.tseg = t;
+  C.mseg = m;
+  C.sseg = s;
+  C.i = 0;
+  C.j = 1;
+  C.active = all;
+}
+
+__device__ void batch_advance(const BatchInst &I, BatchCtl &C, BatchOp &O, BatchSlots &S) {
+  const uint32_t all = (1u << I.n0) - 1u;
+  double y[kBatchMaxRhs], f[kBatchMaxRhs], b0[kBatchMaxRhs];
+  bool bad = false;
+  for (int c = 0; c < kBatchMaxRhs; ++c) {
+    if (c < I.n0) bad |= (S.y[c] >= kInfBits) || (S.f[c] >= kInfBits) || (S.b0[c] >= kInfBits);
+    y[c] = bits_to_d(S.y[c]);
+    f[c] = bits_to_d(S.f[c]);
+    b0[c] = bits_to_d(S.b0[c]);
+    S.y[c] = 0ull;
+    S.f[c] = 0ull;
+    S.b0[c] = 0ull;
+  }
+  if (bad) C.nonfinite = 1;
+  switch (C.last) {
+    case BOP_TERM:
+      for (int c = 0; c < kBatchMaxRhs; ++c) {
+        if (!((C.active >> c) & 1u)) continue;
+        C.c_prev[c] = (C.j == 1) ? b0[c] : C.c_last[c];
+        C.c_last[c] = y[c];
+        C.f_last[c] = f[c];
+      }
+      ++C.products;
+      break;
+    case BOP_POWACC:
+      for (int c = 0; c < kBatchMaxRhs; ++c) I.kn[C.p * kBatchMaxRhs + c] = y[c];
+      C.mhat = C.p;
+      ++C.products;
+      [[fallthrough]];
+    case BOP_ACC:
+      for (int c = 0; c < kBatchMaxRhs; ++c)
+        if ((C.active >> c) & 1u) C.f_last[c] = f[c];
+      break;
+    case BOP_NORM:
+      for (int c = 0; c < kBatchMaxRhs; ++c) I.kn[c] = b0[c];
+      break;
+    default:
+      break;
+  }
+  O.type = BOP_NONE;
+  C.last = BOP_NONE;
+  for (;;) {
+    switch (C.pc) {
+      case PC_LOAD:
+        O.type = BOP_LOAD;
+        C.pc = PC_START;
+        C.last = BOP_LOAD;
+        return;
+      case PC_START:
+        if (I.t0 != 0.0 && I.m0 > 0) {
+          batch_start_segment(C, 0, I.t0, I.m0, I.s0, all);
+          batch_issue_term(I, C, O);
+          C.pc = PC_TERMS;
+          C.last = BOP_TERM;
+          return;
+        }
+        C.point = 0;
+        C.pc = PC_EMIT;
+        continue;
+      case PC_TERMS: {
+        if (C.j < C.mseg) {
+          uint32_t act = 0;
+          for (int c = 0; c < kBatchMaxRhs; ++c)
+            if (((C.active >> c) & 1u) && !(C.c_prev[c] + C.c_last[c] <= I.tol * C.f_last[c]))
+              act |= 1u << c;
+          if (act) {
+            C.active = act;
+            ++C.j;
+            batch_issue_term(I, C, O);
+            C.last = BOP_TERM;
+            return;
+          }
+        }
+        ++C.i;  // the scaling step is complete
+        if (C.i < C.sseg) {
+          C.j = 1;
+          C.active = all;
+          batch_issue_term(I, C, O);
+          C.last = BOP_TERM;
+          return;
+        }
+        C.cur ^= 1;  // the segment is complete
+        C.point = (C.seg == 0) ? 0 : C.point + 1;
+        C.pc = PC_EMIT;
+        continue;
+      }
+      case PC_EMIT:
+        O.type = BOP_EMIT;
+        O.point = C.point;
+        O.x = I.V[C.cur];
+        C.pc = PC_AFTER_EMIT;
+        C.last = BOP_EMIT;
+        return;
+      case PC_AFTER_EMIT:
+        if (C.point >= I.q) {
+          C.done = 1;
+          return;
+        }
+        if (I.branch == 0) {
+          if (I.m == 0) {  // exp(dt L) acts as the identity
+            ++C.point;
+            C.pc = PC_EMIT;
+            continue;
+          }
+          batch_start_segment(C, 1, I.dt, I.m, I.s, all);
+          batch_issue_term(I, C, O);
+          C.pc = PC_TERMS;
+          C.last = BOP_TERM;
+          return;
+        }
+        C.blk = 1;
+        C.zi = 0;
+        C.pc = PC_SBLOCK;
+        continue;
+      case PC_SBLOCK:
+        C.dd = (C.blk <= I.jb) ? I.d : I.r;
+        if (C.dd == 0 || C.zi >= I.q) {
+          C.done = 1;
+          return;
+        }
+        O.type = BOP_NORM;
+        O.x = I.V[C.cur];
+        C.mhat = 0;
+        C.pc = PC_SPOINT0;
+        C.last = BOP_NORM;
+        return;
+      case PC_SPOINT0:
+        C.kk = 1;
+        C.p = 1;
+        C.active = all;
+        batch_issue_series(I, C, O);
+        C.last = O.type;
+        C.pc = PC_SPOINT;
+        return;
+      case PC_SPOINT: {
+        if (C.p < I.m) {
+          const int qq = C.p;
+          const double kk = (double)C.kk;
+          uint32_t act = 0;
+          for (int c = 0; c < kBatchMaxRhs; ++c) {
+            if (!((C.active >> c) & 1u)) continue;
+            const double c1 = (qq == 1) ? I.kn[c]
+                                        : pow(kk, (double)(qq - 1)) * I.kn[(qq - 1) * kBatchMaxRhs + c];
+            const double c2 = pow(kk, (double)qq) * I.kn[qq * kBatchMaxRhs + c];
+            if (!(c1 + c2 <= I.tol * C.f_last[c])) act |= 1u << c;
+          }
+          if (act) {
+            C.active = act;
+            ++C.p;
+            batch_issue_series(I, C, O);
+            C.last = O.type;
+            return;
+          }
+        }
+        O.type = BOP_EMIT;  // the point is complete
+        O.point = C.zi + C.kk;
+        O.x = I.V[C.cur ^ 1];
+        C.pc = PC_SAFTER_EMIT;
+        C.last = BOP_EMIT;
+        return;
+      }
+      case PC_SAFTER_EMIT:
+        if (C.kk < C.dd) {
+          ++C.kk;
+          C.p = 1;
+          C.active = all;
+          batch_issue_series(I, C, O);
+          C.last = O.type;
+          C.pc = PC_SPOINT;
+          return;
+        }
+        C.cur ^= 1;  // the block's last point starts the next block
+        C.zi += C.dd;
+        ++C.blk;
+        C.pc = PC_SBLOCK;
+        continue;
+      default:
+        C.done = 1;
+        return;
+    }
+  }
+}
+
+// One workgroup: walks b = tid, tid + kBlock, ...; writes the number still
+// running to *live.
+__global__ __launch_bounds__(kBlock) void batch_control_kernel(BatchArgs A) {
+  __shared__ unsigned int cnt[kWaves];
+  unsigned int alive = 0;
+  for (int b = threadIdx.x; b < A.count; b += kBlock) {
+    BatchCtl C = A.ctl[b];
+    if (!C.done) {
+      BatchOp O = A.op[b];
+      batch_advance(A.inst[b], C, O, A.slots[b]);
+      A.op[b] = O;
+      A.ctl[b] = C;
+      if (C.nonfinite) *(volatile int *)A.nonfinite = 1;
+    } else {
+      A.op[b].type = BOP_NONE;
+    }
+    alive += C.done ? 0u : 1u;
+  }
+  for (int off = 32; off > 0; off >>= 1) alive += __shfl_xor(alive, off, 64);
+  if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = alive;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned int t = 0;
+    for (int w = 0; w < kWaves; ++w) t += cnt[w];
+    *A.live = t;
+  }
+}
+
+template <int R>
+struct BatchTermEpi {  // TERM and POWACC: y = alpha A x; accumulate active columns
+  double alpha, kpow;
+  const double2 *fin;
+  double2 *fout, *y;
+  uint32_t active;
+  bool first, series;
+  unsigned long long my[R], mf[R], mb0[R];
+  typedef NoPre Pre;
+  __device__ __forceinline__ Pre pre(int64_t) const { return Pre{}; }
+  __device__ __forceinline__ void operator()(int64_t row, const double *acc, Pre) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const double2 yv = make_double2(alpha * acc[2 * r], alpha * acc[2 * r + 1]);
+      y[row * R + r] = yv;
+      my[r] = umax(my[r], abs_bits(cabs2(yv)));
+      if ((active >> r) & 1u) {
+        double2 f = fin[row * R + r];
+        if (series) {
+          f.x = fma(kpow, yv.x, f.x);
+          f.y = fma(kpow, yv.y, f.y);
+        } else {
+          if (first) mb0[r] = umax(mb0[r], abs_bits(cabs2(f)));
+          f.x += yv.x;
+          f.y += yv.y;
+        }
+        fout[row * R + r] = f;
+        mf[r] = umax(mf[r], abs_bits(cabs2(f)));
+      }
+    }
+  }
+};
+
+__device__ __forceinline__ void batch_flush(unsigned long long v, unsigned long long *dst) {
+  v = wave_umax(v);
+  if ((threadIdx.x & 63) == 0 && v) atomicMax(dst, v);
+}
+
+// Global block g -> (walk, block within the walk), rebuilt when the set of
+// running walks changes.
+__global__ void batch_blocks_kernel(BatchArgs A) {
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < A.nblocks;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    int lo = 0, hi = A.nact;  // blk_start[lo] <= g < blk_start[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (A.blk_start[mid] <= g) lo = mid; else hi = mid;
+    }
+    A.blkmap[g] = make_int2(A.act[lo], (int)(g - A.blk_start[lo]));
+  }
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void batch_work_kernel(BatchArgs A) {
+  constexpr int WPB = kBlock / 64;
+  const int lane = threadIdx.x & 63;
+  const int64_t total = A.nblocks;
+  const int64_t nw = (int64_t)gridDim.x * WPB;
+  for (int64_t g = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6); g < total; g += nw) {
+    const int2 bk = A.blkmap[g];
+    const int b = bk.x;
+    const BatchOp &O = A.op[b];
+    const int type = O.type;
+    if (type == BOP_NONE) continue;
+    const BatchInst &I = A.inst[b];
+    BatchSlots &S = A.slots[b];
+    const int64_t k = bk.y;
+    const int64_t r0 = k * kWaveRows;
+    const int64_t n = I.n;
+    const int nr = (int)min((int64_t)kWaveRows, n - r0);
+    const int64_t row = r0 + lane;
+    const bool live = lane < nr;
+    if (type == BOP_TERM || type == BOP_POWACC) {
+      SpmvArgs a{};
+      a.n = n;
+      a.rp = I.rp;
+      a.wcol = I.wcol;
+      a.wval = I.wval;
+      a.wval32 = I.wval32;
+      a.wlen = I.wlen;
+      a.wperm = I.wperm;
+      a.nwb = I.nwb;
+      a.N = I.N;
+      a.x = O.x;
+      BatchTermEpi<R> epi;
+      epi.alpha = O.alpha;
+      epi.kpow = O.kpow;
+      epi.fin = O.fin;
+      epi.fout = O.fout;
+      epi.y = O.y;
+      epi.active = O.active;
+      epi.first = O.first != 0;
+      epi.series = type == BOP_POWACC;
+#pragma unroll
+      for (int r = 0; r < R; ++r) epi.my[r] = epi.mf[r] = epi.mb0[r] = 0ull;
+      if (I.f32)
+        wave_block<R, true, false>(a, k, epi, nullptr, 0);
+      else
+        wave_block<R, false, false>(a, k, epi, nullptr, 0);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        batch_flush(epi.my[r], &S.y[r]);
+        batch_flush(epi.mf[r], &S.f[r]);
+        if (epi.first && !epi.series) batch_flush(epi.mb0[r], &S.b0[r]);
+      }
+    } else if (type == BOP_ACC) {
+      unsigned long long mf[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        mf[r] = 0ull;
+        if (live && ((O.active >> r) & 1u)) {
+          double2 f = O.fin[row * R + r];
+          const double2 kv = O.x[row * R + r];
+          f.x = fma(O.kpow, kv.x, f.x);
+          f.y = fma(O.kpow, kv.y, f.y);
+          O.fout[row * R + r] = f;
+          mf[r] = abs_bits(cabs2(f));
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) batch_flush(mf[r], &S.f[r]);
+    } else if (type == BOP_NORM) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const unsigned long long m = live ? abs_bits(cabs2(O.x[row * R + r])) : 0ull;
+        batch_flush(m, &S.b0[r]);
+      }
+    } else if (type == BOP_LOAD) {
+      // rho0 into V[0]; every other work vector starts at zero, so columns
+      // beyond n0 stay zero throughout
+      if (live) {
+        const double2 z = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int64_t e = row * R + r;
+          I.V[0][e] = r < I.n0 ? I.rho0[(int64_t)r * n + row] : z;
+          I.V[1][e] = z;
+          I.F[0][e] = z;
+          I.F[1][e] = z;
+          I.B[0][e] = z;
+          I.B[1][e] = z;
+        }
+      }
+    } else if (type == BOP_EMIT) {
+      if (live) {
+        const int64_t pt = O.point;
+        const int N1 = I.N + 1;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          if (r >= I.n0) break;
+          const double2 v = O.x[row * R + r];
+          if (I.out) I.out[(pt * I.n0 + r) * n + row] = v;
+          if (I.pops && row % N1 == 0) I.pops[(pt * I.n0 + r) * I.N + row / N1] = v.x;
+        }
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------------ launchers
 
 hipError_t launch_assemble(const AssembleArgs &a, int64_t n, hipStream_t s) {
@@ -1083,6 +1533,45 @@ hipError_t launch_populations(const double2 *rho, int32_t N, int32_t count, doub
   hipLaunchKernelGGL(populations_kernel, dim3(blocks_for(total)), dim3(kBlock), 0, s, rho, N,
                      count, pops);
   return hipGetLastError();
+}
+
+hipError_t launch_batch_control(const BatchArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(batch_control_kernel, dim3(1), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_work(const BatchArgs &a, int rhs, int grid, hipStream_t s) {
+  switch (rhs) {
+    case 1: hipLaunchKernelGGL(batch_work_kernel<1>, dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(batch_work_kernel<2>, dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 4: hipLaunchKernelGGL(batch_work_kernel<4>, dim3(grid), dim3(kBlock), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_blocks(const BatchArgs &a, hipStream_t s) {
+  if (a.nblocks == 0) return hipSuccess;
+  int grid = blocks_for(a.nblocks);
+  if (grid > 4096) grid = 4096;
+  hipLaunchKernelGGL(batch_blocks_kernel, dim3(grid), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+int batch_resident_workgroups(int rhs) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  hipError_t e;
+  if (rhs == 1)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batch_work_kernel<1>, kBlock, 0);
+  else if (rhs == 2)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batch_work_kernel<2>, kBlock, 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batch_work_kernel<4>, kBlock, 0);
+  if (e != hipSuccess || per < 1) per = 1;
+  return cus * per;
 }
 
 int resident_workgroups(int which) {

@@ -109,6 +109,84 @@ struct SpmvArgs {
   int j;                 // term index (1-based)
 };
 
+// ---- batched propagation (several walks advance together) ----
+constexpr int kBatchMaxRhs = 4;
+
+enum BatchOpType : int32_t {
+  BOP_NONE = 0,   // nothing this cycle (finished, or waiting)
+  BOP_LOAD = 1,   // V[0] = rho0 (interleaved, zero columns beyond n0)
+  BOP_TERM = 2,   // Taylor term: y = alpha A x, fout = fin + y on active columns
+  BOP_POWACC = 3, // series power y = K_p = alpha A K_{p-1}, fout = fin + k^p y
+  BOP_ACC = 4,    // series accumulation from a stored power: fout = fin + k^p K_p
+  BOP_NORM = 5,   // series block start: max |Z| per column
+  BOP_EMIT = 6    // out / pops of one grid point from x
+};
+
+// One walk in the batch (fixed while it runs).  Vectors hold R interleaved
+// complex128 columns: element (row, c) at row * R + c.
+struct BatchInst {
+  const int64_t *rp;
+  const int32_t *wcol;
+  const double2 *wval;
+  const float2 *wval32;
+  const int32_t *wlen;
+  const unsigned char *wperm;
+  int64_t n, nwb;
+  int64_t vlen;      // n * R: complex elements of one work vector
+  int32_t N, f32;
+  // plan (as for one walk)
+  int32_t branch, m, s, m0, s0, d, jb, r, q, n0;
+  double t0, dt, tol;
+  double2 *V[2], *F[2], *B[2];
+  double2 *K;        // m stored powers (series branch)
+  double *kn;        // (m + 1) x 4 power norms (series branch)
+  const double2 *rho0;
+  double2 *out;
+  double *pops;
+};
+
+struct BatchOp {
+  int32_t type;
+  uint32_t active;   // columns whose accumulator is updated
+  int32_t first;     // TERM: j == 1; POWACC / ACC: p == 1
+  int32_t point;     // EMIT: grid point
+  double alpha, kpow;
+  const double2 *x;
+  double2 *y;
+  const double2 *fin;
+  double2 *fout;
+};
+
+struct BatchCtl {
+  int32_t pc, cur, i, j, mseg, sseg, seg, point;
+  int32_t blk, dd, zi, kk, p, mhat;
+  uint32_t active;
+  int32_t last;      // type of the op in flight
+  int32_t done;
+  int32_t nonfinite;
+  int64_t products;
+  double tseg;
+  double c_prev[kBatchMaxRhs], c_last[kBatchMaxRhs], f_last[kBatchMaxRhs];
+};
+
+struct BatchSlots {  // maxima of the op in flight, as IEEE bit patterns
+  unsigned long long y[kBatchMaxRhs], f[kBatchMaxRhs], b0[kBatchMaxRhs];
+};
+
+struct BatchArgs {
+  const BatchInst *inst;
+  BatchCtl *ctl;
+  BatchOp *op;
+  BatchSlots *slots;
+  const int32_t *act;        // active instance ids, nact of them
+  const int64_t *blk_start;  // nact + 1 prefix of their wave blocks
+  int2 *blkmap;              // per global block: (instance id, block within it)
+  int64_t nblocks;           // blk_start[nact]
+  int32_t nact, count;
+  unsigned int *live;        // control: instances not finished
+  int *nonfinite;
+};
+
 // ---- launchers (kernels.hip) ----
 hipError_t launch_assemble(const AssembleArgs &a, int64_t n, hipStream_t s);
 hipError_t launch_row_abs_max(int64_t n, const int64_t *rp, const double2 *val,
@@ -164,6 +242,10 @@ hipError_t launch_topk(const double *h, int64_t n, int K, int grid, double *cand
 // Workgroups of the stream kernels that fit on the device at once
 // (which = 0: single right-hand side, 1: two).
 int resident_workgroups(int which);
+hipError_t launch_batch_control(const BatchArgs &a, hipStream_t s);
+hipError_t launch_batch_work(const BatchArgs &a, int rhs, int grid, hipStream_t s);
+hipError_t launch_batch_blocks(const BatchArgs &a, hipStream_t s);
+int batch_resident_workgroups(int rhs);
 
 hipError_t launch_populations(const double2 *rho, int32_t N, int32_t count, double *pops,
                               hipStream_t s);

@@ -6,9 +6,8 @@
 // Propagate: FP64 parameter selection on the host, then launch chains of the
 // fused Taylor-term kernel whose stopping test runs on the device, so the
 // host never waits inside the loop.
-#include "qsw_impl.h"
+#include "handle.h"
 #include "params.h"
-#include "../../include/qsw.h"
 
 #include <hip/hip_runtime.h>
 
@@ -25,53 +24,6 @@
 using namespace qsw;
 
 namespace {
-
-// ---------------------------------------------------------------- helpers
-
-#define HIP_TRY(expr)                                  \
-  do {                                                 \
-    hipError_t _e = (expr);                            \
-    if (_e != hipSuccess) return status_of(_e);        \
-  } while (0)
-
-qsw_status_t status_of(hipError_t e) {
-  if (e == hipSuccess) return QSW_OK;
-  if (e == hipErrorOutOfMemory) return QSW_ERR_OOM;
-  return QSW_ERR_DEVICE;
-}
-
-template <class T>
-hipError_t dalloc(T **p, size_t count) {
-  *p = nullptr;
-  if (count == 0) count = 1;
-  return hipMalloc((void **)p, count * sizeof(T));
-}
-
-template <class T>
-void dfree(T *&p) {
-  if (p) (void)hipFree(p);
-  p = nullptr;
-}
-
-// Save and restore the caller's current device around an API call.
-struct DeviceGuard {
-  int prev = -1;
-  bool ok = true;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    if (dev >= 0 && dev != prev) ok = hipSetDevice(dev) == hipSuccess;
-  }
-  ~DeviceGuard() {
-    int cur = -1;
-    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-  }
-};
-
-int env_int(const char *name, int dflt) {
-  const char *v = std::getenv(name);
-  if (!v || !*v) return dflt;
-  return std::atoi(v);
-}
 
 // Host-side operator data before upload.
 struct HostOps {
@@ -123,40 +75,6 @@ void transpose_csr(int32_t N, const std::vector<int64_t> &rp, const std::vector<
 }
 
 }  // namespace
-
-// ------------------------------------------------------------------ handle
-
-struct qsw_superop_s {
-  int device = -1;
-  int32_t N = 0;
-  int64_t n = 0, nnz = 0;
-  double omega = 0.0;
-  int64_t *row_ptr = nullptr;
-  int32_t *col = nullptr;
-  double2 *val = nullptr;
-  qsw_info_t info{};
-  // launch shape of the product kernels
-  int engine = 0;                 // 0 / 100: wave-jagged (100: rho-row staged in LDS);
-                                  // 3: CSR stream; 4..64: vector engine lanes per row
-  int grid = 0;                   // workgroups of a product launch
-  int64_t rows_per_block = 0;     // vector engine
-  int32_t *blk = nullptr;         // stream engine row blocks
-  int32_t nblk = 0;
-  int32_t blocks_per_wg = 0;
-  // wave-jagged layout (the product kernels' copy of the matrix)
-  int32_t *wcol = nullptr;
-  double2 *wval = nullptr;
-  float2 *wval32 = nullptr;       // complex64 values for QSW_PREC_SINGLE propagation
-  int prec = QSW_PREC_DOUBLE;     // precision of qsw_propagate
-  int32_t *wlen = nullptr;
-  unsigned char *wperm = nullptr;
-  int64_t nwb = 0;
-  // last propagate
-  hipEvent_t ev_start = nullptr, ev_end = nullptr;
-  unsigned long long *stats_dev = nullptr;  // [products, nonfinite]
-  qsw_stats_t last{};
-  bool have_last = false;
-};
 
 namespace {
 
@@ -641,19 +559,12 @@ qsw_status_t build_common(HostOps &op, double omega, hipStream_t s, qsw_superop_
   return QSW_OK;
 }
 
+}  // namespace
+
 // ------------------------------------------------------------ propagate plan
 
-struct Plan {
-  int branch = 0;
-  int m = 0, s = 1;      // per interval (branch 0) or for the span (branch 1)
-  int m0 = 0, s0 = 1;    // exp(t0 L) start
-  int d = 0, j = 0, r = 0;
-  size_t off_state = 0, off_pts = 0, off_B = 0, off_F = 0, off_K = 0, total = 0;
-};
-
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-qsw_status_t make_plan(const qsw_superop_s *h, double t0, double dt, int32_t n_steps, Plan &P) {
+qsw_status_t qsw::make_plan(const qsw_superop_s *h, double t0, double dt, int32_t n_steps,
+                             Plan &P) {
   if (!std::isfinite(t0) || !std::isfinite(dt) || n_steps < 0) return QSW_ERR_ARG;
   const double *d = h->info.d;
   qsw_status_t st;
@@ -692,6 +603,8 @@ qsw_status_t make_plan(const qsw_superop_s *h, double t0, double dt, int32_t n_s
   P.total = off;
   return QSW_OK;
 }
+
+namespace {
 
 struct Runner {
   qsw_superop_s *h;

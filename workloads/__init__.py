@@ -262,3 +262,29 @@ def two_sources_one_sink() -> tuple[Graph, Graph]:
     G = graph_from_arcs(3, [2, 2], [0, 1], [1.0, 1.0])
     Gu = graph_from_arcs(3, [0, 1, 2, 2], [2, 2, 0, 1], [1.0] * 4)
     return G, Gu
+
+
+def basis_states(N: int, vertices) -> np.ndarray:
+    """[len(vertices), N, N] stack of |v><v|."""
+    out = np.zeros((len(vertices), N, N), np.complex128)
+    for i, v in enumerate(vertices):
+        out[i, v, v] = 1.0
+    return out
+
+
+def batch64(seed: int = BASE_SEED + 20, count: int = 64, n0: int = 4, n_steps: int = 100,
+            dt: float = 0.2, n_lo: int = 32, n_hi: int = 512) -> list:
+    """Many small walks: `count` undirected ER graphs with
+    N = round(exp(U(ln n_lo, ln n_hi))), p = 8 / N, unit weights, omega ~ U(0, 1),
+    `n0` distinct basis states |v><v| per graph, t = 0 .. n_steps dt.
+    Each item is a Workload whose rho0 is the [n0, N, N] stack."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(count):
+        N = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
+        g = er_undirected(N, min(1.0, 8.0 / N), rng)
+        omega = float(rng.uniform(0.0, 1.0))
+        verts = rng.choice(N, size=min(n0, N), replace=False)
+        out.append(Workload(f"batch{i}_N{N}", g, omega, "laplacian", "transition", False,
+                            basis_states(N, verts), 0.0, dt, n_steps))
+    return out
