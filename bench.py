@@ -15,7 +15,9 @@ over the device time of the timed propagate calls, measured with HIP events
 on the stream the kernels run on.  `single_values` repeats the pass with
 the superoperator values stored as complex64 and the 2^-24 tolerance
 (vectors and sums stay double) and reports its rate, its product kernel's
-bandwidth and its largest deviation from the double pass.  `cpu_baseline`
+bandwidth and its largest deviation from the double pass.  `batched` runs 64
+small walks with 4 density matrices each through one engine, against the same
+walks one density matrix at a time.  `cpu_baseline`
 times the CPU oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -122,6 +124,60 @@ def single_leg(args, one_pass, out64, torch, n, nnz, q, wl) -> dict:
             "max_abs_diff_vs_double": diff, "first_order_bound_t50": bound}
 
 
+def batch_leg(torch, qsw, workloads, reps: int, compare: bool = True) -> dict:
+    """Batched walks: 64 ER graphs (N log-uniform in [32, 512], p = 8/N,
+    unit weights, omega ~ U(0,1)), 4 basis states each, t = 0..20 in 100
+    steps, all walks in one engine (4 right-hand sides per walk).  Timed
+    against the same walks through qsw_propagate one density matrix at a
+    time; every batched result is bitwise that of its single walk."""
+    dev = torch.device("cuda", 0)
+    wls = workloads.batch64()
+    t0 = time.perf_counter()
+    ops = [qsw.Superop.from_graph(w.graph.N, w.graph.row_ptr, w.graph.col_idx, w.graph.w,
+                                  w.omega) for w in wls]
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    r0 = [torch.from_numpy(w.rho0).to(dev) for w in wls]
+    outs = [torch.empty((w.n_steps + 1,) + w.rho0.shape, dtype=torch.complex128, device=dev)
+            for w in wls]
+    items = [(op, r, w.t0, w.dt, w.n_steps, o, None) for op, r, w, o in zip(ops, r0, wls, outs)]
+    st = qsw.batch_propagate(items)  # warm-up, sizes the workspace
+    ws = torch.empty(st["workspace_bytes"] + 256, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        st = qsw.batch_propagate(items, workspace=ws)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    points = sum(w.n_steps * w.rho0.shape[0] for w in wls)
+    # the same walks one density matrix at a time
+    t0 = time.perf_counter()
+    equal = True
+    for i, (op, w, r) in enumerate(zip(ops, wls, r0) if compare else []):
+        one = torch.empty((w.n_steps + 1, w.graph.N, w.graph.N), dtype=torch.complex128,
+                          device=dev)
+        wsp = torch.empty(op.workspace_bytes(0.0, w.dt, w.n_steps) + 256, dtype=torch.uint8,
+                          device=dev)
+        for c in range(r.shape[0]):
+            op.propagate(r[c], 0.0, w.dt, w.n_steps, out=one, workspace=wsp)
+            if i % 16 == 0:
+                equal = equal and bool(torch.equal(one, outs[i][:, c]))
+    torch.cuda.synchronize()
+    single_s = time.perf_counter() - t0
+    for op in ops:
+        op.close()
+    value = reps * points / elapsed
+    single = {"single_walk_path": {"value": points / single_s, "ms": 1e3 * single_s},
+              "speedup_vs_single_walks": value / (points / single_s),
+              "bitwise_equal_to_single_walks_sampled": equal} if compare else {}
+    return {"metric": "instance-points/s", "value": value, "unit": "points/s",
+            "workload": "64 ER walks, N~logU[32,512], p=8/N, 4 basis states each, "
+                        "t=0..20 in 100 steps", "walks": len(wls), "rhs": 4, "points": points,
+            "ms_per_batch": 1e3 * elapsed / reps, "build_ms": 1e3 * build_s,
+            "cycles": st["cycles"], "products": st["products"],
+            "workspace_gb": st["workspace_bytes"] / 1e9, **single}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +187,11 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-single", action="store_true",
                     help="skip the complex64-values leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-walks leg")
+    ap.add_argument("--only-batch", action="store_true",
+                    help="run only the batched-walks leg (for profiling) and print it")
+    ap.add_argument("--no-batch-compare", action="store_true",
+                    help="skip timing the batched walks one density matrix at a time")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the batched and "
@@ -148,6 +209,10 @@ def main() -> int:
         return 2
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.only_batch:
+        print(json.dumps(batch_leg(torch, qsw, workloads, args.steps, not args.no_batch_compare)),
+              flush=True)
+        return 0
     wl = workloads.outdeg1024()
     g = wl.graph
     N, q = g.N, wl.n_steps
@@ -223,6 +288,9 @@ def main() -> int:
     }
     if not args.no_single:
         result["single_values"] = single_leg(args, one_pass, out, torch, n, nnz, q, wl)
+    if not args.no_batch:
+        result["batched"] = batch_leg(torch, qsw, workloads, args.steps,
+                                      not args.no_batch_compare)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_steps)
     print(json.dumps(result), flush=True)

@@ -158,6 +158,26 @@ qsw_status_t qsw_superop_info(qsw_superop_t h, qsw_info_t *info);
  */
 qsw_status_t qsw_superop_set_precision(qsw_superop_t h, int32_t prec);
 
+/* Launch configuration of the product kernels, as chosen by qsw_superop_autotune. */
+typedef struct {
+    int32_t staged;          /* 1: the rho-row is staged in LDS for the rho H gathers */
+    int32_t grid;            /* workgroups per product launch */
+    double us_per_product;   /* measured time of one product in that configuration */
+    int32_t from_cache;      /* 1: taken from an earlier tuning of the same key */
+} qsw_tuning_t;
+
+/*
+ * Time the product kernel on this handle for each launch configuration
+ * (rho-row staging on and off where N*16 bytes fit, grid of 1, 2, 4 and 8
+ * times the resident workgroups), keep the fastest for later qsw_propagate /
+ * qsw_apply calls and remember it for the key (N, entries per row, precision)
+ * in the process, so that later handles with the same key take it without
+ * timing.  No configuration changes any sum's order: results are bitwise
+ * the same whichever is chosen.  Allocates two vectors of n complex128 for
+ * the timing; synchronises `hip_stream`.
+ */
+qsw_status_t qsw_superop_autotune(qsw_superop_t h, void *hip_stream, qsw_tuning_t *out);
+
 /* Copy the device CSR to caller host buffers (row_ptr[n+1], col[nnz],
  * val[2*nnz] doubles), rows in the structural order described at
  * qsw_superop_build.  Any pointer may be NULL to skip it.  Synchronous. */

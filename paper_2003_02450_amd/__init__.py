@@ -167,6 +167,17 @@ class Superop:
                 self._h, _lib.QSW_PREC_SINGLE if single else _lib.QSW_PREC_DOUBLE)
         _lib.check(st, "qsw_superop_set_precision")
 
+    def autotune(self) -> dict:
+        """Time the product kernel's launch configurations and keep the
+        fastest (results are bitwise unchanged whichever is chosen)."""
+        torch = _torch()
+        t = _lib.Tuning()
+        with torch.cuda.device(self.device):
+            st = _lib.load().qsw_superop_autotune(self._h, _stream(self.device), ctypes.byref(t))
+        _lib.check(st, "qsw_superop_autotune")
+        return {"staged": bool(t.staged), "grid": t.grid, "us_per_product": t.us_per_product,
+                "from_cache": bool(t.from_cache)}
+
     def workspace_bytes(self, t0, dt, n_steps) -> int:
         return int(_lib.load().qsw_propagate_workspace_bytes(self._h, float(t0), float(dt),
                                                              int(n_steps)))

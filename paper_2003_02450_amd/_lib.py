@@ -22,7 +22,8 @@ QSW_PREC_SINGLE = 1
 
 # Every function the header declares, for the export check.
 EXPORTED = ("qsw_superop_build", "qsw_superop_build_ops", "qsw_superop_destroy",
-            "qsw_superop_info", "qsw_superop_set_precision", "qsw_superop_copy_csr", "qsw_propagate_workspace_bytes",
+            "qsw_superop_info", "qsw_superop_set_precision", "qsw_superop_autotune",
+            "qsw_superop_copy_csr", "qsw_propagate_workspace_bytes",
             "qsw_propagate", "qsw_last_stats", "qsw_apply", "qsw_populations", "qsw_theta",
             "qsw_select_params", "qsw_status_str", "qsw_version", "qsw_walk_bytes",
             "qsw_engine_table_bytes", "qsw_engine_create", "qsw_engine_submit", "qsw_engine_run",
@@ -49,6 +50,11 @@ class Stats(ctypes.Structure):
                 ("m0", ctypes.c_int32), ("s0", ctypes.c_int32), ("launched", ctypes.c_int64),
                 ("products", ctypes.c_int64), ("nonfinite", ctypes.c_int32),
                 ("ms", ctypes.c_double), ("bytes", ctypes.c_double), ("prec", ctypes.c_int32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("staged", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("us_per_product", ctypes.c_double), ("from_cache", ctypes.c_int32)]
 
 
 class Walk(ctypes.Structure):
@@ -92,6 +98,8 @@ def load() -> ctypes.CDLL:
     L.qsw_superop_info.argtypes = [_vp, ctypes.POINTER(Info)]
     L.qsw_superop_set_precision.restype = _i32
     L.qsw_superop_set_precision.argtypes = [_vp, _i32]
+    L.qsw_superop_autotune.restype = _i32
+    L.qsw_superop_autotune.argtypes = [_vp, _vp, ctypes.POINTER(Tuning)]
     L.qsw_superop_copy_csr.restype = _i32
     L.qsw_superop_copy_csr.argtypes = [_vp, _vp, _vp, _vp]
     L.qsw_propagate_workspace_bytes.restype = ctypes.c_size_t

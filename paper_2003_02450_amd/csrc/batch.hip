@@ -146,6 +146,7 @@ struct qsw_engine_s {
   std::vector<int64_t> ticket;   // -1: free
   std::vector<size_t> off, bytes;
   std::vector<int64_t> nwb;
+  std::vector<int32_t> N;         // graph order of the walk in the slot
   std::vector<int64_t> deadline;  // cycle count by which the walk must have finished
   std::vector<char> running;
   std::vector<int32_t> act;      // running slots in block order
@@ -191,6 +192,13 @@ qsw_status_t upload_active(qsw_engine_s *e) {
   e->h_blk[e->act.size()] = acc;
   e->args.nact = (int32_t)e->act.size();
   e->args.nblocks = acc;
+  // LDS for the largest rho-row (all rhs columns) that fits the staging budget
+  int64_t sb = 0;
+  for (int32_t b : e->act) {
+    const int64_t need = (int64_t)e->rhs * e->N[b] * (int64_t)sizeof(double2);
+    if (need <= (int64_t)kStageMaxBytes && need > sb) sb = need;
+  }
+  e->args.stage_bytes = env_int("QSW_STAGE", 1) ? (int32_t)sb : 0;
   if (acc > e->blkmap_cap) return QSW_ERR_STATE;  // admission reserves the map entries
   if (!e->act.empty())
     HIP_TRY(hipMemcpyAsync(e->arena + e->tab.act, e->h_act, sizeof(int32_t) * e->act.size(),
@@ -281,6 +289,7 @@ qsw_status_t qsw_engine_create(int32_t max_walks, int32_t rhs, void *arena, size
   e->off.assign(max_walks, 0);
   e->bytes.assign(max_walks, 0);
   e->nwb.assign(max_walks, 0);
+  e->N.assign(max_walks, 0);
   e->deadline.assign(max_walks, 0);
   e->running.assign(max_walks, 0);
   if (hipHostMalloc((void **)&e->h_ctl, sizeof(BatchCtl) * (size_t)max_walks) != hipSuccess ||
@@ -402,6 +411,7 @@ qsw_status_t qsw_engine_submit(qsw_engine_t e, const qsw_walk_t *w, int64_t *tic
   e->off[b] = e->pool_base + off;
   e->bytes[b] = W.total;
   e->nwb[b] = h->nwb;
+  e->N[b] = h->N;
   e->deadline[b] = e->stats.cycles + W.max_cycles + kChunk;
   e->running[b] = 1;
   *ticket = e->ticket[b];
@@ -417,7 +427,7 @@ qsw_status_t qsw_engine_run(qsw_engine_t e, int32_t max_cycles, int32_t *live) {
   while (done_cycles < max_cycles && !e->act.empty()) {
     const int64_t tb = total_blocks(e);
     const int64_t want = (tb + kBlockThreads / 64 - 1) / (kBlockThreads / 64);
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, 4 * (int64_t)std::max(e->resident, 1)));
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)std::max(e->resident, 1)));
     const int chunk = std::min(kChunk, max_cycles - done_cycles);
     for (int c = 0; c < chunk; ++c) {
       HIP_TRY(launch_batch_control(e->args, e->stream));

@@ -76,21 +76,50 @@ __device__ __forceinline__ void block_umax_to(unsigned long long (&v)[NV],
 
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 
+// Every device pointer here addresses global memory.  A pointer the compiler
+// cannot trace to a kernel argument (one read from memory, as in the batched
+// kernels) would otherwise be accessed with generic (flat) instructions, which
+// wait on both the vector-memory and the LDS counters; these helpers access
+// through the global address space.
+#define QSW_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ T gld(const T *p) {
+  return *(const QSW_GLOBAL T *)p;
+}
+template <class T>
+__device__ __forceinline__ void gst(T *p, const T &v) {
+  *(QSW_GLOBAL T *)p = v;
+}
+// double2's copy and assignment are member functions (generic `this`), so
+// complex values travel as plain two-double vectors.
+template <>
+__device__ __forceinline__ double2 gld<double2>(const double2 *p) {
+  const dvec2 v = *(const QSW_GLOBAL dvec2 *)p;
+  return make_double2(v.x, v.y);
+}
+template <>
+__device__ __forceinline__ void gst<double2>(double2 *p, const double2 &v) {
+  dvec2 w;
+  w.x = v.x;
+  w.y = v.y;
+  *(QSW_GLOBAL dvec2 *)p = w;
+}
+
 // Matrix entries are read once per product: non-temporal loads leave the
 // caches to the gathered vector.
 __device__ __forceinline__ double2 load_stream(const double2 *p) {
-  const dvec2 v = __builtin_nontemporal_load(reinterpret_cast<const dvec2 *>(p));
+  const dvec2 v = __builtin_nontemporal_load((const QSW_GLOBAL dvec2 *)p);
   return make_double2(v.x, v.y);
 }
 __device__ __forceinline__ int load_stream(const int32_t *p) {
-  return __builtin_nontemporal_load(p);
+  return __builtin_nontemporal_load((const QSW_GLOBAL int32_t *)p);
 }
 
 typedef float fvec2 __attribute__((ext_vector_type(2)));
 
 // A complex64 entry widened to complex128 (exact).
 __device__ __forceinline__ double2 load_stream(const float2 *p) {
-  const fvec2 v = __builtin_nontemporal_load(reinterpret_cast<const fvec2 *>(p));
+  const fvec2 v = __builtin_nontemporal_load((const QSW_GLOBAL fvec2 *)p);
   return make_double2((double)v.x, (double)v.y);
 }
 
@@ -295,17 +324,22 @@ constexpr int wave_unroll() { return NRHS <= 2 ? 6 : 3; }
 // Block k (64 rows) of the wave-jagged layout: epi(row, acc, pre) receives
 // the NRHS complex sums of each row.  With STAGE, xs holds x[base ..
 // base + N).  Called by a whole wavefront.
-template <int NRHS, bool F32, bool STAGE, class Epi>
+// SOA: the NRHS columns of x are consecutive n-vectors (element (c, r) at
+// r n + c) instead of interleaved (c NRHS + r).  With SOA and STAGE, xs holds
+// the rho-row of every column (xs[r N + i]), `staged` says whether it belongs
+// to this block's x, and each gather reads LDS or global memory through one
+// generic (flat) load.
+template <int NRHS, bool F32, bool STAGE, class Epi, bool SOA = false>
 __device__ __forceinline__ void wave_block(const SpmvArgs &a, int64_t k, Epi &epi,
-                                           const double2 *xs, int64_t base) {
+                                           const double2 *xs, int64_t base, bool staged = true) {
   constexpr int kWaveUnroll = wave_unroll<NRHS>();
   const int lane = threadIdx.x & 63;
   {
     const int64_t r0 = k * kWaveRows;
     const int nr = (int)min((int64_t)kWaveRows, a.n - r0);
-    const int64_t e0 = a.rp[r0];
-    const int len = lane < nr ? a.wlen[r0 + lane] : 0;
-    const int orow = lane < nr ? (int)a.wperm[r0 + lane] : 0;
+    const int64_t e0 = gld(a.rp + r0);
+    const int len = lane < nr ? gld(a.wlen + r0 + lane) : 0;
+    const int orow = lane < nr ? (int)gld(a.wperm + r0 + lane) : 0;
     typename Epi::Pre pre{};
     if (lane < nr) pre = epi.pre(r0 + orow);
     const int maxlen = __shfl(len, 0, 64);  // rank 0 is the longest row
@@ -344,16 +378,26 @@ __device__ __forceinline__ void wave_block(const SpmvArgs &a, int64_t k, Epi &ep
 #pragma unroll
       for (int u = 0; u < kWaveUnroll; ++u) {
         const double2 vz = ok[u] ? v[u] : make_double2(0.0, 0.0);
-        if constexpr (STAGE) {
+        if constexpr (STAGE && SOA) {
+          const uint64_t o = (uint64_t)((int64_t)c[u] - base);
+          const bool in_row = staged && o < (uint64_t)a.N;
+#pragma unroll
+          for (int r = 0; r < NRHS; ++r) {
+            const double2 xl = xs[in_row ? r * a.N + o : 0];
+            const double2 xg = gld(a.x + (in_row ? 0 : (int64_t)r * a.n + c[u]));
+            cmac(acc[2 * r], acc[2 * r + 1], vz, in_row ? xl : xg);
+          }
+        } else if constexpr (STAGE) {
           const uint64_t o = (uint64_t)((int64_t)c[u] - base);
           const bool in_row = o < (uint64_t)a.N;
           const double2 xl = xs[in_row ? o : 0];
-          const double2 xg = a.x[in_row ? base : (int64_t)c[u]];
+          const double2 xg = gld(a.x + (in_row ? base : (int64_t)c[u]));
           cmac(acc[0], acc[1], vz, in_row ? xl : xg);
         } else {
 #pragma unroll
           for (int r = 0; r < NRHS; ++r)
-            cmac(acc[2 * r], acc[2 * r + 1], vz, a.x[(int64_t)c[u] * NRHS + r]);
+            cmac(acc[2 * r], acc[2 * r + 1], vz,
+                 gld(a.x + (SOA ? (int64_t)r * a.n + c[u] : (int64_t)c[u] * NRHS + r)));
         }
       }
     }
@@ -1214,6 +1258,7 @@ __global__ __launch_bounds__(kBlock) void batch_control_kernel(BatchArgs A) {
 
 template <int R>
 struct BatchTermEpi {  // TERM and POWACC: y = alpha A x; accumulate active columns
+  int64_t n;             // column stride of the vectors
   double alpha, kpow;
   const double2 *fin;
   double2 *fout, *y;
@@ -1226,10 +1271,10 @@ struct BatchTermEpi {  // TERM and POWACC: y = alpha A x; accumulate active colu
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const double2 yv = make_double2(alpha * acc[2 * r], alpha * acc[2 * r + 1]);
-      y[row * R + r] = yv;
+      gst(y + r * n + row, yv);
       my[r] = umax(my[r], abs_bits(cabs2(yv)));
       if ((active >> r) & 1u) {
-        double2 f = fin[row * R + r];
+        double2 f = gld(fin + r * n + row);
         if (series) {
           f.x = fma(kpow, yv.x, f.x);
           f.y = fma(kpow, yv.y, f.y);
@@ -1238,12 +1283,13 @@ struct BatchTermEpi {  // TERM and POWACC: y = alpha A x; accumulate active colu
           f.x += yv.x;
           f.y += yv.y;
         }
-        fout[row * R + r] = f;
+        gst(fout + r * n + row, f);
         mf[r] = umax(mf[r], abs_bits(cabs2(f)));
       }
     }
   }
 };
+
 
 __device__ __forceinline__ void batch_flush(unsigned long long v, unsigned long long *dst) {
   v = wave_umax(v);
@@ -1264,107 +1310,157 @@ __global__ void batch_blocks_kernel(BatchArgs A) {
   }
 }
 
+// Staging of the rho-row for the rho-H gathers (as in the single-walk
+// engine, for all R columns): decided per workgroup from the walk of its
+// first block, used by the waves whose block belongs to that walk.
 template <int R>
 __global__ __launch_bounds__(kBlock) void batch_work_kernel(BatchArgs A) {
   constexpr int WPB = kBlock / 64;
+  extern __shared__ double2 xs[];
   const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t total = A.nblocks;
-  const int64_t nw = (int64_t)gridDim.x * WPB;
-  for (int64_t g = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6); g < total; g += nw) {
-    const int2 bk = A.blkmap[g];
-    const int b = bk.x;
-    const BatchOp &O = A.op[b];
-    const int type = O.type;
-    if (type == BOP_NONE) continue;
-    const BatchInst &I = A.inst[b];
-    BatchSlots &S = A.slots[b];
-    const int64_t k = bk.y;
-    const int64_t r0 = k * kWaveRows;
-    const int64_t n = I.n;
-    const int nr = (int)min((int64_t)kWaveRows, n - r0);
-    const int64_t row = r0 + lane;
-    const bool live = lane < nr;
-    if (type == BOP_TERM || type == BOP_POWACC) {
-      SpmvArgs a{};
-      a.n = n;
-      a.rp = I.rp;
-      a.wcol = I.wcol;
-      a.wval = I.wval;
-      a.wval32 = I.wval32;
-      a.wlen = I.wlen;
-      a.wperm = I.wperm;
-      a.nwb = I.nwb;
-      a.N = I.N;
-      a.x = O.x;
-      BatchTermEpi<R> epi;
-      epi.alpha = O.alpha;
-      epi.kpow = O.kpow;
-      epi.fin = O.fin;
-      epi.fout = O.fout;
-      epi.y = O.y;
-      epi.active = O.active;
-      epi.first = O.first != 0;
-      epi.series = type == BOP_POWACC;
-#pragma unroll
-      for (int r = 0; r < R; ++r) epi.my[r] = epi.mf[r] = epi.mb0[r] = 0ull;
-      if (I.f32)
-        wave_block<R, true, false>(a, k, epi, nullptr, 0);
-      else
-        wave_block<R, false, false>(a, k, epi, nullptr, 0);
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        batch_flush(epi.my[r], &S.y[r]);
-        batch_flush(epi.mf[r], &S.f[r]);
-        if (epi.first && !epi.series) batch_flush(epi.mb0[r], &S.b0[r]);
-      }
-    } else if (type == BOP_ACC) {
-      unsigned long long mf[R];
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        mf[r] = 0ull;
-        if (live && ((O.active >> r) & 1u)) {
-          double2 f = O.fin[row * R + r];
-          const double2 kv = O.x[row * R + r];
-          f.x = fma(O.kpow, kv.x, f.x);
-          f.y = fma(O.kpow, kv.y, f.y);
-          O.fout[row * R + r] = f;
-          mf[r] = abs_bits(cabs2(f));
+  // Each workgroup takes one contiguous run of block quads, so consecutive
+  // iterations mostly stay within one walk and its data stays in the caches.
+  // (Claiming quads from one shared counter was slower: its atomics
+  // serialise.)
+  const int64_t quads = (total + WPB - 1) / WPB;
+  const int64_t per = (quads + gridDim.x - 1) / gridDim.x;
+  const int64_t qbeg = (int64_t)blockIdx.x * per, qend = min(quads, qbeg + per);
+  {
+    for (int64_t qd = qbeg; qd < qend; ++qd) {
+      const int64_t kb = qd * WPB;
+      int sb = -1;
+      int64_t base = 0;
+      if (A.stage_bytes > 0) {
+        const int2 f = A.blkmap[kb];
+        const int t0 = A.op[f.x].type;
+        const int32_t N0 = A.inst[f.x].N;
+        if ((t0 == BOP_TERM || t0 == BOP_POWACC) &&
+            (int64_t)R * N0 * (int64_t)sizeof(double2) <= A.stage_bytes) {
+          sb = f.x;
+          const int64_t n0r = A.inst[f.x].n;
+          const double2 *x0 = A.op[f.x].x;
+          base = ((int64_t)f.y * kWaveRows) / N0 * N0;
+          __syncthreads();  // earlier blocks are done with xs
+          for (int i = threadIdx.x; i < R * N0; i += kBlock) {
+            const int r = i / N0;
+            xs[i] = gld(x0 + (int64_t)r * n0r + base + (i - r * N0));
+          }
+          __syncthreads();
         }
       }
-#pragma unroll
-      for (int r = 0; r < R; ++r) batch_flush(mf[r], &S.f[r]);
-    } else if (type == BOP_NORM) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const unsigned long long m = live ? abs_bits(cabs2(O.x[row * R + r])) : 0ull;
-        batch_flush(m, &S.b0[r]);
-      }
-    } else if (type == BOP_LOAD) {
-      // rho0 into V[0]; every other work vector starts at zero, so columns
-      // beyond n0 stay zero throughout
-      if (live) {
-        const double2 z = make_double2(0.0, 0.0);
-#pragma unroll
+      const int64_t g = kb + wave;  // wave-uniform
+      if (g >= total) continue;
+      const int2 bk = A.blkmap[g];
+      const int b = bk.x;
+      const BatchOp &O = A.op[b];
+      const int type = O.type;
+      if (type == BOP_NONE) continue;
+      const BatchInst &I = A.inst[b];
+      BatchSlots *S = &A.slots[b];
+      const int64_t k = bk.y;
+      const int64_t r0 = k * kWaveRows;
+      const int64_t n = I.n;
+      const int nr = (int)min((int64_t)kWaveRows, n - r0);
+      const int64_t row = r0 + lane;
+      const bool live = lane < nr;
+      const double2 *ox = O.x;
+      if (type == BOP_TERM || type == BOP_POWACC) {
+        SpmvArgs a{};
+        a.n = n;
+        a.rp = I.rp;
+        a.wcol = I.wcol;
+        a.wval = I.wval;
+        a.wval32 = I.wval32;
+        a.wlen = I.wlen;
+        a.wperm = I.wperm;
+        a.nwb = I.nwb;
+        a.N = I.N;
+        a.x = ox;
+        BatchTermEpi<R> epi;
+        epi.n = n;
+        epi.alpha = O.alpha;
+        epi.kpow = O.kpow;
+        epi.fin = O.fin;
+        epi.fout = O.fout;
+        epi.y = O.y;
+        epi.active = O.active;
+        epi.first = O.first != 0;
+        epi.series = type == BOP_POWACC;
+  #pragma unroll
+        for (int r = 0; r < R; ++r) epi.my[r] = epi.mf[r] = epi.mb0[r] = 0ull;
+        const bool st = sb == b;
+        if (I.f32)
+          wave_block<R, true, true, BatchTermEpi<R>, true>(a, k, epi, xs, base, st);
+        else
+          wave_block<R, false, true, BatchTermEpi<R>, true>(a, k, epi, xs, base, st);
+  #pragma unroll
         for (int r = 0; r < R; ++r) {
-          const int64_t e = row * R + r;
-          I.V[0][e] = r < I.n0 ? I.rho0[(int64_t)r * n + row] : z;
-          I.V[1][e] = z;
-          I.F[0][e] = z;
-          I.F[1][e] = z;
-          I.B[0][e] = z;
-          I.B[1][e] = z;
+          batch_flush(epi.my[r], &S->y[r]);
+          batch_flush(epi.mf[r], &S->f[r]);
+          if (epi.first && !epi.series) batch_flush(epi.mb0[r], &S->b0[r]);
         }
-      }
-    } else if (type == BOP_EMIT) {
-      if (live) {
-        const int64_t pt = O.point;
-        const int N1 = I.N + 1;
-#pragma unroll
+      } else if (type == BOP_ACC) {
+        const double2 *fin = O.fin;
+        double2 *fout = O.fout;
+        const double kpow = O.kpow;
+        const uint32_t active = O.active;
+        unsigned long long mf[R];
+  #pragma unroll
         for (int r = 0; r < R; ++r) {
-          if (r >= I.n0) break;
-          const double2 v = O.x[row * R + r];
-          if (I.out) I.out[(pt * I.n0 + r) * n + row] = v;
-          if (I.pops && row % N1 == 0) I.pops[(pt * I.n0 + r) * I.N + row / N1] = v.x;
+          mf[r] = 0ull;
+          if (live && ((active >> r) & 1u)) {
+            double2 f = gld(fin + r * n + row);
+            const double2 kv = gld(ox + r * n + row);
+            f.x = fma(kpow, kv.x, f.x);
+            f.y = fma(kpow, kv.y, f.y);
+            gst(fout + r * n + row, f);
+            mf[r] = abs_bits(cabs2(f));
+          }
+        }
+  #pragma unroll
+        for (int r = 0; r < R; ++r) batch_flush(mf[r], &S->f[r]);
+      } else if (type == BOP_NORM) {
+  #pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const unsigned long long m = live ? abs_bits(cabs2(gld(ox + r * n + row))) : 0ull;
+          batch_flush(m, &S->b0[r]);
+        }
+      } else if (type == BOP_LOAD) {
+        // rho0 into V[0]; every other work vector starts at zero, so columns
+        // beyond n0 stay zero throughout
+        if (live) {
+          const double2 *rho0 = I.rho0;
+          double2 *v0 = I.V[0], *v1 = I.V[1], *f0 = I.F[0], *f1 = I.F[1],
+                  *b0 = I.B[0], *b1 = I.B[1];
+          const int n0 = I.n0;
+  #pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const int64_t e = r * n + row;
+            const double2 z = make_double2(0.0, 0.0);
+            gst(v0 + e, r < n0 ? gld(rho0 + e) : z);
+            gst(v1 + e, z);
+            gst(f0 + e, z);
+            gst(f1 + e, z);
+            gst(b0 + e, z);
+            gst(b1 + e, z);
+          }
+        }
+      } else if (type == BOP_EMIT) {
+        if (live) {
+          const int64_t pt = O.point;
+          const int N1 = I.N + 1;
+          const int n0 = I.n0;
+          double2 *out = I.out;
+          double *pops = I.pops;
+  #pragma unroll
+          for (int r = 0; r < R; ++r) {
+            if (r >= n0) break;
+            const double2 v = gld(ox + r * n + row);
+            if (out) gst(out + (pt * n0 + r) * n + row, v);
+            if (pops && row % N1 == 0) gst(pops + (pt * n0 + r) * I.N + row / N1, v.x);
+          }
         }
       }
     }
@@ -1542,9 +1638,9 @@ hipError_t launch_batch_control(const BatchArgs &a, hipStream_t s) {
 
 hipError_t launch_batch_work(const BatchArgs &a, int rhs, int grid, hipStream_t s) {
   switch (rhs) {
-    case 1: hipLaunchKernelGGL(batch_work_kernel<1>, dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 2: hipLaunchKernelGGL(batch_work_kernel<2>, dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 4: hipLaunchKernelGGL(batch_work_kernel<4>, dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 1: hipLaunchKernelGGL(batch_work_kernel<1>, dim3(grid), dim3(kBlock), a.stage_bytes, s, a); break;
+    case 2: hipLaunchKernelGGL(batch_work_kernel<2>, dim3(grid), dim3(kBlock), a.stage_bytes, s, a); break;
+    case 4: hipLaunchKernelGGL(batch_work_kernel<4>, dim3(grid), dim3(kBlock), a.stage_bytes, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

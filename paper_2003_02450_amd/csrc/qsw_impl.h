@@ -122,8 +122,8 @@ enum BatchOpType : int32_t {
   BOP_EMIT = 6    // out / pops of one grid point from x
 };
 
-// One walk in the batch (fixed while it runs).  Vectors hold R interleaved
-// complex128 columns: element (row, c) at row * R + c.
+// One walk in the batch (fixed while it runs).  Vectors hold R complex128
+// columns one after the other: element (row, c) at c * n + row.
 struct BatchInst {
   const int64_t *rp;
   const int32_t *wcol;
@@ -182,6 +182,7 @@ struct BatchArgs {
   const int64_t *blk_start;  // nact + 1 prefix of their wave blocks
   int2 *blkmap;              // per global block: (instance id, block within it)
   int64_t nblocks;           // blk_start[nact]
+  int32_t stage_bytes;       // dynamic LDS for the rho-row of R columns (0: no staging)
   int32_t nact, count;
   unsigned int *live;        // control: instances not finished
   int *nonfinite;

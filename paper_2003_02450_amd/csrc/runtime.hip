@@ -17,7 +17,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <new>
 #include <vector>
 
@@ -855,6 +857,95 @@ qsw_status_t qsw_superop_set_precision(qsw_superop_t h, int32_t prec) {
     h->wval32 = nullptr;
   }
   h->prec = prec;
+  return QSW_OK;
+}
+
+qsw_status_t qsw_superop_autotune(qsw_superop_t h, void *hip_stream, qsw_tuning_t *out) {
+  if (!h) return QSW_ERR_ARG;
+  if (h->engine != 0 && h->engine != 100) return QSW_ERR_STATE;  // wave-jagged engines only
+  DeviceGuard g(h->device);
+  if (!g.ok) return QSW_ERR_DEVICE;
+  hipStream_t s = (hipStream_t)hip_stream;
+  const bool can_stage = (size_t)h->N * sizeof(double2) <= kStageMaxBytes;
+  // key: graph order, entries per row (to a quarter), precision
+  const long epr = h->n > 0 ? std::lround(4.0 * (double)h->nnz / (double)h->n) : 0;
+  const std::tuple<int, long, int> key{h->N, epr, h->prec};
+  static std::mutex mu;
+  static std::map<std::tuple<int, long, int>, qsw_tuning_t> cache;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      h->engine = it->second.staged ? 100 : 0;
+      h->grid = it->second.grid;
+      if (out) {
+        *out = it->second;
+        out->from_cache = 1;
+      }
+      return QSW_OK;
+    }
+  }
+  double2 *x = nullptr, *y = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&]() {
+    dfree(x);
+    dfree(y);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  if (dalloc(&x, (size_t)h->n) != hipSuccess || dalloc(&y, (size_t)h->n) != hipSuccess) {
+    cleanup();
+    return QSW_ERR_OOM;
+  }
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
+      launch_zero(x, (size_t)h->n * sizeof(double2), s) != hipSuccess) {
+    cleanup();
+    return QSW_ERR_DEVICE;
+  }
+  const int resident = std::max(resident_workgroups(0), 1);
+  qsw_tuning_t best{};
+  best.us_per_product = 1e300;
+  hipError_t err = hipSuccess;
+  for (int st = can_stage ? 1 : 0; st >= 0 && err == hipSuccess; --st) {
+    for (int mul : {1, 2, 4, 8}) {
+      const int64_t wgs = (h->nwb + kBlockThreads / 64 - 1) / (kBlockThreads / 64);
+      const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(wgs, (int64_t)mul * resident));
+      SpmvArgs a{};
+      a.n = h->n;
+      a.rp = h->row_ptr;
+      a.col = h->col;
+      a.val = h->val;
+      set_wave(a, h);
+      a.x = x;
+      a.y = y;
+      a.alpha = 1.0;
+      const int engine = (st ? 100 : 0) + (h->prec == QSW_PREC_SINGLE ? 1 : 0);
+      if ((err = launch_spmv(a, engine, grid, s)) != hipSuccess) break;  // warm-up
+      if ((err = hipEventRecord(e0, s)) != hipSuccess) break;
+      const int reps = 5;
+      for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch_spmv(a, engine, grid, s);
+      if (err != hipSuccess || (err = hipEventRecord(e1, s)) != hipSuccess) break;
+      if ((err = hipEventSynchronize(e1)) != hipSuccess) break;
+      float ms = 0.f;
+      if ((err = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+      const double us = 1e3 * ms / reps;
+      if (us < best.us_per_product) {
+        best.us_per_product = us;
+        best.staged = st;
+        best.grid = grid;
+      }
+      if (wgs <= (int64_t)mul * resident) break;  // larger grids are the same launch
+    }
+  }
+  cleanup();
+  if (err != hipSuccess) return status_of(err);
+  h->engine = best.staged ? 100 : 0;
+  h->grid = best.grid;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = best;
+  }
+  if (out) *out = best;
   return QSW_OK;
 }
 
