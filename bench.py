@@ -17,7 +17,9 @@ the superoperator values stored as complex64 and the 2^-24 tolerance
 (vectors and sums stay double) and reports its rate, its product kernel's
 bandwidth and its largest deviation from the double pass.  `batched` runs 64
 small walks with 4 density matrices each through one engine, against the same
-walks one density matrix at a time.  `cpu_baseline`
+walks one density matrix at a time.  `served` drives the continuous-batching
+server with Poisson arrivals at several rates and reports walks/s and
+p50/p99 latency.  `cpu_baseline`
 times the CPU oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -27,6 +29,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -178,6 +182,50 @@ def batch_leg(torch, qsw, workloads, reps: int, compare: bool = True) -> dict:
             "workspace_gb": st["workspace_bytes"] / 1e9, **single}
 
 
+def served_leg(torch, qsw, workloads, qps_list, count: int) -> dict:
+    """Continuous batching: `count` walks (N log-uniform in [16, 2048], ER
+    mean degree 6 with 10 % one-way edges, omega ~ U(0,1), 10..200 steps over
+    t in [0, 10], rho0 = |0><0|, populations out) arrive as a Poisson process
+    at each rate in qps_list.  Latency runs from a walk's arrival time to the
+    moment its populations are ready (operator build, queueing and
+    propagation included)."""
+    GB = 1 << 30
+    reqs = workloads.served_requests(count)
+    points = []
+    for qps in qps_list:
+        arrivals = workloads.poisson_arrivals(count, qps)
+        srv = qsw.Server(96 * GB, 48 * GB, 4096)
+        t_arr = {}
+        lat = []
+        i = 0
+        t0 = time.perf_counter()
+        while len(lat) < count:
+            now = time.perf_counter() - t0
+            while i < count and arrivals[i] <= now:
+                r = reqs[i]
+                rid = srv.submit(r["graph"], r["omega"], 0.0, r["dt"], r["n_steps"])
+                t_arr[rid] = arrivals[i]
+                i += 1
+            running, pending = srv.step(8)
+            t_ready = time.perf_counter() - t0
+            for rid, _, _, _ in srv.poll():
+                lat.append(t_ready - t_arr.pop(rid))
+            if running == 0 and pending == 0 and i < count and len(lat) < count:
+                time.sleep(max(0.0, arrivals[i] - (time.perf_counter() - t0)))
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        lat_ms = 1e3 * np.array(lat)
+        points.append({"qps": qps, "walks_per_s": count / wall,
+                       "p50_ms": float(np.percentile(lat_ms, 50)),
+                       "p99_ms": float(np.percentile(lat_ms, 99)),
+                       "mean_ms": float(lat_ms.mean()), "cycles": st["cycles"],
+                       "build_ms": st["build_ms"]})
+    return {"metric": "walks/s", "workload": "N~logU[16,2048] ER deg 6 (10% one-way), "
+            "omega~U(0,1), 10..200 steps over t=0..10, rho0=|0><0|, populations out",
+            "walks_per_point": count, "points": points}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -192,6 +240,9 @@ def main() -> int:
                     help="run only the batched-walks leg (for profiling) and print it")
     ap.add_argument("--no-batch-compare", action="store_true",
                     help="skip timing the batched walks one density matrix at a time")
+    ap.add_argument("--no-serve", action="store_true", help="skip the continuous-batching leg")
+    ap.add_argument("--serve-qps", default="2,4,8", help="arrival rates of the serving leg")
+    ap.add_argument("--serve-count", type=int, default=32, help="walks per serving rate")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the batched and "
@@ -291,6 +342,10 @@ def main() -> int:
     if not args.no_batch:
         result["batched"] = batch_leg(torch, qsw, workloads, args.steps,
                                       not args.no_batch_compare)
+    if not args.no_serve:
+        result["served"] = served_leg(torch, qsw, workloads,
+                                      [float(x) for x in args.serve_qps.split(",")],
+                                      args.serve_count)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_steps)
     print(json.dumps(result), flush=True)

@@ -291,6 +291,59 @@ qsw_status_t qsw_batch_propagate(const qsw_walk_t *walks, int32_t count, int32_t
                                  void *workspace, size_t ws_bytes, void *hip_stream,
                                  qsw_engine_stats_t *stats);
 
+/* ------------------------------------------------ continuous batching */
+
+typedef struct qsw_server_s *qsw_server_t;
+
+typedef struct {
+    int64_t submitted, completed;
+    int64_t cache_hits, cache_misses, evictions;
+    int64_t cycles, products;
+    int64_t cache_bytes;     /* device bytes of the cached operators */
+    double build_ms;         /* host time spent building operators */
+} qsw_server_stats_t;
+
+/*
+ * A server for walks that arrive one at a time (one density matrix each),
+ * all running in one batch engine (qsw_engine_*) over an arena of
+ * arena_bytes that the server allocates now.  Operators are cached on the
+ * device under cache_bytes, keyed by (N, graph CSR, omega, gamma, flags);
+ * unused ones are evicted least recently used first.  All work goes to
+ * hip_stream.
+ */
+qsw_status_t qsw_server_create(size_t arena_bytes, size_t cache_bytes, int32_t max_walks,
+                               void *hip_stream, qsw_server_t *out);
+
+/*
+ * Queue a walk: the graph and options as for qsw_superop_build (host CSR,
+ * read during the call; the operator is built now unless cached), rho0
+ * (device, N*N complex128), the grid t0 + k dt, k = 0..n_steps, and device
+ * outputs out ((n_steps+1) x N*N complex128) and/or pops ((n_steps+1) x N
+ * doubles), either may be NULL.  rho0 and the outputs must stay alive until
+ * the walk is reported done.  The walk joins the engine as soon as its work
+ * vectors fit (walks are admitted in arrival order); QSW_ERR_OOM when they
+ * could not fit even in an empty arena.
+ */
+qsw_status_t qsw_server_submit(qsw_server_t s, int32_t N, const int64_t *row_ptr,
+                               const int32_t *col_idx, const double *w, double omega,
+                               double gamma, uint32_t flags, const void *rho0, double t0,
+                               double dt, int32_t n_steps, void *out, void *pops,
+                               int64_t *request);
+
+/* Run up to max_cycles engine cycles, collect finished walks and admit
+ * waiting ones; reports how many run and wait.  Synchronous. */
+qsw_status_t qsw_server_step(qsw_server_t s, int32_t max_cycles, int32_t *running,
+                             int32_t *pending);
+
+/* Requests finished since the last poll, with their latency from submit to
+ * the step that saw them finish (latency_ms may be NULL). */
+qsw_status_t qsw_server_poll(qsw_server_t s, int64_t *requests, double *latency_ms,
+                             int32_t capacity, int32_t *count);
+
+qsw_status_t qsw_server_stats(qsw_server_t s, qsw_server_stats_t *st);
+
+void qsw_server_destroy(qsw_server_t s);
+
 /* ------------------------------------------------------------- helpers */
 
 /* y = L x (device complex128 vectors of length n).  Enqueued on the stream. */

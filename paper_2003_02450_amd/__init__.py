@@ -21,8 +21,8 @@ import numpy as np
 from . import _lib
 from ._lib import QswError  # noqa: F401
 
-__all__ = ["Superop", "Engine", "batch_propagate", "QswError", "theta", "select_params",
-           "library_path"]
+__all__ = ["Superop", "Engine", "Server", "batch_propagate", "QswError", "theta",
+           "select_params", "library_path"]
 
 library_path = _lib.LIB_PATH
 
@@ -406,3 +406,109 @@ def batch_propagate(walks, rhs=None, workspace=None):
         _lib.check(st, "qsw_batch_propagate")
     return {"cycles": st_out.cycles, "products": st_out.products, "live": st_out.live,
             "nonfinite": bool(st_out.nonfinite), "ms": st_out.ms, "workspace_bytes": need}
+
+
+# ---------------------------------------------------- continuous batching
+
+def _flags(h_mode, r_mode, dephasing):
+    f = 0
+    if h_mode == "adjacency":
+        f |= _lib.QSW_H_ADJACENCY
+    elif h_mode != "laplacian":
+        raise ValueError(h_mode)
+    if r_mode == "colnorm":
+        f |= _lib.QSW_R_COLNORM
+    elif r_mode != "transition":
+        raise ValueError(r_mode)
+    if dephasing:
+        f |= _lib.QSW_DEPHASING
+    return f
+
+
+class Server:
+    """Walks arriving one at a time, each on its own graph, sharing one batch
+    engine (qsw_server_*).  Operators are cached on the device by graph;
+    outputs are device tensors the server hands back when a walk is done."""
+
+    def __init__(self, arena_bytes: int, cache_bytes: int, max_walks: int = 1024, device=None):
+        torch = _torch()
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None
+                                   else device)
+        self._s = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            st = _lib.load().qsw_server_create(int(arena_bytes), int(cache_bytes), int(max_walks),
+                                               _stream(self.device), ctypes.byref(self._s))
+        _lib.check(st, "qsw_server_create")
+        self._held = {}
+
+    def submit(self, graph, omega, t0, dt, n_steps, rho0=None, gamma=1.0, h_mode="laplacian",
+               r_mode="transition", dephasing=False, want_rho=False):
+        """Queue a walk on `graph` (workloads.Graph-like: N, row_ptr, col_idx,
+        w); rho0 defaults to |0><0|.  Returns the request id."""
+        torch = _torch()
+        N = int(graph.N)
+        if rho0 is None:
+            rho0 = torch.zeros((N, N), dtype=torch.complex128, device=self.device)
+            rho0[0, 0] = 1.0
+        rho0 = rho0.to(device=self.device, dtype=torch.complex128).contiguous()
+        pops = torch.empty((n_steps + 1, N), dtype=torch.float64, device=self.device)
+        out = (torch.empty((n_steps + 1, N, N), dtype=torch.complex128, device=self.device)
+               if want_rho else None)
+        rp = np.ascontiguousarray(graph.row_ptr, np.int64)
+        ci = np.ascontiguousarray(graph.col_idx, np.int32)
+        ww = np.ascontiguousarray(graph.w, np.float64)
+        rid = ctypes.c_int64()
+        with torch.cuda.device(self.device):
+            st = _lib.load().qsw_server_submit(
+                self._s, N, _ptr(rp), _ptr(ci), _ptr(ww), float(omega), float(gamma),
+                _flags(h_mode, r_mode, dephasing), ctypes.c_void_p(rho0.data_ptr()), float(t0),
+                float(dt), int(n_steps),
+                ctypes.c_void_p(out.data_ptr()) if out is not None else None,
+                ctypes.c_void_p(pops.data_ptr()), ctypes.byref(rid))
+        _lib.check(st, "qsw_server_submit")
+        self._held[rid.value] = (rho0, pops, out)
+        return rid.value
+
+    def step(self, max_cycles: int = 16):
+        """Run engine cycles; returns (running, pending)."""
+        torch = _torch()
+        running, pending = ctypes.c_int32(), ctypes.c_int32()
+        with torch.cuda.device(self.device):
+            st = _lib.load().qsw_server_step(self._s, int(max_cycles), ctypes.byref(running),
+                                             ctypes.byref(pending))
+        if st != 5:
+            _lib.check(st, "qsw_server_step")
+        return running.value, pending.value
+
+    def poll(self):
+        """[(request id, server latency ms, pops tensor, rho tensor or None)]
+        for walks finished since the last poll."""
+        ids = (ctypes.c_int64 * 1024)()
+        lat = (ctypes.c_double * 1024)()
+        cnt = ctypes.c_int32()
+        done = []
+        while True:
+            _lib.check(_lib.load().qsw_server_poll(self._s, ids, lat, 1024, ctypes.byref(cnt)),
+                       "qsw_server_poll")
+            for i in range(cnt.value):
+                rho0, pops, out = self._held.pop(ids[i])
+                done.append((ids[i], lat[i], pops, out))
+            if cnt.value < 1024:
+                break
+        return done
+
+    def stats(self) -> dict:
+        s = _lib.ServerStats()
+        _lib.check(_lib.load().qsw_server_stats(self._s, ctypes.byref(s)), "qsw_server_stats")
+        return {k: getattr(s, k) for k, _ in _lib.ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_s", None):
+            _lib.load().qsw_server_destroy(self._s)
+            self._s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -28,7 +28,9 @@ EXPORTED = ("qsw_superop_build", "qsw_superop_build_ops", "qsw_superop_destroy",
             "qsw_select_params", "qsw_status_str", "qsw_version", "qsw_walk_bytes",
             "qsw_engine_table_bytes", "qsw_engine_create", "qsw_engine_submit", "qsw_engine_run",
             "qsw_engine_poll", "qsw_engine_stats", "qsw_engine_destroy",
-            "qsw_batch_workspace_bytes", "qsw_batch_propagate")
+            "qsw_batch_workspace_bytes", "qsw_batch_propagate", "qsw_server_create",
+            "qsw_server_submit", "qsw_server_step", "qsw_server_poll", "qsw_server_stats",
+            "qsw_server_destroy")
 
 
 class QswError(RuntimeError):
@@ -66,6 +68,14 @@ class Walk(ctypes.Structure):
 class EngineStats(ctypes.Structure):
     _fields_ = [("cycles", ctypes.c_int64), ("products", ctypes.c_int64),
                 ("live", ctypes.c_int32), ("nonfinite", ctypes.c_int32), ("ms", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("cache_hits", ctypes.c_int64), ("cache_misses", ctypes.c_int64),
+                ("evictions", ctypes.c_int64), ("cycles", ctypes.c_int64),
+                ("products", ctypes.c_int64), ("cache_bytes", ctypes.c_int64),
+                ("build_ms", ctypes.c_double)]
 
 
 _lib = None
@@ -138,6 +148,19 @@ def load() -> ctypes.CDLL:
     L.qsw_batch_propagate.restype = _i32
     L.qsw_batch_propagate.argtypes = [ctypes.POINTER(Walk), _i32, _i32, _vp, ctypes.c_size_t, _vp,
                                       ctypes.POINTER(EngineStats)]
+    L.qsw_server_create.restype = _i32
+    L.qsw_server_create.argtypes = [ctypes.c_size_t, ctypes.c_size_t, _i32, _vp, ctypes.POINTER(_vp)]
+    L.qsw_server_submit.restype = _i32
+    L.qsw_server_submit.argtypes = [_vp, _i32, _vp, _vp, _vp, _dbl, _dbl, _u32, _vp, _dbl, _dbl,
+                                    _i32, _vp, _vp, ctypes.POINTER(_i64)]
+    L.qsw_server_step.restype = _i32
+    L.qsw_server_step.argtypes = [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]
+    L.qsw_server_poll.restype = _i32
+    L.qsw_server_poll.argtypes = [_vp, _vp, _vp, _i32, ctypes.POINTER(_i32)]
+    L.qsw_server_stats.restype = _i32
+    L.qsw_server_stats.argtypes = [_vp, ctypes.POINTER(ServerStats)]
+    L.qsw_server_destroy.restype = None
+    L.qsw_server_destroy.argtypes = [_vp]
     L.qsw_status_str.restype = ctypes.c_char_p
     L.qsw_status_str.argtypes = [_i32]
     L.qsw_version.restype = ctypes.c_char_p

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libqsw.so")
-SOURCES = ["kernels.hip", "runtime.hip", "batch.hip"]   # HIP (device + host)
+SOURCES = ["kernels.hip", "runtime.hip", "batch.hip", "server.hip"]   # HIP (device + host)
 HOST_SOURCES = ["params.cpp"]               # plain C++, host only
 ARCH = os.environ.get("QSW_OFFLOAD_ARCH", "gfx950")
 BLOCK = int(os.environ.get("QSW_BLOCK", "256"))  # threads per product workgroup

@@ -245,6 +245,10 @@ qsw_status_t collect(qsw_engine_s *e) {
 
 }  // namespace
 
+size_t qsw::engine_pool_bytes(const qsw_engine_s *e) {
+  return e ? e->arena_bytes - e->pool_base : 0;
+}
+
 extern "C" {
 
 size_t qsw_walk_bytes(const qsw_walk_t *walk, int32_t rhs) {

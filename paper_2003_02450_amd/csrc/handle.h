@@ -110,4 +110,7 @@ struct Plan {
 // norms at its precision (runtime.hip).
 qsw_status_t make_plan(const qsw_superop_s *h, double t0, double dt, int32_t n_steps, Plan &P);
 
+// Bytes of an engine's arena available to walks' vectors (batch.hip).
+size_t engine_pool_bytes(const qsw_engine_s *e);
+
 }  // namespace qsw

@@ -1,0 +1,360 @@
+// Continuous-batching server: walks arrive one at a time, each on its own
+// graph; they share one batch engine (qsw_engine_*), so a walk that arrives
+// while others run joins the next cycle as soon as its vectors fit.
+//
+//  * Operator cache: superoperators are kept on the device under a byte
+//    budget, keyed by a 64-bit FNV-1a hash of (N, graph CSR, omega, gamma,
+//    flags) and checked against the stored key, so a repeated graph is not
+//    rebuilt.  Operators no walk uses are evicted least recently used first.
+//  * Admission: pending walks are admitted in arrival order, each when the
+//    engine arena has room for its work vectors (the engine refuses it
+//    otherwise); an admitted walk never waits for memory again.
+//  * Every walk's result is bitwise what it would be alone: the engine keeps
+//    walks independent.
+#include "handle.h"
+
+#include <chrono>
+#include <cstring>
+#include <deque>
+#include <list>
+#include <new>
+#include <unordered_map>
+#include <vector>
+
+using namespace qsw;
+
+namespace {
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct Fnv {
+  uint64_t h = 1469598103934665603ull;
+  void add(const void *p, size_t bytes) {
+    const unsigned char *c = (const unsigned char *)p;
+    for (size_t i = 0; i < bytes; ++i) {
+      h ^= c[i];
+      h *= 1099511628211ull;
+    }
+  }
+};
+
+// What identifies an operator: the arguments of qsw_superop_build.
+struct OpKey {
+  int32_t N = 0;
+  double omega = 0.0, gamma = 1.0;
+  uint32_t flags = 0;
+  std::vector<int64_t> rp;
+  std::vector<int32_t> col;
+  std::vector<double> w;
+  bool operator==(const OpKey &o) const {
+    return N == o.N && omega == o.omega && gamma == o.gamma && flags == o.flags && rp == o.rp &&
+           col == o.col && w == o.w;
+  }
+};
+
+struct CachedOp {
+  OpKey key;
+  uint64_t hash = 0;
+  qsw_superop_t op = nullptr;
+  size_t bytes = 0;
+  int users = 0;  // walks pending or running on it
+};
+
+struct Request {
+  int64_t id = 0;
+  uint64_t hash = 0;
+  qsw_walk_t walk{};
+  double t_submit = 0.0, t_admit = 0.0, t_done = 0.0;
+  int64_t ticket = -1;
+  int state = 0;  // 0 pending, 1 running, 2 done
+};
+
+// Device bytes a handle holds: CSR, wave-jagged copy (padded), complex64
+// copy if any, row blocks of the stream layout.
+size_t op_bytes(const qsw_superop_s *h) {
+  const size_t n = (size_t)h->n, nnz = (size_t)h->nnz;
+  size_t b = 8 * (n + 1) + 4 * nnz + 16 * nnz;                  // CSR
+  b += 4 * (nnz + kWavePad) + 16 * (nnz + kWavePad) + 4 * n + n;  // wave-jagged
+  if (h->wval32) b += 8 * (nnz + kWavePad);
+  b += 4 * ((size_t)h->nblk + 1);
+  return b;
+}
+
+}  // namespace
+
+struct qsw_server_s {
+  int device = -1;
+  hipStream_t stream = nullptr;
+  void *arena = nullptr;
+  qsw_engine_t engine = nullptr;
+  size_t cache_budget = 0, cache_used = 0;
+  std::unordered_multimap<uint64_t, CachedOp *> cache;  // hash -> entries
+  std::list<CachedOp *> lru;                            // entries, newest first
+  std::deque<Request *> pending;
+  std::unordered_map<int64_t, Request *> by_id;
+  std::unordered_map<int64_t, Request *> by_ticket;
+  std::vector<int64_t> done_ids;
+  int64_t next_id = 0;
+  qsw_server_stats_t stats{};
+};
+
+namespace {
+
+void touch(qsw_server_s *s, CachedOp *c) {
+  s->lru.remove(c);
+  s->lru.push_front(c);
+}
+
+void evict_unused(qsw_server_s *s, size_t need) {
+  while (s->cache_used + need > s->cache_budget) {
+    CachedOp *victim = nullptr;
+    for (auto it = s->lru.rbegin(); it != s->lru.rend(); ++it)
+      if ((*it)->users == 0) {
+        victim = *it;
+        break;
+      }
+    if (!victim) return;  // everything cached is in use
+    s->lru.remove(victim);
+    auto range = s->cache.equal_range(victim->hash);
+    for (auto it = range.first; it != range.second; ++it)
+      if (it->second == victim) {
+        s->cache.erase(it);
+        break;
+      }
+    s->cache_used -= victim->bytes;
+    qsw_superop_destroy(victim->op);
+    delete victim;
+    ++s->stats.evictions;
+  }
+}
+
+CachedOp *find_op(qsw_server_s *s, uint64_t hash, const OpKey &key) {
+  auto range = s->cache.equal_range(hash);
+  for (auto it = range.first; it != range.second; ++it)
+    if (it->second->key == key) return it->second;
+  return nullptr;
+}
+
+// Admit pending walks in arrival order while the engine takes them.
+qsw_status_t admit(qsw_server_s *s) {
+  while (!s->pending.empty()) {
+    Request *r = s->pending.front();
+    int64_t ticket = -1;
+    const qsw_status_t st = qsw_engine_submit(s->engine, &r->walk, &ticket);
+    if (st == QSW_ERR_OOM) break;  // waits until running walks free space
+    if (st != QSW_OK) return st;
+    r->ticket = ticket;
+    r->state = 1;
+    r->t_admit = now_ms();
+    s->by_ticket[ticket] = r;
+    s->pending.pop_front();
+  }
+  return QSW_OK;
+}
+
+CachedOp *owner_of(qsw_server_s *s, qsw_superop_t op) {
+  for (CachedOp *c : s->lru)
+    if (c->op == op) return c;
+  return nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+qsw_status_t qsw_server_create(size_t arena_bytes, size_t cache_bytes, int32_t max_walks,
+                               void *hip_stream, qsw_server_t *out) {
+  if (!out) return QSW_ERR_ARG;
+  *out = nullptr;
+  if (max_walks < 1 || arena_bytes == 0) return QSW_ERR_ARG;
+  qsw_server_s *s = new (std::nothrow) qsw_server_s();
+  if (!s) return QSW_ERR_OOM;
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return QSW_ERR_DEVICE;
+  }
+  s->stream = (hipStream_t)hip_stream;
+  s->cache_budget = cache_bytes;
+  if (hipMalloc(&s->arena, arena_bytes) != hipSuccess) {
+    delete s;
+    return QSW_ERR_OOM;
+  }
+  const qsw_status_t st = qsw_engine_create(max_walks, 1, s->arena, arena_bytes, hip_stream,
+                                            &s->engine);
+  if (st != QSW_OK) {
+    (void)hipFree(s->arena);
+    delete s;
+    return st;
+  }
+  *out = s;
+  return QSW_OK;
+}
+
+void qsw_server_destroy(qsw_server_t s) {
+  if (!s) return;
+  DeviceGuard g(s->device);
+  qsw_engine_destroy(s->engine);
+  for (CachedOp *c : s->lru) {
+    qsw_superop_destroy(c->op);
+    delete c;
+  }
+  for (auto &kv : s->by_id) delete kv.second;
+  if (s->arena) (void)hipFree(s->arena);
+  delete s;
+}
+
+qsw_status_t qsw_server_submit(qsw_server_t s, int32_t N, const int64_t *row_ptr,
+                               const int32_t *col_idx, const double *w, double omega,
+                               double gamma, uint32_t flags, const void *rho0, double t0,
+                               double dt, int32_t n_steps, void *out, void *pops,
+                               int64_t *request) {
+  if (!s || !row_ptr || !rho0 || !request || N < 1 || n_steps < 0) return QSW_ERR_ARG;
+  DeviceGuard g(s->device);
+  if (!g.ok) return QSW_ERR_DEVICE;
+  const double t_submit = now_ms();
+  OpKey key;
+  key.N = N;
+  key.omega = omega;
+  key.gamma = gamma;
+  key.flags = flags;
+  const int64_t E = row_ptr[N];
+  if (E < 0 || (E > 0 && (!col_idx || !w))) return QSW_ERR_ARG;
+  key.rp.assign(row_ptr, row_ptr + N + 1);
+  key.col.assign(col_idx, col_idx + E);
+  key.w.assign(w, w + E);
+  Fnv f;
+  f.add(&N, sizeof N);
+  f.add(&omega, sizeof omega);
+  f.add(&gamma, sizeof gamma);
+  f.add(&flags, sizeof flags);
+  f.add(key.rp.data(), key.rp.size() * sizeof(int64_t));
+  f.add(key.col.data(), key.col.size() * sizeof(int32_t));
+  f.add(key.w.data(), key.w.size() * sizeof(double));
+  CachedOp *c = find_op(s, f.h, key);
+  if (c) {
+    ++s->stats.cache_hits;
+  } else {
+    qsw_superop_t op = nullptr;
+    const double tb = now_ms();
+    const qsw_status_t st = qsw_superop_build(N, row_ptr, col_idx, w, omega, gamma, flags,
+                                              s->stream, &op);
+    if (st != QSW_OK) return st;
+    s->stats.build_ms += now_ms() - tb;
+    ++s->stats.cache_misses;
+    c = new (std::nothrow) CachedOp();
+    if (!c) {
+      qsw_superop_destroy(op);
+      return QSW_ERR_OOM;
+    }
+    c->key = std::move(key);
+    c->hash = f.h;
+    c->op = op;
+    c->bytes = op_bytes(op);
+    evict_unused(s, c->bytes);  // may leave the cache over budget while all are in use
+    s->cache.emplace(f.h, c);
+    s->lru.push_front(c);
+    s->cache_used += c->bytes;
+  }
+  touch(s, c);
+  ++c->users;
+  Request *r = new (std::nothrow) Request();
+  if (!r) {
+    --c->users;
+    return QSW_ERR_OOM;
+  }
+  r->id = s->next_id++;
+  r->hash = f.h;
+  r->walk.op = c->op;
+  r->walk.n0 = 1;
+  r->walk.rho0 = rho0;
+  r->walk.t0 = t0;
+  r->walk.dt = dt;
+  r->walk.n_steps = n_steps;
+  r->walk.out = out;
+  r->walk.pops = pops;
+  r->t_submit = t_submit;
+  const size_t need = qsw_walk_bytes(&r->walk, 1);
+  if (need == 0 || need > engine_pool_bytes(s->engine)) {  // bad, or can never fit
+    --c->users;
+    delete r;
+    return need == 0 ? QSW_ERR_ARG : QSW_ERR_OOM;
+  }
+  s->by_id[r->id] = r;
+  s->pending.push_back(r);
+  ++s->stats.submitted;
+  *request = r->id;
+  return admit(s);
+}
+
+qsw_status_t qsw_server_step(qsw_server_t s, int32_t max_cycles, int32_t *running,
+                             int32_t *pending) {
+  if (!s || max_cycles < 0) return QSW_ERR_ARG;
+  DeviceGuard g(s->device);
+  if (!g.ok) return QSW_ERR_DEVICE;
+  qsw_status_t st = admit(s);
+  if (st != QSW_OK) return st;
+  int32_t live = 0;
+  st = qsw_engine_run(s->engine, max_cycles, &live);
+  if (st != QSW_OK && st != QSW_ERR_NONFINITE) return st;
+  int64_t tickets[256];
+  int32_t cnt = 0;
+  do {
+    const qsw_status_t ps = qsw_engine_poll(s->engine, tickets, 256, &cnt);
+    if (ps != QSW_OK) return ps;
+    const double t = now_ms();
+    for (int32_t i = 0; i < cnt; ++i) {
+      auto it = s->by_ticket.find(tickets[i]);
+      if (it == s->by_ticket.end()) continue;
+      Request *r = it->second;
+      s->by_ticket.erase(it);
+      r->state = 2;
+      r->t_done = t;
+      s->done_ids.push_back(r->id);
+      ++s->stats.completed;
+      CachedOp *c = owner_of(s, r->walk.op);
+      if (c) --c->users;
+    }
+  } while (cnt == 256);
+  evict_unused(s, 0);  // operators the finished walks released, if over budget
+  st = admit(s);  // iteration-level admission into the space just freed
+  if (st != QSW_OK) return st;
+  if (running) *running = live;
+  if (pending) *pending = (int32_t)s->pending.size();
+  qsw_engine_stats_t es{};
+  (void)qsw_engine_stats(s->engine, &es);
+  s->stats.cycles = es.cycles;
+  s->stats.products = es.products;
+  s->stats.cache_bytes = (int64_t)s->cache_used;
+  return QSW_OK;
+}
+
+qsw_status_t qsw_server_poll(qsw_server_t s, int64_t *requests, double *latency_ms,
+                             int32_t capacity, int32_t *count) {
+  if (!s || !count || capacity < 0 || (capacity > 0 && !requests)) return QSW_ERR_ARG;
+  const int32_t n = (int32_t)std::min<size_t>((size_t)capacity, s->done_ids.size());
+  for (int32_t i = 0; i < n; ++i) {
+    const int64_t id = s->done_ids[i];
+    requests[i] = id;
+    auto it = s->by_id.find(id);
+    if (it != s->by_id.end()) {
+      if (latency_ms) latency_ms[i] = it->second->t_done - it->second->t_submit;
+      delete it->second;
+      s->by_id.erase(it);
+    }
+  }
+  s->done_ids.erase(s->done_ids.begin(), s->done_ids.begin() + n);
+  *count = n;
+  return QSW_OK;
+}
+
+qsw_status_t qsw_server_stats(qsw_server_t s, qsw_server_stats_t *st) {
+  if (!s || !st) return QSW_ERR_ARG;
+  *st = s->stats;
+  st->cache_bytes = (int64_t)s->cache_used;
+  return QSW_OK;
+}
+
+}  // extern "C"

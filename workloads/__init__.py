@@ -288,3 +288,27 @@ def batch64(seed: int = BASE_SEED + 20, count: int = 64, n0: int = 4, n_steps: i
         out.append(Workload(f"batch{i}_N{N}", g, omega, "laplacian", "transition", False,
                             basis_states(N, verts), 0.0, dt, n_steps))
     return out
+
+
+def served_requests(count: int, seed: int = BASE_SEED + 30, n_lo: int = 16, n_hi: int = 2048,
+                    t_end: float = 10.0) -> list:
+    """Walks for the serving workload: N = round(exp(U(ln n_lo, ln n_hi))),
+    ER with mean degree 6 where each edge is one random arc with probability
+    0.1 (else arcs both ways), unit weights, omega ~ U(0, 1), n_points ~
+    U{10..200} grid steps over t in [0, t_end], rho0 = |0><0|.  Each item is a
+    dict with graph, omega, n_steps, dt."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for _ in range(count):
+        N = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
+        g = er_mixed_direction(N, 6.0, 0.1, rng)
+        omega = float(rng.uniform(0.0, 1.0))
+        steps = int(rng.integers(10, 201))
+        out.append({"graph": g, "omega": omega, "n_steps": steps, "dt": t_end / steps})
+    return out
+
+
+def poisson_arrivals(count: int, qps: float, seed: int = BASE_SEED + 31) -> np.ndarray:
+    """Arrival times (seconds from 0) of a Poisson process of rate qps."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.cumsum(rng.exponential(1.0 / qps, size=count))
