@@ -119,6 +119,24 @@ qsw_status_t qsw_superop_build(int32_t N, const int64_t *row_ptr, const int32_t 
                                void *hip_stream, qsw_superop_t *out);
 
 /*
+ * qsw_superop_build on the augmented digraph of Section 2.4.2 (eq.
+ * dimer_aug, eq. qsw_ss): n_sources source vertices (numbered N .. N +
+ * n_sources - 1, source k feeding graph vertex source_vertex[k] at rate
+ * source_rate[k]) and n_sinks sink vertices (numbered after them, sink k
+ * draining graph vertex sink_vertex[k] at rate sink_rate[k]).  The channels
+ * act outside omega; H and the omega-scaled rates come from G as for
+ * qsw_superop_build and are zero on the added vertices.  rho0 and the
+ * outputs are (N + n_sources + n_sinks)^2.  Synchronises `hip_stream`.
+ */
+qsw_status_t qsw_superop_build_channels(int32_t N, const int64_t *row_ptr, const int32_t *col_idx,
+                                        const double *w, double omega, double gamma,
+                                        uint32_t flags, int32_t n_sources,
+                                        const int32_t *source_vertex, const double *source_rate,
+                                        int32_t n_sinks, const int32_t *sink_vertex,
+                                        const double *sink_rate, void *hip_stream,
+                                        qsw_superop_t *out);
+
+/*
  * Build from explicit operators, as the paper's LQSW(omega, H, M_L) does
  * (Section 4): H is a Hermitian N x N host CSR (complex128 values,
  * interleaved; it may hold a diagonal; its pattern must be symmetric), M_L
@@ -134,6 +152,50 @@ qsw_status_t qsw_superop_build_ops(int32_t N,
                                    const double *l_val,
                                    double omega, uint32_t flags, void *hip_stream,
                                    qsw_superop_t *out);
+
+/*
+ * qsw_superop_build_ops with absorption and emission channels (Section 2.4.2,
+ * eq. qsw_ss): M_free is a second real coefficient matrix (host CSR, same
+ * rules as M_L) whose L_k = M_free[i][j] |i><j| enter with rate
+ * |M_free[i][j]|^2 OUTSIDE the factor omega, e.g. sources (arcs from a source
+ * vertex into the graph, rate Gamma) and sinks (arcs from the graph into a
+ * sink vertex, rate Theta) of the augmented digraph.  The order N counts the
+ * source and sink vertices.  M_free may be NULL (then this is
+ * qsw_superop_build_ops).  flags: 0.  Synchronises `hip_stream`.
+ */
+qsw_status_t qsw_superop_build_open(int32_t N, const int64_t *h_row_ptr, const int32_t *h_col,
+                                    const double *h_val, const int64_t *l_row_ptr,
+                                    const int32_t *l_col, const double *l_val,
+                                    const int64_t *f_row_ptr, const int32_t *f_col,
+                                    const double *f_val, double omega, uint32_t flags,
+                                    void *hip_stream, qsw_superop_t *out);
+
+/*
+ * A walk with explicit Lindblad operators (Section 2.4.3, eq. L_global, and
+ * the non-moralising form eq. nm_gqsw):
+ *     L rho = -i(1-omega)[H, rho] + omega ( i[H_rot, rho] + sum_k D[L_k] rho ),
+ *     D[L] rho = L rho L^dag - 1/2 {L^dag L, rho}.
+ * H and H_rot: Hermitian complex host CSR (H_rot may be NULL); L_k: n_ops
+ * complex host CSRs (arrays of their row_ptr / col / interleaved val).  The
+ * G-QSW is n_ops = 1, L_1 = G.  Assembled on the host (Kronecker terms; the
+ * superoperator's density grows as the square of the L_k's), then handled
+ * exactly as the other builds.  Synchronises `hip_stream`.
+ */
+qsw_status_t qsw_superop_build_general(int32_t N, const int64_t *h_row_ptr, const int32_t *h_col,
+                                       const double *h_val, int32_t n_ops,
+                                       const int64_t *const *l_row_ptr,
+                                       const int32_t *const *l_col, const double *const *l_val,
+                                       const int64_t *r_row_ptr, const int32_t *r_col,
+                                       const double *r_val, double omega, void *hip_stream,
+                                       qsw_superop_t *out);
+
+/*
+ * Rebuild the handle's superoperator for another omega (the paper's
+ * set_omega), from the operators it was built from; the handle keeps its
+ * identity and precision, and the result is the same as a fresh build at
+ * that omega.  Waits for work in flight on the device.
+ */
+qsw_status_t qsw_superop_set_omega(qsw_superop_t h, double omega, void *hip_stream);
 
 void qsw_superop_destroy(qsw_superop_t h);
 
@@ -180,7 +242,8 @@ qsw_status_t qsw_superop_autotune(qsw_superop_t h, void *hip_stream, qsw_tuning_
 
 /* Copy the device CSR to caller host buffers (row_ptr[n+1], col[nnz],
  * val[2*nnz] doubles), rows in the structural order described at
- * qsw_superop_build.  Any pointer may be NULL to skip it.  Synchronous. */
+ * qsw_superop_build (rows of qsw_superop_build_general are sorted by
+ * column).  Any pointer may be NULL to skip it.  Synchronous. */
 qsw_status_t qsw_superop_copy_csr(qsw_superop_t h, int64_t *row_ptr, int32_t *col,
                                   double *val);
 

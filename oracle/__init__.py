@@ -37,3 +37,31 @@ def run_workload(wl, n_steps=None):
                      wl.dephasing, wl.gamma)
     steps = wl.n_steps if n_steps is None else n_steps
     return expmv.propagate(A, wl.rho0, wl.t0, wl.dt, steps)
+
+
+def dense_csr(S):
+    """Dense row-major generator -> oracle CSR (explicit zeros dropped)."""
+    import numpy as np
+    n = S.shape[0]
+    rows, cols = np.nonzero(S)
+    rp = np.zeros(n + 1, np.int64)
+    np.cumsum(np.bincount(rows, minlength=n), out=rp[1:])
+    return CSR(n, rp, cols.astype(np.int32), S[rows, cols])
+
+
+def general_superop(H, Ls, omega, H_rot=None, Ls_free=()) -> "CSR":
+    """Explicit operators (G-QSW, NM-G-QSW, channels) -> row-major CSR,
+    through the dense Kronecker form (small N only)."""
+    return dense_csr(operators.general_rowmajor(H, Ls, omega, H_rot, Ls_free))
+
+
+def channel_superop(graph_dense, omega, sources, sinks, h_mode="laplacian",
+                    r_mode="transition", dephasing=False, gamma=1.0) -> "CSR":
+    """A walk on the augmented digraph (Section 2.4.2): the graph's H and
+    L_k (omega-scaled) padded with the source and sink vertices, plus the
+    channels outside omega.  Dense (small N only)."""
+    import numpy as np
+    Ga, chans = operators.augmented(np.asarray(graph_dense, float), sources, sinks)
+    H, ML = operators.walk_operators(Ga, h_mode, r_mode, dephasing, gamma)
+    Ls = operators.lindblad_ops(ML)
+    return general_superop(H, Ls, omega, None, chans)

@@ -14,6 +14,12 @@ checked against the paper by eye:
 * ``superop_kron``        - the vectorised generator of eq. qsw built literally
   from the Kronecker mappings of eq. vec_mappings with column stacking
   (vec(XYZ) = (Z^T kron X) vec(Y)), one explicit L_k at a time.
+* ``superop_kron_general``- the same for explicit operators: any list of
+  L_k scaled by omega (the G-QSW of eq. L_global has one, L = G), the
+  rotating Hamiltonian term omega i[H_rot, rho] of eq. nm_gqsw, and L_k
+  outside omega (the absorption / emission channels of eq. qsw_ss).
+* ``augmented``           - the augmented digraph of Section 2.4.2 (eq.
+  dimer_aug): source and sink vertices appended after the graph's.
 
 Conventions (readings of the paper, listed in the design notes):
 * G[i, j] is the weight of the arc j -> i (row = target, column = source).
@@ -139,3 +145,61 @@ def superop_kron_rowmajor(H, ML, omega) -> np.ndarray:
     S = superop_kron(H, ML, omega)
     p = colstack_to_rowmajor(N)
     return S[np.ix_(p, p)]
+
+
+def dissipator_kron(L: np.ndarray) -> np.ndarray:
+    """D[L] rho = L rho L^dag - 1/2 {L^dag L, rho} on the column-stacked vec."""
+    N = L.shape[0]
+    I = np.eye(N)
+    LdL = L.conj().T @ L
+    return np.kron(L.conj(), L) - 0.5 * (np.kron(I, LdL) + np.kron(LdL.T, I))
+
+
+def commutator_kron(M: np.ndarray) -> np.ndarray:
+    """[M, rho] on the column-stacked vec."""
+    N = M.shape[0]
+    I = np.eye(N)
+    return np.kron(I, M) - np.kron(M.T, I)
+
+
+def superop_kron_general(H, Ls, omega, H_rot=None, Ls_free=()) -> np.ndarray:
+    """-i(1-omega)[H, .] + omega (i[H_rot, .] + sum_k D[L_k]) + sum_f D[F_f],
+    column-stacked, dense."""
+    Hc = np.asarray(H, dtype=np.complex128)
+    S = -1j * (1.0 - omega) * commutator_kron(Hc)
+    if H_rot is not None:
+        S = S + 1j * omega * commutator_kron(np.asarray(H_rot, dtype=np.complex128))
+    for L in Ls:
+        S = S + omega * dissipator_kron(np.asarray(L, dtype=np.complex128))
+    for F in Ls_free:
+        S = S + dissipator_kron(np.asarray(F, dtype=np.complex128))
+    return S
+
+
+def general_rowmajor(H, Ls, omega, H_rot=None, Ls_free=()) -> np.ndarray:
+    N = np.asarray(H).shape[0]
+    S = superop_kron_general(H, Ls, omega, H_rot, Ls_free)
+    p = colstack_to_rowmajor(N)
+    return S[np.ix_(p, p)]
+
+
+def augmented(G: np.ndarray, sources, sinks):
+    """(G_aug on N + len(sources) + len(sinks) vertices with the graph's arcs
+    only, the list of channel operators).  Source k is vertex N + k and feeds
+    sources[k] = (vertex, Gamma) through L = sqrt(Gamma)|vertex><N + k|; sink k
+    is vertex N + len(sources) + k and drains sinks[k] = (vertex, Theta)
+    through L = sqrt(Theta)|sink><vertex|."""
+    N = G.shape[0]
+    M = N + len(sources) + len(sinks)
+    Ga = np.zeros((M, M))
+    Ga[:N, :N] = G
+    chans = []
+    for k, (v, rate) in enumerate(sources):
+        L = np.zeros((M, M), np.complex128)
+        L[v, N + k] = np.sqrt(rate)
+        chans.append(L)
+    for k, (v, rate) in enumerate(sinks):
+        L = np.zeros((M, M), np.complex128)
+        L[N + len(sources) + k, v] = np.sqrt(rate)
+        chans.append(L)
+    return Ga, chans

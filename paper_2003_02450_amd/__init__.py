@@ -110,13 +110,86 @@ class Superop:
         return cls(h, dev)
 
     @classmethod
+    def from_channels(cls, graph, omega, sources=(), sinks=(), gamma=1.0, h_mode="laplacian",
+                      r_mode="transition", dephasing=False, device=None):
+        """Walk on the augmented digraph (Section 2.4.2): sources = [(vertex,
+        Gamma)], sinks = [(vertex, Theta)]; source k is vertex N + k, sink k
+        vertex N + len(sources) + k; the channels act outside omega."""
+        torch = _torch()
+        L = _lib.load()
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        rp = np.ascontiguousarray(graph.row_ptr, np.int64)
+        ci = np.ascontiguousarray(graph.col_idx, np.int32)
+        ww = np.ascontiguousarray(graph.w, np.float64)
+        sv = np.ascontiguousarray([v for v, _ in sources], np.int32)
+        sr = np.ascontiguousarray([r for _, r in sources], np.float64)
+        kv = np.ascontiguousarray([v for v, _ in sinks], np.int32)
+        kr = np.ascontiguousarray([r for _, r in sinks], np.float64)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(dev):
+            st = L.qsw_superop_build_channels(
+                int(graph.N), _ptr(rp), _ptr(ci), _ptr(ww), float(omega), float(gamma),
+                _flags(h_mode, r_mode, dephasing), len(sources), _ptr(sv), _ptr(sr), len(sinks),
+                _ptr(kv), _ptr(kr), _stream(dev), ctypes.byref(h))
+        _lib.check(st, "qsw_superop_build_channels")
+        return cls(h, dev)
+
+    @classmethod
+    def from_general(cls, H, Ls, omega, H_rot=None, device=None):
+        """Explicit Lindblad operators (Section 2.4.3): H and H_rot Hermitian,
+        Ls a list of complex matrices (scipy sparse or dense); the G-QSW of
+        eq. L_global is Ls = [G]."""
+        torch = _torch()
+        import scipy.sparse as sp
+        L = _lib.load()
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+
+        def csr(M):
+            C = sp.csr_matrix(M, dtype=np.complex128)
+            C.sort_indices()
+            return (np.ascontiguousarray(C.indptr, np.int64), np.ascontiguousarray(C.indices, np.int32),
+                    np.ascontiguousarray(C.data, np.complex128).view(np.float64))
+        hp, hc, hv = csr(H)
+        N = hp.size - 1
+        parts = [csr(M) for M in Ls]
+        keep = parts
+        lp = (ctypes.c_void_p * max(len(parts), 1))(*[_ptr(p[0]).value for p in parts])
+        lc = (ctypes.c_void_p * max(len(parts), 1))(*[_ptr(p[1]).value for p in parts])
+        lv = (ctypes.c_void_p * max(len(parts), 1))(*[_ptr(p[2]).value for p in parts])
+        rp = rc = rv = None
+        if H_rot is not None:
+            rp, rc, rv = csr(H_rot)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(dev):
+            st = L.qsw_superop_build_general(
+                N, _ptr(hp), _ptr(hc), _ptr(hv), len(parts), lp, lc, lv,
+                _ptr(rp) if rp is not None else None, _ptr(rc) if rc is not None else None,
+                _ptr(rv) if rv is not None else None, float(omega), _stream(dev), ctypes.byref(h))
+        del keep
+        _lib.check(st, "qsw_superop_build_general")
+        return cls(h, dev)
+
+    def set_omega(self, omega):
+        """Rebuild for another omega (the paper's set_omega)."""
+        torch = _torch()
+        with torch.cuda.device(self.device):
+            st = _lib.load().qsw_superop_set_omega(self._h, float(omega), _stream(self.device))
+        _lib.check(st, "qsw_superop_set_omega")
+        info = _lib.Info()
+        _lib.check(_lib.load().qsw_superop_info(self._h, ctypes.byref(info)), "qsw_superop_info")
+        self.omega = info.omega
+        self.nnz = info.nnz
+        self._info = info
+
+    @classmethod
     def from_workload_graph(cls, graph, omega, **kw):
         return cls.from_graph(graph.N, graph.row_ptr, graph.col_idx, graph.w, omega, **kw)
 
     @classmethod
-    def from_operators(cls, H, ML, omega, device=None):
+    def from_operators(cls, H, ML, omega, M_free=None, device=None):
         """The paper's LQSW(omega, H, M_L): Hermitian H and condensed Lindblad
-        matrix M_L (each entry one L_k), given as scipy sparse or dense."""
+        matrix M_L (each entry one L_k), given as scipy sparse or dense;
+        M_free adds channels outside omega (eq. qsw_ss)."""
         torch = _torch()
         import scipy.sparse as sp
         L = _lib.load()
@@ -132,11 +205,21 @@ class Superop:
         lp = np.ascontiguousarray(Mc.indptr, np.int64)
         lc = np.ascontiguousarray(Mc.indices, np.int32)
         lv = np.ascontiguousarray(Mc.data, np.float64)
+        fp = fc = fv = None
+        if M_free is not None:
+            Fc = sp.csr_matrix(M_free, dtype=np.float64)
+            Fc.sort_indices()
+            fp = np.ascontiguousarray(Fc.indptr, np.int64)
+            fc = np.ascontiguousarray(Fc.indices, np.int32)
+            fv = np.ascontiguousarray(Fc.data, np.float64)
         h = ctypes.c_void_p()
         with torch.cuda.device(dev):
-            st = L.qsw_superop_build_ops(int(N), _ptr(hp), _ptr(hc), _ptr(hv), _ptr(lp), _ptr(lc),
-                                         _ptr(lv), float(omega), 0, _stream(dev), ctypes.byref(h))
-        _lib.check(st, "qsw_superop_build_ops")
+            st = L.qsw_superop_build_open(
+                int(N), _ptr(hp), _ptr(hc), _ptr(hv), _ptr(lp), _ptr(lc), _ptr(lv),
+                _ptr(fp) if fp is not None else None, _ptr(fc) if fc is not None else None,
+                _ptr(fv) if fv is not None else None, float(omega), 0, _stream(dev),
+                ctypes.byref(h))
+        _lib.check(st, "qsw_superop_build_open")
         return cls(h, dev)
 
     # ------------------------------------------------------------- queries

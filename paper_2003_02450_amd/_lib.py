@@ -21,7 +21,9 @@ QSW_PREC_DOUBLE = 0
 QSW_PREC_SINGLE = 1
 
 # Every function the header declares, for the export check.
-EXPORTED = ("qsw_superop_build", "qsw_superop_build_ops", "qsw_superop_destroy",
+EXPORTED = ("qsw_superop_build", "qsw_superop_build_ops", "qsw_superop_build_channels",
+            "qsw_superop_build_open", "qsw_superop_build_general", "qsw_superop_set_omega",
+            "qsw_superop_destroy",
             "qsw_superop_info", "qsw_superop_set_precision", "qsw_superop_autotune",
             "qsw_superop_copy_csr", "qsw_propagate_workspace_bytes",
             "qsw_propagate", "qsw_last_stats", "qsw_apply", "qsw_populations", "qsw_theta",
@@ -102,6 +104,17 @@ def load() -> ctypes.CDLL:
     L.qsw_superop_build_ops.restype = _i32
     L.qsw_superop_build_ops.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _dbl, _u32, _vp,
                                         ctypes.POINTER(_vp)]
+    L.qsw_superop_build_channels.restype = _i32
+    L.qsw_superop_build_channels.argtypes = [_i32, _vp, _vp, _vp, _dbl, _dbl, _u32, _i32, _vp, _vp,
+                                             _i32, _vp, _vp, _vp, ctypes.POINTER(_vp)]
+    L.qsw_superop_build_open.restype = _i32
+    L.qsw_superop_build_open.argtypes = [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _dbl,
+                                         _u32, _vp, ctypes.POINTER(_vp)]
+    L.qsw_superop_build_general.restype = _i32
+    L.qsw_superop_build_general.argtypes = [_i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp,
+                                            _vp, _dbl, _vp, ctypes.POINTER(_vp)]
+    L.qsw_superop_set_omega.restype = _i32
+    L.qsw_superop_set_omega.argtypes = [_vp, _dbl, _vp]
     L.qsw_superop_destroy.restype = None
     L.qsw_superop_destroy.argtypes = [_vp]
     L.qsw_superop_info.restype = _i32

@@ -9,8 +9,11 @@
 
 #include <cstddef>
 #include <cstdlib>
+#include <memory>
 
 namespace qsw {
+
+struct Assembler;  // what a handle is built from (runtime.hip)
 
 #define HIP_TRY(expr)                                  \
   do {                                                 \
@@ -93,6 +96,7 @@ struct qsw_superop_s {
   unsigned long long *stats_dev = nullptr;  // [products, nonfinite]
   qsw_stats_t last{};
   bool have_last = false;
+  std::shared_ptr<qsw::Assembler> src;  // kept for qsw_superop_set_omega
 };
 
 namespace qsw {

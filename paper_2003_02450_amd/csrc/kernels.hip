@@ -558,7 +558,7 @@ __global__ __launch_bounds__(kBlock) void assemble_kernel(AssembleArgs A, int64_
   if (r == n - 1) A.row_ptr[n] = 2 * N * A.EH + N * N + A.PR[N];
 
   const double ch = A.sigma * (1.0 - A.omega);  // sigma (1 - omega)
-  const double w = A.omega;
+  const double w = A.rscale;                    // omega, or 1 for pre-scaled rates
   // diagonal: sigma(-i)(1-w)(H_aa - H_bb) - w/2 (K_a + K_b) + [a==b] w R_aa
   const double2 dval =
       make_double2(-0.5 * w * (A.K[a] + A.K[b]) + (a == b ? w * A.rdiag[a] : 0.0),

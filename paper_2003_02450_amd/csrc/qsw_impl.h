@@ -62,7 +62,8 @@ struct AssembleArgs {
   const int64_t *PH;     // exclusive prefix sums of the off-diagonal H row counts
   const int64_t *PR;     // exclusive prefix sums of the off-diagonal rate row counts
   int64_t EH;            // off-diagonal H entries
-  double omega;
+  double omega;          // H terms carry 1 - omega
+  double rscale;         // factor on the rates, K and R_aa (omega, or 1 when pre-scaled)
   double sigma;          // +1: L ; -1: L^dagger (with R transposed)
   int64_t *row_ptr;
   int32_t *col;

@@ -16,8 +16,10 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <complex>
 #include <limits>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <tuple>
 #include <new>
@@ -38,8 +40,59 @@ struct HostOps {
   std::vector<int32_t> rc;
   std::vector<double> rv;
   std::vector<double> rdiag;
-  std::vector<double> K;
+  // rates outside omega (absorption / emission channels), same layout; empty
+  // when there are none
+  std::vector<int64_t> fp;
+  std::vector<int32_t> fc;
+  std::vector<double> fv;
+  std::vector<double> fdiag;
 };
+
+// The rates the assembly uses: omega R + F when there are rates outside
+// omega (then pre-scaled: factor 1), else R itself with factor omega.
+struct Rates {
+  std::vector<int64_t> rp;
+  std::vector<int32_t> rc;
+  std::vector<double> rv;
+  std::vector<double> rdiag;
+  double scale = 1.0;
+};
+
+Rates effective_rates(const HostOps &op, double omega) {
+  Rates R;
+  const int32_t N = op.N;
+  if (op.fp.empty()) {
+    R.rp = op.rp;
+    R.rc = op.rc;
+    R.rv = op.rv;
+    R.rdiag = op.rdiag;
+    R.scale = omega;
+    return R;
+  }
+  R.rp.assign(N + 1, 0);
+  R.rdiag.assign(N, 0.0);
+  for (int32_t i = 0; i < N; ++i) {
+    int64_t a = op.rp[i], b = op.fp[i];
+    while (a < op.rp[i + 1] || b < op.fp[i + 1]) {
+      const int32_t ca = a < op.rp[i + 1] ? op.rc[a] : INT32_MAX;
+      const int32_t cb = b < op.fp[i + 1] ? op.fc[b] : INT32_MAX;
+      if (ca == cb) {
+        R.rc.push_back(ca);
+        R.rv.push_back(omega * op.rv[a++] + op.fv[b++]);
+      } else if (ca < cb) {
+        R.rc.push_back(ca);
+        R.rv.push_back(omega * op.rv[a++]);
+      } else {
+        R.rc.push_back(cb);
+        R.rv.push_back(op.fv[b++]);
+      }
+    }
+    R.rp[i + 1] = (int64_t)R.rc.size();
+    R.rdiag[i] = omega * op.rdiag[i] + (op.fdiag.empty() ? 0.0 : op.fdiag[i]);
+  }
+  R.scale = 1.0;
+  return R;
+}
 
 // Check a host CSR: row_ptr monotone from 0, columns in range, strictly
 // increasing within each row.
@@ -126,13 +179,13 @@ void choose_vector_launch(qsw_superop_s *h, int lpr) {
 // Upper bound of the longest row of L and of its adjoint: row (a, b) holds
 // deg_H(a) + deg_H(b) + 1 entries, plus the population-transfer entries when
 // a == b (rates of row a, or of column a for the adjoint).
-int64_t max_row_bound(const HostOps &op) {
+int64_t max_row_bound(const HostOps &op, const Rates &R) {
   int64_t dh = 0, dr = 0;
   std::vector<int64_t> indeg(op.N, 0);
   for (int32_t i = 0; i < op.N; ++i) {
     dh = std::max<int64_t>(dh, op.hp[i + 1] - op.hp[i]);
-    dr = std::max<int64_t>(dr, op.rp[i + 1] - op.rp[i]);
-    for (int64_t e = op.rp[i]; e < op.rp[i + 1]; ++e) indeg[op.rc[e]]++;
+    dr = std::max<int64_t>(dr, R.rp[i + 1] - R.rp[i]);
+    for (int64_t e = R.rp[i]; e < R.rp[i + 1]; ++e) indeg[R.rc[e]]++;
   }
   for (int32_t i = 0; i < op.N; ++i) dr = std::max(dr, indeg[i]);
   return 2 * dh + 1 + dr;
@@ -167,21 +220,28 @@ hipError_t upload(T **dst, const std::vector<T> &src, hipStream_t s) {
 
 // Assemble sigma = +1 (L, rates as given) or -1 (L^dagger, rates transposed)
 // into freshly allocated (row_ptr, col, val).
-qsw_status_t assemble(const HostOps &op, bool adjoint, double omega, hipStream_t s,
-                      int64_t **rp_out, int32_t **col_out, double2 **val_out, int64_t *nnz_out) {
+qsw_status_t assemble(const HostOps &op, const Rates &R, bool adjoint, double omega,
+                      hipStream_t s, int64_t **rp_out, int32_t **col_out, double2 **val_out,
+                      int64_t *nnz_out) {
   const int32_t N = op.N;
   const int64_t n = (int64_t)N * N;
   std::vector<int64_t> rtp;
   std::vector<int32_t> rtc;
   std::vector<double> rtv;
-  const std::vector<int64_t> *rp = &op.rp;
-  const std::vector<int32_t> *rc = &op.rc;
-  const std::vector<double> *rv = &op.rv;
+  const std::vector<int64_t> *rp = &R.rp;
+  const std::vector<int32_t> *rc = &R.rc;
+  const std::vector<double> *rv = &R.rv;
   if (adjoint) {
-    transpose_csr(N, op.rp, op.rc, op.rv, 1, rtp, rtc, rtv);
+    transpose_csr(N, R.rp, R.rc, R.rv, 1, rtp, rtc, rtv);
     rp = &rtp;
     rc = &rtc;
     rv = &rtv;
+  }
+  // K_j = sum_i R_ij over the rates (diagonal included), for L and L^dagger
+  std::vector<double> K(N, 0.0);
+  for (int32_t i = 0; i < N; ++i) {
+    for (int64_t e = R.rp[i]; e < R.rp[i + 1]; ++e) K[R.rc[e]] += R.rv[e];
+    K[i] += R.rdiag[i];
   }
   std::vector<int64_t> PH(N + 1, 0), PR(N + 1, 0);
   for (int32_t i = 0; i < N; ++i) {
@@ -209,8 +269,8 @@ qsw_status_t assemble(const HostOps &op, bool adjoint, double omega, hipStream_t
     if ((e = upload(&d.rp, *rp, s)) != hipSuccess) break;
     if ((e = upload(&d.rc, *rc, s)) != hipSuccess) break;
     if ((e = upload(&d.rv, *rv, s)) != hipSuccess) break;
-    if ((e = upload(&d.rdiag, op.rdiag, s)) != hipSuccess) break;
-    if ((e = upload(&d.K, op.K, s)) != hipSuccess) break;
+    if ((e = upload(&d.rdiag, R.rdiag, s)) != hipSuccess) break;
+    if ((e = upload(&d.K, K, s)) != hipSuccess) break;
     if ((e = upload(&d.PH, PH, s)) != hipSuccess) break;
     if ((e = upload(&d.PR, PR, s)) != hipSuccess) break;
     if ((e = dalloc(&drp, (size_t)n + 1)) != hipSuccess) break;
@@ -222,6 +282,7 @@ qsw_status_t assemble(const HostOps &op, bool adjoint, double omega, hipStream_t
     A.rp = d.rp; A.rc = d.rc; A.rv = d.rv; A.rdiag = d.rdiag;
     A.K = d.K; A.PH = d.PH; A.PR = d.PR; A.EH = EH;
     A.omega = omega;
+    A.rscale = R.scale;
     A.sigma = adjoint ? -1.0 : 1.0;
     A.row_ptr = drp; A.col = dcol; A.val = dval;
     if ((e = launch_assemble(A, n, s)) != hipSuccess) break;
@@ -421,9 +482,308 @@ int wave_grid(int64_t nwb, int resident) {
   return (int)std::max<int64_t>(1, std::min(wgs, cap));
 }
 
-qsw_status_t build_common(HostOps &op, double omega, hipStream_t s, qsw_superop_t *out) {
+// H (Hermitian, complex, may hold a diagonal) into the off-diagonal CSR and
+// diagonal of HostOps; checks pattern symmetry and H_ji = conj(H_ij).
+qsw_status_t parse_hermitian(int32_t N, const int64_t *rp, const int32_t *ci, const double *v,
+                             HostOps &op) {
+  const int64_t E = rp[N];
+  if (E > 0 && (!ci || !v)) return QSW_ERR_ARG;
+  qsw_status_t st = check_csr(N, rp, ci, true);
+  if (st != QSW_OK) return st;
+  op.hp.assign(N + 1, 0);
+  op.hdiag.assign(N, 0.0);
+  for (int32_t i = 0; i < N; ++i) {
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+      const double re = v[2 * e], im = v[2 * e + 1];
+      if (!std::isfinite(re) || !std::isfinite(im)) return QSW_ERR_GRAPH;
+      if (ci[e] == i) {
+        if (std::fabs(im) > 1e-14 * (1.0 + std::fabs(re))) return QSW_ERR_GRAPH;  // not Hermitian
+        op.hdiag[i] = re;
+      } else {
+        op.hc.push_back(ci[e]);
+        op.hv.push_back(re);
+        op.hv.push_back(im);
+      }
+    }
+    op.hp[i + 1] = (int64_t)op.hc.size();
+  }
+  for (int32_t i = 0; i < N; ++i)
+    for (int64_t e = op.hp[i]; e < op.hp[i + 1]; ++e) {
+      const int32_t j = op.hc[e];
+      const auto b = op.hc.begin() + op.hp[j], en = op.hc.begin() + op.hp[j + 1];
+      const auto it = std::lower_bound(b, en, i);
+      if (it == en || *it != i) return QSW_ERR_GRAPH;
+      const int64_t f = it - op.hc.begin();
+      const double tolh = 1e-14 * (1.0 + std::fabs(op.hv[2 * e]) + std::fabs(op.hv[2 * e + 1]));
+      if (std::fabs(op.hv[2 * f] - op.hv[2 * e]) > tolh ||
+          std::fabs(op.hv[2 * f + 1] + op.hv[2 * e + 1]) > tolh)
+        return QSW_ERR_GRAPH;
+    }
+  return QSW_OK;
+}
+
+// A real coefficient matrix M (each entry one L_k = M_ij |i><j|) into rates
+// |M_ij|^2: off-diagonal CSR plus diagonal.
+qsw_status_t parse_rates(int32_t N, const int64_t *rp, const int32_t *ci, const double *v,
+                         std::vector<int64_t> &op_rp, std::vector<int32_t> &op_rc,
+                         std::vector<double> &op_rv, std::vector<double> &op_rdiag) {
+  const int64_t E = rp[N];
+  if (E > 0 && (!ci || !v)) return QSW_ERR_ARG;
+  qsw_status_t st = check_csr(N, rp, ci, true);
+  if (st != QSW_OK) return st;
+  op_rp.assign(N + 1, 0);
+  op_rdiag.assign(N, 0.0);
+  for (int32_t i = 0; i < N; ++i) {
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+      const double x = v[e];
+      if (!std::isfinite(x)) return QSW_ERR_GRAPH;
+      if (ci[e] == i) {
+        op_rdiag[i] = x * x;
+      } else if (x != 0.0) {
+        op_rc.push_back(ci[e]);
+        op_rv.push_back(x * x);
+      }
+    }
+    op_rp[i + 1] = (int64_t)op_rc.size();
+  }
+  return QSW_OK;
+}
+
+}  // namespace
+
+// What a handle is built from, kept so that qsw_superop_set_omega can
+// rebuild it: assembles L (or its adjoint) for a given omega into fresh
+// device CSR arrays.
+struct qsw::Assembler {
+  virtual ~Assembler() {}
+  virtual int32_t order() const = 0;
+  virtual int64_t max_row(double omega) const = 0;
+  virtual qsw_status_t assemble(bool adjoint, double omega, hipStream_t s, int64_t **rp,
+                                int32_t **col, double2 **val, int64_t *nnz) const = 0;
+};
+
+namespace {
+
+// Walks of the local-interaction family (eq. qsw, plus rates outside omega
+// for absorption and emission, eq. qsw_ss): assembled on the device.
+struct LocalAssembler : Assembler {
+  HostOps op;
+  int32_t order() const override { return op.N; }
+  int64_t max_row(double omega) const override {
+    return max_row_bound(op, effective_rates(op, omega));
+  }
+  qsw_status_t assemble(bool adjoint, double omega, hipStream_t s, int64_t **rp, int32_t **col,
+                        double2 **val, int64_t *nnz) const override {
+    return ::assemble(op, effective_rates(op, omega), adjoint, omega, s, rp, col, val, nnz);
+  }
+};
+
+// Complex host CSR (rows sorted, no duplicates) of an N x N operator.
+struct HostCsr {
+  std::vector<int64_t> rp;
+  std::vector<int32_t> col;
+  std::vector<std::complex<double>> val;
+};
+
+// A complex host CSR (interleaved values); `hermitian` also checks
+// H_ji = conj(H_ij) for every stored entry.
+qsw_status_t parse_complex(int32_t N, const int64_t *rp, const int32_t *ci, const double *v,
+                           bool hermitian, HostCsr &A) {
+  if (!rp) return QSW_ERR_ARG;
+  const int64_t E = rp[N];
+  if (E > 0 && (!ci || !v)) return QSW_ERR_ARG;
+  qsw_status_t st = check_csr(N, rp, ci, true);
+  if (st != QSW_OK) return st;
+  A.rp.assign(rp, rp + N + 1);
+  A.col.assign(ci, ci + E);
+  A.val.resize(E);
+  for (int64_t e = 0; e < E; ++e) {
+    if (!std::isfinite(v[2 * e]) || !std::isfinite(v[2 * e + 1])) return QSW_ERR_GRAPH;
+    A.val[e] = {v[2 * e], v[2 * e + 1]};
+  }
+  if (hermitian)
+    for (int32_t i = 0; i < N; ++i)
+      for (int64_t e = A.rp[i]; e < A.rp[i + 1]; ++e) {
+        const int32_t j = A.col[e];
+        const auto b = A.col.begin() + A.rp[j], en = A.col.begin() + A.rp[j + 1];
+        const auto it = std::lower_bound(b, en, i);
+        if (it == en || *it != i) return QSW_ERR_GRAPH;
+        const std::complex<double> x = A.val[e], y = A.val[it - A.col.begin()];
+        if (std::abs(y - std::conj(x)) > 1e-14 * (1.0 + std::abs(x))) return QSW_ERR_GRAPH;
+      }
+  return QSW_OK;
+}
+
+HostCsr conj_transpose(int32_t N, const HostCsr &A) {
+  HostCsr T;
+  T.rp.assign(N + 1, 0);
+  for (int32_t c : A.col) T.rp[c + 1]++;
+  for (int32_t i = 0; i < N; ++i) T.rp[i + 1] += T.rp[i];
+  T.col.resize(A.col.size());
+  T.val.resize(A.col.size());
+  std::vector<int64_t> pos(T.rp.begin(), T.rp.end() - 1);
+  for (int32_t i = 0; i < N; ++i)
+    for (int64_t e = A.rp[i]; e < A.rp[i + 1]; ++e) {
+      const int64_t o = pos[A.col[e]]++;
+      T.col[o] = i;
+      T.val[o] = std::conj(A.val[e]);
+    }
+  return T;
+}
+
+HostCsr product(int32_t N, const HostCsr &A, const HostCsr &B) {  // A B
+  HostCsr C;
+  C.rp.assign(N + 1, 0);
+  std::vector<std::complex<double>> acc(N);
+  std::vector<char> used(N, 0);
+  std::vector<int32_t> cols;
+  for (int32_t i = 0; i < N; ++i) {
+    cols.clear();
+    for (int64_t e = A.rp[i]; e < A.rp[i + 1]; ++e) {
+      const int32_t k = A.col[e];
+      for (int64_t f = B.rp[k]; f < B.rp[k + 1]; ++f) {
+        const int32_t j = B.col[f];
+        if (!used[j]) {
+          used[j] = 1;
+          acc[j] = 0.0;
+          cols.push_back(j);
+        }
+        acc[j] += A.val[e] * B.val[f];
+      }
+    }
+    std::sort(cols.begin(), cols.end());
+    for (int32_t j : cols) {
+      C.col.push_back(j);
+      C.val.push_back(acc[j]);
+      used[j] = 0;
+    }
+    C.rp[i + 1] = (int64_t)C.col.size();
+  }
+  return C;
+}
+
+// Walks given by explicit operators (the global-interaction family):
+//   L = -i(1-omega)[H, .] + omega ( i[H_rot, .] + sum_k D[L_k] )
+// (eq. qsw with one or more general L_k, eq. nm_gqsw with H_rot), assembled
+// on the host as Kronecker terms in the row-major vec(rho)_(aN+b) = rho_ab:
+// A rho B -> A kron B^T.  Its explicit entries are those of the terms'
+// patterns (zeros kept), so the pattern does not depend on omega.
+struct GeneralAssembler : Assembler {
+  int32_t N = 0;
+  HostCsr H, Hrot;
+  std::vector<HostCsr> Ls, LdLs;  // L_k and L_k^dagger L_k
+  int32_t order() const override { return N; }
+
+  // One row r = a N + b of L (sigma = +1) or of L^dagger: (col, val) pairs,
+  // merged.  For the adjoint every operator is replaced by its adjoint
+  // (H, H_rot: -i -> +i; L_k rho L_k^dag -> L_k^dag rho L_k).
+  void row(int64_t a, int64_t b, double omega, bool adjoint, std::vector<int64_t> &c,
+           std::vector<std::complex<double>> &v, const std::vector<HostCsr> &Lt) const {
+    const std::complex<double> I(0.0, 1.0);
+    const double sg = adjoint ? -1.0 : 1.0;
+    auto commutator = [&](const HostCsr &M, std::complex<double> f) {
+      // f (M rho - rho M): M kron I and I kron M^T
+      for (int64_t e = M.rp[a]; e < M.rp[a + 1]; ++e) {
+        c.push_back((int64_t)M.col[e] * N + b);
+        v.push_back(f * M.val[e]);
+      }
+      // (rho M)_ab = sum_d rho_ad M_db: column a N + d over M's column b, i.e.
+      // the row b of M^T; M is Hermitian here so M_db = conj(M_bd)
+      for (int64_t e = M.rp[b]; e < M.rp[b + 1]; ++e) {
+        c.push_back(a * N + M.col[e]);
+        v.push_back(-f * std::conj(M.val[e]));
+      }
+    };
+    commutator(H, sg * -I * (1.0 - omega));
+    if (!Hrot.rp.empty()) commutator(Hrot, sg * I * omega);
+    for (size_t k = 0; k < Ls.size(); ++k) {
+      // L rho L^dag -> (L kron conj(L)); for the adjoint L^dag rho L -> (L^dag kron L^T)
+      const HostCsr &A = adjoint ? Lt[k] : Ls[k];
+      for (int64_t e = A.rp[a]; e < A.rp[a + 1]; ++e)
+        for (int64_t f = A.rp[b]; f < A.rp[b + 1]; ++f) {
+          c.push_back((int64_t)A.col[e] * N + A.col[f]);
+          v.push_back(omega * A.val[e] * std::conj(A.val[f]));
+        }
+      // -1/2 {L^dag L, rho}; L^dag L is Hermitian, the same for the adjoint
+      const HostCsr &M = LdLs[k];
+      for (int64_t e = M.rp[a]; e < M.rp[a + 1]; ++e) {
+        c.push_back((int64_t)M.col[e] * N + b);
+        v.push_back(-0.5 * omega * M.val[e]);
+      }
+      for (int64_t e = M.rp[b]; e < M.rp[b + 1]; ++e) {
+        c.push_back(a * N + M.col[e]);
+        v.push_back(-0.5 * omega * std::conj(M.val[e]));
+      }
+    }
+  }
+
+  int64_t max_row(double) const override { return 0; }  // exact lengths are known
+
+  qsw_status_t assemble(bool adjoint, double omega, hipStream_t s, int64_t **rp_out,
+                        int32_t **col_out, double2 **val_out, int64_t *nnz_out) const override {
+    const int64_t n = (int64_t)N * N;
+    std::vector<HostCsr> Lt;
+    if (adjoint)
+      for (const HostCsr &L : Ls) Lt.push_back(conj_transpose(N, L));
+    std::vector<int64_t> rp(n + 1, 0);
+    std::vector<int32_t> col;
+    std::vector<double> val;
+    std::vector<int64_t> c;
+    std::vector<std::complex<double>> v;
+    std::vector<std::pair<int64_t, std::complex<double>>> ent;
+    for (int64_t a = 0; a < N; ++a)
+      for (int64_t b = 0; b < N; ++b) {
+        c.clear();
+        v.clear();
+        row(a, b, omega, adjoint, c, v, Lt);
+        ent.resize(c.size());
+        for (size_t i = 0; i < c.size(); ++i) ent[i] = {c[i], v[i]};
+        std::sort(ent.begin(), ent.end(),
+                  [](const auto &x, const auto &y) { return x.first < y.first; });
+        for (size_t i = 0; i < ent.size();) {
+          std::complex<double> acc = 0.0;
+          size_t j = i;
+          // summed in a fixed order: the sort is by column, ties in term order
+          for (; j < ent.size() && ent[j].first == ent[i].first; ++j) acc += ent[j].second;
+          col.push_back((int32_t)ent[i].first);
+          val.push_back(acc.real());
+          val.push_back(acc.imag());
+          i = j;
+        }
+        rp[a * N + b + 1] = (int64_t)col.size();
+      }
+    const int64_t nnz = (int64_t)col.size();
+    int64_t *drp = nullptr;
+    int32_t *dcol = nullptr;
+    double2 *dval = nullptr;
+    hipError_t e = hipSuccess;
+    do {
+      if ((e = upload(&drp, rp, s)) != hipSuccess) break;
+      if ((e = upload(&dcol, col, s)) != hipSuccess) break;
+      if ((e = dalloc(&dval, (size_t)nnz)) != hipSuccess) break;
+      if (nnz && (e = hipMemcpyAsync(dval, val.data(), val.size() * sizeof(double),
+                                     hipMemcpyHostToDevice, s)) != hipSuccess)
+        break;
+      e = hipStreamSynchronize(s);  // the host vectors must outlive the copies
+    } while (false);
+    if (e != hipSuccess) {
+      dfree(drp);
+      dfree(dcol);
+      dfree(dval);
+      return status_of(e);
+    }
+    *rp_out = drp;
+    *col_out = dcol;
+    *val_out = dval;
+    *nnz_out = nnz;
+    return QSW_OK;
+  }
+};
+
+qsw_status_t build_common(std::shared_ptr<Assembler> src, double omega, hipStream_t s,
+                          qsw_superop_t *out) {
   auto t_start = std::chrono::steady_clock::now();
-  const int32_t N = op.N;
+  const int32_t N = src->order();
   const int64_t n = (int64_t)N * N;
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
@@ -433,21 +793,21 @@ qsw_status_t build_common(HostOps &op, double omega, hipStream_t s, qsw_superop_
   h->N = N;
   h->n = n;
   h->omega = omega;
+  h->src = src;
   auto fail = [&](qsw_status_t st) {
     qsw_superop_destroy(h);
     return st;
   };
-  // K_j = sum_i R_ij over the rates as given (diagonal included)
-  op.K.assign(N, 0.0);
-  for (int32_t i = 0; i < N; ++i) {
-    for (int64_t e = op.rp[i]; e < op.rp[i + 1]; ++e) op.K[op.rc[e]] += op.rv[e];
-    op.K[i] += op.rdiag[i];
-  }
-  qsw_status_t st = assemble(op, false, omega, s, &h->row_ptr, &h->col, &h->val, &h->nnz);
+  qsw_status_t st = src->assemble(false, omega, s, &h->row_ptr, &h->col, &h->val, &h->nnz);
   if (st != QSW_OK) return fail(st);
   // product-kernel layout of L (stream engine unless QSW_ENGINE selects the
   // vector engine with that many lanes per row)
-  const int64_t maxrow = max_row_bound(op);
+  int64_t maxrow = src->max_row(omega);
+  if (maxrow <= 0) {  // read the longest row from the row pointer
+    std::vector<int64_t> rph((size_t)n + 1);
+    HIP_TRY(hipMemcpy(rph.data(), h->row_ptr, rph.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+    for (int64_t r = 0; r < n; ++r) maxrow = std::max(maxrow, rph[r + 1] - rph[r]);
+  }
   const int resident1 = resident_workgroups(0);
   {
     Layout L;
@@ -486,7 +846,7 @@ qsw_status_t build_common(HostOps &op, double omega, hipStream_t s, qsw_superop_
   int32_t *acol = nullptr;
   double2 *aval = nullptr;
   int64_t annz = 0;
-  st = assemble(op, true, omega, s, &arp, &acol, &aval, &annz);
+  st = src->assemble(true, omega, s, &arp, &acol, &aval, &annz);
   if (st != QSW_OK) return fail(st);
   unsigned long long *nbits = nullptr;
   Estimator E{};
@@ -684,14 +1044,14 @@ const char *qsw_status_str(qsw_status_t s) {
 
 const char *qsw_version(void) { return "qsw 0.1 gfx950"; }
 
-qsw_status_t qsw_superop_build(int32_t N, const int64_t *row_ptr, const int32_t *col_idx,
-                               const double *w, double omega, double gamma, uint32_t flags,
-                               void *hip_stream, qsw_superop_t *out) {
-  if (!out || !row_ptr || N < 1) return QSW_ERR_ARG;
-  *out = nullptr;
-  if (!(omega >= 0.0 && omega <= 1.0) || !(gamma > 0.0) || !std::isfinite(gamma)) return QSW_ERR_ARG;
-  if (flags & ~(uint32_t)(QSW_H_ADJACENCY | QSW_R_COLNORM | QSW_DEPHASING)) return QSW_ERR_ARG;
-  if ((int64_t)N * N > (int64_t)std::numeric_limits<int32_t>::max()) return QSW_ERR_SIZE;
+}  // extern "C"
+
+namespace {
+
+// Operators of a walk on a graph (Section 2.4.1): H from G^u, rates from G
+// (eq. generator_matrix, eq. lindblad), as the flags select.
+qsw_status_t graph_ops(int32_t N, const int64_t *row_ptr, const int32_t *col_idx, const double *w,
+                       double gamma, uint32_t flags, HostOps &op) {
   const int64_t E = row_ptr[N];
   if (E > 0 && (!col_idx || !w)) return QSW_ERR_ARG;
   qsw_status_t st = check_csr(N, row_ptr, col_idx, false);
@@ -703,7 +1063,6 @@ qsw_status_t qsw_superop_build(int32_t N, const int64_t *row_ptr, const int32_t 
   std::vector<int32_t> gc(col_idx, col_idx + E), tc;
   std::vector<double> gw(w, w + E), tw;
   transpose_csr(N, gp, gc, gw, 1, tp, tc, tw);
-  HostOps op;
   op.N = N;
   op.hp.assign(N + 1, 0);
   op.hdiag.assign(N, 0.0);
@@ -754,71 +1113,160 @@ qsw_status_t qsw_superop_build(int32_t N, const int64_t *row_ptr, const int32_t 
   if (flags & QSW_DEPHASING)
     for (int32_t j = 0; j < N; ++j)
       op.rdiag[j] = colnorm ? (outdeg[j] > 0.0 ? 1.0 : 0.0) : gamma * outdeg[j];
-  return build_common(op, omega, (hipStream_t)hip_stream, out);
+  return QSW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qsw_status_t qsw_superop_build(int32_t N, const int64_t *row_ptr, const int32_t *col_idx,
+                               const double *w, double omega, double gamma, uint32_t flags,
+                               void *hip_stream, qsw_superop_t *out) {
+  return qsw_superop_build_channels(N, row_ptr, col_idx, w, omega, gamma, flags, 0, nullptr,
+                                    nullptr, 0, nullptr, nullptr, hip_stream, out);
+}
+
+qsw_status_t qsw_superop_build_channels(int32_t N, const int64_t *row_ptr, const int32_t *col_idx,
+                                        const double *w, double omega, double gamma,
+                                        uint32_t flags, int32_t n_sources,
+                                        const int32_t *source_vertex, const double *source_rate,
+                                        int32_t n_sinks, const int32_t *sink_vertex,
+                                        const double *sink_rate, void *hip_stream,
+                                        qsw_superop_t *out) {
+  if (!out || !row_ptr || N < 1 || n_sources < 0 || n_sinks < 0) return QSW_ERR_ARG;
+  *out = nullptr;
+  if (!(omega >= 0.0 && omega <= 1.0) || !(gamma > 0.0) || !std::isfinite(gamma)) return QSW_ERR_ARG;
+  if (flags & ~(uint32_t)(QSW_H_ADJACENCY | QSW_R_COLNORM | QSW_DEPHASING)) return QSW_ERR_ARG;
+  if ((n_sources > 0 && (!source_vertex || !source_rate)) ||
+      (n_sinks > 0 && (!sink_vertex || !sink_rate)))
+    return QSW_ERR_ARG;
+  const int64_t Na = (int64_t)N + n_sources + n_sinks;  // order of the augmented digraph
+  if (Na * Na > (int64_t)std::numeric_limits<int32_t>::max()) return QSW_ERR_SIZE;
+  if (row_ptr[N] > 0 && (!col_idx || !w)) return QSW_ERR_ARG;
+  for (int32_t k = 0; k < n_sources; ++k)
+    if (source_vertex[k] < 0 || source_vertex[k] >= N || !(source_rate[k] > 0.0) ||
+        !std::isfinite(source_rate[k]))
+      return QSW_ERR_GRAPH;
+  for (int32_t k = 0; k < n_sinks; ++k)
+    if (sink_vertex[k] < 0 || sink_vertex[k] >= N || !(sink_rate[k] > 0.0) ||
+        !std::isfinite(sink_rate[k]))
+      return QSW_ERR_GRAPH;
+  HostOps op;
+  qsw_status_t st = graph_ops(N, row_ptr, col_idx, w, gamma, flags, op);
+  if (st != QSW_OK) return st;
+  if (Na > N) {
+    // the augmented digraph: source k is vertex N + k, sink k is vertex
+    // N + n_sources + k; H and the omega rates are zero on them, and the
+    // channels are rates outside omega (eq. qsw_ss)
+    const int32_t M = (int32_t)Na;
+    op.N = M;
+    op.hp.resize(M + 1, op.hp[N]);
+    op.hdiag.resize(M, 0.0);
+    op.rp.resize(M + 1, op.rp[N]);
+    op.rdiag.resize(M, 0.0);
+    std::vector<std::vector<std::pair<int32_t, double>>> rows(M);
+    for (int32_t k = 0; k < n_sources; ++k)  // source N + k -> vertex
+      rows[source_vertex[k]].push_back({N + k, source_rate[k]});
+    for (int32_t k = 0; k < n_sinks; ++k)  // vertex -> sink N + n_sources + k
+      rows[N + n_sources + k].push_back({sink_vertex[k], sink_rate[k]});
+    op.fp.assign(M + 1, 0);
+    op.fdiag.assign(M, 0.0);
+    for (int32_t i = 0; i < M; ++i) {
+      std::sort(rows[i].begin(), rows[i].end());
+      for (size_t t = 0; t < rows[i].size(); ++t) {
+        if (t > 0 && rows[i][t].first == rows[i][t - 1].first) {
+          op.fv.back() += rows[i][t].second;  // two channels on one arc add up
+          continue;
+        }
+        op.fc.push_back(rows[i][t].first);
+        op.fv.push_back(rows[i][t].second);
+      }
+      op.fp[i + 1] = (int64_t)op.fc.size();
+    }
+  }
+  auto src = std::make_shared<LocalAssembler>();
+  src->op = std::move(op);
+  return build_common(src, omega, (hipStream_t)hip_stream, out);
 }
 
 qsw_status_t qsw_superop_build_ops(int32_t N, const int64_t *h_row_ptr, const int32_t *h_col,
                                    const double *h_val, const int64_t *l_row_ptr,
                                    const int32_t *l_col, const double *l_val, double omega,
                                    uint32_t flags, void *hip_stream, qsw_superop_t *out) {
+  return qsw_superop_build_open(N, h_row_ptr, h_col, h_val, l_row_ptr, l_col, l_val, nullptr,
+                                nullptr, nullptr, omega, flags, hip_stream, out);
+}
+
+qsw_status_t qsw_superop_build_open(int32_t N, const int64_t *h_row_ptr, const int32_t *h_col,
+                                    const double *h_val, const int64_t *l_row_ptr,
+                                    const int32_t *l_col, const double *l_val,
+                                    const int64_t *f_row_ptr, const int32_t *f_col,
+                                    const double *f_val, double omega, uint32_t flags,
+                                    void *hip_stream, qsw_superop_t *out) {
   if (!out || !h_row_ptr || !l_row_ptr || N < 1) return QSW_ERR_ARG;
   *out = nullptr;
   if (!(omega >= 0.0 && omega <= 1.0) || flags != 0) return QSW_ERR_ARG;
   if ((int64_t)N * N > (int64_t)std::numeric_limits<int32_t>::max()) return QSW_ERR_SIZE;
-  const int64_t EH = h_row_ptr[N], EL = l_row_ptr[N];
-  if ((EH > 0 && (!h_col || !h_val)) || (EL > 0 && (!l_col || !l_val))) return QSW_ERR_ARG;
-  qsw_status_t st = check_csr(N, h_row_ptr, h_col, true);
-  if (st != QSW_OK) return st;
-  st = check_csr(N, l_row_ptr, l_col, true);
-  if (st != QSW_OK) return st;
   HostOps op;
   op.N = N;
-  op.hp.assign(N + 1, 0);
-  op.hdiag.assign(N, 0.0);
-  for (int32_t i = 0; i < N; ++i) {
-    for (int64_t e = h_row_ptr[i]; e < h_row_ptr[i + 1]; ++e) {
-      const double re = h_val[2 * e], im = h_val[2 * e + 1];
-      if (!std::isfinite(re) || !std::isfinite(im)) return QSW_ERR_GRAPH;
-      if (h_col[e] == i) {
-        if (std::fabs(im) > 1e-14 * (1.0 + std::fabs(re))) return QSW_ERR_GRAPH;  // not Hermitian
-        op.hdiag[i] = re;
-      } else {
-        op.hc.push_back(h_col[e]);
-        op.hv.push_back(re);
-        op.hv.push_back(im);
-      }
-    }
-    op.hp[i + 1] = (int64_t)op.hc.size();
+  qsw_status_t st = parse_hermitian(N, h_row_ptr, h_col, h_val, op);
+  if (st != QSW_OK) return st;
+  st = parse_rates(N, l_row_ptr, l_col, l_val, op.rp, op.rc, op.rv, op.rdiag);
+  if (st != QSW_OK) return st;
+  if (f_row_ptr) {
+    st = parse_rates(N, f_row_ptr, f_col, f_val, op.fp, op.fc, op.fv, op.fdiag);
+    if (st != QSW_OK) return st;
   }
-  // Hermitian pattern and values: H_ji = conj(H_ij)
-  for (int32_t i = 0; i < N; ++i)
-    for (int64_t e = op.hp[i]; e < op.hp[i + 1]; ++e) {
-      const int32_t j = op.hc[e];
-      const auto b = op.hc.begin() + op.hp[j], en = op.hc.begin() + op.hp[j + 1];
-      const auto it = std::lower_bound(b, en, i);
-      if (it == en || *it != i) return QSW_ERR_GRAPH;
-      const int64_t f = it - op.hc.begin();
-      const double tolh = 1e-14 * (1.0 + std::fabs(op.hv[2 * e]) + std::fabs(op.hv[2 * e + 1]));
-      if (std::fabs(op.hv[2 * f] - op.hv[2 * e]) > tolh ||
-          std::fabs(op.hv[2 * f + 1] + op.hv[2 * e + 1]) > tolh)
-        return QSW_ERR_GRAPH;
-    }
-  op.rp.assign(N + 1, 0);
-  op.rdiag.assign(N, 0.0);
-  for (int32_t i = 0; i < N; ++i) {
-    for (int64_t e = l_row_ptr[i]; e < l_row_ptr[i + 1]; ++e) {
-      const double v = l_val[e];
-      if (!std::isfinite(v)) return QSW_ERR_GRAPH;
-      if (l_col[e] == i) {
-        op.rdiag[i] = v * v;
-      } else if (v != 0.0) {
-        op.rc.push_back(l_col[e]);
-        op.rv.push_back(v * v);
-      }
-    }
-    op.rp[i + 1] = (int64_t)op.rc.size();
+  auto src = std::make_shared<LocalAssembler>();
+  src->op = std::move(op);
+  return build_common(src, omega, (hipStream_t)hip_stream, out);
+}
+
+qsw_status_t qsw_superop_build_general(int32_t N, const int64_t *h_row_ptr, const int32_t *h_col,
+                                       const double *h_val, int32_t n_ops,
+                                       const int64_t *const *l_row_ptr,
+                                       const int32_t *const *l_col, const double *const *l_val,
+                                       const int64_t *r_row_ptr, const int32_t *r_col,
+                                       const double *r_val, double omega, void *hip_stream,
+                                       qsw_superop_t *out) {
+  if (!out || !h_row_ptr || N < 1 || n_ops < 0 || (n_ops > 0 && (!l_row_ptr || !l_col || !l_val)))
+    return QSW_ERR_ARG;
+  *out = nullptr;
+  if (!(omega >= 0.0 && omega <= 1.0)) return QSW_ERR_ARG;
+  if ((int64_t)N * N > (int64_t)std::numeric_limits<int32_t>::max()) return QSW_ERR_SIZE;
+  auto src = std::make_shared<GeneralAssembler>();
+  src->N = N;
+  qsw_status_t st = parse_complex(N, h_row_ptr, h_col, h_val, true, src->H);
+  if (st != QSW_OK) return st;
+  if (r_row_ptr) {
+    st = parse_complex(N, r_row_ptr, r_col, r_val, true, src->Hrot);
+    if (st != QSW_OK) return st;
   }
-  return build_common(op, omega, (hipStream_t)hip_stream, out);
+  for (int32_t k = 0; k < n_ops; ++k) {
+    HostCsr L;
+    st = parse_complex(N, l_row_ptr[k], l_col[k], l_val[k], false, L);
+    if (st != QSW_OK) return st;
+    src->LdLs.push_back(product(N, conj_transpose(N, L), L));
+    src->Ls.push_back(std::move(L));
+  }
+  return build_common(src, omega, (hipStream_t)hip_stream, out);
+}
+
+qsw_status_t qsw_superop_set_omega(qsw_superop_t h, double omega, void *hip_stream) {
+  if (!h || !h->src) return QSW_ERR_ARG;
+  if (!(omega >= 0.0 && omega <= 1.0)) return QSW_ERR_ARG;
+  DeviceGuard g(h->device);
+  if (!g.ok) return QSW_ERR_DEVICE;
+  HIP_TRY(hipDeviceSynchronize());  // work in flight may still use the old arrays
+  qsw_superop_t nh = nullptr;
+  qsw_status_t st = build_common(h->src, omega, (hipStream_t)hip_stream, &nh);
+  if (st != QSW_OK) return st;
+  const int prec = h->prec;
+  std::swap(*h, *nh);
+  qsw_superop_destroy(nh);  // the old arrays
+  if (prec == QSW_PREC_SINGLE) return qsw_superop_set_precision(h, prec);
+  return QSW_OK;
 }
 
 void qsw_superop_destroy(qsw_superop_t h) {
