@@ -190,6 +190,38 @@ qsw_status_t qsw_superop_build_general(int32_t N, const int64_t *h_row_ptr, cons
                                        qsw_superop_t *out);
 
 /*
+ * The non-moralising G-QSW of a digraph (Section 2.4.3, graph demoralisation
+ * and eq. nm_gqsw), built on the expanded vertex set: vertex v keeps
+ * d_v = max(1, number of arcs into v) copies (qsw_demoralised_order),
+ * numbered consecutively; copies of joined vertices are linked with weight
+ * G_vw / sqrt(d_v d_w); H_D is the transition matrix of the linked G^u, the
+ * single L_D takes copy u of parent w of v to copy k of v with coefficient
+ * exp(2 pi i k m / d_v) G_vw / sqrt(d_v d_w) (m: rank of w among v's
+ * parents), and H_rot links consecutive copies of a vertex (+i forward, -i
+ * back, cyclic for d_v > 2).  Graph CSR as for qsw_superop_build.  rho0 and
+ * outputs live on the expanded set (qsw_demoralised_state /
+ * _populations map to and from it).  Synchronises `hip_stream`.
+ */
+qsw_status_t qsw_superop_build_demoralised(int32_t N, const int64_t *row_ptr,
+                                           const int32_t *col_idx, const double *w, double omega,
+                                           double gamma, void *hip_stream, qsw_superop_t *out);
+
+/* Host only: order of the expanded vertex set, copies[v] = d_v (copies may
+ * be NULL); -1 for a malformed graph or an order beyond int32. */
+int32_t qsw_demoralised_order(int32_t N, const int64_t *row_ptr, const int32_t *col_idx,
+                              int32_t *copies);
+
+/* Host only: rho (N x N complex128, interleaved) -> V rho V^dag on the
+ * expanded set, V|v> = d_v^(-1/2) sum_k |v^k> (trace and positivity kept). */
+qsw_status_t qsw_demoralised_state(int32_t N, const int32_t *copies, const double *rho,
+                                   double *rho_d);
+
+/* Host only: p(v) = sum over the copies of v (eq. nm_rho_map), for `count`
+ * population vectors of the expanded set (count x M doubles -> count x N). */
+qsw_status_t qsw_demoralised_populations(int32_t N, const int32_t *copies, const double *pops_d,
+                                         int32_t count, double *pops);
+
+/*
  * Rebuild the handle's superoperator for another omega (the paper's
  * set_omega), from the operators it was built from; the handle keeps its
  * identity and precision, and the result is the same as a fresh build at

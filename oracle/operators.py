@@ -203,3 +203,73 @@ def augmented(G: np.ndarray, sources, sinks):
         L[N + len(sources) + k, v] = np.sqrt(rate)
         chans.append(L)
     return Ga, chans
+
+
+def demoralise(G: np.ndarray, gamma: float = 1.0):
+    """The non-moralising construction of Section 2.4.3 (graph demoralisation),
+    dense: returns (copies, H_D, L_D, H_rot) on the expanded vertex set.
+
+    * Vertex v keeps d_v = max(1, number of arcs into v) copies, numbered
+      consecutively (vertex v's copies after those of vertices < v).
+    * Two copies are joined when their vertices are (G^u for H_D, the arcs of
+      G for L_D), with weight G_vw / sqrt(d_v d_w) (eq. nm_weight, the number
+      of joined copy pairs being d_v d_w).
+    * H_D is the transition matrix of that weighted graph (eq. generator_matrix).
+    * L_D takes copy u of a parent w of v to copy k of v with coefficient
+      F_v[k, m] G^D_vw, m the rank of w among v's parents and F_v the Fourier
+      matrix exp(2 pi i k m / d_v) (unit-modulus entries) (eq. dm_lind).
+    * H_rot couples consecutive copies of one vertex: +i from copy k to k+1,
+      -i back (eq. H_rot), cyclically when d_v > 2.
+    """
+    G = np.asarray(G, dtype=float)
+    N = G.shape[0]
+    parents = [np.nonzero(G[v, :])[0] for v in range(N)]
+    d = np.array([max(1, len(p)) for p in parents])
+    off = np.concatenate([[0], np.cumsum(d)])
+    M = int(off[-1])
+    Gu = undirected(G)
+    A = np.zeros((M, M))
+    for v in range(N):
+        for w in range(N):
+            if Gu[v, w] != 0:
+                A[off[v]:off[v + 1], off[w]:off[w + 1]] = Gu[v, w] / np.sqrt(d[v] * d[w])
+    H_D = transition_matrix(gamma, A)
+    L_D = np.zeros((M, M), np.complex128)
+    for v in range(N):
+        F = np.exp(2j * np.pi * np.outer(np.arange(d[v]), np.arange(d[v])) / d[v])
+        for m, w in enumerate(parents[v]):
+            g = G[v, w] / np.sqrt(d[v] * d[w])
+            for k in range(d[v]):
+                for u in range(d[w]):
+                    L_D[off[v] + k, off[w] + u] = F[k, m] * g
+    H_rot = np.zeros((M, M), np.complex128)
+    for v in range(N):
+        if d[v] < 2:
+            continue
+        links = [(k, k + 1) for k in range(d[v] - 1)]
+        if d[v] > 2:
+            links.append((d[v] - 1, 0))
+        for k, l in links:
+            H_rot[off[v] + l, off[v] + k] = 1j
+            H_rot[off[v] + k, off[v] + l] = -1j
+    return d, H_D, L_D, H_rot
+
+
+def demoralised_state(rho: np.ndarray, copies) -> np.ndarray:
+    """rho on the graph -> V rho V^dag with V|v> = d_v^(-1/2) sum_k |v^k>:
+    trace and positivity kept, populations spread evenly over the copies."""
+    N = rho.shape[0]
+    d = np.asarray(copies)
+    off = np.concatenate([[0], np.cumsum(d)])
+    V = np.zeros((int(off[-1]), N))
+    for v in range(N):
+        V[off[v]:off[v + 1], v] = 1.0 / np.sqrt(d[v])
+    return V @ rho @ V.T
+
+
+def demoralised_populations(rho_d: np.ndarray, copies) -> np.ndarray:
+    """p(v) = sum over the copies of v of the diagonal (eq. nm_rho_map)."""
+    d = np.asarray(copies)
+    off = np.concatenate([[0], np.cumsum(d)])
+    diag = np.real(np.diag(rho_d))
+    return np.array([diag[off[v]:off[v + 1]].sum() for v in range(d.size)])

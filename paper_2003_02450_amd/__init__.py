@@ -169,6 +169,27 @@ class Superop:
         _lib.check(st, "qsw_superop_build_general")
         return cls(h, dev)
 
+    @classmethod
+    def from_demoralised(cls, graph, omega, gamma=1.0, device=None):
+        """The non-moralising G-QSW of a digraph (Section 2.4.3) on its
+        expanded vertex set; `copies` (d_v per vertex) maps states and
+        populations (demoralised_state / demoralised_populations)."""
+        torch = _torch()
+        L = _lib.load()
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        rp = np.ascontiguousarray(graph.row_ptr, np.int64)
+        ci = np.ascontiguousarray(graph.col_idx, np.int32)
+        ww = np.ascontiguousarray(graph.w, np.float64)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(dev):
+            st = L.qsw_superop_build_demoralised(int(graph.N), _ptr(rp), _ptr(ci), _ptr(ww),
+                                                 float(omega), float(gamma), _stream(dev),
+                                                 ctypes.byref(h))
+        _lib.check(st, "qsw_superop_build_demoralised")
+        op = cls(h, dev)
+        op.copies = demoralised_copies(graph)
+        return op
+
     def set_omega(self, omega):
         """Rebuild for another omega (the paper's set_omega)."""
         torch = _torch()
@@ -489,6 +510,43 @@ def batch_propagate(walks, rhs=None, workspace=None):
         _lib.check(st, "qsw_batch_propagate")
     return {"cycles": st_out.cycles, "products": st_out.products, "live": st_out.live,
             "nonfinite": bool(st_out.nonfinite), "ms": st_out.ms, "workspace_bytes": need}
+
+
+# ------------------------------------------------------- demoralisation
+
+def demoralised_copies(graph) -> np.ndarray:
+    """d_v = max(1, number of arcs into v): copies of each vertex (host)."""
+    rp = np.ascontiguousarray(graph.row_ptr, np.int64)
+    ci = np.ascontiguousarray(graph.col_idx, np.int32)
+    d = np.empty(int(graph.N), np.int32)
+    M = _lib.load().qsw_demoralised_order(int(graph.N), _ptr(rp), _ptr(ci), _ptr(d))
+    if M < 0:
+        raise QswError(2, "qsw_demoralised_order")
+    return d
+
+
+def demoralised_state(rho, copies) -> np.ndarray:
+    """rho (N x N) -> the expanded set's density matrix (host)."""
+    rho = np.ascontiguousarray(rho, np.complex128)
+    copies = np.ascontiguousarray(copies, np.int32)
+    M = int(copies.sum())
+    out = np.empty((M, M), np.complex128)
+    _lib.check(_lib.load().qsw_demoralised_state(copies.size, _ptr(copies),
+                                                 _ptr(rho.view(np.float64)),
+                                                 _ptr(out.view(np.float64))),
+               "qsw_demoralised_state")
+    return out
+
+
+def demoralised_populations(pops_d, copies) -> np.ndarray:
+    """[count, M] populations of the expanded set -> [count, N] (host)."""
+    p = np.ascontiguousarray(np.atleast_2d(pops_d), np.float64)
+    copies = np.ascontiguousarray(copies, np.int32)
+    out = np.empty((p.shape[0], copies.size), np.float64)
+    _lib.check(_lib.load().qsw_demoralised_populations(copies.size, _ptr(copies), _ptr(p),
+                                                       p.shape[0], _ptr(out)),
+               "qsw_demoralised_populations")
+    return out
 
 
 # ---------------------------------------------------- continuous batching

@@ -23,6 +23,8 @@ QSW_PREC_SINGLE = 1
 # Every function the header declares, for the export check.
 EXPORTED = ("qsw_superop_build", "qsw_superop_build_ops", "qsw_superop_build_channels",
             "qsw_superop_build_open", "qsw_superop_build_general", "qsw_superop_set_omega",
+            "qsw_superop_build_demoralised", "qsw_demoralised_order", "qsw_demoralised_state",
+            "qsw_demoralised_populations",
             "qsw_superop_destroy",
             "qsw_superop_info", "qsw_superop_set_precision", "qsw_superop_autotune",
             "qsw_superop_copy_csr", "qsw_propagate_workspace_bytes",
@@ -113,6 +115,15 @@ def load() -> ctypes.CDLL:
     L.qsw_superop_build_general.restype = _i32
     L.qsw_superop_build_general.argtypes = [_i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp,
                                             _vp, _dbl, _vp, ctypes.POINTER(_vp)]
+    L.qsw_superop_build_demoralised.restype = _i32
+    L.qsw_superop_build_demoralised.argtypes = [_i32, _vp, _vp, _vp, _dbl, _dbl, _vp,
+                                                ctypes.POINTER(_vp)]
+    L.qsw_demoralised_order.restype = _i32
+    L.qsw_demoralised_order.argtypes = [_i32, _vp, _vp, _vp]
+    L.qsw_demoralised_state.restype = _i32
+    L.qsw_demoralised_state.argtypes = [_i32, _vp, _vp, _vp]
+    L.qsw_demoralised_populations.restype = _i32
+    L.qsw_demoralised_populations.argtypes = [_i32, _vp, _vp, _i32, _vp]
     L.qsw_superop_set_omega.restype = _i32
     L.qsw_superop_set_omega.argtypes = [_vp, _dbl, _vp]
     L.qsw_superop_destroy.restype = None

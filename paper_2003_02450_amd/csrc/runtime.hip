@@ -1253,6 +1253,190 @@ qsw_status_t qsw_superop_build_general(int32_t N, const int64_t *h_row_ptr, cons
   return build_common(src, omega, (hipStream_t)hip_stream, out);
 }
 
+int32_t qsw_demoralised_order(int32_t N, const int64_t *row_ptr, const int32_t *col_idx,
+                              int32_t *copies) {
+  if (!row_ptr || N < 1 || (row_ptr[N] > 0 && !col_idx)) return -1;
+  if (check_csr(N, row_ptr, col_idx, false) != QSW_OK) return -1;
+  int64_t M = 0;
+  for (int32_t v = 0; v < N; ++v) {
+    const int64_t d = std::max<int64_t>(1, row_ptr[v + 1] - row_ptr[v]);  // parents of v
+    if (copies) copies[v] = (int32_t)d;
+    M += d;
+  }
+  return M > std::numeric_limits<int32_t>::max() ? -1 : (int32_t)M;
+}
+
+qsw_status_t qsw_superop_build_demoralised(int32_t N, const int64_t *row_ptr,
+                                           const int32_t *col_idx, const double *w, double omega,
+                                           double gamma, void *hip_stream, qsw_superop_t *out) {
+  if (!out || !row_ptr || N < 1) return QSW_ERR_ARG;
+  *out = nullptr;
+  if (!(omega >= 0.0 && omega <= 1.0) || !(gamma > 0.0) || !std::isfinite(gamma)) return QSW_ERR_ARG;
+  const int64_t E = row_ptr[N];
+  if (E > 0 && (!col_idx || !w)) return QSW_ERR_ARG;
+  qsw_status_t st = check_csr(N, row_ptr, col_idx, false);
+  if (st != QSW_OK) return st;
+  for (int64_t e = 0; e < E; ++e)
+    if (!(w[e] > 0.0) || !std::isfinite(w[e])) return QSW_ERR_GRAPH;
+  std::vector<int32_t> d(N);
+  const int32_t M = qsw_demoralised_order(N, row_ptr, col_idx, d.data());
+  if (M < 0) return QSW_ERR_SIZE;
+  if ((int64_t)M * M > (int64_t)std::numeric_limits<int32_t>::max()) return QSW_ERR_SIZE;
+  std::vector<int64_t> off(N + 1, 0);
+  for (int32_t v = 0; v < N; ++v) off[v + 1] = off[v] + d[v];
+  // G^u = max(G, G^T)
+  std::vector<int64_t> gp(row_ptr, row_ptr + N + 1), tp;
+  std::vector<int32_t> gc(col_idx, col_idx + E), tc;
+  std::vector<double> gw(w, w + E), tw;
+  transpose_csr(N, gp, gc, gw, 1, tp, tc, tw);
+  std::vector<std::vector<std::pair<int32_t, double>>> urow(N);
+  for (int32_t v = 0; v < N; ++v) {
+    int64_t a = gp[v], b = tp[v];
+    while (a < gp[v + 1] || b < tp[v + 1]) {
+      const int32_t ca = a < gp[v + 1] ? gc[a] : INT32_MAX;
+      const int32_t cb = b < tp[v + 1] ? tc[b] : INT32_MAX;
+      if (ca == cb) {
+        urow[v].push_back({ca, std::max(gw[a++], tw[b++])});
+      } else if (ca < cb) {
+        urow[v].push_back({ca, gw[a++]});
+      } else {
+        urow[v].push_back({cb, tw[b++]});
+      }
+    }
+  }
+  auto src = std::make_shared<GeneralAssembler>();
+  src->N = M;
+  // H_D: transition matrix (eq. generator_matrix) of the demoralised graph,
+  // copies joined with weight G^u_vw / sqrt(d_v d_w) (eq. nm_weight)
+  {
+    std::vector<std::vector<std::pair<int32_t, std::complex<double>>>> rows(M);
+    std::vector<double> deg(M, 0.0);
+    for (int32_t v = 0; v < N; ++v)
+      for (const auto &[u, gu] : urow[v]) {
+        const double wd = gu / std::sqrt((double)d[v] * d[u]);
+        for (int32_t k = 0; k < d[v]; ++k)
+          for (int32_t l = 0; l < d[u]; ++l) {
+            rows[off[v] + k].push_back({(int32_t)(off[u] + l), -gamma * wd});
+            deg[off[u] + l] += wd;
+          }
+      }
+    for (int32_t i = 0; i < M; ++i) rows[i].push_back({i, gamma * deg[i]});
+    HostCsr &H = src->H;
+    H.rp.assign(M + 1, 0);
+    for (int32_t i = 0; i < M; ++i) {
+      std::sort(rows[i].begin(), rows[i].end(),
+                [](const auto &x, const auto &y) { return x.first < y.first; });
+      for (const auto &e : rows[i]) {
+        H.col.push_back(e.first);
+        H.val.push_back(e.second);
+      }
+      H.rp[i + 1] = (int64_t)H.col.size();
+    }
+  }
+  // L_D (eq. dm_lind): copy u of parent w of v -> copy k of v with
+  // F_v[k][m] G_vw / sqrt(d_v d_w), m the rank of w among v's parents and F_v
+  // the Fourier matrix exp(2 pi i k m / d_v) with unit-modulus entries
+  {
+    const double pi = std::acos(-1.0);
+    std::vector<std::vector<std::pair<int32_t, std::complex<double>>>> rows(M);
+    for (int32_t v = 0; v < N; ++v)
+      for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+        const int32_t wv = col_idx[e];
+        const int32_t m = (int32_t)(e - row_ptr[v]);
+        const double g = w[e] / std::sqrt((double)d[v] * d[wv]);
+        for (int32_t k = 0; k < d[v]; ++k) {
+          const double ang = 2.0 * pi * (double)((int64_t)k * m % d[v]) / (double)d[v];
+          const std::complex<double> f(std::cos(ang), std::sin(ang));
+          for (int32_t u = 0; u < d[wv]; ++u) rows[off[v] + k].push_back({(int32_t)(off[wv] + u), f * g});
+        }
+      }
+    HostCsr L;
+    L.rp.assign(M + 1, 0);
+    for (int32_t i = 0; i < M; ++i) {
+      std::sort(rows[i].begin(), rows[i].end(),
+                [](const auto &x, const auto &y) { return x.first < y.first; });
+      for (const auto &e : rows[i]) {
+        L.col.push_back(e.first);
+        L.val.push_back(e.second);
+      }
+      L.rp[i + 1] = (int64_t)L.col.size();
+    }
+    src->LdLs.push_back(product(M, conj_transpose(M, L), L));
+    src->Ls.push_back(std::move(L));
+  }
+  // H_rot (eq. H_rot): +i from copy k to copy k+1 of one vertex, -i back;
+  // cyclic (k = d-1 to 0) when d > 2
+  {
+    std::vector<std::vector<std::pair<int32_t, std::complex<double>>>> rows(M);
+    bool any = false;
+    for (int32_t v = 0; v < N; ++v) {
+      if (d[v] < 2) continue;
+      any = true;
+      for (int32_t k = 0; k < d[v]; ++k) {
+        const int32_t l = (k + 1) % d[v];
+        if (d[v] == 2 && k == 1) break;  // the single pair of two copies
+        rows[off[v] + l].push_back({(int32_t)(off[v] + k), std::complex<double>(0.0, 1.0)});
+        rows[off[v] + k].push_back({(int32_t)(off[v] + l), std::complex<double>(0.0, -1.0)});
+      }
+    }
+    if (any) {
+      HostCsr &R = src->Hrot;
+      R.rp.assign(M + 1, 0);
+      for (int32_t i = 0; i < M; ++i) {
+        std::sort(rows[i].begin(), rows[i].end(),
+                  [](const auto &x, const auto &y) { return x.first < y.first; });
+        for (const auto &e : rows[i]) {
+          R.col.push_back(e.first);
+          R.val.push_back(e.second);
+        }
+        R.rp[i + 1] = (int64_t)R.col.size();
+      }
+    }
+  }
+  return build_common(src, omega, (hipStream_t)hip_stream, out);
+}
+
+qsw_status_t qsw_demoralised_state(int32_t N, const int32_t *copies, const double *rho,
+                                   double *rho_d) {
+  if (!copies || !rho || !rho_d || N < 1) return QSW_ERR_ARG;
+  std::vector<int64_t> off(N + 1, 0);
+  for (int32_t v = 0; v < N; ++v) {
+    if (copies[v] < 1) return QSW_ERR_ARG;
+    off[v + 1] = off[v] + copies[v];
+  }
+  const int64_t M = off[N];
+  for (int32_t a = 0; a < N; ++a)
+    for (int32_t b = 0; b < N; ++b) {
+      const double f = 1.0 / std::sqrt((double)copies[a] * copies[b]);
+      const double re = rho[2 * ((int64_t)a * N + b)] * f, im = rho[2 * ((int64_t)a * N + b) + 1] * f;
+      for (int64_t i = off[a]; i < off[a + 1]; ++i)
+        for (int64_t j = off[b]; j < off[b + 1]; ++j) {
+          rho_d[2 * (i * M + j)] = re;
+          rho_d[2 * (i * M + j) + 1] = im;
+        }
+    }
+  return QSW_OK;
+}
+
+qsw_status_t qsw_demoralised_populations(int32_t N, const int32_t *copies, const double *pops_d,
+                                         int32_t count, double *pops) {
+  if (!copies || !pops_d || !pops || N < 1 || count < 0) return QSW_ERR_ARG;
+  int64_t M = 0;
+  for (int32_t v = 0; v < N; ++v) {
+    if (copies[v] < 1) return QSW_ERR_ARG;
+    M += copies[v];
+  }
+  for (int32_t t = 0; t < count; ++t) {
+    int64_t i = 0;
+    for (int32_t v = 0; v < N; ++v) {
+      double p = 0.0;
+      for (int32_t k = 0; k < copies[v]; ++k) p += pops_d[t * M + i++];
+      pops[(int64_t)t * N + v] = p;
+    }
+  }
+  return QSW_OK;
+}
+
 qsw_status_t qsw_superop_set_omega(qsw_superop_t h, double omega, void *hip_stream) {
   if (!h || !h->src) return QSW_ERR_ARG;
   if (!(omega >= 0.0 && omega <= 1.0)) return QSW_ERR_ARG;

@@ -139,3 +139,37 @@ def test_set_omega_equals_fresh_build(kind):
     assert np.array_equal(_run(op, rho0, 0.0, 0.5, 4), _run(fresh, rho0, 0.0, 0.5, 4))
     op.close()
     fresh.close()
+
+
+@pytest.mark.parametrize("omega", [0.0, 0.6, 1.0])
+def test_demoralised_matches_oracle(omega):
+    import paper_2003_02450_amd as qsw
+    rng = np.random.Generator(np.random.PCG64(75))
+    g = workloads.random_out_degree(5, 2, rng)
+    op = qsw.Superop.from_demoralised(g, omega)
+    d, HD, LD, Hr = operators.demoralise(g.dense())
+    assert (op.copies == d).all() and op.N == int(d.sum())
+    A = oracle.general_superop(HD, [LD], omega, Hr)
+    rho0 = qsw.demoralised_state(workloads.random_density(5, rng, rank=2), op.copies)
+    got = _run(op, rho0, 0.0, 0.7, 5)
+    ref, _ = expmv.propagate(A, rho0, 0.0, 0.7, 5)
+    assert np.abs(got - ref).max() <= TOL
+    pops = qsw.demoralised_populations(np.real(np.einsum("kaa->ka", got)), op.copies)
+    assert np.abs(pops.sum(axis=1) - 1).max() < 1e-12
+    op.close()
+
+
+def test_nm_gqsw_example_through_gpu():
+    import paper_2003_02450_amd as qsw
+    gold = json.load(open(os.path.join(GOLDEN, "nm_gqsw_example.json")))
+    g = workloads.graph_from_arcs(3, [2, 2], [0, 1], [1.0, 1.0])
+    for omega, key in ((1.0, "omega_1"), (0.0, "omega_0")):
+        op = qsw.Superop.from_demoralised(g, omega)
+        rho0 = qsw.demoralised_state(np.diag([1.0, 0.0, 0.0]).astype(complex), op.copies)
+        got = _run(op, rho0, 0.0, gold["t"], 1)
+        p = qsw.demoralised_populations(np.real(np.diag(got[1])), op.copies)[0]
+        printed = np.array(gold["printed_populations"][key])
+        assert np.abs(p - printed).max() < 5e-9, (key, p)
+        if omega == 1.0:
+            assert abs(p[0] - np.exp(-100.0)) < 1e-6 * np.exp(-100.0)
+        op.close()

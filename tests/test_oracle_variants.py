@@ -96,3 +96,86 @@ def test_dimer_with_source_and_sink_invariants():
         assert np.real(np.diag(out[k])).min() > -1e-12
     assert all(b >= a - 1e-14 for a, b in zip(sink, sink[1:]))
     assert sink[-1] > 1 - 1e-8
+
+
+# ------------------------------------------------------------- demoralisation
+
+def _nm_example():
+    gold = json.load(open(os.path.join(GOLDEN, "nm_gqsw_example.json")))
+    G = np.zeros((3, 3))
+    for i, j in gold["graph_arcs_target_source"]:
+        G[i, j] = 1.0
+    return gold, G
+
+
+def _nm_run(G, omega, t):
+    d, HD, LD, Hr = operators.demoralise(G)
+    A = oracle.general_superop(HD, [LD], omega, Hr)
+    rho0 = operators.demoralised_state(np.diag([1.0, 0.0, 0.0]).astype(complex), d)
+    out, _ = expmv.propagate(A, rho0, 0.0, t, 1)
+    return d, operators.demoralised_populations(out[1], d)
+
+
+def test_nm_gqsw_omega1_printed():
+    """At omega = 1 nothing flows into v0, which loses population at the rate
+    ||L_D |v0>||^2 = 1: p0 = e^-100, the printed 3.72007598e-44; v2 ends with
+    everything (no spontaneous moralisation into v1)."""
+    gold, G = _nm_example()
+    d, p = _nm_run(G, 1.0, gold["t"])
+    assert list(d) == [1, 1, 2]
+    printed = gold["printed_populations"]["omega_1"]
+    assert abs(p[0] - np.exp(-100.0)) < 1e-8 * np.exp(-100.0)
+    assert abs(p[0] - printed[0]) < 5e-9 * printed[0]
+    assert abs(p[1]) < 1e-30 and abs(p[2] - 1.0) < 1e-12
+
+
+def test_nm_gqsw_omega0_closed_form_and_printed():
+    """At omega = 0 the expanded graph's Laplacian has a uniform diagonal and
+    v0, v1 couple to the symmetric copy of v2 with strength 1: populations are
+    those of the CTQW on the star (cos^4, sin^4, sin^2(sqrt2 t)/2)."""
+    gold, G = _nm_example()
+    _, p = _nm_run(G, 0.0, gold["t"])
+    t = gold["t"]
+    closed = np.array([np.cos(t / np.sqrt(2)) ** 4, np.sin(t / np.sqrt(2)) ** 4,
+                       0.5 * np.sin(np.sqrt(2) * t) ** 2])
+    assert np.abs(p - closed).max() < 5e-12
+    printed = np.array(gold["printed_populations"]["omega_0"])
+    assert np.abs(p - printed).max() < 5e-9
+
+
+def test_demoralised_operators_structure():
+    rng = np.random.Generator(np.random.PCG64(63))
+    G = workloads.random_out_degree(6, 2, rng).dense()
+    d, HD, LD, Hr = operators.demoralise(G)
+    indeg = (G != 0).sum(axis=1)
+    assert (d == np.maximum(1, indeg)).all()
+    assert np.abs(HD - HD.conj().T).max() < 1e-14
+    assert np.abs(Hr - Hr.conj().T).max() < 1e-14
+    # each parent w of v reaches v's copies through its own Fourier column:
+    # the images of two different parents are orthogonal (no moralisation)
+    off = np.concatenate([[0], np.cumsum(d)])
+    for v in range(G.shape[0]):
+        par = np.nonzero(G[v])[0]
+        cols = [LD[off[v]:off[v + 1], off[w]] for w in par]
+        for a in range(len(cols)):
+            for b in range(a + 1, len(cols)):
+                assert abs(np.vdot(cols[a], cols[b])) < 1e-12
+    rho = workloads.random_density(6, rng, rank=2)
+    rd = operators.demoralised_state(rho, d)
+    assert abs(np.trace(rd) - 1) < 1e-14
+    assert np.abs(operators.demoralised_populations(rd, d) - np.real(np.diag(rho))).max() < 1e-14
+
+
+def test_library_host_maps_match_oracle():
+    """The library's host-only demoralisation maps (no GPU needed)."""
+    import paper_2003_02450_amd as qsw
+    rng = np.random.Generator(np.random.PCG64(64))
+    g = workloads.random_out_degree(7, 2, rng)
+    d_lib = qsw.demoralised_copies(g)
+    d, *_ = operators.demoralise(g.dense())
+    assert (d_lib == d).all()
+    rho = workloads.random_density(7, rng, rank=3)
+    assert np.abs(qsw.demoralised_state(rho, d_lib) - operators.demoralised_state(rho, d)).max() < 1e-15
+    pd = rng.random((3, int(d.sum())))
+    ref = np.stack([operators.demoralised_populations(np.diag(x), d) for x in pd])
+    assert np.abs(qsw.demoralised_populations(pd, d_lib) - ref).max() < 1e-14
