@@ -10,9 +10,12 @@ the workspace are resident before the timed region starts.
 
 Prints one JSON line.  `value` is rho(t) grid steps per second of the whole
 pass.  `roofline` rates the fused Taylor-term product kernel: algorithmic
-bytes of the products it computed (20 nnz + 8 (n+1) + 64 n per product)
-over the device time of the timed propagate calls, measured with HIP events
-on the stream the kernels run on.  `single_values` repeats the pass with
+bytes of the products it computed (per product 12 nnz + 8 (n+1) + 16 n +
+64 n with phase-split values: one real coefficient and a column per entry,
+row data, the complex diagonal per row, x, the term and the accumulator;
+20 nnz + 8 (n+1) + 64 n with complex values) over the device time of the
+timed propagate calls, measured with HIP events on the stream the kernels
+run on.  `single_values` repeats the pass with
 the superoperator values stored as complex64 and the 2^-24 tolerance
 (vectors and sums stay double) and reports its rate, its product kernel's
 bandwidth and its largest deviation from the double pass.  `batched` runs 64
@@ -61,13 +64,17 @@ def measured_traffic():
         return None
 
 
-def term_bytes(n: int, nnz: int, value_bytes: int = 16, series: bool = False) -> float:
-    """Algorithmic HBM bytes of one Taylor-term product: values and column
-    indices (16 + 4 per entry, 8 + 4 with complex64 values), row pointers, x
-    gathered once, the new term written, the accumulator read and written
-    (the time-series branch writes the power and accumulates in a second
-    pass: 16 n more)."""
-    return (value_bytes + 4.0) * nnz + 8.0 * (n + 1) + (80.0 if series else 64.0) * n
+def term_bytes(n: int, nnz: int, split: bool, single: bool, series: bool = False) -> float:
+    """Algorithmic HBM bytes of one Taylor-term product (the library's own
+    qsw_stats_t.bytes per product): column index and value per entry (4 + 8
+    phase-split double, 4 + 4 phase-split single, 4 + 16 / 4 + 8 complex),
+    row data 8 (n+1), the diagonal per row with phase-split values (16 or
+    8 n), x gathered once, the new term written, the accumulator read and
+    written (the time-series branch writes the power and accumulates in a
+    second pass: 16 n more)."""
+    entry = (8.0 if single else 12.0) if split else (12.0 if single else 20.0)
+    diag = (8.0 if single else 16.0) if split else 0.0
+    return entry * nnz + 8.0 * (n + 1) + (diag + (80.0 if series else 64.0)) * n
 
 
 def cpu_baseline(wl, sample_steps: int) -> dict:
@@ -111,7 +118,8 @@ def single_leg(args, one_pass, out64, torch, n, nnz, q, wl) -> dict:
     products = sum(s["products"] for s, _ in stats)
     launched = sum(s["launched"] for s, _ in stats)
     st0, info0 = stats[0]
-    per = term_bytes(n, nnz, 8, st0["branch"] == 1)
+    per = term_bytes(n, nnz, info0["split"], True, st0["branch"] == 1)
+    assert abs(per * products - sum(s["bytes"] for s, _ in stats)) <= 1e-6 * per * products
     achieved = products * per / (prop_ms * 1e-3) / 1e9
     diff = float((out32 - out64).abs().max().item())
     bound = 2.0 * 2.0 ** -24 * (q * wl.dt) * info0["norm1"] * float(abs(wl.rho0).sum())
@@ -119,6 +127,7 @@ def single_leg(args, one_pass, out64, torch, n, nnz, q, wl) -> dict:
             "ms_per_step": 1e3 * elapsed / args.steps, "dtype": "c64 values, f64 vectors",
             "m": st0["m"], "s": st0["s"],
             "branch": "single-time per interval" if st0["branch"] == 0 else "series",
+            "values": "phase-split f32" if info0["split"] else "complex64",
             "propagate_ms": round(prop_ms / args.steps, 3),
             "products_per_step": products // args.steps,
             "term_launches_per_step": launched // args.steps,
@@ -304,7 +313,10 @@ def main() -> int:
     products = sum(s["products"] for s, _ in stats)
     launched = sum(s["launched"] for s, _ in stats)
     build_ms = sum(i["build_ms"] for _, i in stats) / len(stats)
-    bytes_total = products * term_bytes(n, nnz)
+    split = stats[0][1]["split"]
+    per_product = term_bytes(n, nnz, split, False)
+    bytes_total = products * per_product
+    assert abs(bytes_total - sum(s["bytes"] for s, _ in stats)) <= 1e-6 * bytes_total
     achieved = bytes_total / (prop_ms * 1e-3) / 1e9
     st0 = stats[0][0]
 
@@ -326,14 +338,18 @@ def main() -> int:
                                "rho0=|0><0|, t=0..50 (51 points)",
                    "n": n, "nnz": nnz, "m": st0["m"], "s": st0["s"],
                    "branch": "single-time per interval" if st0["branch"] == 0 else "series",
+                   "values": "phase-split" if split else "complex",
                    "build_ms": round(build_ms, 3),
                    "propagate_ms": round(prop_ms / args.steps, 3),
                    "products_per_step": products // args.steps,
                    "term_launches_per_step": launched // args.steps},
-        "roofline": {"bound": "hbm", "kernel": "term_kernel<100> (CSR product + Taylor epilogue)",
+        "roofline": {"bound": "hbm",
+                     "kernel": (f"term_kernel<{110 if split else 100}> (CSR product + Taylor "
+                                "epilogue, rho-row staged in LDS, "
+                                f"{'phase-split' if split else 'complex'} values)"),
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(),
-                     "bytes_per_product": term_bytes(n, nnz),
+                     "bytes_per_product": per_product,
                      "avg_launch_us": 1e3 * prop_ms / max(launched, 1),
                      "avg_product_us": 1e3 * prop_ms / max(products, 1)},
     }

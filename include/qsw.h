@@ -77,6 +77,10 @@ typedef struct {
     int32_t d_probe[10]; /* for d_index == -1: which probe column (0 = all-ones/n, 1 = +-1/n) */
     int32_t norm_products; /* sparse products spent on the estimates */
     double build_ms;     /* host wall time of the build call, including device sync */
+    int32_t split;       /* 1: the product kernels read phase-split values (every
+                            off-diagonal entry real or imaginary: one real coefficient
+                            per entry, its phase in the column index, the complex
+                            diagonal per row); 0: complex values */
 } qsw_info_t;
 
 typedef struct {
@@ -90,8 +94,10 @@ typedef struct {
     int32_t nonfinite;   /* 1 if any norm in the run was NaN or infinite */
     double ms;           /* device time of the last propagate call (events on its stream) */
     double bytes;        /* algorithmic HBM bytes of the computed products: per product
-                            (20 or 12) nnz + 8 (n+1) + (64 or 80) n for double or single
-                            values and branch 0 or 1 (branch 1 adds the accumulation pass) */
+                            E nnz + 8 (n+1) + D n + (64 or 80) n for branch 0 or 1 (branch 1
+                            adds the accumulation pass), with (E, D) = (20, 0) / (12, 0) for
+                            complex double / single values and (12, 16) / (8, 8) for
+                            phase-split double / single values (D: the diagonal per row) */
     int32_t prec;        /* QSW_PREC_* the call ran with */
 } qsw_stats_t;
 
@@ -236,10 +242,11 @@ qsw_status_t qsw_superop_info(qsw_superop_t h, qsw_info_t *info);
 /*
  * Precision of later qsw_propagate calls on this handle (default
  * QSW_PREC_DOUBLE).
- *   QSW_PREC_SINGLE: the product kernels read a complex64 copy of the
- *     superoperator values (each component rounded to nearest; made here, 8
- *     bytes per entry of device memory, kept until QSW_PREC_DOUBLE is set or
- *     the handle is destroyed), theta_m and the stopping test use
+ *   QSW_PREC_SINGLE: the product kernels read a single-precision copy of the
+ *     superoperator values (each real and imaginary part rounded to nearest;
+ *     made here, 8 bytes per entry of device memory for complex values, 4 per
+ *     entry and 8 per row for phase-split values, kept until QSW_PREC_DOUBLE
+ *     is set or the handle is destroyed), theta_m and the stopping test use
  *     u = 2^-24 (Al-Mohy and Higham's single-precision choice), and vectors,
  *     products, sums and norms stay complex128 / double.  rho(t) then carries
  *     a backward error of at most about 2 u ||L||_1 per unit time (value
@@ -254,7 +261,9 @@ qsw_status_t qsw_superop_set_precision(qsw_superop_t h, int32_t prec);
 
 /* Launch configuration of the product kernels, as chosen by qsw_superop_autotune. */
 typedef struct {
-    int32_t staged;          /* 1: the rho-row is staged in LDS for the rho H gathers */
+    int32_t staged;          /* 1: the rho-row is staged in LDS for the rho H gathers;
+                                2: staged, and each XCD takes one band of columns of rho
+                                (N = 512, 1024 or 2048) */
     int32_t grid;            /* workgroups per product launch */
     double us_per_product;   /* measured time of one product in that configuration */
     int32_t from_cache;      /* 1: taken from an earlier tuning of the same key */
@@ -262,8 +271,9 @@ typedef struct {
 
 /*
  * Time the product kernel on this handle for each launch configuration
- * (rho-row staging on and off where N*16 bytes fit, grid of 1, 2, 4 and 8
- * times the resident workgroups), keep the fastest for later qsw_propagate /
+ * (rho-row staging off, on where N*16 bytes fit, and with XCD column bands
+ * where N allows; grid of 1, 2, 4 and 8 times the resident workgroups),
+ * keep the fastest for later qsw_propagate /
  * qsw_apply calls and remember it for the key (N, entries per row, precision)
  * in the process, so that later handles with the same key take it without
  * timing.  No configuration changes any sum's order: results are bitwise

@@ -250,7 +250,8 @@ class Superop:
                 "d": {p: i.d[p] for p in range(2, 10)},
                 "d_index": {p: i.d_index[p] for p in range(2, 10)},
                 "d_probe": {p: i.d_probe[p] for p in range(2, 10)},
-                "norm_products": i.norm_products, "build_ms": i.build_ms}
+                "norm_products": i.norm_products, "build_ms": i.build_ms,
+                "split": bool(i.split)}
 
     def csr(self):
         """Host copies (row_ptr int64, col int32, val complex128)."""
@@ -263,8 +264,9 @@ class Superop:
         return rp, col, val
 
     def set_precision(self, single: bool):
-        """single=True: later propagate calls read complex64 superoperator
-        values and use the 2^-24 tolerance; vectors and sums stay complex128."""
+        """single=True: later propagate calls read single-precision
+        superoperator values (each real and imaginary part rounded to nearest)
+        and use the 2^-24 tolerance; vectors and sums stay complex128."""
         torch = _torch()
         with torch.cuda.device(self.device):
             st = _lib.load().qsw_superop_set_precision(
@@ -279,7 +281,7 @@ class Superop:
         with torch.cuda.device(self.device):
             st = _lib.load().qsw_superop_autotune(self._h, _stream(self.device), ctypes.byref(t))
         _lib.check(st, "qsw_superop_autotune")
-        return {"staged": bool(t.staged), "grid": t.grid, "us_per_product": t.us_per_product,
+        return {"staged": int(t.staged), "grid": t.grid, "us_per_product": t.us_per_product,
                 "from_cache": bool(t.from_cache)}
 
     def workspace_bytes(self, t0, dt, n_steps) -> int:

@@ -368,6 +368,11 @@ qsw_status_t qsw_engine_submit(qsw_engine_t e, const qsw_walk_t *w, int64_t *tic
   I.wcol = h->wcol;
   I.wval = h->wval;
   I.wval32 = h->wval32;
+  I.wcoef = h->wcoef;
+  I.wcoef32 = h->wcoef32;
+  I.wdiag = h->wdiag;
+  I.wdiag32 = h->wdiag32;
+  I.split = h->split ? 1 : 0;
   I.wlen = h->wlen;
   I.wperm = h->wperm;
   I.n = h->n;

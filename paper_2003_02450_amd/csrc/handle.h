@@ -76,8 +76,9 @@ struct qsw_superop_s {
   double2 *val = nullptr;
   qsw_info_t info{};
   // launch shape of the product kernels
-  int engine = 0;                 // 0 / 100: wave-jagged (100: rho-row staged in LDS);
-                                  // 3: CSR stream; 4..64: vector engine lanes per row
+  int engine = 0;                 // wave-jagged traversal 0 / 100 (rho-row staged in
+                                  // LDS) / 200 (staged, XCD-banded); 3: CSR stream;
+                                  // 4..64: vector engine lanes per row
   int grid = 0;                   // workgroups of a product launch
   int64_t rows_per_block = 0;     // vector engine
   int32_t *blk = nullptr;         // stream engine row blocks
@@ -85,8 +86,13 @@ struct qsw_superop_s {
   int32_t blocks_per_wg = 0;
   // wave-jagged layout (the product kernels' copy of the matrix)
   int32_t *wcol = nullptr;
-  double2 *wval = nullptr;
+  double2 *wval = nullptr;        // complex values (null with phase-split values)
   float2 *wval32 = nullptr;       // complex64 values for QSW_PREC_SINGLE propagation
+  bool split = false;             // phase-split values: wcoef / wdiag instead of wval
+  double *wcoef = nullptr;
+  float *wcoef32 = nullptr;       // single-precision copies for QSW_PREC_SINGLE
+  double2 *wdiag = nullptr;
+  float2 *wdiag32 = nullptr;
   int prec = QSW_PREC_DOUBLE;     // precision of qsw_propagate
   int32_t *wlen = nullptr;
   unsigned char *wperm = nullptr;
@@ -100,6 +106,15 @@ struct qsw_superop_s {
 };
 
 namespace qsw {
+
+inline bool is_wave_engine(int engine) { return engine == 0 || engine == 100 || engine == 200; }
+
+// Kernel engine of a product launch: the handle's traversal plus its value
+// format (+10 phase-split, +1 single precision when `single`).
+inline int launch_engine(const qsw_superop_s *h, bool single) {
+  if (!is_wave_engine(h->engine)) return h->engine;
+  return h->engine + (h->split ? 10 : 0) + (single ? 1 : 0);
+}
 
 // Parameters and workspace layout of one qsw_propagate call.
 struct Plan {

@@ -115,7 +115,20 @@ __device__ __forceinline__ int load_stream(const int32_t *p) {
   return __builtin_nontemporal_load((const QSW_GLOBAL int32_t *)p);
 }
 
+__device__ __forceinline__ double load_stream(const double *p) {
+  return __builtin_nontemporal_load((const QSW_GLOBAL double *)p);
+}
+__device__ __forceinline__ double load_stream(const float *p) {
+  return (double)__builtin_nontemporal_load((const QSW_GLOBAL float *)p);
+}
+
 typedef float fvec2 __attribute__((ext_vector_type(2)));
+
+template <>
+__device__ __forceinline__ float2 gld<float2>(const float2 *p) {
+  const fvec2 v = *(const QSW_GLOBAL fvec2 *)p;
+  return make_float2(v.x, v.y);
+}
 
 // A complex64 entry widened to complex128 (exact).
 __device__ __forceinline__ double2 load_stream(const float2 *p) {
@@ -316,6 +329,11 @@ __device__ __forceinline__ void stream_engine(const SpmvArgs &a, Epi &epi) {
 // copies x[a N .. a N + N) of its first row into LDS once and every column in
 // that range is read from there (any row may use it: the test is on the
 // column).  Needs N * 16 bytes of dynamic LDS.
+// SPLIT: phase-split values (kImagBit / kDiagBit in the column index, one
+// real coefficient per entry, the diagonal from wdiag).  The complex value is
+// rebuilt as (c, 0), (0, c) or the diagonal before the same fused
+// multiply-adds, so every sum equals the complex layout's up to the sign of
+// a zero.
 // Positions in flight per lane: six for one or two right-hand sides, three
 // for four (each gathered element then takes 16 registers).
 template <int NRHS>
@@ -329,9 +347,12 @@ constexpr int wave_unroll() { return NRHS <= 2 ? 6 : 3; }
 // the rho-row of every column (xs[r N + i]), `staged` says whether it belongs
 // to this block's x, and each gather reads LDS or global memory through one
 // generic (flat) load.
-template <int NRHS, bool F32, bool STAGE, class Epi, bool SOA = false>
+template <int NRHS, bool F32, bool STAGE, class Epi, bool SOA = false, bool SPLIT = false>
 __device__ __forceinline__ void wave_block(const SpmvArgs &a, int64_t k, Epi &epi,
-                                           const double2 *xs, int64_t base, bool staged = true) {
+                                           const double2 *xs, int64_t base, bool staged = true,
+                                           int64_t span = 0) {
+  // one right-hand side: xs holds x[base .. base + span) (span = N by default)
+  const uint64_t lim = (uint64_t)(span ? span : a.N);
   constexpr int kWaveUnroll = wave_unroll<NRHS>();
   const int lane = threadIdx.x & 63;
   {
@@ -342,6 +363,17 @@ __device__ __forceinline__ void wave_block(const SpmvArgs &a, int64_t k, Epi &ep
     const int orow = lane < nr ? (int)gld(a.wperm + r0 + lane) : 0;
     typename Epi::Pre pre{};
     if (lane < nr) pre = epi.pre(r0 + orow);
+    double2 dg = make_double2(0.0, 0.0);
+    if constexpr (SPLIT) {
+      if (lane < nr) {
+        if constexpr (F32) {
+          const float2 d32 = gld(a.wdiag32 + r0 + lane);
+          dg = make_double2((double)d32.x, (double)d32.y);
+        } else {
+          dg = gld(a.wdiag + r0 + lane);
+        }
+      }
+    }
     const int maxlen = __shfl(len, 0, 64);  // rank 0 is the longest row
     double acc[2 * NRHS];
 #pragma unroll
@@ -368,12 +400,26 @@ __device__ __forceinline__ void wave_block(const SpmvArgs &a, int64_t k, Epi &ep
 #pragma unroll
       for (int u = 0; u < kWaveUnroll; ++u) c[u] = load_stream(cb + bcur[u]);
       double2 v[kWaveUnroll];
+      double cf[kWaveUnroll];
 #pragma unroll
       for (int u = 0; u < kWaveUnroll; ++u) {
-        if constexpr (F32)
+        if constexpr (SPLIT && F32)
+          cf[u] = load_stream(a.wcoef32 + e0 + bcur[u]);
+        else if constexpr (SPLIT)
+          cf[u] = load_stream(a.wcoef + e0 + bcur[u]);
+        else if constexpr (F32)
           v[u] = load_stream(a.wval32 + e0 + bcur[u]);
         else
           v[u] = load_stream(a.wval + e0 + bcur[u]);
+      }
+      if constexpr (SPLIT) {
+#pragma unroll
+        for (int u = 0; u < kWaveUnroll; ++u) {
+          const uint32_t raw = (uint32_t)c[u];
+          const bool im = (raw & kImagBit) != 0u;
+          v[u] = (raw & kDiagBit) ? dg : make_double2(im ? 0.0 : cf[u], im ? cf[u] : 0.0);
+          c[u] = (int)(raw & (uint32_t)kColMask);
+        }
       }
 #pragma unroll
       for (int u = 0; u < kWaveUnroll; ++u) {
@@ -389,7 +435,7 @@ __device__ __forceinline__ void wave_block(const SpmvArgs &a, int64_t k, Epi &ep
           }
         } else if constexpr (STAGE) {
           const uint64_t o = (uint64_t)((int64_t)c[u] - base);
-          const bool in_row = o < (uint64_t)a.N;
+          const bool in_row = o < lim;
           const double2 xl = xs[in_row ? o : 0];
           const double2 xg = gld(a.x + (in_row ? base : (int64_t)c[u]));
           cmac(acc[0], acc[1], vz, in_row ? xl : xg);
@@ -405,7 +451,7 @@ __device__ __forceinline__ void wave_block(const SpmvArgs &a, int64_t k, Epi &ep
   }
 }
 
-template <int NRHS, bool F32, bool STAGE, class Epi>
+template <int NRHS, bool F32, bool STAGE, bool SPLIT, class Epi>
 __device__ __forceinline__ void wave_engine(const SpmvArgs &a, Epi &epi) {
   constexpr int WPB = kBlock / 64;  // wavefronts per workgroup
   const int64_t nw = (int64_t)gridDim.x * WPB;
@@ -420,7 +466,46 @@ __device__ __forceinline__ void wave_engine(const SpmvArgs &a, Epi &epi) {
       __syncthreads();
     }
     const int64_t k = kb + (threadIdx.x >> 6);
-    if (k < a.nwb) wave_block<NRHS, F32, STAGE>(a, k, epi, xs, base);
+    if (k < a.nwb) wave_block<NRHS, F32, STAGE, Epi, false, SPLIT>(a, k, epi, xs, base);
+  }
+}
+
+// XCD-banded traversal (engines 200 / 201, N = 512, 1024 or 2048).  The
+// dispatcher deals workgroups to the 8 XCDs in turn, so workgroup w runs on
+// XCD w mod 8.  XCD x takes the rows (a, b) whose b lies in its band of N/8
+// columns, for every a: the H rho gathers x[c N + b] then stay within the
+// band's N x N/8 slice of x, which fits the XCD's L2, instead of ranging
+// over all of x.  A workgroup takes four consecutive blocks of its band;
+// they span 4/bw rho-rows (bw = band blocks per rho-row), whose x rows are
+// staged in LDS for the rho H gathers.  Only the order of the blocks
+// changes: every row's sum is the same as in the other engines.
+__device__ __forceinline__ int band_blocks(int N) { return N / 64 / 8; }
+__device__ __forceinline__ int band_rows(int N) {
+  const int bw = band_blocks(N);
+  return bw >= 4 ? 1 : 4 / bw;
+}
+
+template <bool F32, bool SPLIT, class Epi>
+__device__ __forceinline__ void wave_engine_banded(const SpmvArgs &a, Epi &epi) {
+  constexpr int WPB = kBlock / 64;
+  static_assert(WPB == 4, "a workgroup takes four blocks of its band");
+  extern __shared__ double2 xs[];
+  const int64_t nbr = a.N / 64;         // blocks per rho-row
+  const int64_t bw = band_blocks(a.N);  // band blocks per rho-row
+  const int64_t rows = band_rows(a.N);
+  const int xcd = blockIdx.x & 7;
+  const int64_t wi = blockIdx.x >> 3, g8 = gridDim.x >> 3;
+  const int64_t nq = (int64_t)a.N * bw / WPB;  // quads per band
+  const int wave = threadIdx.x >> 6;
+  for (int64_t q = wi; q < nq; q += g8) {
+    const int64_t i0 = q * WPB;
+    const int64_t base = (i0 / bw) * a.N;
+    __syncthreads();  // the previous quad is done with xs
+    for (int64_t i = threadIdx.x; i < rows * a.N; i += kBlock) xs[i] = gld(a.x + base + i);
+    __syncthreads();
+    const int64_t bi = i0 + wave;
+    const int64_t k = (bi / bw) * nbr + xcd * bw + bi % bw;
+    wave_block<1, F32, true, Epi, false, SPLIT>(a, k, epi, xs, base, true, rows * a.N);
   }
 }
 
@@ -446,23 +531,30 @@ __device__ __forceinline__ void vector_engine(const SpmvArgs &a, Epi &epi) {
   }
 }
 
-// Engines: 0 = wave-jagged layout, 1 = the same with complex64 values,
-// 100 / 101 = the same with the rho-row staged in LDS, 3 = CSR stream,
-// 4..64 = vector with that many lanes per row.
+// Engines: wave-jagged traversal 0 (plain), 100 (rho-row staged in LDS) or
+// 200 (staged and XCD-banded), plus 1 for single-precision values and 10 for
+// phase-split values; 3 = CSR stream, 4..64 = vector with that many lanes per
+// row.
+template <int ENGINE>
+constexpr bool is_vector_engine() {
+  return ENGINE == 4 || ENGINE == 8 || ENGINE == 16 || ENGINE == 32 || ENGINE == 64;
+}
+
 template <int ENGINE, class Epi>
 __device__ __forceinline__ void run_engine(const SpmvArgs &a, Epi &epi) {
-  if constexpr (ENGINE == 0)
-    wave_engine<1, false, false>(a, epi);
-  else if constexpr (ENGINE == 1)
-    wave_engine<1, true, false>(a, epi);
-  else if constexpr (ENGINE == 100)
-    wave_engine<1, false, true>(a, epi);
-  else if constexpr (ENGINE == 101)
-    wave_engine<1, true, true>(a, epi);
-  else if constexpr (ENGINE == 3)
+  if constexpr (ENGINE == 3) {
     stream_engine<1>(a, epi);
-  else
+  } else if constexpr (is_vector_engine<ENGINE>()) {
     vector_engine<ENGINE>(a, epi);
+  } else {
+    constexpr int trav = ENGINE / 100, fmt = ENGINE % 100;
+    static_assert(trav <= 2 && (fmt == 0 || fmt == 1 || fmt == 10 || fmt == 11), "engine");
+    constexpr bool f32 = (fmt % 10) == 1, split = fmt >= 10;
+    if constexpr (trav == 2)
+      wave_engine_banded<f32, split>(a, epi);
+    else
+      wave_engine<1, f32, trav == 1, split>(a, epi);
+  }
 }
 
 // ---------------------------------------------------------------- epilogues
@@ -652,6 +744,67 @@ __global__ __launch_bounds__(kBlock) void wjag_build_kernel(const int64_t *rp, c
   }
 }
 
+// The same with phase-split values.  Lane l finds its row's diagonal entry
+// and its value; off-diagonal entries keep their coefficient and phase.
+__global__ __launch_bounds__(kBlock) void wjag_split_kernel(const int64_t *rp, const int32_t *col,
+                                                            const double2 *val, int64_t n,
+                                                            int64_t nwb, int32_t *wcol,
+                                                            double *wcoef, double2 *wdiag,
+                                                            int32_t *wlen, unsigned char *wperm,
+                                                            int *bad) {
+  const int lane = threadIdx.x & 63;
+  const int64_t k = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  if (k >= nwb) return;
+  const int64_t r0 = k * kWaveRows;
+  const int nr = (int)min((int64_t)kWaveRows, n - r0);
+  const int64_t e0 = rp[r0];
+  const int64_t src0 = lane < nr ? rp[r0 + lane] : 0;
+  const int len = lane < nr ? (int)(rp[r0 + lane + 1] - src0) : -1;
+  int rank = 0;
+  int maxlen = 0;
+  for (int j = 0; j < 64; ++j) {
+    const int lj = __shfl(len, j, 64);
+    rank += (lj > len) || (lj == len && j < lane);
+    maxlen = lj > maxlen ? lj : maxlen;
+  }
+  if (lane < nr) {
+    wlen[r0 + rank] = len;
+    wperm[r0 + rank] = (unsigned char)lane;
+  }
+  const int64_t row = r0 + lane;
+  double2 dg = make_double2(0.0, 0.0);
+  int ndiag = 0;
+  bool mixed = false;
+  int ps = 0;
+  for (int p = 0; p < maxlen; ++p) {
+    const int cnt = __popcll(__ballot(len > p));
+    if (len > p) {
+      const int64_t dst = e0 + ps + rank;
+      const int32_t cc = col[src0 + p];
+      const double2 vv = val[src0 + p];
+      if (cc == row) {
+        dg = vv;
+        ++ndiag;
+        wcol[dst] = (int32_t)((uint32_t)cc | kDiagBit);
+        wcoef[dst] = 0.0;
+      } else if (vv.x != 0.0 && vv.y != 0.0) {
+        mixed = true;
+        wcol[dst] = cc;
+        wcoef[dst] = 0.0;
+      } else if (vv.x == 0.0 && vv.y != 0.0) {
+        wcol[dst] = (int32_t)((uint32_t)cc | kImagBit);
+        wcoef[dst] = vv.y;
+      } else {
+        wcol[dst] = cc;
+        wcoef[dst] = vv.x;
+      }
+    }
+    ps += cnt;
+  }
+  if (lane < nr) wdiag[r0 + rank] = dg;
+  if (mixed || ndiag > 1) *(volatile int *)bad = 1;
+}
+
 // max over rows of sum_e |val[e]|  (on the adjoint this is ||L||_1).
 __global__ __launch_bounds__(kBlock) void row_abs_max_kernel(int64_t n, const int64_t *rp,
                                                              const double2 *val,
@@ -680,6 +833,13 @@ __global__ void to_c64_kernel(float2 *dst, const double2 *src, int64_t n) {
     const double2 v = src[i];
     dst[i] = make_float2((float)v.x, (float)v.y);
   }
+}
+
+// Round doubles to float (to nearest).
+__global__ void to_f32_kernel(float *dst, const double *src, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
 }
 
 __global__ void copy_kernel(double2 *dst, const double2 *src, int64_t n) {
@@ -801,10 +961,11 @@ __global__ __launch_bounds__(kBlock) void series_accum_kernel(DeviceState *st, P
 // --------------------------------------------------------------------------
 // Two right-hand sides (block 1-norm estimation), stream engine.
 // --------------------------------------------------------------------------
+template <bool SPLIT>
 __global__ __launch_bounds__(kBlock) void spmm2_kernel(SpmvArgs a, int mode, double *part,
                                                        double2 *sgn, double *h) {
   Spmm2Epi epi{a.y, mode, sgn, h};
-  wave_engine<2, false, false>(a, epi);
+  wave_engine<2, false, false, SPLIT>(a, epi);
   if (mode == 1) {
     // deterministic per-workgroup column sums: fixed tree over the threads
     __shared__ double sm0[kBlock], sm1[kBlock];
@@ -1314,7 +1475,7 @@ __global__ void batch_blocks_kernel(BatchArgs A) {
 // engine, for all R columns): decided per workgroup from the walk of its
 // first block, used by the waves whose block belongs to that walk.
 template <int R>
-__global__ __launch_bounds__(kBlock) void batch_work_kernel(BatchArgs A) {
+__global__ __launch_bounds__(kBlock, (R >= 2 ? 4 : 1)) void batch_work_kernel(BatchArgs A) {
   constexpr int WPB = kBlock / 64;
   extern __shared__ double2 xs[];
   const int lane = threadIdx.x & 63;
@@ -1373,6 +1534,10 @@ __global__ __launch_bounds__(kBlock) void batch_work_kernel(BatchArgs A) {
         a.wcol = I.wcol;
         a.wval = I.wval;
         a.wval32 = I.wval32;
+        a.wcoef = I.wcoef;
+        a.wcoef32 = I.wcoef32;
+        a.wdiag = I.wdiag;
+        a.wdiag32 = I.wdiag32;
         a.wlen = I.wlen;
         a.wperm = I.wperm;
         a.nwb = I.nwb;
@@ -1391,10 +1556,16 @@ __global__ __launch_bounds__(kBlock) void batch_work_kernel(BatchArgs A) {
   #pragma unroll
         for (int r = 0; r < R; ++r) epi.my[r] = epi.mf[r] = epi.mb0[r] = 0ull;
         const bool st = sb == b;
-        if (I.f32)
+        if (I.split) {
+          if (I.f32)
+            wave_block<R, true, true, BatchTermEpi<R>, true, true>(a, k, epi, xs, base, st);
+          else
+            wave_block<R, false, true, BatchTermEpi<R>, true, true>(a, k, epi, xs, base, st);
+        } else if (I.f32) {
           wave_block<R, true, true, BatchTermEpi<R>, true>(a, k, epi, xs, base, st);
-        else
+        } else {
           wave_block<R, false, true, BatchTermEpi<R>, true>(a, k, epi, xs, base, st);
+        }
   #pragma unroll
         for (int r = 0; r < R; ++r) {
           batch_flush(epi.my[r], &S->y[r]);
@@ -1492,6 +1663,16 @@ hipError_t launch_wjag_build(const int64_t *rp, const int32_t *col, const double
   return hipGetLastError();
 }
 
+hipError_t launch_wjag_split(const int64_t *rp, const int32_t *col, const double2 *val, int64_t n,
+                             int32_t *wcol, double *wcoef, double2 *wdiag, int32_t *wlen,
+                             unsigned char *wperm, int *bad, hipStream_t s) {
+  const int64_t nwb = (n + kWaveRows - 1) / kWaveRows;
+  const int64_t grid = (nwb + kBlock / 64 - 1) / (kBlock / 64);
+  hipLaunchKernelGGL(wjag_split_kernel, dim3((unsigned)grid), dim3(kBlock), 0, s, rp, col, val, n,
+                     nwb, wcol, wcoef, wdiag, wlen, wperm, bad);
+  return hipGetLastError();
+}
+
 hipError_t launch_row_abs_max(int64_t n, const int64_t *rp, const double2 *val,
                               unsigned long long *out_bits, hipStream_t s) {
   hipLaunchKernelGGL(row_abs_max_kernel, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, rp, val,
@@ -1515,6 +1696,14 @@ hipError_t launch_copy(double2 *dst, const double2 *src, int64_t n, hipStream_t 
   return hipGetLastError();
 }
 
+hipError_t launch_to_f32(float *dst, const double *src, int64_t n, hipStream_t s) {
+  int grid = blocks_for(n);
+  if (grid > 8192) grid = 8192;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(to_f32_kernel, dim3(grid), dim3(kBlock), 0, s, dst, src, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_to_c64(float2 *dst, const double2 *src, int64_t n, hipStream_t s) {
   int grid = blocks_for(n);
   if (grid > 8192) grid = 8192;
@@ -1527,8 +1716,16 @@ hipError_t launch_to_c64(float2 *dst, const double2 *src, int64_t n, hipStream_t
   switch (ENG) {                          \
     case 0: CALL(0); break;               \
     case 1: CALL(1); break;               \
+    case 10: CALL(10); break;             \
+    case 11: CALL(11); break;             \
     case 100: CALL(100); break;           \
     case 101: CALL(101); break;           \
+    case 110: CALL(110); break;           \
+    case 111: CALL(111); break;           \
+    case 200: CALL(200); break;           \
+    case 201: CALL(201); break;           \
+    case 210: CALL(210); break;           \
+    case 211: CALL(211); break;           \
     case 3: CALL(3); break;               \
     case 4: CALL(4); break;               \
     case 8: CALL(8); break;               \
@@ -1540,6 +1737,10 @@ hipError_t launch_to_c64(float2 *dst, const double2 *src, int64_t n, hipStream_t
 
 // Dynamic LDS of a product launch: the staged rho-row for engines 100/101.
 inline size_t stage_bytes(int engine, const SpmvArgs &a) {
+  if (engine >= 200) {
+    const int bw = a.N / 64 / 8;
+    return (size_t)(bw >= 4 ? 1 : 4 / bw) * a.N * sizeof(double2);
+  }
   return engine >= 100 ? (size_t)a.N * sizeof(double2) : 0;
 }
 
@@ -1587,9 +1788,12 @@ hipError_t launch_series_accum(DeviceState *st, PointSlots *pt, int k, int p, co
   return hipGetLastError();
 }
 
-hipError_t launch_spmm2(const SpmvArgs &a, int mode, double *part, double2 *sgn, double *h,
-                        int grid, hipStream_t s) {
-  hipLaunchKernelGGL(spmm2_kernel, dim3(grid), dim3(kBlock), 0, s, a, mode, part, sgn, h);
+hipError_t launch_spmm2(const SpmvArgs &a, bool split, int mode, double *part, double2 *sgn,
+                        double *h, int grid, hipStream_t s) {
+  if (split)
+    hipLaunchKernelGGL(spmm2_kernel<true>, dim3(grid), dim3(kBlock), 0, s, a, mode, part, sgn, h);
+  else
+    hipLaunchKernelGGL(spmm2_kernel<false>, dim3(grid), dim3(kBlock), 0, s, a, mode, part, sgn, h);
   return hipGetLastError();
 }
 
@@ -1677,7 +1881,7 @@ int resident_workgroups(int which) {
     return 0;
   hipError_t e;
   if (which == 1)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, spmm2_kernel, kBlock, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, spmm2_kernel<false>, kBlock, 0);
   else
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, term_kernel<0>, kBlock, 0);
   if (e != hipSuccess || per < 1) per = 1;

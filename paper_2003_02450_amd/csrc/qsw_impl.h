@@ -79,6 +79,17 @@ constexpr int kWaveRows = 64;
 constexpr int kWavePad = 64;  // zero entries after the wave-jagged arrays (reads past a block's end)
 constexpr size_t kStageMaxBytes = 32768;  // largest LDS-staged rho-row (N <= 2048)
 
+// Phase-split values.  Every off-diagonal entry of a graph-built L-QSW
+// superoperator is real (the rate terms) or imaginary (the Hamiltonian
+// terms): such an entry is stored as one real coefficient c, with the phase
+// (1 or i) in the top bit of its column index.  The diagonal entry of each
+// row is complex; it keeps its place in the row (flag kDiagBit) and its value
+// is read from a per-row array.  Columns then need n <= 2^30.
+constexpr uint32_t kImagBit = 0x80000000u;  // value i c
+constexpr uint32_t kDiagBit = 0x40000000u;  // value wdiag[row]
+constexpr int32_t kColMask = 0x3fffffff;
+constexpr int64_t kSplitMaxN = (int64_t)1 << 30;
+
 struct SpmvArgs {
   int64_t n;
   const int64_t *rp;
@@ -97,6 +108,10 @@ struct SpmvArgs {
   const int32_t *wcol;
   const double2 *wval;
   const float2 *wval32;  // complex64 copy of wval (engine 1), or null
+  const double *wcoef;   // phase-split values (engines +10): coefficient per entry
+  const float *wcoef32;  //   its single-precision copy
+  const double2 *wdiag;  //   diagonal value of the row of rank r at 64 k + r
+  const float2 *wdiag32; //   its complex64 copy
   const int32_t *wlen;
   const unsigned char *wperm;
   const double2 *x;      // gathered vector (NRHS interleaved columns for the estimator)
@@ -130,11 +145,15 @@ struct BatchInst {
   const int32_t *wcol;
   const double2 *wval;
   const float2 *wval32;
+  const double *wcoef;
+  const float *wcoef32;
+  const double2 *wdiag;
+  const float2 *wdiag32;
   const int32_t *wlen;
   const unsigned char *wperm;
   int64_t n, nwb;
   int64_t vlen;      // n * R: complex elements of one work vector
-  int32_t N, f32;
+  int32_t N, f32, split;  // f32: single-precision values; split: phase-split values
   // plan (as for one walk)
   int32_t branch, m, s, m0, s0, d, jb, r, q, n0;
   double t0, dt, tol;
@@ -196,6 +215,7 @@ hipError_t launch_row_abs_max(int64_t n, const int64_t *rp, const double2 *val,
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_copy(double2 *dst, const double2 *src, int64_t n, hipStream_t s);
 hipError_t launch_to_c64(float2 *dst, const double2 *src, int64_t n, hipStream_t s);
+hipError_t launch_to_f32(float *dst, const double *src, int64_t n, hipStream_t s);
 
 // Stream-engine row blocks: block k starts at the first row whose first
 // entry index is >= k B; blk has nblk + 1 entries.
@@ -206,9 +226,18 @@ hipError_t launch_row_blocks(const int64_t *rp, int64_t n, int64_t B, int32_t *b
 hipError_t launch_wjag_build(const int64_t *rp, const int32_t *col, const double2 *val, int64_t n,
                              int32_t *wcol, double2 *wval, int32_t *wlen, unsigned char *wperm,
                              hipStream_t s);
+// The same layout with phase-split values (n <= 2^30): wcoef per entry,
+// wdiag per row (zero for a row without a diagonal entry).  Sets *bad
+// (zeroed by the caller) when an off-diagonal entry has a non-zero real and
+// imaginary part, or a row holds its diagonal more than once.
+hipError_t launch_wjag_split(const int64_t *rp, const int32_t *col, const double2 *val, int64_t n,
+                             int32_t *wcol, double *wcoef, double2 *wdiag, int32_t *wlen,
+                             unsigned char *wperm, int *bad, hipStream_t s);
 
-// Engine: 0 = wave-jagged, 3 = CSR stream, 4/8/16/32/64 = vector with that
-// many lanes per row.
+// Engine: wave-jagged traversal 0 (plain), 100 (rho-row staged in LDS) or
+// 200 (staged, XCD-banded), plus 1 for single-precision values and 10 for
+// phase-split values; 3 = CSR stream; 4/8/16/32/64 = vector with that many
+// lanes per row.
 // Single-time algorithm term j: y = alpha A x; F_out = F_in + y; norms into
 // st->step[par]; early exit when the previous terms already passed the test.
 hipError_t launch_taylor_term(const SpmvArgs &a, int engine, int grid, hipStream_t s);
@@ -229,8 +258,9 @@ hipError_t launch_series_accum(DeviceState *st, PointSlots *pt, int k, int p,
 // sides (wave-jagged engine; a.x = X, a.y = Y).  mode 0: product only; mode 1:
 // also column |.|_1 partial sums per workgroup into part[2*wg + c] and
 // S = sign(Y) into sgn; mode 2: also h[i] = max_c |Y[i][c]|.
-hipError_t launch_spmm2(const SpmvArgs &a, int mode, double *part, double2 *sgn, double *h,
-                        int grid, hipStream_t s);
+// split: the layout holds phase-split values.
+hipError_t launch_spmm2(const SpmvArgs &a, bool split, int mode, double *part, double2 *sgn,
+                        double *h, int grid, hipStream_t s);
 hipError_t launch_sum_partials(const double *part, int nblocks, double *out2,
                                hipStream_t s);
 // Estimator probe block (column 0 = 1/n, column 1 = signed 1/n; t = 1 zeroes

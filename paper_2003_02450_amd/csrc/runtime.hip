@@ -315,6 +315,7 @@ struct Estimator {
   int64_t n;
   hipStream_t s;
   SpmvArgs fwd{}, adj{};          // A and A^dagger (jagged layouts)
+  bool fsplit = false, asplit = false;  // their value formats
   int grid = 0;                   // workgroups of a product (= partial sums per column)
   double2 *X, *Y, *W0, *W1, *S;  // n x 2 interleaved blocks
   double *h, *part, *sums;
@@ -331,7 +332,8 @@ struct Estimator {
       SpmvArgs a = adjoint ? adj : fwd;
       a.x = src;
       a.y = dst;
-      hipError_t e = launch_spmm2(a, i == p ? mode : 0, part, S, h, grid, s);
+      hipError_t e = launch_spmm2(a, adjoint ? asplit : fsplit, i == p ? mode : 0, part, S, h,
+                                  grid, s);
       if (e != hipSuccess) return e;
       ++products;
       src = dst;
@@ -424,41 +426,74 @@ struct Estimator {
 };
 
 // Wave-jagged execution layout (see kWaveRows) of one CSR.
+// Complex values (val) or phase-split values (coef, diag; split = true).
 struct WaveLayout {
   int32_t *col = nullptr;
   double2 *val = nullptr;
+  double *coef = nullptr;
+  double2 *diag = nullptr;
+  bool split = false;
   int32_t *len = nullptr;
   unsigned char *perm = nullptr;
   int64_t nwb = 0;
   void release() {
     dfree(col);
     dfree(val);
+    dfree(coef);
+    dfree(diag);
     dfree(len);
     dfree(perm);
   }
 };
 
+// Phase-split values unless an off-diagonal entry is neither real nor
+// imaginary (then complex values), or QSW_SPLIT=0.
 hipError_t build_wave_layout(const int64_t *rp, const int32_t *col, const double2 *val, int64_t n,
                              int64_t nnz, hipStream_t s, WaveLayout &W) {
   hipError_t e;
   // kWavePad zero entries (column 0, value 0) after the last one: the
   // product loops read up to 63 entries past a block's end
   if ((e = dalloc(&W.col, (size_t)nnz + kWavePad)) != hipSuccess) return e;
-  if ((e = dalloc(&W.val, (size_t)nnz + kWavePad)) != hipSuccess) return e;
   if ((e = launch_zero(W.col + nnz, kWavePad * sizeof(int32_t), s)) != hipSuccess) return e;
-  if ((e = launch_zero(W.val + nnz, kWavePad * sizeof(double2), s)) != hipSuccess) return e;
   if ((e = dalloc(&W.len, (size_t)n)) != hipSuccess) return e;
   if ((e = dalloc(&W.perm, (size_t)n)) != hipSuccess) return e;
-  if ((e = launch_wjag_build(rp, col, val, n, W.col, W.val, W.len, W.perm, s)) != hipSuccess)
-    return e;
   W.nwb = (n + kWaveRows - 1) / kWaveRows;
-  return hipSuccess;
+  if (n <= kSplitMaxN && env_int("QSW_SPLIT", 1) != 0) {
+    int *bad = nullptr;
+    int hbad = 1;
+    do {
+      if ((e = dalloc(&bad, 1)) != hipSuccess) break;
+      if ((e = launch_zero(bad, sizeof(int), s)) != hipSuccess) break;
+      if ((e = dalloc(&W.coef, (size_t)nnz + kWavePad)) != hipSuccess) break;
+      if ((e = launch_zero(W.coef + nnz, kWavePad * sizeof(double), s)) != hipSuccess) break;
+      if ((e = dalloc(&W.diag, (size_t)n)) != hipSuccess) break;
+      if ((e = launch_wjag_split(rp, col, val, n, W.col, W.coef, W.diag, W.len, W.perm, bad, s)) !=
+          hipSuccess)
+        break;
+      if ((e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess)
+        break;
+      e = hipStreamSynchronize(s);
+    } while (false);
+    dfree(bad);
+    if (e != hipSuccess) return e;
+    if (!hbad) {
+      W.split = true;
+      return hipSuccess;
+    }
+    dfree(W.coef);
+    dfree(W.diag);
+  }
+  if ((e = dalloc(&W.val, (size_t)nnz + kWavePad)) != hipSuccess) return e;
+  if ((e = launch_zero(W.val + nnz, kWavePad * sizeof(double2), s)) != hipSuccess) return e;
+  return launch_wjag_build(rp, col, val, n, W.col, W.val, W.len, W.perm, s);
 }
 
 void set_wave(SpmvArgs &a, const WaveLayout &W) {
   a.nwb = W.nwb;
   a.wcol = W.col;
   a.wval = W.val;
+  a.wcoef = W.coef;
+  a.wdiag = W.diag;
   a.wlen = W.len;
   a.wperm = W.perm;
 }
@@ -469,9 +504,20 @@ void set_wave(SpmvArgs &a, const qsw_superop_s *h) {
   a.wcol = h->wcol;
   a.wval = h->wval;
   a.wval32 = h->wval32;
+  a.wcoef = h->wcoef;
+  a.wcoef32 = h->wcoef32;
+  a.wdiag = h->wdiag;
+  a.wdiag32 = h->wdiag32;
   a.wlen = h->wlen;
   a.wperm = h->wperm;
 }
+
+// The XCD-banded engine needs N/64 blocks per rho-row in 8 bands and at most
+// 32 KB of staged rows: N = 512, 1024 or 2048.
+bool banded_ok(int32_t N) { return N == 512 || N == 1024 || N == 2048; }
+
+// Its grid: a multiple of the 8 XCDs.
+int banded_grid(int grid) { return std::max(8, grid / 8 * 8); }
 
 // Workgroups of a wave-jagged launch: one wavefront per block up to four
 // times the resident capacity, then blocks per wavefront grow.
@@ -824,6 +870,9 @@ qsw_status_t build_common(std::shared_ptr<Assembler> src, double omega, hipStrea
     hipError_t we = build_wave_layout(h->row_ptr, h->col, h->val, h->n, h->nnz, s, W);
     h->wcol = W.col;
     h->wval = W.val;
+    h->wcoef = W.coef;
+    h->wdiag = W.diag;
+    h->split = W.split;
     h->wlen = W.len;
     h->wperm = W.perm;
     if (we != hipSuccess) return fail(status_of(we));
@@ -834,6 +883,13 @@ qsw_status_t build_common(std::shared_ptr<Assembler> src, double omega, hipStrea
     const bool stage = (size_t)N * sizeof(double2) <= kStageMaxBytes && env_int("QSW_STAGE", 1) != 0;
     h->engine = stage ? 100 : 0;
     h->grid = wave_grid(h->nwb, resident1);
+    // the XCD-banded traversal measured no faster than plain staging on the
+    // 1024-vertex workloads, so it is taken only on request (QSW_BANDS=1) or
+    // when the autotuner finds it faster
+    if (stage && banded_ok(N) && env_int("QSW_BANDS", 0) != 0) {
+      h->engine = 200;
+      h->grid = banded_grid(h->grid);
+    }
     if (eng == 3) {
       h->engine = 3;
       h->grid = L.grid;
@@ -876,6 +932,8 @@ qsw_status_t build_common(std::shared_ptr<Assembler> src, double omega, hipStrea
     set_wave(E.fwd, h);
     E.adj.n = n; E.adj.rp = arp; E.adj.col = acol; E.adj.val = aval;
     set_wave(E.adj, WA);
+    E.fsplit = h->split;
+    E.asplit = WA.split;
     E.grid = wave_grid(h->nwb, resident_workgroups(1));
     if ((e = dalloc(&E.X, 2 * (size_t)n)) != hipSuccess) break;
     if ((e = dalloc(&E.Y, 2 * (size_t)n)) != hipSuccess) break;
@@ -912,6 +970,7 @@ qsw_status_t build_common(std::shared_ptr<Assembler> src, double omega, hipStrea
   h->info.nnz = h->nnz;
   h->info.omega = omega;
   h->info.norm_products = E.products;
+  h->info.split = h->split ? 1 : 0;
   if (hipEventCreate(&h->ev_start) != hipSuccess || hipEventCreate(&h->ev_end) != hipSuccess)
     return fail(QSW_ERR_DEVICE);
   if (dalloc(&h->stats_dev, 2) != hipSuccess) return fail(QSW_ERR_OOM);
@@ -977,7 +1036,7 @@ struct Runner {
   int64_t gstep = 0;
   int64_t launched = 0;
   double tol;
-  int engine;  // product engine of this call (1 for complex64 values)
+  int engine;  // product engine of this call (value format included)
 
   SpmvArgs base_args() const {
     SpmvArgs a{};
@@ -1464,6 +1523,10 @@ void qsw_superop_destroy(qsw_superop_t h) {
   dfree(h->wcol);
   dfree(h->wval);
   dfree(h->wval32);
+  dfree(h->wcoef);
+  dfree(h->wcoef32);
+  dfree(h->wdiag);
+  dfree(h->wdiag32);
   dfree(h->wlen);
   dfree(h->wperm);
   if (h->ev_start) (void)hipEventDestroy(h->ev_start);
@@ -1475,18 +1538,30 @@ qsw_status_t qsw_superop_set_precision(qsw_superop_t h, int32_t prec) {
   if (!h || (prec != QSW_PREC_DOUBLE && prec != QSW_PREC_SINGLE)) return QSW_ERR_ARG;
   DeviceGuard g(h->device);
   if (!g.ok) return QSW_ERR_DEVICE;
-  if (prec == QSW_PREC_SINGLE && !h->wval32) {
-    if (h->engine != 0 && h->engine != 100)
-      return QSW_ERR_STATE;  // the complex64 copy exists for the wave layout only
+  const bool have32 = h->split ? h->wcoef32 != nullptr : h->wval32 != nullptr;
+  if (prec == QSW_PREC_SINGLE && !have32) {
+    if (!is_wave_engine(h->engine))
+      return QSW_ERR_STATE;  // the single-precision copy exists for the wave layout only
     // the padding converts to zeros as well
-    HIP_TRY(dalloc(&h->wval32, (size_t)h->nnz + kWavePad));
     hipStream_t s = nullptr;
-    HIP_TRY(launch_to_c64(h->wval32, h->wval, h->nnz + kWavePad, s));
+    if (h->split) {
+      HIP_TRY(dalloc(&h->wcoef32, (size_t)h->nnz + kWavePad));
+      HIP_TRY(dalloc(&h->wdiag32, (size_t)h->n));
+      HIP_TRY(launch_to_f32(h->wcoef32, h->wcoef, h->nnz + kWavePad, s));
+      HIP_TRY(launch_to_c64(h->wdiag32, h->wdiag, h->n, s));
+    } else {
+      HIP_TRY(dalloc(&h->wval32, (size_t)h->nnz + kWavePad));
+      HIP_TRY(launch_to_c64(h->wval32, h->wval, h->nnz + kWavePad, s));
+    }
     HIP_TRY(hipStreamSynchronize(s));
-  } else if (prec == QSW_PREC_DOUBLE && h->wval32) {
+  } else if (prec == QSW_PREC_DOUBLE && have32) {
     HIP_TRY(hipDeviceSynchronize());  // earlier calls may still read the copy
     dfree(h->wval32);
+    dfree(h->wcoef32);
+    dfree(h->wdiag32);
     h->wval32 = nullptr;
+    h->wcoef32 = nullptr;
+    h->wdiag32 = nullptr;
   }
   h->prec = prec;
   return QSW_OK;
@@ -1494,21 +1569,21 @@ qsw_status_t qsw_superop_set_precision(qsw_superop_t h, int32_t prec) {
 
 qsw_status_t qsw_superop_autotune(qsw_superop_t h, void *hip_stream, qsw_tuning_t *out) {
   if (!h) return QSW_ERR_ARG;
-  if (h->engine != 0 && h->engine != 100) return QSW_ERR_STATE;  // wave-jagged engines only
+  if (!is_wave_engine(h->engine)) return QSW_ERR_STATE;  // wave-jagged engines only
   DeviceGuard g(h->device);
   if (!g.ok) return QSW_ERR_DEVICE;
   hipStream_t s = (hipStream_t)hip_stream;
   const bool can_stage = (size_t)h->N * sizeof(double2) <= kStageMaxBytes;
-  // key: graph order, entries per row (to a quarter), precision
+  // key: graph order, entries per row (to a quarter), precision, value format
   const long epr = h->n > 0 ? std::lround(4.0 * (double)h->nnz / (double)h->n) : 0;
-  const std::tuple<int, long, int> key{h->N, epr, h->prec};
+  const std::tuple<int, long, int, int> key{h->N, epr, h->prec, h->split ? 1 : 0};
   static std::mutex mu;
-  static std::map<std::tuple<int, long, int>, qsw_tuning_t> cache;
+  static std::map<std::tuple<int, long, int, int>, qsw_tuning_t> cache;
   {
     std::lock_guard<std::mutex> lk(mu);
     auto it = cache.find(key);
     if (it != cache.end()) {
-      h->engine = it->second.staged ? 100 : 0;
+      h->engine = it->second.staged == 2 ? 200 : (it->second.staged ? 100 : 0);
       h->grid = it->second.grid;
       if (out) {
         *out = it->second;
@@ -1538,10 +1613,11 @@ qsw_status_t qsw_superop_autotune(qsw_superop_t h, void *hip_stream, qsw_tuning_
   qsw_tuning_t best{};
   best.us_per_product = 1e300;
   hipError_t err = hipSuccess;
-  for (int st = can_stage ? 1 : 0; st >= 0 && err == hipSuccess; --st) {
+  for (int st = can_stage ? (banded_ok(h->N) ? 2 : 1) : 0; st >= 0 && err == hipSuccess; --st) {
     for (int mul : {1, 2, 4, 8}) {
       const int64_t wgs = (h->nwb + kBlockThreads / 64 - 1) / (kBlockThreads / 64);
-      const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(wgs, (int64_t)mul * resident));
+      int grid = (int)std::max<int64_t>(1, std::min<int64_t>(wgs, (int64_t)mul * resident));
+      if (st == 2) grid = banded_grid(grid);
       SpmvArgs a{};
       a.n = h->n;
       a.rp = h->row_ptr;
@@ -1551,7 +1627,8 @@ qsw_status_t qsw_superop_autotune(qsw_superop_t h, void *hip_stream, qsw_tuning_
       a.x = x;
       a.y = y;
       a.alpha = 1.0;
-      const int engine = (st ? 100 : 0) + (h->prec == QSW_PREC_SINGLE ? 1 : 0);
+      const int engine = (st == 2 ? 200 : (st ? 100 : 0)) + (h->split ? 10 : 0) +
+                         (h->prec == QSW_PREC_SINGLE ? 1 : 0);
       if ((err = launch_spmv(a, engine, grid, s)) != hipSuccess) break;  // warm-up
       if ((err = hipEventRecord(e0, s)) != hipSuccess) break;
       const int reps = 5;
@@ -1571,7 +1648,7 @@ qsw_status_t qsw_superop_autotune(qsw_superop_t h, void *hip_stream, qsw_tuning_
   }
   cleanup();
   if (err != hipSuccess) return status_of(err);
-  h->engine = best.staged ? 100 : 0;
+  h->engine = best.staged == 2 ? 200 : (best.staged ? 100 : 0);
   h->grid = best.grid;
   {
     std::lock_guard<std::mutex> lk(mu);
@@ -1631,7 +1708,7 @@ qsw_status_t qsw_propagate(qsw_superop_t h, const void *rho0, double t0, double 
   R.F[0] = (double2 *)(ws + P.off_F);
   R.F[1] = (double2 *)(ws + P.off_F + vec);
   R.tol = tol_of(h->prec);
-  R.engine = h->prec == QSW_PREC_SINGLE ? h->engine + 1 : h->engine;
+  R.engine = launch_engine(h, h->prec == QSW_PREC_SINGLE);
   double2 *outv = (double2 *)out;
   const int64_t n = h->n;
   auto slot = [&](int64_t k) { return outv + k * n; };
@@ -1701,10 +1778,13 @@ qsw_status_t qsw_last_stats(qsw_superop_t h, qsw_stats_t *st) {
   h->last.products = (int64_t)buf[0];
   h->last.nonfinite = (int)(buf[1] & 0xffffffffu) != 0;
   h->last.ms = ms;
-  const double entry = h->last.prec == QSW_PREC_SINGLE ? 12.0 : 20.0;
+  const bool single = h->last.prec == QSW_PREC_SINGLE;
+  const bool split = h->split && is_wave_engine(h->engine);
+  const double entry = split ? (single ? 8.0 : 12.0) : (single ? 12.0 : 20.0);
+  const double diag = split ? (single ? 8.0 : 16.0) : 0.0;
   const double vec = h->last.branch == 1 ? 80.0 : 64.0;  // power + separate accumulation
   h->last.bytes = (double)h->last.products *
-                  (entry * (double)h->nnz + 8.0 * (double)(h->n + 1) + vec * (double)h->n);
+                  (entry * (double)h->nnz + 8.0 * (double)(h->n + 1) + (diag + vec) * (double)h->n);
   *st = h->last;
   return h->last.nonfinite ? QSW_ERR_NONFINITE : QSW_OK;
 }
@@ -1726,7 +1806,7 @@ qsw_status_t qsw_apply(qsw_superop_t h, const void *x, void *y, void *hip_stream
   a.nblk = h->nblk;
   a.blocks_per_wg = h->blocks_per_wg;
   set_wave(a, h);
-  HIP_TRY(launch_spmv(a, h->engine, h->grid, (hipStream_t)hip_stream));
+  HIP_TRY(launch_spmv(a, launch_engine(h, false), h->grid, (hipStream_t)hip_stream));
   return QSW_OK;
 }
 

@@ -72,13 +72,16 @@ struct Request {
   int state = 0;  // 0 pending, 1 running, 2 done
 };
 
-// Device bytes a handle holds: CSR, wave-jagged copy (padded), complex64
-// copy if any, row blocks of the stream layout.
+// Device bytes a handle holds: CSR, wave-jagged copy (padded; complex or
+// phase-split values), single-precision copy if any, row blocks of the
+// stream layout.
 size_t op_bytes(const qsw_superop_s *h) {
-  const size_t n = (size_t)h->n, nnz = (size_t)h->nnz;
-  size_t b = 8 * (n + 1) + 4 * nnz + 16 * nnz;                  // CSR
-  b += 4 * (nnz + kWavePad) + 16 * (nnz + kWavePad) + 4 * n + n;  // wave-jagged
-  if (h->wval32) b += 8 * (nnz + kWavePad);
+  const size_t n = (size_t)h->n, nnz = (size_t)h->nnz, pnz = nnz + kWavePad;
+  size_t b = 8 * (n + 1) + 4 * nnz + 16 * nnz;  // CSR
+  b += 4 * pnz + 4 * n + n;                       // columns, lengths, ranks
+  b += h->split ? 8 * pnz + 16 * n : 16 * pnz;    // values
+  if (h->wval32) b += 8 * pnz;
+  if (h->wcoef32) b += 4 * pnz + 8 * n;
   b += 4 * ((size_t)h->nblk + 1);
   return b;
 }
