@@ -96,6 +96,7 @@ struct qsw_superop_s {
   int prec = QSW_PREC_DOUBLE;     // precision of qsw_propagate
   int32_t *wlen = nullptr;
   unsigned char *wperm = nullptr;
+  int32_t *wglob = nullptr;       // per block: where its rows leave the gathers outside the rho-row
   int64_t nwb = 0;
   // last propagate
   hipEvent_t ev_start = nullptr, ev_end = nullptr;

@@ -22,6 +22,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace qsw {
 
 namespace {
@@ -339,6 +341,33 @@ __device__ __forceinline__ void stream_engine(const SpmvArgs &a, Epi &epi) {
 template <int NRHS>
 constexpr int wave_unroll() { return NRHS <= 2 ? 6 : 3; }
 
+// A wave-uniform 64-bit value (taken from lane 0) in scalar registers.
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Where a group of positions gathers x: anywhere (no staging, or several
+// right-hand sides), global memory, the staged rho-row, global memory before
+// a split position and LDS after it, or per lane through generic loads.
+enum { kGatherAny = 0, kGatherGlobal, kGatherLds, kGatherSplitAt, kGatherPerLane };
+
+// Complex value of an entry: stored (complex layouts) or rebuilt from the
+// phase-split coefficient, with scalar selects only.
+template <bool SPLIT>
+__device__ __forceinline__ double2 decode(int raw, double cf, double2 v, double2 dg) {
+  if constexpr (!SPLIT) {
+    return v;
+  } else {
+    const uint32_t r = (uint32_t)raw;
+    const bool im = (r & kImagBit) != 0u, diag = (r & kDiagBit) != 0u;
+    const double re = diag ? dg.x : (im ? 0.0 : cf);
+    const double ii = diag ? dg.y : (im ? cf : 0.0);
+    return make_double2(re, ii);
+  }
+}
+
 // Block k (64 rows) of the wave-jagged layout: epi(row, acc, pre) receives
 // the NRHS complex sums of each row.  With STAGE, xs holds x[base ..
 // base + N).  Called by a whole wavefront.
@@ -355,100 +384,146 @@ __device__ __forceinline__ void wave_block(const SpmvArgs &a, int64_t k, Epi &ep
   const uint64_t lim = (uint64_t)(span ? span : a.N);
   constexpr int kWaveUnroll = wave_unroll<NRHS>();
   const int lane = threadIdx.x & 63;
-  {
-    const int64_t r0 = k * kWaveRows;
-    const int nr = (int)min((int64_t)kWaveRows, a.n - r0);
-    const int64_t e0 = gld(a.rp + r0);
-    const int len = lane < nr ? gld(a.wlen + r0 + lane) : 0;
-    const int orow = lane < nr ? (int)gld(a.wperm + r0 + lane) : 0;
-    typename Epi::Pre pre{};
-    if (lane < nr) pre = epi.pre(r0 + orow);
-    double2 dg = make_double2(0.0, 0.0);
-    if constexpr (SPLIT) {
-      if (lane < nr) {
-        if constexpr (F32) {
-          const float2 d32 = gld(a.wdiag32 + r0 + lane);
-          dg = make_double2((double)d32.x, (double)d32.y);
-        } else {
-          dg = gld(a.wdiag + r0 + lane);
-        }
+  const int64_t r0 = k * kWaveRows;
+  const int nr = (int)min((int64_t)kWaveRows, a.n - r0);
+  // wave-uniform: first entry of the block and the longest row (rank 0)
+  const int64_t e0 = uniform64(gld(a.rp + r0));
+  const int len = lane < nr ? gld(a.wlen + r0 + lane) : 0;
+  const int maxlen = __builtin_amdgcn_readfirstlane(len);
+  const int orow = lane < nr ? (int)gld(a.wperm + r0 + lane) : 0;
+  typename Epi::Pre pre{};
+  if (lane < nr) pre = epi.pre(r0 + orow);
+  double2 dg = make_double2(0.0, 0.0);
+  if constexpr (SPLIT) {
+    if (lane < nr) {
+      if constexpr (F32) {
+        const float2 d32 = gld(a.wdiag32 + r0 + lane);
+        dg = make_double2((double)d32.x, (double)d32.y);
+      } else {
+        dg = gld(a.wdiag + r0 + lane);
       }
     }
-    const int maxlen = __shfl(len, 0, 64);  // rank 0 is the longest row
-    double acc[2 * NRHS];
+  }
+  double acc[2 * NRHS];
 #pragma unroll
-    for (int q = 0; q < 2 * NRHS; ++q) acc[q] = 0.0;
-    // Branch-free body.  Position p's entries start at the wave-uniform
-    // offset ps_p, so lane l reads entry e0 + ps_p + l whether or not its row
-    // is still running (entries past the row belong to other rows, the next
-    // block or the zero padding after the arrays: always a valid column) and
-    // discards the product when it is not.  With no branch around them,
-    // every load of an iteration is issued before the first wait.
-    const int32_t *cb = a.wcol + e0;
-    int ps = 0;
-    for (int p0 = 0; p0 < maxlen; p0 += kWaveUnroll) {
-      int bcur[kWaveUnroll];
-      bool ok[kWaveUnroll];
+  for (int q = 0; q < 2 * NRHS; ++q) acc[q] = 0.0;
+  // Branch-free groups of kWaveUnroll positions.  Position p's entries start
+  // at the wave-uniform offset ps_p, so lane l reads entry e0 + ps_p + l
+  // whether or not its row is still running (entries past the row belong to
+  // other rows, the next block or the zero padding after the arrays: always a
+  // valid column) and discards the product when it is not.  With no branch
+  // around them, every load of a group is issued before the first wait.
+  const int32_t *cb = a.wcol + e0;
+  int ps = 0;
+  int gsplit = 0;
+  // one group: column indices and values, then the x gathers (MODE), then
+  // the multiply-adds in position order
+  auto group = [&](auto mode, int p0) {
+    constexpr int MODE = decltype(mode)::value;
+    int bcur[kWaveUnroll];
+    bool ok[kWaveUnroll];
 #pragma unroll
-      for (int u = 0; u < kWaveUnroll; ++u) {
-        const int cnt = __popcll(__ballot(len > p0 + u));
-        ok[u] = lane < cnt;
-        bcur[u] = ps + lane;
-        ps += cnt;
-      }
-      int c[kWaveUnroll];
+    for (int u = 0; u < kWaveUnroll; ++u) {
+      const int cnt = __popcll(__ballot(len > p0 + u));
+      ok[u] = lane < cnt;
+      bcur[u] = ps + lane;
+      ps += cnt;
+    }
+    int c[kWaveUnroll];
 #pragma unroll
-      for (int u = 0; u < kWaveUnroll; ++u) c[u] = load_stream(cb + bcur[u]);
-      double2 v[kWaveUnroll];
-      double cf[kWaveUnroll];
+    for (int u = 0; u < kWaveUnroll; ++u) c[u] = load_stream(cb + bcur[u]);
+    double2 v[kWaveUnroll];
+    double cf[kWaveUnroll];
 #pragma unroll
-      for (int u = 0; u < kWaveUnroll; ++u) {
-        if constexpr (SPLIT && F32)
-          cf[u] = load_stream(a.wcoef32 + e0 + bcur[u]);
-        else if constexpr (SPLIT)
-          cf[u] = load_stream(a.wcoef + e0 + bcur[u]);
-        else if constexpr (F32)
-          v[u] = load_stream(a.wval32 + e0 + bcur[u]);
-        else
-          v[u] = load_stream(a.wval + e0 + bcur[u]);
-      }
+    for (int u = 0; u < kWaveUnroll; ++u) {
       if constexpr (SPLIT) {
-#pragma unroll
-        for (int u = 0; u < kWaveUnroll; ++u) {
-          const uint32_t raw = (uint32_t)c[u];
-          const bool im = (raw & kImagBit) != 0u;
-          v[u] = (raw & kDiagBit) ? dg : make_double2(im ? 0.0 : cf[u], im ? cf[u] : 0.0);
-          c[u] = (int)(raw & (uint32_t)kColMask);
-        }
+        cf[u] = F32 ? load_stream(a.wcoef32 + e0 + bcur[u]) : load_stream(a.wcoef + e0 + bcur[u]);
+        v[u] = dg;  // unused
+      } else {
+        v[u] = F32 ? load_stream(a.wval32 + e0 + bcur[u]) : load_stream(a.wval + e0 + bcur[u]);
+        cf[u] = 0.0;  // unused
       }
+    }
+    int col[kWaveUnroll];
+#pragma unroll
+    for (int u = 0; u < kWaveUnroll; ++u)
+      col[u] = SPLIT ? (int)((uint32_t)c[u] & (uint32_t)kColMask) : c[u];
+    if constexpr (MODE == kGatherAny) {
+      // no staging, or several right-hand sides
+#pragma unroll
+      for (int u = 0; u < kWaveUnroll; ++u) v[u] = decode<SPLIT>(c[u], cf[u], v[u], dg);
 #pragma unroll
       for (int u = 0; u < kWaveUnroll; ++u) {
         const double2 vz = ok[u] ? v[u] : make_double2(0.0, 0.0);
-        if constexpr (STAGE && SOA) {
-          const uint64_t o = (uint64_t)((int64_t)c[u] - base);
+        if constexpr (STAGE) {  // SOA with the block's rho-row of every column staged
+          const uint64_t o = (uint64_t)((int64_t)col[u] - base);
           const bool in_row = staged && o < (uint64_t)a.N;
 #pragma unroll
           for (int r = 0; r < NRHS; ++r) {
             const double2 xl = xs[in_row ? r * a.N + o : 0];
-            const double2 xg = gld(a.x + (in_row ? 0 : (int64_t)r * a.n + c[u]));
+            const double2 xg = gld(a.x + (in_row ? 0 : (int64_t)r * a.n + col[u]));
             cmac(acc[2 * r], acc[2 * r + 1], vz, in_row ? xl : xg);
           }
-        } else if constexpr (STAGE) {
-          const uint64_t o = (uint64_t)((int64_t)c[u] - base);
-          const bool in_row = o < lim;
-          const double2 xl = xs[in_row ? o : 0];
-          const double2 xg = gld(a.x + (in_row ? base : (int64_t)c[u]));
-          cmac(acc[0], acc[1], vz, in_row ? xl : xg);
         } else {
 #pragma unroll
           for (int r = 0; r < NRHS; ++r)
             cmac(acc[2 * r], acc[2 * r + 1], vz,
-                 gld(a.x + (SOA ? (int64_t)r * a.n + c[u] : (int64_t)c[u] * NRHS + r)));
+                 gld(a.x + (SOA ? (int64_t)r * a.n + col[u] : (int64_t)col[u] * NRHS + r)));
         }
       }
+    } else {
+      double2 xv[kWaveUnroll];
+#pragma unroll
+      for (int u = 0; u < kWaveUnroll; ++u) {
+        const uint64_t o = (uint64_t)((int64_t)col[u] - base);
+        const uint64_t oc = o < lim ? o : 0;
+        if constexpr (MODE == kGatherGlobal) {
+          xv[u] = gld(a.x + col[u]);
+        } else if constexpr (MODE == kGatherLds) {
+          xv[u] = xs[oc];
+        } else if constexpr (MODE == kGatherSplitAt) {
+          // positions before `gsplit` gather globally, the rest from LDS
+          xv[u] = *(p0 + u < gsplit ? a.x + col[u] : xs + oc);
+        } else {  // kGatherPerLane
+          xv[u] = *(o < lim ? xs + o : a.x + col[u]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kWaveUnroll; ++u)
+        cmac(acc[0], acc[1], ok[u] ? decode<SPLIT>(c[u], cf[u], v[u], dg) : make_double2(0.0, 0.0),
+             xv[u]);
     }
-    if (lane < nr) epi(r0 + orow, acc, pre);
+  };
+  if constexpr (STAGE && !SOA) {
+    static_assert(NRHS == 1, "staging holds one right-hand side");
+    // The layout puts each row's entries outside its rho-row first; in a
+    // block whose rows share one rho-row and all leave it at the same
+    // position G (wglob[k] = G, else -1), positions < G gather from global
+    // memory and the rest from the staged rho-row.  Other blocks choose per
+    // lane with generic loads.
+    const int G = a.wglob ? __builtin_amdgcn_readfirstlane(gld(a.wglob + k)) : -1;
+    const int64_t rho = r0 / a.N * a.N;
+    const bool regular = G >= 0 && (uint64_t)(rho - base) < lim;
+    int p0 = 0;
+    if (regular) {
+      const int gend = min(G, maxlen);
+      for (; p0 + kWaveUnroll <= gend; p0 += kWaveUnroll)
+        group(std::integral_constant<int, kGatherGlobal>{}, p0);
+      if (p0 < gend) {
+        gsplit = gend;
+        group(std::integral_constant<int, kGatherSplitAt>{}, p0);
+        p0 += kWaveUnroll;
+      }
+      for (; p0 < maxlen; p0 += kWaveUnroll) group(std::integral_constant<int, kGatherLds>{}, p0);
+    } else {
+      for (; p0 < maxlen; p0 += kWaveUnroll)
+        group(std::integral_constant<int, kGatherPerLane>{}, p0);
+    }
+  } else {
+    for (int p0 = 0; p0 < maxlen; p0 += kWaveUnroll)
+      group(std::integral_constant<int, kGatherAny>{}, p0);
   }
+  if (lane < nr) epi(r0 + orow, acc, pre);
 }
 
 template <int NRHS, bool F32, bool STAGE, bool SPLIT, class Epi>
@@ -705,14 +780,26 @@ __global__ void row_blocks_kernel(const int64_t *rp, int64_t n, int64_t B, int32
   blk[k] = (int32_t)lo;
 }
 
-// Wave-jagged layout, one wavefront per 64-row block: rank the rows by
-// length (longest first, ties by row), then scatter the entries
+// Wave-jagged layout of a CSR, one wavefront per 64-row block: rank the
+// rows by length (longest first, ties by row), then scatter the entries
 // position-major (entry p of rank r at e0 + entries of positions < p + r).
+// Inside each row the entries outside the row's own rho-row (columns c N + b
+// of the H rho part, population transfer) come first and those inside it
+// (the rho H part and the diagonal) last, each group in column order: all
+// rows of a block share their rho-row, so every position of the block
+// gathers from global memory for all rows or from the staged rho-row for all
+// rows.
+// SPLIT: phase-split values (wcoef, wdiag; *bad set when an off-diagonal
+// entry has a non-zero real and imaginary part or a row holds its diagonal
+// twice); otherwise complex values (wval).
+template <bool SPLIT>
 __global__ __launch_bounds__(kBlock) void wjag_build_kernel(const int64_t *rp, const int32_t *col,
                                                             const double2 *val, int64_t n,
-                                                            int64_t nwb, int32_t *wcol,
-                                                            double2 *wval, int32_t *wlen,
-                                                            unsigned char *wperm) {
+                                                            int32_t N, int64_t nwb,
+                                                            int32_t *wcol, double2 *wval,
+                                                            double *wcoef, double2 *wdiag,
+                                                            int32_t *wlen, unsigned char *wperm,
+                                                            int32_t *wglob, int *bad) {
   const int lane = threadIdx.x & 63;
   const int64_t k = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   if (k >= nwb) return;  // the whole wavefront leaves together
@@ -732,46 +819,23 @@ __global__ __launch_bounds__(kBlock) void wjag_build_kernel(const int64_t *rp, c
     wlen[r0 + rank] = len;
     wperm[r0 + rank] = (unsigned char)lane;
   }
-  int ps = 0;
-  for (int p = 0; p < maxlen; ++p) {
-    const int cnt = __popcll(__ballot(len > p));
-    if (len > p) {
-      const int64_t dst = e0 + ps + rank;
-      wcol[dst] = col[src0 + p];
-      wval[dst] = val[src0 + p];
-    }
-    ps += cnt;
-  }
-}
-
-// The same with phase-split values.  Lane l finds its row's diagonal entry
-// and its value; off-diagonal entries keep their coefficient and phase.
-__global__ __launch_bounds__(kBlock) void wjag_split_kernel(const int64_t *rp, const int32_t *col,
-                                                            const double2 *val, int64_t n,
-                                                            int64_t nwb, int32_t *wcol,
-                                                            double *wcoef, double2 *wdiag,
-                                                            int32_t *wlen, unsigned char *wperm,
-                                                            int *bad) {
-  const int lane = threadIdx.x & 63;
-  const int64_t k = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-  if (k >= nwb) return;
-  const int64_t r0 = k * kWaveRows;
-  const int nr = (int)min((int64_t)kWaveRows, n - r0);
-  const int64_t e0 = rp[r0];
-  const int64_t src0 = lane < nr ? rp[r0 + lane] : 0;
-  const int len = lane < nr ? (int)(rp[r0 + lane + 1] - src0) : -1;
-  int rank = 0;
-  int maxlen = 0;
-  for (int j = 0; j < 64; ++j) {
-    const int lj = __shfl(len, j, 64);
-    rank += (lj > len) || (lj == len && j < lane);
-    maxlen = lj > maxlen ? lj : maxlen;
-  }
-  if (lane < nr) {
-    wlen[r0 + rank] = len;
-    wperm[r0 + rank] = (unsigned char)lane;
-  }
   const int64_t row = r0 + lane;
+  const int32_t rho_row = (int32_t)(row / N);
+  auto inside = [&](int i) { return col[src0 + i] / N == rho_row; };
+  int outside = 0;  // entries of this row outside its rho-row
+  for (int i = 0; i < len; ++i) outside += !inside(i);
+  // G = fewest outside entries of a non-empty row; the block is regular when
+  // its rows share one rho-row and every row longer than G has exactly G
+  int G = 1 << 30;
+  for (int j = 0; j < 64; ++j) {
+    const int lj = __shfl(len, j, 64), oj = __shfl(outside, j, 64);
+    if (lj > 0 && oj < G) G = oj;
+  }
+  if (G == (1 << 30)) G = 0;
+  const bool odd = len > G && outside != G;
+  const bool regular = __ballot(odd) == 0 && r0 / N == (r0 + nr - 1) / N;
+  if (lane == 0) wglob[k] = regular ? G : -1;
+  int io = 0, ii = 0;  // cursors over the outside / inside entries
   double2 dg = make_double2(0.0, 0.0);
   int ndiag = 0;
   bool mixed = false;
@@ -779,10 +843,21 @@ __global__ __launch_bounds__(kBlock) void wjag_split_kernel(const int64_t *rp, c
   for (int p = 0; p < maxlen; ++p) {
     const int cnt = __popcll(__ballot(len > p));
     if (len > p) {
+      int src;
+      if (p < outside) {
+        while (inside(io)) ++io;
+        src = io++;
+      } else {
+        while (!inside(ii)) ++ii;
+        src = ii++;
+      }
       const int64_t dst = e0 + ps + rank;
-      const int32_t cc = col[src0 + p];
-      const double2 vv = val[src0 + p];
-      if (cc == row) {
+      const int32_t cc = col[src0 + src];
+      const double2 vv = val[src0 + src];
+      if constexpr (!SPLIT) {
+        wcol[dst] = cc;
+        wval[dst] = vv;
+      } else if (cc == row) {
         dg = vv;
         ++ndiag;
         wcol[dst] = (int32_t)((uint32_t)cc | kDiagBit);
@@ -801,8 +876,10 @@ __global__ __launch_bounds__(kBlock) void wjag_split_kernel(const int64_t *rp, c
     }
     ps += cnt;
   }
-  if (lane < nr) wdiag[r0 + rank] = dg;
-  if (mixed || ndiag > 1) *(volatile int *)bad = 1;
+  if constexpr (SPLIT) {
+    if (lane < nr) wdiag[r0 + rank] = dg;
+    if (mixed || ndiag > 1) *(volatile int *)bad = 1;
+  }
 }
 
 // max over rows of sum_e |val[e]|  (on the adjoint this is ||L||_1).
@@ -1654,22 +1731,23 @@ hipError_t launch_row_blocks(const int64_t *rp, int64_t n, int64_t B, int32_t *b
 }
 
 hipError_t launch_wjag_build(const int64_t *rp, const int32_t *col, const double2 *val, int64_t n,
-                             int32_t *wcol, double2 *wval, int32_t *wlen, unsigned char *wperm,
-                             hipStream_t s) {
+                             int32_t N, int32_t *wcol, double2 *wval, int32_t *wlen,
+                             unsigned char *wperm, int32_t *wglob, hipStream_t s) {
   const int64_t nwb = (n + kWaveRows - 1) / kWaveRows;
   const int64_t grid = (nwb + kBlock / 64 - 1) / (kBlock / 64);
-  hipLaunchKernelGGL(wjag_build_kernel, dim3((unsigned)grid), dim3(kBlock), 0, s, rp, col, val, n,
-                     nwb, wcol, wval, wlen, wperm);
+  hipLaunchKernelGGL(wjag_build_kernel<false>, dim3((unsigned)grid), dim3(kBlock), 0, s, rp, col,
+                     val, n, N, nwb, wcol, wval, nullptr, nullptr, wlen, wperm, wglob, nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_wjag_split(const int64_t *rp, const int32_t *col, const double2 *val, int64_t n,
-                             int32_t *wcol, double *wcoef, double2 *wdiag, int32_t *wlen,
-                             unsigned char *wperm, int *bad, hipStream_t s) {
+                             int32_t N, int32_t *wcol, double *wcoef, double2 *wdiag,
+                             int32_t *wlen, unsigned char *wperm, int32_t *wglob, int *bad,
+                             hipStream_t s) {
   const int64_t nwb = (n + kWaveRows - 1) / kWaveRows;
   const int64_t grid = (nwb + kBlock / 64 - 1) / (kBlock / 64);
-  hipLaunchKernelGGL(wjag_split_kernel, dim3((unsigned)grid), dim3(kBlock), 0, s, rp, col, val, n,
-                     nwb, wcol, wcoef, wdiag, wlen, wperm, bad);
+  hipLaunchKernelGGL(wjag_build_kernel<true>, dim3((unsigned)grid), dim3(kBlock), 0, s, rp, col,
+                     val, n, N, nwb, wcol, nullptr, wcoef, wdiag, wlen, wperm, wglob, bad);
   return hipGetLastError();
 }
 

@@ -114,6 +114,7 @@ struct SpmvArgs {
   const float2 *wdiag32; //   its complex64 copy
   const int32_t *wlen;
   const unsigned char *wperm;
+  const int32_t *wglob;  // per block: first position inside the rho-row, or -1 (may be null)
   const double2 *x;      // gathered vector (NRHS interleaved columns for the estimator)
   const double2 *fin;    // accumulator in (Taylor mode)
   double2 *fout;         // accumulator out (may equal fin)
@@ -222,17 +223,22 @@ hipError_t launch_to_f32(float *dst, const double *src, int64_t n, hipStream_t s
 hipError_t launch_row_blocks(const int64_t *rp, int64_t n, int64_t B, int32_t *blk, int64_t nblk,
                              hipStream_t s);
 
-// Wave-jagged layout of a CSR (n rows): one wavefront per 64-row block.
+// Wave-jagged layout of a CSR (n rows, graph order N): one wavefront per
+// 64-row block; inside each row the entries outside the row's rho-row first.
+// wglob[k] (one per block): the position G at which every row of block k
+// passes from entries outside its rho-row to entries inside it, when all its
+// rows share one rho-row and such a G exists; else -1.
 hipError_t launch_wjag_build(const int64_t *rp, const int32_t *col, const double2 *val, int64_t n,
-                             int32_t *wcol, double2 *wval, int32_t *wlen, unsigned char *wperm,
-                             hipStream_t s);
+                             int32_t N, int32_t *wcol, double2 *wval, int32_t *wlen,
+                             unsigned char *wperm, int32_t *wglob, hipStream_t s);
 // The same layout with phase-split values (n <= 2^30): wcoef per entry,
 // wdiag per row (zero for a row without a diagonal entry).  Sets *bad
 // (zeroed by the caller) when an off-diagonal entry has a non-zero real and
 // imaginary part, or a row holds its diagonal more than once.
 hipError_t launch_wjag_split(const int64_t *rp, const int32_t *col, const double2 *val, int64_t n,
-                             int32_t *wcol, double *wcoef, double2 *wdiag, int32_t *wlen,
-                             unsigned char *wperm, int *bad, hipStream_t s);
+                             int32_t N, int32_t *wcol, double *wcoef, double2 *wdiag,
+                             int32_t *wlen, unsigned char *wperm, int32_t *wglob, int *bad,
+                             hipStream_t s);
 
 // Engine: wave-jagged traversal 0 (plain), 100 (rho-row staged in LDS) or
 // 200 (staged, XCD-banded), plus 1 for single-precision values and 10 for

@@ -435,6 +435,7 @@ struct WaveLayout {
   bool split = false;
   int32_t *len = nullptr;
   unsigned char *perm = nullptr;
+  int32_t *glob = nullptr;
   int64_t nwb = 0;
   void release() {
     dfree(col);
@@ -443,13 +444,14 @@ struct WaveLayout {
     dfree(diag);
     dfree(len);
     dfree(perm);
+    dfree(glob);
   }
 };
 
 // Phase-split values unless an off-diagonal entry is neither real nor
 // imaginary (then complex values), or QSW_SPLIT=0.
 hipError_t build_wave_layout(const int64_t *rp, const int32_t *col, const double2 *val, int64_t n,
-                             int64_t nnz, hipStream_t s, WaveLayout &W) {
+                             int64_t nnz, int32_t N, hipStream_t s, WaveLayout &W) {
   hipError_t e;
   // kWavePad zero entries (column 0, value 0) after the last one: the
   // product loops read up to 63 entries past a block's end
@@ -458,6 +460,7 @@ hipError_t build_wave_layout(const int64_t *rp, const int32_t *col, const double
   if ((e = dalloc(&W.len, (size_t)n)) != hipSuccess) return e;
   if ((e = dalloc(&W.perm, (size_t)n)) != hipSuccess) return e;
   W.nwb = (n + kWaveRows - 1) / kWaveRows;
+  if ((e = dalloc(&W.glob, (size_t)W.nwb)) != hipSuccess) return e;
   if (n <= kSplitMaxN && env_int("QSW_SPLIT", 1) != 0) {
     int *bad = nullptr;
     int hbad = 1;
@@ -467,7 +470,8 @@ hipError_t build_wave_layout(const int64_t *rp, const int32_t *col, const double
       if ((e = dalloc(&W.coef, (size_t)nnz + kWavePad)) != hipSuccess) break;
       if ((e = launch_zero(W.coef + nnz, kWavePad * sizeof(double), s)) != hipSuccess) break;
       if ((e = dalloc(&W.diag, (size_t)n)) != hipSuccess) break;
-      if ((e = launch_wjag_split(rp, col, val, n, W.col, W.coef, W.diag, W.len, W.perm, bad, s)) !=
+      if ((e = launch_wjag_split(rp, col, val, n, N, W.col, W.coef, W.diag, W.len, W.perm, W.glob,
+                                   bad, s)) !=
           hipSuccess)
         break;
       if ((e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess)
@@ -485,7 +489,7 @@ hipError_t build_wave_layout(const int64_t *rp, const int32_t *col, const double
   }
   if ((e = dalloc(&W.val, (size_t)nnz + kWavePad)) != hipSuccess) return e;
   if ((e = launch_zero(W.val + nnz, kWavePad * sizeof(double2), s)) != hipSuccess) return e;
-  return launch_wjag_build(rp, col, val, n, W.col, W.val, W.len, W.perm, s);
+  return launch_wjag_build(rp, col, val, n, N, W.col, W.val, W.len, W.perm, W.glob, s);
 }
 
 void set_wave(SpmvArgs &a, const WaveLayout &W) {
@@ -496,6 +500,7 @@ void set_wave(SpmvArgs &a, const WaveLayout &W) {
   a.wdiag = W.diag;
   a.wlen = W.len;
   a.wperm = W.perm;
+  a.wglob = W.glob;
 }
 
 void set_wave(SpmvArgs &a, const qsw_superop_s *h) {
@@ -510,6 +515,7 @@ void set_wave(SpmvArgs &a, const qsw_superop_s *h) {
   a.wdiag32 = h->wdiag32;
   a.wlen = h->wlen;
   a.wperm = h->wperm;
+  a.wglob = h->wglob;
 }
 
 // The XCD-banded engine needs N/64 blocks per rho-row in 8 bands and at most
@@ -867,7 +873,7 @@ qsw_status_t build_common(std::shared_ptr<Assembler> src, double omega, hipStrea
     h->blocks_per_wg = L.bpw;
     // wave-jagged copy for the product kernels
     WaveLayout W;
-    hipError_t we = build_wave_layout(h->row_ptr, h->col, h->val, h->n, h->nnz, s, W);
+    hipError_t we = build_wave_layout(h->row_ptr, h->col, h->val, h->n, h->nnz, N, s, W);
     h->wcol = W.col;
     h->wval = W.val;
     h->wcoef = W.coef;
@@ -875,6 +881,7 @@ qsw_status_t build_common(std::shared_ptr<Assembler> src, double omega, hipStrea
     h->split = W.split;
     h->wlen = W.len;
     h->wperm = W.perm;
+    h->wglob = W.glob;
     if (we != hipSuccess) return fail(status_of(we));
     h->nwb = W.nwb;
     const int eng = env_int("QSW_ENGINE", 0);
@@ -925,7 +932,7 @@ qsw_status_t build_common(std::shared_ptr<Assembler> src, double omega, hipStrea
     }
     if (!(norm1 > 0.0)) break;  // L = 0: every d_p is 0
     // adjoint wave-jagged layout (transient)
-    if ((e = build_wave_layout(arp, acol, aval, n, annz, s, WA)) != hipSuccess) break;
+    if ((e = build_wave_layout(arp, acol, aval, n, annz, N, s, WA)) != hipSuccess) break;
     E.n = n;
     E.s = s;
     E.fwd.n = n; E.fwd.rp = h->row_ptr; E.fwd.col = h->col; E.fwd.val = h->val;
@@ -1529,6 +1536,7 @@ void qsw_superop_destroy(qsw_superop_t h) {
   dfree(h->wdiag32);
   dfree(h->wlen);
   dfree(h->wperm);
+  dfree(h->wglob);
   if (h->ev_start) (void)hipEventDestroy(h->ev_start);
   if (h->ev_end) (void)hipEventDestroy(h->ev_end);
   delete h;
