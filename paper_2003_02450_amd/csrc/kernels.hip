@@ -339,7 +339,7 @@ __device__ __forceinline__ void stream_engine(const SpmvArgs &a, Epi &epi) {
 // Positions in flight per lane: six for one or two right-hand sides, three
 // for four (each gathered element then takes 16 registers).
 template <int NRHS>
-constexpr int wave_unroll() { return NRHS <= 2 ? 6 : 3; }
+constexpr int wave_unroll() { return NRHS <= 2 ? 8 : 3; }
 
 // A wave-uniform 64-bit value (taken from lane 0) in scalar registers.
 __device__ __forceinline__ int64_t uniform64(int64_t v) {
@@ -352,6 +352,10 @@ __device__ __forceinline__ int64_t uniform64(int64_t v) {
 // right-hand sides), global memory, the staged rho-row, global memory before
 // a split position and LDS after it, or per lane through generic loads.
 enum { kGatherAny = 0, kGatherGlobal, kGatherLds, kGatherSplitAt, kGatherPerLane };
+
+__device__ __forceinline__ double2 masked(bool keep, double2 v) {
+  return make_double2(keep ? v.x : 0.0, keep ? v.y : 0.0);
+}
 
 // Complex value of an entry: stored (complex layouts) or rebuilt from the
 // phase-split coefficient, with scalar selects only.
@@ -454,7 +458,7 @@ __device__ __forceinline__ void wave_block(const SpmvArgs &a, int64_t k, Epi &ep
       for (int u = 0; u < kWaveUnroll; ++u) v[u] = decode<SPLIT>(c[u], cf[u], v[u], dg);
 #pragma unroll
       for (int u = 0; u < kWaveUnroll; ++u) {
-        const double2 vz = ok[u] ? v[u] : make_double2(0.0, 0.0);
+        const double2 vz = masked(ok[u], v[u]);
         if constexpr (STAGE) {  // SOA with the block's rho-row of every column staged
           const uint64_t o = (uint64_t)((int64_t)col[u] - base);
           const bool in_row = staged && o < (uint64_t)a.N;
@@ -490,8 +494,7 @@ __device__ __forceinline__ void wave_block(const SpmvArgs &a, int64_t k, Epi &ep
       }
 #pragma unroll
       for (int u = 0; u < kWaveUnroll; ++u)
-        cmac(acc[0], acc[1], ok[u] ? decode<SPLIT>(c[u], cf[u], v[u], dg) : make_double2(0.0, 0.0),
-             xv[u]);
+        cmac(acc[0], acc[1], masked(ok[u], decode<SPLIT>(c[u], cf[u], v[u], dg)), xv[u]);
     }
   };
   if constexpr (STAGE && !SOA) {
