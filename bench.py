@@ -10,12 +10,13 @@ the workspace are resident before the timed region starts.
 
 Prints one JSON line.  `value` is rho(t) grid steps per second of the whole
 pass.  `roofline` rates the fused Taylor-term product kernel: algorithmic
-bytes of the products it computed (per product 12 nnz + 8 (n+1) + 16 n +
-64 n with phase-split values: one real coefficient and a column per entry,
-row data, the complex diagonal per row, x, the term and the accumulator;
-20 nnz + 8 (n+1) + 64 n with complex values) over the device time of the
-timed propagate calls, measured with HIP events on the stream the kernels
-run on.  `single_values` repeats the pass with
+bytes of the products it computed (per product 12 e + 16 s + 8 (n+1) +
+16 n + 64 n with phase-split values: one real coefficient and a column per
+stored entry e, the entries shared by the 64 rows of a block s, row data,
+the complex diagonal per row, x, the term and the accumulator; 20 nnz +
+8 (n+1) + 64 n with complex values) over the device time of the timed
+propagate calls, measured with HIP events on the stream the kernels run
+on.  `single_values` repeats the pass with
 the superoperator values stored as complex64 and the 2^-24 tolerance
 (vectors and sums stay double) and reports its rate, its product kernel's
 bandwidth and its largest deviation from the double pass.  `batched` runs 64
@@ -64,17 +65,20 @@ def measured_traffic():
         return None
 
 
-def term_bytes(n: int, nnz: int, split: bool, single: bool, series: bool = False) -> float:
+def term_bytes(info: dict, single: bool, series: bool = False) -> float:
     """Algorithmic HBM bytes of one Taylor-term product (the library's own
-    qsw_stats_t.bytes per product): column index and value per entry (4 + 8
-    phase-split double, 4 + 4 phase-split single, 4 + 16 / 4 + 8 complex),
-    row data 8 (n+1), the diagonal per row with phase-split values (16 or
-    8 n), x gathered once, the new term written, the accumulator read and
-    written (the time-series branch writes the power and accumulates in a
-    second pass: 16 n more)."""
+    qsw_stats_t.bytes per product): column index and value per stored entry
+    (4 + 8 phase-split double, 4 + 4 phase-split single, 4 + 16 / 4 + 8
+    complex), 16 bytes per block-shared entry (stored once for the 64 rows of
+    a block), row data 8 (n+1), the diagonal per row with phase-split values
+    (16 or 8 n), x gathered once, the new term written, the accumulator read
+    and written (the time-series branch writes the power and accumulates in
+    a second pass: 16 n more)."""
+    n, split = info["n"], info["split"]
     entry = (8.0 if single else 12.0) if split else (12.0 if single else 20.0)
     diag = (8.0 if single else 16.0) if split else 0.0
-    return entry * nnz + 8.0 * (n + 1) + (diag + (80.0 if series else 64.0)) * n
+    return (entry * info["stream_entries"] + 16.0 * info["shared_entries"] + 8.0 * (n + 1) +
+            (diag + (80.0 if series else 64.0)) * n)
 
 
 def cpu_baseline(wl, sample_steps: int) -> dict:
@@ -118,7 +122,7 @@ def single_leg(args, one_pass, out64, torch, n, nnz, q, wl) -> dict:
     products = sum(s["products"] for s, _ in stats)
     launched = sum(s["launched"] for s, _ in stats)
     st0, info0 = stats[0]
-    per = term_bytes(n, nnz, info0["split"], True, st0["branch"] == 1)
+    per = term_bytes(info0, True, st0["branch"] == 1)
     assert abs(per * products - sum(s["bytes"] for s, _ in stats)) <= 1e-6 * per * products
     achieved = products * per / (prop_ms * 1e-3) / 1e9
     diff = float((out32 - out64).abs().max().item())
@@ -313,8 +317,9 @@ def main() -> int:
     products = sum(s["products"] for s, _ in stats)
     launched = sum(s["launched"] for s, _ in stats)
     build_ms = sum(i["build_ms"] for _, i in stats) / len(stats)
-    split = stats[0][1]["split"]
-    per_product = term_bytes(n, nnz, split, False)
+    info0 = stats[0][1]
+    split = info0["split"]
+    per_product = term_bytes(info0, False)
     bytes_total = products * per_product
     assert abs(bytes_total - sum(s["bytes"] for s, _ in stats)) <= 1e-6 * bytes_total
     achieved = bytes_total / (prop_ms * 1e-3) / 1e9
@@ -339,6 +344,8 @@ def main() -> int:
                    "n": n, "nnz": nnz, "m": st0["m"], "s": st0["s"],
                    "branch": "single-time per interval" if st0["branch"] == 0 else "series",
                    "values": "phase-split" if split else "complex",
+                   "stream_entries": info0["stream_entries"],
+                   "shared_entries": info0["shared_entries"],
                    "build_ms": round(build_ms, 3),
                    "propagate_ms": round(prop_ms / args.steps, 3),
                    "products_per_step": products // args.steps,

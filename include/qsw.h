@@ -81,6 +81,9 @@ typedef struct {
                             off-diagonal entry real or imaginary: one real coefficient
                             per entry, its phase in the column index, the complex
                             diagonal per row); 0: complex values */
+    int64_t stream_entries; /* entries the product kernels read per row (without the shared ones) */
+    int64_t shared_entries; /* entries stored once per 64-row block for all its rows (same offset
+                               from the row and same value; phase-split values only; padded) */
 } qsw_info_t;
 
 typedef struct {
@@ -94,8 +97,9 @@ typedef struct {
     int32_t nonfinite;   /* 1 if any norm in the run was NaN or infinite */
     double ms;           /* device time of the last propagate call (events on its stream) */
     double bytes;        /* algorithmic HBM bytes of the computed products: per product
-                            E nnz + 8 (n+1) + D n + (64 or 80) n for branch 0 or 1 (branch 1
-                            adds the accumulation pass), with (E, D) = (20, 0) / (12, 0) for
+                            E e + 16 s + 8 (n+1) + D n + (64 or 80) n for branch 0 or 1 (branch
+                            1 adds the accumulation pass), with e = stream_entries and s =
+                            shared_entries of qsw_info_t, and (E, D) = (20, 0) / (12, 0) for
                             complex double / single values and (12, 16) / (8, 8) for
                             phase-split double / single values (D: the diagonal per row) */
     int32_t prec;        /* QSW_PREC_* the call ran with */

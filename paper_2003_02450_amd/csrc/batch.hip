@@ -372,6 +372,10 @@ qsw_status_t qsw_engine_submit(qsw_engine_t e, const qsw_walk_t *w, int64_t *tic
   I.wcoef32 = h->wcoef32;
   I.wdiag = h->wdiag;
   I.wdiag32 = h->wdiag32;
+  I.wstart = h->wstart;
+  I.wshn = h->wshared > 0 ? h->wshn : nullptr;
+  I.wshs = h->wshs;
+  I.wsh = h->wsh;
   I.split = h->split ? 1 : 0;
   I.wlen = h->wlen;
   I.wperm = h->wperm;

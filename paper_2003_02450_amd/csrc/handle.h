@@ -97,6 +97,12 @@ struct qsw_superop_s {
   int32_t *wlen = nullptr;
   unsigned char *wperm = nullptr;
   int32_t *wglob = nullptr;       // per block: where its rows leave the gathers outside the rho-row
+  int32_t *wshn = nullptr;        // per block: shared leading positions
+  int64_t *wstart = nullptr;      // per block: first per-row entry
+  int64_t *wshs = nullptr;        // per block: first shared entry (padded prefix)
+  qsw::SharedEntry *wsh = nullptr;
+  int64_t wentries = 0;           // per-row entries stored
+  int64_t wshared = 0;            // shared entries stored (padded)
   int64_t nwb = 0;
   // last propagate
   hipEvent_t ev_start = nullptr, ev_end = nullptr;

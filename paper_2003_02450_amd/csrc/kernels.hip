@@ -126,6 +126,18 @@ __device__ __forceinline__ double load_stream(const float *p) {
 
 typedef float fvec2 __attribute__((ext_vector_type(2)));
 
+// A block-shared entry as one 16-byte load.
+template <>
+__device__ __forceinline__ SharedEntry gld<SharedEntry>(const SharedEntry *p) {
+  const dvec2 v = *(const QSW_GLOBAL dvec2 *)p;
+  const unsigned long long head = (unsigned long long)__double_as_longlong(v.x);
+  SharedEntry e;
+  e.off = (int32_t)(uint32_t)head;
+  e.flags = (uint32_t)(head >> 32);
+  e.coef = v.y;
+  return e;
+}
+
 template <>
 __device__ __forceinline__ float2 gld<float2>(const float2 *p) {
   const fvec2 v = *(const QSW_GLOBAL fvec2 *)p;
@@ -390,9 +402,18 @@ __device__ __forceinline__ void wave_block(const SpmvArgs &a, int64_t k, Epi &ep
   const int lane = threadIdx.x & 63;
   const int64_t r0 = k * kWaveRows;
   const int nr = (int)min((int64_t)kWaveRows, a.n - r0);
-  // wave-uniform: first entry of the block and the longest row (rank 0)
-  const int64_t e0 = uniform64(gld(a.rp + r0));
-  const int len = lane < nr ? gld(a.wlen + r0 + lane) : 0;
+  // wave-uniform: first stored entry of the block, its shared leading
+  // positions (gs, stored padded to gsp) and the longest row (rank 0)
+  const int64_t e0 = uniform64(a.wstart ? gld(a.wstart + k) : gld(a.rp + r0));
+  int gs = 0, gsp = 0;
+  int64_t sh0 = 0;
+  if (a.wshn) {
+    gs = __builtin_amdgcn_readfirstlane(gld(a.wshn + k));
+    sh0 = uniform64(gld(a.wshs + k));
+    gsp = (int)(uniform64(gld(a.wshs + k + 1)) - sh0);
+  }
+  // positions after the shared ones, per row
+  const int len = lane < nr ? gld(a.wlen + r0 + lane) - gs : 0;
   const int maxlen = __builtin_amdgcn_readfirstlane(len);
   const int orow = lane < nr ? (int)gld(a.wperm + r0 + lane) : 0;
   typename Epi::Pre pre{};
@@ -411,6 +432,37 @@ __device__ __forceinline__ void wave_block(const SpmvArgs &a, int64_t k, Epi &ep
   double acc[2 * NRHS];
 #pragma unroll
   for (int q = 0; q < 2 * NRHS; ++q) acc[q] = 0.0;
+  // Shared leading positions: one entry for the whole block (the same for
+  // every lane's row), gathering x at row + off from global memory.  They come
+  // first in every row, as in the per-row order, and the zero padding adds
+  // nothing, so the sums are those of the unshared layout.
+  if (gsp > 0) {
+    const int64_t row = r0 + orow;
+    constexpr int SU = NRHS == 1 ? kSharedPad : (NRHS == 2 ? kSharedPad / 2 : kSharedPad / 4);
+    static_assert(kSharedPad % SU == 0, "shared groups divide the padding");
+    for (int p = 0; p < gsp; p += SU) {
+      double2 v[SU];
+      int64_t c[SU];
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        const SharedEntry e = gld(a.wsh + sh0 + p + u);
+        const double cf = F32 ? (double)(float)e.coef : e.coef;
+        const bool im = (e.flags & kImagBit) != 0u;
+        v[u] = masked(lane < nr, make_double2(im ? 0.0 : cf, im ? cf : 0.0));
+        c[u] = row + e.off;
+      }
+      double2 xg[SU][NRHS];
+#pragma unroll
+      for (int u = 0; u < SU; ++u)
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r)
+          xg[u][r] = gld(a.x + (SOA ? (int64_t)r * a.n + c[u] : c[u] * NRHS + r));
+#pragma unroll
+      for (int u = 0; u < SU; ++u)
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r) cmac(acc[2 * r], acc[2 * r + 1], v[u], xg[u][r]);
+    }
+  }
   // Branch-free groups of kWaveUnroll positions.  Position p's entries start
   // at the wave-uniform offset ps_p, so lane l reads entry e0 + ps_p + l
   // whether or not its row is still running (entries past the row belong to
@@ -504,7 +556,7 @@ __device__ __forceinline__ void wave_block(const SpmvArgs &a, int64_t k, Epi &ep
     // position G (wglob[k] = G, else -1), positions < G gather from global
     // memory and the rest from the staged rho-row.  Other blocks choose per
     // lane with generic loads.
-    const int G = a.wglob ? __builtin_amdgcn_readfirstlane(gld(a.wglob + k)) : -1;
+    const int G = a.wglob ? __builtin_amdgcn_readfirstlane(gld(a.wglob + k)) - gs : -1;
     const int64_t rho = r0 / a.N * a.N;
     const bool regular = G >= 0 && (uint64_t)(rho - base) < lim;
     int p0 = 0;
@@ -785,100 +837,177 @@ __global__ void row_blocks_kernel(const int64_t *rp, int64_t n, int64_t B, int32
 
 // Wave-jagged layout of a CSR, one wavefront per 64-row block: rank the
 // rows by length (longest first, ties by row), then scatter the entries
-// position-major (entry p of rank r at e0 + entries of positions < p + r).
-// Inside each row the entries outside the row's own rho-row (columns c N + b
-// of the H rho part, population transfer) come first and those inside it
-// (the rho H part and the diagonal) last, each group in column order: all
-// rows of a block share their rho-row, so every position of the block
-// gathers from global memory for all rows or from the staged rho-row for all
-// rows.
-// SPLIT: phase-split values (wcoef, wdiag; *bad set when an off-diagonal
-// entry has a non-zero real and imaginary part or a row holds its diagonal
-// twice); otherwise complex values (wval).
-template <bool SPLIT>
-__global__ __launch_bounds__(kBlock) void wjag_build_kernel(const int64_t *rp, const int32_t *col,
-                                                            const double2 *val, int64_t n,
-                                                            int32_t N, int64_t nwb,
-                                                            int32_t *wcol, double2 *wval,
-                                                            double *wcoef, double2 *wdiag,
-                                                            int32_t *wlen, unsigned char *wperm,
-                                                            int32_t *wglob, int *bad) {
+// position-major (entry p of rank r at the block's start + entries of
+// positions < p + r).  Inside each row the entries outside the row's own
+// rho-row (columns c N + b of the H rho part, population transfer) come first
+// and those inside it (the rho H part and the diagonal) last, each group in
+// column order: all rows of a block share their rho-row, so every position of
+// the block gathers from global memory for all rows or from the staged
+// rho-row for all rows.  Leading positions whose entry has the same offset
+// from its row and the same value in every row of the block are stored once
+// for the block (SharedEntry) when phase-split values are built.
+
+// Row of lane `lane` in its block: CSR start, length (-1 for lanes past the
+// last row) and the number of its entries outside its rho-row.
+struct WjagRow {
+  int64_t row, src0;
+  int len, outside;
+  int32_t N, rho_row;
+  __device__ bool inside(const int32_t *col, int i) const { return col[src0 + i] / N == rho_row; }
+};
+
+__device__ __forceinline__ WjagRow wjag_row(const int64_t *rp, const int32_t *col, int64_t r0,
+                                            int nr, int32_t N, int lane) {
+  WjagRow w;
+  w.row = r0 + lane;
+  w.src0 = lane < nr ? rp[w.row] : 0;
+  w.len = lane < nr ? (int)(rp[w.row + 1] - w.src0) : -1;
+  w.N = N;
+  w.rho_row = (int32_t)(w.row / N);
+  w.outside = 0;
+  for (int i = 0; i < w.len; ++i) w.outside += !w.inside(col, i);
+  return w;
+}
+
+// CSR index of the row's entry q in the outside-first order (io, ii: cursors
+// over its outside and inside entries, advanced in order of q).
+__device__ __forceinline__ int64_t wjag_next(const int32_t *col, const WjagRow &w, int q, int &io,
+                                             int &ii) {
+  if (q < w.outside) {
+    while (w.inside(col, io)) ++io;
+    return w.src0 + io++;
+  }
+  while (!w.inside(col, ii)) ++ii;
+  return w.src0 + ii++;
+}
+
+__device__ __forceinline__ bool same_bits(double x, double y) {
+  return __double_as_longlong(x) == __double_as_longlong(y);
+}
+
+template <bool SHARED>
+__global__ __launch_bounds__(kBlock) void wjag_plan_kernel(const int64_t *rp, const int32_t *col,
+                                                           const double2 *val, int64_t n,
+                                                           int32_t N, int64_t nwb, int32_t *wglob,
+                                                           int32_t *wshn, int64_t *wcnt) {
   const int lane = threadIdx.x & 63;
   const int64_t k = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   if (k >= nwb) return;  // the whole wavefront leaves together
   const int64_t r0 = k * kWaveRows;
   const int nr = (int)min((int64_t)kWaveRows, n - r0);
-  const int64_t e0 = rp[r0];
-  const int64_t src0 = lane < nr ? rp[r0 + lane] : 0;
-  const int len = lane < nr ? (int)(rp[r0 + lane + 1] - src0) : -1;  // padding lanes rank last
+  const WjagRow w = wjag_row(rp, col, r0, nr, N, lane);
+  // G = fewest outside entries of a non-empty row; the block is regular when
+  // its rows share one rho-row and every row longer than G has exactly G
+  int G = 1 << 30, gmin = 1 << 30;
+  for (int j = 0; j < 64; ++j) {
+    const int lj = __shfl(w.len, j, 64), oj = __shfl(w.outside, j, 64);
+    if (lj > 0 && oj < G) G = oj;
+    if (lj >= 0 && oj < gmin) gmin = oj;
+  }
+  if (G == (1 << 30)) G = 0;
+  if (gmin == (1 << 30)) gmin = 0;
+  const bool odd = w.len > G && w.outside != G;
+  const bool regular = __ballot(odd) == 0 && r0 / N == (r0 + nr - 1) / N;
+  // shared leading positions: same offset from the row and same real or
+  // imaginary value in every row of the block
+  int gs = 0;
+  if constexpr (SHARED) {
+    int io = 0, ii = 0;
+    for (int q = 0; q < gmin; ++q) {
+      int64_t rel = 0;
+      double2 v = make_double2(0.0, 0.0);
+      if (lane < nr) {
+        const int64_t e = wjag_next(col, w, q, io, ii);
+        rel = (int64_t)col[e] - w.row;
+        v = val[e];
+      }
+      const int64_t rel0 = __shfl(rel, 0, 64);
+      const double vx0 = __shfl(v.x, 0, 64), vy0 = __shfl(v.y, 0, 64);
+      const bool ok = lane >= nr || (rel == rel0 && same_bits(v.x, vx0) && same_bits(v.y, vy0) &&
+                                     (v.x == 0.0 || v.y == 0.0));
+      if (__ballot(!ok) != 0) break;
+      ++gs;
+    }
+  }
+  long long cnt = lane < nr ? (long long)(w.len - gs) : 0;
+  for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+  if (lane == 0) {
+    wglob[k] = regular ? G : -1;
+    wshn[k] = gs;
+    wcnt[k] = cnt;
+  }
+}
+
+template <bool SPLIT>
+__global__ __launch_bounds__(kBlock) void wjag_fill_kernel(
+    const int64_t *rp, const int32_t *col, const double2 *val, int64_t n, int32_t N, int64_t nwb,
+    const int32_t *wshn, const int64_t *wstart, const int64_t *wshs, int32_t *wcol, double2 *wval,
+    double *wcoef, double2 *wdiag, int32_t *wlen, unsigned char *wperm, SharedEntry *wsh,
+    int *bad) {
+  const int lane = threadIdx.x & 63;
+  const int64_t k = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  if (k >= nwb) return;
+  const int64_t r0 = k * kWaveRows;
+  const int nr = (int)min((int64_t)kWaveRows, n - r0);
+  const WjagRow w = wjag_row(rp, col, r0, nr, N, lane);
   int rank = 0;
   int maxlen = 0;
   for (int j = 0; j < 64; ++j) {
-    const int lj = __shfl(len, j, 64);
-    rank += (lj > len) || (lj == len && j < lane);
+    const int lj = __shfl(w.len, j, 64);
+    rank += (lj > w.len) || (lj == w.len && j < lane);
     maxlen = lj > maxlen ? lj : maxlen;
   }
   if (lane < nr) {
-    wlen[r0 + rank] = len;
+    wlen[r0 + rank] = w.len;
     wperm[r0 + rank] = (unsigned char)lane;
   }
-  const int64_t row = r0 + lane;
-  const int32_t rho_row = (int32_t)(row / N);
-  auto inside = [&](int i) { return col[src0 + i] / N == rho_row; };
-  int outside = 0;  // entries of this row outside its rho-row
-  for (int i = 0; i < len; ++i) outside += !inside(i);
-  // G = fewest outside entries of a non-empty row; the block is regular when
-  // its rows share one rho-row and every row longer than G has exactly G
-  int G = 1 << 30;
-  for (int j = 0; j < 64; ++j) {
-    const int lj = __shfl(len, j, 64), oj = __shfl(outside, j, 64);
-    if (lj > 0 && oj < G) G = oj;
-  }
-  if (G == (1 << 30)) G = 0;
-  const bool odd = len > G && outside != G;
-  const bool regular = __ballot(odd) == 0 && r0 / N == (r0 + nr - 1) / N;
-  if (lane == 0) wglob[k] = regular ? G : -1;
-  int io = 0, ii = 0;  // cursors over the outside / inside entries
+  const int gs = wshn[k];
+  const int64_t e0 = wstart[k];
   double2 dg = make_double2(0.0, 0.0);
   int ndiag = 0;
   bool mixed = false;
+  int io = 0, ii = 0;
   int ps = 0;
   for (int p = 0; p < maxlen; ++p) {
-    const int cnt = __popcll(__ballot(len > p));
-    if (len > p) {
-      int src;
-      if (p < outside) {
-        while (inside(io)) ++io;
-        src = io++;
+    const int cnt = __popcll(__ballot(w.len > p));
+    if (w.len > p) {
+      const int64_t e = wjag_next(col, w, p, io, ii);
+      const int32_t cc = col[e];
+      const double2 vv = val[e];
+      if (p < gs) {  // the same in every row: lane 0 stores it for the block
+        if (lane == 0) {
+          const bool im = vv.x == 0.0 && vv.y != 0.0;
+          wsh[wshs[k] + p] =
+              SharedEntry{(int32_t)((int64_t)cc - w.row), im ? kImagBit : 0u, im ? vv.y : vv.x};
+        }
       } else {
-        while (!inside(ii)) ++ii;
-        src = ii++;
-      }
-      const int64_t dst = e0 + ps + rank;
-      const int32_t cc = col[src0 + src];
-      const double2 vv = val[src0 + src];
-      if constexpr (!SPLIT) {
-        wcol[dst] = cc;
-        wval[dst] = vv;
-      } else if (cc == row) {
-        dg = vv;
-        ++ndiag;
-        wcol[dst] = (int32_t)((uint32_t)cc | kDiagBit);
-        wcoef[dst] = 0.0;
-      } else if (vv.x != 0.0 && vv.y != 0.0) {
-        mixed = true;
-        wcol[dst] = cc;
-        wcoef[dst] = 0.0;
-      } else if (vv.x == 0.0 && vv.y != 0.0) {
-        wcol[dst] = (int32_t)((uint32_t)cc | kImagBit);
-        wcoef[dst] = vv.y;
-      } else {
-        wcol[dst] = cc;
-        wcoef[dst] = vv.x;
+        const int64_t dst = e0 + ps + rank;
+        if constexpr (!SPLIT) {
+          wcol[dst] = cc;
+          wval[dst] = vv;
+        } else if (cc == w.row) {
+          dg = vv;
+          ++ndiag;
+          wcol[dst] = (int32_t)((uint32_t)cc | kDiagBit);
+          wcoef[dst] = 0.0;
+        } else if (vv.x != 0.0 && vv.y != 0.0) {
+          mixed = true;
+          wcol[dst] = cc;
+          wcoef[dst] = 0.0;
+        } else if (vv.x == 0.0 && vv.y != 0.0) {
+          wcol[dst] = (int32_t)((uint32_t)cc | kImagBit);
+          wcoef[dst] = vv.y;
+        } else {
+          wcol[dst] = cc;
+          wcoef[dst] = vv.x;
+        }
       }
     }
-    ps += cnt;
+    if (p >= gs) ps += cnt;
   }
+  // zero entries up to the padded count
+  if (lane == 0)
+    for (int64_t q = wshs[k] + gs; q < wshs[k + 1]; ++q) wsh[q] = SharedEntry{0, 0u, 0.0};
   if constexpr (SPLIT) {
     if (lane < nr) wdiag[r0 + rank] = dg;
     if (mixed || ndiag > 1) *(volatile int *)bad = 1;
@@ -1618,6 +1747,10 @@ __global__ __launch_bounds__(kBlock, (R >= 2 ? 4 : 1)) void batch_work_kernel(Ba
         a.wcoef32 = I.wcoef32;
         a.wdiag = I.wdiag;
         a.wdiag32 = I.wdiag32;
+        a.wstart = I.wstart;
+        a.wshn = I.wshn;
+        a.wshs = I.wshs;
+        a.wsh = I.wsh;
         a.wlen = I.wlen;
         a.wperm = I.wperm;
         a.nwb = I.nwb;
@@ -1733,24 +1866,35 @@ hipError_t launch_row_blocks(const int64_t *rp, int64_t n, int64_t B, int32_t *b
   return hipGetLastError();
 }
 
-hipError_t launch_wjag_build(const int64_t *rp, const int32_t *col, const double2 *val, int64_t n,
-                             int32_t N, int32_t *wcol, double2 *wval, int32_t *wlen,
-                             unsigned char *wperm, int32_t *wglob, hipStream_t s) {
+hipError_t launch_wjag_plan(const int64_t *rp, const int32_t *col, const double2 *val, int64_t n,
+                            int32_t N, bool shared, int32_t *wglob, int32_t *wshn, int64_t *wcnt,
+                            hipStream_t s) {
   const int64_t nwb = (n + kWaveRows - 1) / kWaveRows;
   const int64_t grid = (nwb + kBlock / 64 - 1) / (kBlock / 64);
-  hipLaunchKernelGGL(wjag_build_kernel<false>, dim3((unsigned)grid), dim3(kBlock), 0, s, rp, col,
-                     val, n, N, nwb, wcol, wval, nullptr, nullptr, wlen, wperm, wglob, nullptr);
+  if (shared)
+    hipLaunchKernelGGL(wjag_plan_kernel<true>, dim3((unsigned)grid), dim3(kBlock), 0, s, rp, col,
+                       val, n, N, nwb, wglob, wshn, wcnt);
+  else
+    hipLaunchKernelGGL(wjag_plan_kernel<false>, dim3((unsigned)grid), dim3(kBlock), 0, s, rp, col,
+                       val, n, N, nwb, wglob, wshn, wcnt);
   return hipGetLastError();
 }
 
-hipError_t launch_wjag_split(const int64_t *rp, const int32_t *col, const double2 *val, int64_t n,
-                             int32_t N, int32_t *wcol, double *wcoef, double2 *wdiag,
-                             int32_t *wlen, unsigned char *wperm, int32_t *wglob, int *bad,
-                             hipStream_t s) {
+hipError_t launch_wjag_fill(const int64_t *rp, const int32_t *col, const double2 *val, int64_t n,
+                            int32_t N, bool split, const int32_t *wshn, const int64_t *wstart,
+                            const int64_t *wshs, int32_t *wcol, double2 *wval, double *wcoef,
+                            double2 *wdiag, int32_t *wlen, unsigned char *wperm, SharedEntry *wsh,
+                            int *bad, hipStream_t s) {
   const int64_t nwb = (n + kWaveRows - 1) / kWaveRows;
   const int64_t grid = (nwb + kBlock / 64 - 1) / (kBlock / 64);
-  hipLaunchKernelGGL(wjag_build_kernel<true>, dim3((unsigned)grid), dim3(kBlock), 0, s, rp, col,
-                     val, n, N, nwb, wcol, nullptr, wcoef, wdiag, wlen, wperm, wglob, bad);
+  if (split)
+    hipLaunchKernelGGL(wjag_fill_kernel<true>, dim3((unsigned)grid), dim3(kBlock), 0, s, rp, col,
+                       val, n, N, nwb, wshn, wstart, wshs, wcol, wval, wcoef, wdiag, wlen, wperm,
+                       wsh, bad);
+  else
+    hipLaunchKernelGGL(wjag_fill_kernel<false>, dim3((unsigned)grid), dim3(kBlock), 0, s, rp, col,
+                       val, n, N, nwb, wshn, wstart, wshs, wcol, wval, wcoef, wdiag, wlen, wperm,
+                       wsh, bad);
   return hipGetLastError();
 }
 

@@ -90,6 +90,21 @@ constexpr uint32_t kDiagBit = 0x40000000u;  // value wdiag[row]
 constexpr int32_t kColMask = 0x3fffffff;
 constexpr int64_t kSplitMaxN = (int64_t)1 << 30;
 
+// Block-shared positions (phase-split layouts).  When every row of a 64-row
+// block has, at leading position p, an entry at the same offset from its own
+// row (column = row + off) with the same value (as the H rho part does: all
+// rows of a block share their rho-row a, and entry p is c_p N + b with value
+// -i (1 - omega) H_a,c_p), the position is stored once for the block instead
+// of once per row.  A block's shared positions are padded with zero entries
+// (off 0, value 0) to a multiple of kSharedPad.
+struct SharedEntry {
+  int32_t off;     // column - row
+  uint32_t flags;  // kImagBit: value i coef
+  double coef;
+};
+constexpr int kSharedPad = 8;
+static_assert(sizeof(SharedEntry) == 16, "a shared entry is read as one 16-byte load");
+
 struct SpmvArgs {
   int64_t n;
   const int64_t *rp;
@@ -115,6 +130,10 @@ struct SpmvArgs {
   const int32_t *wlen;
   const unsigned char *wperm;
   const int32_t *wglob;  // per block: first position inside the rho-row, or -1 (may be null)
+  const int64_t *wstart; // per block: first per-row entry (with shared positions), or null: rp
+  const int32_t *wshn;   // per block: shared leading positions (null: none)
+  const int64_t *wshs;   //   first shared entry of block k (nwb + 1 prefix, padded counts)
+  const SharedEntry *wsh;
   const double2 *x;      // gathered vector (NRHS interleaved columns for the estimator)
   const double2 *fin;    // accumulator in (Taylor mode)
   double2 *fout;         // accumulator out (may equal fin)
@@ -152,6 +171,10 @@ struct BatchInst {
   const float2 *wdiag32;
   const int32_t *wlen;
   const unsigned char *wperm;
+  const int64_t *wstart;
+  const int32_t *wshn;
+  const int64_t *wshs;
+  const SharedEntry *wsh;
   int64_t n, nwb;
   int64_t vlen;      // n * R: complex elements of one work vector
   int32_t N, f32, split;  // f32: single-precision values; split: phase-split values
@@ -223,22 +246,27 @@ hipError_t launch_to_f32(float *dst, const double *src, int64_t n, hipStream_t s
 hipError_t launch_row_blocks(const int64_t *rp, int64_t n, int64_t B, int32_t *blk, int64_t nblk,
                              hipStream_t s);
 
-// Wave-jagged layout of a CSR (n rows, graph order N): one wavefront per
+// Wave-jagged layout of a CSR (n rows, graph order N), one wavefront per
 // 64-row block; inside each row the entries outside the row's rho-row first.
-// wglob[k] (one per block): the position G at which every row of block k
-// passes from entries outside its rho-row to entries inside it, when all its
-// rows share one rho-row and such a G exists; else -1.
-hipError_t launch_wjag_build(const int64_t *rp, const int32_t *col, const double2 *val, int64_t n,
-                             int32_t N, int32_t *wcol, double2 *wval, int32_t *wlen,
-                             unsigned char *wperm, int32_t *wglob, hipStream_t s);
-// The same layout with phase-split values (n <= 2^30): wcoef per entry,
-// wdiag per row (zero for a row without a diagonal entry).  Sets *bad
-// (zeroed by the caller) when an off-diagonal entry has a non-zero real and
-// imaginary part, or a row holds its diagonal more than once.
-hipError_t launch_wjag_split(const int64_t *rp, const int32_t *col, const double2 *val, int64_t n,
-                             int32_t N, int32_t *wcol, double *wcoef, double2 *wdiag,
-                             int32_t *wlen, unsigned char *wperm, int32_t *wglob, int *bad,
-                             hipStream_t s);
+// Plan: wglob[k] (the position G at which every row of block k passes from
+// entries outside its rho-row to entries inside it, when all its rows share
+// one rho-row and such a G exists; else -1), wshn[k] (shared leading
+// positions; 0 unless `shared`, which needs phase-split values) and wcnt[k]
+// (per-row entries of the block after them).
+hipError_t launch_wjag_plan(const int64_t *rp, const int32_t *col, const double2 *val, int64_t n,
+                            int32_t N, bool shared, int32_t *wglob, int32_t *wshn, int64_t *wcnt,
+                            hipStream_t s);
+// Fill, from the plan's prefix sums wstart (per-row entries) and wshs
+// (padded shared entries): complex values (wval) unless `split`, then
+// phase-split values (wcoef per entry, wdiag per row, zero for a row without
+// a diagonal entry; *bad, zeroed by the caller, is set when an off-diagonal
+// entry has a non-zero real and imaginary part or a row holds its diagonal
+// more than once).
+hipError_t launch_wjag_fill(const int64_t *rp, const int32_t *col, const double2 *val, int64_t n,
+                            int32_t N, bool split, const int32_t *wshn, const int64_t *wstart,
+                            const int64_t *wshs, int32_t *wcol, double2 *wval, double *wcoef,
+                            double2 *wdiag, int32_t *wlen, unsigned char *wperm, SharedEntry *wsh,
+                            int *bad, hipStream_t s);
 
 // Engine: wave-jagged traversal 0 (plain), 100 (rho-row staged in LDS) or
 // 200 (staged, XCD-banded), plus 1 for single-precision values and 10 for

@@ -426,7 +426,8 @@ struct Estimator {
 };
 
 // Wave-jagged execution layout (see kWaveRows) of one CSR.
-// Complex values (val) or phase-split values (coef, diag; split = true).
+// Complex values (val) or phase-split values (coef, diag; split = true),
+// with block-shared leading positions (sh) when split.
 struct WaveLayout {
   int32_t *col = nullptr;
   double2 *val = nullptr;
@@ -436,60 +437,114 @@ struct WaveLayout {
   int32_t *len = nullptr;
   unsigned char *perm = nullptr;
   int32_t *glob = nullptr;
+  int32_t *shn = nullptr;
+  int64_t *start = nullptr, *shs = nullptr;
+  SharedEntry *sh = nullptr;
   int64_t nwb = 0;
-  void release() {
+  int64_t entries = 0;  // per-row entries stored (without the shared positions)
+  int64_t shared = 0;   // shared entries stored (padded)
+  void release_values() {
     dfree(col);
     dfree(val);
     dfree(coef);
     dfree(diag);
+    dfree(sh);
+  }
+  void release() {
+    release_values();
     dfree(len);
     dfree(perm);
     dfree(glob);
+    dfree(shn);
+    dfree(start);
+    dfree(shs);
   }
 };
 
-// Phase-split values unless an off-diagonal entry is neither real nor
-// imaginary (then complex values), or QSW_SPLIT=0.
+// Phase-split values with block-shared positions unless an off-diagonal
+// entry is neither real nor imaginary (then complex values); QSW_SPLIT=0 and
+// QSW_SHARED=0 turn either off.
 hipError_t build_wave_layout(const int64_t *rp, const int32_t *col, const double2 *val, int64_t n,
                              int64_t nnz, int32_t N, hipStream_t s, WaveLayout &W) {
+  (void)nnz;
   hipError_t e;
-  // kWavePad zero entries (column 0, value 0) after the last one: the
-  // product loops read up to 63 entries past a block's end
-  if ((e = dalloc(&W.col, (size_t)nnz + kWavePad)) != hipSuccess) return e;
-  if ((e = launch_zero(W.col + nnz, kWavePad * sizeof(int32_t), s)) != hipSuccess) return e;
+  W.nwb = (n + kWaveRows - 1) / kWaveRows;
+  const size_t nwb = (size_t)W.nwb;
   if ((e = dalloc(&W.len, (size_t)n)) != hipSuccess) return e;
   if ((e = dalloc(&W.perm, (size_t)n)) != hipSuccess) return e;
-  W.nwb = (n + kWaveRows - 1) / kWaveRows;
-  if ((e = dalloc(&W.glob, (size_t)W.nwb)) != hipSuccess) return e;
-  if (n <= kSplitMaxN && env_int("QSW_SPLIT", 1) != 0) {
-    int *bad = nullptr;
-    int hbad = 1;
+  if ((e = dalloc(&W.glob, nwb)) != hipSuccess) return e;
+  if ((e = dalloc(&W.shn, nwb)) != hipSuccess) return e;
+  if ((e = dalloc(&W.start, nwb + 1)) != hipSuccess) return e;
+  if ((e = dalloc(&W.shs, nwb + 1)) != hipSuccess) return e;
+  int64_t *cnt = nullptr;
+  int *bad = nullptr;
+  if ((e = dalloc(&cnt, nwb)) != hipSuccess) return e;
+  if ((e = dalloc(&bad, 1)) != hipSuccess) {
+    dfree(cnt);
+    return e;
+  }
+  std::vector<int32_t> hshn(nwb);
+  std::vector<int64_t> hcnt(nwb), hstart(nwb + 1), hshs(nwb + 1);
+  const bool try_split = n <= kSplitMaxN && env_int("QSW_SPLIT", 1) != 0;
+  for (int attempt = try_split ? 1 : 0; attempt >= 0; --attempt) {
+    const bool split = attempt == 1;
+    const bool shared = split && env_int("QSW_SHARED", 1) != 0;
+    int hbad = 0;
     do {
-      if ((e = dalloc(&bad, 1)) != hipSuccess) break;
-      if ((e = launch_zero(bad, sizeof(int), s)) != hipSuccess) break;
-      if ((e = dalloc(&W.coef, (size_t)nnz + kWavePad)) != hipSuccess) break;
-      if ((e = launch_zero(W.coef + nnz, kWavePad * sizeof(double), s)) != hipSuccess) break;
-      if ((e = dalloc(&W.diag, (size_t)n)) != hipSuccess) break;
-      if ((e = launch_wjag_split(rp, col, val, n, N, W.col, W.coef, W.diag, W.len, W.perm, W.glob,
-                                   bad, s)) !=
+      if ((e = launch_wjag_plan(rp, col, val, n, N, shared, W.glob, W.shn, cnt, s)) != hipSuccess)
+        break;
+      if ((e = hipMemcpyAsync(hshn.data(), W.shn, nwb * sizeof(int32_t), hipMemcpyDeviceToHost,
+                              s)) != hipSuccess)
+        break;
+      if ((e = hipMemcpyAsync(hcnt.data(), cnt, nwb * sizeof(int64_t), hipMemcpyDeviceToHost, s)) !=
           hipSuccess)
+        break;
+      if ((e = hipStreamSynchronize(s)) != hipSuccess) break;
+      hstart[0] = hshs[0] = 0;
+      for (size_t k = 0; k < nwb; ++k) {
+        hstart[k + 1] = hstart[k] + hcnt[k];
+        hshs[k + 1] = hshs[k] + (hshn[k] + kSharedPad - 1) / kSharedPad * kSharedPad;
+      }
+      W.entries = hstart[nwb];
+      W.shared = hshs[nwb];
+      if ((e = hipMemcpyAsync(W.start, hstart.data(), (nwb + 1) * sizeof(int64_t),
+                              hipMemcpyHostToDevice, s)) != hipSuccess)
+        break;
+      if ((e = hipMemcpyAsync(W.shs, hshs.data(), (nwb + 1) * sizeof(int64_t),
+                              hipMemcpyHostToDevice, s)) != hipSuccess)
+        break;
+      // kWavePad zero entries (column 0, value 0) after the last one: the
+      // product loops read up to 63 entries past a block's end
+      const size_t ent = (size_t)W.entries + kWavePad;
+      if ((e = dalloc(&W.col, ent)) != hipSuccess) break;
+      if ((e = launch_zero(W.col + W.entries, kWavePad * sizeof(int32_t), s)) != hipSuccess) break;
+      if (split) {
+        if ((e = dalloc(&W.coef, ent)) != hipSuccess) break;
+        if ((e = launch_zero(W.coef + W.entries, kWavePad * sizeof(double), s)) != hipSuccess) break;
+        if ((e = dalloc(&W.diag, (size_t)n)) != hipSuccess) break;
+      } else {
+        if ((e = dalloc(&W.val, ent)) != hipSuccess) break;
+        if ((e = launch_zero(W.val + W.entries, kWavePad * sizeof(double2), s)) != hipSuccess) break;
+      }
+      if ((e = dalloc(&W.sh, std::max<size_t>(1, (size_t)W.shared))) != hipSuccess) break;
+      if ((e = launch_zero(bad, sizeof(int), s)) != hipSuccess) break;
+      if ((e = launch_wjag_fill(rp, col, val, n, N, split, W.shn, W.start, W.shs, W.col, W.val,
+                                W.coef, W.diag, W.len, W.perm, W.sh, bad, s)) != hipSuccess)
         break;
       if ((e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess)
         break;
       e = hipStreamSynchronize(s);
     } while (false);
-    dfree(bad);
-    if (e != hipSuccess) return e;
-    if (!hbad) {
-      W.split = true;
-      return hipSuccess;
+    if (e != hipSuccess) break;
+    if (!split || !hbad) {
+      W.split = split;
+      break;
     }
-    dfree(W.coef);
-    dfree(W.diag);
+    W.release_values();  // an entry neither real nor imaginary: complex values
   }
-  if ((e = dalloc(&W.val, (size_t)nnz + kWavePad)) != hipSuccess) return e;
-  if ((e = launch_zero(W.val + nnz, kWavePad * sizeof(double2), s)) != hipSuccess) return e;
-  return launch_wjag_build(rp, col, val, n, N, W.col, W.val, W.len, W.perm, W.glob, s);
+  dfree(cnt);
+  dfree(bad);
+  return e;
 }
 
 void set_wave(SpmvArgs &a, const WaveLayout &W) {
@@ -501,6 +556,10 @@ void set_wave(SpmvArgs &a, const WaveLayout &W) {
   a.wlen = W.len;
   a.wperm = W.perm;
   a.wglob = W.glob;
+  a.wstart = W.start;
+  a.wshn = W.shared > 0 ? W.shn : nullptr;
+  a.wshs = W.shs;
+  a.wsh = W.sh;
 }
 
 void set_wave(SpmvArgs &a, const qsw_superop_s *h) {
@@ -516,6 +575,10 @@ void set_wave(SpmvArgs &a, const qsw_superop_s *h) {
   a.wlen = h->wlen;
   a.wperm = h->wperm;
   a.wglob = h->wglob;
+  a.wstart = h->wstart;
+  a.wshn = h->wshared > 0 ? h->wshn : nullptr;
+  a.wshs = h->wshs;
+  a.wsh = h->wsh;
 }
 
 // The XCD-banded engine needs N/64 blocks per rho-row in 8 bands and at most
@@ -882,6 +945,12 @@ qsw_status_t build_common(std::shared_ptr<Assembler> src, double omega, hipStrea
     h->wlen = W.len;
     h->wperm = W.perm;
     h->wglob = W.glob;
+    h->wshn = W.shn;
+    h->wstart = W.start;
+    h->wshs = W.shs;
+    h->wsh = W.sh;
+    h->wentries = W.entries;
+    h->wshared = W.shared;
     if (we != hipSuccess) return fail(status_of(we));
     h->nwb = W.nwb;
     const int eng = env_int("QSW_ENGINE", 0);
@@ -978,6 +1047,8 @@ qsw_status_t build_common(std::shared_ptr<Assembler> src, double omega, hipStrea
   h->info.omega = omega;
   h->info.norm_products = E.products;
   h->info.split = h->split ? 1 : 0;
+  h->info.stream_entries = h->wentries;
+  h->info.shared_entries = h->wshared;
   if (hipEventCreate(&h->ev_start) != hipSuccess || hipEventCreate(&h->ev_end) != hipSuccess)
     return fail(QSW_ERR_DEVICE);
   if (dalloc(&h->stats_dev, 2) != hipSuccess) return fail(QSW_ERR_OOM);
@@ -1537,6 +1608,10 @@ void qsw_superop_destroy(qsw_superop_t h) {
   dfree(h->wlen);
   dfree(h->wperm);
   dfree(h->wglob);
+  dfree(h->wshn);
+  dfree(h->wstart);
+  dfree(h->wshs);
+  dfree(h->wsh);
   if (h->ev_start) (void)hipEventDestroy(h->ev_start);
   if (h->ev_end) (void)hipEventDestroy(h->ev_end);
   delete h;
@@ -1552,14 +1627,15 @@ qsw_status_t qsw_superop_set_precision(qsw_superop_t h, int32_t prec) {
       return QSW_ERR_STATE;  // the single-precision copy exists for the wave layout only
     // the padding converts to zeros as well
     hipStream_t s = nullptr;
+    const int64_t ent = h->wentries + kWavePad;
     if (h->split) {
-      HIP_TRY(dalloc(&h->wcoef32, (size_t)h->nnz + kWavePad));
+      HIP_TRY(dalloc(&h->wcoef32, (size_t)ent));
       HIP_TRY(dalloc(&h->wdiag32, (size_t)h->n));
-      HIP_TRY(launch_to_f32(h->wcoef32, h->wcoef, h->nnz + kWavePad, s));
+      HIP_TRY(launch_to_f32(h->wcoef32, h->wcoef, ent, s));
       HIP_TRY(launch_to_c64(h->wdiag32, h->wdiag, h->n, s));
     } else {
-      HIP_TRY(dalloc(&h->wval32, (size_t)h->nnz + kWavePad));
-      HIP_TRY(launch_to_c64(h->wval32, h->wval, h->nnz + kWavePad, s));
+      HIP_TRY(dalloc(&h->wval32, (size_t)ent));
+      HIP_TRY(launch_to_c64(h->wval32, h->wval, ent, s));
     }
     HIP_TRY(hipStreamSynchronize(s));
   } else if (prec == QSW_PREC_DOUBLE && have32) {
@@ -1791,8 +1867,10 @@ qsw_status_t qsw_last_stats(qsw_superop_t h, qsw_stats_t *st) {
   const double entry = split ? (single ? 8.0 : 12.0) : (single ? 12.0 : 20.0);
   const double diag = split ? (single ? 8.0 : 16.0) : 0.0;
   const double vec = h->last.branch == 1 ? 80.0 : 64.0;  // power + separate accumulation
-  h->last.bytes = (double)h->last.products *
-                  (entry * (double)h->nnz + 8.0 * (double)(h->n + 1) + (diag + vec) * (double)h->n);
+  const double entries = is_wave_engine(h->engine) ? (double)h->wentries : (double)h->nnz;
+  const double shared = is_wave_engine(h->engine) ? 16.0 * (double)h->wshared : 0.0;
+  h->last.bytes = (double)h->last.products * (entry * entries + shared + 8.0 * (double)(h->n + 1) +
+                                              (diag + vec) * (double)h->n);
   *st = h->last;
   return h->last.nonfinite ? QSW_ERR_NONFINITE : QSW_OK;
 }

@@ -4,7 +4,10 @@ product kernels read one real coefficient per entry, the phase in the column
 index and the complex diagonal per row.  The complex value is rebuilt before
 the same multiply-adds, so results equal the complex layout's (QSW_SPLIT=0)
 element for element (np.array_equal: up to the sign of zeros), in both
-precisions and both branches, and the 1-norm estimates are the same."""
+precisions and both branches, and the 1-norm estimates are the same.  Block-
+shared leading positions (stored once per 64-row block when every row has
+the same offset and value there) keep each row's order of summation, so
+they change nothing either (QSW_SHARED=0 turns them off)."""
 import numpy as np
 import pytest
 
@@ -98,3 +101,28 @@ def test_complex_entries_fall_back():
     op = qsw.Superop.from_general(H, [np.array([[0, 1.0, 0], [0, 0, 0], [0, 0, 0]])], 0.5)
     assert not op.info()["split"]
     op.close()
+
+
+@pytest.mark.parametrize("single", [False, True])
+def test_shared_positions_change_nothing(monkeypatch, single):
+    import torch
+    wl = random_workload(256, 6, 0.35, 815, n_steps=3, dt=0.5)
+    monkeypatch.delenv("QSW_SHARED", raising=False)
+    sh = build_gpu(wl)
+    monkeypatch.setenv("QSW_SHARED", "0")
+    un = build_gpu(wl)
+    monkeypatch.delenv("QSW_SHARED", raising=False)
+    i_sh, i_un = sh.info(), un.info()
+    assert i_sh["split"] and i_un["split"]
+    assert i_sh["shared_entries"] > 0 and i_un["shared_entries"] == 0
+    assert i_sh["stream_entries"] < i_un["stream_entries"] == i_un["nnz"]
+    assert i_sh["d"] == i_un["d"] and i_sh["norm1"] == i_un["norm1"]
+    for op in (sh, un):
+        op.set_precision(single)
+    a = sh.propagate(wl.rho0, wl.t0, wl.dt, wl.n_steps).cpu().numpy()
+    b = un.propagate(wl.rho0, wl.t0, wl.dt, wl.n_steps).cpu().numpy()
+    torch.cuda.synchronize()
+    assert np.isfinite(a).all()
+    assert np.array_equal(a, b)
+    sh.close()
+    un.close()
