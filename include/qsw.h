@@ -84,6 +84,9 @@ typedef struct {
     int64_t stream_entries; /* entries the product kernels read per row (without the shared ones) */
     int64_t shared_entries; /* entries stored once per 64-row block for all its rows (same offset
                                from the row and same value; phase-split values only; padded) */
+    int64_t distinct_entries; /* per-row entries in the copies the blocks read: blocks whose
+                                 stored rows are word for word equal (columns as offsets from
+                                 the row) read one copy */
 } qsw_info_t;
 
 typedef struct {

@@ -49,7 +49,8 @@ class Info(ctypes.Structure):
                 ("d", ctypes.c_double * 10), ("d_index", ctypes.c_int64 * 10),
                 ("d_probe", ctypes.c_int32 * 10), ("norm_products", ctypes.c_int32),
                 ("build_ms", ctypes.c_double), ("split", ctypes.c_int32),
-                ("stream_entries", ctypes.c_int64), ("shared_entries", ctypes.c_int64)]
+                ("stream_entries", ctypes.c_int64), ("shared_entries", ctypes.c_int64),
+                ("distinct_entries", ctypes.c_int64)]
 
 
 class Stats(ctypes.Structure):

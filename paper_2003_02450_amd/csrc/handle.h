@@ -103,6 +103,7 @@ struct qsw_superop_s {
   qsw::SharedEntry *wsh = nullptr;
   int64_t wentries = 0;           // per-row entries stored
   int64_t wshared = 0;            // shared entries stored (padded)
+  int64_t wdistinct = 0;          // per-row entries in the copies the blocks read
   int64_t nwb = 0;
   // last propagate
   hipEvent_t ev_start = nullptr, ev_end = nullptr;

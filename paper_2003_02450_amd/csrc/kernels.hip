@@ -365,6 +365,17 @@ __device__ __forceinline__ int64_t uniform64(int64_t v) {
 // a split position and LDS after it, or per lane through generic loads.
 enum { kGatherAny = 0, kGatherGlobal, kGatherLds, kGatherSplitAt, kGatherPerLane };
 
+// Column offset of a stored entry (column - row).
+template <bool SPLIT>
+__device__ __forceinline__ int64_t entry_offset(int raw) {
+  if constexpr (SPLIT)
+    return (int64_t)((int32_t)((uint32_t)raw << 2) >> 2);
+  else
+    return (int64_t)raw;
+}
+
+// v, or zero where !keep: per-component selects (a conditional expression on
+// double2 itself is compiled to a branch around its operands).
 __device__ __forceinline__ double2 masked(bool keep, double2 v) {
   return make_double2(keep ? v.x : 0.0, keep ? v.y : 0.0);
 }
@@ -466,10 +477,12 @@ __device__ __forceinline__ void wave_block(const SpmvArgs &a, int64_t k, Epi &ep
   // Branch-free groups of kWaveUnroll positions.  Position p's entries start
   // at the wave-uniform offset ps_p, so lane l reads entry e0 + ps_p + l
   // whether or not its row is still running (entries past the row belong to
-  // other rows, the next block or the zero padding after the arrays: always a
-  // valid column) and discards the product when it is not.  With no branch
-  // around them, every load of a group is issued before the first wait.
+  // other rows, the next block or the zero padding after the arrays: always
+  // in bounds) and discards the product when it is not, gathering x at its
+  // own row then.  With no branch around them, every load of a group is
+  // issued before the first wait.
   const int32_t *cb = a.wcol + e0;
+  const int64_t lane_row = r0 + orow;
   int ps = 0;
   int gsplit = 0;
   // one group: column indices and values, then the x gathers (MODE), then
@@ -500,10 +513,12 @@ __device__ __forceinline__ void wave_block(const SpmvArgs &a, int64_t k, Epi &ep
         cf[u] = 0.0;  // unused
       }
     }
-    int col[kWaveUnroll];
+    // a lane past its row's end read another row's entry: its offset is
+    // relative to that row, so the lane gathers at its own row instead
+    int64_t col[kWaveUnroll];
 #pragma unroll
     for (int u = 0; u < kWaveUnroll; ++u)
-      col[u] = SPLIT ? (int)((uint32_t)c[u] & (uint32_t)kColMask) : c[u];
+      col[u] = lane_row + (ok[u] ? entry_offset<SPLIT>(c[u]) : 0);
     if constexpr (MODE == kGatherAny) {
       // no staging, or several right-hand sides
 #pragma unroll
@@ -982,23 +997,25 @@ __global__ __launch_bounds__(kBlock) void wjag_fill_kernel(
         }
       } else {
         const int64_t dst = e0 + ps + rank;
+        const int32_t rel = (int32_t)((int64_t)cc - w.row);
+        const uint32_t off = (uint32_t)rel & kOffMask;
         if constexpr (!SPLIT) {
-          wcol[dst] = cc;
+          wcol[dst] = rel;
           wval[dst] = vv;
         } else if (cc == w.row) {
           dg = vv;
           ++ndiag;
-          wcol[dst] = (int32_t)((uint32_t)cc | kDiagBit);
+          wcol[dst] = (int32_t)kDiagBit;
           wcoef[dst] = 0.0;
         } else if (vv.x != 0.0 && vv.y != 0.0) {
           mixed = true;
-          wcol[dst] = cc;
+          wcol[dst] = (int32_t)off;
           wcoef[dst] = 0.0;
         } else if (vv.x == 0.0 && vv.y != 0.0) {
-          wcol[dst] = (int32_t)((uint32_t)cc | kImagBit);
+          wcol[dst] = (int32_t)(off | kImagBit);
           wcoef[dst] = vv.y;
         } else {
-          wcol[dst] = cc;
+          wcol[dst] = (int32_t)off;
           wcoef[dst] = vv.x;
         }
       }
@@ -1012,6 +1029,76 @@ __global__ __launch_bounds__(kBlock) void wjag_fill_kernel(
     if (lane < nr) wdiag[r0 + rank] = dg;
     if (mixed || ndiag > 1) *(volatile int *)bad = 1;
   }
+}
+
+// Blocks whose stored rows are word for word the same (after the shared
+// positions, with columns as offsets from the row) can read one copy.  The
+// hash covers each rank's remaining length and the block's stored words;
+// equal hashes are then compared in full before a block is pointed at
+// another's copy.
+__device__ __forceinline__ unsigned long long mix64(unsigned long long h, unsigned long long v) {
+  // SplitMix64 finaliser (Steele, Lea and Flood, 2014) of h ^ v
+  unsigned long long z = h ^ v;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ unsigned long long value_word(const double *wcoef, const double2 *wval,
+                                                         int64_t i, int half) {
+  return (unsigned long long)__double_as_longlong(wcoef ? wcoef[i] : (half ? wval[i].y : wval[i].x));
+}
+
+__global__ __launch_bounds__(kBlock) void wjag_hash_kernel(const int32_t *wcol, const double *wcoef,
+                                                           const double2 *wval, const int32_t *wlen,
+                                                           const int32_t *wshn,
+                                                           const int64_t *wstart, int64_t n,
+                                                           int64_t nwb, unsigned long long *hash) {
+  const int lane = threadIdx.x & 63;
+  const int64_t k = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  if (k >= nwb) return;
+  const int64_t r0 = k * kWaveRows;
+  const int nr = (int)min((int64_t)kWaveRows, n - r0);
+  const int gs = wshn[k];
+  unsigned long long h = mix64(0x51A7E5ull + lane, lane < nr ? (unsigned)(wlen[r0 + lane] - gs) : ~0u);
+  for (int64_t i = wstart[k] + lane; i < wstart[k + 1]; i += 64) {
+    h = mix64(h, (unsigned)wcol[i]);
+    h = mix64(h, value_word(wcoef, wval, i, 0));
+    if (!wcoef) h = mix64(h, value_word(wcoef, wval, i, 1));
+  }
+  for (int off = 32; off > 0; off >>= 1) h += __shfl_xor(h, off, 64);
+  if (lane == 0) hash[k] = h;
+}
+
+// same[k] = 1 when block k's stored rows equal those of block canon[k].
+__global__ __launch_bounds__(kBlock) void wjag_same_kernel(const int32_t *wcol, const double *wcoef,
+                                                           const double2 *wval, const int32_t *wlen,
+                                                           const int32_t *wshn,
+                                                           const int64_t *wstart, int64_t n,
+                                                           int64_t nwb, const int64_t *canon,
+                                                           int *same) {
+  const int lane = threadIdx.x & 63;
+  const int64_t k = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  if (k >= nwb) return;
+  const int64_t c = canon[k];
+  if (c == k) {
+    if (lane == 0) same[k] = 0;
+    return;
+  }
+  const int64_t r0 = k * kWaveRows, q0 = c * kWaveRows;
+  const int nr = (int)min((int64_t)kWaveRows, n - r0), nq = (int)min((int64_t)kWaveRows, n - q0);
+  bool diff = nr != nq || wstart[k + 1] - wstart[k] != wstart[c + 1] - wstart[c];
+  if (!diff && lane < nr) diff = wlen[r0 + lane] - wshn[k] != wlen[q0 + lane] - wshn[c];
+  const int64_t d = wstart[c] - wstart[k];
+  if (__ballot(diff) == 0) {
+    for (int64_t i = wstart[k] + lane; i < wstart[k + 1]; i += 64) {
+      diff = diff || wcol[i] != wcol[i + d] ||
+             value_word(wcoef, wval, i, 0) != value_word(wcoef, wval, i + d, 0) ||
+             (!wcoef && value_word(wcoef, wval, i, 1) != value_word(wcoef, wval, i + d, 1));
+    }
+  }
+  const bool any = __ballot(diff) != 0;
+  if (lane == 0) same[k] = any ? 0 : 1;
 }
 
 // max over rows of sum_e |val[e]|  (on the adjoint this is ||L||_1).
@@ -1895,6 +1982,26 @@ hipError_t launch_wjag_fill(const int64_t *rp, const int32_t *col, const double2
     hipLaunchKernelGGL(wjag_fill_kernel<false>, dim3((unsigned)grid), dim3(kBlock), 0, s, rp, col,
                        val, n, N, nwb, wshn, wstart, wshs, wcol, wval, wcoef, wdiag, wlen, wperm,
                        wsh, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_wjag_hash(const int32_t *wcol, const double *wcoef, const double2 *wval,
+                            const int32_t *wlen, const int32_t *wshn, const int64_t *wstart,
+                            int64_t n, unsigned long long *hash, hipStream_t s) {
+  const int64_t nwb = (n + kWaveRows - 1) / kWaveRows;
+  const int64_t grid = (nwb + kBlock / 64 - 1) / (kBlock / 64);
+  hipLaunchKernelGGL(wjag_hash_kernel, dim3((unsigned)grid), dim3(kBlock), 0, s, wcol, wcoef, wval,
+                     wlen, wshn, wstart, n, nwb, hash);
+  return hipGetLastError();
+}
+
+hipError_t launch_wjag_same(const int32_t *wcol, const double *wcoef, const double2 *wval,
+                            const int32_t *wlen, const int32_t *wshn, const int64_t *wstart,
+                            int64_t n, const int64_t *canon, int *same, hipStream_t s) {
+  const int64_t nwb = (n + kWaveRows - 1) / kWaveRows;
+  const int64_t grid = (nwb + kBlock / 64 - 1) / (kBlock / 64);
+  hipLaunchKernelGGL(wjag_same_kernel, dim3((unsigned)grid), dim3(kBlock), 0, s, wcol, wcoef, wval,
+                     wlen, wshn, wstart, n, nwb, canon, same);
   return hipGetLastError();
 }
 

@@ -79,16 +79,20 @@ constexpr int kWaveRows = 64;
 constexpr int kWavePad = 64;  // zero entries after the wave-jagged arrays (reads past a block's end)
 constexpr size_t kStageMaxBytes = 32768;  // largest LDS-staged rho-row (N <= 2048)
 
+// The wave layout stores each entry's column as its offset from the entry's
+// row (column - row), so that blocks whose rows have the same pattern and
+// values relative to themselves store the same words.
 // Phase-split values.  Every off-diagonal entry of a graph-built L-QSW
 // superoperator is real (the rate terms) or imaginary (the Hamiltonian
 // terms): such an entry is stored as one real coefficient c, with the phase
-// (1 or i) in the top bit of its column index.  The diagonal entry of each
-// row is complex; it keeps its place in the row (flag kDiagBit) and its value
-// is read from a per-row array.  Columns then need n <= 2^30.
+// (1 or i) in the top bit of its column word and the offset in the low 30
+// bits (two's complement).  The diagonal entry of each row is complex; it
+// keeps its place in the row (flag kDiagBit) and its value is read from a
+// per-row array.  Offsets then need n <= 2^29.
 constexpr uint32_t kImagBit = 0x80000000u;  // value i c
 constexpr uint32_t kDiagBit = 0x40000000u;  // value wdiag[row]
-constexpr int32_t kColMask = 0x3fffffff;
-constexpr int64_t kSplitMaxN = (int64_t)1 << 30;
+constexpr uint32_t kOffMask = 0x3fffffffu;
+constexpr int64_t kSplitMaxN = (int64_t)1 << 29;
 
 // Block-shared positions (phase-split layouts).  When every row of a 64-row
 // block has, at leading position p, an entry at the same offset from its own
@@ -267,6 +271,16 @@ hipError_t launch_wjag_fill(const int64_t *rp, const int32_t *col, const double2
                             const int64_t *wshs, int32_t *wcol, double2 *wval, double *wcoef,
                             double2 *wdiag, int32_t *wlen, unsigned char *wperm, SharedEntry *wsh,
                             int *bad, hipStream_t s);
+
+// Block dedup: hash[k] of block k's stored rows (lengths after the shared
+// positions and its words from wstart[k] to wstart[k+1]); same[k] = 1 when
+// they equal those of block canon[k] (0 for canon[k] == k).
+hipError_t launch_wjag_hash(const int32_t *wcol, const double *wcoef, const double2 *wval,
+                            const int32_t *wlen, const int32_t *wshn, const int64_t *wstart,
+                            int64_t n, unsigned long long *hash, hipStream_t s);
+hipError_t launch_wjag_same(const int32_t *wcol, const double *wcoef, const double2 *wval,
+                            const int32_t *wlen, const int32_t *wshn, const int64_t *wstart,
+                            int64_t n, const int64_t *canon, int *same, hipStream_t s);
 
 // Engine: wave-jagged traversal 0 (plain), 100 (rho-row staged in LDS) or
 // 200 (staged, XCD-banded), plus 1 for single-precision values and 10 for

@@ -443,6 +443,7 @@ struct WaveLayout {
   int64_t nwb = 0;
   int64_t entries = 0;  // per-row entries stored (without the shared positions)
   int64_t shared = 0;   // shared entries stored (padded)
+  int64_t distinct = 0; // per-row entries in the copies the blocks read (after dedup)
   void release_values() {
     dfree(col);
     dfree(val);
@@ -461,9 +462,78 @@ struct WaveLayout {
   }
 };
 
+// Point every block whose stored rows equal an earlier block's (same
+// lengths after the shared positions, same words, same split position) at
+// that block's copy, so the blocks read one copy (cached) instead of their
+// own.  Candidates come from a hash; each is compared in full on the device.
+hipError_t dedup_blocks(WaveLayout &W, int64_t n, const std::vector<int64_t> &hcnt,
+                        const std::vector<int32_t> &hshn, const std::vector<int64_t> &hstart,
+                        hipStream_t s) {
+  const size_t nwb = (size_t)W.nwb;
+  if (nwb < 2) return hipSuccess;
+  unsigned long long *hash = nullptr;
+  int64_t *canon = nullptr;
+  int *same = nullptr;
+  hipError_t e;
+  std::vector<unsigned long long> hh(nwb);
+  std::vector<int32_t> hglob(nwb);
+  std::vector<int64_t> hcanon(nwb);
+  std::vector<int> hsame(nwb);
+  do {
+    if ((e = dalloc(&hash, nwb)) != hipSuccess) break;
+    if ((e = dalloc(&canon, nwb)) != hipSuccess) break;
+    if ((e = dalloc(&same, nwb)) != hipSuccess) break;
+    if ((e = launch_wjag_hash(W.col, W.coef, W.val, W.len, W.shn, W.start, n, hash, s)) !=
+        hipSuccess)
+      break;
+    if ((e = hipMemcpyAsync(hh.data(), hash, nwb * sizeof(unsigned long long),
+                            hipMemcpyDeviceToHost, s)) != hipSuccess)
+      break;
+    if ((e = hipMemcpyAsync(hglob.data(), W.glob, nwb * sizeof(int32_t), hipMemcpyDeviceToHost,
+                            s)) != hipSuccess)
+      break;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) break;
+    // key: hash, stored entries, split position within the stored rows
+    std::map<std::tuple<unsigned long long, int64_t, int32_t>, int64_t> first;
+    int64_t dup = 0;
+    for (size_t k = 0; k < nwb; ++k) {
+      const int32_t g = hglob[k] < 0 ? -1 : hglob[k] - hshn[k];
+      auto it = first.emplace(std::make_tuple(hh[k], hcnt[k], g), (int64_t)k).first;
+      hcanon[k] = it->second;
+      dup += it->second != (int64_t)k;
+    }
+    if (dup == 0) break;
+    if ((e = hipMemcpyAsync(canon, hcanon.data(), nwb * sizeof(int64_t), hipMemcpyHostToDevice,
+                            s)) != hipSuccess)
+      break;
+    if ((e = launch_wjag_same(W.col, W.coef, W.val, W.len, W.shn, W.start, n, canon, same, s)) !=
+        hipSuccess)
+      break;
+    if ((e = hipMemcpyAsync(hsame.data(), same, nwb * sizeof(int), hipMemcpyDeviceToHost, s)) !=
+        hipSuccess)
+      break;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) break;
+    std::vector<int64_t> start(hstart);
+    for (size_t k = 0; k < nwb; ++k)
+      if (hsame[k]) {
+        start[k] = hstart[(size_t)hcanon[k]];
+        W.distinct -= hcnt[k];
+      }
+    if ((e = hipMemcpyAsync(W.start, start.data(), nwb * sizeof(int64_t), hipMemcpyHostToDevice,
+                            s)) != hipSuccess)
+      break;
+    e = hipStreamSynchronize(s);
+  } while (false);
+  dfree(hash);
+  dfree(canon);
+  dfree(same);
+  return e;
+}
+
 // Phase-split values with block-shared positions unless an off-diagonal
-// entry is neither real nor imaginary (then complex values); QSW_SPLIT=0 and
-// QSW_SHARED=0 turn either off.
+// entry is neither real nor imaginary (then complex values); blocks with
+// equal stored rows read one copy.  QSW_SPLIT=0, QSW_SHARED=0 and
+// QSW_DEDUP=0 turn each off.
 hipError_t build_wave_layout(const int64_t *rp, const int32_t *col, const double2 *val, int64_t n,
                              int64_t nnz, int32_t N, hipStream_t s, WaveLayout &W) {
   (void)nnz;
@@ -505,7 +575,7 @@ hipError_t build_wave_layout(const int64_t *rp, const int32_t *col, const double
         hstart[k + 1] = hstart[k] + hcnt[k];
         hshs[k + 1] = hshs[k] + (hshn[k] + kSharedPad - 1) / kSharedPad * kSharedPad;
       }
-      W.entries = hstart[nwb];
+      W.entries = W.distinct = hstart[nwb];
       W.shared = hshs[nwb];
       if ((e = hipMemcpyAsync(W.start, hstart.data(), (nwb + 1) * sizeof(int64_t),
                               hipMemcpyHostToDevice, s)) != hipSuccess)
@@ -513,7 +583,7 @@ hipError_t build_wave_layout(const int64_t *rp, const int32_t *col, const double
       if ((e = hipMemcpyAsync(W.shs, hshs.data(), (nwb + 1) * sizeof(int64_t),
                               hipMemcpyHostToDevice, s)) != hipSuccess)
         break;
-      // kWavePad zero entries (column 0, value 0) after the last one: the
+      // kWavePad zero entries (offset 0, value 0) after the last one: the
       // product loops read up to 63 entries past a block's end
       const size_t ent = (size_t)W.entries + kWavePad;
       if ((e = dalloc(&W.col, ent)) != hipSuccess) break;
@@ -538,6 +608,7 @@ hipError_t build_wave_layout(const int64_t *rp, const int32_t *col, const double
     if (e != hipSuccess) break;
     if (!split || !hbad) {
       W.split = split;
+      if (env_int("QSW_DEDUP", 1) != 0) e = dedup_blocks(W, n, hcnt, hshn, hstart, s);
       break;
     }
     W.release_values();  // an entry neither real nor imaginary: complex values
@@ -951,6 +1022,7 @@ qsw_status_t build_common(std::shared_ptr<Assembler> src, double omega, hipStrea
     h->wsh = W.sh;
     h->wentries = W.entries;
     h->wshared = W.shared;
+    h->wdistinct = W.distinct;
     if (we != hipSuccess) return fail(status_of(we));
     h->nwb = W.nwb;
     const int eng = env_int("QSW_ENGINE", 0);
@@ -1049,6 +1121,7 @@ qsw_status_t build_common(std::shared_ptr<Assembler> src, double omega, hipStrea
   h->info.split = h->split ? 1 : 0;
   h->info.stream_entries = h->wentries;
   h->info.shared_entries = h->wshared;
+  h->info.distinct_entries = h->wdistinct;
   if (hipEventCreate(&h->ev_start) != hipSuccess || hipEventCreate(&h->ev_end) != hipSuccess)
     return fail(QSW_ERR_DEVICE);
   if (dalloc(&h->stats_dev, 2) != hipSuccess) return fail(QSW_ERR_OOM);

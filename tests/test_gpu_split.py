@@ -126,3 +126,29 @@ def test_shared_positions_change_nothing(monkeypatch, single):
     assert np.array_equal(a, b)
     sh.close()
     un.close()
+
+
+@pytest.mark.parametrize("single", [False, True])
+def test_block_dedup_changes_nothing(monkeypatch, single):
+    """Blocks whose stored rows are word for word equal (columns as offsets
+    from the row) read one copy; QSW_DEDUP=0 gives each block its own."""
+    import torch
+    wl = random_workload(512, 5, 0.45, 816, n_steps=3, dt=0.4)
+    monkeypatch.delenv("QSW_DEDUP", raising=False)
+    dd = build_gpu(wl)
+    monkeypatch.setenv("QSW_DEDUP", "0")
+    own = build_gpu(wl)
+    monkeypatch.delenv("QSW_DEDUP", raising=False)
+    i_dd, i_own = dd.info(), own.info()
+    assert i_dd["distinct_entries"] < i_dd["stream_entries"] == i_own["stream_entries"]
+    assert i_own["distinct_entries"] == i_own["stream_entries"]
+    assert i_dd["d"] == i_own["d"]
+    for op in (dd, own):
+        op.set_precision(single)
+    a = dd.propagate(wl.rho0, wl.t0, wl.dt, wl.n_steps).cpu().numpy()
+    b = own.propagate(wl.rho0, wl.t0, wl.dt, wl.n_steps).cpu().numpy()
+    torch.cuda.synchronize()
+    assert np.isfinite(a).all()
+    assert np.array_equal(a, b)
+    dd.close()
+    own.close()
