@@ -348,10 +348,10 @@ __device__ __forceinline__ void stream_engine(const SpmvArgs &a, Epi &epi) {
 // rebuilt as (c, 0), (0, c) or the diagonal before the same fused
 // multiply-adds, so every sum equals the complex layout's up to the sign of
 // a zero.
-// Positions in flight per lane: six for one or two right-hand sides, three
-// for four (each gathered element then takes 16 registers).
+// Positions in flight per lane: eight for one right-hand side, four for
+// two, two for four (each position's gathers then take 4 NRHS registers).
 template <int NRHS>
-constexpr int wave_unroll() { return NRHS <= 2 ? 8 : 3; }
+constexpr int wave_unroll() { return NRHS == 1 ? 8 : (NRHS == 2 ? 4 : 2); }
 
 // A wave-uniform 64-bit value (taken from lane 0) in scalar registers.
 __device__ __forceinline__ int64_t uniform64(int64_t v) {
@@ -400,9 +400,8 @@ __device__ __forceinline__ double2 decode(int raw, double cf, double2 v, double2
 // base + N).  Called by a whole wavefront.
 // SOA: the NRHS columns of x are consecutive n-vectors (element (c, r) at
 // r n + c) instead of interleaved (c NRHS + r).  With SOA and STAGE, xs holds
-// the rho-row of every column (xs[r N + i]), `staged` says whether it belongs
-// to this block's x, and each gather reads LDS or global memory through one
-// generic (flat) load.
+// the rho-row of every column (xs[r N + i]) and `staged` says whether it
+// belongs to this block's x.
 template <int NRHS, bool F32, bool STAGE, class Epi, bool SOA = false, bool SPLIT = false>
 __device__ __forceinline__ void wave_block(const SpmvArgs &a, int64_t k, Epi &epi,
                                            const double2 *xs, int64_t base, bool staged = true,
@@ -520,62 +519,65 @@ __device__ __forceinline__ void wave_block(const SpmvArgs &a, int64_t k, Epi &ep
     for (int u = 0; u < kWaveUnroll; ++u)
       col[u] = lane_row + (ok[u] ? entry_offset<SPLIT>(c[u]) : 0);
     if constexpr (MODE == kGatherAny) {
-      // no staging, or several right-hand sides
+      // no staging: global gathers first (they need the columns only), the
+      // values decoded where they are used
+      double2 xg[kWaveUnroll][NRHS];
 #pragma unroll
-      for (int u = 0; u < kWaveUnroll; ++u) v[u] = decode<SPLIT>(c[u], cf[u], v[u], dg);
+      for (int u = 0; u < kWaveUnroll; ++u)
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r)
+          xg[u][r] = gld(a.x + (SOA ? (int64_t)r * a.n + col[u] : col[u] * NRHS + r));
 #pragma unroll
       for (int u = 0; u < kWaveUnroll; ++u) {
-        const double2 vz = masked(ok[u], v[u]);
-        if constexpr (STAGE) {  // SOA with the block's rho-row of every column staged
-          const uint64_t o = (uint64_t)((int64_t)col[u] - base);
-          const bool in_row = staged && o < (uint64_t)a.N;
+        const double2 vz = masked(ok[u], decode<SPLIT>(c[u], cf[u], v[u], dg));
 #pragma unroll
-          for (int r = 0; r < NRHS; ++r) {
-            const double2 xl = xs[in_row ? r * a.N + o : 0];
-            const double2 xg = gld(a.x + (in_row ? 0 : (int64_t)r * a.n + col[u]));
-            cmac(acc[2 * r], acc[2 * r + 1], vz, in_row ? xl : xg);
-          }
-        } else {
-#pragma unroll
-          for (int r = 0; r < NRHS; ++r)
-            cmac(acc[2 * r], acc[2 * r + 1], vz,
-                 gld(a.x + (SOA ? (int64_t)r * a.n + col[u] : (int64_t)col[u] * NRHS + r)));
-        }
+        for (int r = 0; r < NRHS; ++r) cmac(acc[2 * r], acc[2 * r + 1], vz, xg[u][r]);
       }
     } else {
-      double2 xv[kWaveUnroll];
+      // staged: xs holds the staged rho-row of every column (xs[r N' + o],
+      // N' = lim for one column); column r of x at r n + col (SOA) or col
+      double2 xv[kWaveUnroll][NRHS];
 #pragma unroll
       for (int u = 0; u < kWaveUnroll; ++u) {
         const uint64_t o = (uint64_t)((int64_t)col[u] - base);
         const uint64_t oc = o < lim ? o : 0;
-        if constexpr (MODE == kGatherGlobal) {
-          xv[u] = gld(a.x + col[u]);
-        } else if constexpr (MODE == kGatherLds) {
-          xv[u] = xs[oc];
-        } else if constexpr (MODE == kGatherSplitAt) {
-          // positions before `gsplit` gather globally, the rest from LDS
-          xv[u] = *(p0 + u < gsplit ? a.x + col[u] : xs + oc);
-        } else {  // kGatherPerLane
-          xv[u] = *(o < lim ? xs + o : a.x + col[u]);
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r) {
+          const double2 *xgp = a.x + (SOA ? (int64_t)r * a.n : 0) + col[u];
+          const double2 *xlp = xs + (SOA ? (uint64_t)r * lim : 0);
+          if constexpr (MODE == kGatherGlobal)
+            xv[u][r] = gld(xgp);
+          else if constexpr (MODE == kGatherLds)
+            xv[u][r] = xlp[oc];
+          else if constexpr (MODE == kGatherSplitAt)  // before `gsplit` global, then LDS
+            xv[u][r] = *(p0 + u < gsplit ? xgp : xlp + oc);
+          else  // kGatherPerLane
+            xv[u][r] = *(o < lim ? xlp + o : xgp);
         }
       }
 #pragma unroll
-      for (int u = 0; u < kWaveUnroll; ++u)
-        cmac(acc[0], acc[1], masked(ok[u], decode<SPLIT>(c[u], cf[u], v[u], dg)), xv[u]);
+      for (int u = 0; u < kWaveUnroll; ++u) {
+        const double2 vz = masked(ok[u], decode<SPLIT>(c[u], cf[u], v[u], dg));
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r) cmac(acc[2 * r], acc[2 * r + 1], vz, xv[u][r]);
+      }
     }
   };
-  if constexpr (STAGE && !SOA) {
-    static_assert(NRHS == 1, "staging holds one right-hand side");
+  if constexpr (STAGE) {
     // The layout puts each row's entries outside its rho-row first; in a
     // block whose rows share one rho-row and all leave it at the same
     // position G (wglob[k] = G, else -1), positions < G gather from global
     // memory and the rest from the staged rho-row.  Other blocks choose per
-    // lane with generic loads.
+    // lane with generic loads, and blocks whose rho-row is not staged (SOA:
+    // `staged` false) gather from global memory throughout.
     const int G = a.wglob ? __builtin_amdgcn_readfirstlane(gld(a.wglob + k)) - gs : -1;
     const int64_t rho = r0 / a.N * a.N;
     const bool regular = G >= 0 && (uint64_t)(rho - base) < lim;
     int p0 = 0;
-    if (regular) {
+    if (SOA && !staged) {
+      for (; p0 < maxlen; p0 += kWaveUnroll)
+        group(std::integral_constant<int, kGatherGlobal>{}, p0);
+    } else if (regular) {
       const int gend = min(G, maxlen);
       for (; p0 + kWaveUnroll <= gend; p0 += kWaveUnroll)
         group(std::integral_constant<int, kGatherGlobal>{}, p0);
