@@ -246,6 +246,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-sample-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pace", type=int, default=2,
+                    help="launch pacing lookahead of the single-walk passes (0: off)")
     ap.add_argument("--no-single", action="store_true",
                     help="skip the complex64-values leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-walks leg")
@@ -295,6 +297,7 @@ def main() -> int:
 
     def one_pass(single=False, dst=out):
         op = build()
+        op.set_pacing(args.pace)
         if single:
             op.set_precision(True)
         op.propagate(rho0, wl.t0, wl.dt, q, out=dst, workspace=ws)
@@ -346,6 +349,7 @@ def main() -> int:
                    "values": "phase-split" if split else "complex",
                    "stream_entries": info0["stream_entries"],
                    "shared_entries": info0["shared_entries"],
+                   "launch_pacing": args.pace,
                    "build_ms": round(build_ms, 3),
                    "propagate_ms": round(prop_ms / args.steps, 3),
                    "products_per_step": products // args.steps,

@@ -266,6 +266,23 @@ qsw_status_t qsw_superop_info(qsw_superop_t h, qsw_info_t *info);
  */
 qsw_status_t qsw_superop_set_precision(qsw_superop_t h, int32_t prec);
 
+/*
+ * Launch pacing of later qsw_propagate calls on this handle (default 0: off).
+ * The single-time branch launches up to m Taylor terms per scaling step and
+ * the terms after the one that passes the stopping test (Al-Mohy and
+ * Higham's two-term test) exit at once; each such launch still costs a few
+ * microseconds.  With lookahead > 0 every term launch posts to a pinned host
+ * word that its predecessor has ended and whether the step passed the test
+ * after it, and qsw_propagate keeps at most `lookahead` term launches beyond
+ * the last one known to have ended (2 or more keeps the device busy),
+ * enqueuing no further terms of a step once it has passed the test.  The
+ * results are the same.  qsw_propagate then returns only when its last
+ * launches are enqueued (it waits on the device meanwhile), and paced calls
+ * on one handle are serialised.  Allocates 256 bytes of pinned host memory
+ * on first use.  QSW_ERR_ARG for lookahead outside 0..4096.
+ */
+qsw_status_t qsw_superop_set_pacing(qsw_superop_t h, int32_t lookahead);
+
 /* Launch configuration of the product kernels, as chosen by qsw_superop_autotune. */
 typedef struct {
     int32_t staged;          /* 1: the rho-row is staged in LDS for the rho H gathers;

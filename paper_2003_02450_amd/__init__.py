@@ -264,6 +264,16 @@ class Superop:
         _lib.check(st, "qsw_superop_copy_csr")
         return rp, col, val
 
+    def set_pacing(self, lookahead: int):
+        """lookahead > 0: later propagate calls keep at most that many Taylor
+        term launches in flight and enqueue no further terms of a scaling
+        step once it has passed the stopping test (the call then returns
+        when its last launches are enqueued); 0 turns pacing off."""
+        torch = _torch()
+        with torch.cuda.device(self.device):
+            st = _lib.load().qsw_superop_set_pacing(self._h, int(lookahead))
+        _lib.check(st, "qsw_superop_set_pacing")
+
     def set_precision(self, single: bool):
         """single=True: later propagate calls read single-precision
         superoperator values (each real and imaginary part rounded to nearest)

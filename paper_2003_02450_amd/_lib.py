@@ -27,6 +27,7 @@ EXPORTED = ("qsw_superop_build", "qsw_superop_build_ops", "qsw_superop_build_cha
             "qsw_demoralised_populations",
             "qsw_superop_destroy",
             "qsw_superop_info", "qsw_superop_set_precision", "qsw_superop_autotune",
+            "qsw_superop_set_pacing",
             "qsw_superop_copy_csr", "qsw_propagate_workspace_bytes",
             "qsw_propagate", "qsw_last_stats", "qsw_apply", "qsw_populations", "qsw_theta",
             "qsw_select_params", "qsw_status_str", "qsw_version", "qsw_walk_bytes",
@@ -132,6 +133,8 @@ def load() -> ctypes.CDLL:
     L.qsw_superop_destroy.argtypes = [_vp]
     L.qsw_superop_info.restype = _i32
     L.qsw_superop_info.argtypes = [_vp, ctypes.POINTER(Info)]
+    L.qsw_superop_set_pacing.restype = _i32
+    L.qsw_superop_set_pacing.argtypes = [_vp, _i32]
     L.qsw_superop_set_precision.restype = _i32
     L.qsw_superop_set_precision.argtypes = [_vp, _i32]
     L.qsw_superop_autotune.restype = _i32

@@ -10,6 +10,7 @@
 #include <cstddef>
 #include <cstdlib>
 #include <memory>
+#include <mutex>
 
 namespace qsw {
 
@@ -111,6 +112,13 @@ struct qsw_superop_s {
   qsw_stats_t last{};
   bool have_last = false;
   std::shared_ptr<qsw::Assembler> src;  // kept for qsw_superop_set_omega
+  // paced term launches (qsw_superop_set_pacing): at most `pace` ahead of the
+  // device; the device posts progress to a pinned host word
+  int pace = 0;
+  unsigned long long *pace_host = nullptr;  // pinned, coherent
+  unsigned long long *pace_dev = nullptr;   // its device address
+  unsigned long long pace_seq = 0;          // last paced launch number
+  std::unique_ptr<std::mutex> pace_mu;
 };
 
 namespace qsw {

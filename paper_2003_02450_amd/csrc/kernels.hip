@@ -869,8 +869,11 @@ __global__ void row_blocks_kernel(const int64_t *rp, int64_t n, int64_t B, int32
 struct WjagRow {
   int64_t row, src0;
   int len, outside;
-  int32_t N, rho_row;
-  __device__ bool inside(const int32_t *col, int i) const { return col[src0 + i] / N == rho_row; }
+  int64_t rho0;  // first column of the row's rho-row
+  int32_t N;
+  __device__ bool inside(const int32_t *col, int i) const {
+    return (uint64_t)((int64_t)col[src0 + i] - rho0) < (uint64_t)N;
+  }
 };
 
 __device__ __forceinline__ WjagRow wjag_row(const int64_t *rp, const int32_t *col, int64_t r0,
@@ -880,7 +883,7 @@ __device__ __forceinline__ WjagRow wjag_row(const int64_t *rp, const int32_t *co
   w.src0 = lane < nr ? rp[w.row] : 0;
   w.len = lane < nr ? (int)(rp[w.row + 1] - w.src0) : -1;
   w.N = N;
-  w.rho_row = (int32_t)(w.row / N);
+  w.rho0 = w.row / N * N;
   w.outside = 0;
   for (int i = 0; i < w.len; ++i) w.outside += !w.inside(col, i);
   return w;
@@ -1155,20 +1158,31 @@ __global__ void copy_kernel(double2 *dst, const double2 *src, int64_t n) {
 // workgroup from values written by earlier launches.
 __device__ __forceinline__ bool taylor_prologue(const SpmvArgs &a) {
   StepSlots *S = &a.st->step[a.par];
+  bool stop = false;
   if (a.j >= 2) {
-    if (*(volatile int *)&S->stop) return true;
-    const double c1 = bits_to_d(a.j == 2 ? S->b0 : S->b[a.j - 2]);
-    const double c2 = bits_to_d(S->b[a.j - 1]);
-    const double f = bits_to_d(S->f[a.j - 1]);
-    if (c1 + c2 <= a.tol * f) {
-      if (threadIdx.x == 0) *(volatile int *)&S->stop = 1;
-      return true;
+    if (*(volatile int *)&S->stop) {
+      stop = true;
+    } else {
+      const double c1 = bits_to_d(a.j == 2 ? S->b0 : S->b[a.j - 2]);
+      const double c2 = bits_to_d(S->b[a.j - 1]);
+      const double f = bits_to_d(S->f[a.j - 1]);
+      if (c1 + c2 <= a.tol * f) {
+        if (threadIdx.x == 0) *(volatile int *)&S->stop = 1;
+        stop = true;
+      }
     }
   } else if (blockIdx.x == 0) {
     // first term of a step: clear the other parity for the next step
     unsigned int *o = (unsigned int *)&a.st->step[a.par ^ 1];
     for (int i = threadIdx.x; i < (int)(sizeof(StepSlots) / 4); i += kBlock) o[i] = 0u;
   }
+  // Paced launches: launch seq - 1 has ended when this one runs, and `stop`
+  // says whether its step passed the test after it; posted to the host word
+  // (which the host alone reads: no ordering of other writes is needed).
+  if (a.progress && blockIdx.x == 0 && threadIdx.x == 0)
+    __hip_atomic_store(a.progress, ((a.seq - 1) << 1) | (stop ? 1ull : 0ull), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
+  if (stop) return true;
   if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&a.st->products, 1ull);
   return false;
 }

@@ -147,6 +147,11 @@ struct SpmvArgs {
   DeviceState *st;
   int par;               // scaling-step parity
   int j;                 // term index (1-based)
+  // paced launches (null progress: none): launch number seq posts
+  // ((seq - 1) << 1) | (the step passed its test after launch seq - 1) to
+  // this host-visible word
+  unsigned long long *progress;
+  unsigned long long seq;
 };
 
 // ---- batched propagation (several walks advance together) ----

@@ -21,6 +21,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <thread>
 #include <tuple>
 #include <new>
 #include <vector>
@@ -1188,6 +1189,32 @@ struct Runner {
   int64_t launched = 0;
   double tol;
   int engine;  // product engine of this call (value format included)
+  // paced term launches (null pace_dev: not paced)
+  unsigned long long *pace_dev = nullptr;
+  unsigned long long *pace_host = nullptr;
+  unsigned long long *seq = nullptr;
+  int pace = 0;
+  // launches up to `retired` count as finished: those of earlier calls and
+  // those of a step that has passed its test (they exit at once)
+  unsigned long long retired = 0;
+
+  // Waits until launch number `next` is at most `pace` launches ahead of the
+  // last launch known to have ended (each term launch posts its predecessor);
+  // returns true instead once the step whose first launch was `first` has
+  // passed its test (its remaining terms would exit at once).  Stops waiting
+  // when the stream has drained, as no further word can arrive then.
+  bool wait_paced(unsigned long long next, unsigned long long first) {
+    for (unsigned spins = 1;; ++spins) {
+      const unsigned long long w = __atomic_load_n(pace_host, __ATOMIC_ACQUIRE);
+      const unsigned long long done = w >> 1;
+      if ((w & 1ull) && done >= first) {
+        retired = std::max(retired, next - 1);
+        return true;
+      }
+      if (next <= std::max(done, retired) + (unsigned long long)pace) return false;
+      if ((spins & 1023u) == 0 && hipStreamQuery(s) != hipErrorNotReady) return false;
+    }
+  }
 
   SpmvArgs base_args() const {
     SpmvArgs a{};
@@ -1213,8 +1240,14 @@ struct Runner {
       const int par = (int)(gstep & 1);
       ++gstep;
       double2 *Fdst = (i == s_steps - 1) ? x_out : F[i & 1];
+      const unsigned long long first = seq ? *seq + 1 : 0;
       for (int j = 1; j <= m; ++j) {
         SpmvArgs a = base_args();
+        if (pace_dev) {
+          if (wait_paced(*seq + 1, first)) break;
+          a.progress = pace_dev;
+          a.seq = ++*seq;
+        }
         a.x = (j == 1) ? Fsrc : B[(j - 1) & 1];
         a.y = B[j & 1];
         a.fin = (j == 1) ? Fsrc : Fdst;
@@ -1657,6 +1690,12 @@ qsw_status_t qsw_superop_set_omega(qsw_superop_t h, double omega, void *hip_stre
   qsw_status_t st = build_common(h->src, omega, (hipStream_t)hip_stream, &nh);
   if (st != QSW_OK) return st;
   const int prec = h->prec;
+  // the pacing state stays with the handle
+  std::swap(h->pace, nh->pace);
+  std::swap(h->pace_host, nh->pace_host);
+  std::swap(h->pace_dev, nh->pace_dev);
+  std::swap(h->pace_seq, nh->pace_seq);
+  std::swap(h->pace_mu, nh->pace_mu);
   std::swap(*h, *nh);
   qsw_superop_destroy(nh);  // the old arrays
   if (prec == QSW_PREC_SINGLE) return qsw_superop_set_precision(h, prec);
@@ -1687,6 +1726,7 @@ void qsw_superop_destroy(qsw_superop_t h) {
   dfree(h->wsh);
   if (h->ev_start) (void)hipEventDestroy(h->ev_start);
   if (h->ev_end) (void)hipEventDestroy(h->ev_end);
+  if (h->pace_host) (void)hipHostFree(h->pace_host);
   delete h;
 }
 
@@ -1721,6 +1761,29 @@ qsw_status_t qsw_superop_set_precision(qsw_superop_t h, int32_t prec) {
     h->wdiag32 = nullptr;
   }
   h->prec = prec;
+  return QSW_OK;
+}
+
+qsw_status_t qsw_superop_set_pacing(qsw_superop_t h, int32_t lookahead) {
+  if (!h || lookahead < 0 || lookahead > 4096) return QSW_ERR_ARG;
+  DeviceGuard g(h->device);
+  if (!g.ok) return QSW_ERR_DEVICE;
+  if (lookahead > 0 && !h->pace_host) {
+    void *p = nullptr;
+    HIP_TRY(hipHostMalloc(&p, 256, hipHostMallocCoherent));
+    h->pace_host = (unsigned long long *)p;
+    *h->pace_host = 0ull;
+    void *d = nullptr;
+    if (hipHostGetDevicePointer(&d, p, 0) != hipSuccess) {
+      (void)hipHostFree(p);
+      h->pace_host = nullptr;
+      return QSW_ERR_DEVICE;
+    }
+    h->pace_dev = (unsigned long long *)d;
+    h->pace_seq = 0;
+    h->pace_mu.reset(new std::mutex);
+  }
+  h->pace = lookahead;
   return QSW_OK;
 }
 
@@ -1866,6 +1929,15 @@ qsw_status_t qsw_propagate(qsw_superop_t h, const void *rho0, double t0, double 
   R.F[1] = (double2 *)(ws + P.off_F + vec);
   R.tol = tol_of(h->prec);
   R.engine = launch_engine(h, h->prec == QSW_PREC_SINGLE);
+  std::unique_lock<std::mutex> pace_lock;
+  if (h->pace > 0 && h->pace_dev) {
+    pace_lock = std::unique_lock<std::mutex>(*h->pace_mu);
+    R.pace_dev = h->pace_dev;
+    R.pace_host = h->pace_host;
+    R.seq = &h->pace_seq;
+    R.pace = h->pace;
+    R.retired = h->pace_seq;
+  }
   double2 *outv = (double2 *)out;
   const int64_t n = h->n;
   auto slot = [&](int64_t k) { return outv + k * n; };

@@ -100,4 +100,5 @@ def test_propagate_rejects_null_handle_and_workspace_query():
     assert L.qsw_apply(None, None, None, None) == ARG
     assert L.qsw_populations(None, None, 1, None, None) == ARG
     assert L.qsw_superop_set_precision(None, 0) == ARG
+    assert L.qsw_superop_set_pacing(None, 4) == ARG
     L.qsw_superop_destroy(None)  # no-op
