@@ -323,6 +323,39 @@ struct Estimator {
   double *cand_v, *top_v;
   int64_t *cand_i, *top_i;
   int products = 0;
+  // first iteration of every estimate, from one chain of products (first_pass)
+  double2 *Sp[kPMax + 2] = {};    // sign block of A^p X0
+  double first_cs[kPMax + 2][2] = {};
+  double *first_sums = nullptr;  // device, 2 per power
+  bool have_first = false;
+
+  // The probe block X0 is the same for every p, so the first iteration's
+  // products A^p X0 (p = 2..pmax) come from one chain A X0, A^2 X0, ...: each
+  // power's column sums and sign block are kept.  The same products in the
+  // same order as in estimate(p), so the estimates are unchanged.
+  hipError_t first_pass(int pmax) {
+    const int t = n >= 2 ? 2 : 1;
+    hipError_t e = launch_probe_init(X, n, t, s);
+    if (e != hipSuccess) return e;
+    const double2 *src = X;
+    for (int q = 1; q <= pmax; ++q) {
+      double2 *dst = (q & 1) ? W0 : W1;
+      SpmvArgs a = fwd;
+      a.x = src;
+      a.y = dst;
+      e = launch_spmm2(a, fsplit, q >= 2 ? 1 : 0, part, q >= 2 ? Sp[q] : S, h, grid, s);
+      if (e != hipSuccess) return e;
+      ++products;
+      if (q >= 2 && (e = launch_sum_partials(part, grid, first_sums + 2 * q, s)) != hipSuccess)
+        return e;
+      src = dst;
+    }
+    e = hipMemcpyAsync(first_cs, first_sums, sizeof(first_cs), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(s);
+    have_first = e == hipSuccess;
+    return e;
+  }
 
   // out = (A or A^dagger)^p in; intermediates alternate between W0 and W1,
   // the epilogue `mode` runs on the last product only.
@@ -344,7 +377,8 @@ struct Estimator {
 
   hipError_t estimate(int p, double *est_out, int64_t *index_out, int *probe_out) {
     const int t = n >= 2 ? 2 : 1;
-    hipError_t e = launch_probe_init(X, n, t, s);
+    const bool first_known = have_first && Sp[p] != nullptr;
+    hipError_t e = first_known ? hipSuccess : launch_probe_init(X, n, t, s);
     if (e != hipSuccess) return e;
     double est_old = 0.0, est = 0.0;
     int64_t ind_best = -1;
@@ -353,16 +387,23 @@ struct Estimator {
     std::vector<int64_t> hist;
     const int itmax = 5;
     for (int k = 1;; ++k) {
-      // Y = A^p X, column 1-norms and S = sign(Y)
-      e = power(false, X, Y, p, 1);
-      if (e != hipSuccess) return e;
-      e = launch_sum_partials(part, grid, sums, s);
-      if (e != hipSuccess) return e;
+      // Y = A^p X, column 1-norms and S = sign(Y) (k = 1: from first_pass)
+      const bool from_first = k == 1 && first_known;
+      const double2 *sign = from_first ? Sp[p] : S;
       double cs[2] = {0.0, 0.0};
-      e = hipMemcpyAsync(cs, sums, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
-      if (e != hipSuccess) return e;
-      e = hipStreamSynchronize(s);
-      if (e != hipSuccess) return e;
+      if (from_first) {
+        cs[0] = first_cs[p][0];
+        cs[1] = first_cs[p][1];
+      } else {
+        e = power(false, X, Y, p, 1);
+        if (e != hipSuccess) return e;
+        e = launch_sum_partials(part, grid, sums, s);
+        if (e != hipSuccess) return e;
+        e = hipMemcpyAsync(cs, sums, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return e;
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+      }
       int jbest = 0;
       est = cs[0];
       if (t == 2 && cs[1] > est) {
@@ -385,7 +426,7 @@ struct Estimator {
       if (k > itmax) break;
       // Z = (A^dagger)^p S, h_i = max_j |Z_ij|; the first t + |hist| indices
       // by decreasing h (ties: smaller index) decide the next columns
-      e = power(true, S, Y, p, 2);
+      e = power(true, sign, Y, p, 2);
       if (e != hipSuccess) return e;
       const int want = (int)std::min<int64_t>(n, (int64_t)t + (int64_t)hist.size());
       e = launch_topk(h, n, want, grid, cand_v, cand_i, top_v, top_i, s);
@@ -1096,6 +1137,10 @@ qsw_status_t build_common(std::shared_ptr<Assembler> src, double omega, hipStrea
     if ((e = dalloc(&E.cand_i, (size_t)E.grid * kTopKMax)) != hipSuccess) break;
     if ((e = dalloc(&E.top_v, kTopKMax)) != hipSuccess) break;
     if ((e = dalloc(&E.top_i, kTopKMax)) != hipSuccess) break;
+    if ((e = dalloc(&E.first_sums, 2 * (kPMax + 2))) != hipSuccess) break;
+    for (int p = 2; p <= kPMax + 1 && e == hipSuccess; ++p) e = dalloc(&E.Sp[p], 2 * (size_t)n);
+    if (e != hipSuccess) break;
+    if ((e = E.first_pass(kPMax + 1)) != hipSuccess) break;
     for (int p = 2; p <= kPMax + 1; ++p) {
       double est = 0.0;
       int64_t idx = -1;
@@ -1111,6 +1156,8 @@ qsw_status_t build_common(std::shared_ptr<Assembler> src, double omega, hipStrea
   WA.release();
   dfree(E.X); dfree(E.Y); dfree(E.W0); dfree(E.W1); dfree(E.S); dfree(E.h); dfree(E.part); dfree(E.sums);
   dfree(E.cand_v); dfree(E.cand_i); dfree(E.top_v); dfree(E.top_i);
+  dfree(E.first_sums);
+  for (double2 *&b : E.Sp) dfree(b);
   dfree(arp); dfree(acol); dfree(aval);
   if (e != hipSuccess) return fail(status_of(e));
   if (!std::isfinite(norm1)) return fail(QSW_ERR_NONFINITE);
