@@ -450,27 +450,41 @@ __device__ __forceinline__ void wave_block(const SpmvArgs &a, int64_t k, Epi &ep
     const int64_t row = r0 + orow;
     constexpr int SU = NRHS == 1 ? kSharedPad : (NRHS == 2 ? kSharedPad / 2 : kSharedPad / 4);
     static_assert(kSharedPad % SU == 0, "shared groups divide the padding");
-    for (int p = 0; p < gsp; p += SU) {
-      double2 v[SU];
-      int64_t c[SU];
+    // up to 64 entries at a time: lane i loads entry i once, and each
+    // group takes its entries from the lanes (no load between the groups'
+    // gathers)
+    for (int b = 0; b < gsp; b += 64) {
+      const int cnt = min(64, gsp - b);  // a multiple of SU
+      SharedEntry mine{0, 0u, 0.0};
+      if (lane < cnt) mine = gld(a.wsh + sh0 + b + lane);
+      const unsigned long long mine_coef = (unsigned long long)__double_as_longlong(mine.coef);
+      for (int p = 0; p < cnt; p += SU) {
+        double2 v[SU];
+        int64_t c[SU];
 #pragma unroll
-      for (int u = 0; u < SU; ++u) {
-        const SharedEntry e = gld(a.wsh + sh0 + p + u);
-        const double cf = F32 ? (double)(float)e.coef : e.coef;
-        const bool im = (e.flags & kImagBit) != 0u;
-        v[u] = masked(lane < nr, make_double2(im ? 0.0 : cf, im ? cf : 0.0));
-        c[u] = row + e.off;
+        for (int u = 0; u < SU; ++u) {
+          const int off = __builtin_amdgcn_readlane(mine.off, p + u);
+          const uint32_t flags = (uint32_t)__builtin_amdgcn_readlane((int)mine.flags, p + u);
+          const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mine_coef, p + u);
+          const uint32_t hi =
+              (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(mine_coef >> 32), p + u);
+          const double e = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+          const double cf = F32 ? (double)(float)e : e;
+          const bool im = (flags & kImagBit) != 0u;
+          v[u] = masked(lane < nr, make_double2(im ? 0.0 : cf, im ? cf : 0.0));
+          c[u] = row + off;
+        }
+        double2 xg[SU][NRHS];
+#pragma unroll
+        for (int u = 0; u < SU; ++u)
+#pragma unroll
+          for (int r = 0; r < NRHS; ++r)
+            xg[u][r] = gld(a.x + (SOA ? (int64_t)r * a.n + c[u] : c[u] * NRHS + r));
+#pragma unroll
+        for (int u = 0; u < SU; ++u)
+#pragma unroll
+          for (int r = 0; r < NRHS; ++r) cmac(acc[2 * r], acc[2 * r + 1], v[u], xg[u][r]);
       }
-      double2 xg[SU][NRHS];
-#pragma unroll
-      for (int u = 0; u < SU; ++u)
-#pragma unroll
-        for (int r = 0; r < NRHS; ++r)
-          xg[u][r] = gld(a.x + (SOA ? (int64_t)r * a.n + c[u] : c[u] * NRHS + r));
-#pragma unroll
-      for (int u = 0; u < SU; ++u)
-#pragma unroll
-        for (int r = 0; r < NRHS; ++r) cmac(acc[2 * r], acc[2 * r + 1], v[u], xg[u][r]);
     }
   }
   // Branch-free groups of kWaveUnroll positions.  Position p's entries start
