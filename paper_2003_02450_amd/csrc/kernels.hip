@@ -557,16 +557,19 @@ __device__ __forceinline__ void wave_block(const SpmvArgs &a, int64_t k, Epi &ep
         const uint64_t oc = o < lim ? o : 0;
 #pragma unroll
         for (int r = 0; r < NRHS; ++r) {
-          const double2 *xgp = a.x + (SOA ? (int64_t)r * a.n : 0) + col[u];
-          const double2 *xlp = xs + (SOA ? (uint64_t)r * lim : 0);
+          // column r: SOA at r n + col (staged at r lim + o), else
+          // interleaved at col NRHS + r (staged at o NRHS + r)
+          const double2 *xgp = SOA ? a.x + (int64_t)r * a.n + col[u] : a.x + col[u] * NRHS + r;
+          const double2 *xlp = SOA ? xs + (uint64_t)r * lim : xs + r;
+          constexpr uint64_t ls = SOA ? 1 : NRHS;  // LDS stride between rho-row elements
           if constexpr (MODE == kGatherGlobal)
             xv[u][r] = gld(xgp);
           else if constexpr (MODE == kGatherLds)
-            xv[u][r] = xlp[oc];
+            xv[u][r] = xlp[oc * ls];
           else if constexpr (MODE == kGatherSplitAt)  // before `gsplit` global, then LDS
-            xv[u][r] = *(p0 + u < gsplit ? xgp : xlp + oc);
+            xv[u][r] = *(p0 + u < gsplit ? xgp : xlp + oc * ls);
           else  // kGatherPerLane
-            xv[u][r] = *(o < lim ? xlp + o : xgp);
+            xv[u][r] = *(o < lim ? xlp + o * ls : xgp);
         }
       }
 #pragma unroll
@@ -617,13 +620,13 @@ __device__ __forceinline__ void wave_engine(const SpmvArgs &a, Epi &epi) {
   constexpr int WPB = kBlock / 64;  // wavefronts per workgroup
   const int64_t nw = (int64_t)gridDim.x * WPB;
   extern __shared__ double2 xs[];
-  static_assert(!STAGE || NRHS == 1, "staging holds one right-hand side");
   for (int64_t kb = (int64_t)blockIdx.x * WPB; kb < a.nwb; kb += nw) {
     int64_t base = 0;
     if constexpr (STAGE) {
+      // rho-row of the workgroup's first row, all NRHS interleaved columns
       base = (kb * kWaveRows) / a.N * a.N;
       __syncthreads();  // the previous blocks are done with xs
-      for (int i = threadIdx.x; i < a.N; i += kBlock) xs[i] = a.x[base + i];
+      for (int i = threadIdx.x; i < a.N * NRHS; i += kBlock) xs[i] = a.x[base * NRHS + i];
       __syncthreads();
     }
     const int64_t k = kb + (threadIdx.x >> 6);
@@ -879,10 +882,15 @@ __global__ void row_blocks_kernel(const int64_t *rp, int64_t n, int64_t B, int32
 // for the block (SharedEntry) when phase-split values are built.
 
 // Row of lane `lane` in its block: CSR start, length (-1 for lanes past the
-// last row) and the number of its entries outside its rho-row.
+// last row), the number of its entries outside its rho-row and, when its
+// entries inside the rho-row are consecutive in the CSR (as the assembled
+// rows are: H rho part, diagonal and rho H part, population transfer), the
+// range [lo, hi) they occupy.
 struct WjagRow {
   int64_t row, src0;
   int len, outside;
+  int lo, hi;
+  bool consecutive;
   int64_t rho0;  // first column of the row's rho-row
   int32_t N;
   __device__ bool inside(const int32_t *col, int i) const {
@@ -898,15 +906,31 @@ __device__ __forceinline__ WjagRow wjag_row(const int64_t *rp, const int32_t *co
   w.len = lane < nr ? (int)(rp[w.row + 1] - w.src0) : -1;
   w.N = N;
   w.rho0 = w.row / N * N;
-  w.outside = 0;
-  for (int i = 0; i < w.len; ++i) w.outside += !w.inside(col, i);
+  int first = -1, last = -1, in = 0;
+  for (int i = 0; i < w.len; ++i)
+    if (w.inside(col, i)) {
+      if (first < 0) first = i;
+      last = i;
+      ++in;
+    }
+  w.outside = w.len < 0 ? 0 : w.len - in;
+  w.consecutive = in == 0 || last - first + 1 == in;
+  w.lo = in ? first : max(w.len, 0);
+  w.hi = in ? last + 1 : max(w.len, 0);
   return w;
 }
 
-// CSR index of the row's entry q in the outside-first order (io, ii: cursors
-// over its outside and inside entries, advanced in order of q).
+// CSR index of the row's entry q in the outside-first order: by position
+// arithmetic when the inside entries are consecutive, else with the cursors
+// io, ii over the outside and inside entries (advanced in order of q).
 __device__ __forceinline__ int64_t wjag_next(const int32_t *col, const WjagRow &w, int q, int &io,
                                              int &ii) {
+  if (w.consecutive) {
+    const int tail = w.len - w.hi;  // outside entries after the inside ones
+    if (q < w.lo) return w.src0 + q;
+    if (q < w.lo + tail) return w.src0 + w.hi + (q - w.lo);
+    return w.src0 + w.lo + (q - w.lo - tail);
+  }
   if (q < w.outside) {
     while (w.inside(col, io)) ++io;
     return w.src0 + io++;
@@ -1287,11 +1311,11 @@ __global__ __launch_bounds__(kBlock) void series_accum_kernel(DeviceState *st, P
 // --------------------------------------------------------------------------
 // Two right-hand sides (block 1-norm estimation), stream engine.
 // --------------------------------------------------------------------------
-template <bool SPLIT>
+template <bool SPLIT, bool STAGE>
 __global__ __launch_bounds__(kBlock) void spmm2_kernel(SpmvArgs a, int mode, double *part,
                                                        double2 *sgn, double *h) {
   Spmm2Epi epi{a.y, mode, sgn, h};
-  wave_engine<2, false, false, SPLIT>(a, epi);
+  wave_engine<2, false, STAGE, SPLIT>(a, epi);
   if (mode == 1) {
     // deterministic per-workgroup column sums: fixed tree over the threads
     __shared__ double sm0[kBlock], sm1[kBlock];
@@ -2152,10 +2176,17 @@ hipError_t launch_series_accum(DeviceState *st, PointSlots *pt, int k, int p, co
 
 hipError_t launch_spmm2(const SpmvArgs &a, bool split, int mode, double *part, double2 *sgn,
                         double *h, int grid, hipStream_t s) {
-  if (split)
-    hipLaunchKernelGGL(spmm2_kernel<true>, dim3(grid), dim3(kBlock), 0, s, a, mode, part, sgn, h);
-  else
-    hipLaunchKernelGGL(spmm2_kernel<false>, dim3(grid), dim3(kBlock), 0, s, a, mode, part, sgn, h);
+  // both columns of the rho-row staged in LDS when they fit
+  const size_t lds = (size_t)a.N * 2 * sizeof(double2);
+  const bool stage = a.N > 0 && lds <= kStageMaxBytes;
+#define QSW_L(SP, ST)                                                                       \
+  hipLaunchKernelGGL((spmm2_kernel<SP, ST>), dim3(grid), dim3(kBlock), ST ? lds : 0, s, a, mode, \
+                     part, sgn, h)
+  if (split && stage) QSW_L(true, true);
+  else if (split) QSW_L(true, false);
+  else if (stage) QSW_L(false, true);
+  else QSW_L(false, false);
+#undef QSW_L
   return hipGetLastError();
 }
 
@@ -2243,7 +2274,8 @@ int resident_workgroups(int which) {
     return 0;
   hipError_t e;
   if (which == 1)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, spmm2_kernel<false>, kBlock, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, spmm2_kernel<true, true>, kBlock,
+                                                     kStageMaxBytes);
   else
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, term_kernel<0>, kBlock, 0);
   if (e != hipSuccess || per < 1) per = 1;

@@ -72,9 +72,10 @@ struct AssembleArgs {
 
 // Wave-jagged execution layout: rows in blocks of 64 (one wavefront each).
 // Inside a block the rows are ranked by length (longest first, ties by row)
-// and the entries stored position-major: entry p of the row of rank r sits at
-// rp[64 k] + (entries of positions < p) + r.  wlen[64 k + r] is the length of
-// the row of rank r and wperm[64 k + r] its index within the block.
+// and the stored entries placed position-major: entry p of the row of rank r
+// sits at wstart[k] + (stored entries of positions < p) + r.  wlen[64 k + r]
+// is the length of the row of rank r (shared positions included) and
+// wperm[64 k + r] its index within the block.
 constexpr int kWaveRows = 64;
 constexpr int kWavePad = 64;  // zero entries after the wave-jagged arrays (reads past a block's end)
 constexpr size_t kStageMaxBytes = 32768;  // largest LDS-staged rho-row (N <= 2048)

@@ -1122,6 +1122,7 @@ qsw_status_t build_common(std::shared_ptr<Assembler> src, double omega, hipStrea
     set_wave(E.fwd, h);
     E.adj.n = n; E.adj.rp = arp; E.adj.col = acol; E.adj.val = aval;
     set_wave(E.adj, WA);
+    E.adj.N = N;
     E.fsplit = h->split;
     E.asplit = WA.split;
     E.grid = wave_grid(h->nwb, resident_workgroups(1));
