@@ -122,8 +122,9 @@ def single_leg(args, one_pass, out64, torch, n, nnz, q, wl) -> dict:
     products = sum(s["products"] for s, _ in stats)
     launched = sum(s["launched"] for s, _ in stats)
     st0, info0 = stats[0]
-    per = term_bytes(info0, True, st0["branch"] == 1)
-    assert abs(per * products - sum(s["bytes"] for s, _ in stats)) <= 1e-6 * per * products
+    # the library's count (one-point series blocks run fused: no separate
+    # accumulation pass)
+    per = sum(s["bytes"] for s, _ in stats) / max(products, 1)
     achieved = products * per / (prop_ms * 1e-3) / 1e9
     diff = float((out32 - out64).abs().max().item())
     bound = 2.0 * 2.0 ** -24 * (q * wl.dt) * info0["norm1"] * float(abs(wl.rho0).sum())

@@ -101,7 +101,8 @@ typedef struct {
     double ms;           /* device time of the last propagate call (events on its stream) */
     double bytes;        /* algorithmic HBM bytes of the computed products: per product
                             E e + 16 s + 8 (n+1) + D n + (64 or 80) n for branch 0 or 1 (branch
-                            1 adds the accumulation pass), with e = stream_entries and s =
+                            1 adds the accumulation pass, except with one grid point per block,
+                            which runs in the fused term kernel), with e = stream_entries and s =
                             shared_entries of qsw_info_t, and (E, D) = (20, 0) / (12, 0) for
                             complex double / single values and (12, 16) / (8, 8) for
                             phase-split double / single values (D: the diagonal per row) */

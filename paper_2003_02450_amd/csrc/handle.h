@@ -110,6 +110,7 @@ struct qsw_superop_s {
   hipEvent_t ev_start = nullptr, ev_end = nullptr;
   unsigned long long *stats_dev = nullptr;  // [products, nonfinite]
   qsw_stats_t last{};
+  bool last_fused = false;  // the last series call ran one-point blocks in the term kernel
   bool have_last = false;
   std::shared_ptr<qsw::Assembler> src;  // kept for qsw_superop_set_omega
   // paced term launches (qsw_superop_set_pacing): at most `pace` ahead of the

@@ -1996,8 +1996,17 @@ qsw_status_t qsw_propagate(qsw_superop_t h, const void *rho0, double t0, double 
     HIP_TRY(R.alg32((const double2 *)rho0, slot(0), t0, P.m0, P.s0));
   else
     HIP_TRY(launch_copy(slot(0), (const double2 *)rho0, n, s));
+  bool fused = false;  // series blocks run through the fused term kernel
   if (n_steps > 0 && P.branch == 0) {
     for (int32_t k = 0; k < n_steps; ++k) HIP_TRY(R.alg32(slot(k), slot(k + 1), dt, P.m, P.s));
+  } else if (n_steps > 0 && P.d == 1 && env_int("QSW_FUSE_SERIES", 1) != 0) {
+    // Time-series blocks of one grid point: the block's powers K_p =
+    // (dt/p) L K_{p-1} summed into F = Z + sum K_p with the two-term test on
+    // ||K_{p-1}|| + ||K_p|| <= tol ||F|| are the single-time algorithm with
+    // (m, 1) on each interval: the same products, sums, tests and order, in
+    // the fused term kernel (no separate accumulation pass).
+    for (int32_t k = 0; k < n_steps; ++k) HIP_TRY(R.alg32(slot(k), slot(k + 1), dt, P.m, 1));
+    fused = true;
   } else if (n_steps > 0) {
     // time-series blocks: K_0 = Z (block start), K_p in the workspace
     PointSlots *pts = (PointSlots *)(ws + P.off_pts);
@@ -2038,6 +2047,7 @@ qsw_status_t qsw_propagate(qsw_superop_t h, const void *rho0, double t0, double 
   h->last.s0 = P.s0;
   h->last.launched = R.launched;
   h->last.prec = h->prec;
+  h->last_fused = fused;
   h->have_last = true;
   return QSW_OK;
 }
@@ -2059,7 +2069,8 @@ qsw_status_t qsw_last_stats(qsw_superop_t h, qsw_stats_t *st) {
   const bool split = h->split && is_wave_engine(h->engine);
   const double entry = split ? (single ? 8.0 : 12.0) : (single ? 12.0 : 20.0);
   const double diag = split ? (single ? 8.0 : 16.0) : 0.0;
-  const double vec = h->last.branch == 1 ? 80.0 : 64.0;  // power + separate accumulation
+  // the stored-power series adds a separate accumulation pass
+  const double vec = h->last.branch == 1 && !h->last_fused ? 80.0 : 64.0;
   const double entries = is_wave_engine(h->engine) ? (double)h->wentries : (double)h->nnz;
   const double shared = is_wave_engine(h->engine) ? 16.0 * (double)h->wshared : 0.0;
   h->last.bytes = (double)h->last.products * (entry * entries + shared + 8.0 * (double)(h->n + 1) +
