@@ -28,16 +28,25 @@ inline qsw_status_t status_of(hipError_t e) {
   return QSW_ERR_DEVICE;
 }
 
+// Device memory of the library (handle arrays and build temporaries).  A
+// freed block is kept, per device and size, for the next allocation of the
+// same size (repeated builds ask for the same sizes), up to QSW_POOL_MB
+// megabytes (default 16384; 0: free at once).  Before it keeps a block the
+// pool waits for the device to finish its work, as hipFree would.  When
+// hipMalloc fails, the device's kept blocks are released and it is retried.
+hipError_t pool_alloc(void **p, size_t bytes);
+void pool_free(void *p);
+
 template <class T>
 hipError_t dalloc(T **p, size_t count) {
   *p = nullptr;
   if (count == 0) count = 1;
-  return hipMalloc((void **)p, count * sizeof(T));
+  return pool_alloc((void **)p, count * sizeof(T));
 }
 
 template <class T>
 void dfree(T *&p) {
-  if (p) (void)hipFree(p);
+  if (p) pool_free((void *)p);
   p = nullptr;
 }
 

@@ -23,6 +23,7 @@
 #include <mutex>
 #include <thread>
 #include <tuple>
+#include <unordered_map>
 #include <new>
 #include <vector>
 
@@ -1336,6 +1337,86 @@ const char *qsw_status_str(qsw_status_t s) {
 const char *qsw_version(void) { return "qsw 0.1 gfx950"; }
 
 }  // extern "C"
+
+namespace {
+
+struct Pool {
+  std::mutex mu;
+  std::map<std::pair<int, size_t>, std::vector<void *>> kept;   // (device, bytes) -> blocks
+  std::unordered_map<void *, std::pair<int, size_t>> live;      // allocated blocks
+  size_t held = 0;                                               // bytes kept
+  size_t cap = 0;
+  Pool() { cap = (size_t)std::max(0, env_int("QSW_POOL_MB", 16384)) << 20; }
+  void release_device(int dev) {  // mu held; `dev` current
+    for (auto it = kept.begin(); it != kept.end();) {
+      if (it->first.first != dev) {
+        ++it;
+        continue;
+      }
+      for (void *b : it->second) {
+        (void)hipFree(b);
+        held -= it->first.second;
+      }
+      it = kept.erase(it);
+    }
+  }
+};
+
+Pool &pool() {
+  static Pool *p = new Pool();  // kept until the process ends
+  return *p;
+}
+
+}  // namespace
+
+hipError_t qsw::pool_alloc(void **p, size_t bytes) {
+  *p = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  Pool &P = pool();
+  std::lock_guard<std::mutex> lk(P.mu);
+  auto it = P.kept.find({dev, bytes});
+  if (it != P.kept.end() && !it->second.empty()) {
+    *p = it->second.back();
+    it->second.pop_back();
+    P.held -= bytes;
+  } else {
+    e = hipMalloc(p, bytes);
+    if (e == hipErrorOutOfMemory && P.held > 0) {
+      (void)hipGetLastError();
+      P.release_device(dev);
+      e = hipMalloc(p, bytes);
+    }
+    if (e != hipSuccess) {
+      *p = nullptr;
+      return e;
+    }
+  }
+  P.live[*p] = {dev, bytes};
+  return hipSuccess;
+}
+
+void qsw::pool_free(void *p) {
+  if (!p) return;
+  Pool &P = pool();
+  std::lock_guard<std::mutex> lk(P.mu);
+  auto it = P.live.find(p);
+  if (it == P.live.end()) {  // not from pool_alloc
+    (void)hipFree(p);
+    return;
+  }
+  const int dev = it->second.first;
+  const size_t bytes = it->second.second;
+  P.live.erase(it);
+  DeviceGuard g(dev);
+  if (g.ok && P.held + bytes <= P.cap && hipDeviceSynchronize() == hipSuccess) {
+    P.kept[{dev, bytes}].push_back(p);
+    P.held += bytes;
+  } else {
+    (void)hipFree(p);
+  }
+}
 
 namespace {
 

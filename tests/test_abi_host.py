@@ -32,6 +32,19 @@ def test_library_exports_every_declared_function():
     assert set(declared) == set(_lib.EXPORTED)
 
 
+def test_library_leaves_no_internal_symbol_undefined():
+    """Every internal function the library calls is defined in it (a shared
+    object would otherwise build and fail only when the call is reached)."""
+    import shutil
+    import subprocess
+    nm = shutil.which("nm")
+    if nm is None:
+        pytest.skip("nm not available")
+    out = subprocess.run([nm, "-D", "--undefined-only", _lib.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    assert "_ZN3qsw" not in out, [ln for ln in out.splitlines() if "_ZN3qsw" in ln]
+
+
 def test_status_strings_and_version():
     L = _lib.load()
     for code in range(8):
