@@ -1198,17 +1198,19 @@ __device__ __forceinline__ bool taylor_prologue(const SpmvArgs &a) {
   StepSlots *S = &a.st->step[a.par];
   bool stop = false;
   if (a.j >= 2) {
-    if (*(volatile int *)&S->stop) {
-      stop = true;
-    } else {
-      const double c1 = bits_to_d(a.j == 2 ? S->b0 : S->b[a.j - 2]);
-      const double c2 = bits_to_d(S->b[a.j - 1]);
-      const double f = bits_to_d(S->f[a.j - 1]);
-      if (c1 + c2 <= a.tol * f) {
-        if (threadIdx.x == 0) *(volatile int *)&S->stop = 1;
-        stop = true;
-      }
-    }
+    // The flag and the norms were written by earlier launches, which the
+    // kernel boundary makes visible: plain (cached) loads, issued together.
+    // Coherent loads here would all queue at the memory side on the line
+    // that this launch's norm atomics update.
+    const int flag = S->stop;
+    const double c1 = bits_to_d(a.j == 2 ? S->b0 : S->b[a.j - 2]);
+    const double c2 = bits_to_d(S->b[a.j - 1]);
+    const double f = bits_to_d(S->f[a.j - 1]);
+    const bool pass = c1 + c2 <= a.tol * f;
+    stop = (flag != 0) | pass;  // one branch on both loads
+    // one writer: the rest of this launch reaches the same verdict itself,
+    // and later launches see the flag across the kernel boundary
+    if (!flag && pass && blockIdx.x == 0 && threadIdx.x == 0) S->stop = 1;
   } else if (blockIdx.x == 0) {
     // first term of a step: clear the other parity for the next step
     unsigned int *o = (unsigned int *)&a.st->step[a.par ^ 1];
@@ -1260,7 +1262,8 @@ __global__ __launch_bounds__(kBlock) void vec_norm_kernel(const double2 *x, int6
 // way by every workgroup from values written by earlier launches.)
 __device__ __forceinline__ bool point_done(const DeviceState *st, PointSlots *pt, int k, int p,
                                            double tol) {
-  if (*(volatile int *)&pt->stop) return true;
+  // flags and norms come from earlier launches: plain loads (see taylor_prologue)
+  if (pt->stop) return true;
   if (p < 2) return false;
   const int q = p - 1;  // last term added
   const double kk = (double)k;
@@ -1268,7 +1271,7 @@ __device__ __forceinline__ bool point_done(const DeviceState *st, PointSlots *pt
                              : pow(kk, (double)(q - 1)) * bits_to_d(st->series.kn[q - 1]);
   const double c2 = pow(kk, (double)q) * bits_to_d(st->series.kn[q]);
   if (c1 + c2 <= tol * bits_to_d(pt->f[q])) {
-    if (threadIdx.x == 0) *(volatile int *)&pt->stop = 1;
+    if (blockIdx.x == 0 && threadIdx.x == 0) pt->stop = 1;  // one writer
     return true;
   }
   return false;
@@ -1278,7 +1281,7 @@ template <int ENGINE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void series_power_kernel(SpmvArgs a, PointSlots *pt, int k,
                                                               int p) {
   if (point_done(a.st, pt, k, p, a.tol)) return;
-  if (p <= *(volatile int *)&a.st->series.mhat) return;  // K_p already formed
+  if (p <= a.st->series.mhat) return;  // K_p already formed (by an earlier launch)
   if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&a.st->products, 1ull);
   PowerEpi epi(a);
   run_engine<ENGINE>(a, epi);
@@ -1291,7 +1294,7 @@ __global__ __launch_bounds__(kBlock) void series_accum_kernel(DeviceState *st, P
                                                               int k, int p, const double2 *Kp,
                                                               const double2 *Z, double2 *F,
                                                               int64_t n, double tol) {
-  if (*(volatile int *)&pt->stop) return;
+  if (pt->stop) return;  // set by an earlier launch
   if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(&st->series.mhat, p);
   const double kp = pow((double)k, (double)p);
   unsigned long long mf[1] = {0};
