@@ -402,43 +402,104 @@ __device__ __forceinline__ double2 decode(int raw, double cf, double2 v, double2
 // r n + c) instead of interleaved (c NRHS + r).  With SOA and STAGE, xs holds
 // the rho-row of every column (xs[r N + i]) and `staged` says whether it
 // belongs to this block's x.
+// Header of block k of the wave layout, per lane: the block's first stored
+// entry e0, its shared leading positions (gs, stored padded to gsp, from
+// sh0), the position G where its rows enter their rho-row (-1: none, after
+// the shared ones), the lane's row length after the shared positions, the
+// longest one (rank 0), the lane's row (orow) and its diagonal (phase-split
+// layouts).
+struct WaveHead {
+  int64_t e0, sh0;
+  int gs, gsp, G, len, maxlen, orow;
+  double2 dg;
+};
+
+// Stand-ins read by blocks of layouts without shared positions or G.
+__device__ const int64_t kHeadZero64[2] = {0, 0};
+__device__ const int32_t kHeadZero32[1] = {0};
+__device__ const int32_t kHeadNoG[1] = {-1};
+
+// The header's loads, issued before any value is used (pointer selects and
+// clamped lanes instead of branches) so that they cost one memory round trip
+// together, and with whatever the caller issues before wave_head_use; k is
+// wave-uniform.  Lanes past the block's rows read row r0 and are masked.
+struct WaveRaw {
+  int64_t e0, s0, s1;
+  int n, g, len, perm;
+  double2 dg;
+};
+
+template <bool F32, bool SPLIT>
+__device__ __forceinline__ WaveRaw wave_head_load(const SpmvArgs &a, int64_t k) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r0 = k * kWaveRows;
+  const int nr = (int)min((int64_t)kWaveRows, a.n - r0);
+  const int li = lane < nr ? lane : 0;
+  const int64_t *pe = a.wstart ? a.wstart + k : a.rp + r0;
+  const int32_t *pn = a.wshn ? a.wshn + k : kHeadZero32;
+  const int64_t *ps = a.wshn ? a.wshs + k : kHeadZero64;
+  const int32_t *pg = a.wglob ? a.wglob + k : kHeadNoG;
+  WaveRaw w;
+  w.e0 = gld(pe);
+  w.n = gld(pn);
+  w.s0 = gld(ps);
+  w.s1 = gld(ps + 1);
+  w.g = gld(pg);
+  w.len = gld(a.wlen + r0 + li);
+  w.perm = (int)gld(a.wperm + r0 + li);
+  w.dg = make_double2(0.0, 0.0);
+  if constexpr (SPLIT) {
+    if constexpr (F32) {
+      const float2 d32 = gld(a.wdiag32 + r0 + li);
+      w.dg = make_double2((double)d32.x, (double)d32.y);
+    } else {
+      w.dg = gld(a.wdiag + r0 + li);
+    }
+  }
+  return w;
+}
+
+__device__ __forceinline__ WaveHead wave_head_use(const SpmvArgs &a, int64_t k, const WaveRaw &w) {
+  const int lane = threadIdx.x & 63;
+  const int nr = (int)min((int64_t)kWaveRows, a.n - k * kWaveRows);
+  WaveHead h;
+  h.e0 = uniform64(w.e0);
+  h.gs = __builtin_amdgcn_readfirstlane(w.n);
+  h.sh0 = uniform64(w.s0);
+  h.gsp = (int)(uniform64(w.s1) - h.sh0);
+  const int g = __builtin_amdgcn_readfirstlane(w.g);
+  h.G = g >= 0 ? g - h.gs : -1;
+  h.len = lane < nr ? w.len - h.gs : 0;
+  h.maxlen = __builtin_amdgcn_readfirstlane(h.len);
+  h.orow = lane < nr ? w.perm : 0;
+  h.dg = w.dg;
+  return h;
+}
+
+template <bool F32, bool SPLIT>
+__device__ __forceinline__ WaveHead wave_head(const SpmvArgs &a, int64_t k) {
+  return wave_head_use(a, k, wave_head_load<F32, SPLIT>(a, k));
+}
+
 template <int NRHS, bool F32, bool STAGE, class Epi, bool SOA = false, bool SPLIT = false>
-__device__ __forceinline__ void wave_block(const SpmvArgs &a, int64_t k, Epi &epi,
-                                           const double2 *xs, int64_t base, bool staged = true,
-                                           int64_t span = 0) {
+__device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const WaveHead &hd,
+                                             Epi &epi, const double2 *xs, int64_t base,
+                                             bool staged = true, int64_t span = 0) {
   // one right-hand side: xs holds x[base .. base + span) (span = N by default)
   const uint64_t lim = (uint64_t)(span ? span : a.N);
   constexpr int kWaveUnroll = wave_unroll<NRHS>();
   const int lane = threadIdx.x & 63;
   const int64_t r0 = k * kWaveRows;
   const int nr = (int)min((int64_t)kWaveRows, a.n - r0);
-  // wave-uniform: first stored entry of the block, its shared leading
-  // positions (gs, stored padded to gsp) and the longest row (rank 0)
-  const int64_t e0 = uniform64(a.wstart ? gld(a.wstart + k) : gld(a.rp + r0));
-  int gs = 0, gsp = 0;
-  int64_t sh0 = 0;
-  if (a.wshn) {
-    gs = __builtin_amdgcn_readfirstlane(gld(a.wshn + k));
-    sh0 = uniform64(gld(a.wshs + k));
-    gsp = (int)(uniform64(gld(a.wshs + k + 1)) - sh0);
-  }
-  // positions after the shared ones, per row
-  const int len = lane < nr ? gld(a.wlen + r0 + lane) - gs : 0;
-  const int maxlen = __builtin_amdgcn_readfirstlane(len);
-  const int orow = lane < nr ? (int)gld(a.wperm + r0 + lane) : 0;
+  const int64_t e0 = hd.e0;
+  const int gsp = hd.gsp;
+  const int64_t sh0 = hd.sh0;
+  const int len = hd.len;
+  const int maxlen = hd.maxlen;
+  const int orow = hd.orow;
   typename Epi::Pre pre{};
   if (lane < nr) pre = epi.pre(r0 + orow);
-  double2 dg = make_double2(0.0, 0.0);
-  if constexpr (SPLIT) {
-    if (lane < nr) {
-      if constexpr (F32) {
-        const float2 d32 = gld(a.wdiag32 + r0 + lane);
-        dg = make_double2((double)d32.x, (double)d32.y);
-      } else {
-        dg = gld(a.wdiag + r0 + lane);
-      }
-    }
-  }
+  const double2 dg = hd.dg;
   double acc[2 * NRHS];
 #pragma unroll
   for (int q = 0; q < 2 * NRHS; ++q) acc[q] = 0.0;
@@ -587,7 +648,7 @@ __device__ __forceinline__ void wave_block(const SpmvArgs &a, int64_t k, Epi &ep
     // memory and the rest from the staged rho-row.  Other blocks choose per
     // lane with generic loads, and blocks whose rho-row is not staged (SOA:
     // `staged` false) gather from global memory throughout.
-    const int G = a.wglob ? __builtin_amdgcn_readfirstlane(gld(a.wglob + k)) - gs : -1;
+    const int G = hd.G;
     const int64_t rho = r0 / a.N * a.N;
     const bool regular = G >= 0 && (uint64_t)(rho - base) < lim;
     int p0 = 0;
@@ -615,22 +676,54 @@ __device__ __forceinline__ void wave_block(const SpmvArgs &a, int64_t k, Epi &ep
   if (lane < nr) epi(r0 + orow, acc, pre);
 }
 
+template <int NRHS, bool F32, bool STAGE, class Epi, bool SOA = false, bool SPLIT = false>
+__device__ __forceinline__ void wave_block(const SpmvArgs &a, int64_t k, Epi &epi,
+                                           const double2 *xs, int64_t base, bool staged = true,
+                                           int64_t span = 0) {
+  const WaveHead hd = wave_head<F32, SPLIT>(a, k);
+  wave_block_h<NRHS, F32, STAGE, Epi, SOA, SPLIT>(a, k, hd, epi, xs, base, staged, span);
+}
+
+// xs[0 .. cnt) = src[0 .. cnt) by the whole workgroup, cnt at most the
+// staging budget (kStageMaxBytes): straight-line code with every load issued
+// before the first LDS write (a load-wait-write loop takes one memory round
+// trip per kBlock elements, and a loop head makes the compiler wait for the
+// loads issued before it).  The guards are wave-uniform.
+constexpr int kStageMaxPerThread = (int)((kStageMaxBytes / sizeof(double2) + kBlock - 1) / kBlock);
+
+__device__ __forceinline__ void stage_copy(double2 *xs, const double2 *src, int cnt) {
+  double2 v[kStageMaxPerThread];
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < kStageMaxPerThread; ++u)
+    if (u * kBlock < cnt) v[u] = gld(src + min(t + u * kBlock, cnt - 1));
+#pragma unroll
+  for (int u = 0; u < kStageMaxPerThread; ++u)
+    if (u * kBlock < cnt && t + u * kBlock < cnt) xs[t + u * kBlock] = v[u];
+}
+
 template <int NRHS, bool F32, bool STAGE, bool SPLIT, class Epi>
 __device__ __forceinline__ void wave_engine(const SpmvArgs &a, Epi &epi) {
   constexpr int WPB = kBlock / 64;  // wavefronts per workgroup
   const int64_t nw = (int64_t)gridDim.x * WPB;
   extern __shared__ double2 xs[];
   for (int64_t kb = (int64_t)blockIdx.x * WPB; kb < a.nwb; kb += nw) {
+    const int64_t k = kb + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    // the block header's loads are issued before the staging (a wave past
+    // the last block reads the last one's and does nothing with it), so the
+    // two share one memory round trip
+    const WaveRaw raw = wave_head_load<F32, SPLIT>(a, k < a.nwb ? k : a.nwb - 1);
     int64_t base = 0;
     if constexpr (STAGE) {
       // rho-row of the workgroup's first row, all NRHS interleaved columns
       base = (kb * kWaveRows) / a.N * a.N;
-      __syncthreads();  // the previous blocks are done with xs
-      for (int i = threadIdx.x; i < a.N * NRHS; i += kBlock) xs[i] = a.x[base * NRHS + i];
+      if (kb != (int64_t)blockIdx.x * WPB) __syncthreads();  // the previous blocks are done with xs
+      stage_copy(xs, a.x + base * NRHS, a.N * NRHS);
       __syncthreads();
     }
-    const int64_t k = kb + (threadIdx.x >> 6);
-    if (k < a.nwb) wave_block<NRHS, F32, STAGE, Epi, false, SPLIT>(a, k, epi, xs, base);
+    if (k < a.nwb)
+      wave_block_h<NRHS, F32, STAGE, Epi, false, SPLIT>(a, k, wave_head_use(a, k, raw), epi, xs,
+                                                        base);
   }
 }
 
