@@ -519,11 +519,14 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
       SharedEntry mine{0, 0u, 0.0};
       if (lane < cnt) mine = gld(a.wsh + sh0 + b + lane);
       const unsigned long long mine_coef = (unsigned long long)__double_as_longlong(mine.coef);
-      for (int p = 0; p < cnt; p += SU) {
-        double2 v[SU];
-        int64_t c[SU];
+      // one group of S positions: S gathers in flight, then the sums (wider
+      // groups of 16 measured no faster)
+      auto sgroup = [&](auto width, int p) {
+        constexpr int S = decltype(width)::value;
+        double2 v[S];
+        int64_t c[S];
 #pragma unroll
-        for (int u = 0; u < SU; ++u) {
+        for (int u = 0; u < S; ++u) {
           const int off = __builtin_amdgcn_readlane(mine.off, p + u);
           const uint32_t flags = (uint32_t)__builtin_amdgcn_readlane((int)mine.flags, p + u);
           const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mine_coef, p + u);
@@ -532,20 +535,23 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
           const double e = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
           const double cf = F32 ? (double)(float)e : e;
           const bool im = (flags & kImagBit) != 0u;
-          v[u] = masked(lane < nr, make_double2(im ? 0.0 : cf, im ? cf : 0.0));
+          // wave-uniform (lanes past the block's rows gather at row r0, in
+          // bounds, and their sums are never written)
+          v[u] = make_double2(im ? 0.0 : cf, im ? cf : 0.0);
           c[u] = row + off;
         }
-        double2 xg[SU][NRHS];
+        double2 xg[S][NRHS];
 #pragma unroll
-        for (int u = 0; u < SU; ++u)
+        for (int u = 0; u < S; ++u)
 #pragma unroll
           for (int r = 0; r < NRHS; ++r)
             xg[u][r] = gld(a.x + (SOA ? (int64_t)r * a.n + c[u] : c[u] * NRHS + r));
 #pragma unroll
-        for (int u = 0; u < SU; ++u)
+        for (int u = 0; u < S; ++u)
 #pragma unroll
           for (int r = 0; r < NRHS; ++r) cmac(acc[2 * r], acc[2 * r + 1], v[u], xg[u][r]);
-      }
+      };
+      for (int p = 0; p < cnt; p += SU) sgroup(std::integral_constant<int, SU>{}, p);
     }
   }
   // Branch-free groups of kWaveUnroll positions.  Position p's entries start
@@ -1000,12 +1006,22 @@ __device__ __forceinline__ WjagRow wjag_row(const int64_t *rp, const int32_t *co
   w.N = N;
   w.rho0 = w.row / N * N;
   int first = -1, last = -1, in = 0;
-  for (int i = 0; i < w.len; ++i)
-    if (w.inside(col, i)) {
-      if (first < 0) first = i;
-      last = i;
-      ++in;
+  // eight column loads in flight per step (clamped into the row, so a row
+  // shorter than the step re-reads its last entry)
+  for (int i0 = 0; i0 < w.len; i0 += 8) {
+    int32_t c8[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) c8[u] = col[w.src0 + min(i0 + u, w.len - 1)];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u;
+      if (i < w.len && (uint64_t)((int64_t)c8[u] - w.rho0) < (uint64_t)N) {
+        if (first < 0) first = i;
+        last = i;
+        ++in;
+      }
     }
+  }
   w.outside = w.len < 0 ? 0 : w.len - in;
   w.consecutive = in == 0 || last - first + 1 == in;
   w.lo = in ? first : max(w.len, 0);
@@ -1013,17 +1029,34 @@ __device__ __forceinline__ WjagRow wjag_row(const int64_t *rp, const int32_t *co
   return w;
 }
 
+// CSR index of entry q (outside-first order) of a row whose inside entries
+// are consecutive: position arithmetic.
+__device__ __forceinline__ int64_t wjag_consecutive_index(const WjagRow &w, int q) {
+  const int tail = w.len - w.hi;  // outside entries after the inside ones
+  if (q < w.lo) return w.src0 + q;
+  if (q < w.lo + tail) return w.src0 + w.hi + (q - w.lo);
+  return w.src0 + w.lo + (q - w.lo - tail);
+}
+
+// Loads of entries q0 .. q0 + 7 of the lane's row (consecutive rows only),
+// issued together; positions past the row re-read its last entry, and a lane
+// without entries reads entry 0 of the CSR (callers have nnz > 0).
+__device__ __forceinline__ void wjag_load8(const int32_t *col, const double2 *val, const WjagRow &w,
+                                           int q0, int32_t (&cc)[8], double2 (&vv)[8]) {
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int64_t e = w.len > 0 ? wjag_consecutive_index(w, min(q0 + u, w.len - 1)) : 0;
+    cc[u] = col[e];
+    vv[u] = val[e];
+  }
+}
+
 // CSR index of the row's entry q in the outside-first order: by position
 // arithmetic when the inside entries are consecutive, else with the cursors
 // io, ii over the outside and inside entries (advanced in order of q).
 __device__ __forceinline__ int64_t wjag_next(const int32_t *col, const WjagRow &w, int q, int &io,
                                              int &ii) {
-  if (w.consecutive) {
-    const int tail = w.len - w.hi;  // outside entries after the inside ones
-    if (q < w.lo) return w.src0 + q;
-    if (q < w.lo + tail) return w.src0 + w.hi + (q - w.lo);
-    return w.src0 + w.lo + (q - w.lo - tail);
-  }
+  if (w.consecutive) return wjag_consecutive_index(w, q);
   if (q < w.outside) {
     while (w.inside(col, io)) ++io;
     return w.src0 + io++;
@@ -1063,21 +1096,42 @@ __global__ __launch_bounds__(kBlock) void wjag_plan_kernel(const int64_t *rp, co
   // imaginary value in every row of the block
   int gs = 0;
   if constexpr (SHARED) {
-    int io = 0, ii = 0;
-    for (int q = 0; q < gmin; ++q) {
-      int64_t rel = 0;
-      double2 v = make_double2(0.0, 0.0);
-      if (lane < nr) {
-        const int64_t e = wjag_next(col, w, q, io, ii);
-        rel = (int64_t)col[e] - w.row;
-        v = val[e];
-      }
+    // is position q the same in every row? (entry of the lane's row given)
+    auto same = [&](int64_t e_col, double2 v) {
+      const int64_t rel = lane < nr ? e_col - w.row : 0;
+      if (lane >= nr) v = make_double2(0.0, 0.0);
       const int64_t rel0 = __shfl(rel, 0, 64);
       const double vx0 = __shfl(v.x, 0, 64), vy0 = __shfl(v.y, 0, 64);
       const bool ok = lane >= nr || (rel == rel0 && same_bits(v.x, vx0) && same_bits(v.y, vy0) &&
                                      (v.x == 0.0 || v.y == 0.0));
-      if (__ballot(!ok) != 0) break;
-      ++gs;
+      return __ballot(!ok) == 0;
+    };
+    if (__ballot(!w.consecutive) == 0) {
+      // eight positions' loads in flight per step (gmin > 0: every row of
+      // the block has entries)
+      for (int q0 = 0; q0 < gmin && gs == q0; q0 += 8) {
+        int32_t cc[8];
+        double2 vv[8];
+        wjag_load8(col, val, w, q0, cc, vv);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (q0 + u >= gmin || gs != q0 + u) break;
+          if (same((int64_t)cc[u], vv[u])) ++gs;
+        }
+      }
+    } else {
+      int io = 0, ii = 0;
+      for (int q = 0; q < gmin; ++q) {
+        int64_t c = 0;
+        double2 v = make_double2(0.0, 0.0);
+        if (lane < nr) {
+          const int64_t e = wjag_next(col, w, q, io, ii);
+          c = (int64_t)col[e];
+          v = val[e];
+        }
+        if (!same(c, v)) break;
+        ++gs;
+      }
     }
   }
   long long cnt = lane < nr ? (long long)(w.len - gs) : 0;
@@ -1117,14 +1171,9 @@ __global__ __launch_bounds__(kBlock) void wjag_fill_kernel(
   double2 dg = make_double2(0.0, 0.0);
   int ndiag = 0;
   bool mixed = false;
-  int io = 0, ii = 0;
   int ps = 0;
-  for (int p = 0; p < maxlen; ++p) {
-    const int cnt = __popcll(__ballot(w.len > p));
-    if (w.len > p) {
-      const int64_t e = wjag_next(col, w, p, io, ii);
-      const int32_t cc = col[e];
-      const double2 vv = val[e];
+  // the lane's entry at position p (w.len > p)
+  auto put = [&](int p, int32_t cc, double2 vv) {
       if (p < gs) {  // the same in every row: lane 0 stores it for the block
         if (lane == 0) {
           const bool im = vv.x == 0.0 && vv.y != 0.0;
@@ -1155,8 +1204,32 @@ __global__ __launch_bounds__(kBlock) void wjag_fill_kernel(
           wcoef[dst] = vv.x;
         }
       }
+  };
+  if (__ballot(!w.consecutive) == 0) {
+    // eight positions' loads in flight per step (maxlen > 0: nnz > 0)
+    for (int p0 = 0; p0 < maxlen; p0 += 8) {
+      int32_t cc[8];
+      double2 vv[8];
+      wjag_load8(col, val, w, p0, cc, vv);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int p = p0 + u;
+        if (p >= maxlen) break;
+        const int cnt = __popcll(__ballot(w.len > p));
+        if (w.len > p) put(p, cc[u], vv[u]);
+        if (p >= gs) ps += cnt;
+      }
     }
-    if (p >= gs) ps += cnt;
+  } else {
+    int io = 0, ii = 0;
+    for (int p = 0; p < maxlen; ++p) {
+      const int cnt = __popcll(__ballot(w.len > p));
+      if (w.len > p) {
+        const int64_t e = wjag_next(col, w, p, io, ii);
+        put(p, col[e], val[e]);
+      }
+      if (p >= gs) ps += cnt;
+    }
   }
   // zero entries up to the padded count
   if (lane == 0)

@@ -305,10 +305,6 @@ qsw_status_t assemble(const HostOps &op, const Rates &R, bool adjoint, double om
 
 // Block 1-norm estimator (Higham and Tisseur's algorithm, two columns,
 // complex case, at most five iterations) applied to A^p, with the products
-// formed by p sparse products on the device.  Returns the estimate and the
-// unit column (or probe column) that attains it.
-// Block 1-norm estimator (Higham and Tisseur's algorithm, two columns,
-// complex case, at most five iterations) applied to A^p, with the products
 // formed by p sparse products on the device and the ranking of the
 // candidate columns done on the device; the host reads back a few scalars
 // per iteration.  Returns the estimate and the unit column (or probe column)
