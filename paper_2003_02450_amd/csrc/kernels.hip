@@ -923,27 +923,67 @@ __global__ __launch_bounds__(kBlock) void assemble_kernel(AssembleArgs A, int64_
   // ascending c), then the population-transfer entries (column j (N + 1),
   // ascending j).  Rows of one rho-row a then share the column offsets c N of
   // their leading entries, which the product kernels use to coalesce gathers.
+  // The operator's entries are read eight at a time before they are written
+  // (the output may alias the inputs as far as the compiler knows, so a
+  // load-store loop would wait for every load).
   int64_t o = start;
   // sigma(-i)(1-w) H_ac on rho_cb
-  for (int64_t i = ha0; i < ha1; ++i, ++o) {
-    const double2 h = A.hv[i];
-    A.col[o] = (int32_t)((int64_t)A.hc[i] * N + b);
-    A.val[o] = make_double2(ch * h.y, -ch * h.x);
+  for (int64_t i0 = ha0; i0 < ha1; i0 += 8) {
+    double2 h[8];
+    int32_t c[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t i = min(i0 + u, ha1 - 1);
+      h[u] = A.hv[i];
+      c[u] = A.hc[i];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (i0 + u < ha1) {
+        A.col[o] = (int32_t)((int64_t)c[u] * N + b);
+        A.val[o] = make_double2(ch * h[u].y, -ch * h[u].x);
+        ++o;
+      }
   }
   A.col[o] = (int32_t)(a * N + b);
   A.val[o] = dval;
   ++o;
   // sigma(+i)(1-w) conj(H_bc) on rho_ac
-  for (int64_t i = hb0; i < hb1; ++i, ++o) {
-    const double2 h = A.hv[i];
-    A.col[o] = (int32_t)(a * N + A.hc[i]);
-    A.val[o] = make_double2(ch * h.y, ch * h.x);
+  for (int64_t i0 = hb0; i0 < hb1; i0 += 8) {
+    double2 h[8];
+    int32_t c[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t i = min(i0 + u, hb1 - 1);
+      h[u] = A.hv[i];
+      c[u] = A.hc[i];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (i0 + u < hb1) {
+        A.col[o] = (int32_t)(a * N + c[u]);
+        A.val[o] = make_double2(ch * h[u].y, ch * h[u].x);
+        ++o;
+      }
   }
   // w R_aj on rho_jj
   if (a == b) {
-    for (int64_t i = ra0; i < ra1; ++i, ++o) {
-      A.col[o] = (int32_t)((int64_t)A.rc[i] * (N + 1));
-      A.val[o] = make_double2(w * A.rv[i], 0.0);
+    for (int64_t i0 = ra0; i0 < ra1; i0 += 8) {
+      double rv[8];
+      int32_t c[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t i = min(i0 + u, ra1 - 1);
+        rv[u] = A.rv[i];
+        c[u] = A.rc[i];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (i0 + u < ra1) {
+          A.col[o] = (int32_t)((int64_t)c[u] * (N + 1));
+          A.val[o] = make_double2(w * rv[u], 0.0);
+          ++o;
+        }
     }
   }
 }
@@ -1317,8 +1357,17 @@ __global__ __launch_bounds__(kBlock) void row_abs_max_kernel(int64_t n, const in
   const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   unsigned long long m[1] = {0ull};
   if (r < n) {
+    // entries in order; eight loads in flight per step
     double s = 0.0;
-    for (int64_t e = rp[r]; e < rp[r + 1]; ++e) s += cabs2(val[e]);
+    const int64_t e0 = rp[r], e1 = rp[r + 1];
+    for (int64_t i0 = e0; i0 < e1; i0 += 8) {
+      double2 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = val[min(i0 + u, e1 - 1)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (i0 + u < e1) s += cabs2(v[u]);
+    }
     m[0] = abs_bits(s);
   }
   unsigned long long *const dst[1] = {out};
