@@ -2413,6 +2413,25 @@ hipError_t launch_sum_partials(const double *part, int nblocks, double *out2, hi
   return hipGetLastError();
 }
 
+// One wavefront: the small results, then the sequence number (a release
+// store at system scope orders it after them for the host).
+__global__ __launch_bounds__(64) void post_kernel(const double *v, int nv, const int64_t *iv,
+                                                  int ni, const double *extra, HostPost *dst,
+                                                  unsigned long long seq) {
+  const int t = threadIdx.x;
+  if (t < nv) dst->v[t] = v[t];
+  if (t < ni) dst->i[t] = iv[t];
+  if (t == 0 && extra) dst->v[nv] = *extra;
+  if (t == 0) __hip_atomic_store(&dst->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+hipError_t launch_post(const double *v, int nv, const int64_t *iv, int ni, const double *extra,
+                       HostPost *dst, unsigned long long seq, hipStream_t s) {
+  if (nv < 0 || ni < 0 || nv + 1 > kPostMax || ni > kPostMax) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(post_kernel, dim3(1), dim3(64), 0, s, v, nv, iv, ni, extra, dst, seq);
+  return hipGetLastError();
+}
+
 hipError_t launch_probe_init(double2 *X, int64_t n, int t, hipStream_t s) {
   int grid = blocks_for(n);
   if (grid > 4096) grid = 4096;

@@ -321,6 +321,21 @@ hipError_t launch_sum_partials(const double *part, int nblocks, double *out2,
 // column 1), unit columns [e_i0, e_i1] (i1 < 0: zero), and the top K <= 16
 // of h by (larger value, then smaller index) through grid * K candidates.
 hipError_t launch_probe_init(double2 *X, int64_t n, int t, hipStream_t s);
+
+// A few results of the 1-norm estimator posted to pinned host memory: the
+// values, the indices, then the sequence number with a system-scope release
+// store, on which the host waits instead of synchronising the stream.
+constexpr int kPostMax = 32;
+struct HostPost {
+  double v[kPostMax];
+  int64_t i[kPostMax];
+  unsigned long long seq;
+};
+static_assert(kTopKMax + 1 <= kPostMax, "the top-k values and one more fit");
+// dst->v[0 .. nv) = v, dst->i[0 .. ni) = iv, dst->v[nv] = *extra (if given),
+// then dst->seq = seq; nv + 1, ni <= kPostMax.
+hipError_t launch_post(const double *v, int nv, const int64_t *iv, int ni, const double *extra,
+                       HostPost *dst, unsigned long long seq, hipStream_t s);
 hipError_t launch_unit_cols(double2 *X, int64_t n, int64_t i0, int64_t i1, hipStream_t s);
 hipError_t launch_topk(const double *h, int64_t n, int K, int grid, double *cand_v, int64_t *cand_i,
                        double *out_v, int64_t *out_i, hipStream_t s);

@@ -309,6 +309,51 @@ qsw_status_t assemble(const HostOps &op, const Rates &R, bool adjoint, double om
 // candidate columns done on the device; the host reads back a few scalars
 // per iteration.  Returns the estimate and the unit column (or probe column)
 // that attains it.
+// Pinned mailboxes (HostPost) of finished builds, kept per device for later
+// builds (a pinned allocation costs more than a build's waits save).
+struct PostPool {
+  std::mutex mu;
+  std::map<int, std::vector<std::pair<HostPost *, HostPost *>>> free;  // device -> (host, dev)
+};
+PostPool &post_pool() {
+  static PostPool *p = new PostPool();  // kept until the process ends
+  return *p;
+}
+hipError_t post_get(HostPost **host, HostPost **dev) {
+  int d = 0;
+  hipError_t e = hipGetDevice(&d);
+  if (e != hipSuccess) return e;
+  PostPool &P = post_pool();
+  {
+    std::lock_guard<std::mutex> lk(P.mu);
+    auto &v = P.free[d];
+    if (!v.empty()) {
+      *host = v.back().first;
+      *dev = v.back().second;
+      v.pop_back();
+      return hipSuccess;
+    }
+  }
+  void *hp = nullptr, *dp = nullptr;
+  if ((e = hipHostMalloc(&hp, sizeof(HostPost), hipHostMallocCoherent)) != hipSuccess) return e;
+  if ((e = hipHostGetDevicePointer(&dp, hp, 0)) != hipSuccess) {
+    (void)hipHostFree(hp);
+    return e;
+  }
+  std::memset(hp, 0, sizeof(HostPost));
+  *host = (HostPost *)hp;
+  *dev = (HostPost *)dp;
+  return hipSuccess;
+}
+void post_put(HostPost *host, HostPost *dev) {
+  if (!host) return;
+  int d = 0;
+  if (hipGetDevice(&d) != hipSuccess) return;
+  PostPool &P = post_pool();
+  std::lock_guard<std::mutex> lk(P.mu);
+  P.free[d].push_back({host, dev});
+}
+
 struct Estimator {
   int64_t n;
   hipStream_t s;
@@ -325,6 +370,32 @@ struct Estimator {
   double first_cs[kPMax + 2][2] = {};
   double *first_sums = nullptr;  // device, 2 per power
   bool have_first = false;
+  // pinned mailbox for the per-iteration results (host and device views)
+  HostPost *post_host = nullptr, *post_dev = nullptr;
+  unsigned long long post_seq = 0;
+
+  // Posts v[0 .. nv), iv[0 .. ni) and *extra to the mailbox and waits for
+  // them: the host spins on the sequence number (a stream synchronisation
+  // costs tens of microseconds per iteration), and after 10 ms checks
+  // whether the stream has stopped without posting (a device error).
+  hipError_t fetch(const double *v, int nv, const int64_t *iv, int ni, const double *extra) {
+    const unsigned long long seq = ++post_seq;
+    hipError_t e = launch_post(v, nv, iv, ni, extra, post_dev, seq, s);
+    if (e != hipSuccess) return e;
+    using clock = std::chrono::steady_clock;
+    auto query_at = clock::now() + std::chrono::milliseconds(10);
+    for (unsigned spins = 1;; ++spins) {
+      if (__atomic_load_n(&post_host->seq, __ATOMIC_ACQUIRE) == seq) return hipSuccess;
+      if ((spins & 1023u) == 0 && clock::now() >= query_at) {
+        const hipError_t q = hipStreamQuery(s);
+        if (q != hipErrorNotReady) {
+          if (__atomic_load_n(&post_host->seq, __ATOMIC_ACQUIRE) == seq) return hipSuccess;
+          return q == hipSuccess ? hipErrorUnknown : q;
+        }
+        query_at = clock::now() + std::chrono::milliseconds(10);
+      }
+    }
+  }
 
   // The probe block X0 is the same for every p, so the first iteration's
   // products A^p X0 (p = 2..pmax) come from one chain A X0, A^2 X0, ...: each
@@ -396,10 +467,10 @@ struct Estimator {
         if (e != hipSuccess) return e;
         e = launch_sum_partials(part, grid, sums, s);
         if (e != hipSuccess) return e;
-        e = hipMemcpyAsync(cs, sums, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+        e = fetch(sums, 2, nullptr, 0, nullptr);
         if (e != hipSuccess) return e;
-        e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return e;
+        cs[0] = post_host->v[0];
+        cs[1] = post_host->v[1];
       }
       int jbest = 0;
       est = cs[0];
@@ -431,16 +502,14 @@ struct Estimator {
       double tv[kTopKMax];
       int64_t ti[kTopKMax];
       double hb = 0.0;
-      e = hipMemcpyAsync(tv, top_v, want * sizeof(double), hipMemcpyDeviceToHost, s);
+      const bool want_hb = k >= 2 && ind_best >= 0;
+      e = fetch(top_v, want, top_i, want, want_hb ? h + ind_best : nullptr);
       if (e != hipSuccess) return e;
-      e = hipMemcpyAsync(ti, top_i, want * sizeof(int64_t), hipMemcpyDeviceToHost, s);
-      if (e != hipSuccess) return e;
-      if (k >= 2 && ind_best >= 0) {
-        e = hipMemcpyAsync(&hb, h + ind_best, sizeof(double), hipMemcpyDeviceToHost, s);
-        if (e != hipSuccess) return e;
+      for (int j = 0; j < want; ++j) {
+        tv[j] = post_host->v[j];
+        ti[j] = post_host->i[j];
       }
-      e = hipStreamSynchronize(s);
-      if (e != hipSuccess) return e;
+      if (want_hb) hb = post_host->v[want];
       if (k >= 2 && ind_best >= 0 && tv[0] == hb) break;
       auto in_hist = [&](int64_t i) { return std::find(hist.begin(), hist.end(), i) != hist.end(); };
       if (t > 1) {
@@ -1137,6 +1206,8 @@ qsw_status_t build_common(std::shared_ptr<Assembler> src, double omega, hipStrea
     if ((e = dalloc(&E.top_i, kTopKMax)) != hipSuccess) break;
     if ((e = dalloc(&E.first_sums, 2 * (kPMax + 2))) != hipSuccess) break;
     for (int p = 2; p <= kPMax + 1 && e == hipSuccess; ++p) e = dalloc(&E.Sp[p], 2 * (size_t)n);
+    if (e == hipSuccess) e = post_get(&E.post_host, &E.post_dev);
+    if (e == hipSuccess) E.post_seq = __atomic_load_n(&E.post_host->seq, __ATOMIC_ACQUIRE);
     if (e != hipSuccess) break;
     if ((e = E.first_pass(kPMax + 1)) != hipSuccess) break;
     for (int p = 2; p <= kPMax + 1; ++p) {
@@ -1156,6 +1227,8 @@ qsw_status_t build_common(std::shared_ptr<Assembler> src, double omega, hipStrea
   dfree(E.cand_v); dfree(E.cand_i); dfree(E.top_v); dfree(E.top_i);
   dfree(E.first_sums);
   for (double2 *&b : E.Sp) dfree(b);
+  // back to the pool only with no post in flight (else it is left allocated)
+  if (e == hipSuccess || hipStreamSynchronize(s) == hipSuccess) post_put(E.post_host, E.post_dev);
   dfree(arp); dfree(acol); dfree(aval);
   if (e != hipSuccess) return fail(status_of(e));
   if (!std::isfinite(norm1)) return fail(QSW_ERR_NONFINITE);
