@@ -107,21 +107,23 @@ __device__ __forceinline__ void gst<double2>(double2 *p, const double2 &v) {
   *(QSW_GLOBAL dvec2 *)p = w;
 }
 
-// Matrix entries are read once per product: non-temporal loads leave the
-// caches to the gathered vector.
-__device__ __forceinline__ double2 load_stream(const double2 *p) {
+// Matrix entries of the wave layout.  Blocks with equal stored rows share
+// one copy, which many blocks of a product read again, so these are plain
+// (cached) loads: non-temporal hints evicted the shared copies and cost 8 %
+// of a product on the 1024-vertex operator.
+__device__ __forceinline__ double2 load_entry(const double2 *p) { return gld(p); }
+__device__ __forceinline__ int load_entry(const int32_t *p) { return gld(p); }
+__device__ __forceinline__ double load_entry(const double *p) { return gld(p); }
+__device__ __forceinline__ double load_entry(const float *p) { return (double)gld(p); }
+
+// Entries of the plain CSR (stream and vector engines), each read once per
+// product: non-temporal loads leave the caches to the gathered vector.
+__device__ __forceinline__ double2 load_csr(const double2 *p) {
   const dvec2 v = __builtin_nontemporal_load((const QSW_GLOBAL dvec2 *)p);
   return make_double2(v.x, v.y);
 }
-__device__ __forceinline__ int load_stream(const int32_t *p) {
+__device__ __forceinline__ int load_csr(const int32_t *p) {
   return __builtin_nontemporal_load((const QSW_GLOBAL int32_t *)p);
-}
-
-__device__ __forceinline__ double load_stream(const double *p) {
-  return __builtin_nontemporal_load((const QSW_GLOBAL double *)p);
-}
-__device__ __forceinline__ double load_stream(const float *p) {
-  return (double)__builtin_nontemporal_load((const QSW_GLOBAL float *)p);
 }
 
 typedef float fvec2 __attribute__((ext_vector_type(2)));
@@ -145,8 +147,8 @@ __device__ __forceinline__ float2 gld<float2>(const float2 *p) {
 }
 
 // A complex64 entry widened to complex128 (exact).
-__device__ __forceinline__ double2 load_stream(const float2 *p) {
-  const fvec2 v = __builtin_nontemporal_load((const QSW_GLOBAL fvec2 *)p);
+__device__ __forceinline__ double2 load_entry(const float2 *p) {
+  const float2 v = gld(p);
   return make_double2((double)v.x, (double)v.y);
 }
 
@@ -218,8 +220,8 @@ __device__ __forceinline__ void stream_engine(const SpmvArgs &a, Epi &epi) {
     for (int u = 0; u < kUnroll; ++u) {
       const int i = tid + u * kBlock;
       if (i < d.cnt) {
-        c[u] = load_stream(cb + i);
-        v[u] = load_stream(vb + i);
+        c[u] = load_csr(cb + i);
+        v[u] = load_csr(vb + i);
       }
     }
   };
@@ -580,16 +582,16 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
     }
     int c[kWaveUnroll];
 #pragma unroll
-    for (int u = 0; u < kWaveUnroll; ++u) c[u] = load_stream(cb + bcur[u]);
+    for (int u = 0; u < kWaveUnroll; ++u) c[u] = load_entry(cb + bcur[u]);
     double2 v[kWaveUnroll];
     double cf[kWaveUnroll];
 #pragma unroll
     for (int u = 0; u < kWaveUnroll; ++u) {
       if constexpr (SPLIT) {
-        cf[u] = F32 ? load_stream(a.wcoef32 + e0 + bcur[u]) : load_stream(a.wcoef + e0 + bcur[u]);
+        cf[u] = F32 ? load_entry(a.wcoef32 + e0 + bcur[u]) : load_entry(a.wcoef + e0 + bcur[u]);
         v[u] = dg;  // unused
       } else {
-        v[u] = F32 ? load_stream(a.wval32 + e0 + bcur[u]) : load_stream(a.wval + e0 + bcur[u]);
+        v[u] = F32 ? load_entry(a.wval32 + e0 + bcur[u]) : load_entry(a.wval + e0 + bcur[u]);
         cf[u] = 0.0;  // unused
       }
     }
@@ -759,16 +761,19 @@ __device__ __forceinline__ void wave_engine_banded(const SpmvArgs &a, Epi &epi) 
   const int xcd = blockIdx.x & 7;
   const int64_t wi = blockIdx.x >> 3, g8 = gridDim.x >> 3;
   const int64_t nq = (int64_t)a.N * bw / WPB;  // quads per band
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   for (int64_t q = wi; q < nq; q += g8) {
     const int64_t i0 = q * WPB;
     const int64_t base = (i0 / bw) * a.N;
-    __syncthreads();  // the previous quad is done with xs
-    for (int64_t i = threadIdx.x; i < rows * a.N; i += kBlock) xs[i] = gld(a.x + base + i);
-    __syncthreads();
     const int64_t bi = i0 + wave;
     const int64_t k = (bi / bw) * nbr + xcd * bw + bi % bw;
-    wave_block<1, F32, true, Epi, false, SPLIT>(a, k, epi, xs, base, true, rows * a.N);
+    // header loads before the staging, as in wave_engine
+    const WaveRaw raw = wave_head_load<F32, SPLIT>(a, k);
+    if (q != wi) __syncthreads();  // the previous quad is done with xs
+    stage_copy(xs, a.x + base, (int)(rows * a.N));
+    __syncthreads();
+    wave_block_h<1, F32, true, Epi, false, SPLIT>(a, k, wave_head_use(a, k, raw), epi, xs, base,
+                                                  true, rows * a.N);
   }
 }
 
@@ -783,7 +788,7 @@ __device__ __forceinline__ void vector_engine(const SpmvArgs &a, Epi &epi) {
     double acc[2] = {0.0, 0.0};
     if (row < r1) {
       for (int64_t e = a.rp[row] + lane; e < a.rp[row + 1]; e += LPR)
-        cmac(acc[0], acc[1], load_stream(a.val + e), a.x[load_stream(a.col + e)]);
+        cmac(acc[0], acc[1], load_csr(a.val + e), a.x[load_csr(a.col + e)]);
     }
 #pragma unroll
     for (int off = LPR / 2; off > 0; off >>= 1) {
