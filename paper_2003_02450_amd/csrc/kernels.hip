@@ -413,6 +413,7 @@ __device__ __forceinline__ double2 decode(int raw, double cf, double2 v, double2
 struct WaveHead {
   int64_t e0, sh0;
   int gs, gsp, G, len, maxlen, orow;
+  bool dfirst;  // position G holds every row's diagonal
   double2 dg;
 };
 
@@ -470,7 +471,8 @@ __device__ __forceinline__ WaveHead wave_head_use(const SpmvArgs &a, int64_t k, 
   h.sh0 = uniform64(w.s0);
   h.gsp = (int)(uniform64(w.s1) - h.sh0);
   const int g = __builtin_amdgcn_readfirstlane(w.g);
-  h.G = g >= 0 ? g - h.gs : -1;
+  h.G = g >= 0 ? (g & kGlobMask) - h.gs : -1;
+  h.dfirst = g >= 0 && (g & kGlobDiagFirst) != 0;
   h.len = lane < nr ? w.len - h.gs : 0;
   h.maxlen = __builtin_amdgcn_readfirstlane(h.len);
   h.orow = lane < nr ? w.perm : 0;
@@ -649,7 +651,81 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
       }
     }
   };
-  if constexpr (STAGE) {
+  // Phase-split fast path (one right-hand side): in a regular block whose
+  // position G holds every row's diagonal, every other entry is real or
+  // imaginary, and such an entry's product takes two multiply-adds with the
+  // components of x chosen by its phase; they are the complex product's
+  // multiply-adds that do not multiply by zero, in the same order, so the
+  // sums are the generic path's up to the sign of a zero.  The diagonal at G
+  // is a full complex product with x at the lane's own row.  Offsets into the
+  // staged rho-row are 32-bit.  Taken for single-precision values: on the
+  // 1024-vertex operator it measured 81.5 -> 80.0 us per Taylor-term product
+  // there, but 77.6 -> 78.7 us with double values (whose product kernel is
+  // at the edge of its register budget).
+  bool fast = false;
+  if constexpr (STAGE && SPLIT && F32 && NRHS == 1 && !SOA) {
+    const int G = hd.G;
+    const int64_t rho = r0 / a.N * a.N;
+    if (G >= 0 && hd.dfirst && (uint64_t)(rho - base) < lim) {
+      fast = true;
+      const int lrel = (int)(lane_row - base);  // the lane's row in the staged rows
+      const uint32_t lmax = (uint32_t)lim - 1u;
+      // positions p0 .. min(p0 + kWaveUnroll, pend) - 1, gathering from
+      // global memory (MODE kGatherGlobal) or the staged rows (kGatherLds)
+      auto fgroup = [&](auto mode, int p0, int pend) {
+        constexpr int MODE = decltype(mode)::value;
+        int bcur[kWaveUnroll];
+        bool ok[kWaveUnroll];
+#pragma unroll
+        for (int u = 0; u < kWaveUnroll; ++u) {
+          const int cnt = p0 + u < pend ? __popcll(__ballot(len > p0 + u)) : 0;
+          ok[u] = lane < cnt;
+          bcur[u] = ps + lane;
+          ps += cnt;
+        }
+        int c[kWaveUnroll];
+        double cf[kWaveUnroll];
+#pragma unroll
+        for (int u = 0; u < kWaveUnroll; ++u) c[u] = load_entry(cb + bcur[u]);
+#pragma unroll
+        for (int u = 0; u < kWaveUnroll; ++u)
+          cf[u] = F32 ? load_entry(a.wcoef32 + e0 + bcur[u]) : load_entry(a.wcoef + e0 + bcur[u]);
+        double2 xv[kWaveUnroll];
+#pragma unroll
+        for (int u = 0; u < kWaveUnroll; ++u) {
+          const int off = ok[u] ? (int)((uint32_t)c[u] << 2) >> 2 : 0;
+          if constexpr (MODE == kGatherLds)
+            xv[u] = xs[min((uint32_t)(lrel + off), lmax)];
+          else
+            xv[u] = gld(a.x + (lane_row + off));
+        }
+#pragma unroll
+        for (int u = 0; u < kWaveUnroll; ++u) {
+          const bool im = ((uint32_t)c[u] & kImagBit) != 0u;
+          const double cm = ok[u] ? cf[u] : 0.0;
+          const double sx = im ? xv[u].y : xv[u].x;
+          const double sy = im ? xv[u].x : xv[u].y;
+          acc[0] = fma(im ? -cm : cm, sx, acc[0]);
+          acc[1] = fma(cm, sy, acc[1]);
+        }
+      };
+      int p0 = 0;
+      for (; p0 < G; p0 += kWaveUnroll) fgroup(std::integral_constant<int, kGatherGlobal>{}, p0, G);
+      {
+        // position G: every running row's diagonal (stored in the stream as
+        // a marker, its value in dg)
+        const int cnt = __popcll(__ballot(len > G));
+        const double2 vz = masked(lane < cnt, dg);
+        cmac(acc[0], acc[1], vz, xs[lrel]);
+        ps += cnt;
+      }
+      for (p0 = G + 1; p0 < maxlen; p0 += kWaveUnroll)
+        fgroup(std::integral_constant<int, kGatherLds>{}, p0, maxlen);
+    }
+  }
+  if (fast) {
+    // done above
+  } else if constexpr (STAGE) {
     // The layout puts each row's entries outside its rho-row first; in a
     // block whose rows share one rho-row and all leave it at the same
     // position G (wglob[k] = G, else -1), positions < G gather from global
@@ -1179,10 +1255,17 @@ __global__ __launch_bounds__(kBlock) void wjag_plan_kernel(const int64_t *rp, co
       }
     }
   }
+  // In a regular block, is the entry at position G (the first inside entry,
+  // at CSR index lo) every row's diagonal?  (Assembled rows put it first.)
+  bool dfirst = false;
+  if (regular) {
+    const bool okd = lane >= nr || (w.len > G && (int64_t)col[w.src0 + w.lo] == w.row);
+    dfirst = __ballot(!okd) == 0;
+  }
   long long cnt = lane < nr ? (long long)(w.len - gs) : 0;
   for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
   if (lane == 0) {
-    wglob[k] = regular ? G : -1;
+    wglob[k] = regular ? (G | (dfirst ? kGlobDiagFirst : 0)) : -1;
     wshn[k] = gs;
     wcnt[k] = cnt;
   }

@@ -77,6 +77,9 @@ struct AssembleArgs {
 // is the length of the row of rank r (shared positions included) and
 // wperm[64 k + r] its index within the block.
 constexpr int kWaveRows = 64;
+// wglob[k]: G | kGlobDiagFirst when position G holds every row's diagonal
+constexpr int32_t kGlobDiagFirst = 1 << 30;
+constexpr int32_t kGlobMask = kGlobDiagFirst - 1;
 constexpr int kWavePad = 64;  // zero entries after the wave-jagged arrays (reads past a block's end)
 constexpr size_t kStageMaxBytes = 32768;  // largest LDS-staged rho-row (N <= 2048)
 

@@ -605,7 +605,7 @@ hipError_t dedup_blocks(WaveLayout &W, int64_t n, const std::vector<int64_t> &hc
     std::map<std::tuple<unsigned long long, int64_t, int32_t>, int64_t> first;
     int64_t dup = 0;
     for (size_t k = 0; k < nwb; ++k) {
-      const int32_t g = hglob[k] < 0 ? -1 : hglob[k] - hshn[k];
+      const int32_t g = hglob[k] < 0 ? -1 : (hglob[k] & kGlobMask) - hshn[k];
       auto it = first.emplace(std::make_tuple(hh[k], hcnt[k], g), (int64_t)k).first;
       hcanon[k] = it->second;
       dup += it->second != (int64_t)k;
