@@ -2160,9 +2160,23 @@ __global__ __launch_bounds__(kBlock, (R >= 2 ? 4 : 1)) void batch_work_kernel(Ba
           const double2 *x0 = A.op[f.x].x;
           base = ((int64_t)f.y * kWaveRows) / N0 * N0;
           __syncthreads();  // earlier blocks are done with xs
-          for (int i = threadIdx.x; i < R * N0; i += kBlock) {
-            const int r = i / N0;
-            xs[i] = gld(x0 + (int64_t)r * n0r + base + (i - r * N0));
+          // xs[r N0 + c] = x0[r n0r + base + c], four loads per thread in
+          // flight before their LDS writes (one round trip per 4 kBlock
+          // elements instead of per kBlock; more would cost registers here)
+          {
+            const int cnt = R * N0;
+            for (int i0 = threadIdx.x; i0 < cnt; i0 += 4 * kBlock) {
+              double2 v[4];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                const int i = min(i0 + u * kBlock, cnt - 1);
+                const int r = i / N0;
+                v[u] = gld(x0 + (int64_t)r * n0r + base + (i - r * N0));
+              }
+#pragma unroll
+              for (int u = 0; u < 4; ++u)
+                if (i0 + u * kBlock < cnt) xs[i0 + u * kBlock] = v[u];
+            }
           }
           __syncthreads();
         }
