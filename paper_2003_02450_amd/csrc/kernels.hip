@@ -2551,11 +2551,15 @@ hipError_t launch_unit_cols(double2 *X, int64_t n, int64_t i0, int64_t i1, hipSt
 hipError_t launch_topk(const double *h, int64_t n, int K, int grid, double *cand_v, int64_t *cand_i,
                        double *out_v, int64_t *out_i, hipStream_t s) {
   if (K < 1 || K > kTopKMax) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(topk_partial_kernel, dim3(grid), dim3(kBlock), 0, s, h, n, K, cand_v, cand_i);
+  // At most 256 partial workgroups: the one-workgroup merge scans every
+  // candidate once per round (with 4096 partials it took 60 us).  The top K
+  // under the (value, smaller index) order does not depend on the split.
+  const int g = grid < 256 ? grid : 256;
+  hipLaunchKernelGGL(topk_partial_kernel, dim3(g), dim3(kBlock), 0, s, h, n, K, cand_v, cand_i);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(topk_merge_kernel, dim3(1), dim3(kBlock), 0, s, cand_v, cand_i,
-                     (int64_t)grid * K, K, out_v, out_i);
+                     (int64_t)g * K, K, out_v, out_i);
   return hipGetLastError();
 }
 

@@ -206,9 +206,41 @@ struct DeviceOps {
   double *K = nullptr;
   int64_t *PH = nullptr;
   int64_t *PR = nullptr;
-  void release() {
-    dfree(hp); dfree(hc); dfree(hv); dfree(hdiag); dfree(rp); dfree(rc); dfree(rv);
-    dfree(rdiag); dfree(K); dfree(PH); dfree(PR);
+  char *block = nullptr;  // all of the above, one allocation
+  void release() { dfree(block); }
+};
+
+// Host arrays uploaded as one device block: one allocation and one copy
+// (eleven pageable copies took about 40 us each).  Each array starts on a
+// 256-byte boundary.  The staging vector must outlive the copy.
+struct PackedUpload {
+  struct Item {
+    void **dst;
+    const void *src;
+    size_t bytes;
+  };
+  std::vector<Item> items;
+  std::vector<char> host;
+  template <class T>
+  void add(T **dst, const void *src, size_t count) {
+    items.push_back({(void **)dst, src, count * sizeof(T)});
+  }
+  hipError_t run(char **block, hipStream_t s) {
+    std::vector<size_t> off;
+    size_t total = 0;
+    for (const Item &it : items) {
+      off.push_back(total);
+      total += (it.bytes + 255) & ~(size_t)255;
+    }
+    if (total == 0) total = 256;
+    hipError_t e = dalloc(block, total);
+    if (e != hipSuccess) return e;
+    host.assign(total, 0);
+    for (size_t k = 0; k < items.size(); ++k) {
+      if (items[k].bytes) std::memcpy(host.data() + off[k], items[k].src, items[k].bytes);
+      *items[k].dst = *block + off[k];
+    }
+    return hipMemcpyAsync(*block, host.data(), total, hipMemcpyHostToDevice, s);
   }
 };
 
@@ -259,22 +291,20 @@ qsw_status_t assemble(const HostOps &op, const Rates &R, bool adjoint, double om
   int64_t *drp = nullptr;
   int32_t *dcol = nullptr;
   double2 *dval = nullptr;
+  PackedUpload up;
   do {
-    if ((e = upload(&d.hp, op.hp, s)) != hipSuccess) break;
-    if ((e = upload(&d.hc, op.hc, s)) != hipSuccess) break;
-    if ((e = dalloc(&d.hv, op.hc.size())) != hipSuccess) break;
-    if (!op.hc.empty() &&
-        (e = hipMemcpyAsync(d.hv, hvec.data(), hvec.size() * sizeof(double),
-                            hipMemcpyHostToDevice, s)) != hipSuccess)
-      break;
-    if ((e = upload(&d.hdiag, op.hdiag, s)) != hipSuccess) break;
-    if ((e = upload(&d.rp, *rp, s)) != hipSuccess) break;
-    if ((e = upload(&d.rc, *rc, s)) != hipSuccess) break;
-    if ((e = upload(&d.rv, *rv, s)) != hipSuccess) break;
-    if ((e = upload(&d.rdiag, R.rdiag, s)) != hipSuccess) break;
-    if ((e = upload(&d.K, K, s)) != hipSuccess) break;
-    if ((e = upload(&d.PH, PH, s)) != hipSuccess) break;
-    if ((e = upload(&d.PR, PR, s)) != hipSuccess) break;
+    up.add<int64_t>(&d.hp, op.hp.data(), op.hp.size());
+    up.add<int32_t>(&d.hc, op.hc.data(), op.hc.size());
+    up.add<double2>(&d.hv, hvec.data(), hvec.size() / 2);
+    up.add<double>(&d.hdiag, op.hdiag.data(), op.hdiag.size());
+    up.add<int64_t>(&d.rp, rp->data(), rp->size());
+    up.add<int32_t>(&d.rc, rc->data(), rc->size());
+    up.add<double>(&d.rv, rv->data(), rv->size());
+    up.add<double>(&d.rdiag, R.rdiag.data(), R.rdiag.size());
+    up.add<double>(&d.K, K.data(), K.size());
+    up.add<int64_t>(&d.PH, PH.data(), PH.size());
+    up.add<int64_t>(&d.PR, PR.data(), PR.size());
+    if ((e = up.run(&d.block, s)) != hipSuccess) break;
     if ((e = dalloc(&drp, (size_t)n + 1)) != hipSuccess) break;
     if ((e = dalloc(&dcol, (size_t)nnz)) != hipSuccess) break;
     if ((e = dalloc(&dval, (size_t)nnz)) != hipSuccess) break;
