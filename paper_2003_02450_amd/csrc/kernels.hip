@@ -109,8 +109,8 @@ __device__ __forceinline__ void gst<double2>(double2 *p, const double2 &v) {
 
 // Matrix entries of the wave layout.  Blocks with equal stored rows share
 // one copy, which many blocks of a product read again, so these are plain
-// (cached) loads: non-temporal hints evicted the shared copies and cost 8 %
-// of a product on the 1024-vertex operator.
+// (cached) loads: with non-temporal hints a product on the 1024-vertex
+// operator took 8 % longer (at about the same L2 traffic).
 __device__ __forceinline__ double2 load_entry(const double2 *p) { return gld(p); }
 __device__ __forceinline__ int load_entry(const int32_t *p) { return gld(p); }
 __device__ __forceinline__ double load_entry(const double *p) { return gld(p); }
