@@ -797,11 +797,14 @@ bool banded_ok(int32_t N) { return N == 512 || N == 1024 || N == 2048; }
 // Its grid: a multiple of the 8 XCDs.
 int banded_grid(int grid) { return std::max(8, grid / 8 * 8); }
 
-// Workgroups of a wave-jagged launch: one wavefront per block up to four
-// times the resident capacity, then blocks per wavefront grow.
+// Workgroups of a wave-jagged launch: one wavefront per block up to twice
+// the resident capacity, then blocks per wavefront grow.
 int wave_grid(int64_t nwb, int resident) {
   const int64_t wgs = (nwb + kBlockThreads / 64 - 1) / (kBlockThreads / 64);
-  int64_t cap = 4 * (int64_t)std::max(resident, 1);
+  // two rounds of resident workgroups, each taking its quads grid-stride:
+  // on the 1024-vertex operator a Taylor-term product took 78.2 us with one
+  // quad per workgroup (4096), 72.4-73.0 with 1.5-2 rounds, 74.1 with one
+  int64_t cap = 2 * (int64_t)std::max(resident, 1);
   cap = env_int("QSW_GRID", (int)cap);
   return (int)std::max<int64_t>(1, std::min(wgs, cap));
 }
