@@ -375,6 +375,7 @@ qsw_status_t qsw_engine_submit(qsw_engine_t e, const qsw_walk_t *w, int64_t *tic
   I.wstart = h->wstart;
   I.wshn = h->wshared > 0 ? h->wshn : nullptr;
   I.wshs = h->wshs;
+  I.wsh_stride = h->wsh_stride;
   I.wsh = h->wsh;
   I.split = h->split ? 1 : 0;
   I.wlen = h->wlen;

@@ -111,6 +111,7 @@ struct qsw_superop_s {
   int64_t *wstart = nullptr;      // per block: first per-row entry
   int64_t *wshs = nullptr;        // per block: first shared entry (padded prefix)
   qsw::SharedEntry *wsh = nullptr;
+  int32_t wsh_stride = 0;         // shared entries of block k at wsh + k wsh_stride
   int64_t wentries = 0;           // per-row entries stored
   int64_t wshared = 0;            // shared entries stored (padded)
   int64_t wdistinct = 0;          // per-row entries in the copies the blocks read

@@ -405,20 +405,21 @@ __device__ __forceinline__ double2 decode(int raw, double cf, double2 v, double2
 // the rho-row of every column (xs[r N + i]) and `staged` says whether it
 // belongs to this block's x.
 // Header of block k of the wave layout, per lane: the block's first stored
-// entry e0, its shared leading positions (gs, stored padded to gsp, from
-// sh0), the position G where its rows enter their rho-row (-1: none, after
-// the shared ones), the lane's row length after the shared positions, the
-// longest one (rank 0), the lane's row (orow) and its diagonal (phase-split
-// layouts).
+// entry e0, its shared leading positions (gs, stored zero-padded to gsp at
+// k wsh_stride; the lane's entry in `mine`), the position G where its rows
+// enter their rho-row (-1: none, after the shared ones), the lane's row
+// length after the shared positions, the longest one (rank 0), the lane's
+// row (orow) and its diagonal (phase-split layouts).
 struct WaveHead {
-  int64_t e0, sh0;
+  int64_t e0;
   int gs, gsp, G, len, maxlen, orow;
   bool dfirst;  // position G holds every row's diagonal
   double2 dg;
+  SharedEntry mine;  // shared entry `lane` of the block (lanes < gsp used)
 };
 
 // Stand-ins read by blocks of layouts without shared positions or G.
-__device__ const int64_t kHeadZero64[2] = {0, 0};
+__device__ const SharedEntry kHeadNoShared[1] = {{0, 0u, 0.0}};
 __device__ const int32_t kHeadZero32[1] = {0};
 __device__ const int32_t kHeadNoG[1] = {-1};
 
@@ -427,9 +428,10 @@ __device__ const int32_t kHeadNoG[1] = {-1};
 // together, and with whatever the caller issues before wave_head_use; k is
 // wave-uniform.  Lanes past the block's rows read row r0 and are masked.
 struct WaveRaw {
-  int64_t e0, s0, s1;
+  int64_t e0;
   int n, g, len, perm;
   double2 dg;
+  SharedEntry sh;
 };
 
 template <bool F32, bool SPLIT>
@@ -440,14 +442,17 @@ __device__ __forceinline__ WaveRaw wave_head_load(const SpmvArgs &a, int64_t k) 
   const int li = lane < nr ? lane : 0;
   const int64_t *pe = a.wstart ? a.wstart + k : a.rp + r0;
   const int32_t *pn = a.wshn ? a.wshn + k : kHeadZero32;
-  const int64_t *ps = a.wshn ? a.wshs + k : kHeadZero64;
   const int32_t *pg = a.wglob ? a.wglob + k : kHeadNoG;
+  // the block's shared entries sit at k wsh_stride: lane i loads entry i
+  // with the header (lanes past the stride re-read the last one)
+  const SharedEntry *psh = a.wshn && a.wsh_stride > 0
+                               ? a.wsh + k * (int64_t)a.wsh_stride + min(lane, a.wsh_stride - 1)
+                               : kHeadNoShared;
   WaveRaw w;
   w.e0 = gld(pe);
   w.n = gld(pn);
-  w.s0 = gld(ps);
-  w.s1 = gld(ps + 1);
   w.g = gld(pg);
+  w.sh = gld(psh);
   w.len = gld(a.wlen + r0 + li);
   w.perm = (int)gld(a.wperm + r0 + li);
   w.dg = make_double2(0.0, 0.0);
@@ -468,8 +473,8 @@ __device__ __forceinline__ WaveHead wave_head_use(const SpmvArgs &a, int64_t k, 
   WaveHead h;
   h.e0 = uniform64(w.e0);
   h.gs = __builtin_amdgcn_readfirstlane(w.n);
-  h.sh0 = uniform64(w.s0);
-  h.gsp = (int)(uniform64(w.s1) - h.sh0);
+  h.gsp = (h.gs + kSharedPad - 1) / kSharedPad * kSharedPad;  // zero-padded count
+  h.mine = w.sh;
   const int g = __builtin_amdgcn_readfirstlane(w.g);
   h.G = g >= 0 ? (g & kGlobMask) - h.gs : -1;
   h.dfirst = g >= 0 && (g & kGlobDiagFirst) != 0;
@@ -497,7 +502,6 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
   const int nr = (int)min((int64_t)kWaveRows, a.n - r0);
   const int64_t e0 = hd.e0;
   const int gsp = hd.gsp;
-  const int64_t sh0 = hd.sh0;
   const int len = hd.len;
   const int maxlen = hd.maxlen;
   const int orow = hd.orow;
@@ -515,13 +519,13 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
     const int64_t row = r0 + orow;
     constexpr int SU = NRHS == 1 ? kSharedPad : (NRHS == 2 ? kSharedPad / 2 : kSharedPad / 4);
     static_assert(kSharedPad % SU == 0, "shared groups divide the padding");
-    // up to 64 entries at a time: lane i loads entry i once, and each
-    // group takes its entries from the lanes (no load between the groups'
-    // gathers)
-    for (int b = 0; b < gsp; b += 64) {
-      const int cnt = min(64, gsp - b);  // a multiple of SU
-      SharedEntry mine{0, 0u, 0.0};
-      if (lane < cnt) mine = gld(a.wsh + sh0 + b + lane);
+    // lane i loaded entry i with the block header (at most kSharedMax
+    // entries), and each group takes its entries from the lanes (no load
+    // between the groups' gathers)
+    static_assert(kSharedMax <= 64, "one shared entry per lane");
+    {
+      const int cnt = gsp;  // a multiple of SU
+      const SharedEntry mine = hd.mine;
       const unsigned long long mine_coef = (unsigned long long)__double_as_longlong(mine.coef);
       // one group of S positions: S gathers in flight, then the sums (wider
       // groups of 16 measured no faster)
@@ -1230,7 +1234,7 @@ __global__ __launch_bounds__(kBlock) void wjag_plan_kernel(const int64_t *rp, co
     if (__ballot(!w.consecutive) == 0) {
       // eight positions' loads in flight per step (gmin > 0: every row of
       // the block has entries)
-      for (int q0 = 0; q0 < gmin && gs == q0; q0 += 8) {
+      for (int q0 = 0; q0 < gmin && q0 < kSharedMax && gs == q0; q0 += 8) {
         int32_t cc[8];
         double2 vv[8];
         wjag_load8(col, val, w, q0, cc, vv);
@@ -1242,7 +1246,7 @@ __global__ __launch_bounds__(kBlock) void wjag_plan_kernel(const int64_t *rp, co
       }
     } else {
       int io = 0, ii = 0;
-      for (int q = 0; q < gmin; ++q) {
+      for (int q = 0; q < gmin && q < kSharedMax; ++q) {
         int64_t c = 0;
         double2 v = make_double2(0.0, 0.0);
         if (lane < nr) {
@@ -2212,6 +2216,7 @@ __global__ __launch_bounds__(kBlock, (R >= 2 ? 4 : 1)) void batch_work_kernel(Ba
         a.wshn = I.wshn;
         a.wshs = I.wshs;
         a.wsh = I.wsh;
+        a.wsh_stride = I.wsh_stride;
         a.wlen = I.wlen;
         a.wperm = I.wperm;
         a.nwb = I.nwb;

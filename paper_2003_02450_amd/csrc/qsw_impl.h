@@ -111,6 +111,10 @@ struct SharedEntry {
   double coef;
 };
 constexpr int kSharedPad = 8;
+// At most this many leading positions of a block are shared, so a block's
+// shared entries are one load per lane and sit at a fixed stride (a block
+// with more keeps the rest in its rows).
+constexpr int kSharedMax = 64;
 static_assert(sizeof(SharedEntry) == 16, "a shared entry is read as one 16-byte load");
 
 struct SpmvArgs {
@@ -140,8 +144,9 @@ struct SpmvArgs {
   const int32_t *wglob;  // per block: first position inside the rho-row, or -1 (may be null)
   const int64_t *wstart; // per block: first per-row entry (with shared positions), or null: rp
   const int32_t *wshn;   // per block: shared leading positions (null: none)
-  const int64_t *wshs;   //   first shared entry of block k (nwb + 1 prefix, padded counts)
+  const int64_t *wshs;   //   first shared entry of block k: k wsh_stride
   const SharedEntry *wsh;
+  int32_t wsh_stride;    //   entries per block (a multiple of kSharedPad, <= kSharedMax)
   const double2 *x;      // gathered vector (NRHS interleaved columns for the estimator)
   const double2 *fin;    // accumulator in (Taylor mode)
   double2 *fout;         // accumulator out (may equal fin)
@@ -188,6 +193,7 @@ struct BatchInst {
   const int32_t *wshn;
   const int64_t *wshs;
   const SharedEntry *wsh;
+  int32_t wsh_stride;
   int64_t n, nwb;
   int64_t vlen;      // n * R: complex elements of one work vector
   int32_t N, f32, split;  // f32: single-precision values; split: phase-split values

@@ -578,9 +578,10 @@ struct WaveLayout {
   int32_t *shn = nullptr;
   int64_t *start = nullptr, *shs = nullptr;
   SharedEntry *sh = nullptr;
+  int32_t stride = 0;   // shared entries of block k at sh + k stride
   int64_t nwb = 0;
   int64_t entries = 0;  // per-row entries stored (without the shared positions)
-  int64_t shared = 0;   // shared entries stored (padded)
+  int64_t shared = 0;   // shared entries read per product (padded counts)
   int64_t distinct = 0; // per-row entries in the copies the blocks read (after dedup)
   void release_values() {
     dfree(col);
@@ -708,13 +709,21 @@ hipError_t build_wave_layout(const int64_t *rp, const int32_t *col, const double
           hipSuccess)
         break;
       if ((e = hipStreamSynchronize(s)) != hipSuccess) break;
-      hstart[0] = hshs[0] = 0;
+      // shared entries at a fixed stride per block (the largest padded
+      // count): a block's address is known before its header is read
+      hstart[0] = 0;
+      int64_t padded = 0;
+      int32_t stride = 0;
       for (size_t k = 0; k < nwb; ++k) {
         hstart[k + 1] = hstart[k] + hcnt[k];
-        hshs[k + 1] = hshs[k] + (hshn[k] + kSharedPad - 1) / kSharedPad * kSharedPad;
+        const int32_t pc = (hshn[k] + kSharedPad - 1) / kSharedPad * kSharedPad;
+        padded += pc;
+        stride = std::max(stride, pc);
       }
+      for (size_t k = 0; k <= nwb; ++k) hshs[k] = (int64_t)k * stride;
+      W.stride = stride;
       W.entries = W.distinct = hstart[nwb];
-      W.shared = hshs[nwb];
+      W.shared = padded;
       if ((e = hipMemcpyAsync(W.start, hstart.data(), (nwb + 1) * sizeof(int64_t),
                               hipMemcpyHostToDevice, s)) != hipSuccess)
         break;
@@ -734,7 +743,8 @@ hipError_t build_wave_layout(const int64_t *rp, const int32_t *col, const double
         if ((e = dalloc(&W.val, ent)) != hipSuccess) break;
         if ((e = launch_zero(W.val + W.entries, kWavePad * sizeof(double2), s)) != hipSuccess) break;
       }
-      if ((e = dalloc(&W.sh, std::max<size_t>(1, (size_t)W.shared))) != hipSuccess) break;
+      if ((e = dalloc(&W.sh, std::max<size_t>(1, (size_t)nwb * (size_t)W.stride))) != hipSuccess)
+        break;
       if ((e = launch_zero(bad, sizeof(int), s)) != hipSuccess) break;
       if ((e = launch_wjag_fill(rp, col, val, n, N, split, W.shn, W.start, W.shs, W.col, W.val,
                                 W.coef, W.diag, W.len, W.perm, W.sh, bad, s)) != hipSuccess)
@@ -769,6 +779,7 @@ void set_wave(SpmvArgs &a, const WaveLayout &W) {
   a.wshn = W.shared > 0 ? W.shn : nullptr;
   a.wshs = W.shs;
   a.wsh = W.sh;
+  a.wsh_stride = W.stride;
 }
 
 void set_wave(SpmvArgs &a, const qsw_superop_s *h) {
@@ -788,6 +799,7 @@ void set_wave(SpmvArgs &a, const qsw_superop_s *h) {
   a.wshn = h->wshared > 0 ? h->wshn : nullptr;
   a.wshs = h->wshs;
   a.wsh = h->wsh;
+  a.wsh_stride = h->wsh_stride;
 }
 
 // The XCD-banded engine needs N/64 blocks per rho-row in 8 bands and at most
@@ -1161,6 +1173,7 @@ qsw_status_t build_common(std::shared_ptr<Assembler> src, double omega, hipStrea
     h->wstart = W.start;
     h->wshs = W.shs;
     h->wsh = W.sh;
+    h->wsh_stride = W.stride;
     h->wentries = W.entries;
     h->wshared = W.shared;
     h->wdistinct = W.distinct;

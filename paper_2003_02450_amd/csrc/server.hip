@@ -79,7 +79,7 @@ size_t op_bytes(const qsw_superop_s *h) {
   const size_t n = (size_t)h->n, nnz = (size_t)h->nnz, pnz = (size_t)h->wentries + kWavePad;
   const size_t nwb = (n + 63) / 64;
   size_t b = 8 * (n + 1) + 4 * nnz + 16 * nnz;  // CSR
-  b += 4 * pnz + 4 * n + n + 24 * nwb + 16 * (size_t)h->wshared;  // columns, rows, blocks, shared
+  b += 4 * pnz + 4 * n + n + 24 * nwb + 16 * (size_t)nwb * (size_t)h->wsh_stride;  // columns, rows, blocks, shared
   b += h->split ? 8 * pnz + 16 * n : 16 * pnz;    // values
   if (h->wval32) b += 8 * pnz;
   if (h->wcoef32) b += 4 * pnz + 8 * n;
