@@ -104,9 +104,16 @@ def test_complex_entries_fall_back():
 
 
 @pytest.mark.parametrize("single", [False, True])
-def test_shared_positions_change_nothing(monkeypatch, single):
+@pytest.mark.parametrize("dense", [False, True])
+def test_shared_positions_change_nothing(monkeypatch, single, dense):
+    """Shared leading positions (at most 64 per block: the dense graph's
+    H rows have more neighbours, and the rest stay in the rows) give the
+    unshared layout's sums."""
     import torch
-    wl = random_workload(256, 6, 0.35, 815, n_steps=3, dt=0.5)
+    if dense:
+        wl = random_workload(128, 40, 0.35, 816, n_steps=2, dt=0.2)
+    else:
+        wl = random_workload(256, 6, 0.35, 815, n_steps=3, dt=0.5)
     monkeypatch.delenv("QSW_SHARED", raising=False)
     sh = build_gpu(wl)
     monkeypatch.setenv("QSW_SHARED", "0")
@@ -115,6 +122,7 @@ def test_shared_positions_change_nothing(monkeypatch, single):
     i_sh, i_un = sh.info(), un.info()
     assert i_sh["split"] and i_un["split"]
     assert i_sh["shared_entries"] > 0 and i_un["shared_entries"] == 0
+    assert i_sh["shared_entries"] <= 64 * ((i_sh["n"] + 63) // 64)
     assert i_sh["stream_entries"] < i_un["stream_entries"] == i_un["nnz"]
     assert i_sh["d"] == i_un["d"] and i_sh["norm1"] == i_un["norm1"]
     for op in (sh, un):
