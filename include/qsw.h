@@ -3,7 +3,7 @@
  * walk) propagation on one AMD MI355X (gfx950) GPU.
  *
  * The library builds the vectorised Lindblad superoperator L of a walk on a
- * graph (Section 2.4.1 eq. qsw, vectorised by eq. vec_mappings) as a
+ * graph (Section 2.5.1 eq. qsw, vectorised by eq. vec_mappings) as a
  * complex128 CSR matrix in device memory, and evaluates
  *     rho(t_k) = unvec( exp(t_k L) vec(rho0) ),  t_k = t0 + k dt,
  * by the truncated-Taylor method with scaling and early termination that the
@@ -55,7 +55,7 @@ typedef enum {
 /* Build flags (bitwise OR). */
 enum {
     QSW_H_LAPLACIAN = 0,    /* H = transition matrix of G^u (eq. generator_matrix on the
-                               undirected companion, Section 2.4.1): the weighted Laplacian for gamma = 1 */
+                               undirected companion, Section 2.5.1): the weighted Laplacian for gamma = 1 */
     QSW_H_ADJACENCY = 1,    /* H = G^u itself (the paper's three-vertex example passes H = GU) */
     QSW_R_TRANSITION = 0,   /* L_k = sqrt(gamma G_ij)|i><j| for every arc (eq. lindblad) */
     QSW_R_COLNORM = 2,      /* L_k = sqrt(G_ij / OutDeg(j))|i><j| (column-normalised rates) */
@@ -112,7 +112,7 @@ typedef struct {
 /* ---------------------------------------------------------------- build */
 
 /*
- * Build the L-QSW superoperator of a graph (Section 2.4.1; H from G^u,
+ * Build the L-QSW superoperator of a graph (Section 2.5.1; H from G^u,
  * L_k from the CTRW transition matrix of G, eq. generator_matrix and eq.
  * lindblad), assemble it in device CSR (int64 row_ptr, int32 columns,
  * complex128 values; each row in structural order: the H rho entries by
@@ -133,7 +133,7 @@ qsw_status_t qsw_superop_build(int32_t N, const int64_t *row_ptr, const int32_t 
                                void *hip_stream, qsw_superop_t *out);
 
 /*
- * qsw_superop_build on the augmented digraph of Section 2.4.2 (eq.
+ * qsw_superop_build on the augmented digraph of Section 2.5.1 (eq.
  * dimer_aug, eq. qsw_ss): n_sources source vertices (numbered N .. N +
  * n_sources - 1, source k feeding graph vertex source_vertex[k] at rate
  * source_rate[k]) and n_sinks sink vertices (numbered after them, sink k
@@ -168,7 +168,7 @@ qsw_status_t qsw_superop_build_ops(int32_t N,
                                    qsw_superop_t *out);
 
 /*
- * qsw_superop_build_ops with absorption and emission channels (Section 2.4.2,
+ * qsw_superop_build_ops with absorption and emission channels (Section 2.5.1,
  * eq. qsw_ss): M_free is a second real coefficient matrix (host CSR, same
  * rules as M_L) whose L_k = M_free[i][j] |i><j| enter with rate
  * |M_free[i][j]|^2 OUTSIDE the factor omega, e.g. sources (arcs from a source
@@ -185,7 +185,7 @@ qsw_status_t qsw_superop_build_open(int32_t N, const int64_t *h_row_ptr, const i
                                     void *hip_stream, qsw_superop_t *out);
 
 /*
- * A walk with explicit Lindblad operators (Section 2.4.3, eq. L_global, and
+ * A walk with explicit Lindblad operators (Section 2.5.2, eq. L_global, and
  * the non-moralising form eq. nm_gqsw):
  *     L rho = -i(1-omega)[H, rho] + omega ( i[H_rot, rho] + sum_k D[L_k] rho ),
  *     D[L] rho = L rho L^dag - 1/2 {L^dag L, rho}.
@@ -204,7 +204,7 @@ qsw_status_t qsw_superop_build_general(int32_t N, const int64_t *h_row_ptr, cons
                                        qsw_superop_t *out);
 
 /*
- * The non-moralising G-QSW of a digraph (Section 2.4.3, graph demoralisation
+ * The non-moralising G-QSW of a digraph (Section 2.5.2, graph demoralisation
  * and eq. nm_gqsw), built on the expanded vertex set: vertex v keeps
  * d_v = max(1, number of arcs into v) copies (qsw_demoralised_order),
  * numbered consecutively; copies of joined vertices are linked with weight

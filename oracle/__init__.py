@@ -14,7 +14,7 @@ Pins (each checked by the CPU tests):
 * dense.expm against closed forms and against scipy.linalg.expm;
 * theta_m against the definition at two series lengths and against the
   published magnitudes of Al-Mohy and Higham's table;
-* the omega = 0 closed form (Liouville-von Neumann / CTQW, Section 2.3),
+* the omega = 0 closed form (CTQW and Liouville-von Neumann, Sections 2.3-2.4),
   the omega = 1 classical limit (CTRW, Section 2.2), the paper's printed
   three-vertex results (Section 4), density-matrix invariants (Section 2.4),
   the maximally mixed fixed point on regular graphs (Section 4), step vs
@@ -57,7 +57,7 @@ def general_superop(H, Ls, omega, H_rot=None, Ls_free=()) -> "CSR":
 
 def channel_superop(graph_dense, omega, sources, sinks, h_mode="laplacian",
                     r_mode="transition", dephasing=False, gamma=1.0) -> "CSR":
-    """A walk on the augmented digraph (Section 2.4.2): the graph's H and
+    """A walk on the augmented digraph (Section 2.5.1): the graph's H and
     L_k (omega-scaled) padded with the source and sink vertices, plus the
     channels outside omega.  Dense (small N only)."""
     import numpy as np

@@ -9,7 +9,7 @@ checked against the paper by eye:
   for i != j, M_jj = gamma OutDeg(j), OutDeg(v_j) = sum_i G_ij (eq. out_degree).
 * ``undirected``          - G^u_ij = max(G_ij, G_ji) (Section 2.1).
 * ``walk_operators``      - H and the Lindblad operators of the L-QSW
-  (Section 2.4.1, eq. lindblad): L_k = sqrt(|M_ij|) |v_i><v_j|.
+  (Section 2.5.1, eq. lindblad): L_k = sqrt(|M_ij|) |v_i><v_j|.
 * ``lindblad_ops``        - the explicit list of L_k matrices.
 * ``superop_kron``        - the vectorised generator of eq. qsw built literally
   from the Kronecker mappings of eq. vec_mappings with column stacking
@@ -18,7 +18,7 @@ checked against the paper by eye:
   L_k scaled by omega (the G-QSW of eq. L_global has one, L = G), the
   rotating Hamiltonian term omega i[H_rot, rho] of eq. nm_gqsw, and L_k
   outside omega (the absorption / emission channels of eq. qsw_ss).
-* ``augmented``           - the augmented digraph of Section 2.4.2 (eq.
+* ``augmented``           - the augmented digraph of Section 2.5.1 (eq.
   dimer_aug): source and sink vertices appended after the graph's.
 
 Conventions (readings of the paper, listed in the design notes):
@@ -206,7 +206,7 @@ def augmented(G: np.ndarray, sources, sinks):
 
 
 def demoralise(G: np.ndarray, gamma: float = 1.0):
-    """The non-moralising construction of Section 2.4.3 (graph demoralisation),
+    """The non-moralising construction of Section 2.5.2 (graph demoralisation),
     dense: returns (copies, H_D, L_D, H_rot) on the expanded vertex set.
 
     * Vertex v keeps d_v = max(1, number of arcs into v) copies, numbered

@@ -8,7 +8,7 @@
  *
  * Everything is plain float64 / complex128, one obvious loop per formula.
  *
- * Superoperator (Section 2.4.1 eq. qsw with the vectorisation of eq.
+ * Superoperator (Section 2.5.1 eq. qsw with the vectorisation of eq.
  * vec_mappings, written for the ROW-MAJOR vec index r(a,b) = a*N + b of
  * rho_ab).  With L_k = sqrt(R_ij)|i><j| (eq. lindblad, R_ij = |M_ij|) one has
  * L_k rho L_k^dag = R_ij rho_jj |i><i| and sum_k L_k^dag L_k = diag(K),

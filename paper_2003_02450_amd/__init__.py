@@ -112,7 +112,7 @@ class Superop:
     @classmethod
     def from_channels(cls, graph, omega, sources=(), sinks=(), gamma=1.0, h_mode="laplacian",
                       r_mode="transition", dephasing=False, device=None):
-        """Walk on the augmented digraph (Section 2.4.2): sources = [(vertex,
+        """Walk on the augmented digraph (Section 2.5.1): sources = [(vertex,
         Gamma)], sinks = [(vertex, Theta)]; source k is vertex N + k, sink k
         vertex N + len(sources) + k; the channels act outside omega."""
         torch = _torch()
@@ -136,7 +136,7 @@ class Superop:
 
     @classmethod
     def from_general(cls, H, Ls, omega, H_rot=None, device=None):
-        """Explicit Lindblad operators (Section 2.4.3): H and H_rot Hermitian,
+        """Explicit Lindblad operators (Section 2.5.2): H and H_rot Hermitian,
         Ls a list of complex matrices (scipy sparse or dense); the G-QSW of
         eq. L_global is Ls = [G]."""
         torch = _torch()
@@ -171,7 +171,7 @@ class Superop:
 
     @classmethod
     def from_demoralised(cls, graph, omega, gamma=1.0, device=None):
-        """The non-moralising G-QSW of a digraph (Section 2.4.3) on its
+        """The non-moralising G-QSW of a digraph (Section 2.5.2) on its
         expanded vertex set; `copies` (d_v per vertex) maps states and
         populations (demoralised_state / demoralised_populations)."""
         torch = _torch()

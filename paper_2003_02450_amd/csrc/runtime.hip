@@ -1551,7 +1551,7 @@ void qsw::pool_free(void *p) {
 
 namespace {
 
-// Operators of a walk on a graph (Section 2.4.1): H from G^u, rates from G
+// Operators of a walk on a graph (Section 2.5.1): H from G^u, rates from G
 // (eq. generator_matrix, eq. lindblad), as the flags select.
 qsw_status_t graph_ops(int32_t N, const int64_t *row_ptr, const int32_t *col_idx, const double *w,
                        double gamma, uint32_t flags, HostOps &op) {

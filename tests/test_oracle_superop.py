@@ -44,7 +44,7 @@ def test_kron_equals_sparse_cycle16():
 
 
 def test_omega_limits_of_generator():
-    # omega = 0 -> -i[H, .] only (Liouville-von Neumann, Section 2.3);
+    # omega = 0 -> -i[H, .] only (Liouville-von Neumann, Section 2.4);
     # omega = 1 -> no Hamiltonian part.
     rng = np.random.Generator(np.random.PCG64(3))
     G = _random_digraph(5, 0.6, rng)

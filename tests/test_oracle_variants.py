@@ -82,7 +82,7 @@ def test_source_into_graph_closed_form():
 
 
 def test_dimer_with_source_and_sink_invariants():
-    """The dimer of the augmented-digraph figure (Section 2.4.2): source at
+    """The dimer of the augmented-digraph figure (Section 2.5.1): source at
     rate 2 into v1, sink at rate 3 out of v2; trace one, populations
     non-negative, the sink fills monotonically and ends with everything."""
     G = np.array([[0.0, 1.0], [1.0, 0.0]])
