@@ -317,3 +317,26 @@ def test_single_values_within_first_order_bound(omega, t0):
         err = np.abs(out[k].reshape(-1) - ref).max()
         assert err <= max(expmv.single_values_bound(info["norm1"], t, rho0), 1e-15), (k, err)
         assert err > 1e-12 or t == 0.0   # the rounding is really there
+
+
+def test_fullgrid_fixture_is_the_oracles():
+    """The committed N = 1024 full-grid fixture (tests/golden/make_fullgrid.py)
+    holds the oracle's own values: its first interval recomputed here agrees
+    bit for bit, and every stored point has unit trace."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "make_fullgrid", os.path.join(GOLDEN, "make_fullgrid.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    hdr, pops, samples, trace = mod.load("outdeg1024")
+    wl = workloads.outdeg1024()
+    A = oracle.walk_superop(wl.graph.dense(), wl.omega, wl.h_mode, wl.r_mode,
+                            wl.dephasing, wl.gamma)
+    out, info = expmv.propagate(A, wl.rho0, wl.t0, wl.dt, 1)
+    n = wl.graph.N ** 2
+    assert (hdr["oracle"]["m"], hdr["oracle"]["s"]) == (info["m"], info["s"])
+    for k in (0, 1):
+        assert np.array_equal(np.diag(out[k]).real, pops[k])
+        assert np.array_equal(out[k].reshape(-1)[mod.sample_indices(n, k)], samples[k])
+    assert np.abs(trace - 1).max() < 1e-12
+    assert len(np.unique(mod.sample_indices(n, 3))) == mod.SAMPLES
