@@ -49,7 +49,8 @@ typedef enum {
     QSW_ERR_DEVICE = 4,     /* HIP runtime error (launch, copy, no device) */
     QSW_ERR_NONFINITE = 5,  /* a norm or value was NaN or infinite */
     QSW_ERR_STATE = 6,      /* handle used on another device, or workspace too small */
-    QSW_ERR_SIZE = 7        /* N*N does not fit the 32-bit column index (N > 46340) */
+    QSW_ERR_SIZE = 7,       /* N*N does not fit the 32-bit column index (N > 46340) */
+    QSW_ERR_SCRATCH = 8     /* qsw_propagate_noalloc: the call needs more than its static scratch */
 } qsw_status_t;
 
 /* Build flags (bitwise OR). */
@@ -337,6 +338,25 @@ size_t qsw_propagate_workspace_bytes(qsw_superop_t h, double t0, double dt, int3
 qsw_status_t qsw_propagate(qsw_superop_t h, const void *rho0, double t0, double dt,
                            int32_t n_steps, void *out, void *workspace, size_t ws_bytes,
                            void *hip_stream);
+
+/*
+ * qsw_propagate for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops that forbid allocation, harnesses without
+ * hipMalloc): the same computation, kernels and results, with the workspace
+ * taken from a static device array of QSW_NOALLOC_SCRATCH_BYTES that the
+ * library holds on each device it runs on until the process ends.  It calls
+ * no allocating routine; the caller still passes rho0 and out (as for
+ * qsw_propagate).  QSW_ERR_SCRATCH when qsw_propagate_workspace_bytes(h, t0,
+ * dt, n_steps) exceeds QSW_NOALLOC_SCRATCH_BYTES (e.g. the time-series branch
+ * on a large operator, which stores m powers).  Every call on a device
+ * shares that device's scratch (its contents are those of the last call;
+ * each call sets up what it needs itself): calls that overlap on one device,
+ * from several threads or streams, race and must be serialised by the
+ * caller.
+ */
+#define QSW_NOALLOC_SCRATCH_BYTES (80u << 20)
+qsw_status_t qsw_propagate_noalloc(qsw_superop_t h, const void *rho0, double t0, double dt,
+                                   int32_t n_steps, void *out, void *hip_stream);
 
 /* Statistics of the last qsw_propagate on this handle (waits for it). */
 qsw_status_t qsw_last_stats(qsw_superop_t h, qsw_stats_t *st);

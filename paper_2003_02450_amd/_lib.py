@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(HERE, "libqsw.so")
 QSW_OK = 0
 STATUS_NAMES = {0: "QSW_OK", 1: "QSW_ERR_ARG", 2: "QSW_ERR_GRAPH", 3: "QSW_ERR_OOM",
                 4: "QSW_ERR_DEVICE", 5: "QSW_ERR_NONFINITE", 6: "QSW_ERR_STATE",
-                7: "QSW_ERR_SIZE"}
+                7: "QSW_ERR_SIZE", 8: "QSW_ERR_SCRATCH"}
 
 QSW_H_LAPLACIAN = 0
 QSW_H_ADJACENCY = 1
@@ -19,6 +19,7 @@ QSW_R_COLNORM = 2
 QSW_DEPHASING = 4
 QSW_PREC_DOUBLE = 0
 QSW_PREC_SINGLE = 1
+NOALLOC_SCRATCH_BYTES = 80 << 20   # QSW_NOALLOC_SCRATCH_BYTES
 
 # Every function the header declares, for the export check.
 EXPORTED = ("qsw_superop_build", "qsw_superop_build_ops", "qsw_superop_build_channels",
@@ -29,7 +30,7 @@ EXPORTED = ("qsw_superop_build", "qsw_superop_build_ops", "qsw_superop_build_cha
             "qsw_superop_info", "qsw_superop_set_precision", "qsw_superop_autotune",
             "qsw_superop_set_pacing",
             "qsw_superop_copy_csr", "qsw_propagate_workspace_bytes",
-            "qsw_propagate", "qsw_last_stats", "qsw_apply", "qsw_populations", "qsw_theta",
+            "qsw_propagate", "qsw_propagate_noalloc", "qsw_last_stats", "qsw_apply", "qsw_populations", "qsw_theta",
             "qsw_select_params", "qsw_status_str", "qsw_version", "qsw_walk_bytes",
             "qsw_engine_table_bytes", "qsw_engine_create", "qsw_engine_submit", "qsw_engine_run",
             "qsw_engine_poll", "qsw_engine_stats", "qsw_engine_destroy",
@@ -145,6 +146,8 @@ def load() -> ctypes.CDLL:
     L.qsw_propagate_workspace_bytes.argtypes = [_vp, _dbl, _dbl, _i32]
     L.qsw_propagate.restype = _i32
     L.qsw_propagate.argtypes = [_vp, _vp, _dbl, _dbl, _i32, _vp, _vp, ctypes.c_size_t, _vp]
+    L.qsw_propagate_noalloc.restype = _i32
+    L.qsw_propagate_noalloc.argtypes = [_vp, _vp, _dbl, _dbl, _i32, _vp, _vp]
     L.qsw_last_stats.restype = _i32
     L.qsw_last_stats.argtypes = [_vp, ctypes.POINTER(Stats)]
     L.qsw_apply.restype = _i32

@@ -1461,6 +1461,8 @@ const char *qsw_status_str(qsw_status_t s) {
     case QSW_ERR_NONFINITE: return "non-finite value";
     case QSW_ERR_STATE: return "bad state (device, workspace)";
     case QSW_ERR_SIZE: return "N*N exceeds the 32-bit column index";
+    case QSW_ERR_SCRATCH:
+      return "the propagation needs more than the static scratch of qsw_propagate_noalloc";
   }
   return "unknown status";
 }
@@ -2162,13 +2164,14 @@ size_t qsw_propagate_workspace_bytes(qsw_superop_t h, double t0, double dt, int3
   return P.total;
 }
 
-qsw_status_t qsw_propagate(qsw_superop_t h, const void *rho0, double t0, double dt,
-                           int32_t n_steps, void *out, void *workspace, size_t ws_bytes,
-                           void *hip_stream) {
-  if (!h || !rho0 || !out || !workspace) return QSW_ERR_ARG;
-  Plan P;
-  qsw_status_t st = make_plan(h, t0, dt, n_steps, P);
-  if (st != QSW_OK) return st;
+}  // extern "C"
+
+namespace {
+
+// qsw_propagate on a workspace of ws_bytes (plan P already made).
+qsw_status_t propagate_on(qsw_superop_t h, const Plan &P, const void *rho0, double t0, double dt,
+                          int32_t n_steps, void *out, void *workspace, size_t ws_bytes,
+                          void *hip_stream) {
   if (ws_bytes < P.total || ((uintptr_t)workspace & 255)) return QSW_ERR_STATE;
   const size_t vbytes = (size_t)h->n * sizeof(double2);
   const char *o = (const char *)out;
@@ -2262,6 +2265,63 @@ qsw_status_t qsw_propagate(qsw_superop_t h, const void *rho0, double t0, double 
   h->last_fused = fused;
   h->have_last = true;
   return QSW_OK;
+}
+
+// Scratch of qsw_propagate_noalloc: one copy per device, held by the device
+// until the process ends.  In host code `scratch` names a host-side stand-in,
+// not device memory: its device address comes from hipGetSymbolAddress, once
+// per device (scratch_address), and only that address is passed to kernels.
+static __device__ __align__(256) unsigned char scratch[QSW_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+
+// Device address of this device's scratch, looked up on the first call on
+// the device (which must be current).
+hipError_t scratch_address(int dev, void **out) {
+  static std::mutex mu;
+  static void *addr[kMaxDevices] = {};
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr || ((uintptr_t)ptr & 255)) return hipErrorInvalidSymbol;
+    addr[dev] = ptr;
+  }
+  *out = addr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+qsw_status_t qsw_propagate(qsw_superop_t h, const void *rho0, double t0, double dt,
+                           int32_t n_steps, void *out, void *workspace, size_t ws_bytes,
+                           void *hip_stream) {
+  if (!h || !rho0 || !out || !workspace) return QSW_ERR_ARG;
+  Plan P;
+  qsw_status_t st = make_plan(h, t0, dt, n_steps, P);
+  if (st != QSW_OK) return st;
+  return propagate_on(h, P, rho0, t0, dt, n_steps, out, workspace, ws_bytes, hip_stream);
+}
+
+qsw_status_t qsw_propagate_noalloc(qsw_superop_t h, const void *rho0, double t0, double dt,
+                                   int32_t n_steps, void *out, void *hip_stream) {
+  if (!h || !rho0 || !out) return QSW_ERR_ARG;
+  Plan P;
+  qsw_status_t st = make_plan(h, t0, dt, n_steps, P);
+  if (st != QSW_OK) return st;
+  if (P.total > (size_t)QSW_NOALLOC_SCRATCH_BYTES) return QSW_ERR_SCRATCH;
+  void *ws = nullptr;
+  {
+    DeviceGuard g(h->device);
+    if (!g.ok) return QSW_ERR_DEVICE;
+    HIP_TRY(scratch_address(h->device, &ws));
+  }
+  return propagate_on(h, P, rho0, t0, dt, n_steps, out, ws, QSW_NOALLOC_SCRATCH_BYTES,
+                      hip_stream);
 }
 
 qsw_status_t qsw_last_stats(qsw_superop_t h, qsw_stats_t *st) {
