@@ -63,8 +63,14 @@ enum {
     QSW_DEPHASING = 4       /* also the diagonal L_k = sqrt(|M_jj|)|j><j| that eq. qsw sums over */
 };
 
-/* Precision of the tolerance used for theta_m and the stopping test. */
-enum { QSW_PREC_DOUBLE = 0 /* u = 2^-53 */, QSW_PREC_SINGLE = 1 /* u = 2^-24 */ };
+/* Precision of qsw_propagate (qsw_superop_set_precision) and of the
+ * tolerance used for theta_m and the stopping test. */
+enum {
+    QSW_PREC_DOUBLE = 0,  /* complex128 throughout, u = 2^-53 */
+    QSW_PREC_SINGLE = 1,  /* complex64 operator values, complex128 vectors, u = 2^-24 */
+    QSW_PREC_FP32 = 2     /* complex64 values, vectors and products with two-float
+                             accumulation, u = 2^-24 and Taylor degree at most 20 */
+};
 
 typedef struct {
     int32_t N;           /* graph order */
@@ -108,6 +114,8 @@ typedef struct {
                             complex double / single values and (12, 16) / (8, 8) for
                             phase-split double / single values (D: the diagonal per row) */
     int32_t prec;        /* QSW_PREC_* the call ran with */
+    double trace_dev;    /* QSW_PREC_FP32: largest |Tr rho_k - Tr rho0| of the output points
+                            before their trace renormalisation (0 for the other precisions) */
 } qsw_stats_t;
 
 /* ---------------------------------------------------------------- build */
@@ -260,6 +268,24 @@ qsw_status_t qsw_superop_info(qsw_superop_t h, qsw_info_t *info);
  *     products, sums and norms stay complex128 / double.  rho(t) then carries
  *     a backward error of at most about 2 u ||L||_1 per unit time (value
  *     rounding plus truncation) instead of u = 2^-53.
+ *   QSW_PREC_FP32: the same single-precision values, and the vectors and
+ *     products in single precision too: each Taylor term is a complex64
+ *     vector (the row sums in float, scaled in double and rounded once), the
+ *     accumulator is an unevaluated pair hi + lo of complex64 vectors updated
+ *     by two-sum (about twice the float significand, so adding the terms
+ *     loses nothing beyond their own rounding), and the norms, the stopping
+ *     test and (m, s) stay in double with u = 2^-24.  The Taylor degree is at
+ *     most 20 (p <= 5 in the alpha_p rule): the terms of one scaling step then
+ *     grow to at most about e^theta_20 = 35 times the step's input before they
+ *     cancel, which bounds the single-precision rounding they carry.  Every
+ *     interval is one single-time application (no time-series reuse).  Each
+ *     output point is checked in double: its trace is summed from hi + lo and,
+ *     when it is within 2^-10 relative of Tr rho0, the point (and the state
+ *     carried on) is scaled to Tr rho0, which the exact evolution keeps
+ *     (every Lindblad generator preserves the trace); the largest deviation
+ *     before scaling is qsw_stats_t.trace_dev.  Outputs are complex128
+ *     (hi + lo); out[0] = rho0 exactly when t0 = 0.  Workspace: 48 bytes per
+ *     element of vec(rho) instead of 64.
  *   ||L||_1, the d_p and the parameter choice always come from the complex128
  *   values; qsw_apply and qsw_superop_copy_csr always use them.
  * Returns QSW_ERR_STATE when the handle runs a product engine other than the
@@ -371,7 +397,8 @@ qsw_status_t qsw_last_stats(qsw_superop_t h, qsw_stats_t *st);
  * together in one engine, so small operators share launches and each
  * operator's values are read once per product for all n0 right-hand sides.
  *
- *   op:    built handle, on the engine's device; its precision applies.  It
+ *   op:    built handle, on the engine's device; its precision applies (QSW_PREC_DOUBLE
+ *          or QSW_PREC_SINGLE; QSW_ERR_STATE for QSW_PREC_FP32).  It
  *          must stay alive until the walk has finished.
  *   rho0:  device, n0 consecutive N*N complex128 row-major matrices.
  *   out:   device, (n_steps+1) x n0 x N*N complex128 (point-major), or NULL.
@@ -517,8 +544,9 @@ double qsw_theta(int32_t m, int32_t prec);
  * (d may be NULL: the 1-norm alone is used), n0 right-hand sides, tolerance
  * prec.  The rule is Al-Mohy and Higham's (cited in Section 3.1): the 1-norm
  * choice when ||tL||_1 is small, else the minimum of m * ceil(alpha_p / theta_m)
- * over 2 <= p <= 8, p(p-1)-1 <= m <= 55, alpha_p = t max(d_p, d_{p+1});
- * smallest m on ties; t||L||_1 = 0 gives m = 0, s = 1.
+ * over 2 <= p <= p_max, p(p-1)-1 <= m <= m_max, alpha_p = t max(d_p, d_{p+1});
+ * smallest m on ties; t||L||_1 = 0 gives m = 0, s = 1.  (m_max, p_max) =
+ * (55, 8), or (20, 5) for QSW_PREC_FP32, whose theta_m are the single ones.
  */
 qsw_status_t qsw_select_params(double norm1, const double *d, double t, int32_t n0,
                                int32_t prec, int32_t *m, int32_t *s);

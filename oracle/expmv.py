@@ -23,6 +23,12 @@ without the trace shift.  This module restates them:
   with every stored value of A rounded to complex64, theta_m and the stopping
   test at u = 2^-24 (Al-Mohy and Higham's single-precision choice), the
   1-norm and all vector arithmetic in double.
+* ``propagate_fp32_products`` - the single-precision-products variant: values,
+  terms and their products in complex64 (each term's row sums accumulated in
+  complex64, scaled in double and rounded once), the accumulator exact (in
+  double), the Taylor degree at most 20, u = 2^-24, and each output point
+  scaled back to the input's trace.  It shows what that arithmetic costs in
+  accuracy, so the GPU's single-precision path can be held to it.
 """
 from __future__ import annotations
 
@@ -32,6 +38,10 @@ import numpy as np
 
 from . import native
 from .theta import M_MAX, P_MAX, TOL_DOUBLE, TOL_SINGLE, theta_table
+
+
+M_MAX_FP32 = 20     # Taylor degree cap of the single-precision products
+P_MAX_FP32 = 5      # largest p with p(p-1)-1 <= 20
 
 
 def select_params_norm1(norm_tA: float, thetas=None, m_max: int = M_MAX):
@@ -213,3 +223,92 @@ def single_values_bound(norm1: float, t: float, rho0: np.ndarray) -> float:
     error of at most u ||tA||_1; with a semigroup of 1-norm at most one the
     two give 2 u |t| ||A||_1 ||vec rho0||_1."""
     return 2.0 * TOL_SINGLE * abs(t) * norm1 * float(np.abs(rho0).sum())
+
+
+def _fp32_matvec(A32, x32: np.ndarray, alpha: float) -> np.ndarray:
+    """round32(alpha * (A32 x32)) with the row sums in complex64 (scipy's CSR
+    product accumulates in the operands' type, in storage order)."""
+    y = A32 @ x32
+    assert y.dtype == np.complex64
+    return (alpha * y.astype(np.complex128)).astype(np.complex64)
+
+
+def _fp32_taylor(A32, F: np.ndarray, t: float, m: int, s: int, tol: float):
+    """T_m(tA/s)^s F with complex64 terms and an exact (double) accumulator;
+    the stopping test of the single-time algorithm in double."""
+    products = 0
+    for _ in range(s):
+        c1 = np.max(np.abs(F))
+        b = F.astype(np.complex64)
+        G = F.copy()
+        for j in range(1, m + 1):
+            b = _fp32_matvec(A32, b, t / (s * j))
+            products += 1
+            c2 = np.max(np.abs(b.astype(np.complex128)))
+            G = G + b.astype(np.complex128)
+            if c1 + c2 <= tol * np.max(np.abs(G)):
+                break
+            c1 = c2
+        F = G
+    return F, products
+
+
+def propagate_fp32_products(A: native.CSR, rho0: np.ndarray, t0: float, dt: float,
+                            n_steps: int):
+    """rho(t0 + k dt), k = 0..n_steps, with single-precision values, terms and
+    products (see the module header).  (m, s) from ||tA||_1 of the unrounded
+    A with the single-precision theta table and m <= 20."""
+    import scipy.sparse
+    N = rho0.shape[0]
+    norm1 = A.norm1()
+    thetas = theta_table(TOL_SINGLE)
+    A32 = scipy.sparse.csr_matrix((A.val.astype(np.complex64), A.col, A.row_ptr),
+                                  shape=(A.n, A.n))
+    x = np.ascontiguousarray(rho0, np.complex128).reshape(-1)
+    diag = np.arange(N) * (N + 1)
+    tr0 = float(x[diag].real.sum())
+    products = 0
+
+    def renormalise(v):
+        tr = float(v[diag].real.sum())
+        if tr != 0.0 and tr0 != 0.0 and abs(tr - tr0) <= 2.0 ** -10 * abs(tr0):
+            return v * (tr0 / tr)
+        return v
+
+    if t0 != 0.0:
+        m0, s0 = select_params_norm1(abs(t0) * norm1, thetas, M_MAX_FP32)
+        x, k = _fp32_taylor(A32, x, t0, m0, s0, TOL_SINGLE)
+        x = renormalise(x)
+        products += k
+    out = np.empty((n_steps + 1, N * N), np.complex128)
+    out[0] = x
+    m, s = select_params_norm1(abs(dt) * norm1, thetas, M_MAX_FP32)
+    for k in range(1, n_steps + 1):
+        x, kk = _fp32_taylor(A32, x, dt, m, s, TOL_SINGLE)
+        x = renormalise(x)
+        products += kk
+        out[k] = x
+    return out.reshape(n_steps + 1, N, N), {"m": m, "s": s, "norm1": norm1,
+                                            "products": products}
+
+
+def fp32_products_bound(norm1: float, t: float, steps: int, theta: float, r_max: int,
+                        vec1: float) -> float:
+    """First-order bound on max |rho_fp32(t) - rho(t)| for the single-precision
+    products, u = 2^-24:
+
+        u [ 2 |t| ||A||_1 + (r_max + 2) steps e^theta ] vec1
+
+    * rounding the values perturbs A by at most u ||A||_1 and truncating at u
+      adds a backward error of at most u ||tA||_1 (2 u |t| ||A||_1 together);
+    * one scaling step of degree m sums terms b_j with sum_j ||b_j||_1 <=
+      e^theta ||b_0||_1 (theta = ||A||_1 |t_step| / s); each term's row sums of
+      at most r_max products, its scaling and its rounding add at most
+      (r_max + 2) u of its size; the two-float accumulator adds O(u^2);
+    * the evolution is completely positive and trace preserving, so it does
+      not increase the trace norm of an error, and |X_ab| <= ||X||_tr <=
+      ||vec X||_1: errors made at any step reach rho(t) at most as large;
+    * vec1 bounds ||vec rho||_1 of the states along the way (the caller takes
+      it from the oracle's double-precision solution)."""
+    u = TOL_SINGLE
+    return u * (2.0 * abs(t) * norm1 + (r_max + 2) * steps * math.exp(theta)) * vec1

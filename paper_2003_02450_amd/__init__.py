@@ -41,6 +41,16 @@ def _stream(device):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
+def _prec_code(mode) -> int:
+    if mode is True or mode == "single":
+        return _lib.QSW_PREC_SINGLE
+    if mode is False or mode is None or mode == "double":
+        return _lib.QSW_PREC_DOUBLE
+    if mode == "fp32":
+        return _lib.QSW_PREC_FP32
+    raise ValueError(f"precision {mode!r}")
+
+
 def theta(m: int, single: bool = False) -> float:
     """theta_m of the Taylor backward-error bound (host-only library call)."""
     return float(_lib.load().qsw_theta(int(m), _lib.QSW_PREC_SINGLE if single else
@@ -49,7 +59,8 @@ def theta(m: int, single: bool = False) -> float:
 
 def select_params(norm1: float, d=None, t: float = 1.0, n0: int = 1, single: bool = False):
     """(m, s) for exp(t L) from ||L||_1 and d[p] = ||L^p||_1^(1/p), p = 2..9
-    (host-only library call; ``d`` indexable by p, or None)."""
+    (host-only library call; ``d`` indexable by p, or None).  ``single``: a
+    precision as for Superop.set_precision (True / "single" / "fp32")."""
     L = _lib.load()
     darr = None
     if d is not None:
@@ -58,7 +69,7 @@ def select_params(norm1: float, d=None, t: float = 1.0, n0: int = 1, single: boo
             darr[p] = float(d[p])
     m, s = ctypes.c_int32(), ctypes.c_int32()
     st = L.qsw_select_params(float(norm1), None if darr is None else _ptr(darr), float(t),
-                             int(n0), _lib.QSW_PREC_SINGLE if single else _lib.QSW_PREC_DOUBLE,
+                             int(n0), _prec_code(single),
                              ctypes.byref(m), ctypes.byref(s))
     _lib.check(st, "qsw_select_params")
     return m.value, s.value
@@ -274,14 +285,17 @@ class Superop:
             st = _lib.load().qsw_superop_set_pacing(self._h, int(lookahead))
         _lib.check(st, "qsw_superop_set_pacing")
 
-    def set_precision(self, single: bool):
-        """single=True: later propagate calls read single-precision
-        superoperator values (each real and imaginary part rounded to nearest)
-        and use the 2^-24 tolerance; vectors and sums stay complex128."""
+    def set_precision(self, mode):
+        """Precision of later propagate calls: False / "double" (complex128);
+        True / "single": single-precision superoperator values (each real and
+        imaginary part rounded to nearest) with the 2^-24 tolerance, vectors
+        and sums complex128; "fp32": single-precision values, vectors and
+        products with two-float (hi + lo) accumulation of the Taylor terms,
+        norms and parameters in double, and a trace check per output point."""
         torch = _torch()
+        prec = _prec_code(mode)
         with torch.cuda.device(self.device):
-            st = _lib.load().qsw_superop_set_precision(
-                self._h, _lib.QSW_PREC_SINGLE if single else _lib.QSW_PREC_DOUBLE)
+            st = _lib.load().qsw_superop_set_precision(self._h, prec)
         _lib.check(st, "qsw_superop_set_precision")
 
     def autotune(self) -> dict:
@@ -348,8 +362,8 @@ class Superop:
             _lib.check(st, "qsw_last_stats")
         return {"branch": s.branch, "m": s.m, "s": s.s, "m0": s.m0, "s0": s.s0,
                 "launched": s.launched, "products": s.products, "nonfinite": bool(s.nonfinite),
-                "ms": s.ms, "bytes": s.bytes,
-                "prec": "single" if s.prec == _lib.QSW_PREC_SINGLE else "double"}
+                "ms": s.ms, "bytes": s.bytes, "prec": _lib.PREC_NAMES.get(s.prec, s.prec),
+                "trace_dev": s.trace_dev}
 
     def apply(self, x, out=None):
         """y = L x for a length-n complex128 device vector."""

@@ -19,6 +19,8 @@ QSW_R_COLNORM = 2
 QSW_DEPHASING = 4
 QSW_PREC_DOUBLE = 0
 QSW_PREC_SINGLE = 1
+QSW_PREC_FP32 = 2
+PREC_NAMES = {0: "double", 1: "single", 2: "fp32"}
 NOALLOC_SCRATCH_BYTES = 80 << 20   # QSW_NOALLOC_SCRATCH_BYTES
 
 # Every function the header declares, for the export check.
@@ -59,7 +61,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("branch", ctypes.c_int32), ("m", ctypes.c_int32), ("s", ctypes.c_int32),
                 ("m0", ctypes.c_int32), ("s0", ctypes.c_int32), ("launched", ctypes.c_int64),
                 ("products", ctypes.c_int64), ("nonfinite", ctypes.c_int32),
-                ("ms", ctypes.c_double), ("bytes", ctypes.c_double), ("prec", ctypes.c_int32)]
+                ("ms", ctypes.c_double), ("bytes", ctypes.c_double), ("prec", ctypes.c_int32),
+                ("trace_dev", ctypes.c_double)]
 
 
 class Tuning(ctypes.Structure):

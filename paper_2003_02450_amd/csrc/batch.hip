@@ -82,6 +82,9 @@ struct WalkPlan {
 
 qsw_status_t plan_walk(const qsw_walk_t *w, int32_t rhs, WalkPlan &W) {
   if (!w || !w->op || !w->rho0 || w->n0 < 1 || w->n0 > rhs || w->n_steps < 0) return QSW_ERR_ARG;
+  // the engine's products are complex128 (single-precision products run in
+  // qsw_propagate only)
+  if (w->op->prec == QSW_PREC_FP32) return QSW_ERR_STATE;
   qsw_status_t st = make_plan(w->op, w->t0, w->dt, w->n_steps, W.P);
   if (st != QSW_OK) return st;
   W.vec = align256((size_t)w->op->n * rhs * sizeof(double2));

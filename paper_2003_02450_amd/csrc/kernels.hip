@@ -145,6 +145,13 @@ __device__ __forceinline__ float2 gld<float2>(const float2 *p) {
   const fvec2 v = *(const QSW_GLOBAL fvec2 *)p;
   return make_float2(v.x, v.y);
 }
+template <>
+__device__ __forceinline__ void gst<float2>(float2 *p, const float2 &v) {
+  fvec2 w;
+  w.x = v.x;
+  w.y = v.y;
+  *(QSW_GLOBAL fvec2 *)p = w;
+}
 
 // A complex64 entry widened to complex128 (exact).
 __device__ __forceinline__ double2 load_entry(const float2 *p) {
@@ -160,6 +167,46 @@ __device__ __forceinline__ void cmac(double &ax, double &ay, double2 v, double2 
 }
 __device__ __forceinline__ double2 cmul(double2 v, double2 x) {
   return make_double2(fma(v.x, x.x, -v.y * x.y), fma(v.x, x.y, v.y * x.x));
+}
+
+// Single-precision products (complex64 vectors, single-precision values and
+// sums): the same multiply-adds in float.
+__device__ __forceinline__ void cmac(float &ax, float &ay, float2 v, float2 x) {
+  ax = fmaf(v.x, x.x, ax);
+  ax = fmaf(-v.y, x.y, ax);
+  ay = fmaf(v.x, x.y, ay);
+  ay = fmaf(v.y, x.x, ay);
+}
+__device__ __forceinline__ float rfma(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double rfma(double a, double b, double c) { return fma(a, b, c); }
+
+// Vector element and arithmetic types of a product: complex128 / double, or
+// complex64 / float for the single-precision products (X32).
+template <bool X32>
+using VecT = std::conditional_t<X32, float2, double2>;
+template <bool X32>
+using RealT = std::conditional_t<X32, float, double>;
+
+template <class V>
+__device__ __forceinline__ V cplx(double re, double im);
+template <>
+__device__ __forceinline__ double2 cplx<double2>(double re, double im) {
+  return make_double2(re, im);
+}
+template <>
+__device__ __forceinline__ float2 cplx<float2>(double re, double im) {
+  return make_float2((float)re, (float)im);
+}
+__device__ __forceinline__ float2 cplxf(float re, float im) { return make_float2(re, im); }
+__device__ __forceinline__ double2 cplxf(double re, double im) { return make_double2(re, im); }
+
+// The gathered vector of a product.
+template <bool X32>
+__device__ __forceinline__ const VecT<X32> *xbase(const SpmvArgs &a) {
+  if constexpr (X32)
+    return a.x32;
+  else
+    return a.x;
 }
 
 // --------------------------------------------------------------------------
@@ -381,19 +428,22 @@ __device__ __forceinline__ int64_t entry_offset(int raw) {
 __device__ __forceinline__ double2 masked(bool keep, double2 v) {
   return make_double2(keep ? v.x : 0.0, keep ? v.y : 0.0);
 }
+__device__ __forceinline__ float2 masked(bool keep, float2 v) {
+  return make_float2(keep ? v.x : 0.0f, keep ? v.y : 0.0f);
+}
 
 // Complex value of an entry: stored (complex layouts) or rebuilt from the
 // phase-split coefficient, with scalar selects only.
-template <bool SPLIT>
-__device__ __forceinline__ double2 decode(int raw, double cf, double2 v, double2 dg) {
+template <bool SPLIT, class V, class R>
+__device__ __forceinline__ V decode(int raw, R cf, V v, V dg) {
   if constexpr (!SPLIT) {
     return v;
   } else {
     const uint32_t r = (uint32_t)raw;
     const bool im = (r & kImagBit) != 0u, diag = (r & kDiagBit) != 0u;
-    const double re = diag ? dg.x : (im ? 0.0 : cf);
-    const double ii = diag ? dg.y : (im ? cf : 0.0);
-    return make_double2(re, ii);
+    const R re = diag ? dg.x : (im ? R(0) : cf);
+    const R ii = diag ? dg.y : (im ? cf : R(0));
+    return cplxf(re, ii);
   }
 }
 
@@ -490,10 +540,15 @@ __device__ __forceinline__ WaveHead wave_head(const SpmvArgs &a, int64_t k) {
   return wave_head_use(a, k, wave_head_load<F32, SPLIT>(a, k));
 }
 
-template <int NRHS, bool F32, bool STAGE, class Epi, bool SOA = false, bool SPLIT = false>
+template <int NRHS, bool F32, bool STAGE, class Epi, bool SOA = false, bool SPLIT = false,
+          bool X32 = false>
 __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const WaveHead &hd,
-                                             Epi &epi, const double2 *xs, int64_t base,
+                                             Epi &epi, const VecT<X32> *xs, int64_t base,
                                              bool staged = true, int64_t span = 0) {
+  // X32: complex64 x, single-precision values and sums (F32 layouts only)
+  static_assert(!X32 || (F32 && NRHS == 1 && !SOA), "single-precision products");
+  using V = VecT<X32>;
+  using R = RealT<X32>;
   // one right-hand side: xs holds x[base .. base + span) (span = N by default)
   const uint64_t lim = (uint64_t)(span ? span : a.N);
   constexpr int kWaveUnroll = wave_unroll<NRHS>();
@@ -507,10 +562,10 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
   const int orow = hd.orow;
   typename Epi::Pre pre{};
   if (lane < nr) pre = epi.pre(r0 + orow);
-  const double2 dg = hd.dg;
-  double acc[2 * NRHS];
+  const V dg = cplx<V>(hd.dg.x, hd.dg.y);  // exact: single values come from floats
+  R acc[2 * NRHS];
 #pragma unroll
-  for (int q = 0; q < 2 * NRHS; ++q) acc[q] = 0.0;
+  for (int q = 0; q < 2 * NRHS; ++q) acc[q] = R(0);
   // Shared leading positions: one entry for the whole block (the same for
   // every lane's row), gathering x at row + off from global memory.  They come
   // first in every row, as in the per-row order, and the zero padding adds
@@ -531,7 +586,7 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
       // groups of 16 measured no faster)
       auto sgroup = [&](auto width, int p) {
         constexpr int S = decltype(width)::value;
-        double2 v[S];
+        V v[S];
         int64_t c[S];
 #pragma unroll
         for (int u = 0; u < S; ++u) {
@@ -541,19 +596,19 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
           const uint32_t hi =
               (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(mine_coef >> 32), p + u);
           const double e = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-          const double cf = F32 ? (double)(float)e : e;
+          const R cf = F32 ? (R)(float)e : (R)e;
           const bool im = (flags & kImagBit) != 0u;
           // wave-uniform (lanes past the block's rows gather at row r0, in
           // bounds, and their sums are never written)
-          v[u] = make_double2(im ? 0.0 : cf, im ? cf : 0.0);
+          v[u] = cplxf(im ? R(0) : cf, im ? cf : R(0));
           c[u] = row + off;
         }
-        double2 xg[S][NRHS];
+        V xg[S][NRHS];
 #pragma unroll
         for (int u = 0; u < S; ++u)
 #pragma unroll
           for (int r = 0; r < NRHS; ++r)
-            xg[u][r] = gld(a.x + (SOA ? (int64_t)r * a.n + c[u] : c[u] * NRHS + r));
+            xg[u][r] = gld(xbase<X32>(a) + (SOA ? (int64_t)r * a.n + c[u] : c[u] * NRHS + r));
 #pragma unroll
         for (int u = 0; u < S; ++u)
 #pragma unroll
@@ -589,16 +644,22 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
     int c[kWaveUnroll];
 #pragma unroll
     for (int u = 0; u < kWaveUnroll; ++u) c[u] = load_entry(cb + bcur[u]);
-    double2 v[kWaveUnroll];
-    double cf[kWaveUnroll];
+    V v[kWaveUnroll];
+    R cf[kWaveUnroll];
 #pragma unroll
     for (int u = 0; u < kWaveUnroll; ++u) {
       if constexpr (SPLIT) {
-        cf[u] = F32 ? load_entry(a.wcoef32 + e0 + bcur[u]) : load_entry(a.wcoef + e0 + bcur[u]);
+        if constexpr (X32)
+          cf[u] = gld(a.wcoef32 + e0 + bcur[u]);
+        else
+          cf[u] = F32 ? load_entry(a.wcoef32 + e0 + bcur[u]) : load_entry(a.wcoef + e0 + bcur[u]);
         v[u] = dg;  // unused
       } else {
-        v[u] = F32 ? load_entry(a.wval32 + e0 + bcur[u]) : load_entry(a.wval + e0 + bcur[u]);
-        cf[u] = 0.0;  // unused
+        if constexpr (X32)
+          v[u] = gld(a.wval32 + e0 + bcur[u]);
+        else
+          v[u] = F32 ? load_entry(a.wval32 + e0 + bcur[u]) : load_entry(a.wval + e0 + bcur[u]);
+        cf[u] = R(0);  // unused
       }
     }
     // a lane past its row's end read another row's entry: its offset is
@@ -610,22 +671,22 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
     if constexpr (MODE == kGatherAny) {
       // no staging: global gathers first (they need the columns only), the
       // values decoded where they are used
-      double2 xg[kWaveUnroll][NRHS];
+      V xg[kWaveUnroll][NRHS];
 #pragma unroll
       for (int u = 0; u < kWaveUnroll; ++u)
 #pragma unroll
         for (int r = 0; r < NRHS; ++r)
-          xg[u][r] = gld(a.x + (SOA ? (int64_t)r * a.n + col[u] : col[u] * NRHS + r));
+          xg[u][r] = gld(xbase<X32>(a) + (SOA ? (int64_t)r * a.n + col[u] : col[u] * NRHS + r));
 #pragma unroll
       for (int u = 0; u < kWaveUnroll; ++u) {
-        const double2 vz = masked(ok[u], decode<SPLIT>(c[u], cf[u], v[u], dg));
+        const V vz = masked(ok[u], decode<SPLIT>(c[u], cf[u], v[u], dg));
 #pragma unroll
         for (int r = 0; r < NRHS; ++r) cmac(acc[2 * r], acc[2 * r + 1], vz, xg[u][r]);
       }
     } else {
       // staged: xs holds the staged rho-row of every column (xs[r N' + o],
       // N' = lim for one column); column r of x at r n + col (SOA) or col
-      double2 xv[kWaveUnroll][NRHS];
+      V xv[kWaveUnroll][NRHS];
 #pragma unroll
       for (int u = 0; u < kWaveUnroll; ++u) {
         const uint64_t o = (uint64_t)((int64_t)col[u] - base);
@@ -634,8 +695,8 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
         for (int r = 0; r < NRHS; ++r) {
           // column r: SOA at r n + col (staged at r lim + o), else
           // interleaved at col NRHS + r (staged at o NRHS + r)
-          const double2 *xgp = SOA ? a.x + (int64_t)r * a.n + col[u] : a.x + col[u] * NRHS + r;
-          const double2 *xlp = SOA ? xs + (uint64_t)r * lim : xs + r;
+          const V *xgp = SOA ? xbase<X32>(a) + (int64_t)r * a.n + col[u] : xbase<X32>(a) + col[u] * NRHS + r;
+          const V *xlp = SOA ? xs + (uint64_t)r * lim : xs + r;
           constexpr uint64_t ls = SOA ? 1 : NRHS;  // LDS stride between rho-row elements
           if constexpr (MODE == kGatherGlobal)
             xv[u][r] = gld(xgp);
@@ -649,7 +710,7 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
       }
 #pragma unroll
       for (int u = 0; u < kWaveUnroll; ++u) {
-        const double2 vz = masked(ok[u], decode<SPLIT>(c[u], cf[u], v[u], dg));
+        const V vz = masked(ok[u], decode<SPLIT>(c[u], cf[u], v[u], dg));
 #pragma unroll
         for (int r = 0; r < NRHS; ++r) cmac(acc[2 * r], acc[2 * r + 1], vz, xv[u][r]);
       }
@@ -688,29 +749,33 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
           ps += cnt;
         }
         int c[kWaveUnroll];
-        double cf[kWaveUnroll];
+        R cf[kWaveUnroll];
 #pragma unroll
         for (int u = 0; u < kWaveUnroll; ++u) c[u] = load_entry(cb + bcur[u]);
 #pragma unroll
-        for (int u = 0; u < kWaveUnroll; ++u)
-          cf[u] = F32 ? load_entry(a.wcoef32 + e0 + bcur[u]) : load_entry(a.wcoef + e0 + bcur[u]);
-        double2 xv[kWaveUnroll];
+        for (int u = 0; u < kWaveUnroll; ++u) {
+          if constexpr (X32)
+            cf[u] = gld(a.wcoef32 + e0 + bcur[u]);
+          else
+            cf[u] = F32 ? load_entry(a.wcoef32 + e0 + bcur[u]) : load_entry(a.wcoef + e0 + bcur[u]);
+        }
+        V xv[kWaveUnroll];
 #pragma unroll
         for (int u = 0; u < kWaveUnroll; ++u) {
           const int off = ok[u] ? (int)((uint32_t)c[u] << 2) >> 2 : 0;
           if constexpr (MODE == kGatherLds)
             xv[u] = xs[min((uint32_t)(lrel + off), lmax)];
           else
-            xv[u] = gld(a.x + (lane_row + off));
+            xv[u] = gld(xbase<X32>(a) + (lane_row + off));
         }
 #pragma unroll
         for (int u = 0; u < kWaveUnroll; ++u) {
           const bool im = ((uint32_t)c[u] & kImagBit) != 0u;
-          const double cm = ok[u] ? cf[u] : 0.0;
-          const double sx = im ? xv[u].y : xv[u].x;
-          const double sy = im ? xv[u].x : xv[u].y;
-          acc[0] = fma(im ? -cm : cm, sx, acc[0]);
-          acc[1] = fma(cm, sy, acc[1]);
+          const R cm = ok[u] ? cf[u] : R(0);
+          const R sx = im ? xv[u].y : xv[u].x;
+          const R sy = im ? xv[u].x : xv[u].y;
+          acc[0] = rfma(im ? -cm : cm, sx, acc[0]);
+          acc[1] = rfma(cm, sy, acc[1]);
         }
       };
       int p0 = 0;
@@ -719,7 +784,7 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
         // position G: every running row's diagonal (stored in the stream as
         // a marker, its value in dg)
         const int cnt = __popcll(__ballot(len > G));
-        const double2 vz = masked(lane < cnt, dg);
+        const V vz = masked(lane < cnt, dg);
         cmac(acc[0], acc[1], vz, xs[lrel]);
         ps += cnt;
       }
@@ -779,8 +844,9 @@ __device__ __forceinline__ void wave_block(const SpmvArgs &a, int64_t k, Epi &ep
 // loads issued before it).  The guards are wave-uniform.
 constexpr int kStageMaxPerThread = (int)((kStageMaxBytes / sizeof(double2) + kBlock - 1) / kBlock);
 
-__device__ __forceinline__ void stage_copy(double2 *xs, const double2 *src, int cnt) {
-  double2 v[kStageMaxPerThread];
+template <class T>
+__device__ __forceinline__ void stage_copy(T *xs, const T *src, int cnt) {
+  T v[kStageMaxPerThread];
   const int t = threadIdx.x;
 #pragma unroll
   for (int u = 0; u < kStageMaxPerThread; ++u)
@@ -790,11 +856,12 @@ __device__ __forceinline__ void stage_copy(double2 *xs, const double2 *src, int 
     if (u * kBlock < cnt && t + u * kBlock < cnt) xs[t + u * kBlock] = v[u];
 }
 
-template <int NRHS, bool F32, bool STAGE, bool SPLIT, class Epi>
+template <int NRHS, bool F32, bool STAGE, bool SPLIT, class Epi, bool X32 = false>
 __device__ __forceinline__ void wave_engine(const SpmvArgs &a, Epi &epi) {
   constexpr int WPB = kBlock / 64;  // wavefronts per workgroup
   const int64_t nw = (int64_t)gridDim.x * WPB;
-  extern __shared__ double2 xs[];
+  extern __shared__ double2 xs_lds[];
+  VecT<X32> *xs = reinterpret_cast<VecT<X32> *>(xs_lds);
   for (int64_t kb = (int64_t)blockIdx.x * WPB; kb < a.nwb; kb += nw) {
     const int64_t k = kb + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     // the block header's loads are issued before the staging (a wave past
@@ -806,12 +873,12 @@ __device__ __forceinline__ void wave_engine(const SpmvArgs &a, Epi &epi) {
       // rho-row of the workgroup's first row, all NRHS interleaved columns
       base = (kb * kWaveRows) / a.N * a.N;
       if (kb != (int64_t)blockIdx.x * WPB) __syncthreads();  // the previous blocks are done with xs
-      stage_copy(xs, a.x + base * NRHS, a.N * NRHS);
+      stage_copy(xs, xbase<X32>(a) + base * NRHS, a.N * NRHS);
       __syncthreads();
     }
     if (k < a.nwb)
-      wave_block_h<NRHS, F32, STAGE, Epi, false, SPLIT>(a, k, wave_head_use(a, k, raw), epi, xs,
-                                                        base);
+      wave_block_h<NRHS, F32, STAGE, Epi, false, SPLIT, X32>(a, k, wave_head_use(a, k, raw), epi,
+                                                             xs, base);
   }
 }
 
@@ -1543,6 +1610,146 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
   unsigned long long v[3] = {epi.mb, epi.mf, epi.mb0};
   unsigned long long *const dst[3] = {&S->b[a.j], &S->f[a.j], a.j == 1 ? &S->b0 : nullptr};
   block_umax_to<3>(v, dst, &a.st->nonfinite);
+}
+
+// ---------------------------------------------------------------------------
+// Single-precision products (QSW_PREC_FP32).  The term is a complex64
+// vector; the accumulator F is a pair of complex64 vectors whose unevaluated
+// sum hi + lo carries about twice the float significand, so that adding m
+// terms to it loses nothing beyond the terms' own rounding.  Norms, the
+// stopping test and the parameters stay in double.
+// ---------------------------------------------------------------------------
+
+// s + e = a + b exactly (Knuth's two-sum; the build keeps every operation
+// as written: no contraction, no reassociation).
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
+  s = a + b;
+  const float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// (hi, lo) + y for one component: the two-sum of hi and y, its error folded
+// into lo, then renormalised so that |lo| is at most half an ulp of hi.
+__device__ __forceinline__ void df_add(float hi, float lo, float y, float &h2, float &l2) {
+  float s, e;
+  two_sum(hi, y, s, e);
+  const float t = lo + e;
+  h2 = s + t;
+  l2 = t - (h2 - s);
+}
+
+__device__ __forceinline__ double cabs_df(float2 hi, float2 lo) {
+  return cabs2(make_double2((double)hi.x + (double)lo.x, (double)hi.y + (double)lo.y));
+}
+
+struct Taylor32Epi {  // y = alpha A x (complex64) ; F_out = F_in + y (two-float) ; norms
+  const SpmvArgs &a;
+  unsigned long long mb = 0, mf = 0, mb0 = 0;
+  struct Pre {
+    float2 hi, lo;
+  };
+  __device__ explicit Taylor32Epi(const SpmvArgs &args) : a(args) {}
+  __device__ __forceinline__ Pre pre(int64_t row) const {
+    return Pre{gld(a.fin_hi + row), gld(a.fin_lo + row)};
+  }
+  __device__ __forceinline__ void operator()(int64_t row, const float *acc, Pre f) {
+    // the row sum scaled in double and rounded once
+    const float2 y = make_float2((float)(a.alpha * (double)acc[0]),
+                                 (float)(a.alpha * (double)acc[1]));
+    gst(a.y32 + row, y);
+    if (a.j == 1) mb0 = umax(mb0, abs_bits(cabs_df(f.hi, f.lo)));
+    float2 h, l;
+    df_add(f.hi.x, f.lo.x, y.x, h.x, l.x);
+    df_add(f.hi.y, f.lo.y, y.y, h.y, l.y);
+    gst(a.fout_hi + row, h);
+    gst(a.fout_lo + row, l);
+    mb = umax(mb, abs_bits(cabs2(make_double2((double)y.x, (double)y.y))));
+    mf = umax(mf, abs_bits(cabs_df(h, l)));
+  }
+};
+
+// Engines of the single-precision products: the wave layouts' traversal 0
+// (plain) or 1 (rho-row staged; the XCD-banded traversal runs staged), with
+// complex (1) or phase-split (11) single-precision values.
+template <int ENGINE, class Epi>
+__device__ __forceinline__ void run_engine32(const SpmvArgs &a, Epi &epi) {
+  constexpr int trav = ENGINE / 100, fmt = ENGINE % 100;
+  static_assert(trav <= 1 && (fmt == 1 || fmt == 11), "single-precision engine");
+  wave_engine<1, true, trav == 1, fmt == 11, Epi, true>(a, epi);
+}
+
+template <int ENGINE>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void term32_kernel(SpmvArgs a) {
+  if (taylor_prologue(a)) return;
+  Taylor32Epi epi(a);
+  run_engine32<ENGINE>(a, epi);
+  StepSlots *S = &a.st->step[a.par];
+  unsigned long long v[3] = {epi.mb, epi.mf, epi.mb0};
+  unsigned long long *const dst[3] = {&S->b[a.j], &S->f[a.j], a.j == 1 ? &S->b0 : nullptr};
+  block_umax_to<3>(v, dst, &a.st->nonfinite);
+}
+
+__global__ __launch_bounds__(kBlock) void split_c64_kernel(const double2 *v, float2 *hi,
+                                                           float2 *lo, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock) {
+    const double2 z = gld(v + i);
+    const float2 h = make_float2((float)z.x, (float)z.y);
+    gst(hi + i, h);
+    gst(lo + i, make_float2((float)(z.x - (double)h.x), (float)(z.y - (double)h.y)));
+  }
+}
+
+// One workgroup: the diagonal's sum in double, in a fixed order (strided
+// partial sums, then a tree over the workgroup).
+__global__ __launch_bounds__(kBlock) void trace32_kernel(DeviceState *st, const float2 *hi,
+                                                         const float2 *lo, int32_t N,
+                                                         int reference) {
+  __shared__ double part[kBlock];
+  double acc = 0.0;
+  for (int64_t a = threadIdx.x; a < N; a += kBlock) {
+    const int64_t i = a * (N + 1);
+    acc += (double)gld(hi + i).x + (double)gld(lo + i).x;
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double tr = part[0];
+    if (!isfinite(tr)) st->nonfinite = 1;
+    if (reference) {
+      st->tr0 = tr;
+      st->scale = 1.0;
+    } else {
+      const double tr0 = st->tr0;
+      // scaled only when the deviation is small: a traceless or nearly
+      // traceless input keeps its values
+      const bool ok = isfinite(tr) && isfinite(tr0) && tr != 0.0 && tr0 != 0.0 &&
+                      fabs(tr - tr0) <= 0x1p-10 * fabs(tr0);
+      st->scale = ok ? tr0 / tr : 1.0;
+      const unsigned long long d = abs_bits(tr - tr0);
+      if (d > st->trace_dev) st->trace_dev = d;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void emit32_kernel(const DeviceState *st, float2 *hi,
+                                                        float2 *lo, double2 *out, int64_t n) {
+  const double f = st->scale;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock) {
+    const float2 h = gld(hi + i), l = gld(lo + i);
+    const double2 z = make_double2(((double)h.x + (double)l.x) * f, ((double)h.y + (double)l.y) * f);
+    gst(out + i, z);
+    if (f != 1.0) {
+      const float2 h2 = make_float2((float)z.x, (float)z.y);
+      gst(hi + i, h2);
+      gst(lo + i, make_float2((float)(z.x - (double)h2.x), (float)(z.y - (double)h2.y)));
+    }
+  }
 }
 
 template <int ENGINE>
@@ -2460,6 +2667,41 @@ hipError_t launch_taylor_term(const SpmvArgs &a, int engine, int grid, hipStream
   hipLaunchKernelGGL(term_kernel<E>, dim3(grid), dim3(kBlock), stage_bytes(E, a), s, a)
   QSW_ENGINE_SWITCH(engine, QSW_L)
 #undef QSW_L
+  return hipGetLastError();
+}
+
+hipError_t launch_taylor_term32(const SpmvArgs &a, int engine, int grid, hipStream_t s) {
+  const size_t lds = (size_t)a.N * sizeof(float2);
+  switch (engine) {
+    case 1: hipLaunchKernelGGL(term32_kernel<1>, dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 11: hipLaunchKernelGGL(term32_kernel<11>, dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 101: hipLaunchKernelGGL(term32_kernel<101>, dim3(grid), dim3(kBlock), lds, s, a); break;
+    case 111: hipLaunchKernelGGL(term32_kernel<111>, dim3(grid), dim3(kBlock), lds, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_split_c64(const double2 *v, float2 *hi, float2 *lo, int64_t n, hipStream_t s) {
+  int grid = blocks_for(n);
+  if (grid > 4096) grid = 4096;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(split_c64_kernel, dim3(grid), dim3(kBlock), 0, s, v, hi, lo, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_trace32(DeviceState *st, const float2 *hi, const float2 *lo, int32_t N,
+                          int reference, hipStream_t s) {
+  hipLaunchKernelGGL(trace32_kernel, dim3(1), dim3(kBlock), 0, s, st, hi, lo, N, reference);
+  return hipGetLastError();
+}
+
+hipError_t launch_emit32(const DeviceState *st, float2 *hi, float2 *lo, double2 *out, int64_t n,
+                         hipStream_t s) {
+  int grid = blocks_for(n);
+  if (grid > 4096) grid = 4096;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(emit32_kernel, dim3(grid), dim3(kBlock), 0, s, st, hi, lo, out, n);
   return hipGetLastError();
 }
 

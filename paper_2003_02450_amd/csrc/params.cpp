@@ -13,6 +13,11 @@ namespace {
 
 constexpr int kMMax = 55;  // largest Taylor degree
 constexpr int kPMax = 8;   // largest p in alpha_p = max(d_p, d_{p+1})
+// Single-precision products: the degree is capped so that the terms of a
+// scaling step stay within e^theta_20 (about 35) of its input; p_max is then
+// the largest p with p(p-1)-1 <= 20.
+constexpr int kMMax32 = 20;
+constexpr int kPMax32 = 5;
 constexpr int kEll = 2;    // columns of the block 1-norm estimator
 
 // ---------------------------------------------------------------- theta_m
@@ -77,7 +82,7 @@ void compute_theta(quad tol, ThetaTable &T) {
 const ThetaTable &table(int prec) {
   static ThetaTable tables[2];
   static std::once_flag once[2];
-  const int i = prec == QSW_PREC_SINGLE ? 1 : 0;
+  const int i = prec == QSW_PREC_DOUBLE ? 0 : 1;
   std::call_once(once[i], [i] {
     quad tol = 1;
     for (int k = 0; k < (i == 1 ? 24 : 53); ++k) tol /= 2;
@@ -90,7 +95,11 @@ const ThetaTable &table(int prec) {
 
 double theta_of(int m, int prec) { return table(prec).th[m]; }
 
-double tol_of(int prec) { return prec == QSW_PREC_SINGLE ? std::ldexp(1.0, -24) : std::ldexp(1.0, -53); }
+double tol_of(int prec) {
+  return prec == QSW_PREC_DOUBLE ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
+}
+
+int mmax_of(int prec) { return prec == QSW_PREC_FP32 ? kMMax32 : kMMax; }
 
 // Al-Mohy and Higham's choice (cited in Section 3.1): when ||tL||_1 is at
 // most 2 ell p_max (p_max + 3) theta_{m_max} / (n0 m_max) the 1-norm alone
@@ -102,6 +111,7 @@ qsw_status_t select_params_impl(double norm1, const double *d, double t, int n0,
                                 int *m_out, int *s_out) {
   if (!m_out || !s_out || n0 < 1 || !(norm1 >= 0.0) || !std::isfinite(t)) return QSW_ERR_ARG;
   const ThetaTable &T = table(prec);
+  const int mmax = mmax_of(prec), pmax = prec == QSW_PREC_FP32 ? kPMax32 : kPMax;
   t = std::fabs(t);
   const double x = t * norm1;
   if (!std::isfinite(x)) return QSW_ERR_NONFINITE;
@@ -111,11 +121,11 @@ qsw_status_t select_params_impl(double norm1, const double *d, double t, int n0,
     return QSW_OK;
   }
   const double bound =
-      2.0 * kEll * kPMax * (kPMax + 3) * T.th[kMMax] / ((double)n0 * (double)kMMax);
+      2.0 * kEll * pmax * (pmax + 3) * T.th[mmax] / ((double)n0 * (double)mmax);
   int best_m = -1;
   double best_cost = 0.0, best_s = 0.0;
   if (d == nullptr || x <= bound) {
-    for (int m = 1; m <= kMMax; ++m) {
+    for (int m = 1; m <= mmax; ++m) {
       const double sm = std::ceil(x / T.th[m]);
       const double cost = m * sm;
       if (best_m < 0 || cost < best_cost) {
@@ -125,11 +135,11 @@ qsw_status_t select_params_impl(double norm1, const double *d, double t, int n0,
       }
     }
   } else {
-    for (int p = 2; p <= kPMax + 1; ++p)
+    for (int p = 2; p <= pmax + 1; ++p)
       if (!(d[p] >= 0.0) || !std::isfinite(d[p])) return QSW_ERR_ARG;
-    for (int m = 1; m <= kMMax; ++m) {
+    for (int m = 1; m <= mmax; ++m) {
       double sm = -1.0;
-      for (int p = 2; p <= kPMax; ++p) {
+      for (int p = 2; p <= pmax; ++p) {
         if (p * (p - 1) - 1 > m) break;
         const double alpha = t * std::max(d[p], d[p + 1]);
         const double sp = std::ceil(alpha / T.th[m]);
@@ -156,13 +166,16 @@ qsw_status_t select_params_impl(double norm1, const double *d, double t, int n0,
 extern "C" {
 
 double qsw_theta(int32_t m, int32_t prec) {
-  if (m < 1 || m > qsw::kMMax || (prec != QSW_PREC_DOUBLE && prec != QSW_PREC_SINGLE)) return -1.0;
+  if (m < 1 || m > qsw::kMMax ||
+      (prec != QSW_PREC_DOUBLE && prec != QSW_PREC_SINGLE && prec != QSW_PREC_FP32))
+    return -1.0;
   return qsw::theta_of(m, prec);
 }
 
 qsw_status_t qsw_select_params(double norm1, const double *d, double t, int32_t n0, int32_t prec,
                                int32_t *m, int32_t *s) {
-  if (prec != QSW_PREC_DOUBLE && prec != QSW_PREC_SINGLE) return QSW_ERR_ARG;
+  if (prec != QSW_PREC_DOUBLE && prec != QSW_PREC_SINGLE && prec != QSW_PREC_FP32)
+    return QSW_ERR_ARG;
   int mm = 0, ss = 0;
   qsw_status_t st = qsw::select_params_impl(norm1, d, t, n0, prec, &mm, &ss);
   if (st == QSW_OK) {

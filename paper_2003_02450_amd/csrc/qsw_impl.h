@@ -39,6 +39,12 @@ struct DeviceState {
   unsigned long long products;         // sparse products computed
   int nonfinite;
   int pad[3];
+  // single-precision products (QSW_PREC_FP32): the trace check of each
+  // output point in double
+  double tr0;                          // Tr rho0 (after exp(t0 L), the reference)
+  double scale;                        // factor of the point being written
+  unsigned long long trace_dev;        // max |Tr rho_k - tr0| before the factor (bits)
+  unsigned long long pad2;
 };
 
 // Per point k of a series block: ||F_k||_inf after term p, and the stop flag.
@@ -161,6 +167,12 @@ struct SpmvArgs {
   // this host-visible word
   unsigned long long *progress;
   unsigned long long seq;
+  // single-precision products (QSW_PREC_FP32): complex64 x and term, and the
+  // accumulator as a two-float (hi + lo) pair of complex64 vectors
+  const float2 *x32;
+  float2 *y32;
+  const float2 *fin_hi, *fin_lo;
+  float2 *fout_hi, *fout_lo;
 };
 
 // ---- batched propagation (several walks advance together) ----
@@ -304,6 +316,24 @@ hipError_t launch_wjag_same(const int32_t *wcol, const double *wcoef, const doub
 // Single-time algorithm term j: y = alpha A x; F_out = F_in + y; norms into
 // st->step[par]; early exit when the previous terms already passed the test.
 hipError_t launch_taylor_term(const SpmvArgs &a, int engine, int grid, hipStream_t s);
+
+// The same with complex64 vectors and single-precision products (engines
+// 1, 11, 101, 111; a.x32, a.y32, a.fin_hi/lo, a.fout_hi/lo): the term y32 =
+// alpha A x32 is rounded once from the float row sum scaled in double, and
+// F = F_in + y32 is kept as an unevaluated hi + lo pair of floats.
+hipError_t launch_taylor_term32(const SpmvArgs &a, int engine, int grid, hipStream_t s);
+// hi + lo = v for n complex128 elements (hi the nearest float, lo the nearest
+// float to the remainder).
+hipError_t launch_split_c64(const double2 *v, float2 *hi, float2 *lo, int64_t n, hipStream_t s);
+// Trace check of a two-float density matrix (N x N): tr = sum_a (hi + lo)_aa
+// in double; reference = 1 stores it as st->tr0, else st->scale = tr0 / tr
+// (1 when either is zero or not finite, or |tr - tr0| > 2^-10 |tr0|) and
+// st->trace_dev = max(., |tr - tr0|).
+hipError_t launch_trace32(DeviceState *st, const float2 *hi, const float2 *lo, int32_t N,
+                          int reference, hipStream_t s);
+// out = (hi + lo) st->scale in complex128, and hi, lo re-split from it.
+hipError_t launch_emit32(const DeviceState *st, float2 *hi, float2 *lo, double2 *out, int64_t n,
+                         hipStream_t s);
 
 // y = alpha A x (no accumulation, no norms).
 hipError_t launch_spmv(const SpmvArgs &a, int engine, int grid, hipStream_t s);

@@ -1289,7 +1289,7 @@ qsw_status_t build_common(std::shared_ptr<Assembler> src, double omega, hipStrea
   h->info.distinct_entries = h->wdistinct;
   if (hipEventCreate(&h->ev_start) != hipSuccess || hipEventCreate(&h->ev_end) != hipSuccess)
     return fail(QSW_ERR_DEVICE);
-  if (dalloc(&h->stats_dev, 2) != hipSuccess) return fail(QSW_ERR_OOM);
+  if (dalloc(&h->stats_dev, 3) != hipSuccess) return fail(QSW_ERR_OOM);
   auto t_end = std::chrono::steady_clock::now();
   h->info.build_ms = std::chrono::duration<double, std::milli>(t_end - t_start).count();
   *out = h;
@@ -1312,6 +1312,24 @@ qsw_status_t qsw::make_plan(const qsw_superop_s *h, double t0, double dt, int32_
   const size_t vec = (size_t)h->n * sizeof(double2);
   P.off_state = 0;
   size_t off = align256(sizeof(DeviceState));
+  if (h->prec == QSW_PREC_FP32) {
+    // single-precision products: one single-time application per interval;
+    // two complex64 terms, two hi + lo accumulator pairs
+    if (n_steps > 0) {
+      st = select_params_impl(h->info.norm1, d, dt, 1, h->prec, &P.m, &P.s);
+      if (st != QSW_OK) return st;
+    }
+    const size_t v32 = align256((size_t)h->n * sizeof(float2));
+    P.branch = 0;
+    P.off_pts = off;
+    P.off_B = off;
+    off += 2 * v32;
+    P.off_F = off;
+    off += 4 * v32;
+    P.off_K = off;
+    P.total = off;
+    return QSW_OK;
+  }
   if (n_steps > 0) {
     int mS = 0, sS = 1;
     st = select_params_impl(h->info.norm1, d, (double)n_steps * dt, 1, h->prec, &mS, &sS);
@@ -1410,6 +1428,47 @@ struct Runner {
     a.blocks_per_wg = h->blocks_per_wg;
     set_wave(a, h);
     return a;
+  }
+
+  // Single-precision products: complex64 terms B32 and the hi + lo
+  // accumulator pairs (Fh[c], Fl[c]); the state is pair `cur`.
+  float2 *B32[2] = {nullptr, nullptr};
+  float2 *Fh[2] = {nullptr, nullptr}, *Fl[2] = {nullptr, nullptr};
+  int cur = 0;
+
+  // State = T_m(t L / s)^s state, terms in single precision (the stopping
+  // test and the sums of the norms as in alg32).
+  hipError_t alg32_f32(double t, int m, int s_steps) {
+    if (m == 0) return hipSuccess;
+    for (int i = 0; i < s_steps; ++i) {
+      const int par = (int)(gstep & 1);
+      ++gstep;
+      const int src = cur, dst = cur ^ 1;
+      const unsigned long long first = seq ? *seq + 1 : 0;
+      for (int j = 1; j <= m; ++j) {
+        SpmvArgs a = base_args();
+        if (pace_dev) {
+          if (wait_paced(*seq + 1, first)) break;
+          a.progress = pace_dev;
+          a.seq = ++*seq;
+        }
+        // term 1 multiplies the state's hi part (the state rounded to float)
+        a.x32 = (j == 1) ? Fh[src] : B32[(j - 1) & 1];
+        a.y32 = B32[j & 1];
+        a.fin_hi = (j == 1) ? Fh[src] : Fh[dst];
+        a.fin_lo = (j == 1) ? Fl[src] : Fl[dst];
+        a.fout_hi = Fh[dst];
+        a.fout_lo = Fl[dst];
+        a.alpha = t / ((double)s_steps * (double)j);
+        a.par = par;
+        a.j = j;
+        hipError_t e = launch_taylor_term32(a, engine, h->grid, s);
+        if (e != hipSuccess) return e;
+        ++launched;
+      }
+      cur = dst;
+    }
+    return hipSuccess;
   }
 
   // x_out = T_m(t L / s)^s x_in with the early-termination test on the device.
@@ -1960,7 +2019,7 @@ qsw_status_t qsw_superop_set_omega(qsw_superop_t h, double omega, void *hip_stre
   std::swap(h->pace_mu, nh->pace_mu);
   std::swap(*h, *nh);
   qsw_superop_destroy(nh);  // the old arrays
-  if (prec == QSW_PREC_SINGLE) return qsw_superop_set_precision(h, prec);
+  if (prec != QSW_PREC_DOUBLE) return qsw_superop_set_precision(h, prec);
   return QSW_OK;
 }
 
@@ -1993,11 +2052,12 @@ void qsw_superop_destroy(qsw_superop_t h) {
 }
 
 qsw_status_t qsw_superop_set_precision(qsw_superop_t h, int32_t prec) {
-  if (!h || (prec != QSW_PREC_DOUBLE && prec != QSW_PREC_SINGLE)) return QSW_ERR_ARG;
+  if (!h || (prec != QSW_PREC_DOUBLE && prec != QSW_PREC_SINGLE && prec != QSW_PREC_FP32))
+    return QSW_ERR_ARG;
   DeviceGuard g(h->device);
   if (!g.ok) return QSW_ERR_DEVICE;
   const bool have32 = h->split ? h->wcoef32 != nullptr : h->wval32 != nullptr;
-  if (prec == QSW_PREC_SINGLE && !have32) {
+  if (prec != QSW_PREC_DOUBLE && !have32) {
     if (!is_wave_engine(h->engine))
       return QSW_ERR_STATE;  // the single-precision copy exists for the wave layout only
     // the padding converts to zeros as well
@@ -2110,7 +2170,7 @@ qsw_status_t qsw_superop_autotune(qsw_superop_t h, void *hip_stream, qsw_tuning_
       a.y = y;
       a.alpha = 1.0;
       const int engine = (st == 2 ? 200 : (st ? 100 : 0)) + (h->split ? 10 : 0) +
-                         (h->prec == QSW_PREC_SINGLE ? 1 : 0);
+                         (h->prec != QSW_PREC_DOUBLE ? 1 : 0);
       if ((err = launch_spmv(a, engine, grid, s)) != hipSuccess) break;  // warm-up
       if ((err = hipEventRecord(e0, s)) != hipSuccess) break;
       const int reps = 5;
@@ -2191,7 +2251,19 @@ qsw_status_t propagate_on(qsw_superop_t h, const Plan &P, const void *rho0, doub
   R.F[0] = (double2 *)(ws + P.off_F);
   R.F[1] = (double2 *)(ws + P.off_F + vec);
   R.tol = tol_of(h->prec);
-  R.engine = launch_engine(h, h->prec == QSW_PREC_SINGLE);
+  R.engine = launch_engine(h, h->prec != QSW_PREC_DOUBLE);
+  const bool fp32 = h->prec == QSW_PREC_FP32;
+  if (fp32) {
+    // single-precision products: the XCD-banded traversal runs staged
+    if (R.engine >= 200) R.engine -= 100;
+    const size_t v32 = align256((size_t)h->n * sizeof(float2));
+    R.B32[0] = (float2 *)(ws + P.off_B);
+    R.B32[1] = (float2 *)(ws + P.off_B + v32);
+    for (int c = 0; c < 2; ++c) {
+      R.Fh[c] = (float2 *)(ws + P.off_F + (size_t)(2 * c) * v32);
+      R.Fl[c] = (float2 *)(ws + P.off_F + (size_t)(2 * c + 1) * v32);
+    }
+  }
   std::unique_lock<std::mutex> pace_lock;
   if (h->pace > 0 && h->pace_dev) {
     pace_lock = std::unique_lock<std::mutex>(*h->pace_mu);
@@ -2206,13 +2278,33 @@ qsw_status_t propagate_on(qsw_superop_t h, const Plan &P, const void *rho0, doub
   auto slot = [&](int64_t k) { return outv + k * n; };
   HIP_TRY(hipEventRecord(h->ev_start, s));
   HIP_TRY(launch_zero(R.st, sizeof(DeviceState), s));
-  // out[0] = exp(t0 L) rho0
-  if (t0 != 0.0)
+  bool fused = false;  // series blocks run through the fused term kernel
+  if (fp32) {
+    // the state as hi + lo, its trace the reference of every point's check
+    HIP_TRY(launch_split_c64((const double2 *)rho0, R.Fh[0], R.Fl[0], n, s));
+    HIP_TRY(launch_trace32(R.st, R.Fh[0], R.Fl[0], h->N, 1, s));
+    auto emit = [&](int64_t k) -> hipError_t {
+      hipError_t e = launch_trace32(R.st, R.Fh[R.cur], R.Fl[R.cur], h->N, 0, s);
+      if (e != hipSuccess) return e;
+      return launch_emit32(R.st, R.Fh[R.cur], R.Fl[R.cur], slot(k), n, s);
+    };
+    if (t0 != 0.0) {
+      HIP_TRY(R.alg32_f32(t0, P.m0, P.s0));
+      HIP_TRY(emit(0));
+    } else {
+      HIP_TRY(launch_copy(slot(0), (const double2 *)rho0, n, s));
+    }
+    for (int32_t k = 0; k < n_steps; ++k) {
+      HIP_TRY(R.alg32_f32(dt, P.m, P.s));
+      HIP_TRY(emit(k + 1));
+    }
+  } else if (t0 != 0.0)
     HIP_TRY(R.alg32((const double2 *)rho0, slot(0), t0, P.m0, P.s0));
   else
     HIP_TRY(launch_copy(slot(0), (const double2 *)rho0, n, s));
-  bool fused = false;  // series blocks run through the fused term kernel
-  if (n_steps > 0 && P.branch == 0) {
+  if (fp32) {
+    // done above
+  } else if (n_steps > 0 && P.branch == 0) {
     for (int32_t k = 0; k < n_steps; ++k) HIP_TRY(R.alg32(slot(k), slot(k + 1), dt, P.m, P.s));
   } else if (n_steps > 0 && P.d == 1 && env_int("QSW_FUSE_SERIES", 1) != 0) {
     // Time-series blocks of one grid point: the block's powers K_p =
@@ -2253,6 +2345,8 @@ qsw_status_t propagate_on(qsw_superop_t h, const Plan &P, const void *rho0, doub
   HIP_TRY(hipMemcpyAsync(h->stats_dev, &R.st->products, sizeof(unsigned long long),
                          hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipMemcpyAsync(h->stats_dev + 1, &R.st->nonfinite, sizeof(int), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(h->stats_dev + 2, &R.st->trace_dev, sizeof(unsigned long long),
+                         hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipEventRecord(h->ev_end, s));
   h->last = qsw_stats_t{};
   h->last.branch = P.branch;
@@ -2330,19 +2424,24 @@ qsw_status_t qsw_last_stats(qsw_superop_t h, qsw_stats_t *st) {
   DeviceGuard g(h->device);
   if (!g.ok) return QSW_ERR_DEVICE;
   HIP_TRY(hipEventSynchronize(h->ev_end));
-  unsigned long long buf[2] = {0, 0};
+  unsigned long long buf[3] = {0, 0, 0};
   HIP_TRY(hipMemcpy(buf, h->stats_dev, sizeof(buf), hipMemcpyDeviceToHost));
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, h->ev_start, h->ev_end));
   h->last.products = (int64_t)buf[0];
   h->last.nonfinite = (int)(buf[1] & 0xffffffffu) != 0;
   h->last.ms = ms;
-  const bool single = h->last.prec == QSW_PREC_SINGLE;
+  const bool fp32 = h->last.prec == QSW_PREC_FP32;
+  double tdev = 0.0;
+  std::memcpy(&tdev, &buf[2], sizeof(double));
+  h->last.trace_dev = fp32 ? tdev : 0.0;
+  const bool single = h->last.prec != QSW_PREC_DOUBLE;
   const bool split = h->split && is_wave_engine(h->engine);
   const double entry = split ? (single ? 8.0 : 12.0) : (single ? 12.0 : 20.0);
   const double diag = split ? (single ? 8.0 : 16.0) : 0.0;
-  // the stored-power series adds a separate accumulation pass
-  const double vec = h->last.branch == 1 && !h->last_fused ? 80.0 : 64.0;
+  // the stored-power series adds a separate accumulation pass; single-precision
+  // products move x, the term and the hi + lo accumulator in complex64
+  const double vec = fp32 ? 48.0 : (h->last.branch == 1 && !h->last_fused ? 80.0 : 64.0);
   const double entries = is_wave_engine(h->engine) ? (double)h->wentries : (double)h->nnz;
   const double shared = is_wave_engine(h->engine) ? 16.0 * (double)h->wshared : 0.0;
   h->last.bytes = (double)h->last.products * (entry * entries + shared + 8.0 * (double)(h->n + 1) +

@@ -10,7 +10,8 @@ propagation (one single-time application per interval, exact 1-norm):
 * ``samples[k]`` - rho_k at SAMPLES flat row-major indices given by
   ``sample_indices(n, k)`` below (a fixed odd-stride walk over the n = N^2
   elements, offset per point, so different points cover different elements);
-* ``trace[k]``   - Tr rho_k.
+* ``trace[k]``   - Tr rho_k;
+* ``vec1[k]``    - ||vec rho_k||_1 (sum of the element moduli), for error bounds.
 
 The files hold plain arrays (numpy .npz, no pickled objects) and a JSON
 header.  Section 5 of the paper compares against an independent code at every
@@ -65,6 +66,7 @@ def write(name: str) -> str:
     pops = np.stack([np.diag(out[k]).real for k in range(K)])
     samples = np.stack([flat[k, sample_indices(n, k)] for k in range(K)])
     trace = np.array([np.trace(out[k]) for k in range(K)])
+    vec1 = np.abs(flat).sum(axis=1)
     header = {
         "workload": name, "N": N, "n": n, "points": K, "t0": wl.t0, "dt": wl.dt,
         "omega": wl.omega, "samples_per_point": SAMPLES,
@@ -75,16 +77,17 @@ def write(name: str) -> str:
                   "application per interval); written by tests/golden/make_fullgrid.py",
     }
     path = fixture_path(name)
-    np.savez(path, pops=pops, samples=samples, trace=trace,
+    np.savez(path, pops=pops, samples=samples, trace=trace, vec1=vec1,
              header=np.frombuffer(json.dumps(header).encode(), np.uint8))
     print(f"{path}: {K} points, {secs:.1f} s", flush=True)
     return path
 
 
 def load(name: str):
+    """(header, arrays): arrays holds pops, samples, trace and vec1."""
     z = np.load(fixture_path(name), allow_pickle=False)
     header = json.loads(bytes(z["header"]).decode())
-    return header, z["pops"], z["samples"], z["trace"]
+    return header, {k: z[k] for k in ("pops", "samples", "trace", "vec1")}
 
 
 if __name__ == "__main__":

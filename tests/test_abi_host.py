@@ -95,3 +95,19 @@ def test_select_params_rejects_bad_input():
         qsw.select_params(float("nan"), None, 1.0)
     with pytest.raises(qsw.QswError):
         qsw.select_params(1.0, None, float("inf"))
+
+
+def test_select_params_fp32_matches_oracle_capped_rule():
+    """QSW_PREC_FP32: the single-precision theta_m with m <= 20, p <= 5."""
+    th = otheta.theta_table(otheta.TOL_SINGLE)
+    rng = np.random.Generator(np.random.PCG64(9))
+    for _ in range(300):
+        nrm = float(10 ** rng.uniform(-1, 2))
+        d = {p: nrm * float(rng.uniform(0.01, 1.0)) for p in range(2, 10)}
+        t = float(10 ** rng.uniform(-2, 3))
+        n0 = int(rng.integers(1, 5))
+        got = qsw.select_params(nrm, d, t, n0, single="fp32")
+        want = oexpmv.select_params(nrm, d, t, n0, thetas=th, m_max=20, p_max=5)
+        assert got == want, (nrm, t, n0, got, want)
+        assert got[0] <= 20
+

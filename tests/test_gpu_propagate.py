@@ -115,7 +115,8 @@ def test_outdeg1024_matches_oracle_every_point():
     oracle's full-grid fixture: at every point all 1024 populations, the
     trace and 10^4 sampled elements (different ones per point), plus the
     trace and Hermiticity of every point."""
-    mod, (hdr, pops, samples, trace) = _fullgrid("outdeg1024")
+    mod, (hdr, fx) = _fullgrid("outdeg1024")
+    pops, samples, trace = fx["pops"], fx["samples"], fx["trace"]
     wl = workloads.outdeg1024()
     assert hdr["points"] == wl.n_steps + 1 and hdr["N"] == wl.graph.N
     op = build_gpu(wl)

@@ -30,9 +30,9 @@ from oracle import theta as oth
 TH = oth.theta_table()
 
 
-def _admissible_pairs():
-    for p in range(2, oth.P_MAX + 1):
-        for m in range(max(1, p * (p - 1) - 1), oth.M_MAX + 1):
+def _admissible_pairs(m_max=oth.M_MAX, p_max=oth.P_MAX):
+    for p in range(2, p_max + 1):
+        for m in range(max(1, p * (p - 1) - 1), m_max + 1):
             yield m, p
 
 
@@ -100,19 +100,24 @@ def test_norm1_of_walk_superop_matches_dense():
 
 # ---------------------------------------------------------- the alpha_p rule
 
-def test_select_params_feasible_and_optimal():
+@pytest.mark.parametrize("tol,m_max,p_max", [(oth.TOL_DOUBLE, oth.M_MAX, oth.P_MAX),
+                                               (oth.TOL_SINGLE, 20, 5)])
+def test_select_params_feasible_and_optimal(tol, m_max, p_max):
+    th = oth.theta_table(tol)
     rng = np.random.Generator(np.random.PCG64(41))
     for _ in range(300):
         nrm, d, t = _random_case(rng)
         n0 = int(rng.integers(1, 5))
-        assert not expmv.condition_3_13(t * nrm, n0)
-        m, s = expmv.select_params(nrm, d, t, n0)
+        if expmv.condition_3_13(t * nrm, n0, thetas=th, m_max=m_max, p_max=p_max):
+            continue
+        m, s = expmv.select_params(nrm, d, t, n0, thetas=th, m_max=m_max, p_max=p_max)
+        assert m <= m_max
         # feasibility: the bound holds for some admissible p
-        assert any(p * (p - 1) - 1 <= m and _alpha(d, p, t) / s <= TH[m - 1]
-                   for p in range(2, oth.P_MAX + 1)), (nrm, t, m, s)
+        assert any(p * (p - 1) - 1 <= m and _alpha(d, p, t) / s <= th[m - 1]
+                   for p in range(2, p_max + 1)), (nrm, t, m, s)
         # optimality over every admissible pair, smallest m among the best
-        costs = [(mm * math.ceil(_alpha(d, p, t) / TH[mm - 1]), mm)
-                 for mm, p in _admissible_pairs()]
+        costs = [(mm * math.ceil(_alpha(d, p, t) / th[mm - 1]), mm)
+                 for mm, p in _admissible_pairs(m_max, p_max)]
         best = min(c for c, _ in costs)
         assert m * s == best, (m, s, best)
         assert m == min(mm for c, mm in costs if c == best)

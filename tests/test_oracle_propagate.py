@@ -328,7 +328,8 @@ def test_fullgrid_fixture_is_the_oracles():
         "make_fullgrid", os.path.join(GOLDEN, "make_fullgrid.py"))
     mod = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(mod)
-    hdr, pops, samples, trace = mod.load("outdeg1024")
+    hdr, fx = mod.load("outdeg1024")
+    pops, samples, trace = fx["pops"], fx["samples"], fx["trace"]
     wl = workloads.outdeg1024()
     A = oracle.walk_superop(wl.graph.dense(), wl.omega, wl.h_mode, wl.r_mode,
                             wl.dephasing, wl.gamma)
@@ -339,4 +340,65 @@ def test_fullgrid_fixture_is_the_oracles():
         assert np.array_equal(np.diag(out[k]).real, pops[k])
         assert np.array_equal(out[k].reshape(-1)[mod.sample_indices(n, k)], samples[k])
     assert np.abs(trace - 1).max() < 1e-12
+    assert fx["vec1"][0] == 1.0 and abs(fx["vec1"][1] - np.abs(out[1]).sum()) < 1e-12
     assert len(np.unique(mod.sample_indices(n, 3))) == mod.SAMPLES
+
+
+# ------------------------------------------- single-precision products variant
+
+def _vec1_max(ref):
+    return max(float(np.abs(ref[k]).sum()) for k in range(ref.shape[0]))
+
+
+def _fp32_check(A, rho0, t0, dt, n):
+    out, info = expmv.propagate_fp32_products(A, rho0, t0, dt, n)
+    S = A.dense()
+    rmax = int(np.diff(A.row_ptr).max())
+    th = oracle.theta.theta_table(oracle.theta.TOL_SINGLE)
+    theta = th[expmv.M_MAX_FP32 - 1]     # every step has ||A||_1 |t_step| / s <= theta_20
+    s0 = expmv.select_params_norm1(abs(t0) * info["norm1"], th, expmv.M_MAX_FP32)[1] \
+        if t0 != 0.0 else 0
+    errs = []
+    refs = [scipy.linalg.expm((t0 + dt * k) * S) @ rho0.reshape(-1) for k in range(n + 1)]
+    vec1 = max(float(np.abs(r).sum()) for r in refs)
+    for k in range(n + 1):
+        t = t0 + dt * k
+        err = np.abs(out[k].reshape(-1) - refs[k]).max()
+        steps = k * info["s"] + s0
+        bound = expmv.fp32_products_bound(info["norm1"], t, max(steps, 1), theta, rmax, vec1)
+        assert err <= bound, (k, err, bound)
+        errs.append(err)
+        assert abs(np.trace(out[k]).real - np.trace(rho0).real) < 1e-13
+    assert info["m"] <= expmv.M_MAX_FP32
+    return errs, info
+
+
+def test_fp32_products_dyadic_cycle_within_bound():
+    """Cycle with dyadic entries (float storage exact): only the products'
+    rounding and the 2^-24 truncation remain; within the first-order bound and
+    clearly above double rounding."""
+    wl = _cycle_wl(0.5, r_mode="transition")
+    A = oracle.walk_superop(wl.graph.dense(), wl.omega, wl.h_mode, wl.r_mode,
+                            wl.dephasing, wl.gamma)
+    errs, info = _fp32_check(A, wl.rho0, 0.0, wl.dt, wl.n_steps)
+    assert max(errs) > 1e-12
+
+
+@pytest.mark.parametrize("omega,t0", [(0.0, 0.0), (0.4, 0.0), (0.9, 0.6), (1.0, 0.0)])
+def test_fp32_products_random_digraphs_within_bound(omega, t0):
+    rng = np.random.Generator(np.random.PCG64(33))
+    g = workloads.random_out_degree(12, 3, rng)
+    A = oracle.walk_superop(g.dense(), omega)
+    rho0 = workloads.random_density(12, rng, rank=2)
+    errs, info = _fp32_check(A, rho0, t0, 0.9, 4)
+    assert max(errs) > 1e-12
+
+
+def test_fp32_products_degree_cap_and_parameters():
+    """The degree never exceeds 20 and (m, s) is the 1-norm rule at u = 2^-24
+    restricted to m <= 20: theta_m s covers ||tA||_1 with the least m s."""
+    th = oracle.theta.theta_table(oracle.theta.TOL_SINGLE)
+    for x in (0.3, 3.0, 23.09, 150.0):
+        m, s = expmv.select_params_norm1(x, th, expmv.M_MAX_FP32)
+        assert 1 <= m <= 20 and x / s <= th[m - 1]
+        assert all(mm * math.ceil(x / th[mm - 1]) >= m * s for mm in range(1, 21))
