@@ -9,22 +9,28 @@ propagation to all 51 grid points.  The graph, rho0, the output series and
 the workspace are resident before the timed region starts.
 
 Prints one JSON line.  `value` is rho(t) grid steps per second of the whole
-pass.  `roofline` rates the fused Taylor-term product kernel: algorithmic
-bytes of the products it computed (per product 12 e + 16 s + 8 (n+1) +
-16 n + 64 n with phase-split values: one real coefficient and a column per
-stored entry e, the entries shared by the 64 rows of a block s, row data,
-the complex diagonal per row, x, the term and the accumulator; 20 nnz +
-8 (n+1) + 64 n with complex values) over the device time of the timed
-propagate calls, measured with HIP events on the stream the kernels run
-on.  `single_values` repeats the pass with
-the superoperator values stored as complex64 and the 2^-24 tolerance
-(vectors and sums stay double) and reports its rate, its product kernel's
-bandwidth and its largest deviation from the double pass.  `batched` runs 64
-small walks with 4 density matrices each through one engine, against the same
-walks one density matrix at a time.  `served` drives the continuous-batching
-server with Poisson arrivals at several rates and reports walks/s and
-p50/p99 latency.  `cpu_baseline`
-times the CPU oracle on a bounded sample of the same workload.
+pass.  `roofline` rates the fused Taylor-term product kernel over the device
+time of the timed propagate calls (HIP events on the stream the kernels run
+on).  Its `achieved` counts the layout bytes: every word the kernel reads or
+writes per product (12 e + 16 s + 8 (n+1) + 16 n + 64 n with phase-split
+values: one real coefficient and a column per stored entry e, the entries
+shared by the 64 rows of a block s, row data, the complex diagonal per row, x,
+the term and the accumulator), whether the HBM or a cache serves it; blocks
+with equal rows read one cached copy, so the HBM traffic (`traffic`, from
+rocprofv3 counters) is lower.  `csr_equivalent_gbps` divides the complex CSR's
+bytes (20 nnz + 8 (n+1) + 64 n) by the same time.  `csr_engine` times the
+plain CSR stream engine on the same pass, whose reads are exactly those CSR
+bytes.  `fp32` repeats the pass with single-precision products (complex64
+values, vectors and terms, two-float accumulation, FP64 norms, parameters and
+trace check) and reports its rate, its kernel's bandwidth and its largest
+deviation from the FP64 oracle at every point (the committed full-grid
+fixture); `single_values` does the same with only the values in complex64.
+`configs` reports the rate of the N = 16 cycle and N = 256 ER workloads.
+`batched` runs 64 small walks with 4 density matrices each through one
+engine, against the same walks one density matrix at a time.  `served` drives
+the continuous-batching server with Poisson arrivals at several rates and
+reports walks/s and p50/p99 latency.  `cpu_baseline` times the CPU oracle on
+a bounded sample of the same workload, with all host threads and with one.
 """
 from __future__ import annotations
 
@@ -45,10 +51,11 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_term_kernel_outdeg1024.tx
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2003_02450_amd", "csrc", "kernels.hip")
 
 
-def measured_traffic():
+def measured_traffic(key: str = "traffic_bytes_per_product"):
     """HBM bytes per computing Taylor-term product from the committed
-    rocprofv3 FETCH_SIZE / WRITE_SIZE runs, or None when the kernel source
-    has changed since those counters were taken."""
+    rocprofv3 FETCH_SIZE / WRITE_SIZE runs (key: the FP64 kernel's, or
+    "traffic_bytes_per_product_fp32"), or None when the kernel source has
+    changed since those counters were taken."""
     import hashlib
     try:
         fields = {}
@@ -60,12 +67,18 @@ def measured_traffic():
         h = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
         if fields.get("kernels_sha256_16") != h:
             return None
-        return float(fields["traffic_bytes_per_product"])
+        return float(fields[key])
     except (OSError, KeyError, ValueError):
         return None
 
 
-def term_bytes(info: dict, single: bool, series: bool = False) -> float:
+def csr_bytes(n: int, nnz: int) -> float:
+    """Algorithmic bytes of one Taylor-term product through the complex CSR:
+    column and value per entry, row pointers, x, the term, the accumulator."""
+    return 20.0 * nnz + 8.0 * (n + 1) + 64.0 * n
+
+
+def term_bytes(info: dict, single: bool, series: bool = False, fp32: bool = False) -> float:
     """Algorithmic HBM bytes of one Taylor-term product (the library's own
     qsw_stats_t.bytes per product): column index and value per stored entry
     (4 + 8 phase-split double, 4 + 4 phase-split single, 4 + 16 / 4 + 8
@@ -75,16 +88,48 @@ def term_bytes(info: dict, single: bool, series: bool = False) -> float:
     and written (the time-series branch writes the power and accumulates in
     a second pass: 16 n more)."""
     n, split = info["n"], info["split"]
+    single = single or fp32
     entry = (8.0 if single else 12.0) if split else (12.0 if single else 20.0)
     diag = (8.0 if single else 16.0) if split else 0.0
+    vec = 48.0 if fp32 else (80.0 if series else 64.0)
     return (entry * info["stream_entries"] + 16.0 * info["shared_entries"] + 8.0 * (n + 1) +
-            (diag + (80.0 if series else 64.0)) * n)
+            (diag + vec) * n)
 
 
-def cpu_baseline(wl, sample_steps: int) -> dict:
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+_ONE_THREAD = r"""
+import json, sys, time
+sys.path.insert(0, sys.argv[1])
+import oracle, workloads
+from oracle import expmv
+wl = workloads.outdeg1024()
+t0 = time.perf_counter()
+A = oracle.walk_superop(wl.graph.dense(), wl.omega, wl.h_mode, wl.r_mode, wl.dephasing, wl.gamma)
+t_build = time.perf_counter() - t0
+k = int(sys.argv[2])
+t0 = time.perf_counter()
+_, info = expmv.propagate(A, wl.rho0, wl.t0, wl.dt, k)
+print(json.dumps({"build": t_build, "seconds": time.perf_counter() - t0, "intervals": k,
+                  "products": info["products"]}))
+"""
+
+
+def cpu_baseline(wl, sample_steps: int, one_thread_steps: int) -> dict:
     """The oracle (plain C, OpenMP over rows) on the host cores: build the
     superoperator and propagate `sample_steps` intervals, then scale to the
-    full grid."""
+    full grid.  Then the same on one thread (a child process with
+    OMP_NUM_THREADS=1) for `one_thread_steps` intervals."""
+    import subprocess
+
     import oracle
     from oracle import expmv
 
@@ -98,26 +143,69 @@ def cpu_baseline(wl, sample_steps: int) -> dict:
     t_steps = time.perf_counter() - t0
     per_step = t_steps / sample_steps
     full = t_build + wl.n_steps * per_step
-    return {"value": wl.n_steps / full, "unit": "steps/s", "cores": threads, "kind": "oracle",
-            "sample": (f"oracle superoperator build ({t_build:.2f} s) + {sample_steps} of "
-                       f"{wl.n_steps} intervals ({t_steps:.2f} s, {info['products']} products); "
-                       f"rate = {wl.n_steps} / (build + {wl.n_steps} x mean interval)")}
+    out = {"value": wl.n_steps / full, "unit": "steps/s", "cores": threads, "kind": "oracle",
+           "cpu_model": cpu_model(),
+           "sample": (f"oracle superoperator build ({t_build:.2f} s) + {sample_steps} of "
+                      f"{wl.n_steps} intervals ({t_steps:.2f} s, {info['products']} products); "
+                      f"rate = {wl.n_steps} / (build + {wl.n_steps} x mean interval)")}
+    if one_thread_steps > 0:
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, "-c", _ONE_THREAD, ROOT, str(one_thread_steps)],
+                           env=env, capture_output=True, text=True, timeout=600)
+        if r.returncode == 0:
+            one = json.loads(r.stdout.strip().splitlines()[-1])
+            per_step = one["seconds"] / one["intervals"]
+            out["single_thread"] = {
+                "value": wl.n_steps / (one["build"] + wl.n_steps * per_step), "unit": "steps/s",
+                "cores": 1, "kind": "oracle",
+                "sample": (f"oracle on one thread: build ({one['build']:.2f} s) + "
+                           f"{one['intervals']} of {wl.n_steps} intervals ({one['seconds']:.2f} s, "
+                           f"{one['products']} products); rate = {wl.n_steps} / (build + "
+                           f"{wl.n_steps} x mean interval)")}
+    return out
 
 
-def single_leg(args, one_pass, out64, torch, n, nnz, q, wl) -> dict:
-    """The same pass with complex64 superoperator values and the 2^-24
-    tolerance (vectors and sums in double), timed the same way, and its
-    largest element difference from the double pass over all 51 points."""
-    out32 = torch.empty_like(out64)
+def timed_passes(args, one_pass, dst):
     for _ in range(args.warmup):
-        one_pass(True, out32)
+        one_pass(dst)
+    import torch
     torch.cuda.synchronize()
     stats = []
     t_start = time.perf_counter()
     for _ in range(args.steps):
-        stats.append(one_pass(True, out32))
+        stats.append(one_pass(dst))
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
+    return stats, time.perf_counter() - t_start
+
+
+def fixture_error(got) -> float:
+    """Largest |rho - rho_oracle| of a [51, 1024, 1024] device series over the
+    committed full-grid oracle fixture (all populations, the trace and 10^4
+    sampled elements per point)."""
+    import importlib.util
+    path = os.path.join(ROOT, "tests", "golden", "make_fullgrid.py")
+    spec = importlib.util.spec_from_file_location("make_fullgrid", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    _, fx = mod.load("outdeg1024")
+    g = got.cpu().numpy()
+    K, N = g.shape[0], g.shape[1]
+    flat = g.reshape(K, N * N)
+    worst = 0.0
+    for k in range(K):
+        worst = max(worst, float(np.abs(np.diag(g[k]).real - fx["pops"][k]).max()),
+                    float(np.abs(flat[k, mod.sample_indices(N * N, k)] - fx["samples"][k]).max()),
+                    float(abs(np.trace(g[k]) - fx["trace"][k])))
+    return worst
+
+
+def precision_leg(args, make_pass, out64, torch, q, mode) -> dict:
+    """The same pass at another precision ("single": complex64 values,
+    complex128 vectors; "fp32": single-precision products), timed the same
+    way, its largest element difference from the double pass and from the
+    FP64 oracle's full-grid fixture over all 51 points."""
+    out = torch.empty_like(out64)
+    stats, elapsed = timed_passes(args, make_pass(mode), out)
     prop_ms = sum(s["ms"] for s, _ in stats)
     products = sum(s["products"] for s, _ in stats)
     launched = sum(s["launched"] for s, _ in stats)
@@ -126,20 +214,92 @@ def single_leg(args, one_pass, out64, torch, n, nnz, q, wl) -> dict:
     # accumulation pass)
     per = sum(s["bytes"] for s, _ in stats) / max(products, 1)
     achieved = products * per / (prop_ms * 1e-3) / 1e9
-    diff = float((out32 - out64).abs().max().item())
-    bound = 2.0 * 2.0 ** -24 * (q * wl.dt) * info0["norm1"] * float(abs(wl.rho0).sum())
-    return {"value": args.steps * q / elapsed, "unit": "steps/s",
-            "ms_per_step": 1e3 * elapsed / args.steps, "dtype": "c64 values, f64 vectors",
-            "m": st0["m"], "s": st0["s"],
-            "branch": "single-time per interval" if st0["branch"] == 0 else "series",
-            "values": "phase-split f32" if info0["split"] else "complex64",
-            "propagate_ms": round(prop_ms / args.steps, 3),
-            "products_per_step": products // args.steps,
-            "term_launches_per_step": launched // args.steps,
-            "achieved": achieved, "frac": achieved / HBM_PEAK_GBPS,
-            "bytes_per_product": per,
+    diff = float((out - out64).abs().max().item())
+    res = {"value": args.steps * q / elapsed, "unit": "steps/s",
+           "ms_per_step": 1e3 * elapsed / args.steps,
+           "dtype": "c64 values, f64 vectors" if mode == "single" else
+                    "c64 values, vectors and products; hi+lo c64 accumulator; f64 norms",
+           "m": st0["m"], "s": st0["s"],
+           "branch": "single-time per interval" if st0["branch"] == 0 else "series",
+           "values": "phase-split f32" if info0["split"] else "complex64",
+           "propagate_ms": round(prop_ms / args.steps, 3),
+           "products_per_step": products // args.steps,
+           "term_launches_per_step": launched // args.steps,
+           "kernel": "term32_kernel<111>" if mode == "fp32" else "term_kernel<111>",
+           "achieved": achieved, "unit_bw": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
+           "bytes_per_product": per,
+           "avg_product_us": 1e3 * prop_ms / max(products, 1),
+           "max_abs_diff_vs_double": diff}
+    try:
+        res["max_abs_err_vs_fp64_oracle"] = fixture_error(out)
+    except (OSError, KeyError, ValueError):
+        res["max_abs_err_vs_fp64_oracle"] = None
+    if mode == "fp32":
+        res["trace_dev_max"] = max(s["trace_dev"] for s, _ in stats)
+        traffic = measured_traffic("traffic_bytes_per_product_fp32")
+        res["traffic"] = traffic
+        if traffic is not None:
+            res["measured_hbm_frac"] = traffic / (res["avg_product_us"] * 1e3) / HBM_PEAK_GBPS
+    return res
+
+
+def csr_leg(args, make_pass, out64, torch, q, n, nnz) -> dict:
+    """The plain CSR stream engine (the paper's format: row_ptr, columns,
+    complex128 values, read once per product) on the same pass.  Its reads
+    are the complex CSR's bytes, 20 nnz + 8 (n+1) + 64 n per product."""
+    out = torch.empty_like(out64)
+    os.environ["QSW_ENGINE"] = "3"
+    try:
+        stats, elapsed = timed_passes(args, make_pass("double"), out)
+    finally:
+        os.environ.pop("QSW_ENGINE", None)
+    prop_ms = sum(s["ms"] for s, _ in stats)
+    products = sum(s["products"] for s, _ in stats)
+    per = csr_bytes(n, nnz)
+    achieved = products * per / (prop_ms * 1e-3) / 1e9
+    return {"kernel": "term_kernel<3> (CSR stream engine)", "value": args.steps * q / elapsed,
+            "unit": "steps/s", "propagate_ms": round(prop_ms / args.steps, 3),
             "avg_product_us": 1e3 * prop_ms / max(products, 1),
-            "max_abs_diff_vs_double": diff, "first_order_bound_t50": bound}
+            "achieved": achieved, "unit_bw": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
+            "bytes_per_product": per,
+            "max_abs_diff_vs_wave_layout": float((out - out64).abs().max().item())}
+
+
+def configs_leg(torch, qsw, workloads, reps: int) -> dict:
+    """The N = 16 cycle (11 points, time-series branch) and the N = 256 ER
+    workload (101 points): propagate-only rates (operators built once, inputs
+    resident), device time from HIP events, effective GB/s from the library's
+    byte count of the products."""
+    res = {}
+    dev = torch.device("cuda", 0)
+    for wl in (workloads.cycle16(), workloads.er256()):
+        g = wl.graph
+        op = qsw.Superop.from_graph(g.N, g.row_ptr, g.col_idx, g.w, wl.omega, gamma=wl.gamma,
+                                    h_mode=wl.h_mode, r_mode=wl.r_mode, dephasing=wl.dephasing)
+        rho0 = torch.from_numpy(wl.rho0).to(dev)
+        out = torch.empty((wl.n_steps + 1, g.N, g.N), dtype=torch.complex128, device=dev)
+        ws = torch.empty(op.workspace_bytes(wl.t0, wl.dt, wl.n_steps) + 256, dtype=torch.uint8,
+                         device=dev)
+        op.propagate(rho0, wl.t0, wl.dt, wl.n_steps, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ms = bytes_ = 0.0
+        for _ in range(reps):
+            op.propagate(rho0, wl.t0, wl.dt, wl.n_steps, out=out, workspace=ws)
+            st = op.last_stats()
+            ms += st["ms"]
+            bytes_ += st["bytes"]
+        elapsed = time.perf_counter() - t0
+        res[wl.name] = {"steps_per_s": reps * wl.n_steps / elapsed,
+                        "device_steps_per_s": reps * wl.n_steps / (ms * 1e-3),
+                        "ms_per_propagate": ms / reps, "build_ms": op.info()["build_ms"],
+                        "m": st["m"], "s": st["s"],
+                        "branch": "single-time per interval" if st["branch"] == 0 else "series",
+                        "products": st["products"],
+                        "effective_gbps": bytes_ / (ms * 1e-3) / 1e9,
+                        "note": "L2/Infinity-Cache resident operator: effective, not HBM"}
+        op.close()
+    return res
 
 
 def batch_leg(torch, qsw, workloads, reps: int, compare: bool = True) -> dict:
@@ -246,11 +406,16 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-sample-steps", type=int, default=2)
+    ap.add_argument("--cpu-one-thread-steps", type=int, default=1,
+                    help="oracle intervals timed on one thread (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pace", type=int, default=2,
                     help="launch pacing lookahead of the single-walk passes (0: off)")
     ap.add_argument("--no-single", action="store_true",
                     help="skip the complex64-values leg")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the single-precision leg")
+    ap.add_argument("--no-csr", action="store_true", help="skip the CSR stream-engine leg")
+    ap.add_argument("--no-configs", action="store_true", help="skip the N=16 / N=256 legs")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-walks leg")
     ap.add_argument("--only-batch", action="store_true",
                     help="run only the batched-walks leg (for profiling) and print it")
@@ -296,26 +461,20 @@ def main() -> int:
     n, nnz = probe.n, probe.nnz
     probe.close()
 
-    def one_pass(single=False, dst=out):
-        op = build()
-        op.set_pacing(args.pace)
-        if single:
-            op.set_precision(True)
-        op.propagate(rho0, wl.t0, wl.dt, q, out=dst, workspace=ws)
-        st = op.last_stats()        # waits for the pass on the library stream
-        info = op.info()
-        op.close()
-        return st, info
+    def make_pass(mode):
+        def one_pass(dst):
+            op = build()
+            op.set_pacing(args.pace)
+            if mode != "double":
+                op.set_precision(mode)
+            op.propagate(rho0, wl.t0, wl.dt, q, out=dst, workspace=ws)
+            st = op.last_stats()        # waits for the pass on the library stream
+            info = op.info()
+            op.close()
+            return st, info
+        return one_pass
 
-    for _ in range(args.warmup):
-        one_pass()
-    torch.cuda.synchronize()
-    stats = []
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        stats.append(one_pass())
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
+    stats, elapsed = timed_passes(args, make_pass("double"), out)
 
     prop_ms = sum(s["ms"] for s, _ in stats)
     products = sum(s["products"] for s, _ in stats)
@@ -328,6 +487,8 @@ def main() -> int:
     assert abs(bytes_total - sum(s["bytes"] for s, _ in stats)) <= 1e-6 * bytes_total
     achieved = bytes_total / (prop_ms * 1e-3) / 1e9
     st0 = stats[0][0]
+    traffic = measured_traffic()
+    per_us = 1e3 * prop_ms / max(products, 1)
 
     result = {
         "metric": "rho(t) steps/s",
@@ -350,23 +511,38 @@ def main() -> int:
                    "values": "phase-split" if split else "complex",
                    "stream_entries": info0["stream_entries"],
                    "shared_entries": info0["shared_entries"],
+                   "distinct_entries": info0["distinct_entries"],
                    "launch_pacing": args.pace,
                    "build_ms": round(build_ms, 3),
                    "propagate_ms": round(prop_ms / args.steps, 3),
                    "products_per_step": products // args.steps,
                    "term_launches_per_step": launched // args.steps},
         "roofline": {"bound": "hbm",
-                     "kernel": (f"term_kernel<{110 if split else 100}> (CSR product + Taylor "
-                                "epilogue, rho-row staged in LDS, "
+                     "kernel": (f"term_kernel<{110 if split else 100}> (sparse product + Taylor "
+                                "epilogue, wave layout, rho-row staged in LDS, "
                                 f"{'phase-split' if split else 'complex'} values)"),
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(),
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
+                     "bytes_basis": ("layout bytes: every word each product reads or writes, "
+                                     "served by HBM or by a cache (equal blocks share one "
+                                     "copy); the complex CSR's bytes give csr_equivalent_gbps"),
                      "bytes_per_product": per_product,
+                     "csr_bytes_per_product": csr_bytes(n, nnz),
+                     "csr_equivalent_gbps": csr_bytes(n, nnz) / (per_us * 1e3),
+                     "measured_hbm_gbps": None if traffic is None else traffic / (per_us * 1e3),
+                     "measured_hbm_frac": (None if traffic is None else
+                                           traffic / (per_us * 1e3) / HBM_PEAK_GBPS),
                      "avg_launch_us": 1e3 * prop_ms / max(launched, 1),
-                     "avg_product_us": 1e3 * prop_ms / max(products, 1)},
+                     "avg_product_us": per_us},
     }
+    if not args.no_csr:
+        result["csr_engine"] = csr_leg(args, make_pass, out, torch, q, n, nnz)
+    if not args.no_fp32:
+        result["fp32"] = precision_leg(args, make_pass, out, torch, q, "fp32")
     if not args.no_single:
-        result["single_values"] = single_leg(args, one_pass, out, torch, n, nnz, q, wl)
+        result["single_values"] = precision_leg(args, make_pass, out, torch, q, "single")
+    if not args.no_configs:
+        result["configs"] = configs_leg(torch, qsw, workloads, max(3, args.steps))
     if not args.no_batch:
         result["batched"] = batch_leg(torch, qsw, workloads, args.steps,
                                       not args.no_batch_compare)
@@ -375,7 +551,8 @@ def main() -> int:
                                       [float(x) for x in args.serve_qps.split(",")],
                                       args.serve_count)
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_steps)
+        result["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_steps,
+                                              args.cpu_one_thread_steps)
     print(json.dumps(result), flush=True)
     return 0
 
