@@ -305,9 +305,12 @@ def configs_leg(torch, qsw, workloads, reps: int) -> dict:
 def batch_leg(torch, qsw, workloads, reps: int, compare: bool = True) -> dict:
     """Batched walks: 64 ER graphs (N log-uniform in [32, 512], p = 8/N,
     unit weights, omega ~ U(0,1)), 4 basis states each, t = 0..20 in 100
-    steps, all walks in one engine (4 right-hand sides per walk).  Timed
-    against the same walks through qsw_propagate one density matrix at a
-    time; every batched result is bitwise that of its single walk."""
+    steps, all walks in one engine (4 right-hand sides per walk; chunks of
+    cycles replayed as HIP graphs, launch shape tuned on the first run).
+    Timed against the same walks through qsw_propagate one density matrix at
+    a time; every batched result is bitwise that of its single walk.  Then
+    the same batch with single-precision values (`single_values`), with its
+    largest difference from the double batch."""
     dev = torch.device("cuda", 0)
     wls = workloads.batch64()
     t0 = time.perf_counter()
@@ -319,15 +322,23 @@ def batch_leg(torch, qsw, workloads, reps: int, compare: bool = True) -> dict:
     outs = [torch.empty((w.n_steps + 1,) + w.rho0.shape, dtype=torch.complex128, device=dev)
             for w in wls]
     items = [(op, r, w.t0, w.dt, w.n_steps, o, None) for op, r, w, o in zip(ops, r0, wls, outs)]
-    st = qsw.batch_propagate(items)  # warm-up, sizes the workspace
+    st = qsw.batch_propagate(items)  # warm-up (tunes the launch shape), sizes the workspace
     ws = torch.empty(st["workspace_bytes"] + 256, dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        st = qsw.batch_propagate(items, workspace=ws)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+
+    def timed(its):
+        t_0 = time.perf_counter()
+        dev_ms = byts = 0.0
+        for _ in range(reps):
+            s_ = qsw.batch_propagate(its, workspace=ws)
+            dev_ms += s_["ms"]
+            byts += s_["bytes"]
+        torch.cuda.synchronize()
+        return time.perf_counter() - t_0, dev_ms, byts, s_
+
+    elapsed, dev_ms, byts, st = timed(items)
     points = sum(w.n_steps * w.rho0.shape[0] for w in wls)
+    achieved = byts / (dev_ms * 1e-3) / 1e9
     # the same walks one density matrix at a time
     t0 = time.perf_counter()
     equal = True
@@ -342,36 +353,104 @@ def batch_leg(torch, qsw, workloads, reps: int, compare: bool = True) -> dict:
                 equal = equal and bool(torch.equal(one, outs[i][:, c]))
     torch.cuda.synchronize()
     single_s = time.perf_counter() - t0
-    for op in ops:
-        op.close()
     value = reps * points / elapsed
     single = {"single_walk_path": {"value": points / single_s, "ms": 1e3 * single_s},
               "speedup_vs_single_walks": value / (points / single_s),
               "bitwise_equal_to_single_walks_sampled": equal} if compare else {}
+    # single-precision values, same batch
+    outs32 = [torch.empty_like(o) for o in outs]
+    for op in ops:
+        op.set_precision(True)
+    items32 = [(op, r, w.t0, w.dt, w.n_steps, o, None)
+               for op, r, w, o in zip(ops, r0, wls, outs32)]
+    qsw.batch_propagate(items32, workspace=ws)
+    e32, ms32, by32, s32 = timed(items32)
+    diff = max(float((a - b).abs().max().item()) for a, b in zip(outs32, outs))
+    for op in ops:
+        op.close()
     return {"metric": "instance-points/s", "value": value, "unit": "points/s",
             "workload": "64 ER walks, N~logU[32,512], p=8/N, 4 basis states each, "
                         "t=0..20 in 100 steps", "walks": len(wls), "rhs": 4, "points": points,
-            "ms_per_batch": 1e3 * elapsed / reps, "build_ms": 1e3 * build_s,
-            "cycles": st["cycles"], "products": st["products"],
-            "workspace_gb": st["workspace_bytes"] / 1e9, **single}
+            "ms_per_batch": 1e3 * elapsed / reps, "device_ms_per_batch": dev_ms / reps,
+            "build_ms": 1e3 * build_s, "cycles": st["cycles"], "products": st["products"],
+            "graphs": st["graphs"], "graph_launches": st["graph_launches"],
+            "launch_shape": {"rounds_of_resident_workgroups": st["rounds"],
+                             "staged": st["staged"]},
+            "roofline": {"bound": "hbm", "kernel": "batch_work_kernel<4>",
+                         "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBPS,
+                         "bytes_basis": "layout bytes of every product (values once for "
+                                        "the 4 columns, 64 bytes per element and column) "
+                                        "over the engine's device time"},
+            "workspace_gb": st["workspace_bytes"] / 1e9, **single,
+            "single_values": {"value": reps * points / e32, "unit": "points/s",
+                              "dtype": "c64 values, f64 vectors",
+                              "ms_per_batch": 1e3 * e32 / reps,
+                              "achieved_gbps": by32 / (ms32 * 1e-3) / 1e9,
+                              "max_abs_diff_vs_double_batch": diff}}
 
 
-def served_leg(torch, qsw, workloads, qps_list, count: int) -> dict:
-    """Continuous batching: `count` walks (N log-uniform in [16, 2048], ER
-    mean degree 6 with 10 % one-way edges, omega ~ U(0,1), 10..200 steps over
-    t in [0, 10], rho0 = |0><0|, populations out) arrive as a Poisson process
-    at each rate in qps_list.  Latency runs from a walk's arrival time to the
-    moment its populations are ready (operator build, queueing and
-    propagation included)."""
+def single_instance_service(torch, qsw, reqs) -> list:
+    """Service time of each request through the plain single-instance FP64
+    path on the same GPU: build the operator, qsw_propagate the grid, gather
+    the populations, synchronise."""
+    dev = torch.device("cuda", 0)
+    times = []
+    for r in reqs:
+        g = r["graph"]
+        rho0 = torch.zeros((g.N, g.N), dtype=torch.complex128, device=dev)
+        rho0[0, 0] = 1.0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        op = qsw.Superop.from_graph(g.N, g.row_ptr, g.col_idx, g.w, r["omega"])
+        out = op.propagate(rho0, 0.0, r["dt"], r["n_steps"])
+        op.populations(out)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        op.close()
+        del out
+    return times
+
+
+def fifo_latencies(arrivals, service) -> np.ndarray:
+    """Latencies of one server taking requests in arrival order with the
+    given service times (the single-instance path has no overlap)."""
+    free = 0.0
+    lat = []
+    for a, sv in zip(arrivals, service):
+        start = max(a, free)
+        free = start + sv
+        lat.append(free - a)
+    return np.array(lat)
+
+
+def served_leg(torch, qsw, workloads, qps_list, seconds: float, min_count: int) -> dict:
+    """Continuous batching: walks (N log-uniform in [16, 2048], ER mean degree
+    6 with 10 % one-way edges, omega ~ U(0,1), 10..200 steps over t in
+    [0, 10], rho0 = |0><0|, populations out) arrive as a Poisson process at
+    each rate in qps_list for about `seconds` (at least `min_count` walks).
+    Latency runs from a walk's arrival time to the moment its populations are
+    ready (operator build, queueing and propagation included).  `backlog` is
+    the number of walks not yet finished when the last one arrived.  The
+    same request stream through the single-instance FP64 path (qsw_propagate
+    per walk, measured service times, one walk at a time in arrival order)
+    gives the baseline."""
     GB = 1 << 30
-    reqs = workloads.served_requests(count)
+    count_max = max(min_count, int(max(qps_list) * seconds))
+    reqs = workloads.served_requests(count_max)
+    # baseline: measured service times of the single-instance path
+    n_base = min(count_max, 48)
+    service = single_instance_service(torch, qsw, reqs[:n_base])
+    base_rate = n_base / sum(service)
     points = []
     for qps in qps_list:
+        count = max(min_count, int(qps * seconds))
         arrivals = workloads.poisson_arrivals(count, qps)
         srv = qsw.Server(96 * GB, 48 * GB, 4096)
         t_arr = {}
         lat = []
         i = 0
+        backlog = None
         t0 = time.perf_counter()
         while len(lat) < count:
             now = time.perf_counter() - t0
@@ -380,6 +459,8 @@ def served_leg(torch, qsw, workloads, qps_list, count: int) -> dict:
                 rid = srv.submit(r["graph"], r["omega"], 0.0, r["dt"], r["n_steps"])
                 t_arr[rid] = arrivals[i]
                 i += 1
+                if i == count:
+                    backlog = count - len(lat)
             running, pending = srv.step(8)
             t_ready = time.perf_counter() - t0
             for rid, _, _, _ in srv.poll():
@@ -390,14 +471,29 @@ def served_leg(torch, qsw, workloads, qps_list, count: int) -> dict:
         st = srv.stats()
         srv.close()
         lat_ms = 1e3 * np.array(lat)
-        points.append({"qps": qps, "walks_per_s": count / wall,
+        half = len(lat_ms) // 2
+        svc = np.array([service[k % n_base] for k in range(count)])
+        base = 1e3 * fifo_latencies(arrivals, svc)
+        points.append({"qps": qps, "walks": count, "walks_per_s": count / wall,
                        "p50_ms": float(np.percentile(lat_ms, 50)),
                        "p99_ms": float(np.percentile(lat_ms, 99)),
-                       "mean_ms": float(lat_ms.mean()), "cycles": st["cycles"],
-                       "build_ms": st["build_ms"]})
+                       "mean_ms": float(lat_ms.mean()),
+                       "p50_first_half_ms": float(np.percentile(lat_ms[:half], 50)),
+                       "p50_second_half_ms": float(np.percentile(lat_ms[half:], 50)),
+                       "backlog_at_last_arrival": backlog, "cycles": st["cycles"],
+                       "build_ms": st["build_ms"],
+                       "single_instance": {
+                           "walks_per_s": count / max(arrivals[-1] + base[-1] / 1e3, 1e-9),
+                           "p50_ms": float(np.percentile(base, 50)),
+                           "p99_ms": float(np.percentile(base, 99))}})
     return {"metric": "walks/s", "workload": "N~logU[16,2048] ER deg 6 (10% one-way), "
             "omega~U(0,1), 10..200 steps over t=0..10, rho0=|0><0|, populations out",
-            "walks_per_point": count, "points": points}
+            "seconds_per_rate": seconds, "points": points,
+            "single_instance_path": {
+                "walks_per_s": base_rate, "sampled_walks": n_base,
+                "note": "qsw_propagate per walk (build + propagate + populations, FP64), "
+                        "one at a time; latencies from its measured service times in "
+                        "arrival order"}}
 
 
 def main() -> int:
@@ -423,7 +519,9 @@ def main() -> int:
                     help="skip timing the batched walks one density matrix at a time")
     ap.add_argument("--no-serve", action="store_true", help="skip the continuous-batching leg")
     ap.add_argument("--serve-qps", default="2,4,8", help="arrival rates of the serving leg")
-    ap.add_argument("--serve-count", type=int, default=32, help="walks per serving rate")
+    ap.add_argument("--serve-seconds", type=float, default=12.0,
+                    help="arrival time span of each serving rate")
+    ap.add_argument("--serve-count", type=int, default=24, help="least walks per serving rate")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the batched and "
@@ -549,7 +647,7 @@ def main() -> int:
     if not args.no_serve:
         result["served"] = served_leg(torch, qsw, workloads,
                                       [float(x) for x in args.serve_qps.split(",")],
-                                      args.serve_count)
+                                      args.serve_seconds, args.serve_count)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_steps,
                                               args.cpu_one_thread_steps)

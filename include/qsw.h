@@ -422,6 +422,15 @@ typedef struct {
     int32_t live;        /* walks admitted and not finished */
     int32_t nonfinite;   /* 1 once any norm was NaN or infinite */
     double ms;           /* device time of the last qsw_engine_run */
+    double bytes;        /* algorithmic bytes of the finished walks' products: per product
+                            each stored entry's column and value, the block-shared entries,
+                            row data, the diagonal per row, and 64 bytes per element and
+                            right-hand side (x, the term, the accumulator read and written) */
+    int64_t graphs;      /* chunk graphs captured (a walk finishing or joining changes them) */
+    int64_t graph_launches; /* chunk graphs launched (one per chunk of cycles) */
+    int32_t rounds;      /* launch shape in use: work-launch grid of `rounds` x the
+                            resident workgroups (at most one wave per block) */
+    int32_t staged;      /*   and rho-row staging in LDS on (1) or off (0) */
 } qsw_engine_stats_t;
 
 /* Device bytes one walk takes in an engine with `rhs` (1, 2 or 4)
@@ -477,7 +486,7 @@ typedef struct {
     int64_t cache_hits, cache_misses, evictions;
     int64_t cycles, products;
     int64_t cache_bytes;     /* device bytes of the cached operators */
-    double build_ms;         /* host time spent building operators */
+    double build_ms;         /* builder-thread time spent building operators */
 } qsw_server_stats_t;
 
 /*
@@ -485,21 +494,28 @@ typedef struct {
  * all running in one batch engine (qsw_engine_*) over an arena of
  * arena_bytes that the server allocates now.  Operators are cached on the
  * device under cache_bytes, keyed by (N, graph CSR, omega, gamma, flags);
- * unused ones are evicted least recently used first.  All work goes to
- * hip_stream.
+ * unused ones are evicted least recently used first.  The walks' work goes
+ * to hip_stream; operator builds run on a stream of the server's own that
+ * does not wait for the legacy default stream.
  */
 qsw_status_t qsw_server_create(size_t arena_bytes, size_t cache_bytes, int32_t max_walks,
                                void *hip_stream, qsw_server_t *out);
 
 /*
  * Queue a walk: the graph and options as for qsw_superop_build (host CSR,
- * read during the call; the operator is built now unless cached), rho0
- * (device, N*N complex128), the grid t0 + k dt, k = 0..n_steps, and device
- * outputs out ((n_steps+1) x N*N complex128) and/or pops ((n_steps+1) x N
- * doubles), either may be NULL.  rho0 and the outputs must stay alive until
- * the walk is reported done.  The walk joins the engine as soon as its work
- * vectors fit (walks are admitted in arrival order); QSW_ERR_OOM when they
- * could not fit even in an empty arena.
+ * copied during the call), rho0 (device, N*N complex128), the grid t0 + k dt,
+ * k = 0..n_steps, and device outputs out ((n_steps+1) x N*N complex128)
+ * and/or pops ((n_steps+1) x N doubles), either may be NULL.  rho0 and the
+ * outputs must stay alive until the walk is reported done.  An operator not
+ * in the cache is built by the server's builder thread on its own stream
+ * (so walks on the device keep advancing), once the cache budget has room
+ * for it: before the build its size counts as an upper bound from the graph,
+ * afterwards as the handle's size.  The walk joins the engine as soon as its
+ * operator is ready and its work vectors fit; walks with ready operators are
+ * admitted in arrival order.  QSW_ERR_OOM when the vectors could not fit
+ * even in an empty arena (reported here for a cached operator, else by the
+ * qsw_server_step that sees the build finish, which also completes the
+ * request).
  */
 qsw_status_t qsw_server_submit(qsw_server_t s, int32_t N, const int64_t *row_ptr,
                                const int32_t *col_idx, const double *w, double omega,
@@ -507,8 +523,11 @@ qsw_status_t qsw_server_submit(qsw_server_t s, int32_t N, const int64_t *row_ptr
                                double dt, int32_t n_steps, void *out, void *pops,
                                int64_t *request);
 
-/* Run up to max_cycles engine cycles, collect finished walks and admit
- * waiting ones; reports how many run and wait.  Synchronous. */
+/* Take finished operator builds, run up to max_cycles engine cycles (when
+ * nothing runs and walks wait for builds, first wait up to 5 ms for one),
+ * collect finished walks and admit waiting ones; reports how many run and
+ * wait.  Synchronous.  A failed build finishes its requests (they are
+ * polled as done, with no output) and its status is returned here. */
 qsw_status_t qsw_server_step(qsw_server_t s, int32_t max_cycles, int32_t *running,
                              int32_t *pending);
 

@@ -490,8 +490,7 @@ class Engine:
     def stats(self) -> dict:
         s = _lib.EngineStats()
         _lib.check(_lib.load().qsw_engine_stats(self._e, ctypes.byref(s)), "qsw_engine_stats")
-        return {"cycles": s.cycles, "products": s.products, "live": s.live,
-                "nonfinite": bool(s.nonfinite), "ms": s.ms}
+        return _engine_stats_dict(s)
 
     def close(self):
         if getattr(self, "_e", None):
@@ -503,6 +502,12 @@ class Engine:
             self.close()
         except Exception:
             pass
+
+
+def _engine_stats_dict(s) -> dict:
+    return {"cycles": s.cycles, "products": s.products, "live": s.live,
+            "nonfinite": bool(s.nonfinite), "ms": s.ms, "bytes": s.bytes, "graphs": s.graphs,
+            "graph_launches": s.graph_launches, "rounds": s.rounds, "staged": bool(s.staged)}
 
 
 def batch_propagate(walks, rhs=None, workspace=None):
@@ -535,8 +540,7 @@ def batch_propagate(walks, rhs=None, workspace=None):
                                    _stream(dev), ctypes.byref(st_out))
     if st != 5:
         _lib.check(st, "qsw_batch_propagate")
-    return {"cycles": st_out.cycles, "products": st_out.products, "live": st_out.live,
-            "nonfinite": bool(st_out.nonfinite), "ms": st_out.ms, "workspace_bytes": need}
+    return {**_engine_stats_dict(st_out), "workspace_bytes": need}
 
 
 # ------------------------------------------------------- demoralisation

@@ -78,7 +78,10 @@ class Walk(ctypes.Structure):
 
 class EngineStats(ctypes.Structure):
     _fields_ = [("cycles", ctypes.c_int64), ("products", ctypes.c_int64),
-                ("live", ctypes.c_int32), ("nonfinite", ctypes.c_int32), ("ms", ctypes.c_double)]
+                ("live", ctypes.c_int32), ("nonfinite", ctypes.c_int32), ("ms", ctypes.c_double),
+                ("bytes", ctypes.c_double), ("graphs", ctypes.c_int64),
+                ("graph_launches", ctypes.c_int64), ("rounds", ctypes.c_int32),
+                ("staged", ctypes.c_int32)]
 
 
 class ServerStats(ctypes.Structure):

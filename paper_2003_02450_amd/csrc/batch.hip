@@ -9,6 +9,15 @@
 // the GPU alone, each walk's matrix is read once for all its right-hand
 // sides, and the host only waits between chunks of cycles.
 //
+// A chunk of cycles (kChunk control + work launch pairs) is captured once in
+// a HIP graph and replayed while the running walks and the launch shape stay
+// the same (a walk finishing or joining changes the arguments and the graph
+// is captured again), so the host enqueues one graph launch per chunk.  The
+// launch shape (workgroups per work launch and rho-row staging) is tuned on
+// the first chunks of a run for the batch's key (right-hand sides, value
+// precision, largest graph order, entries per row) and remembered for the
+// process; no choice changes any sum, so results are bitwise the same.
+//
 // Device memory is the caller's arena: the tables at its start, then the
 // walks' vectors, handed out first-fit and returned when a walk finishes.
 // A walk is admitted only when its vectors fit (qsw_engine_submit returns
@@ -20,6 +29,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <new>
 #include <vector>
 
@@ -162,8 +172,21 @@ struct qsw_engine_s {
   int64_t *h_blk = nullptr;
   BatchInst *h_inst = nullptr;   // one entry (staging for a submit)
   int64_t blkmap_cap = 0;        // entries of the block map in the arena
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
   qsw_engine_stats_t stats{};
+  std::vector<double> wbytes;    // per slot: algorithmic bytes of one product
+  std::vector<int> f32;          // per slot: single-precision values
+  std::vector<double> went;      // per slot: stored entries of the walk's layout
+  // chunk graph: captured on a private stream, launched on `stream`
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  BatchArgs gargs{};
+  int ggrid = 0, gchunk = 0;
+  bool use_graph = true;
+  // launch shape: work-launch grid = rounds x resident workgroups (at most
+  // one wave per block), rho-row staging on or off
+  int rounds = 1, stage = 1;
+  bool tuned = false;
 };
 
 namespace {
@@ -178,6 +201,10 @@ void destroy_engine(qsw_engine_s *e) {
   if (e->h_inst) (void)hipHostFree(e->h_inst);
   if (e->ev0) (void)hipEventDestroy(e->ev0);
   if (e->ev1) (void)hipEventDestroy(e->ev1);
+  if (e->ev_t0) (void)hipEventDestroy(e->ev_t0);
+  if (e->ev_t1) (void)hipEventDestroy(e->ev_t1);
+  if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
+  if (e->cap_stream) (void)hipStreamDestroy(e->cap_stream);
   delete e;
 }
 
@@ -201,7 +228,7 @@ qsw_status_t upload_active(qsw_engine_s *e) {
     const int64_t need = (int64_t)e->rhs * e->N[b] * (int64_t)sizeof(double2);
     if (need <= (int64_t)kStageMaxBytes && need > sb) sb = need;
   }
-  e->args.stage_bytes = env_int("QSW_STAGE", 1) ? (int32_t)sb : 0;
+  e->args.stage_bytes = (e->stage && env_int("QSW_STAGE", 1)) ? (int32_t)sb : 0;
   if (acc > e->blkmap_cap) return QSW_ERR_STATE;  // admission reserves the map entries
   if (!e->act.empty())
     HIP_TRY(hipMemcpyAsync(e->arena + e->tab.act, e->h_act, sizeof(int32_t) * e->act.size(),
@@ -233,6 +260,7 @@ qsw_status_t collect(qsw_engine_s *e) {
     if (!e->running[b] || !e->h_ctl[b].done) continue;
     e->running[b] = 0;
     e->stats.products += e->h_ctl[b].products;
+    e->stats.bytes += (double)e->h_ctl[b].products * e->wbytes[b];
     e->finished.push_back(e->ticket[b]);
     e->ticket[b] = -1;
     e->pool.give(e->off[b] - e->pool_base, e->bytes[b]);
@@ -244,6 +272,94 @@ qsw_status_t collect(qsw_engine_s *e) {
   e->stats.live = live;
   if (changed) return upload_active(e);
   return QSW_OK;
+}
+
+// Candidate launch shapes {rounds of resident workgroups, staging}.
+constexpr int kTuneCount = 4;
+constexpr int kTuneShapes[kTuneCount][2] = {{1, 1}, {2, 1}, {1, 0}, {2, 0}};
+
+struct TuneKey {
+  int rhs = 0, f32 = 0, nlog = 0, epr = 0;
+  bool operator<(const TuneKey &o) const {
+    return std::tie(rhs, f32, nlog, epr) < std::tie(o.rhs, o.f32, o.nlog, o.epr);
+  }
+};
+
+std::map<TuneKey, std::pair<int, int>> &tune_cache() {
+  static std::map<TuneKey, std::pair<int, int>> c;
+  return c;
+}
+
+// The batch's key: right-hand sides, single-precision values on any walk,
+// log2 of the largest graph order, entries per row of all running walks.
+TuneKey tune_key(const qsw_engine_s *e) {
+  TuneKey k;
+  k.rhs = e->rhs;
+  int32_t nmax = 1;
+  double ent = 0.0, rows = 0.0;
+  for (int32_t b : e->act) {
+    nmax = std::max(nmax, e->N[b]);
+    k.f32 |= e->f32[b];
+    ent += e->went[b];
+    rows += (double)e->N[b] * e->N[b];
+  }
+  k.nlog = (int)std::ceil(std::log2((double)nmax));
+  k.epr = rows > 0 ? (int)std::lround(ent / rows) : 0;
+  return k;
+}
+
+void set_shape(qsw_engine_s *e, int rounds, int stage) {
+  e->rounds = rounds;
+  e->stage = stage;
+}
+
+// kChunk cycles (or fewer): control + work launch pairs, through the chunk
+// graph when possible.  The graph is captured again when the arguments or
+// the shape changed; any capture failure falls back to direct launches.
+hipError_t run_chunk(qsw_engine_s *e, int grid, int chunk) {
+  if (e->use_graph) {
+    const bool same = e->gexec && e->ggrid == grid && e->gchunk == chunk &&
+                      std::memcmp(&e->gargs, &e->args, sizeof(BatchArgs)) == 0;
+    if (!same) {
+      if (e->gexec) {
+        (void)hipGraphExecDestroy(e->gexec);
+        e->gexec = nullptr;
+      }
+      hipError_t err = hipStreamBeginCapture(e->cap_stream, hipStreamCaptureModeThreadLocal);
+      if (err == hipSuccess) {
+        for (int c = 0; c < chunk && err == hipSuccess; ++c) {
+          err = launch_batch_control(e->args, e->cap_stream);
+          if (err == hipSuccess) err = launch_batch_work(e->args, e->rhs, grid, e->cap_stream);
+        }
+        hipGraph_t graph = nullptr;
+        const hipError_t end = hipStreamEndCapture(e->cap_stream, &graph);
+        if (err == hipSuccess) err = end;
+        if (err == hipSuccess) err = hipGraphInstantiate(&e->gexec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+      }
+      if (err != hipSuccess || !e->gexec) {
+        (void)hipGetLastError();
+        if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
+        e->gexec = nullptr;
+        e->use_graph = false;  // direct launches from now on
+      } else {
+        e->gargs = e->args;
+        e->ggrid = grid;
+        e->gchunk = chunk;
+        e->stats.graphs += 1;
+      }
+    }
+    if (e->use_graph) {
+      e->stats.graph_launches += 1;
+      return hipGraphLaunch(e->gexec, e->stream);
+    }
+  }
+  for (int c = 0; c < chunk; ++c) {
+    hipError_t err = launch_batch_control(e->args, e->stream);
+    if (err == hipSuccess) err = launch_batch_work(e->args, e->rhs, grid, e->stream);
+    if (err != hipSuccess) return err;
+  }
+  return hipSuccess;
 }
 
 }  // namespace
@@ -299,13 +415,19 @@ qsw_status_t qsw_engine_create(int32_t max_walks, int32_t rhs, void *arena, size
   e->N.assign(max_walks, 0);
   e->deadline.assign(max_walks, 0);
   e->running.assign(max_walks, 0);
+  e->wbytes.assign(max_walks, 0.0);
+  e->f32.assign(max_walks, 0);
+  e->went.assign(max_walks, 0.0);
+  e->use_graph = env_int("QSW_BATCH_GRAPH", 1) != 0;
+  if (hipStreamCreate(&e->cap_stream) != hipSuccess) return fail(QSW_ERR_DEVICE);
   if (hipHostMalloc((void **)&e->h_ctl, sizeof(BatchCtl) * (size_t)max_walks) != hipSuccess ||
       hipHostMalloc((void **)&e->h_rb, sizeof(Readback)) != hipSuccess ||
       hipHostMalloc((void **)&e->h_act, sizeof(int32_t) * ((size_t)max_walks + 1)) != hipSuccess ||
       hipHostMalloc((void **)&e->h_blk, sizeof(int64_t) * ((size_t)max_walks + 1)) != hipSuccess ||
       hipHostMalloc((void **)&e->h_inst, sizeof(BatchInst)) != hipSuccess)
     return fail(QSW_ERR_OOM);
-  if (hipEventCreate(&e->ev0) != hipSuccess || hipEventCreate(&e->ev1) != hipSuccess)
+  if (hipEventCreate(&e->ev0) != hipSuccess || hipEventCreate(&e->ev1) != hipSuccess ||
+      hipEventCreate(&e->ev_t0) != hipSuccess || hipEventCreate(&e->ev_t1) != hipSuccess)
     return fail(QSW_ERR_DEVICE);
   BatchArgs &A = e->args;
   A.inst = (const BatchInst *)(e->arena + tab.inst);
@@ -345,10 +467,10 @@ void qsw_engine_destroy(qsw_engine_t e) {
 
 qsw_status_t qsw_engine_submit(qsw_engine_t e, const qsw_walk_t *w, int64_t *ticket) {
   if (!e || !w || !ticket) return QSW_ERR_ARG;
-  if (w->op->device != e->device) return QSW_ERR_STATE;
   WalkPlan W;
-  qsw_status_t st = plan_walk(w, e->rhs, W);
+  qsw_status_t st = plan_walk(w, e->rhs, W);  // checks w->op
   if (st != QSW_OK) return st;
+  if (w->op->device != e->device) return QSW_ERR_STATE;
   int32_t b = -1;
   for (int32_t i = 0; i < e->cap; ++i)
     if (e->ticket[i] < 0) {
@@ -428,6 +550,19 @@ qsw_status_t qsw_engine_submit(qsw_engine_t e, const qsw_walk_t *w, int64_t *tic
   e->off[b] = e->pool_base + off;
   e->bytes[b] = W.total;
   e->nwb[b] = h->nwb;
+  {
+    // one product: each stored entry's column and value, the block-shared
+    // entries, row data and the diagonal per row, and for every column x
+    // read, the term written and the accumulator read and written
+    const bool f32 = I.f32 != 0, split = I.split != 0;
+    const double entry = split ? (f32 ? 8.0 : 12.0) : (f32 ? 12.0 : 20.0);
+    const double diag = split ? (f32 ? 8.0 : 16.0) : 0.0;
+    e->wbytes[b] = entry * (double)h->wentries + 16.0 * (double)h->wshared +
+                   8.0 * (double)(h->n + 1) + diag * (double)h->n +
+                   64.0 * (double)e->rhs * (double)h->n;
+    e->f32[b] = f32 ? 1 : 0;
+    e->went[b] = (double)h->wentries;
+  }
   e->N[b] = h->N;
   e->deadline[b] = e->stats.cycles + W.max_cycles + kChunk;
   e->running[b] = 1;
@@ -441,19 +576,55 @@ qsw_status_t qsw_engine_run(qsw_engine_t e, int32_t max_cycles, int32_t *live) {
   if (!g.ok) return QSW_ERR_DEVICE;
   HIP_TRY(hipEventRecord(e->ev0, e->stream));
   int32_t done_cycles = 0;
+  // tuning: one chunk per candidate shape, timed on the stream, while the
+  // batch's key has no remembered shape
+  TuneKey key{};
+  int cand = -1;
+  std::vector<double> cand_us;
+  if (!e->tuned && env_int("QSW_BATCH_TUNE", 1) != 0 && !e->act.empty()) {
+    key = tune_key(e);
+    auto it = tune_cache().find(key);
+    if (it != tune_cache().end()) {
+      set_shape(e, it->second.first, it->second.second);
+      e->tuned = true;
+    } else {
+      cand = 0;
+      set_shape(e, kTuneShapes[0][0], kTuneShapes[0][1]);
+    }
+  }
   while (done_cycles < max_cycles && !e->act.empty()) {
     const int64_t tb = total_blocks(e);
     const int64_t want = (tb + kBlockThreads / 64 - 1) / (kBlockThreads / 64);
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)std::max(e->resident, 1)));
+    const int64_t res = (int64_t)std::max(e->resident, 1) * e->rounds;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, res));
     const int chunk = std::min(kChunk, max_cycles - done_cycles);
-    for (int c = 0; c < chunk; ++c) {
-      HIP_TRY(launch_batch_control(e->args, e->stream));
-      HIP_TRY(launch_batch_work(e->args, e->rhs, grid, e->stream));
-    }
+    if (cand >= 0) HIP_TRY(hipEventRecord(e->ev_t0, e->stream));
+    HIP_TRY(run_chunk(e, grid, chunk));
+    if (cand >= 0) HIP_TRY(hipEventRecord(e->ev_t1, e->stream));
     done_cycles += chunk;
     e->stats.cycles += chunk;
     qsw_status_t st = collect(e);
     if (st != QSW_OK) return st;
+    if (cand >= 0) {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, e->ev_t0, e->ev_t1));
+      // per block of work, so that shrinking batches compare fairly
+      cand_us.push_back(1e3 * ms / (double)std::max<int64_t>(1, tb));
+      ++cand;
+      if (cand < kTuneCount && !e->act.empty()) {
+        set_shape(e, kTuneShapes[cand][0], kTuneShapes[cand][1]);
+      } else {
+        const int best = (int)(std::min_element(cand_us.begin(), cand_us.end()) - cand_us.begin());
+        set_shape(e, kTuneShapes[best][0], kTuneShapes[best][1]);
+        tune_cache()[key] = {e->rounds, e->stage};
+        e->tuned = true;
+        cand = -1;
+      }
+      if (e->stage != (e->args.stage_bytes > 0 ? 1 : 0)) {
+        st = upload_active(e);  // staging changed: new LDS size
+        if (st != QSW_OK) return st;
+      }
+    }
     for (int32_t b : e->act)
       if (e->stats.cycles > e->deadline[b]) return QSW_ERR_STATE;  // cannot happen
   }
@@ -462,6 +633,8 @@ qsw_status_t qsw_engine_run(qsw_engine_t e, int32_t max_cycles, int32_t *live) {
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, e->ev0, e->ev1));
   e->stats.ms = ms;
+  e->stats.rounds = e->rounds;
+  e->stats.staged = e->stage;
   if (live) *live = e->stats.live;
   return e->stats.nonfinite ? QSW_ERR_NONFINITE : QSW_OK;
 }

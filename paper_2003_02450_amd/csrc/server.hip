@@ -9,15 +9,27 @@
 //  * Admission: pending walks are admitted in arrival order, each when the
 //    engine arena has room for its work vectors (the engine refuses it
 //    otherwise); an admitted walk never waits for memory again.
+//  * Operators are built off the serving loop: a cache miss queues the build
+//    for a builder thread, which runs it on its own (non-blocking) stream,
+//    so walks already on the device keep advancing meanwhile; the walk waits
+//    in the queue until its operator is ready, without holding back walks
+//    behind it whose operators are.
+//  * Operator memory counts against the cache budget before it is built (an
+//    upper bound from the graph, replaced by the handle's size once built):
+//    a build that would exceed the budget while every cached operator is in
+//    use waits until walks finish and release some.
 //  * Every walk's result is bitwise what it would be alone: the engine keeps
 //    walks independent.
 #include "handle.h"
 
 #include <chrono>
+#include <condition_variable>
 #include <cstring>
 #include <deque>
 #include <list>
+#include <mutex>
 #include <new>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -58,14 +70,17 @@ struct OpKey {
 struct CachedOp {
   OpKey key;
   uint64_t hash = 0;
-  qsw_superop_t op = nullptr;
-  size_t bytes = 0;
-  int users = 0;  // walks pending or running on it
+  qsw_superop_t op = nullptr;  // null until built
+  size_t bytes = 0;            // device bytes (an upper bound until built)
+  int users = 0;               // walks pending or running on it
+  int state = 0;               // 0 built, 1 waiting for cache room, 2 building, 3 failed
+  qsw_status_t error = QSW_OK;
 };
 
 struct Request {
   int64_t id = 0;
   uint64_t hash = 0;
+  CachedOp *cop = nullptr;
   qsw_walk_t walk{};
   double t_submit = 0.0, t_admit = 0.0, t_done = 0.0;
   int64_t ticket = -1;
@@ -87,16 +102,37 @@ size_t op_bytes(const qsw_superop_s *h) {
   return b;
 }
 
+// Upper bound of op_bytes before the build, from the graph alone: the
+// undirected companion has at most 2E off-diagonal entries for E arcs, so L
+// has at most 2N(2E) + N^2 + E + N entries (dephasing included).
+size_t op_bytes_bound(int32_t N, int64_t E) {
+  const double n = (double)N * N;
+  const double nnz = 2.0 * N * 2.0 * (double)E + n + (double)E + N;
+  return (size_t)(64.0 * nnz + 160.0 * n + 4096.0);
+}
+
 }  // namespace
 
 struct qsw_server_s {
   int device = -1;
   hipStream_t stream = nullptr;
+  // builder thread: jobs in, finished builds out (under mu)
+  hipStream_t build_stream = nullptr;
+  std::thread builder;
+  std::mutex mu;
+  std::condition_variable cv_job, cv_done;
+  std::deque<CachedOp *> jobs;
+  std::vector<std::pair<CachedOp *, qsw_superop_t>> built;
+  std::vector<std::pair<CachedOp *, qsw_status_t>> failed;
+  std::vector<double> build_ms;
+  int in_flight = 0;
+  bool stop = false;
   void *arena = nullptr;
   qsw_engine_t engine = nullptr;
   size_t cache_budget = 0, cache_used = 0;
   std::unordered_multimap<uint64_t, CachedOp *> cache;  // hash -> entries
   std::list<CachedOp *> lru;                            // entries, newest first
+  std::deque<CachedOp *> waiting;   // operators waiting for cache room, first come first
   std::deque<Request *> pending;
   std::unordered_map<int64_t, Request *> by_id;
   std::unordered_map<int64_t, Request *> by_ticket;
@@ -116,7 +152,7 @@ void evict_unused(qsw_server_s *s, size_t need) {
   while (s->cache_used + need > s->cache_budget) {
     CachedOp *victim = nullptr;
     for (auto it = s->lru.rbegin(); it != s->lru.rend(); ++it)
-      if ((*it)->users == 0) {
+      if ((*it)->users == 0 && (*it)->state == 0) {
         victim = *it;
         break;
       }
@@ -142,10 +178,17 @@ CachedOp *find_op(qsw_server_s *s, uint64_t hash, const OpKey &key) {
   return nullptr;
 }
 
-// Admit pending walks in arrival order while the engine takes them.
+// Admit pending walks in arrival order while the engine takes them; a walk
+// whose operator is still being built is passed over (it does not hold the
+// walks behind it back), a walk that does not fit stops the admission.
 qsw_status_t admit(qsw_server_s *s) {
-  while (!s->pending.empty()) {
-    Request *r = s->pending.front();
+  for (auto it = s->pending.begin(); it != s->pending.end();) {
+    Request *r = *it;
+    if (r->cop->state != 0) {
+      ++it;
+      continue;
+    }
+    r->walk.op = r->cop->op;
     int64_t ticket = -1;
     const qsw_status_t st = qsw_engine_submit(s->engine, &r->walk, &ticket);
     if (st == QSW_ERR_OOM) break;  // waits until running walks free space
@@ -154,15 +197,132 @@ qsw_status_t admit(qsw_server_s *s) {
     r->state = 1;
     r->t_admit = now_ms();
     s->by_ticket[ticket] = r;
-    s->pending.pop_front();
+    it = s->pending.erase(it);
   }
   return QSW_OK;
 }
 
-CachedOp *owner_of(qsw_server_s *s, qsw_superop_t op) {
-  for (CachedOp *c : s->lru)
-    if (c->op == op) return c;
-  return nullptr;
+// The builder thread: builds queued operators on its own stream.
+void builder_main(qsw_server_s *s) {
+  (void)hipSetDevice(s->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    s->cv_job.wait(lk, [s] { return s->stop || !s->jobs.empty(); });
+    if (s->jobs.empty()) return;  // stop requested and nothing queued
+    CachedOp *c = s->jobs.front();
+    s->jobs.pop_front();
+    lk.unlock();
+    const OpKey &k = c->key;  // not modified while the build is in flight
+    const double t0 = now_ms();
+    qsw_superop_t op = nullptr;
+    const qsw_status_t st =
+        qsw_superop_build(k.N, k.rp.data(), k.col.empty() ? nullptr : k.col.data(),
+                          k.w.empty() ? nullptr : k.w.data(), k.omega, k.gamma, k.flags,
+                          s->build_stream, &op);
+    const double ms = now_ms() - t0;
+    lk.lock();
+    if (st == QSW_OK)
+      s->built.emplace_back(c, op);
+    else
+      s->failed.emplace_back(c, st);
+    s->build_ms.push_back(ms);
+    --s->in_flight;
+    s->cv_done.notify_all();
+  }
+}
+
+// Queue the builds of waiting operators, first come first, while the cache
+// budget allows them (evicting unused operators first); an operator larger
+// than the whole budget is built once nothing else is cached.
+void start_builds(qsw_server_s *s) {
+  while (!s->waiting.empty()) {
+    CachedOp *c = s->waiting.front();
+    evict_unused(s, c->bytes);
+    if (s->cache_used + c->bytes > s->cache_budget && s->cache_used > 0) break;
+    s->waiting.pop_front();
+    c->state = 2;
+    s->cache_used += c->bytes;
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->jobs.push_back(c);
+    ++s->in_flight;
+    s->cv_job.notify_one();
+  }
+}
+
+// Finish a request without running it (its operator failed to build, or its
+// vectors can never fit the arena).
+void drop_request(qsw_server_s *s, Request *r) {
+  r->state = 2;
+  r->t_done = now_ms();
+  --r->cop->users;
+  s->done_ids.push_back(r->id);
+  ++s->stats.completed;
+  for (auto it = s->pending.begin(); it != s->pending.end(); ++it)
+    if (*it == r) {
+      s->pending.erase(it);
+      break;
+    }
+}
+
+// Take the builder's results: built operators become usable (their size
+// replaces the bound), failed ones finish their requests.  Returns the first
+// build error, if any.
+qsw_status_t drain_builds(qsw_server_s *s) {
+  std::vector<std::pair<CachedOp *, qsw_superop_t>> built;
+  std::vector<std::pair<CachedOp *, qsw_status_t>> failed;
+  std::vector<double> ms;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    built.swap(s->built);
+    failed.swap(s->failed);
+    ms.swap(s->build_ms);
+  }
+  for (double m : ms) s->stats.build_ms += m;
+  qsw_status_t err = QSW_OK;
+  for (auto &bc : built) {
+    CachedOp *c = bc.first;
+    c->op = bc.second;
+    const size_t actual = op_bytes(c->op);
+    s->cache_used = s->cache_used - c->bytes + actual;
+    c->bytes = actual;
+    c->state = 0;
+  }
+  for (auto &fc : failed) {
+    CachedOp *c = fc.first;
+    c->state = 3;
+    c->error = fc.second;
+    if (err == QSW_OK) err = fc.second;
+  }
+  // requests on failed operators, or too large for the arena, finish now
+  std::vector<Request *> drop;
+  for (Request *r : s->pending) {
+    if (r->cop->state == 3) {
+      drop.push_back(r);
+    } else if (r->cop->state == 0) {
+      r->walk.op = r->cop->op;
+      const size_t need = qsw_walk_bytes(&r->walk, 1);
+      if (need == 0 || need > engine_pool_bytes(s->engine)) {
+        if (err == QSW_OK) err = need == 0 ? QSW_ERR_ARG : QSW_ERR_OOM;
+        drop.push_back(r);
+      }
+    }
+  }
+  for (Request *r : drop) drop_request(s, r);
+  // failed operators nobody waits for leave the cache
+  for (auto &fc : failed) {
+    CachedOp *c = fc.first;
+    if (c->users > 0) continue;
+    s->lru.remove(c);
+    auto range = s->cache.equal_range(c->hash);
+    for (auto it = range.first; it != range.second; ++it)
+      if (it->second == c) {
+        s->cache.erase(it);
+        break;
+      }
+    s->cache_used -= c->bytes;
+    delete c;
+  }
+  return err;
 }
 
 }  // namespace
@@ -193,6 +353,23 @@ qsw_status_t qsw_server_create(size_t arena_bytes, size_t cache_bytes, int32_t m
     delete s;
     return st;
   }
+  // builds overlap the engine's work: a stream that does not wait for the
+  // legacy default stream (default priority)
+  if (hipStreamCreateWithFlags(&s->build_stream, hipStreamNonBlocking) != hipSuccess) {
+    qsw_engine_destroy(s->engine);
+    (void)hipFree(s->arena);
+    delete s;
+    return QSW_ERR_DEVICE;
+  }
+  try {
+    s->builder = std::thread(builder_main, s);
+  } catch (...) {
+    (void)hipStreamDestroy(s->build_stream);
+    qsw_engine_destroy(s->engine);
+    (void)hipFree(s->arena);
+    delete s;
+    return QSW_ERR_OOM;
+  }
   *out = s;
   return QSW_OK;
 }
@@ -200,11 +377,22 @@ qsw_status_t qsw_server_create(size_t arena_bytes, size_t cache_bytes, int32_t m
 void qsw_server_destroy(qsw_server_t s) {
   if (!s) return;
   DeviceGuard g(s->device);
+  {
+    // queued builds are dropped; the one in flight finishes
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->in_flight -= (int)s->jobs.size();
+    s->jobs.clear();
+    s->stop = true;
+    s->cv_job.notify_all();
+  }
+  if (s->builder.joinable()) s->builder.join();
+  (void)drain_builds(s);
   qsw_engine_destroy(s->engine);
   for (CachedOp *c : s->lru) {
-    qsw_superop_destroy(c->op);
+    if (c->op) qsw_superop_destroy(c->op);
     delete c;
   }
+  if (s->build_stream) (void)hipStreamDestroy(s->build_stream);
   for (auto &kv : s->by_id) delete kv.second;
   if (s->arena) (void)hipFree(s->arena);
   delete s;
@@ -241,26 +429,17 @@ qsw_status_t qsw_server_submit(qsw_server_t s, int32_t N, const int64_t *row_ptr
   if (c) {
     ++s->stats.cache_hits;
   } else {
-    qsw_superop_t op = nullptr;
-    const double tb = now_ms();
-    const qsw_status_t st = qsw_superop_build(N, row_ptr, col_idx, w, omega, gamma, flags,
-                                              s->stream, &op);
-    if (st != QSW_OK) return st;
-    s->stats.build_ms += now_ms() - tb;
+    // built by the builder thread once the cache has room for it
     ++s->stats.cache_misses;
     c = new (std::nothrow) CachedOp();
-    if (!c) {
-      qsw_superop_destroy(op);
-      return QSW_ERR_OOM;
-    }
+    if (!c) return QSW_ERR_OOM;
     c->key = std::move(key);
     c->hash = f.h;
-    c->op = op;
-    c->bytes = op_bytes(op);
-    evict_unused(s, c->bytes);  // may leave the cache over budget while all are in use
+    c->bytes = op_bytes_bound(N, E);
+    c->state = 1;
     s->cache.emplace(f.h, c);
     s->lru.push_front(c);
-    s->cache_used += c->bytes;
+    s->waiting.push_back(c);
   }
   touch(s, c);
   ++c->users;
@@ -271,6 +450,7 @@ qsw_status_t qsw_server_submit(qsw_server_t s, int32_t N, const int64_t *row_ptr
   }
   r->id = s->next_id++;
   r->hash = f.h;
+  r->cop = c;
   r->walk.op = c->op;
   r->walk.n0 = 1;
   r->walk.rho0 = rho0;
@@ -280,16 +460,19 @@ qsw_status_t qsw_server_submit(qsw_server_t s, int32_t N, const int64_t *row_ptr
   r->walk.out = out;
   r->walk.pops = pops;
   r->t_submit = t_submit;
-  const size_t need = qsw_walk_bytes(&r->walk, 1);
-  if (need == 0 || need > engine_pool_bytes(s->engine)) {  // bad, or can never fit
-    --c->users;
-    delete r;
-    return need == 0 ? QSW_ERR_ARG : QSW_ERR_OOM;
+  if (c->state == 0) {
+    const size_t need = qsw_walk_bytes(&r->walk, 1);
+    if (need == 0 || need > engine_pool_bytes(s->engine)) {  // bad, or can never fit
+      --c->users;
+      delete r;
+      return need == 0 ? QSW_ERR_ARG : QSW_ERR_OOM;
+    }
   }
   s->by_id[r->id] = r;
   s->pending.push_back(r);
   ++s->stats.submitted;
   *request = r->id;
+  start_builds(s);
   return admit(s);
 }
 
@@ -298,8 +481,30 @@ qsw_status_t qsw_server_step(qsw_server_t s, int32_t max_cycles, int32_t *runnin
   if (!s || max_cycles < 0) return QSW_ERR_ARG;
   DeviceGuard g(s->device);
   if (!g.ok) return QSW_ERR_DEVICE;
+  qsw_status_t build_err = drain_builds(s);
+  start_builds(s);
   qsw_status_t st = admit(s);
   if (st != QSW_OK) return st;
+  qsw_engine_stats_t es0{};
+  (void)qsw_engine_stats(s->engine, &es0);
+  if (es0.live == 0 && !s->pending.empty()) {
+    // nothing runs and every queued walk waits for its operator: wait a
+    // little for a build instead of returning at once
+    bool busy;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      busy = s->in_flight > 0;
+      if (busy && s->built.empty() && s->failed.empty())
+        s->cv_done.wait_for(lk, std::chrono::milliseconds(5));
+    }
+    if (busy) {
+      const qsw_status_t e2 = drain_builds(s);
+      if (build_err == QSW_OK) build_err = e2;
+      start_builds(s);
+      st = admit(s);
+      if (st != QSW_OK) return st;
+    }
+  }
   int32_t live = 0;
   st = qsw_engine_run(s->engine, max_cycles, &live);
   if (st != QSW_OK && st != QSW_ERR_NONFINITE) return st;
@@ -318,11 +523,11 @@ qsw_status_t qsw_server_step(qsw_server_t s, int32_t max_cycles, int32_t *runnin
       r->t_done = t;
       s->done_ids.push_back(r->id);
       ++s->stats.completed;
-      CachedOp *c = owner_of(s, r->walk.op);
-      if (c) --c->users;
+      --r->cop->users;
     }
   } while (cnt == 256);
   evict_unused(s, 0);  // operators the finished walks released, if over budget
+  start_builds(s);     // builds that waited for cache room
   st = admit(s);  // iteration-level admission into the space just freed
   if (st != QSW_OK) return st;
   if (running) *running = live;
@@ -332,7 +537,7 @@ qsw_status_t qsw_server_step(qsw_server_t s, int32_t max_cycles, int32_t *runnin
   s->stats.cycles = es.cycles;
   s->stats.products = es.products;
   s->stats.cache_bytes = (int64_t)s->cache_used;
-  return QSW_OK;
+  return build_err;
 }
 
 qsw_status_t qsw_server_poll(qsw_server_t s, int64_t *requests, double *latency_ms,

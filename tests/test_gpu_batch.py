@@ -150,3 +150,39 @@ def test_single_rhs_engine_and_zero_steps():
         assert np.array_equal(outs[i][:, 0], ref), wl.name
     for op in ops:
         op.close()
+
+
+@pytest.mark.parametrize("graph,tune", [("0", "0"), ("1", "0"), ("1", "1")])
+def test_graph_chunks_and_tuned_shapes_change_nothing(graph, tune, monkeypatch):
+    """Chunk graphs (captured once per set of running walks, replayed per
+    chunk) and every tuned launch shape give bitwise the results of direct
+    launches with the default shape."""
+    monkeypatch.setenv("QSW_BATCH_GRAPH", graph)
+    monkeypatch.setenv("QSW_BATCH_TUNE", tune)
+    wls = workloads.batch64(count=8, n_steps=40)
+    ops, outs, pops, st = _run_batch(wls)
+    assert st["live"] == 0 and not st["nonfinite"]
+    if graph == "1":
+        assert st["graph_launches"] > 0 and 1 <= st["graphs"] <= st["graph_launches"]
+    else:
+        assert st["graph_launches"] == 0
+    assert st["bytes"] > 0
+    monkeypatch.setenv("QSW_BATCH_GRAPH", "0")
+    monkeypatch.setenv("QSW_BATCH_TUNE", "0")
+    _, ref, rpops, _ = _run_batch(wls)
+    for i in range(len(wls)):
+        assert np.array_equal(outs[i], ref[i]) and np.array_equal(pops[i], rpops[i])
+    for op in ops:
+        op.close()
+
+
+def test_tuned_shape_is_remembered_for_the_key(monkeypatch):
+    monkeypatch.setenv("QSW_BATCH_TUNE", "1")
+    wls = workloads.batch64(count=6, n_steps=60)
+    ops1, a, _, st1 = _run_batch(wls)
+    ops2, b, _, st2 = _run_batch(wls)              # same key: the shape is taken, not tuned
+    assert (st1["rounds"], st1["staged"]) == (st2["rounds"], st2["staged"])
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    for op in ops1 + ops2:
+        op.close()

@@ -106,7 +106,42 @@ def test_admission_waits_for_space():
     assert seen_pending and st["completed"] == 5
     for a, b, c in zip(full, slots, tight):
         assert np.array_equal(a, b) and np.array_equal(a, c)
+    # an arena too small for any walk: the operator is built off the serving
+    # loop, and the step that sees the build finish refuses the walk
     srv = qsw.Server(64 << 10, 1 << 30, 4)
-    with pytest.raises(qsw.QswError):
-        srv.submit(reqs[0]["graph"], reqs[0]["omega"], 0.0, reqs[0]["dt"], reqs[0]["n_steps"])
+    rid = srv.submit(reqs[0]["graph"], reqs[0]["omega"], 0.0, reqs[0]["dt"], reqs[0]["n_steps"])
+    with pytest.raises(qsw.QswError, match="QSW_ERR_OOM"):
+        for _ in range(20000):
+            srv.step(1)
+    assert [d[0] for d in srv.poll()] == [rid]
     srv.close()
+
+
+def test_builds_overlap_running_walks():
+    """A walk that arrives while others run has its operator built off the
+    serving loop: the running walks keep stepping (the step calls return while
+    the build is in flight) and every result is bitwise that of the walk alone."""
+    import paper_2003_02450_amd as qsw
+    reqs = _requests(6, 505, n_hi=48)
+    srv = qsw.Server(2 * GB, 2 * GB, 64)
+    first = [srv.submit(r["graph"], r["omega"], 0.0, r["dt"], r["n_steps"]) for r in reqs[:3]]
+    steps_before_late = 0
+    results = {}
+    late = None
+    for _ in range(100000):
+        running, pending = srv.step(2)
+        for rid, lat, pops, _ in srv.poll():
+            results[rid] = pops.cpu().numpy()
+        if late is None and running > 0:
+            late = [srv.submit(r["graph"], r["omega"], 0.0, r["dt"], r["n_steps"])
+                    for r in reqs[3:]]
+        elif late is not None and len(results) < 6:
+            steps_before_late += 1
+        if late is not None and len(results) == 6 and running == 0 and pending == 0:
+            break
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == 6 and st["cache_misses"] == 6 and st["build_ms"] > 0
+    alone = [_serve([r])[0][0] for r in reqs]
+    for rid, a in zip(first + late, alone):
+        assert np.array_equal(results[rid], a)
