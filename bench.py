@@ -518,7 +518,7 @@ def main() -> int:
     ap.add_argument("--no-batch-compare", action="store_true",
                     help="skip timing the batched walks one density matrix at a time")
     ap.add_argument("--no-serve", action="store_true", help="skip the continuous-batching leg")
-    ap.add_argument("--serve-qps", default="2,4,8", help="arrival rates of the serving leg")
+    ap.add_argument("--serve-qps", default="2,4,8,12", help="arrival rates of the serving leg")
     ap.add_argument("--serve-seconds", type=float, default=12.0,
                     help="arrival time span of each serving rate")
     ap.add_argument("--serve-count", type=int, default=24, help="least walks per serving rate")

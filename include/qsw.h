@@ -496,7 +496,13 @@ typedef struct {
  * device under cache_bytes, keyed by (N, graph CSR, omega, gamma, flags);
  * unused ones are evicted least recently used first.  The walks' work goes
  * to hip_stream; operator builds run on a stream of the server's own that
- * does not wait for the legacy default stream.
+ * does not wait for the legacy default stream.  A walk whose graph order is
+ * at least QSW_SERVER_DIRECT_N (environment, read here; default 384, 0: off)
+ * fills the device on its own: it runs through qsw_propagate (launch pacing
+ * 2) in a direct lane, on a runner thread and stream of the server's own,
+ * one such walk at a time in arrival order, beside the engine; the lane's
+ * workspace and the output series of a populations-only walk are device
+ * buffers the server allocates and keeps (growing them as needed).
  */
 qsw_status_t qsw_server_create(size_t arena_bytes, size_t cache_bytes, int32_t max_walks,
                                void *hip_stream, qsw_server_t *out);

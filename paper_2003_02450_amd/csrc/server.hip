@@ -18,8 +18,17 @@
 //    upper bound from the graph, replaced by the handle's size once built):
 //    a build that would exceed the budget while every cached operator is in
 //    use waits until walks finish and release some.
-//  * Every walk's result is bitwise what it would be alone: the engine keeps
-//    walks independent.
+//  * Two lanes.  A walk whose operator is large enough to fill the device on
+//    its own (graph order at least QSW_SERVER_DIRECT_N, default 384; 0
+//    turns the lane off) gains nothing from sharing launches, and would
+//    slow every cycle of the engine down to its own pace: it runs through
+//    qsw_propagate (launch pacing 2) on a runner thread and stream of its
+//    own, one such walk at a time in arrival order, while the smaller walks
+//    keep cycling in the engine.  The runner's workspace, and the output
+//    series of a walk that asked for populations only, are device buffers
+//    the server keeps and grows as needed.
+//  * Every walk's result is bitwise what it would be alone, in either lane:
+//    the engine keeps walks independent and equal to qsw_propagate.
 #include "handle.h"
 
 #include <chrono>
@@ -81,6 +90,7 @@ struct Request {
   int64_t id = 0;
   uint64_t hash = 0;
   CachedOp *cop = nullptr;
+  bool direct = false;  // runs in the direct lane
   qsw_walk_t walk{};
   double t_submit = 0.0, t_admit = 0.0, t_done = 0.0;
   int64_t ticket = -1;
@@ -127,6 +137,16 @@ struct qsw_server_s {
   std::vector<double> build_ms;
   int in_flight = 0;
   bool stop = false;
+  // direct lane: runner thread, its stream and buffers (runner only), its
+  // queue and results (under mu)
+  int32_t direct_min_N = 384;
+  hipStream_t direct_stream = nullptr;
+  std::thread runner;
+  std::deque<Request *> djobs;
+  std::vector<std::pair<Request *, qsw_status_t>> ddone;
+  int d_in_flight = 0;
+  void *dws = nullptr, *dout = nullptr;
+  size_t dws_bytes = 0, dout_bytes = 0;
   void *arena = nullptr;
   qsw_engine_t engine = nullptr;
   size_t cache_budget = 0, cache_used = 0;
@@ -189,6 +209,20 @@ qsw_status_t admit(qsw_server_s *s) {
       continue;
     }
     r->walk.op = r->cop->op;
+    if (s->direct_min_N > 0 && r->cop->op->N >= s->direct_min_N) {
+      // the direct lane, in arrival order
+      r->direct = true;
+      r->state = 1;
+      r->t_admit = now_ms();
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->djobs.push_back(r);
+        ++s->d_in_flight;
+        s->cv_job.notify_all();
+      }
+      it = s->pending.erase(it);
+      continue;
+    }
     int64_t ticket = -1;
     const qsw_status_t st = qsw_engine_submit(s->engine, &r->walk, &ticket);
     if (st == QSW_ERR_OOM) break;  // waits until running walks free space
@@ -231,6 +265,60 @@ void builder_main(qsw_server_s *s) {
   }
 }
 
+// Grow a device buffer of the direct lane to at least `bytes` (the runner
+// thread alone uses it; the lane's earlier work has finished).
+hipError_t grow(void **buf, size_t *have, size_t bytes) {
+  if (*have >= bytes) return hipSuccess;
+  if (*buf) (void)hipFree(*buf);
+  *buf = nullptr;
+  *have = 0;
+  const hipError_t e = hipMalloc(buf, bytes);
+  if (e == hipSuccess) *have = bytes;
+  return e;
+}
+
+// One walk of the direct lane: qsw_propagate of its whole grid, then its
+// populations when asked for, on the lane's stream.
+qsw_status_t run_direct(qsw_server_s *s, Request *r) {
+  const qsw_walk_t &w = r->walk;
+  const size_t ws = qsw_propagate_workspace_bytes(w.op, w.t0, w.dt, w.n_steps);
+  if (ws == 0) return QSW_ERR_ARG;
+  HIP_TRY(grow(&s->dws, &s->dws_bytes, ws));
+  void *out = w.out;
+  if (!out) {
+    HIP_TRY(grow(&s->dout, &s->dout_bytes,
+                 (size_t)(w.n_steps + 1) * (size_t)w.op->n * sizeof(double2)));
+    out = s->dout;
+  }
+  qsw_status_t st = qsw_propagate(w.op, w.rho0, w.t0, w.dt, w.n_steps, out, s->dws, ws,
+                                  s->direct_stream);
+  if (st != QSW_OK) return st;
+  if (w.pops) {
+    st = qsw_populations(w.op, out, w.n_steps + 1, w.pops, s->direct_stream);
+    if (st != QSW_OK) return st;
+  }
+  HIP_TRY(hipStreamSynchronize(s->direct_stream));
+  qsw_stats_t ps{};
+  st = qsw_last_stats(w.op, &ps);
+  return st == QSW_ERR_NONFINITE ? QSW_OK : st;
+}
+
+void runner_main(qsw_server_s *s) {
+  (void)hipSetDevice(s->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    s->cv_job.wait(lk, [s] { return s->stop || !s->djobs.empty(); });
+    if (s->djobs.empty()) return;
+    Request *r = s->djobs.front();
+    s->djobs.pop_front();
+    lk.unlock();
+    const qsw_status_t st = run_direct(s, r);
+    lk.lock();
+    s->ddone.emplace_back(r, st);
+    s->cv_done.notify_all();
+  }
+}
+
 // Queue the builds of waiting operators, first come first, while the cache
 // budget allows them (evicting unused operators first); an operator larger
 // than the whole budget is built once nothing else is cached.
@@ -245,7 +333,7 @@ void start_builds(qsw_server_s *s) {
     std::lock_guard<std::mutex> lk(s->mu);
     s->jobs.push_back(c);
     ++s->in_flight;
-    s->cv_job.notify_one();
+    s->cv_job.notify_all();  // the runner waits on it too
   }
 }
 
@@ -322,6 +410,32 @@ qsw_status_t drain_builds(qsw_server_s *s) {
     s->cache_used -= c->bytes;
     delete c;
   }
+  // operators of the direct lane run with launch pacing
+  for (auto &bc : built)
+    if (s->direct_min_N > 0 && bc.first->op->N >= s->direct_min_N)
+      (void)qsw_superop_set_pacing(bc.first->op, 2);
+  return err;
+}
+
+// Walks the direct lane finished.  Returns the first error of one.
+qsw_status_t drain_direct(qsw_server_s *s) {
+  std::vector<std::pair<Request *, qsw_status_t>> done;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    done.swap(s->ddone);
+    s->d_in_flight -= (int)done.size();
+  }
+  qsw_status_t err = QSW_OK;
+  const double t = now_ms();
+  for (auto &rd : done) {
+    Request *r = rd.first;
+    r->state = 2;
+    r->t_done = t;
+    s->done_ids.push_back(r->id);
+    ++s->stats.completed;
+    --r->cop->users;
+    if (rd.second != QSW_OK && err == QSW_OK) err = rd.second;
+  }
   return err;
 }
 
@@ -361,10 +475,26 @@ qsw_status_t qsw_server_create(size_t arena_bytes, size_t cache_bytes, int32_t m
     delete s;
     return QSW_ERR_DEVICE;
   }
+  s->direct_min_N = env_int("QSW_SERVER_DIRECT_N", 384);
+  if (hipStreamCreateWithFlags(&s->direct_stream, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipStreamDestroy(s->build_stream);
+    qsw_engine_destroy(s->engine);
+    (void)hipFree(s->arena);
+    delete s;
+    return QSW_ERR_DEVICE;
+  }
   try {
     s->builder = std::thread(builder_main, s);
+    s->runner = std::thread(runner_main, s);
   } catch (...) {
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->stop = true;
+      s->cv_job.notify_all();
+    }
+    if (s->builder.joinable()) s->builder.join();
     (void)hipStreamDestroy(s->build_stream);
+    (void)hipStreamDestroy(s->direct_stream);
     qsw_engine_destroy(s->engine);
     (void)hipFree(s->arena);
     delete s;
@@ -382,11 +512,18 @@ void qsw_server_destroy(qsw_server_t s) {
     std::lock_guard<std::mutex> lk(s->mu);
     s->in_flight -= (int)s->jobs.size();
     s->jobs.clear();
+    s->d_in_flight -= (int)s->djobs.size();
+    s->djobs.clear();
     s->stop = true;
     s->cv_job.notify_all();
   }
   if (s->builder.joinable()) s->builder.join();
+  if (s->runner.joinable()) s->runner.join();
   (void)drain_builds(s);
+  (void)drain_direct(s);
+  if (s->dws) (void)hipFree(s->dws);
+  if (s->dout) (void)hipFree(s->dout);
+  if (s->direct_stream) (void)hipStreamDestroy(s->direct_stream);
   qsw_engine_destroy(s->engine);
   for (CachedOp *c : s->lru) {
     if (c->op) qsw_superop_destroy(c->op);
@@ -482,23 +619,29 @@ qsw_status_t qsw_server_step(qsw_server_t s, int32_t max_cycles, int32_t *runnin
   DeviceGuard g(s->device);
   if (!g.ok) return QSW_ERR_DEVICE;
   qsw_status_t build_err = drain_builds(s);
+  {
+    const qsw_status_t e2 = drain_direct(s);
+    if (build_err == QSW_OK) build_err = e2;
+  }
   start_builds(s);
   qsw_status_t st = admit(s);
   if (st != QSW_OK) return st;
   qsw_engine_stats_t es0{};
   (void)qsw_engine_stats(s->engine, &es0);
-  if (es0.live == 0 && !s->pending.empty()) {
-    // nothing runs and every queued walk waits for its operator: wait a
-    // little for a build instead of returning at once
+  if (es0.live == 0) {
+    // the engine is idle and the other threads are busy (builds, the direct
+    // lane): wait a little for one of them instead of returning at once
     bool busy;
     {
       std::unique_lock<std::mutex> lk(s->mu);
-      busy = s->in_flight > 0;
-      if (busy && s->built.empty() && s->failed.empty())
+      busy = (s->in_flight > 0 && !s->pending.empty()) || s->d_in_flight > 0;
+      if (busy && s->built.empty() && s->failed.empty() && s->ddone.empty())
         s->cv_done.wait_for(lk, std::chrono::milliseconds(5));
     }
     if (busy) {
-      const qsw_status_t e2 = drain_builds(s);
+      qsw_status_t e2 = drain_builds(s);
+      if (build_err == QSW_OK) build_err = e2;
+      e2 = drain_direct(s);
       if (build_err == QSW_OK) build_err = e2;
       start_builds(s);
       st = admit(s);
@@ -526,11 +669,20 @@ qsw_status_t qsw_server_step(qsw_server_t s, int32_t max_cycles, int32_t *runnin
       --r->cop->users;
     }
   } while (cnt == 256);
+  {
+    const qsw_status_t e2 = drain_direct(s);
+    if (build_err == QSW_OK) build_err = e2;
+  }
   evict_unused(s, 0);  // operators the finished walks released, if over budget
   start_builds(s);     // builds that waited for cache room
   st = admit(s);  // iteration-level admission into the space just freed
   if (st != QSW_OK) return st;
-  if (running) *running = live;
+  int d_live = 0;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    d_live = s->d_in_flight;
+  }
+  if (running) *running = live + d_live;
   if (pending) *pending = (int32_t)s->pending.size();
   qsw_engine_stats_t es{};
   (void)qsw_engine_stats(s->engine, &es);

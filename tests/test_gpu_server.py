@@ -145,3 +145,24 @@ def test_builds_overlap_running_walks():
     alone = [_serve([r])[0][0] for r in reqs]
     for rid, a in zip(first + late, alone):
         assert np.array_equal(results[rid], a)
+
+
+def test_direct_lane_and_engine_lane_mix(monkeypatch):
+    """With the direct lane taking every walk of order 30 or more, walks run
+    in both lanes at once; every result is bitwise that of qsw_propagate
+    alone."""
+    import torch
+    import paper_2003_02450_amd as qsw
+    monkeypatch.setenv("QSW_SERVER_DIRECT_N", "30")
+    reqs = _requests(8, 506, n_hi=60)
+    assert any(r["graph"].N >= 30 for r in reqs) and any(r["graph"].N < 30 for r in reqs)
+    mixed, st, _ = _serve(reqs)
+    assert st["completed"] == 8
+    for r, got in zip(reqs, mixed):
+        g = r["graph"]
+        op = qsw.Superop.from_graph(g.N, g.row_ptr, g.col_idx, g.w, r["omega"])
+        ref = op.populations(op.propagate(workloads.basis_state(g.N, 0), 0.0, r["dt"],
+                                          r["n_steps"]))
+        torch.cuda.synchronize()
+        assert np.array_equal(got, ref.cpu().numpy()), g.N
+        op.close()
