@@ -496,6 +496,49 @@ def served_leg(torch, qsw, workloads, qps_list, seconds: float, min_count: int) 
                         "arrival order"}}
 
 
+PAPER_XC40_S = {"line": 1973.0, "lattice": 2010.0, "er": 2842.0, "complete": 27821.0}
+
+
+def paper_leg(torch, qsw, workloads, kinds) -> dict:
+    """The paper's four Section 5 benchmark shapes (about 1.28e8 superoperator
+    entries each; omega = 0.5, which the paper does not state; rho0 = I/N):
+    build, then one step to t = 100 (FP64, launch pacing 2).  The paper's
+    single-process Cray XC40 wall times to t = 100 are quoted as context."""
+    dev = torch.device("cuda", 0)
+    res = {}
+    for kind in kinds:
+        wl = workloads.paper_shaped(kind)
+        g = wl.graph
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        op = qsw.Superop.from_graph(g.N, g.row_ptr, g.col_idx, g.w, wl.omega)
+        torch.cuda.synchronize()
+        build_s = time.perf_counter() - t0
+        op.set_pacing(2)
+        rho0 = torch.from_numpy(wl.rho0).to(dev)
+        t0 = time.perf_counter()
+        out = op.propagate(rho0, 0.0, wl.dt, wl.n_steps)
+        st = op.last_stats()
+        prop_s = time.perf_counter() - t0
+        info = op.info()
+        tr = float(torch.diagonal(out[-1]).real.sum().item())
+        per_us = 1e3 * st["ms"] / max(st["products"], 1)
+        res[kind] = {"N": g.N, "n": info["n"], "nnz": info["nnz"], "arcs": g.n_arcs,
+                     "norm1": info["norm1"], "m": st["m"], "s": st["s"],
+                     "products": st["products"], "build_s": build_s,
+                     "propagate_s": prop_s, "total_s": build_s + prop_s,
+                     "avg_product_us": per_us,
+                     "layout_gbps": st["bytes"] / max(st["products"], 1) / (per_us * 1e3),
+                     "csr_equivalent_gbps": csr_bytes(info["n"], info["nnz"]) / (per_us * 1e3),
+                     "trace_at_t100": tr,
+                     "paper_xc40_one_process_s": PAPER_XC40_S[kind],
+                     "note": "paper: Cray XC40, 2x Xeon E5-2690 v3, one MPI process, "
+                             "omega not stated (context only)"}
+        del out
+        op.close()
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -522,6 +565,9 @@ def main() -> int:
     ap.add_argument("--serve-seconds", type=float, default=12.0,
                     help="arrival time span of each serving rate")
     ap.add_argument("--serve-count", type=int, default=24, help="least walks per serving rate")
+    ap.add_argument("--paper", default="",
+                    help="comma list of the paper's benchmark shapes to run to t=100 "
+                         "(line,lattice,er,complete); none by default")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the batched and "
@@ -648,6 +694,8 @@ def main() -> int:
         result["served"] = served_leg(torch, qsw, workloads,
                                       [float(x) for x in args.serve_qps.split(",")],
                                       args.serve_seconds, args.serve_count)
+    if args.paper:
+        result["paper_shaped"] = paper_leg(torch, qsw, workloads, args.paper.split(","))
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_steps,
                                               args.cpu_one_thread_steps)
