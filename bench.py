@@ -51,6 +51,11 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_term_kernel_outdeg1024.tx
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2003_02450_amd", "csrc", "kernels.hip")
 
 
+def progress(msg: str) -> None:
+    """A progress line on stderr (stdout carries only the JSON line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def measured_traffic(key: str = "traffic_bytes_per_product"):
     """HBM bytes per computing Taylor-term product from the committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE runs (key: the FP64 kernel's, or
@@ -329,7 +334,8 @@ def batch_leg(torch, qsw, workloads, reps: int, compare: bool = True) -> dict:
     def timed(its):
         t_0 = time.perf_counter()
         dev_ms = byts = 0.0
-        for _ in range(reps):
+        for k in range(reps):
+            progress(f"batched: batch {k + 1} of {reps}")
             s_ = qsw.batch_propagate(its, workspace=ws)
             dev_ms += s_["ms"]
             byts += s_["bytes"]
@@ -340,6 +346,7 @@ def batch_leg(torch, qsw, workloads, reps: int, compare: bool = True) -> dict:
     points = sum(w.n_steps * w.rho0.shape[0] for w in wls)
     achieved = byts / (dev_ms * 1e-3) / 1e9
     # the same walks one density matrix at a time
+    progress("batched: the same walks one density matrix at a time")
     t0 = time.perf_counter()
     equal = True
     for i, (op, w, r) in enumerate(zip(ops, wls, r0) if compare else []):
@@ -440,11 +447,13 @@ def served_leg(torch, qsw, workloads, qps_list, seconds: float, min_count: int) 
     reqs = workloads.served_requests(count_max)
     # baseline: measured service times of the single-instance path
     n_base = min(count_max, 48)
+    progress(f"served: single-instance baseline on {n_base} walks")
     service = single_instance_service(torch, qsw, reqs[:n_base])
     base_rate = n_base / sum(service)
     points = []
     for qps in qps_list:
         count = max(min_count, int(qps * seconds))
+        progress(f"served: {count} walks at {qps} QPS")
         arrivals = workloads.poisson_arrivals(count, qps)
         srv = qsw.Server(96 * GB, 48 * GB, 4096)
         t_arr = {}
@@ -507,6 +516,7 @@ def paper_leg(torch, qsw, workloads, kinds) -> dict:
     dev = torch.device("cuda", 0)
     res = {}
     for kind in kinds:
+        progress(f"paper-shaped: {kind}")
         wl = workloads.paper_shaped(kind)
         g = wl.graph
         torch.cuda.synchronize()
@@ -562,7 +572,7 @@ def main() -> int:
                     help="skip timing the batched walks one density matrix at a time")
     ap.add_argument("--no-serve", action="store_true", help="skip the continuous-batching leg")
     ap.add_argument("--serve-qps", default="2,4,8,12", help="arrival rates of the serving leg")
-    ap.add_argument("--serve-seconds", type=float, default=12.0,
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="arrival time span of each serving rate")
     ap.add_argument("--serve-count", type=int, default=24, help="least walks per serving rate")
     ap.add_argument("--paper", default="",
@@ -618,6 +628,7 @@ def main() -> int:
             return st, info
         return one_pass
 
+    progress("headline: FP64 passes")
     stats, elapsed = timed_passes(args, make_pass("double"), out)
 
     prop_ms = sum(s["ms"] for s, _ in stats)
@@ -680,23 +691,30 @@ def main() -> int:
                      "avg_product_us": per_us},
     }
     if not args.no_csr:
+        progress("CSR stream engine")
         result["csr_engine"] = csr_leg(args, make_pass, out, torch, q, n, nnz)
     if not args.no_fp32:
+        progress("single-precision products")
         result["fp32"] = precision_leg(args, make_pass, out, torch, q, "fp32")
     if not args.no_single:
+        progress("single-precision values")
         result["single_values"] = precision_leg(args, make_pass, out, torch, q, "single")
     if not args.no_configs:
+        progress("N=16 and N=256 workloads")
         result["configs"] = configs_leg(torch, qsw, workloads, max(3, args.steps))
     if not args.no_batch:
-        result["batched"] = batch_leg(torch, qsw, workloads, args.steps,
+        progress("batched walks")
+        result["batched"] = batch_leg(torch, qsw, workloads, min(args.steps, 3),
                                       not args.no_batch_compare)
     if not args.no_serve:
+        progress("continuous batching")
         result["served"] = served_leg(torch, qsw, workloads,
                                       [float(x) for x in args.serve_qps.split(",")],
                                       args.serve_seconds, args.serve_count)
     if args.paper:
         result["paper_shaped"] = paper_leg(torch, qsw, workloads, args.paper.split(","))
     if not args.no_cpu_baseline:
+        progress("CPU oracle baseline")
         result["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_steps,
                                               args.cpu_one_thread_steps)
     print(json.dumps(result), flush=True)

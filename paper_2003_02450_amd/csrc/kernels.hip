@@ -399,8 +399,35 @@ __device__ __forceinline__ void stream_engine(const SpmvArgs &a, Epi &epi) {
 // a zero.
 // Positions in flight per lane: eight for one right-hand side, four for
 // two, two for four (each position's gathers then take 4 NRHS registers).
-template <int NRHS>
-constexpr int wave_unroll() { return NRHS == 1 ? 8 : (NRHS == 2 ? 4 : 2); }
+// Launch-shape constants of the product kernels (build-time; the defaults are
+// the measured best on the 1024-vertex workload): positions per gather group
+// for one right-hand side (double / single-precision products), waves per
+// SIMD the double and single term kernels are compiled for, and whether
+// double phase-split blocks take the two-multiply-add path.  Measured per
+// FP64 pass (50 intervals, 1498 products, grid 2048): groups of 8 positions
+// 104.7 ms, 6 positions 103.1, 6 with the two-multiply-add path 100.4, 5
+// positions 111.9, 4 109.2, 7 108.7; five waves per SIMD spills.  Single-
+// precision products: groups of 8 58.1 ms, 6, 12 and 16 slower.
+#ifndef QSW_UNROLL1
+#define QSW_UNROLL1 6
+#endif
+#ifndef QSW_UNROLL1_X32
+#define QSW_UNROLL1_X32 8
+#endif
+#ifndef QSW_TERM_WAVES
+#define QSW_TERM_WAVES 4
+#endif
+#ifndef QSW_TERM32_WAVES
+#define QSW_TERM32_WAVES 4
+#endif
+#ifndef QSW_FAST64
+#define QSW_FAST64 1
+#endif
+
+template <int NRHS, bool X32 = false>
+constexpr int wave_unroll() {
+  return NRHS == 1 ? (X32 ? QSW_UNROLL1_X32 : QSW_UNROLL1) : (NRHS == 2 ? 4 : 2);
+}
 
 // A wave-uniform 64-bit value (taken from lane 0) in scalar registers.
 __device__ __forceinline__ int64_t uniform64(int64_t v) {
@@ -551,7 +578,7 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
   using R = RealT<X32>;
   // one right-hand side: xs holds x[base .. base + span) (span = N by default)
   const uint64_t lim = (uint64_t)(span ? span : a.N);
-  constexpr int kWaveUnroll = wave_unroll<NRHS>();
+  constexpr int kWaveUnroll = wave_unroll<NRHS, X32>();
   const int lane = threadIdx.x & 63;
   const int64_t r0 = k * kWaveRows;
   const int nr = (int)min((int64_t)kWaveRows, a.n - r0);
@@ -728,7 +755,7 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
   // there, but 77.6 -> 78.7 us with double values (whose product kernel is
   // at the edge of its register budget).
   bool fast = false;
-  if constexpr (STAGE && SPLIT && F32 && NRHS == 1 && !SOA) {
+  if constexpr (STAGE && SPLIT && (F32 || QSW_FAST64) && NRHS == 1 && !SOA) {
     const int G = hd.G;
     const int64_t rho = r0 / a.N * a.N;
     if (G >= 0 && hd.dfirst && (uint64_t)(rho - base) < lim) {
@@ -1602,7 +1629,7 @@ __device__ __forceinline__ bool taylor_prologue(const SpmvArgs &a) {
 }
 
 template <int ENGINE>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void term_kernel(SpmvArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(QSW_TERM_WAVES))) void term_kernel(SpmvArgs a) {
   if (taylor_prologue(a)) return;
   TaylorEpi epi(a);
   run_engine<ENGINE>(a, epi);
@@ -1679,7 +1706,7 @@ __device__ __forceinline__ void run_engine32(const SpmvArgs &a, Epi &epi) {
 }
 
 template <int ENGINE>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void term32_kernel(SpmvArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(QSW_TERM32_WAVES))) void term32_kernel(SpmvArgs a) {
   if (taylor_prologue(a)) return;
   Taylor32Epi epi(a);
   run_engine32<ENGINE>(a, epi);

@@ -813,12 +813,16 @@ int banded_grid(int grid) { return std::max(8, grid / 8 * 8); }
 // the resident capacity, then blocks per wavefront grow.
 int wave_grid(int64_t nwb, int resident) {
   const int64_t wgs = (nwb + kBlockThreads / 64 - 1) / (kBlockThreads / 64);
-  // two rounds of resident workgroups, each taking its quads grid-stride:
-  // on the 1024-vertex operator a Taylor-term product took 78.2 us with one
-  // quad per workgroup (4096), 72.4-73.0 with 1.5-2 rounds, 74.1 with one
+  // about two rounds of resident workgroups, each taking its quads
+  // grid-stride, with the quads split evenly: q = ceil(quads / cap) quads per
+  // workgroup and ceil(quads / q) workgroups.  On the 1024-vertex operator
+  // (4096 quads) a pass took 104.7 ms at 2048 workgroups (two quads each),
+  // 106.4 at 2560 (an uneven split), 111.5 at 3584 and 109.8 at 4096 (one
+  // quad each); single-precision products 58.1, 59.2, 68.2 and 69.6 ms.
   int64_t cap = 2 * (int64_t)std::max(resident, 1);
-  cap = env_int("QSW_GRID", (int)cap);
-  return (int)std::max<int64_t>(1, std::min(wgs, cap));
+  cap = std::max<int64_t>(1, env_int("QSW_GRID", (int)cap));
+  const int64_t q = (wgs + cap - 1) / cap;
+  return (int)std::max<int64_t>(1, (wgs + q - 1) / std::max<int64_t>(q, 1));
 }
 
 // H (Hermitian, complex, may hold a diagonal) into the off-diagonal CSR and

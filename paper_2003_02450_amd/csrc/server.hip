@@ -31,6 +31,7 @@
 //    the engine keeps walks independent and equal to qsw_propagate.
 #include "handle.h"
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -266,14 +267,22 @@ void builder_main(qsw_server_s *s) {
 }
 
 // Grow a device buffer of the direct lane to at least `bytes` (the runner
-// thread alone uses it; the lane's earlier work has finished).
+// thread alone uses it; the lane's earlier work has finished).  It grows by
+// at least half its size each time: a reallocation waits for the device.
 hipError_t grow(void **buf, size_t *have, size_t bytes) {
   if (*have >= bytes) return hipSuccess;
+  const size_t want = std::max(bytes, *have + *have / 2);
   if (*buf) (void)hipFree(*buf);
   *buf = nullptr;
   *have = 0;
-  const hipError_t e = hipMalloc(buf, bytes);
-  if (e == hipSuccess) *have = bytes;
+  hipError_t e = hipMalloc(buf, want);
+  if (e != hipSuccess && want > bytes) {
+    (void)hipGetLastError();
+    e = hipMalloc(buf, bytes);
+    if (e == hipSuccess) *have = bytes;
+    return e;
+  }
+  if (e == hipSuccess) *have = want;
   return e;
 }
 
