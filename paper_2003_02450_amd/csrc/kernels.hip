@@ -424,9 +424,18 @@ __device__ __forceinline__ void stream_engine(const SpmvArgs &a, Epi &epi) {
 #define QSW_FAST64 1
 #endif
 
+// Two and four right-hand sides (estimator, batched walks): groups of 3 or 6
+// (two columns) and 3 or 1 (four columns) measured level or slower.
+#ifndef QSW_UNROLL2
+#define QSW_UNROLL2 4
+#endif
+#ifndef QSW_UNROLL4
+#define QSW_UNROLL4 2
+#endif
+
 template <int NRHS, bool X32 = false>
 constexpr int wave_unroll() {
-  return NRHS == 1 ? (X32 ? QSW_UNROLL1_X32 : QSW_UNROLL1) : (NRHS == 2 ? 4 : 2);
+  return NRHS == 1 ? (X32 ? QSW_UNROLL1_X32 : QSW_UNROLL1) : (NRHS == 2 ? QSW_UNROLL2 : QSW_UNROLL4);
 }
 
 // A wave-uniform 64-bit value (taken from lane 0) in scalar registers.
