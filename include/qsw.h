@@ -572,7 +572,12 @@ double qsw_theta(int32_t m, int32_t prec);
  * over 2 <= p <= p_max, p(p-1)-1 <= m <= m_max, alpha_p = t max(d_p, d_{p+1});
  * smallest m on ties; t||L||_1 = 0 gives m = 0, s = 1.  (m_max, p_max) =
  * (55, 8), or (20, 5) for QSW_PREC_FP32, whose theta_m are the single ones.
+ * prec | QSW_PARAMS_KNOWN_NORMS: the alpha_p rule whenever d is given, also
+ * for small ||tL||_1 (their switch to the 1-norm rule only saves the products
+ * of estimating the d_p).  qsw_propagate chooses this way: a handle's d_p are
+ * estimated once, at construction.
  */
+#define QSW_PARAMS_KNOWN_NORMS 16
 qsw_status_t qsw_select_params(double norm1, const double *d, double t, int32_t n0,
                                int32_t prec, int32_t *m, int32_t *s);
 

@@ -71,17 +71,19 @@ def condition_3_13(norm_tA: float, n0: int = 1, ell: int = 2,
 
 
 def select_params(norm1_A: float, d: dict, t: float, n0: int = 1, ell: int = 2,
-                  thetas=None, m_max: int = M_MAX, p_max: int = P_MAX):
+                  thetas=None, m_max: int = M_MAX, p_max: int = P_MAX, switch: bool = True):
     """Full choice for tA given ||A||_1 and d[p] = ||A^p||_1^(1/p),
     p = 2..p_max+1.  Minimises m * ceil(alpha_p / theta_m) over
-    2 <= p <= p_max and p(p-1)-1 <= m <= m_max, smallest m on ties."""
+    2 <= p <= p_max and p(p-1)-1 <= m <= m_max, smallest m on ties.  With
+    switch=False the alpha_p rule applies for every t (the norms are known
+    already, so condition 3.13's saving does not arise)."""
     if thetas is None:
         thetas = theta_table()
     t = abs(t)
     norm_tA = t * norm1_A
     if norm_tA == 0.0:
         return 0, 1
-    if condition_3_13(norm_tA, n0, ell, thetas, m_max, p_max):
+    if switch and condition_3_13(norm_tA, n0, ell, thetas, m_max, p_max):
         return select_params_norm1(norm_tA, thetas, m_max)
     best = None  # (cost, m, s)
     for m in range(1, m_max + 1):

@@ -57,10 +57,13 @@ def theta(m: int, single: bool = False) -> float:
                                        _lib.QSW_PREC_DOUBLE))
 
 
-def select_params(norm1: float, d=None, t: float = 1.0, n0: int = 1, single: bool = False):
+def select_params(norm1: float, d=None, t: float = 1.0, n0: int = 1, single: bool = False,
+                  known_norms: bool = False):
     """(m, s) for exp(t L) from ||L||_1 and d[p] = ||L^p||_1^(1/p), p = 2..9
     (host-only library call; ``d`` indexable by p, or None).  ``single``: a
-    precision as for Superop.set_precision (True / "single" / "fp32")."""
+    precision as for Superop.set_precision (True / "single" / "fp32").
+    ``known_norms``: the alpha_p rule whenever d is given (as propagate
+    chooses with a handle's norms), without the switch for small ||tL||_1."""
     L = _lib.load()
     darr = None
     if d is not None:
@@ -69,7 +72,8 @@ def select_params(norm1: float, d=None, t: float = 1.0, n0: int = 1, single: boo
             darr[p] = float(d[p])
     m, s = ctypes.c_int32(), ctypes.c_int32()
     st = L.qsw_select_params(float(norm1), None if darr is None else _ptr(darr), float(t),
-                             int(n0), _prec_code(single),
+                             int(n0), _prec_code(single) |
+                             (_lib.QSW_PARAMS_KNOWN_NORMS if known_norms else 0),
                              ctypes.byref(m), ctypes.byref(s))
     _lib.check(st, "qsw_select_params")
     return m.value, s.value

@@ -20,6 +20,7 @@ QSW_DEPHASING = 4
 QSW_PREC_DOUBLE = 0
 QSW_PREC_SINGLE = 1
 QSW_PREC_FP32 = 2
+QSW_PARAMS_KNOWN_NORMS = 16
 PREC_NAMES = {0: "double", 1: "single", 2: "fp32"}
 NOALLOC_SCRATCH_BYTES = 80 << 20   # QSW_NOALLOC_SCRATCH_BYTES
 

@@ -106,9 +106,11 @@ int mmax_of(int prec) { return prec == QSW_PREC_FP32 ? kMMax32 : kMMax; }
 // decides, m* = argmin m ceil(||tL||_1 / theta_m); otherwise
 // m * ceil(alpha_p / theta_m) is minimised over 2 <= p <= p_max and
 // p(p-1)-1 <= m <= m_max with alpha_p = t max(d_p, d_{p+1}).  Ties go to the
-// smallest m; s = max(1, ceil(.)).
+// smallest m; s = max(1, ceil(.)).  The switch weighs the products spent on
+// estimating the d_p against those they save; with `switch313` false the
+// alpha_p rule decides whenever d is given (the d_p already estimated).
 qsw_status_t select_params_impl(double norm1, const double *d, double t, int n0, int prec,
-                                int *m_out, int *s_out) {
+                                int *m_out, int *s_out, bool switch313) {
   if (!m_out || !s_out || n0 < 1 || !(norm1 >= 0.0) || !std::isfinite(t)) return QSW_ERR_ARG;
   const ThetaTable &T = table(prec);
   const int mmax = mmax_of(prec), pmax = prec == QSW_PREC_FP32 ? kPMax32 : kPMax;
@@ -124,7 +126,7 @@ qsw_status_t select_params_impl(double norm1, const double *d, double t, int n0,
       2.0 * kEll * pmax * (pmax + 3) * T.th[mmax] / ((double)n0 * (double)mmax);
   int best_m = -1;
   double best_cost = 0.0, best_s = 0.0;
-  if (d == nullptr || x <= bound) {
+  if (d == nullptr || (switch313 && x <= bound)) {
     for (int m = 1; m <= mmax; ++m) {
       const double sm = std::ceil(x / T.th[m]);
       const double cost = m * sm;
@@ -174,10 +176,12 @@ double qsw_theta(int32_t m, int32_t prec) {
 
 qsw_status_t qsw_select_params(double norm1, const double *d, double t, int32_t n0, int32_t prec,
                                int32_t *m, int32_t *s) {
+  const bool known = (prec & QSW_PARAMS_KNOWN_NORMS) != 0;
+  prec &= ~QSW_PARAMS_KNOWN_NORMS;
   if (prec != QSW_PREC_DOUBLE && prec != QSW_PREC_SINGLE && prec != QSW_PREC_FP32)
     return QSW_ERR_ARG;
   int mm = 0, ss = 0;
-  qsw_status_t st = qsw::select_params_impl(norm1, d, t, n0, prec, &mm, &ss);
+  qsw_status_t st = qsw::select_params_impl(norm1, d, t, n0, prec, &mm, &ss, !known);
   if (st == QSW_OK) {
     *m = mm;
     *s = ss;

@@ -20,7 +20,9 @@ double tol_of(int prec);
 int mmax_of(int prec);
 
 // m and s for exp(t L); d = NULL uses ||L||_1 only, else d[p], p = 2..9.
+// switch313: apply Al-Mohy and Higham's switch to the 1-norm rule for small
+// ||tL||_1 (false: the alpha_p rule whenever d is given).
 qsw_status_t select_params_impl(double norm1, const double *d, double t, int n0, int prec,
-                                int *m_out, int *s_out);
+                                int *m_out, int *s_out, bool switch313 = true);
 
 }  // namespace qsw

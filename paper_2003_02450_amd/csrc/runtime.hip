@@ -1307,10 +1307,14 @@ qsw_status_t build_common(std::shared_ptr<Assembler> src, double omega, hipStrea
 qsw_status_t qsw::make_plan(const qsw_superop_s *h, double t0, double dt, int32_t n_steps,
                              Plan &P) {
   if (!std::isfinite(t0) || !std::isfinite(dt) || n_steps < 0) return QSW_ERR_ARG;
+  // The handle's d_p were estimated at construction (the paper computes the
+  // 1-norm series once, Section 4 footnote), so the alpha_p rule decides for
+  // every t: Al-Mohy and Higham's switch to the 1-norm rule for small
+  // ||tL||_1 only saves the products of estimating them.
   const double *d = h->info.d;
   qsw_status_t st;
   if (t0 != 0.0) {
-    st = select_params_impl(h->info.norm1, d, t0, 1, h->prec, &P.m0, &P.s0);
+    st = select_params_impl(h->info.norm1, d, t0, 1, h->prec, &P.m0, &P.s0, false);
     if (st != QSW_OK) return st;
   }
   const size_t vec = (size_t)h->n * sizeof(double2);
@@ -1320,7 +1324,7 @@ qsw_status_t qsw::make_plan(const qsw_superop_s *h, double t0, double dt, int32_
     // single-precision products: one single-time application per interval;
     // two complex64 terms, two hi + lo accumulator pairs
     if (n_steps > 0) {
-      st = select_params_impl(h->info.norm1, d, dt, 1, h->prec, &P.m, &P.s);
+      st = select_params_impl(h->info.norm1, d, dt, 1, h->prec, &P.m, &P.s, false);
       if (st != QSW_OK) return st;
     }
     const size_t v32 = align256((size_t)h->n * sizeof(float2));
@@ -1336,11 +1340,11 @@ qsw_status_t qsw::make_plan(const qsw_superop_s *h, double t0, double dt, int32_
   }
   if (n_steps > 0) {
     int mS = 0, sS = 1;
-    st = select_params_impl(h->info.norm1, d, (double)n_steps * dt, 1, h->prec, &mS, &sS);
+    st = select_params_impl(h->info.norm1, d, (double)n_steps * dt, 1, h->prec, &mS, &sS, false);
     if (st != QSW_OK) return st;
     if (n_steps <= sS || mS == 0) {
       P.branch = 0;
-      st = select_params_impl(h->info.norm1, d, dt, 1, h->prec, &P.m, &P.s);
+      st = select_params_impl(h->info.norm1, d, dt, 1, h->prec, &P.m, &P.s, false);
       if (st != QSW_OK) return st;
     } else {
       P.branch = 1;

@@ -111,3 +111,23 @@ def test_select_params_fp32_matches_oracle_capped_rule():
         assert got == want, (nrm, t, n0, got, want)
         assert got[0] <= 20
 
+
+def test_select_params_known_norms_matches_oracle_without_switch():
+    """QSW_PARAMS_KNOWN_NORMS (the rule propagate uses with a handle's norms):
+    the alpha_p rule at every ||tL||_1, as the oracle's rule without the
+    condition-3.13 switch; for large ||tL||_1 it is the published rule."""
+    rng = np.random.Generator(np.random.PCG64(10))
+    for prec, th, mm, pm in (("double", otheta.theta_table(), 55, 8),
+                             ("fp32", otheta.theta_table(otheta.TOL_SINGLE), 20, 5)):
+        for _ in range(300):
+            nrm = float(10 ** rng.uniform(-1, 2))
+            d = {p: nrm * float(rng.uniform(0.01, 1.0)) for p in range(2, 10)}
+            t = float(10 ** rng.uniform(-3, 3))
+            n0 = int(rng.integers(1, 5))
+            got = qsw.select_params(nrm, d, t, n0, single=prec, known_norms=True)
+            want = oexpmv.select_params(nrm, d, t, n0, thetas=th, m_max=mm, p_max=pm,
+                                        switch=False)
+            assert got == want, (prec, nrm, t, n0, got, want)
+            if not oexpmv.condition_3_13(t * nrm, n0, thetas=th, m_max=mm, p_max=pm):
+                assert got == qsw.select_params(nrm, d, t, n0, single=prec)
+

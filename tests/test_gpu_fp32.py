@@ -136,7 +136,8 @@ def test_parameters_rerun_and_double_untouched():
     assert np.array_equal(a, b)                       # reruns are bitwise identical
     inf = op.info()
     d = [inf["norm1"], inf["norm1"]] + [inf["d"][p] for p in range(2, 10)]
-    assert (s32["m"], s32["s"]) == qsw.select_params(inf["norm1"], d, wl.dt, single="fp32")
+    assert (s32["m"], s32["s"]) == qsw.select_params(inf["norm1"], d, wl.dt, single="fp32",
+                                                            known_norms=True)
     assert s32["products"] < s64["products"] and s32["bytes"] < s64["bytes"]
     op.set_precision(False)
     again = _run(op, wl)

@@ -43,7 +43,12 @@ def test_paced_equals_unpaced(case, lookahead):
     for x, st in ((got, st1), (again, st2), (off, st3)):
         assert np.array_equal(x, ref)
         assert st["products"] == st0["products"]
-    assert st1["launched"] < st0["launched"] and st2["launched"] < st0["launched"]
+    # never more launches than unpaced, at least the computed products; with
+    # a short lookahead, fewer (a long one may cover what a step leaves)
+    for st in (st1, st2):
+        assert st0["products"] <= st["launched"] <= st0["launched"]
+        if lookahead <= 3:
+            assert st["launched"] < st0["launched"], (lookahead, st0["m"])
     assert st3["launched"] == st0["launched"]
     op.close()
 

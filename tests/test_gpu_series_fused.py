@@ -15,7 +15,8 @@ def _one_point_blocks(op, wl, single):
     """n_steps and dt for which the series branch takes d = 1 (s < q < 2 s)."""
     info = op.info()
     for q in range(3, 60):
-        m, s = qsw.select_params(info["norm1"], info["d"], q * wl.dt, single=single)
+        m, s = qsw.select_params(info["norm1"], info["d"], q * wl.dt, single=single,
+                                 known_norms=True)
         if s < q < 2 * s:
             return q
     pytest.skip("no one-point block split for this operator")

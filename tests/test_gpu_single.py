@@ -98,7 +98,8 @@ def test_fewer_products_than_double_and_parameters():
     s32 = op.last_stats()
     inf = op.info()
     d = [inf["norm1"], inf["norm1"]] + [inf["d"][p] for p in range(2, 10)]
-    assert (s32["m"], s32["s"]) == qsw.select_params(inf["norm1"], d, wl.dt, single=True)
+    assert (s32["m"], s32["s"]) == qsw.select_params(inf["norm1"], d, wl.dt, single=True,
+                                                            known_norms=True)
     assert s32["products"] < s64["products"]
     assert s32["bytes"] < s64["bytes"]
     op.set_precision(False)

@@ -190,3 +190,22 @@ def test_select_params_end_to_end_accuracy():
         F, _ = native.taylor_expmv(A, rho0, t, m, s, oth.TOL_DOUBLE)
         ref = scipy.linalg.expm(t * D) @ rho0
         assert np.abs(F - ref).max() <= 1e-12, t
+
+
+@pytest.mark.parametrize("tol,m_max,p_max", [(oth.TOL_DOUBLE, oth.M_MAX, oth.P_MAX),
+                                               (oth.TOL_SINGLE, 20, 5)])
+def test_select_params_without_switch_feasible_and_optimal(tol, m_max, p_max):
+    """Without the condition-3.13 switch the alpha_p rule holds at every
+    ||tA||_1, small ones included: feasible and optimal as above."""
+    th = oth.theta_table(tol)
+    rng = np.random.Generator(np.random.PCG64(43))
+    for _ in range(300):
+        nrm, d, t = _random_case(rng, large=False)
+        m, s = expmv.select_params(nrm, d, t, thetas=th, m_max=m_max, p_max=p_max,
+                                   switch=False)
+        assert any(p * (p - 1) - 1 <= m and _alpha(d, p, t) / s <= th[m - 1]
+                   for p in range(2, p_max + 1)), (nrm, t, m, s)
+        costs = [(mm * math.ceil(_alpha(d, p, t) / th[mm - 1]), mm)
+                 for mm, p in _admissible_pairs(m_max, p_max)]
+        best = min(c for c, _ in costs)
+        assert m * s == best and m == min(mm for c, mm in costs if c == best)
