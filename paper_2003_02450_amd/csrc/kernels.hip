@@ -420,6 +420,9 @@ __device__ __forceinline__ void stream_engine(const SpmvArgs &a, Epi &epi) {
 #ifndef QSW_TERM32_WAVES
 #define QSW_TERM32_WAVES 4
 #endif
+#ifndef QSW_FAST_NRHS
+#define QSW_FAST_NRHS 2  // widest interleaved block taking the phase-split fast path
+#endif
 #ifndef QSW_FAST64
 #define QSW_FAST64 1
 #endif
@@ -433,9 +436,14 @@ __device__ __forceinline__ void stream_engine(const SpmvArgs &a, Epi &epi) {
 #define QSW_UNROLL4 2
 #endif
 
+#ifndef QSW_UNROLLW
+#define QSW_UNROLLW 1
+#endif
+
 template <int NRHS, bool X32 = false>
 constexpr int wave_unroll() {
-  return NRHS == 1 ? (X32 ? QSW_UNROLL1_X32 : QSW_UNROLL1) : (NRHS == 2 ? QSW_UNROLL2 : QSW_UNROLL4);
+  return NRHS == 1 ? (X32 ? QSW_UNROLL1_X32 : QSW_UNROLL1)
+                   : (NRHS == 2 ? QSW_UNROLL2 : (NRHS <= 4 ? QSW_UNROLL4 : QSW_UNROLLW));
 }
 
 // A wave-uniform 64-bit value (taken from lane 0) in scalar registers.
@@ -608,7 +616,8 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
   // nothing, so the sums are those of the unshared layout.
   if (gsp > 0) {
     const int64_t row = r0 + orow;
-    constexpr int SU = NRHS == 1 ? kSharedPad : (NRHS == 2 ? kSharedPad / 2 : kSharedPad / 4);
+    constexpr int SU = NRHS == 1 ? kSharedPad
+                                 : (NRHS == 2 ? kSharedPad / 2 : (NRHS <= 4 ? kSharedPad / 4 : 1));
     static_assert(kSharedPad % SU == 0, "shared groups divide the padding");
     // lane i loaded entry i with the block header (at most kSharedMax
     // entries), and each group takes its entries from the lanes (no load
@@ -752,8 +761,9 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
       }
     }
   };
-  // Phase-split fast path (one right-hand side): in a regular block whose
-  // position G holds every row's diagonal, every other entry is real or
+  // Phase-split fast path (one or two interleaved right-hand sides): in a
+  // regular block whose position G holds every row's diagonal, every other
+  // entry is real or
   // imaginary, and such an entry's product takes two multiply-adds with the
   // components of x chosen by its phase; they are the complex product's
   // multiply-adds that do not multiply by zero, in the same order, so the
@@ -764,7 +774,7 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
   // there, but 77.6 -> 78.7 us with double values (whose product kernel is
   // at the edge of its register budget).
   bool fast = false;
-  if constexpr (STAGE && SPLIT && (F32 || QSW_FAST64) && NRHS == 1 && !SOA) {
+  if constexpr (STAGE && SPLIT && (F32 || QSW_FAST64) && NRHS <= QSW_FAST_NRHS && !SOA) {
     const int G = hd.G;
     const int64_t rho = r0 / a.N * a.N;
     if (G >= 0 && hd.dfirst && (uint64_t)(rho - base) < lim) {
@@ -772,7 +782,8 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
       const int lrel = (int)(lane_row - base);  // the lane's row in the staged rows
       const uint32_t lmax = (uint32_t)lim - 1u;
       // positions p0 .. min(p0 + kWaveUnroll, pend) - 1, gathering from
-      // global memory (MODE kGatherGlobal) or the staged rows (kGatherLds)
+      // global memory (MODE kGatherGlobal) or the staged rows (kGatherLds);
+      // column r of x at row NRHS + r in both
       auto fgroup = [&](auto mode, int p0, int pend) {
         constexpr int MODE = decltype(mode)::value;
         int bcur[kWaveUnroll];
@@ -795,23 +806,29 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
           else
             cf[u] = F32 ? load_entry(a.wcoef32 + e0 + bcur[u]) : load_entry(a.wcoef + e0 + bcur[u]);
         }
-        V xv[kWaveUnroll];
+        V xv[kWaveUnroll][NRHS];
 #pragma unroll
         for (int u = 0; u < kWaveUnroll; ++u) {
           const int off = ok[u] ? (int)((uint32_t)c[u] << 2) >> 2 : 0;
-          if constexpr (MODE == kGatherLds)
-            xv[u] = xs[min((uint32_t)(lrel + off), lmax)];
-          else
-            xv[u] = gld(xbase<X32>(a) + (lane_row + off));
+#pragma unroll
+          for (int r = 0; r < NRHS; ++r) {
+            if constexpr (MODE == kGatherLds)
+              xv[u][r] = xs[min((uint32_t)(lrel + off), lmax) * NRHS + r];
+            else
+              xv[u][r] = gld(xbase<X32>(a) + (lane_row + off) * NRHS + r);
+          }
         }
 #pragma unroll
         for (int u = 0; u < kWaveUnroll; ++u) {
           const bool im = ((uint32_t)c[u] & kImagBit) != 0u;
           const R cm = ok[u] ? cf[u] : R(0);
-          const R sx = im ? xv[u].y : xv[u].x;
-          const R sy = im ? xv[u].x : xv[u].y;
-          acc[0] = rfma(im ? -cm : cm, sx, acc[0]);
-          acc[1] = rfma(cm, sy, acc[1]);
+#pragma unroll
+          for (int r = 0; r < NRHS; ++r) {
+            const R sx = im ? xv[u][r].y : xv[u][r].x;
+            const R sy = im ? xv[u][r].x : xv[u][r].y;
+            acc[2 * r] = rfma(im ? -cm : cm, sx, acc[2 * r]);
+            acc[2 * r + 1] = rfma(cm, sy, acc[2 * r + 1]);
+          }
         }
       };
       int p0 = 0;
@@ -821,7 +838,8 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
         // a marker, its value in dg)
         const int cnt = __popcll(__ballot(len > G));
         const V vz = masked(lane < cnt, dg);
-        cmac(acc[0], acc[1], vz, xs[lrel]);
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r) cmac(acc[2 * r], acc[2 * r + 1], vz, xs[lrel * NRHS + r]);
         ps += cnt;
       }
       for (p0 = G + 1; p0 < maxlen; p0 += kWaveUnroll)
@@ -1889,6 +1907,84 @@ __global__ __launch_bounds__(kBlock) void spmm2_kernel(SpmvArgs a, int mode, dou
   }
 }
 
+// Merged power chains of the 1-norm estimator (see WideOut): nr interleaved
+// columns, no staging (the rho-rows of many columns do not fit the LDS).
+// The per-column sums are the two-column product's, in the same order, and
+// the finishing pair's epilogue and per-workgroup column sums are the same
+// as spmm2_kernel's with the same grid.
+template <int NR>
+struct WideEpi {
+  WideOut o;
+  double s0 = 0.0, s1 = 0.0;
+  typedef NoPre Pre;
+  __device__ __forceinline__ Pre pre(int64_t) const { return Pre{}; }
+  __device__ __forceinline__ void operator()(int64_t row, const double *acc, Pre) {
+#pragma unroll
+    for (int c = 0; c < NR; ++c)
+      if (c < o.ys) o.Y[row * o.ys + c] = make_double2(acc[2 * c], acc[2 * c + 1]);
+    if (o.fin) {
+      const double2 y0 = make_double2(acc[2 * NR - 4], acc[2 * NR - 3]);
+      const double2 y1 = make_double2(acc[2 * NR - 2], acc[2 * NR - 1]);
+      const double m0 = cabs2(y0), m1 = cabs2(y1);
+      if (o.mode == 1) {
+        s0 += m0;
+        s1 += m1;
+        o.sgn[2 * row] = m0 > 0.0 ? make_double2(y0.x / m0, y0.y / m0) : make_double2(1.0, 0.0);
+        o.sgn[2 * row + 1] =
+            m1 > 0.0 ? make_double2(y1.x / m1, y1.y / m1) : make_double2(1.0, 0.0);
+      } else if (o.mode == 2) {
+        o.h[row] = m0 > m1 ? m0 : m1;
+      }
+    }
+  }
+};
+
+template <bool SPLIT, int NR>
+__global__ __launch_bounds__(kBlock) void spmm_wide_kernel(SpmvArgs a, WideOut o) {
+  WideEpi<NR> epi{o};
+  wave_engine<NR, false, false, SPLIT>(a, epi);
+  if (o.fin && o.mode == 1) {
+    __shared__ double sm0[kBlock], sm1[kBlock];
+    sm0[threadIdx.x] = epi.s0;
+    sm1[threadIdx.x] = epi.s1;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) {
+        sm0[threadIdx.x] += sm0[threadIdx.x + w];
+        sm1[threadIdx.x] += sm1[threadIdx.x + w];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      o.part[2 * blockIdx.x] = sm0[0];
+      o.part[2 * blockIdx.x + 1] = sm1[0];
+    }
+  }
+}
+
+__global__ void pack_pairs_kernel(double2 *W, int64_t n, PairSources ps) {
+  const int c = 2 * ps.chains;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    for (int j = 0; j < ps.chains; ++j) {
+      const double2 a = ps.src[j][2 * i], b = ps.src[j][2 * i + 1];
+      W[i * c + 2 * j] = a;
+      W[i * c + 2 * j + 1] = b;
+    }
+  }
+}
+
+__global__ void unit_pairs_kernel(double2 *W, int64_t n, PairUnits pu) {
+  const int c = 2 * pu.chains;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    for (int j = 0; j < pu.chains; ++j) {
+      W[i * c + 2 * j] = make_double2(i == pu.ind[j][0] ? 1.0 : 0.0, 0.0);
+      W[i * c + 2 * j + 1] = make_double2(i == pu.ind[j][1] ? 1.0 : 0.0, 0.0);
+    }
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void sum_partials_kernel(const double *part, int nb,
                                                               double *out2) {
   __shared__ double sm0[kBlock], sm1[kBlock];
@@ -2793,6 +2889,43 @@ hipError_t launch_spmm2(const SpmvArgs &a, bool split, int mode, double *part, d
   return hipGetLastError();
 }
 
+hipError_t launch_spmm_wide(const SpmvArgs &a, bool split, int nr, const WideOut &o, int grid,
+                            hipStream_t s) {
+  if (nr < 2 || nr > 2 * kEstChainsMax || (nr & 1) || o.ys < 0 || o.ys > nr) return hipErrorInvalidValue;
+  if (o.ys != nr - 2 * (o.fin ? 1 : 0)) return hipErrorInvalidValue;
+#define QSW_L(SP, R) hipLaunchKernelGGL((spmm_wide_kernel<SP, R>), dim3(grid), dim3(kBlock), 0, s, a, o)
+#define QSW_W(R)            \
+  case R:                   \
+    if (split) QSW_L(true, R); \
+    else QSW_L(false, R);   \
+    break;
+  switch (nr) {
+    QSW_W(2) QSW_W(4) QSW_W(6) QSW_W(8) QSW_W(10) QSW_W(12) QSW_W(14) QSW_W(16)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef QSW_W
+#undef QSW_L
+  return hipGetLastError();
+}
+static_assert(2 * kEstChainsMax == 16, "instantiated widths cover every chain count");
+
+hipError_t launch_pack_pairs(double2 *W, int64_t n, const PairSources &ps, hipStream_t s) {
+  if (ps.chains < 1 || ps.chains > kEstChainsMax) return hipErrorInvalidValue;
+  int grid = blocks_for(n);
+  if (grid > 4096) grid = 4096;
+  hipLaunchKernelGGL(pack_pairs_kernel, dim3(grid), dim3(kBlock), 0, s, W, n, ps);
+  return hipGetLastError();
+}
+
+hipError_t launch_unit_pairs(double2 *W, int64_t n, const PairUnits &pu, hipStream_t s) {
+  if (pu.chains < 1 || pu.chains > kEstChainsMax) return hipErrorInvalidValue;
+  int grid = blocks_for(n);
+  if (grid > 4096) grid = 4096;
+  hipLaunchKernelGGL(unit_pairs_kernel, dim3(grid), dim3(kBlock), 0, s, W, n, pu);
+  return hipGetLastError();
+}
+
 hipError_t launch_sum_partials(const double *part, int nblocks, double *out2, hipStream_t s) {
   hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(kBlock), 0, s, part, nblocks, out2);
   return hipGetLastError();
@@ -2804,10 +2937,35 @@ __global__ __launch_bounds__(64) void post_kernel(const double *v, int nv, const
                                                   int ni, const double *extra, HostPost *dst,
                                                   unsigned long long seq) {
   const int t = threadIdx.x;
-  if (t < nv) dst->v[t] = v[t];
-  if (t < ni) dst->i[t] = iv[t];
+  for (int q = t; q < nv; q += 64) dst->v[q] = v[q];
+  for (int q = t; q < ni; q += 64) dst->i[q] = iv[q];
   if (t == 0 && extra) dst->v[nv] = *extra;
+  __syncthreads();
   if (t == 0) __hip_atomic_store(&dst->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__global__ __launch_bounds__(64) void post_list_kernel(PostList l, HostPost *dst,
+                                                       unsigned long long seq) {
+  const int t = threadIdx.x;
+  for (int j = 0; j < l.chains; ++j) {
+    double *dv = dst->v + j * (kTopKMax + 1);
+    int64_t *di = dst->i + j * kTopKMax;
+    if (t < l.nv[j]) dv[t] = l.v[j][t];
+    if (t < l.ni[j]) di[t] = l.i[j][t];
+    if (t == 0 && l.extra[j]) dv[l.nv[j]] = *l.extra[j];
+  }
+  __syncthreads();
+  if (t == 0) __hip_atomic_store(&dst->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+hipError_t launch_post_list(const PostList &l, HostPost *dst, unsigned long long seq,
+                            hipStream_t s) {
+  if (l.chains < 1 || l.chains > kEstChainsMax) return hipErrorInvalidValue;
+  for (int j = 0; j < l.chains; ++j)
+    if (l.nv[j] < 0 || l.ni[j] < 0 || l.nv[j] + 1 > kTopKMax + 1 || l.ni[j] > kTopKMax)
+      return hipErrorInvalidValue;
+  hipLaunchKernelGGL(post_list_kernel, dim3(1), dim3(64), 0, s, l, dst, seq);
+  return hipGetLastError();
 }
 
 hipError_t launch_post(const double *v, int nv, const int64_t *iv, int ni, const double *extra,

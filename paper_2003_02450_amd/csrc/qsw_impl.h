@@ -356,6 +356,40 @@ hipError_t launch_spmm2(const SpmvArgs &a, bool split, int mode, double *part, d
                         double *h, int grid, hipStream_t s);
 hipError_t launch_sum_partials(const double *part, int nblocks, double *out2,
                                hipStream_t s);
+
+// Several estimates at once.  The power chains of the estimates of ||A^p||_1
+// for different p (two columns each) advance together: step i applies A (or
+// A^dagger) to the columns of every chain with p >= i, held interleaved
+// (element (row, c) at row nr + c, chains by decreasing p), so one pass over
+// the matrix serves them all.  The chain with p = i (the last pair of
+// columns) finishes at step i; its epilogue is the two-column product's.
+constexpr int kEstChainsMax = kPMax;  // estimates of p = 2 .. kPMax + 1
+constexpr size_t kEstWideBytes = (size_t)4 << 30;  // largest wide block (three are held)
+constexpr int64_t kEstMergeMaxN = (int64_t)1 << 16;  // merged by default up to this many rows
+struct WideOut {
+  double2 *Y;     // continuing columns: Y[row ys + c], c < ys
+  int ys;         // nr - 2 fin
+  int fin;        // the last pair finishes at this step
+  int mode;       // 1: column sums and sign block; 2: row maxima (of the last pair)
+  double2 *sgn;   // mode 1: sign block of the last pair (n x 2 interleaved)
+  double *h;      // mode 2: h[row] = max |Y_row,c| over the last pair
+  double *part;   // mode 1: per-workgroup column sums of the last pair (2 per workgroup)
+};
+// nr = 2 .. 2 kEstChainsMax, even; a.x holds the nr interleaved columns.
+hipError_t launch_spmm_wide(const SpmvArgs &a, bool split, int nr, const WideOut &o, int grid,
+                            hipStream_t s);
+// W[row c + 2 j + q] = src[j][2 row + q] (j < chains, q < 2; c = 2 chains).
+struct PairSources {
+  const double2 *src[kEstChainsMax];
+  int chains;
+};
+hipError_t launch_pack_pairs(double2 *W, int64_t n, const PairSources &ps, hipStream_t s);
+// W[row c + 2 j + q] = 1 where row = ind[j][q] (ind < 0: none), else 0.
+struct PairUnits {
+  int64_t ind[kEstChainsMax][2];
+  int chains;
+};
+hipError_t launch_unit_pairs(double2 *W, int64_t n, const PairUnits &pu, hipStream_t s);
 // Estimator probe block (column 0 = 1/n, column 1 = signed 1/n; t = 1 zeroes
 // column 1), unit columns [e_i0, e_i1] (i1 < 0: zero), and the top K <= 16
 // of h by (larger value, then smaller index) through grid * K candidates.
@@ -364,7 +398,7 @@ hipError_t launch_probe_init(double2 *X, int64_t n, int t, hipStream_t s);
 // A few results of the 1-norm estimator posted to pinned host memory: the
 // values, the indices, then the sequence number with a system-scope release
 // store, on which the host waits instead of synchronising the stream.
-constexpr int kPostMax = 32;
+constexpr int kPostMax = kEstChainsMax * (kTopKMax + 1);
 struct HostPost {
   double v[kPostMax];
   int64_t i[kPostMax];
@@ -375,6 +409,19 @@ static_assert(kTopKMax + 1 <= kPostMax, "the top-k values and one more fit");
 // then dst->seq = seq; nv + 1, ni <= kPostMax.
 hipError_t launch_post(const double *v, int nv, const int64_t *iv, int ni, const double *extra,
                        HostPost *dst, unsigned long long seq, hipStream_t s);
+// Several chains' results in one post: chain j's nv[j] values at
+// dst->v[j (kTopKMax + 1)], then *extra[j] (if given), and its ni[j] indices
+// at dst->i[j kTopKMax]; nv[j] + 1, ni[j] <= kTopKMax + 1.
+struct PostList {
+  const double *v[kEstChainsMax];
+  const int64_t *i[kEstChainsMax];
+  const double *extra[kEstChainsMax];
+  int nv[kEstChainsMax];
+  int ni[kEstChainsMax];
+  int chains;
+};
+hipError_t launch_post_list(const PostList &l, HostPost *dst, unsigned long long seq,
+                            hipStream_t s);
 hipError_t launch_unit_cols(double2 *X, int64_t n, int64_t i0, int64_t i1, hipStream_t s);
 hipError_t launch_topk(const double *h, int64_t n, int K, int grid, double *cand_v, int64_t *cand_i,
                        double *out_v, int64_t *out_i, hipStream_t s);

@@ -412,6 +412,9 @@ struct Estimator {
     const unsigned long long seq = ++post_seq;
     hipError_t e = launch_post(v, nv, iv, ni, extra, post_dev, seq, s);
     if (e != hipSuccess) return e;
+    return wait_post(seq);
+  }
+  hipError_t wait_post(unsigned long long seq) {
     using clock = std::chrono::steady_clock;
     auto query_at = clock::now() + std::chrono::milliseconds(10);
     for (unsigned spins = 1;; ++spins) {
@@ -473,20 +476,86 @@ struct Estimator {
     return hipSuccess;
   }
 
-  hipError_t estimate(int p, double *est_out, int64_t *index_out, int *probe_out) {
-    const int t = n >= 2 ? 2 : 1;
-    const bool first_known = have_first && Sp[p] != nullptr;
-    hipError_t e = first_known ? hipSuccess : launch_probe_init(X, n, t, s);
-    if (e != hipSuccess) return e;
+  // The decisions of one estimate (Higham and Tisseur's iteration): the
+  // sequential path and the merged chains share them, so both reach the same
+  // estimate from the same products.
+  struct Chain {
+    int p = 0, k = 1;
     double est_old = 0.0, est = 0.0;
     int64_t ind_best = -1;
     int probe_best = 0;
     int64_t ind[2] = {-1, -1};
     std::vector<int64_t> hist;
-    const int itmax = 5;
-    for (int k = 1;; ++k) {
+  };
+  static constexpr int kItMax = 5;
+  int columns() const { return n >= 2 ? 2 : 1; }
+  int want(const Chain &c) const {
+    return (int)std::min<int64_t>(n, (int64_t)columns() + (int64_t)c.hist.size());
+  }
+  static bool want_hb(const Chain &c) { return c.k >= 2 && c.ind_best >= 0; }
+
+  // Y = A^p X of iteration c.k has column 1-norms cs: true when the estimate
+  // is final, else the adjoint product follows.
+  bool after_forward(Chain &c, const double cs[2]) const {
+    const int t = columns();
+    int jbest = 0;
+    c.est = cs[0];
+    if (t == 2 && cs[1] > c.est) {
+      c.est = cs[1];
+      jbest = 1;
+    }
+    if (c.est > c.est_old || c.k == 2) {
+      if (c.k == 1) {
+        c.ind_best = -1;
+        c.probe_best = jbest;
+      } else {
+        c.ind_best = c.ind[jbest];
+      }
+    }
+    if (c.k >= 2 && c.est <= c.est_old) {
+      c.est = c.est_old;
+      return true;
+    }
+    c.est_old = c.est;
+    return c.k > kItMax;
+  }
+
+  // Z = (A^dagger)^p sign(Y), h_i = max_j |Z_ij|: the first `nw` indices by
+  // decreasing h (ties: smaller index; values tv, indices ti) and h at
+  // ind_best (hb, when want_hb) decide the next unit columns (c.ind, c.k
+  // advanced); true when the estimate is final.
+  bool after_adjoint(Chain &c, const double *tv, const int64_t *ti, int nw, double hb) const {
+    const int t = columns();
+    if (c.k >= 2 && c.ind_best >= 0 && tv[0] == hb) return true;
+    auto in_hist = [&](int64_t i) {
+      return std::find(c.hist.begin(), c.hist.end(), i) != c.hist.end();
+    };
+    if (t > 1) {
+      bool all_seen = true;
+      for (int j = 0; j < t && j < nw; ++j)
+        if (!in_hist(ti[j])) all_seen = false;
+      if (all_seen) return true;
+    }
+    int got = 0;
+    for (int q = 0; q < nw && got < t; ++q)
+      if (!in_hist(ti[q])) c.ind[got++] = ti[q];
+    if (got < t) return true;
+    for (int j = 0; j < t; ++j) c.hist.push_back(c.ind[j]);
+    ++c.k;
+    return false;
+  }
+
+  // One estimate, its products one chain at a time.
+  hipError_t estimate(int p, double *est_out, int64_t *index_out, int *probe_out) {
+    const int t = columns();
+    const bool first_known = have_first && Sp[p] != nullptr;
+    hipError_t e = first_known ? hipSuccess : launch_probe_init(X, n, t, s);
+    if (e != hipSuccess) return e;
+    Chain c;
+    c.p = p;
+    for (;;) {
       // Y = A^p X, column 1-norms and S = sign(Y) (k = 1: from first_pass)
-      const bool from_first = k == 1 && first_known;
+      const bool from_first = c.k == 1 && first_known;
       const double2 *sign = from_first ? Sp[p] : S;
       double cs[2] = {0.0, 0.0};
       if (from_first) {
@@ -502,63 +571,164 @@ struct Estimator {
         cs[0] = post_host->v[0];
         cs[1] = post_host->v[1];
       }
-      int jbest = 0;
-      est = cs[0];
-      if (t == 2 && cs[1] > est) {
-        est = cs[1];
-        jbest = 1;
-      }
-      if (est > est_old || k == 2) {
-        if (k == 1) {
-          ind_best = -1;
-          probe_best = jbest;
-        } else {
-          ind_best = ind[jbest];
-        }
-      }
-      if (k >= 2 && est <= est_old) {
-        est = est_old;
-        break;
-      }
-      est_old = est;
-      if (k > itmax) break;
-      // Z = (A^dagger)^p S, h_i = max_j |Z_ij|; the first t + |hist| indices
-      // by decreasing h (ties: smaller index) decide the next columns
+      if (after_forward(c, cs)) break;
       e = power(true, sign, Y, p, 2);
       if (e != hipSuccess) return e;
-      const int want = (int)std::min<int64_t>(n, (int64_t)t + (int64_t)hist.size());
-      e = launch_topk(h, n, want, grid, cand_v, cand_i, top_v, top_i, s);
+      const int nw = want(c);
+      e = launch_topk(h, n, nw, grid, cand_v, cand_i, top_v, top_i, s);
+      if (e != hipSuccess) return e;
+      const bool hb_wanted = want_hb(c);
+      e = fetch(top_v, nw, top_i, nw, hb_wanted ? h + c.ind_best : nullptr);
       if (e != hipSuccess) return e;
       double tv[kTopKMax];
       int64_t ti[kTopKMax];
-      double hb = 0.0;
-      const bool want_hb = k >= 2 && ind_best >= 0;
-      e = fetch(top_v, want, top_i, want, want_hb ? h + ind_best : nullptr);
-      if (e != hipSuccess) return e;
-      for (int j = 0; j < want; ++j) {
+      for (int j = 0; j < nw; ++j) {
         tv[j] = post_host->v[j];
         ti[j] = post_host->i[j];
       }
-      if (want_hb) hb = post_host->v[want];
-      if (k >= 2 && ind_best >= 0 && tv[0] == hb) break;
-      auto in_hist = [&](int64_t i) { return std::find(hist.begin(), hist.end(), i) != hist.end(); };
-      if (t > 1) {
-        bool all_seen = true;
-        for (int j = 0; j < t && j < want; ++j)
-          if (!in_hist(ti[j])) all_seen = false;
-        if (all_seen) break;
-      }
-      int got = 0;
-      for (int q = 0; q < want && got < t; ++q)
-        if (!in_hist(ti[q])) ind[got++] = ti[q];
-      if (got < t) break;
-      for (int j = 0; j < t; ++j) hist.push_back(ind[j]);
-      e = launch_unit_cols(X, n, ind[0], t == 2 ? ind[1] : -1, s);
+      const double hb = hb_wanted ? post_host->v[nw] : 0.0;
+      if (after_adjoint(c, tv, ti, nw, hb)) break;
+      e = launch_unit_cols(X, n, c.ind[0], t == 2 ? c.ind[1] : -1, s);
       if (e != hipSuccess) return e;
     }
-    *est_out = est;
-    *index_out = ind_best;
-    *probe_out = probe_best;
+    *est_out = c.est;
+    *index_out = c.ind_best;
+    *probe_out = c.probe_best;
+    return hipSuccess;
+  }
+
+  // Merged chains (WideOut): wide blocks of n x 2 `width` columns (Win the
+  // phase input, Wa / Wb the steps' outputs), h and column-sum partials per
+  // chain.
+  int width = 0;
+  double2 *Win = nullptr, *Wa = nullptr, *Wb = nullptr;
+  double *hc = nullptr, *partc = nullptr, *sumc = nullptr;
+  double *topc_v = nullptr;
+  int64_t *topc_i = nullptr;
+  int wide_passes = 0;  // matrix passes of the merged chains
+
+  // Steps 1 .. p of the chains `act` (decreasing p, slots into hc / partc /
+  // Sp): Win holds their interleaved inputs; the chain with p = i finishes
+  // at step i with epilogue `mode` (1: sign block into Sp[p], column-sum
+  // partials; 2: h).
+  hipError_t run_chains(bool adjoint, const std::vector<int> &act, const std::vector<int> &slot,
+                        int mode) {
+    const int m0 = (int)act.size();
+    const int pmax = act[0];
+    const double2 *in = Win;
+    int m = m0;
+    for (int i = 1; i <= pmax; ++i) {
+      while (m > 0 && act[m - 1] < i) --m;  // chains still running at step i
+      if (m == 0) break;
+      const int fin = act[m - 1] == i ? 1 : 0;
+      const int sl = slot[m - 1];
+      double2 *out = (i & 1) ? Wa : Wb;
+      WideOut o{};
+      o.Y = out;
+      o.ys = 2 * m - 2 * fin;
+      o.fin = fin;
+      o.mode = fin ? mode : 0;
+      o.sgn = Sp[act[m - 1]];
+      o.h = hc + (size_t)sl * n;
+      o.part = partc + (size_t)sl * 2 * grid;
+      SpmvArgs a = adjoint ? adj : fwd;
+      a.x = in;
+      a.y = nullptr;
+      hipError_t e = launch_spmm_wide(a, adjoint ? asplit : fsplit, 2 * m, o, grid, s);
+      if (e != hipSuccess) return e;
+      products += m;
+      ++wide_passes;
+      in = out;
+    }
+    return hipSuccess;
+  }
+
+  // The estimates of ps (decreasing p) together, after first_pass; the
+  // results are those of estimate(p) for each p, bit for bit.
+  hipError_t estimate_merged(const std::vector<int> &ps, double *est_out, int64_t *index_out,
+                             int *probe_out) {
+    const int g = (int)ps.size();
+    const int t = columns();
+    if (g < 1 || g > width || t != 2) return hipErrorInvalidValue;
+    std::vector<Chain> ch(g);
+    std::vector<bool> done(g, false);
+    for (int j = 0; j < g; ++j) {
+      ch[j].p = ps[j];
+      done[j] = after_forward(ch[j], first_cs[ps[j]]);
+    }
+    hipError_t e = hipSuccess;
+    for (bool adjoint = true;; adjoint = !adjoint) {
+      std::vector<int> act, slot;
+      for (int j = 0; j < g; ++j)
+        if (!done[j]) {
+          act.push_back(ps[j]);
+          slot.push_back(j);
+        }
+      if (act.empty()) break;
+      const int m = (int)act.size();
+      if (adjoint) {
+        PairSources src{};
+        src.chains = m;
+        for (int q = 0; q < m; ++q) src.src[q] = Sp[act[q]];
+        if ((e = launch_pack_pairs(Win, n, src, s)) != hipSuccess) return e;
+        if ((e = run_chains(true, act, slot, 2)) != hipSuccess) return e;
+        PostList pl{};
+        pl.chains = m;
+        for (int q = 0; q < m; ++q) {
+          const Chain &c = ch[slot[q]];
+          const int nw = want(c);
+          double *tv = topc_v + (size_t)q * kTopKMax;
+          int64_t *ti = topc_i + (size_t)q * kTopKMax;
+          const double *hq = hc + (size_t)slot[q] * n;
+          if ((e = launch_topk(hq, n, nw, grid, cand_v, cand_i, tv, ti, s)) != hipSuccess) return e;
+          pl.v[q] = tv;
+          pl.i[q] = ti;
+          pl.nv[q] = nw;
+          pl.ni[q] = nw;
+          pl.extra[q] = want_hb(c) ? hq + c.ind_best : nullptr;
+        }
+        const unsigned long long seq = ++post_seq;
+        if ((e = launch_post_list(pl, post_dev, seq, s)) != hipSuccess) return e;
+        if ((e = wait_post(seq)) != hipSuccess) return e;
+        for (int q = 0; q < m; ++q) {
+          Chain &c = ch[slot[q]];
+          const int nw = pl.nv[q];
+          const double *pv = post_host->v + q * (kTopKMax + 1);
+          const int64_t *pi = post_host->i + q * kTopKMax;
+          double tv[kTopKMax];
+          int64_t ti[kTopKMax];
+          for (int j = 0; j < nw; ++j) {
+            tv[j] = pv[j];
+            ti[j] = pi[j];
+          }
+          const double hb = pl.extra[q] ? pv[nw] : 0.0;
+          done[slot[q]] = after_adjoint(c, tv, ti, nw, hb);
+        }
+      } else {
+        PairUnits pu{};
+        pu.chains = m;
+        for (int q = 0; q < m; ++q) {
+          pu.ind[q][0] = ch[slot[q]].ind[0];
+          pu.ind[q][1] = ch[slot[q]].ind[1];
+        }
+        if ((e = launch_unit_pairs(Win, n, pu, s)) != hipSuccess) return e;
+        if ((e = run_chains(false, act, slot, 1)) != hipSuccess) return e;
+        for (int q = 0; q < m; ++q)
+          if ((e = launch_sum_partials(partc + (size_t)slot[q] * 2 * grid, grid, sumc + 2 * q,
+                                       s)) != hipSuccess)
+            return e;
+        if ((e = fetch(sumc, 2 * m, nullptr, 0, nullptr)) != hipSuccess) return e;
+        for (int q = 0; q < m; ++q) {
+          const double cs[2] = {post_host->v[2 * q], post_host->v[2 * q + 1]};
+          done[slot[q]] = after_forward(ch[slot[q]], cs);
+        }
+      }
+    }
+    for (int j = 0; j < g; ++j) {
+      est_out[j] = ch[j].est;
+      index_out[j] = ch[j].ind_best;
+      probe_out[j] = ch[j].probe_best;
+    }
     return hipSuccess;
   }
 };
@@ -1259,15 +1429,55 @@ qsw_status_t build_common(std::shared_ptr<Assembler> src, double omega, hipStrea
     if (e == hipSuccess) e = post_get(&E.post_host, &E.post_dev);
     if (e == hipSuccess) E.post_seq = __atomic_load_n(&E.post_host->seq, __ATOMIC_ACQUIRE);
     if (e != hipSuccess) break;
+    // Chains merged per matrix pass (QSW_EST_CHAINS; 1: one estimate at a
+    // time).  By default only for operators of at most kEstMergeMaxN rows:
+    // there the launches and host round trips they save dominate (N = 256:
+    // build 2.87 -> 2.52 ms), while on larger ones the wide blocks' gathers,
+    // unstaged and many columns wide, cost more than the passes they save
+    // (N = 1024: 21.1 -> 36.3 ms).
+    const int dflt = n <= kEstMergeMaxN ? kEstChainsMax : 1;
+    E.width = std::min(kEstChainsMax, std::max(1, env_int("QSW_EST_CHAINS", dflt)));
+    E.width = (int)std::min<int64_t>(E.width, (int64_t)(kEstWideBytes / (2 * sizeof(double2) * (size_t)n)));
+    if (n < 2) E.width = 1;
+    if (E.width >= 2) {
+      const size_t wide = 2 * (size_t)E.width * (size_t)n;
+      if ((e = dalloc(&E.Win, wide)) != hipSuccess) break;
+      if ((e = dalloc(&E.Wa, wide)) != hipSuccess) break;
+      if ((e = dalloc(&E.Wb, wide)) != hipSuccess) break;
+      if ((e = dalloc(&E.hc, (size_t)E.width * (size_t)n)) != hipSuccess) break;
+      if ((e = dalloc(&E.partc, (size_t)E.width * 2 * (size_t)E.grid)) != hipSuccess) break;
+      if ((e = dalloc(&E.sumc, 2 * (size_t)E.width)) != hipSuccess) break;
+      if ((e = dalloc(&E.topc_v, (size_t)E.width * kTopKMax)) != hipSuccess) break;
+      if ((e = dalloc(&E.topc_i, (size_t)E.width * kTopKMax)) != hipSuccess) break;
+    }
     if ((e = E.first_pass(kPMax + 1)) != hipSuccess) break;
-    for (int p = 2; p <= kPMax + 1; ++p) {
-      double est = 0.0;
-      int64_t idx = -1;
-      int probe = 0;
-      if ((e = E.estimate(p, &est, &idx, &probe)) != hipSuccess) break;
-      h->info.d[p] = std::pow(est, 1.0 / p);
-      h->info.d_index[p] = idx;
-      h->info.d_probe[p] = probe;
+    if (E.width >= 2) {
+      // groups of `width` estimates, largest p first
+      for (int top = kPMax + 1; top >= 2 && e == hipSuccess;) {
+        std::vector<int> ps;
+        for (int p = top; p >= 2 && (int)ps.size() < E.width; --p) ps.push_back(p);
+        top -= (int)ps.size();
+        double est[kEstChainsMax];
+        int64_t idx[kEstChainsMax];
+        int probe[kEstChainsMax];
+        if ((e = E.estimate_merged(ps, est, idx, probe)) != hipSuccess) break;
+        for (size_t j = 0; j < ps.size(); ++j) {
+          h->info.d[ps[j]] = std::pow(est[j], 1.0 / ps[j]);
+          h->info.d_index[ps[j]] = idx[j];
+          h->info.d_probe[ps[j]] = probe[j];
+        }
+      }
+      if (e != hipSuccess) break;
+    } else {
+      for (int p = 2; p <= kPMax + 1; ++p) {
+        double est = 0.0;
+        int64_t idx = -1;
+        int probe = 0;
+        if ((e = E.estimate(p, &est, &idx, &probe)) != hipSuccess) break;
+        h->info.d[p] = std::pow(est, 1.0 / p);
+        h->info.d_index[p] = idx;
+        h->info.d_probe[p] = probe;
+      }
     }
   } while (false);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1276,6 +1486,8 @@ qsw_status_t build_common(std::shared_ptr<Assembler> src, double omega, hipStrea
   dfree(E.X); dfree(E.Y); dfree(E.W0); dfree(E.W1); dfree(E.S); dfree(E.h); dfree(E.part); dfree(E.sums);
   dfree(E.cand_v); dfree(E.cand_i); dfree(E.top_v); dfree(E.top_i);
   dfree(E.first_sums);
+  dfree(E.Win); dfree(E.Wa); dfree(E.Wb); dfree(E.hc); dfree(E.partc); dfree(E.sumc);
+  dfree(E.topc_v); dfree(E.topc_i);
   for (double2 *&b : E.Sp) dfree(b);
   // back to the pool only with no post in flight (else it is left allocated)
   if (e == hipSuccess || hipStreamSynchronize(s) == hipSuccess) post_put(E.post_host, E.post_dev);
