@@ -397,9 +397,11 @@ qsw_status_t qsw_last_stats(qsw_superop_t h, qsw_stats_t *st);
  * together in one engine, so small operators share launches and each
  * operator's values are read once per product for all n0 right-hand sides.
  *
- *   op:    built handle, on the engine's device; its precision applies (QSW_PREC_DOUBLE
- *          or QSW_PREC_SINGLE; QSW_ERR_STATE for QSW_PREC_FP32).  It
- *          must stay alive until the walk has finished.
+ *   op:    built handle, on the engine's device; its precision applies
+ *          (QSW_PREC_DOUBLE, QSW_PREC_SINGLE, or QSW_PREC_FP32: single-precision
+ *          products with hi + lo accumulation and the FP64 trace check at every
+ *          point, exactly as qsw_propagate runs them).  It must stay alive until
+ *          the walk has finished; walks of every precision share one engine.
  *   rho0:  device, n0 consecutive N*N complex128 row-major matrices.
  *   out:   device, (n_steps+1) x n0 x N*N complex128 (point-major), or NULL.
  *   pops:  device, (n_steps+1) x n0 x N doubles (Re rho_aa), or NULL.
@@ -431,16 +433,20 @@ typedef struct {
     int32_t rounds;      /* launch shape in use: work-launch grid of `rounds` x the
                             resident workgroups (at most one wave per block) */
     int32_t staged;      /*   and rho-row staging in LDS on (1) or off (0) */
+    double trace_dev;    /* walks with single-precision products (QSW_PREC_FP32): largest
+                            |Tr rho_k - Tr rho0| of their checked points before scaling, over
+                            the finished walks and their right-hand sides */
 } qsw_engine_stats_t;
 
 /* Device bytes one walk takes in an engine with `rhs` (1, 2 or 4)
- * right-hand sides: six work vectors of n*rhs complex128, plus m stored
- * powers in the time-series branch.  0 for a bad walk. */
+ * right-hand sides: six work vectors of n*rhs complex128 (complex64 with
+ * single-precision products), plus m stored powers in the time-series
+ * branch.  0 for a bad walk. */
 size_t qsw_walk_bytes(const qsw_walk_t *walk, int32_t rhs);
 
 /* Bytes the engine's own tables take at the start of its arena.  The engine
  * also keeps a map of the running walks' 64-row blocks: about
- * arena_bytes / (768 rhs) + 8 (max_walks + 1) bytes after the tables. */
+ * arena_bytes / (384 rhs) + 8 (max_walks + 1) bytes after the tables. */
 size_t qsw_engine_table_bytes(int32_t max_walks);
 
 /*

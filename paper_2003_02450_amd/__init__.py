@@ -511,7 +511,8 @@ class Engine:
 def _engine_stats_dict(s) -> dict:
     return {"cycles": s.cycles, "products": s.products, "live": s.live,
             "nonfinite": bool(s.nonfinite), "ms": s.ms, "bytes": s.bytes, "graphs": s.graphs,
-            "graph_launches": s.graph_launches, "rounds": s.rounds, "staged": bool(s.staged)}
+            "graph_launches": s.graph_launches, "rounds": s.rounds, "staged": bool(s.staged),
+            "trace_dev": s.trace_dev}
 
 
 def batch_propagate(walks, rhs=None, workspace=None):

@@ -82,7 +82,7 @@ class EngineStats(ctypes.Structure):
                 ("live", ctypes.c_int32), ("nonfinite", ctypes.c_int32), ("ms", ctypes.c_double),
                 ("bytes", ctypes.c_double), ("graphs", ctypes.c_int64),
                 ("graph_launches", ctypes.c_int64), ("rounds", ctypes.c_int32),
-                ("staged", ctypes.c_int32)]
+                ("staged", ctypes.c_int32), ("trace_dev", ctypes.c_double)]
 
 
 class ServerStats(ctypes.Structure):

@@ -92,12 +92,12 @@ struct WalkPlan {
 
 qsw_status_t plan_walk(const qsw_walk_t *w, int32_t rhs, WalkPlan &W) {
   if (!w || !w->op || !w->rho0 || w->n0 < 1 || w->n0 > rhs || w->n_steps < 0) return QSW_ERR_ARG;
-  // the engine's products are complex128 (single-precision products run in
-  // qsw_propagate only)
-  if (w->op->prec == QSW_PREC_FP32) return QSW_ERR_STATE;
   qsw_status_t st = make_plan(w->op, w->t0, w->dt, w->n_steps, W.P);
   if (st != QSW_OK) return st;
-  W.vec = align256((size_t)w->op->n * rhs * sizeof(double2));
+  // single-precision products (one single-time application per interval):
+  // two hi + lo state pairs and two terms of complex64
+  const bool p32 = w->op->prec == QSW_PREC_FP32;
+  W.vec = align256((size_t)w->op->n * rhs * (p32 ? sizeof(float2) : sizeof(double2)));
   W.total = 6 * W.vec;
   if (W.P.branch == 1)
     W.total += (size_t)W.P.m * W.vec + align256((size_t)(W.P.m + 1) * kBatchMaxRhs * sizeof(double));
@@ -107,6 +107,7 @@ qsw_status_t plan_walk(const qsw_walk_t *w, int32_t rhs, WalkPlan &W) {
     c += q * ((int64_t)W.P.m * W.P.s + 1);
   else
     c += ((int64_t)W.P.j + 1) * (1 + (int64_t)W.P.d * (W.P.m + 1));
+  if (p32) c += q + 2;  // the reference trace and one trace check per point
   W.max_cycles = c + 2;
   return QSW_OK;
 }
@@ -130,10 +131,10 @@ struct Tables {
 };
 
 // Entries of the block map for a pool of `pool` bytes: a walk's six work
-// vectors take at least 6 * 64 * rhs * 16 bytes per full 64-row block, plus
-// one ragged block per walk.
+// vectors take at least 6 * 64 * rhs * 8 bytes per full 64-row block
+// (complex64 vectors), plus one ragged block per walk.
 int64_t map_entries(size_t pool, int32_t rhs, int32_t cap) {
-  return (int64_t)(pool / (6 * 64 * 16 * (size_t)rhs)) + cap + 1;
+  return (int64_t)(pool / (6 * 64 * 8 * (size_t)rhs)) + cap + 1;
 }
 
 // Host copy of the control state read back after each chunk.
@@ -176,12 +177,13 @@ struct qsw_engine_s {
   qsw_engine_stats_t stats{};
   std::vector<double> wbytes;    // per slot: algorithmic bytes of one product
   std::vector<int> f32;          // per slot: single-precision values
+  std::vector<int> p32;          // per slot: single-precision products
   std::vector<double> went;      // per slot: stored entries of the walk's layout
   // chunk graph: captured on a private stream, launched on `stream`
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec = nullptr;
   BatchArgs gargs{};
-  int ggrid = 0, gchunk = 0;
+  int ggrid = 0, gchunk = 0, gkinds = 0;
   bool use_graph = true;
   // launch shape: work-launch grid = rounds x resident workgroups (at most
   // one wave per block), rho-row staging on or off
@@ -246,6 +248,21 @@ int64_t total_blocks(const qsw_engine_s *e) {
   return t;
 }
 
+// Work kernels a cycle needs: bit 0 double products, bit 1 single-precision
+// products (a walk's load, checks and emissions run in its own kind).
+int work_kinds(const qsw_engine_s *e) {
+  int k = 0;
+  for (int32_t b : e->act) k |= e->p32[b] ? 2 : 1;
+  return k;
+}
+
+hipError_t launch_cycle(const qsw_engine_s *e, int grid, int kinds, hipStream_t s) {
+  hipError_t err = launch_batch_control(e->args, s);
+  if (err == hipSuccess && (kinds & 1)) err = launch_batch_work(e->args, e->rhs, false, grid, s);
+  if (err == hipSuccess && (kinds & 2)) err = launch_batch_work(e->args, e->rhs, true, grid, s);
+  return err;
+}
+
 // Read back the control state; release finished walks.
 qsw_status_t collect(qsw_engine_s *e) {
   HIP_TRY(hipMemcpyAsync(e->h_ctl, e->arena + e->tab.ctl, sizeof(BatchCtl) * (size_t)e->cap,
@@ -261,6 +278,9 @@ qsw_status_t collect(qsw_engine_s *e) {
     e->running[b] = 0;
     e->stats.products += e->h_ctl[b].products;
     e->stats.bytes += (double)e->h_ctl[b].products * e->wbytes[b];
+    double tdev = 0.0;  // non-negative: its bits order as the values
+    std::memcpy(&tdev, &e->h_ctl[b].trace_dev, sizeof(double));
+    e->stats.trace_dev = std::max(e->stats.trace_dev, tdev);
     e->finished.push_back(e->ticket[b]);
     e->ticket[b] = -1;
     e->pool.give(e->off[b] - e->pool_base, e->bytes[b]);
@@ -279,9 +299,9 @@ constexpr int kTuneCount = 4;
 constexpr int kTuneShapes[kTuneCount][2] = {{1, 1}, {2, 1}, {1, 0}, {2, 0}};
 
 struct TuneKey {
-  int rhs = 0, f32 = 0, nlog = 0, epr = 0;
+  int rhs = 0, f32 = 0, p32 = 0, nlog = 0, epr = 0;
   bool operator<(const TuneKey &o) const {
-    return std::tie(rhs, f32, nlog, epr) < std::tie(o.rhs, o.f32, o.nlog, o.epr);
+    return std::tie(rhs, f32, p32, nlog, epr) < std::tie(o.rhs, o.f32, o.p32, o.nlog, o.epr);
   }
 };
 
@@ -290,8 +310,9 @@ std::map<TuneKey, std::pair<int, int>> &tune_cache() {
   return c;
 }
 
-// The batch's key: right-hand sides, single-precision values on any walk,
-// log2 of the largest graph order, entries per row of all running walks.
+// The batch's key: right-hand sides, single-precision values and
+// single-precision products on any walk, log2 of the largest graph order,
+// entries per row of all running walks.
 TuneKey tune_key(const qsw_engine_s *e) {
   TuneKey k;
   k.rhs = e->rhs;
@@ -300,6 +321,7 @@ TuneKey tune_key(const qsw_engine_s *e) {
   for (int32_t b : e->act) {
     nmax = std::max(nmax, e->N[b]);
     k.f32 |= e->f32[b];
+    k.p32 |= e->p32[b];
     ent += e->went[b];
     rows += (double)e->N[b] * e->N[b];
   }
@@ -317,8 +339,9 @@ void set_shape(qsw_engine_s *e, int rounds, int stage) {
 // graph when possible.  The graph is captured again when the arguments or
 // the shape changed; any capture failure falls back to direct launches.
 hipError_t run_chunk(qsw_engine_s *e, int grid, int chunk) {
+  const int kinds = work_kinds(e);
   if (e->use_graph) {
-    const bool same = e->gexec && e->ggrid == grid && e->gchunk == chunk &&
+    const bool same = e->gexec && e->ggrid == grid && e->gchunk == chunk && e->gkinds == kinds &&
                       std::memcmp(&e->gargs, &e->args, sizeof(BatchArgs)) == 0;
     if (!same) {
       if (e->gexec) {
@@ -327,10 +350,8 @@ hipError_t run_chunk(qsw_engine_s *e, int grid, int chunk) {
       }
       hipError_t err = hipStreamBeginCapture(e->cap_stream, hipStreamCaptureModeThreadLocal);
       if (err == hipSuccess) {
-        for (int c = 0; c < chunk && err == hipSuccess; ++c) {
-          err = launch_batch_control(e->args, e->cap_stream);
-          if (err == hipSuccess) err = launch_batch_work(e->args, e->rhs, grid, e->cap_stream);
-        }
+        for (int c = 0; c < chunk && err == hipSuccess; ++c)
+          err = launch_cycle(e, grid, kinds, e->cap_stream);
         hipGraph_t graph = nullptr;
         const hipError_t end = hipStreamEndCapture(e->cap_stream, &graph);
         if (err == hipSuccess) err = end;
@@ -346,6 +367,7 @@ hipError_t run_chunk(qsw_engine_s *e, int grid, int chunk) {
         e->gargs = e->args;
         e->ggrid = grid;
         e->gchunk = chunk;
+        e->gkinds = kinds;
         e->stats.graphs += 1;
       }
     }
@@ -355,8 +377,7 @@ hipError_t run_chunk(qsw_engine_s *e, int grid, int chunk) {
     }
   }
   for (int c = 0; c < chunk; ++c) {
-    hipError_t err = launch_batch_control(e->args, e->stream);
-    if (err == hipSuccess) err = launch_batch_work(e->args, e->rhs, grid, e->stream);
+    hipError_t err = launch_cycle(e, grid, kinds, e->stream);
     if (err != hipSuccess) return err;
   }
   return hipSuccess;
@@ -417,6 +438,7 @@ qsw_status_t qsw_engine_create(int32_t max_walks, int32_t rhs, void *arena, size
   e->running.assign(max_walks, 0);
   e->wbytes.assign(max_walks, 0.0);
   e->f32.assign(max_walks, 0);
+  e->p32.assign(max_walks, 0);
   e->went.assign(max_walks, 0.0);
   e->use_graph = env_int("QSW_BATCH_GRAPH", 1) != 0;
   if (hipStreamCreate(&e->cap_stream) != hipSuccess) return fail(QSW_ERR_DEVICE);
@@ -537,6 +559,16 @@ qsw_status_t qsw_engine_submit(qsw_engine_t e, const qsw_walk_t *w, int64_t *tic
   I.rho0 = (const double2 *)w->rho0;
   I.out = (double2 *)w->out;
   I.pops = (double *)w->pops;
+  I.prec32 = h->prec == QSW_PREC_FP32 ? 1 : 0;
+  if (I.prec32) {
+    // the same six vectors as hi + lo state pairs and terms of complex64
+    for (int v = 0; v < 2; ++v) {
+      I.Ph[v] = (float2 *)(base + (size_t)(2 * v) * W.vec);
+      I.Pl[v] = (float2 *)(base + (size_t)(2 * v + 1) * W.vec);
+      I.B32[v] = (float2 *)(base + (size_t)(4 + v) * W.vec);
+      I.V[v] = I.F[v] = I.B[v] = nullptr;
+    }
+  }
   BatchCtl &C = e->h_ctl[b];
   std::memset(&C, 0, sizeof(C));
   C.pc = 0;  // load
@@ -553,14 +585,18 @@ qsw_status_t qsw_engine_submit(qsw_engine_t e, const qsw_walk_t *w, int64_t *tic
   {
     // one product: each stored entry's column and value, the block-shared
     // entries, row data and the diagonal per row, and for every column x
-    // read, the term written and the accumulator read and written
-    const bool f32 = I.f32 != 0, split = I.split != 0;
+    // read, the term written and the accumulator read and written (64
+    // bytes per element; 48 with single-precision products: complex64 x and
+    // term, the accumulator a pair of complex64)
+    const bool p32 = I.prec32 != 0;
+    const bool f32 = I.f32 != 0 || p32, split = I.split != 0;
     const double entry = split ? (f32 ? 8.0 : 12.0) : (f32 ? 12.0 : 20.0);
     const double diag = split ? (f32 ? 8.0 : 16.0) : 0.0;
     e->wbytes[b] = entry * (double)h->wentries + 16.0 * (double)h->wshared +
                    8.0 * (double)(h->n + 1) + diag * (double)h->n +
-                   64.0 * (double)e->rhs * (double)h->n;
-    e->f32[b] = f32 ? 1 : 0;
+                   (p32 ? 48.0 : 64.0) * (double)e->rhs * (double)h->n;
+    e->f32[b] = I.f32 != 0 ? 1 : 0;
+    e->p32[b] = p32 ? 1 : 0;
     e->went[b] = (double)h->wentries;
   }
   e->N[b] = h->N;

@@ -590,7 +590,7 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
                                              Epi &epi, const VecT<X32> *xs, int64_t base,
                                              bool staged = true, int64_t span = 0) {
   // X32: complex64 x, single-precision values and sums (F32 layouts only)
-  static_assert(!X32 || (F32 && NRHS == 1 && !SOA), "single-precision products");
+  static_assert(!X32 || F32, "single-precision products read single-precision values");
   using V = VecT<X32>;
   using R = RealT<X32>;
   // one right-hand side: xs holds x[base .. base + span) (span = N by default)
@@ -883,12 +883,13 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
   if (lane < nr) epi(r0 + orow, acc, pre);
 }
 
-template <int NRHS, bool F32, bool STAGE, class Epi, bool SOA = false, bool SPLIT = false>
+template <int NRHS, bool F32, bool STAGE, class Epi, bool SOA = false, bool SPLIT = false,
+          bool X32 = false>
 __device__ __forceinline__ void wave_block(const SpmvArgs &a, int64_t k, Epi &epi,
-                                           const double2 *xs, int64_t base, bool staged = true,
+                                           const VecT<X32> *xs, int64_t base, bool staged = true,
                                            int64_t span = 0) {
   const WaveHead hd = wave_head<F32, SPLIT>(a, k);
-  wave_block_h<NRHS, F32, STAGE, Epi, SOA, SPLIT>(a, k, hd, epi, xs, base, staged, span);
+  wave_block_h<NRHS, F32, STAGE, Epi, SOA, SPLIT, X32>(a, k, hd, epi, xs, base, staged, span);
 }
 
 // xs[0 .. cnt) = src[0 .. cnt) by the whole workgroup, cnt at most the
@@ -2157,7 +2158,9 @@ enum BatchPc : int32_t {
   PC_SBLOCK,
   PC_SPOINT0,
   PC_SPOINT,
-  PC_SAFTER_EMIT
+  PC_SAFTER_EMIT,
+  PC_TREF,   // single-precision products: reference trace after the load
+  PC_EMIT2   //   the emission after the point's trace check
 };
 
 __device__ void batch_issue_term(const BatchInst &I, const BatchCtl &C, BatchOp &O) {
@@ -2172,6 +2175,29 @@ __device__ void batch_issue_term(const BatchInst &I, const BatchCtl &C, BatchOp 
   O.y = I.B[j & 1];
   O.fin = (j == 1) ? src : dst;
   O.fout = dst;
+}
+
+// Single-precision products: term j of the scaling step from state pair
+// `cur` into the other pair (as qsw_propagate's single-precision steps).
+__device__ void batch_issue_term32(const BatchInst &I, const BatchCtl &C, BatchOp &O) {
+  const int j = C.j, src = C.cur, dst = C.cur ^ 1;
+  O.type = BOP_TERM;
+  O.active = C.active;
+  O.first = (j == 1);
+  O.alpha = C.tseg / ((double)C.sseg * (double)j);
+  O.x32 = (j == 1) ? I.Ph[src] : I.B32[(j - 1) & 1];
+  O.y32 = I.B32[j & 1];
+  O.fin_hi = (j == 1) ? I.Ph[src] : I.Ph[dst];
+  O.fin_lo = (j == 1) ? I.Pl[src] : I.Pl[dst];
+  O.fout_hi = I.Ph[dst];
+  O.fout_lo = I.Pl[dst];
+}
+
+__device__ void batch_issue(const BatchInst &I, const BatchCtl &C, BatchOp &O) {
+  if (I.prec32)
+    batch_issue_term32(I, C, O);
+  else
+    batch_issue_term(I, C, O);
 }
 
 __device__ void batch_issue_series(const BatchInst &I, const BatchCtl &C, BatchOp &O) {
@@ -2241,6 +2267,9 @@ __device__ void batch_advance(const BatchInst &I, BatchCtl &C, BatchOp &O, Batch
     case BOP_NORM:
       for (int c = 0; c < kBatchMaxRhs; ++c) I.kn[c] = b0[c];
       break;
+    case BOP_TRACE:
+      C.trace_dev = C.trace_dev > S.trace_dev ? C.trace_dev : S.trace_dev;
+      break;
     default:
       break;
   }
@@ -2250,13 +2279,21 @@ __device__ void batch_advance(const BatchInst &I, BatchCtl &C, BatchOp &O, Batch
     switch (C.pc) {
       case PC_LOAD:
         O.type = BOP_LOAD;
-        C.pc = PC_START;
+        C.pc = I.prec32 ? PC_TREF : PC_START;
         C.last = BOP_LOAD;
+        return;
+      case PC_TREF:  // the loaded state's trace: every later point's reference
+        O.type = BOP_TRACE;
+        O.first = 1;
+        O.fout_hi = I.Ph[0];
+        O.fout_lo = I.Pl[0];
+        C.pc = PC_START;
+        C.last = BOP_TRACE;
         return;
       case PC_START:
         if (I.t0 != 0.0 && I.m0 > 0) {
           batch_start_segment(C, 0, I.t0, I.m0, I.s0, all);
-          batch_issue_term(I, C, O);
+          batch_issue(I, C, O);
           C.pc = PC_TERMS;
           C.last = BOP_TERM;
           return;
@@ -2273,28 +2310,49 @@ __device__ void batch_advance(const BatchInst &I, BatchCtl &C, BatchOp &O, Batch
           if (act) {
             C.active = act;
             ++C.j;
-            batch_issue_term(I, C, O);
+            batch_issue(I, C, O);
             C.last = BOP_TERM;
             return;
           }
         }
-        ++C.i;  // the scaling step is complete
+        // the scaling step is complete (single-precision products: its
+        // accumulator pair is the state from now on)
+        if (I.prec32) C.cur ^= 1;
+        ++C.i;
         if (C.i < C.sseg) {
           C.j = 1;
           C.active = all;
-          batch_issue_term(I, C, O);
+          batch_issue(I, C, O);
           C.last = BOP_TERM;
           return;
         }
-        C.cur ^= 1;  // the segment is complete
+        if (!I.prec32) C.cur ^= 1;  // the segment is complete
         C.point = (C.seg == 0) ? 0 : C.point + 1;
         C.pc = PC_EMIT;
         continue;
       }
       case PC_EMIT:
+        // single-precision products: the trace check first, except for
+        // point 0 at t0 = 0 (rho0 itself is emitted)
+        if (I.prec32 && !(C.point == 0 && I.t0 == 0.0)) {
+          O.type = BOP_TRACE;
+          O.first = 0;
+          O.fout_hi = I.Ph[C.cur];
+          O.fout_lo = I.Pl[C.cur];
+          C.pc = PC_EMIT2;
+          C.last = BOP_TRACE;
+          return;
+        }
+        [[fallthrough]];
+      case PC_EMIT2:
         O.type = BOP_EMIT;
         O.point = C.point;
         O.x = I.V[C.cur];
+        if (I.prec32) {
+          O.first = (C.point == 0 && I.t0 == 0.0) ? 1 : 0;  // 1: copy rho0
+          O.fout_hi = I.Ph[C.cur];
+          O.fout_lo = I.Pl[C.cur];
+        }
         C.pc = PC_AFTER_EMIT;
         C.last = BOP_EMIT;
         return;
@@ -2310,7 +2368,7 @@ __device__ void batch_advance(const BatchInst &I, BatchCtl &C, BatchOp &O, Batch
             continue;
           }
           batch_start_segment(C, 1, I.dt, I.m, I.s, all);
-          batch_issue_term(I, C, O);
+          batch_issue(I, C, O);
           C.pc = PC_TERMS;
           C.last = BOP_TERM;
           return;
@@ -2451,6 +2509,94 @@ struct BatchTermEpi {  // TERM and POWACC: y = alpha A x; accumulate active colu
 };
 
 
+// Single-precision products: y = alpha A x in complex64 (the row sum scaled
+// in double and rounded once), added by two-sum to the active columns' hi +
+// lo accumulator pairs; the norms as in Taylor32Epi.
+template <int R>
+struct BatchTerm32Epi {
+  int64_t n;  // column stride of the vectors
+  double alpha;
+  const float2 *fin_hi, *fin_lo;
+  float2 *fout_hi, *fout_lo, *y;
+  uint32_t active;
+  bool first;
+  unsigned long long my[R], mf[R], mb0[R];
+  typedef NoPre Pre;
+  __device__ __forceinline__ Pre pre(int64_t) const { return Pre{}; }
+  __device__ __forceinline__ void operator()(int64_t row, const float *acc, Pre) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const float2 yv = make_float2((float)(alpha * (double)acc[2 * r]),
+                                    (float)(alpha * (double)acc[2 * r + 1]));
+      gst(y + r * n + row, yv);
+      my[r] = umax(my[r], abs_bits(cabs2(make_double2((double)yv.x, (double)yv.y))));
+      if ((active >> r) & 1u) {
+        const float2 fh = gld(fin_hi + r * n + row), fl = gld(fin_lo + r * n + row);
+        if (first) mb0[r] = umax(mb0[r], abs_bits(cabs_df(fh, fl)));
+        float2 h, l;
+        df_add(fh.x, fl.x, yv.x, h.x, l.x);
+        df_add(fh.y, fl.y, yv.y, h.y, l.y);
+        gst(fout_hi + r * n + row, h);
+        gst(fout_lo + r * n + row, l);
+        mf[r] = umax(mf[r], abs_bits(cabs_df(h, l)));
+      }
+    }
+  }
+};
+
+// Tr of a state pair by one wavefront, in trace32_kernel's order: kBlock
+// strided partial sums (lane l holds those of threads l + 64 q), then the
+// same tree (levels of 64 and more within the lanes, the rest across them).
+// Every lane returns the sum.
+__device__ double wave_trace(const float2 *hi, const float2 *lo, int32_t N) {
+  constexpr int Q = kBlock / 64 > 0 ? kBlock / 64 : 1;
+  const int l = threadIdx.x & 63;
+  double p[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    double acc = 0.0;
+    for (int64_t a = l + 64 * q; a < N; a += kBlock) {
+      const int64_t i = a * (N + 1);
+      acc += (double)gld(hi + i).x + (double)gld(lo + i).x;
+    }
+    p[q] = acc;
+  }
+#pragma unroll
+  for (int w = kBlock / 2; w >= 64; w >>= 1) {
+    const int wq = w / 64;
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+      if (q < wq) p[q] += p[q + wq];
+  }
+  double v = p[0];
+  for (int w = 32; w >= 1; w >>= 1) {
+    const double o = __shfl_down(v, w, 64);
+    if (l < w) v += o;
+  }
+  return __shfl(v, 0, 64);
+}
+
+// xs[r N0 + c] = x0[r n0r + base + c] (all R columns), four loads per thread
+// in flight before their LDS writes (one round trip per 4 kBlock elements
+// instead of per kBlock; more would cost registers here).
+template <int R, class T>
+__device__ __forceinline__ void batch_stage(T *xs, const T *x0, int64_t n0r, int64_t base,
+                                            int N0) {
+  const int cnt = R * N0;
+  for (int i0 = threadIdx.x; i0 < cnt; i0 += 4 * kBlock) {
+    T v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = min(i0 + u * kBlock, cnt - 1);
+      const int r = i / N0;
+      v[u] = gld(x0 + (int64_t)r * n0r + base + (i - r * N0));
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i0 + u * kBlock < cnt) xs[i0 + u * kBlock] = v[u];
+  }
+}
+
 __device__ __forceinline__ void batch_flush(unsigned long long v, unsigned long long *dst) {
   v = wave_umax(v);
   if ((threadIdx.x & 63) == 0 && v) atomicMax(dst, v);
@@ -2473,7 +2619,9 @@ __global__ void batch_blocks_kernel(BatchArgs A) {
 // Staging of the rho-row for the rho-H gathers (as in the single-walk
 // engine, for all R columns): decided per workgroup from the walk of its
 // first block, used by the waves whose block belongs to that walk.
-template <int R>
+// P32: the walks with single-precision products (the others skip theirs);
+// a cycle with walks of both kinds launches both kernels.
+template <int R, bool P32>
 __global__ __launch_bounds__(kBlock, (R >= 2 ? 4 : 1)) void batch_work_kernel(BatchArgs A) {
   constexpr int WPB = kBlock / 64;
   extern __shared__ double2 xs[];
@@ -2496,31 +2644,18 @@ __global__ __launch_bounds__(kBlock, (R >= 2 ? 4 : 1)) void batch_work_kernel(Ba
         const int2 f = A.blkmap[kb];
         const int t0 = A.op[f.x].type;
         const int32_t N0 = A.inst[f.x].N;
-        if ((t0 == BOP_TERM || t0 == BOP_POWACC) &&
-            (int64_t)R * N0 * (int64_t)sizeof(double2) <= A.stage_bytes) {
+        const bool mine = (A.inst[f.x].prec32 != 0) == P32;
+        const int64_t esz = P32 ? (int64_t)sizeof(float2) : (int64_t)sizeof(double2);
+        if (mine && (t0 == BOP_TERM || t0 == BOP_POWACC) &&
+            (int64_t)R * N0 * esz <= A.stage_bytes) {
           sb = f.x;
           const int64_t n0r = A.inst[f.x].n;
-          const double2 *x0 = A.op[f.x].x;
           base = ((int64_t)f.y * kWaveRows) / N0 * N0;
           __syncthreads();  // earlier blocks are done with xs
-          // xs[r N0 + c] = x0[r n0r + base + c], four loads per thread in
-          // flight before their LDS writes (one round trip per 4 kBlock
-          // elements instead of per kBlock; more would cost registers here)
-          {
-            const int cnt = R * N0;
-            for (int i0 = threadIdx.x; i0 < cnt; i0 += 4 * kBlock) {
-              double2 v[4];
-#pragma unroll
-              for (int u = 0; u < 4; ++u) {
-                const int i = min(i0 + u * kBlock, cnt - 1);
-                const int r = i / N0;
-                v[u] = gld(x0 + (int64_t)r * n0r + base + (i - r * N0));
-              }
-#pragma unroll
-              for (int u = 0; u < 4; ++u)
-                if (i0 + u * kBlock < cnt) xs[i0 + u * kBlock] = v[u];
-            }
-          }
+          if constexpr (P32)
+            batch_stage<R>(reinterpret_cast<float2 *>(xs), A.op[f.x].x32, n0r, base, N0);
+          else
+            batch_stage<R>(xs, A.op[f.x].x, n0r, base, N0);
           __syncthreads();
         }
       }
@@ -2532,6 +2667,7 @@ __global__ __launch_bounds__(kBlock, (R >= 2 ? 4 : 1)) void batch_work_kernel(Ba
       const int type = O.type;
       if (type == BOP_NONE) continue;
       const BatchInst &I = A.inst[b];
+      if ((I.prec32 != 0) != P32) continue;  // the other kernel's walk
       BatchSlots *S = &A.slots[b];
       const int64_t k = bk.y;
       const int64_t r0 = k * kWaveRows;
@@ -2540,6 +2676,124 @@ __global__ __launch_bounds__(kBlock, (R >= 2 ? 4 : 1)) void batch_work_kernel(Ba
       const int64_t row = r0 + lane;
       const bool live = lane < nr;
       const double2 *ox = O.x;
+      if constexpr (P32) {
+      if (type == BOP_TERM) {
+        SpmvArgs a{};
+        a.n = n;
+        a.rp = I.rp;
+        a.wcol = I.wcol;
+        a.wval32 = I.wval32;
+        a.wcoef = I.wcoef;
+        a.wcoef32 = I.wcoef32;
+        a.wdiag32 = I.wdiag32;
+        a.wstart = I.wstart;
+        a.wshn = I.wshn;
+        a.wshs = I.wshs;
+        a.wsh = I.wsh;
+        a.wsh_stride = I.wsh_stride;
+        a.wlen = I.wlen;
+        a.wperm = I.wperm;
+        a.nwb = I.nwb;
+        a.N = I.N;
+        a.x32 = O.x32;
+        BatchTerm32Epi<R> epi;
+        epi.n = n;
+        epi.alpha = O.alpha;
+        epi.fin_hi = O.fin_hi;
+        epi.fin_lo = O.fin_lo;
+        epi.fout_hi = O.fout_hi;
+        epi.fout_lo = O.fout_lo;
+        epi.y = O.y32;
+        epi.active = O.active;
+        epi.first = O.first != 0;
+  #pragma unroll
+        for (int r = 0; r < R; ++r) epi.my[r] = epi.mf[r] = epi.mb0[r] = 0ull;
+        const bool st = sb == b;
+        const float2 *xs32 = reinterpret_cast<const float2 *>(xs);
+        if (I.split)
+          wave_block<R, true, true, BatchTerm32Epi<R>, true, true, true>(a, k, epi, xs32, base, st);
+        else
+          wave_block<R, true, true, BatchTerm32Epi<R>, true, false, true>(a, k, epi, xs32, base, st);
+  #pragma unroll
+        for (int r = 0; r < R; ++r) {
+          batch_flush(epi.my[r], &S->y[r]);
+          batch_flush(epi.mf[r], &S->f[r]);
+          if (epi.first) batch_flush(epi.mb0[r], &S->b0[r]);
+        }
+      } else if (type == BOP_TRACE) {
+        // one wave (the walk's first block) checks every column's trace
+        if (k == 0) {
+          for (int r = 0; r < R && r < I.n0; ++r) {
+            const double tr = wave_trace(O.fout_hi + r * n, O.fout_lo + r * n, I.N);
+            if (lane == 0) {
+              if (!isfinite(tr)) *(volatile int *)A.nonfinite = 1;
+              if (O.first) {
+                S->tr0[r] = tr;
+                S->scale[r] = 1.0;
+              } else {
+                // as trace32_kernel: scaled only when the deviation is small
+                const double tr0 = S->tr0[r];
+                const bool ok = isfinite(tr) && isfinite(tr0) && tr != 0.0 && tr0 != 0.0 &&
+                                fabs(tr - tr0) <= 0x1p-10 * fabs(tr0);
+                S->scale[r] = ok ? tr0 / tr : 1.0;
+                const unsigned long long d = abs_bits(tr - tr0);
+                if (d > S->trace_dev) S->trace_dev = d;
+              }
+            }
+          }
+        }
+      } else if (type == BOP_LOAD) {
+        // rho0 split into the state pair 0 (as split_c64_kernel); the other
+        // vectors start at zero, so columns beyond n0 stay zero throughout
+        if (live) {
+          const int n0 = I.n0;
+  #pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const int64_t e = r * n + row;
+            const double2 z = r < n0 ? gld(I.rho0 + e) : make_double2(0.0, 0.0);
+            const float2 h = make_float2((float)z.x, (float)z.y);
+            const float2 zf = make_float2(0.0f, 0.0f);
+            gst(I.Ph[0] + e, h);
+            gst(I.Pl[0] + e, make_float2((float)(z.x - (double)h.x), (float)(z.y - (double)h.y)));
+            gst(I.Ph[1] + e, zf);
+            gst(I.Pl[1] + e, zf);
+            gst(I.B32[0] + e, zf);
+            gst(I.B32[1] + e, zf);
+          }
+        }
+      } else if (type == BOP_EMIT) {
+        // (hi + lo) times the check's factor in complex128 (as emit32_kernel;
+        // the pair re-split when the factor is not 1), or rho0 itself
+        if (live) {
+          const int64_t pt = O.point;
+          const int N1 = I.N + 1;
+          const int n0 = I.n0;
+          double2 *out = I.out;
+          double *pops = I.pops;
+  #pragma unroll
+          for (int r = 0; r < R; ++r) {
+            if (r >= n0) break;
+            const int64_t e = r * n + row;
+            double2 v;
+            if (O.first) {
+              v = gld(I.rho0 + e);
+            } else {
+              const double f = S->scale[r];
+              const float2 h = gld(O.fout_hi + e), l = gld(O.fout_lo + e);
+              v = make_double2(((double)h.x + (double)l.x) * f, ((double)h.y + (double)l.y) * f);
+              if (f != 1.0) {
+                const float2 h2 = make_float2((float)v.x, (float)v.y);
+                gst(O.fout_hi + e, h2);
+                gst(O.fout_lo + e,
+                    make_float2((float)(v.x - (double)h2.x), (float)(v.y - (double)h2.y)));
+              }
+            }
+            if (out) gst(out + (pt * n0 + r) * n + row, v);
+            if (pops && row % N1 == 0) gst(pops + (pt * n0 + r) * I.N + row / N1, v.x);
+          }
+        }
+      }
+      } else {
       if (type == BOP_TERM || type == BOP_POWACC) {
         SpmvArgs a{};
         a.n = n;
@@ -2651,6 +2905,7 @@ __global__ __launch_bounds__(kBlock, (R >= 2 ? 4 : 1)) void batch_work_kernel(Ba
             if (pops && row % N1 == 0) gst(pops + (pt * n0 + r) * I.N + row / N1, v.x);
           }
         }
+      }
       }
     }
   }
@@ -3017,13 +3272,19 @@ hipError_t launch_batch_control(const BatchArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_batch_work(const BatchArgs &a, int rhs, int grid, hipStream_t s) {
+hipError_t launch_batch_work(const BatchArgs &a, int rhs, bool p32, int grid, hipStream_t s) {
+#define QSW_L(R)                                                                                  \
+  if (p32)                                                                                        \
+    hipLaunchKernelGGL((batch_work_kernel<R, true>), dim3(grid), dim3(kBlock), a.stage_bytes, s, a); \
+  else                                                                                            \
+    hipLaunchKernelGGL((batch_work_kernel<R, false>), dim3(grid), dim3(kBlock), a.stage_bytes, s, a);
   switch (rhs) {
-    case 1: hipLaunchKernelGGL(batch_work_kernel<1>, dim3(grid), dim3(kBlock), a.stage_bytes, s, a); break;
-    case 2: hipLaunchKernelGGL(batch_work_kernel<2>, dim3(grid), dim3(kBlock), a.stage_bytes, s, a); break;
-    case 4: hipLaunchKernelGGL(batch_work_kernel<4>, dim3(grid), dim3(kBlock), a.stage_bytes, s, a); break;
+    case 1: QSW_L(1) break;
+    case 2: QSW_L(2) break;
+    case 4: QSW_L(4) break;
     default: return hipErrorInvalidValue;
   }
+#undef QSW_L
   return hipGetLastError();
 }
 
@@ -3042,11 +3303,11 @@ int batch_resident_workgroups(int rhs) {
     return 0;
   hipError_t e;
   if (rhs == 1)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batch_work_kernel<1>, kBlock, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batch_work_kernel<1, false>, kBlock, 0);
   else if (rhs == 2)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batch_work_kernel<2>, kBlock, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batch_work_kernel<2, false>, kBlock, 0);
   else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batch_work_kernel<4>, kBlock, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batch_work_kernel<4, false>, kBlock, 0);
   if (e != hipSuccess || per < 1) per = 1;
   return cus * per;
 }

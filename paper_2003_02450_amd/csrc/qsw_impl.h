@@ -185,7 +185,9 @@ enum BatchOpType : int32_t {
   BOP_POWACC = 3, // series power y = K_p = alpha A K_{p-1}, fout = fin + k^p y
   BOP_ACC = 4,    // series accumulation from a stored power: fout = fin + k^p K_p
   BOP_NORM = 5,   // series block start: max |Z| per column
-  BOP_EMIT = 6    // out / pops of one grid point from x
+  BOP_EMIT = 6,   // out / pops of one grid point from x
+  BOP_TRACE = 7   // single-precision products: trace of the state pair per column
+                  // (first: the reference; else the check's scale factor)
 };
 
 // One walk in the batch (fixed while it runs).  Vectors hold R complex128
@@ -218,6 +220,11 @@ struct BatchInst {
   const double2 *rho0;
   double2 *out;
   double *pops;
+  // single-precision products (prec32): the state and accumulator as hi + lo
+  // pairs of complex64 vectors (pair c: Ph[c], Pl[c]; the state is pair
+  // `cur`, each scaling step accumulates into the other), complex64 terms
+  int32_t prec32;
+  float2 *Ph[2], *Pl[2], *B32[2];
 };
 
 struct BatchOp {
@@ -230,6 +237,12 @@ struct BatchOp {
   double2 *y;
   const double2 *fin;
   double2 *fout;
+  // single-precision products: TERM x32, y32 and the accumulator pairs;
+  // TRACE and EMIT: the state pair (fout_hi, fout_lo)
+  const float2 *x32;
+  float2 *y32;
+  const float2 *fin_hi, *fin_lo;
+  float2 *fout_hi, *fout_lo;
 };
 
 struct BatchCtl {
@@ -242,10 +255,16 @@ struct BatchCtl {
   int64_t products;
   double tseg;
   double c_prev[kBatchMaxRhs], c_last[kBatchMaxRhs], f_last[kBatchMaxRhs];
+  unsigned long long trace_dev;  // largest |Tr - Tr rho0| seen (bits; single-precision products)
 };
 
 struct BatchSlots {  // maxima of the op in flight, as IEEE bit patterns
   unsigned long long y[kBatchMaxRhs], f[kBatchMaxRhs], b0[kBatchMaxRhs];
+  // single-precision products: per column the reference trace and the
+  // scale factor of the last check, and the largest deviation of the last
+  // check (bits)
+  double tr0[kBatchMaxRhs], scale[kBatchMaxRhs];
+  unsigned long long trace_dev;
 };
 
 struct BatchArgs {
@@ -430,7 +449,9 @@ hipError_t launch_topk(const double *h, int64_t n, int K, int grid, double *cand
 // (which = 0: single right-hand side, 1: two).
 int resident_workgroups(int which);
 hipError_t launch_batch_control(const BatchArgs &a, hipStream_t s);
-hipError_t launch_batch_work(const BatchArgs &a, int rhs, int grid, hipStream_t s);
+// The work kernel of the walks with double (p32 false) or single-precision
+// (p32 true) products.
+hipError_t launch_batch_work(const BatchArgs &a, int rhs, bool p32, int grid, hipStream_t s);
 hipError_t launch_batch_blocks(const BatchArgs &a, hipStream_t s);
 int batch_resident_workgroups(int rhs);
 

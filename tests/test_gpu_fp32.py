@@ -146,7 +146,9 @@ def test_parameters_rerun_and_double_untouched():
     op.close()
 
 
-def test_batch_engine_rejects_fp32_handles():
+def test_batch_engine_takes_fp32_handles():
+    """A single-precision-products handle runs in the batch engine too,
+    bitwise as qsw_propagate runs it (more in test_gpu_batch_fp32.py)."""
     import torch
     import paper_2003_02450_amd as qsw
     wl = random_workload(9, 2, 0.3, 56, n_steps=3)
@@ -154,8 +156,10 @@ def test_batch_engine_rejects_fp32_handles():
     op.set_precision("fp32")
     r0 = torch.from_numpy(wl.rho0[None]).cuda()
     out = torch.empty((4, 1, 9, 9), dtype=torch.complex128, device="cuda")
-    with pytest.raises(qsw.QswError):            # no engine plan for an FP32 handle
-        qsw.batch_propagate([(op, r0, 0.0, wl.dt, 3, out, None)])
+    st = qsw.batch_propagate([(op, r0, 0.0, wl.dt, 3, out, None)])
+    torch.cuda.synchronize()
+    assert st["live"] == 0 and st["trace_dev"] > 0.0
+    assert np.array_equal(out.cpu().numpy()[:, 0], _run(op, wl))
     op.close()
 
 
