@@ -27,7 +27,8 @@ deviation from the FP64 oracle at every point (the committed full-grid
 fixture); `single_values` does the same with only the values in complex64.
 `configs` reports the rate of the N = 16 cycle and N = 256 ER workloads.
 `batched` runs 64 small walks with 4 density matrices each through one
-engine, against the same walks one density matrix at a time.  `served` drives
+engine, against the same walks one density matrix at a time, and again with
+single-precision values and with single-precision products.  `served` drives
 the continuous-batching server with Poisson arrivals at several rates and
 reports walks/s and p50/p99 latency.  `cpu_baseline` times the CPU oracle on
 a bounded sample of the same workload, with all host threads and with one.
@@ -314,8 +315,9 @@ def batch_leg(torch, qsw, workloads, reps: int, compare: bool = True) -> dict:
     cycles replayed as HIP graphs, launch shape tuned on the first run).
     Timed against the same walks through qsw_propagate one density matrix at
     a time; every batched result is bitwise that of its single walk.  Then
-    the same batch with single-precision values (`single_values`), with its
-    largest difference from the double batch."""
+    the same batch with single-precision values (`single_values`) and with
+    single-precision products (`fp32`), each with its largest difference from
+    the double batch."""
     dev = torch.device("cuda", 0)
     wls = workloads.batch64()
     t0 = time.perf_counter()
@@ -373,6 +375,25 @@ def batch_leg(torch, qsw, workloads, reps: int, compare: bool = True) -> dict:
     qsw.batch_propagate(items32, workspace=ws)
     e32, ms32, by32, s32 = timed(items32)
     diff = max(float((a - b).abs().max().item()) for a, b in zip(outs32, outs))
+    # single-precision products, same batch: against the double batch (itself
+    # within 1e-10 of the oracle in the tests) and, sampled, bitwise against
+    # the same walks' single-precision single-walk path
+    progress("batched: single-precision products")
+    outsp = [torch.empty_like(o) for o in outs]
+    for op in ops:
+        op.set_precision("fp32")
+    itemsp = [(op, r, w.t0, w.dt, w.n_steps, o, None)
+              for op, r, w, o in zip(ops, r0, wls, outsp)]
+    qsw.batch_propagate(itemsp, workspace=ws)
+    ep, msp, byp, sp = timed(itemsp)
+    diffp = max(float((a - b).abs().max().item()) for a, b in zip(outsp, outs))
+    eqp = True
+    for i in range(0, len(wls), 16):
+        w = wls[i]
+        for c in range(r0[i].shape[0]):
+            one = ops[i].propagate(r0[i][c], 0.0, w.dt, w.n_steps)
+            eqp = eqp and bool(torch.equal(one, outsp[i][:, c]))
+    achp = byp / (msp * 1e-3) / 1e9
     for op in ops:
         op.close()
     return {"metric": "instance-points/s", "value": value, "unit": "points/s",
@@ -394,7 +415,18 @@ def batch_leg(torch, qsw, workloads, reps: int, compare: bool = True) -> dict:
                               "dtype": "c64 values, f64 vectors",
                               "ms_per_batch": 1e3 * e32 / reps,
                               "achieved_gbps": by32 / (ms32 * 1e-3) / 1e9,
-                              "max_abs_diff_vs_double_batch": diff}}
+                              "max_abs_diff_vs_double_batch": diff},
+            "fp32": {"value": reps * points / ep, "unit": "points/s",
+                     "dtype": "c64 values, vectors and products; hi+lo c64 accumulator; "
+                              "f64 norms and trace check",
+                     "ms_per_batch": 1e3 * ep / reps, "device_ms_per_batch": msp / reps,
+                     "products": sp["products"], "cycles": sp["cycles"],
+                     "kernel": "batch_work_kernel<4, true>", "achieved": achp,
+                     "unit_bw": "GB/s", "frac": achp / HBM_PEAK_GBPS,
+                     "bytes_basis": "layout bytes with single-precision values and 48 bytes "
+                                    "per element and column",
+                     "max_abs_diff_vs_double_batch": diffp, "trace_dev_max": sp["trace_dev"],
+                     "bitwise_equal_to_single_walks_sampled": eqp}}
 
 
 def single_instance_service(torch, qsw, reqs) -> list:
