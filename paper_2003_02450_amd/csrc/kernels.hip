@@ -955,7 +955,9 @@ __device__ __forceinline__ int band_rows(int N) {
 template <bool F32, bool SPLIT, class Epi>
 __device__ __forceinline__ void wave_engine_banded(const SpmvArgs &a, Epi &epi) {
   constexpr int WPB = kBlock / 64;
-  static_assert(WPB == 4, "a workgroup takes four blocks of its band");
+  // a workgroup takes four blocks of its band: other workgroup sizes build
+  // without this traversal (banded_ok is false for them)
+  if constexpr (WPB != 4) return;
   extern __shared__ double2 xs[];
   const int64_t nbr = a.N / 64;         // blocks per rho-row
   const int64_t bw = band_blocks(a.N);  // band blocks per rho-row

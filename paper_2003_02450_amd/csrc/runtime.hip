@@ -974,7 +974,9 @@ void set_wave(SpmvArgs &a, const qsw_superop_s *h) {
 
 // The XCD-banded engine needs N/64 blocks per rho-row in 8 bands and at most
 // 32 KB of staged rows: N = 512, 1024 or 2048.
-bool banded_ok(int32_t N) { return N == 512 || N == 1024 || N == 2048; }
+bool banded_ok(int32_t N) {
+  return kBlockThreads == 256 && (N == 512 || N == 1024 || N == 2048);
+}
 
 // Its grid: a multiple of the 8 XCDs.
 int banded_grid(int grid) { return std::max(8, grid / 8 * 8); }
