@@ -463,7 +463,8 @@ def fifo_latencies(arrivals, service) -> np.ndarray:
     return np.array(lat)
 
 
-def served_leg(torch, qsw, workloads, qps_list, seconds: float, min_count: int) -> dict:
+def served_leg(torch, qsw, workloads, qps_list, seconds: float, min_count: int,
+               warmup_seconds: float = 3.0) -> dict:
     """Continuous batching: walks (N log-uniform in [16, 2048], ER mean degree
     6 with 10 % one-way edges, omega ~ U(0,1), 10..200 steps over t in
     [0, 10], rho0 = |0><0|, populations out) arrive as a Poisson process at
@@ -473,7 +474,10 @@ def served_leg(torch, qsw, workloads, qps_list, seconds: float, min_count: int) 
     the number of walks not yet finished when the last one arrived.  The
     same request stream through the single-instance FP64 path (qsw_propagate
     per walk, measured service times, one walk at a time in arrival order)
-    gives the baseline."""
+    gives the baseline.  Each rate starts with `warmup_seconds` of other walks
+    of the same mix through the same server (unmeasured), so that the
+    measured stream meets a running server rather than its first
+    allocations."""
     GB = 1 << 30
     count_max = max(min_count, int(max(qps_list) * seconds))
     reqs = workloads.served_requests(count_max)
@@ -482,12 +486,10 @@ def served_leg(torch, qsw, workloads, qps_list, seconds: float, min_count: int) 
     progress(f"served: single-instance baseline on {n_base} walks")
     service = single_instance_service(torch, qsw, reqs[:n_base])
     base_rate = n_base / sum(service)
-    points = []
-    for qps in qps_list:
-        count = max(min_count, int(qps * seconds))
-        progress(f"served: {count} walks at {qps} QPS")
-        arrivals = workloads.poisson_arrivals(count, qps)
-        srv = qsw.Server(96 * GB, 48 * GB, 4096)
+    def drive(srv, rq, arrivals):
+        """Submit rq at their arrival times, step until all are done:
+        (latencies in finishing order, backlog at the last arrival, wall)."""
+        count = len(arrivals)
         t_arr = {}
         lat = []
         i = 0
@@ -496,7 +498,7 @@ def served_leg(torch, qsw, workloads, qps_list, seconds: float, min_count: int) 
         while len(lat) < count:
             now = time.perf_counter() - t0
             while i < count and arrivals[i] <= now:
-                r = reqs[i]
+                r = rq[i]
                 rid = srv.submit(r["graph"], r["omega"], 0.0, r["dt"], r["n_steps"])
                 t_arr[rid] = arrivals[i]
                 i += 1
@@ -508,7 +510,22 @@ def served_leg(torch, qsw, workloads, qps_list, seconds: float, min_count: int) 
                 lat.append(t_ready - t_arr.pop(rid))
             if running == 0 and pending == 0 and i < count and len(lat) < count:
                 time.sleep(max(0.0, arrivals[i] - (time.perf_counter() - t0)))
-        wall = time.perf_counter() - t0
+        return lat, backlog, time.perf_counter() - t0
+
+    points = []
+    for qps in qps_list:
+        count = max(min_count, int(qps * seconds))
+        srv = qsw.Server(96 * GB, 48 * GB, 4096)
+        # warm-up: other walks of the same mix at the same rate (their graphs
+        # differ from the measured ones, so no measured operator is cached)
+        n_warm = max(8, int(qps * warmup_seconds))
+        progress(f"served: {n_warm} warm-up walks at {qps} QPS")
+        drive(srv, workloads.served_requests(n_warm, seed=workloads.BASE_SEED + 32),
+              workloads.poisson_arrivals(n_warm, qps, seed=workloads.BASE_SEED + 33))
+        st0 = srv.stats()
+        progress(f"served: {count} walks at {qps} QPS")
+        arrivals = workloads.poisson_arrivals(count, qps)
+        lat, backlog, wall = drive(srv, reqs, arrivals)
         st = srv.stats()
         srv.close()
         lat_ms = 1e3 * np.array(lat)
@@ -521,15 +538,17 @@ def served_leg(torch, qsw, workloads, qps_list, seconds: float, min_count: int) 
                        "mean_ms": float(lat_ms.mean()),
                        "p50_first_half_ms": float(np.percentile(lat_ms[:half], 50)),
                        "p50_second_half_ms": float(np.percentile(lat_ms[half:], 50)),
-                       "backlog_at_last_arrival": backlog, "cycles": st["cycles"],
-                       "build_ms": st["build_ms"],
+                       "backlog_at_last_arrival": backlog,
+                       "cycles": st["cycles"] - st0["cycles"],
+                       "build_ms": st["build_ms"] - st0["build_ms"], "warmup_walks": n_warm,
                        "single_instance": {
                            "walks_per_s": count / max(arrivals[-1] + base[-1] / 1e3, 1e-9),
                            "p50_ms": float(np.percentile(base, 50)),
                            "p99_ms": float(np.percentile(base, 99))}})
     return {"metric": "walks/s", "workload": "N~logU[16,2048] ER deg 6 (10% one-way), "
             "omega~U(0,1), 10..200 steps over t=0..10, rho0=|0><0|, populations out",
-            "seconds_per_rate": seconds, "points": points,
+            "seconds_per_rate": seconds, "warmup_seconds_per_rate": warmup_seconds,
+            "points": points,
             "single_instance_path": {
                 "walks_per_s": base_rate, "sampled_walks": n_base,
                 "note": "qsw_propagate per walk (build + propagate + populations, FP64), "
@@ -607,6 +626,8 @@ def main() -> int:
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="arrival time span of each serving rate")
     ap.add_argument("--serve-count", type=int, default=24, help="least walks per serving rate")
+    ap.add_argument("--serve-warmup", type=float, default=3.0,
+                    help="seconds of unmeasured warm-up walks before each serving rate")
     ap.add_argument("--paper", default="",
                     help="comma list of the paper's benchmark shapes to run to t=100 "
                          "(line,lattice,er,complete); none by default")
@@ -742,7 +763,8 @@ def main() -> int:
         progress("continuous batching")
         result["served"] = served_leg(torch, qsw, workloads,
                                       [float(x) for x in args.serve_qps.split(",")],
-                                      args.serve_seconds, args.serve_count)
+                                      args.serve_seconds, args.serve_count,
+                                      args.serve_warmup)
     if args.paper:
         result["paper_shaped"] = paper_leg(torch, qsw, workloads, args.paper.split(","))
     if not args.no_cpu_baseline:
