@@ -726,7 +726,7 @@ def main() -> int:
                    "products_per_step": products // args.steps,
                    "term_launches_per_step": launched // args.steps},
         "roofline": {"bound": "hbm",
-                     "kernel": (f"term_kernel<{110 if split else 100}> (sparse product + Taylor "
+                     "kernel": (f"term_kernel<{info0['engine']}> (sparse product + Taylor "
                                 "epilogue, wave layout, rho-row staged in LDS, "
                                 f"{'phase-split' if split else 'complex'} values)"),
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",

@@ -94,6 +94,10 @@ typedef struct {
     int64_t distinct_entries; /* per-row entries in the copies the blocks read: blocks whose
                                  stored rows are word for word equal (columns as offsets from
                                  the row) read one copy */
+    int32_t engine;      /* product kernel of complex128 qsw_propagate calls: traversal (0
+                            plain, 100 rho-row staged in LDS, 200 staged with XCD column
+                            bands) + 10 for phase-split values; 3: the CSR stream engine;
+                            4..64: the CSR vector engine with that many lanes per row */
 } qsw_info_t;
 
 typedef struct {

@@ -267,7 +267,8 @@ class Superop:
                 "d_probe": {p: i.d_probe[p] for p in range(2, 10)},
                 "norm_products": i.norm_products, "build_ms": i.build_ms,
                 "split": bool(i.split), "stream_entries": i.stream_entries,
-                "shared_entries": i.shared_entries, "distinct_entries": i.distinct_entries}
+                "shared_entries": i.shared_entries, "distinct_entries": i.distinct_entries,
+                "engine": i.engine}
 
     def csr(self):
         """Host copies (row_ptr int64, col int32, val complex128)."""

@@ -55,7 +55,7 @@ class Info(ctypes.Structure):
                 ("d_probe", ctypes.c_int32 * 10), ("norm_products", ctypes.c_int32),
                 ("build_ms", ctypes.c_double), ("split", ctypes.c_int32),
                 ("stream_entries", ctypes.c_int64), ("shared_entries", ctypes.c_int64),
-                ("distinct_entries", ctypes.c_int64)]
+                ("distinct_entries", ctypes.c_int64), ("engine", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

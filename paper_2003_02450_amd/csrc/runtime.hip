@@ -2425,6 +2425,7 @@ qsw_status_t qsw_superop_autotune(qsw_superop_t h, void *hip_stream, qsw_tuning_
 qsw_status_t qsw_superop_info(qsw_superop_t h, qsw_info_t *info) {
   if (!h || !info) return QSW_ERR_ARG;
   *info = h->info;
+  info->engine = launch_engine(h, false);  // the autotuner may have changed it
   return QSW_OK;
 }
 
