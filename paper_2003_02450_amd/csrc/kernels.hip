@@ -404,22 +404,30 @@ __device__ __forceinline__ void stream_engine(const SpmvArgs &a, Epi &epi) {
 // for one right-hand side (double / single-precision products), waves per
 // SIMD the double and single term kernels are compiled for, and whether
 // double phase-split blocks take the two-multiply-add path.  Measured per
-// FP64 pass (50 intervals, 1498 products, grid 2048): groups of 8 positions
-// 104.7 ms, 6 positions 103.1, 6 with the two-multiply-add path 100.4, 5
-// positions 111.9, 4 109.2, 7 108.7; five waves per SIMD spills.  Single-
-// precision products: groups of 8 58.1 ms, 6, 12 and 16 slower.
+// FP64 pass (50 intervals, 1498 products, grid 2048, four waves per SIMD):
+// groups of 8 positions 104.7 ms, 6 positions 103.1, 6 with the
+// two-multiply-add path 100.4, 5 positions 111.9, 4 109.2, 7 108.7; six
+// positions spill at five waves.  Later (1402 products): groups of 6 at four
+// waves 93.7 ms, 5 at five waves 92.1-92.3, 4 at five waves 93.3-93.4.
+// Single-precision products: groups of 8 58.1 ms, 6, 12 and 16 slower.
 #ifndef QSW_UNROLL1
-#define QSW_UNROLL1 6
+#define QSW_UNROLL1 5
 #endif
 #ifndef QSW_UNROLL1_X32
 #define QSW_UNROLL1_X32 8
 #endif
 #ifndef QSW_TERM_WAVES
-#define QSW_TERM_WAVES 4
+#define QSW_TERM_WAVES 5
 #endif
 #ifndef QSW_TERM32_WAVES
 #define QSW_TERM32_WAVES 4
 #endif
+// Waves per SIMD of term_kernel<ENGINE>: the wave layouts with double values
+// QSW_TERM_WAVES; single-precision values (format 1 / 11), where five spill,
+// and the CSR engines four.
+constexpr int term_waves(int engine) {
+  return (engine % 10 == 1 || (engine % 100 != 0 && engine % 100 != 10)) ? 4 : QSW_TERM_WAVES;
+}
 #ifndef QSW_FAST_NRHS
 #define QSW_FAST_NRHS 2  // widest interleaved block taking the phase-split fast path
 #endif
@@ -1659,7 +1667,7 @@ __device__ __forceinline__ bool taylor_prologue(const SpmvArgs &a) {
 }
 
 template <int ENGINE>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(QSW_TERM_WAVES))) void term_kernel(SpmvArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(term_waves(ENGINE)))) void term_kernel(SpmvArgs a) {
   if (taylor_prologue(a)) return;
   TaylorEpi epi(a);
   run_engine<ENGINE>(a, epi);
