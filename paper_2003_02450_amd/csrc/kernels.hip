@@ -428,6 +428,9 @@ __device__ __forceinline__ void stream_engine(const SpmvArgs &a, Epi &epi) {
 constexpr int term_waves(int engine) {
   return (engine % 10 == 1 || (engine % 100 != 0 && engine % 100 != 10)) ? 4 : QSW_TERM_WAVES;
 }
+#ifndef QSW_SHARED_U1
+#define QSW_SHARED_U1 8  // block-shared positions per group, one right-hand side
+#endif
 #ifndef QSW_FAST_NRHS
 #define QSW_FAST_NRHS 2  // widest interleaved block taking the phase-split fast path
 #endif
@@ -448,9 +451,14 @@ constexpr int term_waves(int engine) {
 #define QSW_UNROLLW 1
 #endif
 
-template <int NRHS, bool X32 = false>
+// single-precision values with double vectors (four waves per SIMD)
+#ifndef QSW_UNROLL1_V32
+#define QSW_UNROLL1_V32 6
+#endif
+
+template <int NRHS, bool X32 = false, bool F32 = false>
 constexpr int wave_unroll() {
-  return NRHS == 1 ? (X32 ? QSW_UNROLL1_X32 : QSW_UNROLL1)
+  return NRHS == 1 ? (X32 ? QSW_UNROLL1_X32 : (F32 ? QSW_UNROLL1_V32 : QSW_UNROLL1))
                    : (NRHS == 2 ? QSW_UNROLL2 : (NRHS <= 4 ? QSW_UNROLL4 : QSW_UNROLLW));
 }
 
@@ -603,7 +611,7 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
   using R = RealT<X32>;
   // one right-hand side: xs holds x[base .. base + span) (span = N by default)
   const uint64_t lim = (uint64_t)(span ? span : a.N);
-  constexpr int kWaveUnroll = wave_unroll<NRHS, X32>();
+  constexpr int kWaveUnroll = wave_unroll<NRHS, X32, F32>();
   const int lane = threadIdx.x & 63;
   const int64_t r0 = k * kWaveRows;
   const int nr = (int)min((int64_t)kWaveRows, a.n - r0);
@@ -624,7 +632,7 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
   // nothing, so the sums are those of the unshared layout.
   if (gsp > 0) {
     const int64_t row = r0 + orow;
-    constexpr int SU = NRHS == 1 ? kSharedPad
+    constexpr int SU = NRHS == 1 ? QSW_SHARED_U1
                                  : (NRHS == 2 ? kSharedPad / 2 : (NRHS <= 4 ? kSharedPad / 4 : 1));
     static_assert(kSharedPad % SU == 0, "shared groups divide the padding");
     // lane i loaded entry i with the block header (at most kSharedMax
