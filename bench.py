@@ -463,6 +463,20 @@ def fifo_latencies(arrivals, service) -> np.ndarray:
     return np.array(lat)
 
 
+def served_reference() -> dict:
+    """{request index: the oracle's populations} of the sampled walks of the
+    serving stream, from the committed fixture tests/golden/served_pops.npz
+    (written from the oracle by tests/golden/make_served.py), or {} if it is
+    absent."""
+    path = os.path.join(ROOT, "tests", "golden", "served_pops.npz")
+    try:
+        z = np.load(path, allow_pickle=False)
+    except OSError:
+        return {}
+    header = json.loads(bytes(z["header"]).decode())
+    return {w["index"]: z[f"pops_{w['index']}"] for w in header["walks"]}
+
+
 def served_leg(torch, qsw, workloads, qps_list, seconds: float, min_count: int,
                warmup_seconds: float = 3.0) -> dict:
     """Continuous batching: walks (N log-uniform in [16, 2048], ER mean degree
@@ -481,16 +495,20 @@ def served_leg(torch, qsw, workloads, qps_list, seconds: float, min_count: int,
     GB = 1 << 30
     count_max = max(min_count, int(max(qps_list) * seconds))
     reqs = workloads.served_requests(count_max)
+    ref_pops = served_reference()  # sampled walks of the stream: the oracle's populations
     # baseline: measured service times of the single-instance path
     n_base = min(count_max, 48)
     progress(f"served: single-instance baseline on {n_base} walks")
     service = single_instance_service(torch, qsw, reqs[:n_base])
     base_rate = n_base / sum(service)
-    def drive(srv, rq, arrivals):
+    def drive(srv, rq, arrivals, keep=()):
         """Submit rq at their arrival times, step until all are done:
-        (latencies in finishing order, backlog at the last arrival, wall)."""
+        (latencies in finishing order, backlog at the last arrival, wall,
+        {index: populations} of the walks whose index is in keep)."""
         count = len(arrivals)
         t_arr = {}
+        idx = {}
+        kept = {}
         lat = []
         i = 0
         backlog = None
@@ -501,16 +519,19 @@ def served_leg(torch, qsw, workloads, qps_list, seconds: float, min_count: int,
                 r = rq[i]
                 rid = srv.submit(r["graph"], r["omega"], 0.0, r["dt"], r["n_steps"])
                 t_arr[rid] = arrivals[i]
+                idx[rid] = i
                 i += 1
                 if i == count:
                     backlog = count - len(lat)
             running, pending = srv.step(8)
             t_ready = time.perf_counter() - t0
-            for rid, _, _, _ in srv.poll():
+            for rid, _, pops, _ in srv.poll():
                 lat.append(t_ready - t_arr.pop(rid))
+                if idx[rid] in keep:
+                    kept[idx[rid]] = pops.cpu().numpy()
             if running == 0 and pending == 0 and i < count and len(lat) < count:
                 time.sleep(max(0.0, arrivals[i] - (time.perf_counter() - t0)))
-        return lat, backlog, time.perf_counter() - t0
+        return lat, backlog, time.perf_counter() - t0, kept
 
     points = []
     for qps in qps_list:
@@ -525,7 +546,9 @@ def served_leg(torch, qsw, workloads, qps_list, seconds: float, min_count: int,
         st0 = srv.stats()
         progress(f"served: {count} walks at {qps} QPS")
         arrivals = workloads.poisson_arrivals(count, qps)
-        lat, backlog, wall = drive(srv, reqs, arrivals)
+        lat, backlog, wall, kept = drive(srv, reqs, arrivals, set(ref_pops))
+        err = max((float(np.abs(kept[i] - p).max()) for i, p in ref_pops.items() if i in kept),
+                  default=None)
         st = srv.stats()
         srv.close()
         lat_ms = 1e3 * np.array(lat)
@@ -539,6 +562,7 @@ def served_leg(torch, qsw, workloads, qps_list, seconds: float, min_count: int,
                        "p50_first_half_ms": float(np.percentile(lat_ms[:half], 50)),
                        "p50_second_half_ms": float(np.percentile(lat_ms[half:], 50)),
                        "backlog_at_last_arrival": backlog,
+                       "max_abs_err_vs_oracle_sampled": err,
                        "cycles": st["cycles"] - st0["cycles"],
                        "build_ms": st["build_ms"] - st0["build_ms"], "warmup_walks": n_warm,
                        "single_instance": {
@@ -549,6 +573,10 @@ def served_leg(torch, qsw, workloads, qps_list, seconds: float, min_count: int,
             "omega~U(0,1), 10..200 steps over t=0..10, rho0=|0><0|, populations out",
             "seconds_per_rate": seconds, "warmup_seconds_per_rate": warmup_seconds,
             "points": points,
+            "accuracy": "max_abs_err_vs_oracle_sampled: the populations of the stream's "
+                        "sampled walks (N <= 32) against the oracle's, committed in "
+                        "tests/golden/served_pops.npz; every served walk is bitwise the "
+                        "single-instance FP64 path (tested)",
             "single_instance_path": {
                 "walks_per_s": base_rate, "sampled_walks": n_base,
                 "note": "qsw_propagate per walk (build + propagate + populations, FP64), "

@@ -67,6 +67,29 @@ def test_matches_oracle():
     assert np.abs(got[0] - pops).max() <= 1e-10
 
 
+def test_benchmark_stream_walks_match_oracle_fixture():
+    """The sampled walks of the serving benchmark's request stream, served in
+    a mix with their neighbours of the stream, against the oracle's committed
+    populations (tests/golden/make_served.py) at the FP64 bar."""
+    import importlib.util
+    import os
+    here = os.path.join(os.path.dirname(__file__), "golden", "make_served.py")
+    spec = importlib.util.spec_from_file_location("make_served", here)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    hdr, pops = mod.load()
+    reqs = workloads.served_requests(mod.MIN_COUNT)
+    last = max(pops) + 1
+    small = [i for i in range(last) if reqs[i]["graph"].N <= 256]   # the mix, kept small
+    got, st, _ = _serve([reqs[i] for i in small])
+    for i, p in pops.items():
+        err = np.abs(got[small.index(i)] - p).max()
+        assert err <= 1e-10, (i, err)
+    print(f"served sampled walks {sorted(pops)}: max |d pops| vs oracle "
+          f"{max(np.abs(got[small.index(i)] - p).max() for i, p in pops.items()):.2e}",
+          flush=True)
+
+
 def test_cache_hits_and_evictions():
     reqs = _requests(4, 503)
     again = [reqs[0], reqs[1], reqs[0]]

@@ -344,6 +344,33 @@ def test_fullgrid_fixture_is_the_oracles():
     assert len(np.unique(mod.sample_indices(n, 3))) == mod.SAMPLES
 
 
+def test_served_fixture_is_the_oracles():
+    """The committed serving-workload fixture (tests/golden/make_served.py)
+    holds the oracle's populations of the sampled walks of the serving stream:
+    the smallest one recomputed here agrees bit for bit; every point's
+    populations sum to 1 and lie in [0, 1]."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "make_served", os.path.join(GOLDEN, "make_served.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    hdr, pops = mod.load()
+    assert len(pops) == mod.SAMPLES
+    reqs = workloads.served_requests(mod.MIN_COUNT)
+    for w in hdr["walks"]:
+        r = reqs[w["index"]]
+        assert r["graph"].N == w["N"] <= mod.N_MAX and r["n_steps"] == w["n_steps"]
+        p = pops[w["index"]]
+        assert p.shape == (r["n_steps"] + 1, r["graph"].N)
+        assert np.abs(p.sum(axis=1) - 1).max() < 1e-12
+        assert p.min() > -1e-12 and p.max() < 1 + 1e-12
+    w = min(hdr["walks"], key=lambda w: w["N"])
+    r = reqs[w["index"]]
+    A = oracle.walk_superop(r["graph"].dense(), r["omega"], "laplacian", "transition", False, 1.0)
+    out, _ = expmv.propagate(A, workloads.basis_state(r["graph"].N, 0), 0.0, r["dt"], r["n_steps"])
+    assert np.array_equal(np.real(np.einsum("kaa->ka", out)), pops[w["index"]])
+
+
 # ------------------------------------------- single-precision products variant
 
 def _vec1_max(ref):
