@@ -752,7 +752,9 @@ def main() -> int:
                    "build_ms": round(build_ms, 3),
                    "propagate_ms": round(prop_ms / args.steps, 3),
                    "products_per_step": products // args.steps,
-                   "term_launches_per_step": launched // args.steps},
+                   "term_launches_per_step": launched // args.steps,
+                   "terms_per_point": products / (args.steps * q),
+                   "steps_per_s_excluding_build": q / (prop_ms / args.steps / 1e3)},
         "roofline": {"bound": "hbm",
                      "kernel": (f"term_kernel<{info0['engine']}> (sparse product + Taylor "
                                 "epilogue, wave layout, rho-row staged in LDS, "
