@@ -19,6 +19,7 @@
 #include <complex>
 #include <limits>
 #include <map>
+#include <unordered_map>
 #include <memory>
 #include <mutex>
 #include <thread>
@@ -802,12 +803,26 @@ hipError_t dedup_blocks(WaveLayout &W, int64_t n, const std::vector<int64_t> &hc
                             s)) != hipSuccess)
       break;
     if ((e = hipStreamSynchronize(s)) != hipSuccess) break;
-    // key: hash, stored entries, split position within the stored rows
-    std::map<std::tuple<unsigned long long, int64_t, int32_t>, int64_t> first;
+    // key: hash, stored entries, split position within the stored rows; the
+    // first block of each key (the smallest index) is its candidate copy
+    struct Key {
+      unsigned long long h;
+      int64_t cnt;
+      int32_t g;
+      bool operator==(const Key &o) const { return h == o.h && cnt == o.cnt && g == o.g; }
+    };
+    struct KeyHash {
+      size_t operator()(const Key &k) const {
+        return (size_t)(k.h ^ ((unsigned long long)k.cnt * 0x9E3779B97F4A7C15ull) ^
+                        ((unsigned long long)(uint32_t)k.g << 17));
+      }
+    };
+    std::unordered_map<Key, int64_t, KeyHash> first;
+    first.reserve(nwb);
     int64_t dup = 0;
     for (size_t k = 0; k < nwb; ++k) {
       const int32_t g = hglob[k] < 0 ? -1 : (hglob[k] & kGlobMask) - hshn[k];
-      auto it = first.emplace(std::make_tuple(hh[k], hcnt[k], g), (int64_t)k).first;
+      auto it = first.emplace(Key{hh[k], hcnt[k], g}, (int64_t)k).first;
       hcanon[k] = it->second;
       dup += it->second != (int64_t)k;
     }
