@@ -1117,98 +1117,110 @@ struct Spmm2Epi {  // two right-hand sides for the 1-norm estimator
 };
 
 // --------------------------------------------------------------------------
-// Superoperator assembly: one thread per row r = a*N + b.
+// Superoperator assembly: one wavefront per 64-row block (grid-stride over
+// blocks).  Lane i first loads row r0 + i's descriptors (all rows' loads in
+// one round trip); then the rows are written one after the other, the lanes
+// covering consecutive entries of a row, so that every column and value
+// store of the wave is contiguous.
 // --------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void assemble_kernel(AssembleArgs A, int64_t n) {
-  const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (r >= n) return;
+struct AsmRow {
+  int64_t start, ha0, hb0, ra0;
+  int32_t d0, r1, len;  // H rho entries, + diagonal + rho H entries, all entries
+  int32_t a, b;
+  double2 dval;
+};
+
+__device__ __forceinline__ AsmRow asm_row(const AssembleArgs &A, int64_t r) {
   const int64_t N = A.N;
+  const double ch = A.sigma * (1.0 - A.omega);  // sigma (1 - omega)
+  const double w = A.rscale;                    // omega, or 1 for pre-scaled rates
   const int64_t a = r / N, b = r - a * N;
   const int64_t ha0 = A.hp[a], ha1 = A.hp[a + 1];
   const int64_t hb0 = A.hp[b], hb1 = A.hp[b + 1];
-  const int64_t degHa = ha1 - ha0;
   const int64_t ra0 = A.rp[a], ra1 = A.rp[a + 1];
-  const int64_t degRa = ra1 - ra0;
+  const int64_t degHa = ha1 - ha0, degHb = hb1 - hb0, degRa = ra1 - ra0;
+  AsmRow R;
   // Rows before (a, 0): sum over a' < a of (N degH(a') + E_H + N + degR(a'));
   // rows (a, b') with b' < b: b' (degH(a) + 1) + degH(b') plus the
   // population-transfer entries of row (a, a) once b > a.
-  const int64_t start = N * A.PH[a] + a * (A.EH + N) + A.PR[a] + b * (degHa + 1) + A.PH[b] +
-                        (b > a ? degRa : 0);
-  A.row_ptr[r] = start;
-  if (r == n - 1) A.row_ptr[n] = 2 * N * A.EH + N * N + A.PR[N];
-
-  const double ch = A.sigma * (1.0 - A.omega);  // sigma (1 - omega)
-  const double w = A.rscale;                    // omega, or 1 for pre-scaled rates
+  R.start = N * A.PH[a] + a * (A.EH + N) + A.PR[a] + b * (degHa + 1) + A.PH[b] +
+            (b > a ? degRa : 0);
+  R.ha0 = ha0;
+  R.hb0 = hb0;
+  R.ra0 = ra0;
+  R.d0 = (int32_t)degHa;
+  R.r1 = (int32_t)(degHa + 1 + degHb);
+  R.len = R.r1 + (int32_t)(a == b ? degRa : 0);
+  R.a = (int32_t)a;
+  R.b = (int32_t)b;
   // diagonal: sigma(-i)(1-w)(H_aa - H_bb) - w/2 (K_a + K_b) + [a==b] w R_aa
-  const double2 dval =
-      make_double2(-0.5 * w * (A.K[a] + A.K[b]) + (a == b ? w * A.rdiag[a] : 0.0),
-                   -ch * (A.hdiag[a] - A.hdiag[b]));
-  // Each row is written in structural order: the H rho entries (column
-  // c N + b, ascending c), the diagonal, the rho H entries (column a N + c,
-  // ascending c), then the population-transfer entries (column j (N + 1),
-  // ascending j).  Rows of one rho-row a then share the column offsets c N of
-  // their leading entries, which the product kernels use to coalesce gathers.
-  // The operator's entries are read eight at a time before they are written
-  // (the output may alias the inputs as far as the compiler knows, so a
-  // load-store loop would wait for every load).
-  int64_t o = start;
-  // sigma(-i)(1-w) H_ac on rho_cb
-  for (int64_t i0 = ha0; i0 < ha1; i0 += 8) {
-    double2 h[8];
-    int32_t c[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int64_t i = min(i0 + u, ha1 - 1);
-      h[u] = A.hv[i];
-      c[u] = A.hc[i];
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (i0 + u < ha1) {
-        A.col[o] = (int32_t)((int64_t)c[u] * N + b);
-        A.val[o] = make_double2(ch * h[u].y, -ch * h[u].x);
-        ++o;
-      }
-  }
-  A.col[o] = (int32_t)(a * N + b);
-  A.val[o] = dval;
-  ++o;
-  // sigma(+i)(1-w) conj(H_bc) on rho_ac
-  for (int64_t i0 = hb0; i0 < hb1; i0 += 8) {
-    double2 h[8];
-    int32_t c[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int64_t i = min(i0 + u, hb1 - 1);
-      h[u] = A.hv[i];
-      c[u] = A.hc[i];
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (i0 + u < hb1) {
-        A.col[o] = (int32_t)(a * N + c[u]);
-        A.val[o] = make_double2(ch * h[u].y, ch * h[u].x);
-        ++o;
-      }
-  }
-  // w R_aj on rho_jj
-  if (a == b) {
-    for (int64_t i0 = ra0; i0 < ra1; i0 += 8) {
-      double rv[8];
-      int32_t c[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int64_t i = min(i0 + u, ra1 - 1);
-        rv[u] = A.rv[i];
-        c[u] = A.rc[i];
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (i0 + u < ra1) {
-          A.col[o] = (int32_t)((int64_t)c[u] * (N + 1));
-          A.val[o] = make_double2(w * rv[u], 0.0);
-          ++o;
+  R.dval = make_double2(-0.5 * w * (A.K[a] + A.K[b]) + (a == b ? w * A.rdiag[a] : 0.0),
+                        -ch * (A.hdiag[a] - A.hdiag[b]));
+  return R;
+}
+
+__device__ __forceinline__ int64_t rd64(int64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double rdd(double v, int l) {
+  return __longlong_as_double(rd64(__double_as_longlong(v), l));
+}
+
+__global__ __launch_bounds__(kBlock) void assemble_kernel(AssembleArgs A, int64_t n) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nwb = (n + kWaveRows - 1) / kWaveRows;
+  const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
+  const int64_t N = A.N;
+  const double ch = A.sigma * (1.0 - A.omega);
+  const double w = A.rscale;
+  for (int64_t k = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); k < nwb;
+       k += nwaves) {
+    const int64_t r0 = k * kWaveRows;
+    const int nr = (int)min((int64_t)kWaveRows, n - r0);
+    const AsmRow mine = asm_row(A, r0 + (lane < nr ? lane : 0));
+    if (lane < nr) A.row_ptr[r0 + lane] = mine.start;
+    if (r0 + nr == n && lane == 0) A.row_ptr[n] = 2 * N * A.EH + N * N + A.PR[N];
+    for (int i = 0; i < nr; ++i) {
+      // row r0 + i, from lane i (wave-uniform)
+      const int64_t start = rd64(mine.start, i);
+      const int64_t ha0 = rd64(mine.ha0, i), hb0 = rd64(mine.hb0, i), ra0 = rd64(mine.ra0, i);
+      const int d0 = __builtin_amdgcn_readlane(mine.d0, i);
+      const int r1 = __builtin_amdgcn_readlane(mine.r1, i);
+      const int len = __builtin_amdgcn_readlane(mine.len, i);
+      const int64_t a = __builtin_amdgcn_readlane(mine.a, i);
+      const int64_t b = __builtin_amdgcn_readlane(mine.b, i);
+      const double2 dval = make_double2(rdd(mine.dval.x, i), rdd(mine.dval.y, i));
+      // Each row in structural order: the H rho entries (column c N + b,
+      // ascending c), the diagonal, the rho H entries (column a N + c,
+      // ascending c), then the population-transfer entries (column
+      // j (N + 1), ascending j).  Rows of one rho-row a then share the
+      // column offsets c N of their leading entries, which the product
+      // kernels use to coalesce gathers.
+      for (int e = lane; e < len; e += 64) {
+        int32_t c;
+        double2 v;
+        if (e < d0) {  // sigma(-i)(1-w) H_ac on rho_cb
+          const double2 h = A.hv[ha0 + e];
+          c = (int32_t)((int64_t)A.hc[ha0 + e] * N + b);
+          v = make_double2(ch * h.y, -ch * h.x);
+        } else if (e == d0) {
+          c = (int32_t)(a * N + b);
+          v = dval;
+        } else if (e < r1) {  // sigma(+i)(1-w) conj(H_bc) on rho_ac
+          const int64_t j = hb0 + (e - d0 - 1);
+          const double2 h = A.hv[j];
+          c = (int32_t)(a * N + A.hc[j]);
+          v = make_double2(ch * h.y, ch * h.x);
+        } else {  // w R_aj on rho_jj
+          const int64_t j = ra0 + (e - r1);
+          c = (int32_t)((int64_t)A.rc[j] * (N + 1));
+          v = make_double2(w * A.rv[j], 0.0);
         }
+        A.col[start + e] = c;
+        A.val[start + e] = v;
+      }
     }
   }
 }
@@ -2932,8 +2944,11 @@ __global__ __launch_bounds__(kBlock, (R >= 2 ? 4 : 1)) void batch_work_kernel(Ba
 // ------------------------------------------------------------------ launchers
 
 hipError_t launch_assemble(const AssembleArgs &a, int64_t n, hipStream_t s) {
-  const int64_t nb = (n + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(assemble_kernel, dim3((unsigned)nb), dim3(kBlock), 0, s, a, n);
+  // one wave per 64-row block, grid-stride
+  const int64_t nwb = (n + kWaveRows - 1) / kWaveRows;
+  const int64_t want = (nwb + kBlock / 64 - 1) / (kBlock / 64);
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, 4096));
+  hipLaunchKernelGGL(assemble_kernel, dim3((unsigned)grid), dim3(kBlock), 0, s, a, n);
   return hipGetLastError();
 }
 
