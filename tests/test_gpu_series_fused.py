@@ -11,15 +11,18 @@ from tests.gpu_util import build_gpu, random_workload
 pytestmark = pytest.mark.gpu
 
 
-def _one_point_blocks(op, wl, single):
-    """n_steps and dt for which the series branch takes d = 1 (s < q < 2 s)."""
+def _one_point_blocks(op, single):
+    """(n_steps, dt) for which the series branch takes d = 1 (s < q < 2 s):
+    q/s is about theta_m / (dt alpha), so a dt in the right range is looked
+    for along with q."""
     info = op.info()
-    for q in range(3, 60):
-        m, s = qsw.select_params(info["norm1"], info["d"], q * wl.dt, single=single,
-                                 known_norms=True)
-        if s < q < 2 * s:
-            return q
-    pytest.skip("no one-point block split for this operator")
+    for dt in (0.35, 0.5, 0.7, 1.0, 1.4, 2.0, 2.8, 4.0, 0.25, 0.18, 0.12):
+        for q in range(3, 60):
+            m, s = qsw.select_params(info["norm1"], info["d"], q * dt, single=single,
+                                     known_norms=True)
+            if s < q < 2 * s:
+                return q, dt
+    raise AssertionError("no one-point block split for this operator")
 
 
 @pytest.mark.parametrize("single", [False, True])
@@ -29,7 +32,7 @@ def test_one_point_blocks_fused(monkeypatch, single, pace):
     op = build_gpu(wl)
     op.set_precision(single)
     op.set_pacing(pace)
-    wl.n_steps = _one_point_blocks(op, wl, single)
+    wl.n_steps, wl.dt = _one_point_blocks(op, single)
     import torch
     monkeypatch.setenv("QSW_FUSE_SERIES", "0")
     ref = op.propagate(wl.rho0, wl.t0, wl.dt, wl.n_steps).cpu().numpy()
