@@ -360,6 +360,14 @@ class Superop:
         """rho(t) = exp(t L) rho0 (the paper's `step`)."""
         return self.propagate(rho0, 0.0, float(t), 1)[1]
 
+    def series(self, rho0, t1, tq, steps):
+        """rho(t) at t = t1 + k (tq - t1) / steps, k = 0..steps (the paper's
+        `series`): a [steps + 1, N, N] device tensor."""
+        steps = int(steps)
+        if steps < 1:
+            raise ValueError("steps must be at least 1")
+        return self.propagate(rho0, float(t1), (float(tq) - float(t1)) / steps, steps)
+
     def last_stats(self) -> dict:
         s = _lib.Stats()
         st = _lib.load().qsw_last_stats(self._h, ctypes.byref(s))

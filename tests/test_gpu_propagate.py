@@ -163,7 +163,11 @@ def test_step_vs_series_agree():
     import torch
     wl = workloads.cycle16()
     op = build_gpu(wl)
-    ser = op.propagate(wl.rho0, 0.0, 1.0, 10).cpu().numpy()
+    ser = op.series(wl.rho0, 0.0, 10.0, 10).cpu().numpy()
+    assert np.array_equal(ser, op.propagate(wl.rho0, 0.0, 1.0, 10).cpu().numpy())
+    late = op.series(wl.rho0, 2.0, 5.0, 3).cpu().numpy()          # t1 != 0
+    assert np.abs(late - op.propagate(wl.rho0, 2.0, 1.0, 3).cpu().numpy()).max() == 0.0
+    assert np.abs(late[0] - ser[2]).max() <= 1e-13
     rho = torch.from_numpy(wl.rho0).cuda()
     for k in range(1, 11):
         rho = op.step(rho, 1.0)
