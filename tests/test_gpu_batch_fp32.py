@@ -116,3 +116,43 @@ def test_fp32_walk_bytes_are_half():
     b32 = qsw.Engine.walk_bytes(op, 4, 0.0, wl.dt, wl.n_steps, 4)
     assert 0 < b32 < b64 and b32 * 2 <= b64 + 6 * 256
     op.close()
+
+
+def test_fp32_complex_valued_operator():
+    """An explicit operator with complex entries (complex layout, no
+    phase-split values) as a single-precision-products walk, next to a
+    graph walk: each column bitwise its single-walk result."""
+    import torch
+    import paper_2003_02450_amd as qsw
+    rng = np.random.Generator(np.random.PCG64(91))
+    N = 12
+    A = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    H = (A + A.conj().T) / 2
+    Ls = [np.outer(rng.standard_normal(N) + 1j * rng.standard_normal(N), np.eye(N)[k])
+          for k in range(3)]
+    op_c = qsw.Superop.from_general(H, Ls, 0.4)
+    assert not op_c.info()["split"]
+    op_c.set_precision("fp32")
+    wl_g = _mixed_walks()[0]
+    op_g = build_gpu(wl_g)
+    op_g.set_precision("fp32")
+    dev = torch.device("cuda", 0)
+    rho_c = np.stack([workloads.random_density(N, rng, rank=2) for _ in range(2)])
+    items, outs = [], []
+    for op, r0, t0, dt, q in ((op_c, rho_c, 0.3, 0.5, 6), (op_g, wl_g.rho0, wl_g.t0, wl_g.dt,
+                                                             wl_g.n_steps)):
+        r = torch.from_numpy(r0).to(dev)
+        o = torch.empty((q + 1,) + r0.shape, dtype=torch.complex128, device=dev)
+        items.append((op, r, t0, dt, q, o, None))
+        outs.append(o)
+    st = qsw.batch_propagate(items)
+    torch.cuda.synchronize()
+    assert st["live"] == 0 and not st["nonfinite"]
+    for (op, r, t0, dt, q, _, _), o in zip(items, outs):
+        got = o.cpu().numpy()
+        for c in range(r.shape[0]):
+            ref = op.propagate(r[c], t0, dt, q)
+            torch.cuda.synchronize()
+            assert np.array_equal(got[:, c], ref.cpu().numpy()), c
+    op_c.close()
+    op_g.close()
