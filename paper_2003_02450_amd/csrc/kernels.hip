@@ -2070,6 +2070,16 @@ __global__ void unit_cols_kernel(double2 *X, int64_t n, int64_t i0, int64_t i1) 
   }
 }
 
+// dst = src with the two interleaved columns of every row exchanged.
+__global__ void swap_pairs_kernel(double2 *dst, const double2 *src, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double2 u = src[2 * i], v = src[2 * i + 1];
+    dst[2 * i] = v;
+    dst[2 * i + 1] = u;
+  }
+}
+
 // Total order of the estimator's candidates: larger h first, then smaller index.
 __device__ __forceinline__ bool cand_better(double va, int64_t ia, double vb, int64_t ib) {
   return va > vb || (va == vb && ia < ib);
@@ -3274,6 +3284,13 @@ hipError_t launch_unit_cols(double2 *X, int64_t n, int64_t i0, int64_t i1, hipSt
   int grid = blocks_for(n);
   if (grid > 4096) grid = 4096;
   hipLaunchKernelGGL(unit_cols_kernel, dim3(grid), dim3(kBlock), 0, s, X, n, i0, i1);
+  return hipGetLastError();
+}
+
+hipError_t launch_swap_pairs(double2 *dst, const double2 *src, int64_t n, hipStream_t s) {
+  int grid = blocks_for(n);
+  if (grid > 4096) grid = 4096;
+  hipLaunchKernelGGL(swap_pairs_kernel, dim3(grid), dim3(kBlock), 0, s, dst, src, n);
   return hipGetLastError();
 }
 

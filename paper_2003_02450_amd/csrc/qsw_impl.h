@@ -442,6 +442,8 @@ struct PostList {
 hipError_t launch_post_list(const PostList &l, HostPost *dst, unsigned long long seq,
                             hipStream_t s);
 hipError_t launch_unit_cols(double2 *X, int64_t n, int64_t i0, int64_t i1, hipStream_t s);
+// dst = src (n x 2 interleaved) with its two columns exchanged; dst != src.
+hipError_t launch_swap_pairs(double2 *dst, const double2 *src, int64_t n, hipStream_t s);
 hipError_t launch_topk(const double *h, int64_t n, int K, int grid, double *cand_v, int64_t *cand_i,
                        double *out_v, int64_t *out_i, hipStream_t s);
 

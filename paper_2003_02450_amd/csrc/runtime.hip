@@ -477,6 +477,62 @@ struct Estimator {
     return hipSuccess;
   }
 
+  // Unit-column chains.  The forward products of an iteration k >= 2 start
+  // from unit columns X = [e_i, e_j]; their intermediate powers A^q X are
+  // kept in lad[q] (q < the chain's p), so that a later estimate whose unit
+  // pair is the same, in either order, takes A^(p-1) X from there (columns
+  // exchanged if need be) and computes only its last product: the same
+  // products in the same order, so the estimates are unchanged.  The
+  // estimates run from the largest p down, so a kept chain is at least as
+  // long as a later one needs.  Null lad[1]: nothing kept.
+  double2 *lad[kPMax + 1] = {};
+  int lad_len = 0;                 // lad[1 .. lad_len] hold A^q X_lad
+  int64_t lad_ind[2] = {-1, -1};   // X_lad = [e_lad_ind[0], e_lad_ind[1]]
+
+  // Y = A^p [e_ind[0], e_ind[1]] (second column zero for one probe
+  // column), epilogue 1.
+  hipError_t forward_units(const int64_t ind[2], int p) {
+    const int64_t i1 = columns() == 2 ? ind[1] : -1;
+    if (!lad[1] || p < 2 || p - 1 > kPMax) {
+      hipError_t e = launch_unit_cols(X, n, ind[0], i1, s);
+      return e != hipSuccess ? e : power(false, X, Y, p, 1);
+    }
+    const bool same = ind[0] == lad_ind[0] && i1 == lad_ind[1];
+    const bool swapped = i1 >= 0 && ind[0] == lad_ind[1] && i1 == lad_ind[0];
+    SpmvArgs a = fwd;
+    if ((same || swapped) && lad_len >= p - 1) {
+      const double2 *src = lad[p - 1];
+      if (swapped) {
+        hipError_t e = launch_swap_pairs(W0, src, n, s);
+        if (e != hipSuccess) return e;
+        src = W0;
+      }
+      a.x = src;
+      a.y = Y;
+      hipError_t e = launch_spmm2(a, fsplit, 1, part, S, h, grid, s);
+      if (e != hipSuccess) return e;
+      ++products;
+      return hipSuccess;
+    }
+    hipError_t e0 = launch_unit_cols(X, n, ind[0], i1, s);
+    if (e0 != hipSuccess) return e0;
+    lad_len = 0;
+    lad_ind[0] = ind[0];
+    lad_ind[1] = i1;
+    const double2 *src = X;
+    for (int q = 1; q <= p; ++q) {
+      double2 *dst = q == p ? Y : lad[q];
+      a.x = src;
+      a.y = dst;
+      hipError_t e = launch_spmm2(a, fsplit, q == p ? 1 : 0, part, S, h, grid, s);
+      if (e != hipSuccess) return e;
+      ++products;
+      src = dst;
+    }
+    lad_len = p - 1;
+    return hipSuccess;
+  }
+
   // The decisions of one estimate (Higham and Tisseur's iteration): the
   // sequential path and the merged chains share them, so both reach the same
   // estimate from the same products.
@@ -563,7 +619,7 @@ struct Estimator {
         cs[0] = first_cs[p][0];
         cs[1] = first_cs[p][1];
       } else {
-        e = power(false, X, Y, p, 1);
+        e = forward_units(c.ind, p);
         if (e != hipSuccess) return e;
         e = launch_sum_partials(part, grid, sums, s);
         if (e != hipSuccess) return e;
@@ -589,8 +645,6 @@ struct Estimator {
       }
       const double hb = hb_wanted ? post_host->v[nw] : 0.0;
       if (after_adjoint(c, tv, ti, nw, hb)) break;
-      e = launch_unit_cols(X, n, c.ind[0], t == 2 ? c.ind[1] : -1, s);
-      if (e != hipSuccess) return e;
     }
     *est_out = c.est;
     *index_out = c.ind_best;
@@ -1486,7 +1540,13 @@ qsw_status_t build_common(std::shared_ptr<Assembler> src, double omega, hipStrea
       }
       if (e != hipSuccess) break;
     } else {
-      for (int p = 2; p <= kPMax + 1; ++p) {
+      // one estimate at a time, largest p first (unit-column chains kept
+      // for the later ones when the memory allows)
+      const size_t lad_bytes = (size_t)kPMax * 2 * sizeof(double2) * (size_t)n;
+      if (env_int("QSW_EST_SHARE", 1) != 0 && lad_bytes <= kEstWideBytes)
+        for (int q = 1; q <= kPMax && e == hipSuccess; ++q) e = dalloc(&E.lad[q], 2 * (size_t)n);
+      if (e != hipSuccess) break;
+      for (int p = kPMax + 1; p >= 2; --p) {
         double est = 0.0;
         int64_t idx = -1;
         int probe = 0;
@@ -1506,6 +1566,7 @@ qsw_status_t build_common(std::shared_ptr<Assembler> src, double omega, hipStrea
   dfree(E.Win); dfree(E.Wa); dfree(E.Wb); dfree(E.hc); dfree(E.partc); dfree(E.sumc);
   dfree(E.topc_v); dfree(E.topc_i);
   for (double2 *&b : E.Sp) dfree(b);
+  for (double2 *&b : E.lad) dfree(b);
   // back to the pool only with no post in flight (else it is left allocated)
   if (e == hipSuccess || hipStreamSynchronize(s) == hipSuccess) post_put(E.post_host, E.post_dev);
   dfree(arp); dfree(acol); dfree(aval);
