@@ -1543,9 +1543,15 @@ qsw_status_t build_common(std::shared_ptr<Assembler> src, double omega, hipStrea
       // one estimate at a time, largest p first (unit-column chains kept
       // for the later ones when the memory allows)
       const size_t lad_bytes = (size_t)kPMax * 2 * sizeof(double2) * (size_t)n;
-      if (env_int("QSW_EST_SHARE", 1) != 0 && lad_bytes <= kEstWideBytes)
+      if (env_int("QSW_EST_SHARE", 1) != 0 && lad_bytes <= kEstWideBytes) {
         for (int q = 1; q <= kPMax && e == hipSuccess; ++q) e = dalloc(&E.lad[q], 2 * (size_t)n);
-      if (e != hipSuccess) break;
+        if (e != hipSuccess) {
+          // an optimisation only: without the memory, no chains are kept
+          (void)hipGetLastError();
+          for (double2 *&b : E.lad) dfree(b);
+          e = hipSuccess;
+        }
+      }
       for (int p = kPMax + 1; p >= 2; --p) {
         double est = 0.0;
         int64_t idx = -1;
