@@ -494,16 +494,29 @@ __device__ __forceinline__ float2 masked(bool keep, float2 v) {
 
 // Complex value of an entry: stored (complex layouts) or rebuilt from the
 // phase-split coefficient, with scalar selects only.
-template <bool SPLIT, class V, class R>
+//
+// ADJ (phase-split layouts of graph walks with a real H): the entry of
+// L^dagger at the same place instead.  Off the rows (a, a), L^dagger has the
+// rows of L with every Hamiltonian entry (imaginary) negated and the
+// diagonal conjugated; in a row (a, a) the real off-diagonal entries of L
+// are its population transfers, which L^dagger does not hold there: the
+// product kernels leave the rows (a, a) to adj_diag_rows.
+template <bool SPLIT, class V, class R, bool ADJ = false>
 __device__ __forceinline__ V decode(int raw, R cf, V v, V dg) {
   if constexpr (!SPLIT) {
     return v;
   } else {
     const uint32_t r = (uint32_t)raw;
     const bool im = (r & kImagBit) != 0u, diag = (r & kDiagBit) != 0u;
-    const R re = diag ? dg.x : (im ? R(0) : cf);
-    const R ii = diag ? dg.y : (im ? cf : R(0));
-    return cplxf(re, ii);
+    if constexpr (ADJ) {
+      const R re = diag ? dg.x : R(0);
+      const R ii = diag ? -dg.y : (im ? -cf : R(0));
+      return cplxf(re, ii);
+    } else {
+      const R re = diag ? dg.x : (im ? R(0) : cf);
+      const R ii = diag ? dg.y : (im ? cf : R(0));
+      return cplxf(re, ii);
+    }
   }
 }
 
@@ -601,12 +614,14 @@ __device__ __forceinline__ WaveHead wave_head(const SpmvArgs &a, int64_t k) {
 }
 
 template <int NRHS, bool F32, bool STAGE, class Epi, bool SOA = false, bool SPLIT = false,
-          bool X32 = false>
+          bool X32 = false, bool ADJ = false>
 __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const WaveHead &hd,
                                              Epi &epi, const VecT<X32> *xs, int64_t base,
                                              bool staged = true, int64_t span = 0) {
   // X32: complex64 x, single-precision values and sums (F32 layouts only)
   static_assert(!X32 || F32, "single-precision products read single-precision values");
+  // ADJ: products with L^dagger through the layout of L (see decode)
+  static_assert(!ADJ || (SPLIT && !X32 && !SOA), "adjoint products read phase-split double layouts");
   using V = VecT<X32>;
   using R = RealT<X32>;
   // one right-hand side: xs holds x[base .. base + span) (span = N by default)
@@ -622,6 +637,12 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
   const int orow = hd.orow;
   typename Epi::Pre pre{};
   if (lane < nr) pre = epi.pre(r0 + orow);
+  // ADJ: rows (a, a) are left to adj_diag_rows
+  bool adj_skip = false;
+  if constexpr (ADJ) {
+    const int64_t row = r0 + orow;
+    adj_skip = row == (row / a.N) * ((int64_t)a.N + 1);
+  }
   const V dg = cplx<V>(hd.dg.x, hd.dg.y);  // exact: single values come from floats
   R acc[2 * NRHS];
 #pragma unroll
@@ -660,8 +681,12 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
           const R cf = F32 ? (R)(float)e : (R)e;
           const bool im = (flags & kImagBit) != 0u;
           // wave-uniform (lanes past the block's rows gather at row r0, in
-          // bounds, and their sums are never written)
-          v[u] = cplxf(im ? R(0) : cf, im ? cf : R(0));
+          // bounds, and their sums are never written); ADJ: a shared real
+          // entry is a population transfer of a lone row (a, a) (decode)
+          if constexpr (ADJ)
+            v[u] = cplxf(R(0), im ? -cf : R(0));
+          else
+            v[u] = cplxf(im ? R(0) : cf, im ? cf : R(0));
           c[u] = row + off;
         }
         V xg[S][NRHS];
@@ -740,7 +765,7 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
           xg[u][r] = gld(xbase<X32>(a) + (SOA ? (int64_t)r * a.n + col[u] : col[u] * NRHS + r));
 #pragma unroll
       for (int u = 0; u < kWaveUnroll; ++u) {
-        const V vz = masked(ok[u], decode<SPLIT>(c[u], cf[u], v[u], dg));
+        const V vz = masked(ok[u], decode<SPLIT, V, R, ADJ>(c[u], cf[u], v[u], dg));
 #pragma unroll
         for (int r = 0; r < NRHS; ++r) cmac(acc[2 * r], acc[2 * r + 1], vz, xg[u][r]);
       }
@@ -771,7 +796,7 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
       }
 #pragma unroll
       for (int u = 0; u < kWaveUnroll; ++u) {
-        const V vz = masked(ok[u], decode<SPLIT>(c[u], cf[u], v[u], dg));
+        const V vz = masked(ok[u], decode<SPLIT, V, R, ADJ>(c[u], cf[u], v[u], dg));
 #pragma unroll
         for (int r = 0; r < NRHS; ++r) cmac(acc[2 * r], acc[2 * r + 1], vz, xv[u][r]);
       }
@@ -837,7 +862,8 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
 #pragma unroll
         for (int u = 0; u < kWaveUnroll; ++u) {
           const bool im = ((uint32_t)c[u] & kImagBit) != 0u;
-          const R cm = ok[u] ? cf[u] : R(0);
+          // ADJ: Hamiltonian entries negated, real ones (transfers) dropped
+          const R cm = ok[u] ? (ADJ ? (im ? -cf[u] : R(0)) : cf[u]) : R(0);
 #pragma unroll
           for (int r = 0; r < NRHS; ++r) {
             const R sx = im ? xv[u][r].y : xv[u][r].x;
@@ -853,7 +879,7 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
         // position G: every running row's diagonal (stored in the stream as
         // a marker, its value in dg)
         const int cnt = __popcll(__ballot(len > G));
-        const V vz = masked(lane < cnt, dg);
+        const V vz = masked(lane < cnt, ADJ ? cplxf(dg.x, -dg.y) : dg);
 #pragma unroll
         for (int r = 0; r < NRHS; ++r) cmac(acc[2 * r], acc[2 * r + 1], vz, xs[lrel * NRHS + r]);
         ps += cnt;
@@ -896,7 +922,7 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
     for (int p0 = 0; p0 < maxlen; p0 += kWaveUnroll)
       group(std::integral_constant<int, kGatherAny>{}, p0);
   }
-  if (lane < nr) epi(r0 + orow, acc, pre);
+  if (lane < nr && !adj_skip) epi(r0 + orow, acc, pre);
 }
 
 template <int NRHS, bool F32, bool STAGE, class Epi, bool SOA = false, bool SPLIT = false,
@@ -927,10 +953,12 @@ __device__ __forceinline__ void stage_copy(T *xs, const T *src, int cnt) {
     if (u * kBlock < cnt && t + u * kBlock < cnt) xs[t + u * kBlock] = v[u];
 }
 
-template <int NRHS, bool F32, bool STAGE, bool SPLIT, class Epi, bool X32 = false>
-__device__ __forceinline__ void wave_engine(const SpmvArgs &a, Epi &epi) {
+// `grid`: the workgroups that take blocks (0: all of the launch).
+template <int NRHS, bool F32, bool STAGE, bool SPLIT, class Epi, bool X32 = false,
+          bool ADJ = false>
+__device__ __forceinline__ void wave_engine(const SpmvArgs &a, Epi &epi, int grid = 0) {
   constexpr int WPB = kBlock / 64;  // wavefronts per workgroup
-  const int64_t nw = (int64_t)gridDim.x * WPB;
+  const int64_t nw = (int64_t)(grid > 0 ? grid : (int)gridDim.x) * WPB;
   extern __shared__ double2 xs_lds[];
   VecT<X32> *xs = reinterpret_cast<VecT<X32> *>(xs_lds);
   for (int64_t kb = (int64_t)blockIdx.x * WPB; kb < a.nwb; kb += nw) {
@@ -948,8 +976,8 @@ __device__ __forceinline__ void wave_engine(const SpmvArgs &a, Epi &epi) {
       __syncthreads();
     }
     if (k < a.nwb)
-      wave_block_h<NRHS, F32, STAGE, Epi, false, SPLIT, X32>(a, k, wave_head_use(a, k, raw), epi,
-                                                             xs, base);
+      wave_block_h<NRHS, F32, STAGE, Epi, false, SPLIT, X32, ADJ>(a, k, wave_head_use(a, k, raw),
+                                                                  epi, xs, base);
   }
 }
 
@@ -1595,6 +1623,41 @@ __global__ __launch_bounds__(kBlock) void wjag_same_kernel(const int32_t *wcol, 
 }
 
 // max over rows of sum_e |val[e]|  (on the adjoint this is ||L||_1).
+// ||L||_1 as the largest row sum of |L^dagger| from the CSR of L (graph
+// walks with a real H, whose rows are in structural order: the H rho
+// entries, the diagonal, the rho H entries, then the population transfers):
+// off the rows (a, a) a row of L^dagger holds the moduli of the row of L in
+// the same order; a row (a, a) holds those of its first entries and then
+// its own transfers (omega R_ja, ascending j; frp: the rates' row pointer of
+// L, whose transfers it drops) - the sums, in the order of the assembled
+// CSR of L^dagger, are bit for bit row_abs_max_kernel's on that CSR.
+__global__ __launch_bounds__(kBlock) void adj_row_abs_max_kernel(
+    int64_t n, int32_t N, const int64_t *rp, const double2 *val, const int64_t *frp,
+    const int64_t *trp, const double *tval, unsigned long long *out) {
+  const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  unsigned long long m[1] = {0ull};
+  if (r < n) {
+    const int64_t a = r / N;
+    const bool diag_row = r == a * ((int64_t)N + 1);
+    double s = 0.0;
+    const int64_t e0 = rp[r];
+    const int64_t e1 = rp[r + 1] - (diag_row ? frp[a + 1] - frp[a] : 0);
+    for (int64_t i0 = e0; i0 < e1; i0 += 8) {
+      double2 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = val[min(i0 + u, e1 - 1)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (i0 + u < e1) s += cabs2(v[u]);
+    }
+    if (diag_row)
+      for (int64_t e = trp[a]; e < trp[a + 1]; ++e) s += cabs2(make_double2(tval[e], 0.0));
+    m[0] = abs_bits(s);
+  }
+  unsigned long long *const dst[1] = {out};
+  block_umax_to<1>(m, dst, nullptr);
+}
+
 __global__ __launch_bounds__(kBlock) void row_abs_max_kernel(int64_t n, const int64_t *rp,
                                                              const double2 *val,
                                                              unsigned long long *out) {
@@ -1911,13 +1974,101 @@ __global__ __launch_bounds__(kBlock) void series_accum_kernel(DeviceState *st, P
 }
 
 // --------------------------------------------------------------------------
-// Two right-hand sides (block 1-norm estimation), stream engine.
+// ADJ products: the rows (a, a) of L^dagger, one wavefront each, from the
+// CSR of L (structural row order: H rho entries, diagonal, rho H entries,
+// then the transfers of L, which are dropped) and the transposed rates.  The
+// terms go in the order and form of the assembled L^dagger's phase-split
+// layout, where the row's H rho entries and its own transfers are its
+// entries outside its rho-row and come first, then the diagonal and the
+// rho H entries: each a complex multiply-add with the value (0, coef),
+// (coef, 0) or the diagonal.  The lanes fetch 64 terms at a time; every
+// lane then takes them in order from the lanes (readlane), so the sums are
+// that layout's (up to the sign of a zero) and reach the same epilogue.
+__device__ __forceinline__ double rdl(double v, int l) {
+  const long long u = __double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)u >> 32), l);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+template <int NRHS, class Epi>
+__device__ __forceinline__ void adj_diag_row(const SpmvArgs &a, int64_t ra, Epi &epi) {
+  const int lane = threadIdx.x & 63;
+  const int64_t N = a.N, row = ra * (N + 1);
+  const int64_t e0 = a.rp[row], e1 = a.rp[row + 1];
+  const int64_t t0 = a.trp[ra], t1 = a.trp[ra + 1];
+  // the diagonal (ed; always stored) and the end of the rho H entries (er)
+  int64_t ed = e1, er = e1;
+  for (int64_t b = e0; b < e1 && ed == e1; b += 64) {
+    const int64_t e = b + lane;
+    const unsigned long long m = __ballot(e < e1 && (int64_t)a.col[e] == row);
+    if (m) ed = b + __ffsll((long long)m) - 1;
+  }
+  for (int64_t b = ed + 1; b < e1 && er == e1; b += 64) {
+    const int64_t e = b + lane;
+    const unsigned long long m = __ballot(e < e1 && (int64_t)a.col[e] / N != ra);
+    if (m) er = b + __ffsll((long long)m) - 1;
+  }
+  const int64_t nh = ed - e0, nt = t1 - t0;
+  const int64_t terms = ed < e1 ? nh + nt + 1 + (er - ed - 1) : nh + nt;
+  double acc[2 * NRHS];
+#pragma unroll
+  for (int q = 0; q < 2 * NRHS; ++q) acc[q] = 0.0;
+  for (int64_t b = 0; b < terms; b += 64) {
+    // term q = b + lane: value and column
+    const int64_t q = b + lane;
+    double2 v = make_double2(0.0, 0.0);
+    int64_t c = row;
+    if (q < terms) {
+      if (q < nh) {
+        v = make_double2(0.0, -a.val[e0 + q].y);
+        c = a.col[e0 + q];
+      } else if (q < nh + nt) {
+        v = make_double2(a.tval[t0 + q - nh], 0.0);
+        c = (int64_t)a.tcol[t0 + q - nh] * (N + 1);
+      } else if (q == nh + nt) {
+        const double2 d = a.val[ed];
+        v = make_double2(d.x, -d.y);
+      } else {
+        const int64_t e = ed + 1 + (q - nh - nt - 1);
+        v = make_double2(0.0, -a.val[e].y);
+        c = a.col[e];
+      }
+    }
+    double2 xq[NRHS];
+#pragma unroll
+    for (int r = 0; r < NRHS; ++r) xq[r] = a.x[c * NRHS + r];
+    const int cnt = (int)min((int64_t)64, terms - b);
+    for (int i = 0; i < cnt; ++i) {
+      const double2 vi = make_double2(rdl(v.x, i), rdl(v.y, i));
+#pragma unroll
+      for (int r = 0; r < NRHS; ++r)
+        cmac(acc[2 * r], acc[2 * r + 1], vi, make_double2(rdl(xq[r].x, i), rdl(xq[r].y, i)));
+    }
+  }
+  if (lane == 0) epi(row, acc, typename Epi::Pre{});
+}
+
+// The ADJ product kernels' last workgroups (from a.adj_grid on) take the rows
+// (a, a), one per wavefront; true for them.
+template <int NRHS, class Epi>
+__device__ __forceinline__ bool adj_diag_rows(const SpmvArgs &a, Epi &epi) {
+  if ((int)blockIdx.x < a.adj_grid) return false;
+  const int64_t ra = (int64_t)(blockIdx.x - a.adj_grid) * (kBlock / 64) + (threadIdx.x >> 6);
+  if (ra < a.N) adj_diag_row<NRHS>(a, ra, epi);
+  return true;
+}
+
+// Two right-hand sides (block 1-norm estimation) through the wave layout;
+// ADJ: products with L^dagger through the layout of L.
 // --------------------------------------------------------------------------
-template <bool SPLIT, bool STAGE>
+template <bool SPLIT, bool STAGE, bool ADJ = false>
 __global__ __launch_bounds__(kBlock) void spmm2_kernel(SpmvArgs a, int mode, double *part,
                                                        double2 *sgn, double *h) {
   Spmm2Epi epi{a.y, mode, sgn, h};
-  wave_engine<2, false, STAGE, SPLIT>(a, epi);
+  if constexpr (ADJ)
+    if (adj_diag_rows<2>(a, epi)) return;
+  wave_engine<2, false, STAGE, SPLIT, Spmm2Epi, false, ADJ>(a, epi, ADJ ? a.adj_grid : 0);
   if (mode == 1) {
     // deterministic per-workgroup column sums: fixed tree over the threads
     __shared__ double sm0[kBlock], sm1[kBlock];
@@ -1970,10 +2121,12 @@ struct WideEpi {
   }
 };
 
-template <bool SPLIT, int NR>
+template <bool SPLIT, int NR, bool ADJ = false>
 __global__ __launch_bounds__(kBlock) void spmm_wide_kernel(SpmvArgs a, WideOut o) {
   WideEpi<NR> epi{o};
-  wave_engine<NR, false, false, SPLIT>(a, epi);
+  if constexpr (ADJ)
+    if (adj_diag_rows<NR>(a, epi)) return;
+  wave_engine<NR, false, false, SPLIT, WideEpi<NR>, false, ADJ>(a, epi, ADJ ? a.adj_grid : 0);
   if (o.fin && o.mode == 1) {
     __shared__ double sm0[kBlock], sm1[kBlock];
     sm0[threadIdx.x] = epi.s0;
@@ -1992,6 +2145,7 @@ __global__ __launch_bounds__(kBlock) void spmm_wide_kernel(SpmvArgs a, WideOut o
     }
   }
 }
+
 
 __global__ void pack_pairs_kernel(double2 *W, int64_t n, PairSources ps) {
   const int c = 2 * ps.chains;
@@ -3028,6 +3182,15 @@ hipError_t launch_row_abs_max(int64_t n, const int64_t *rp, const double2 *val,
   return hipGetLastError();
 }
 
+hipError_t launch_adj_row_abs_max(int64_t n, int32_t N, const int64_t *rp, const double2 *val,
+                                  const int64_t *frp, const int64_t *trp, const double *tval,
+                                  unsigned long long *out_bits, hipStream_t s) {
+  if (n <= 0 || N <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(adj_row_abs_max_kernel, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, N, rp,
+                     val, frp, trp, tval, out_bits);
+  return hipGetLastError();
+}
+
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s) {
   const size_t words = bytes / 4;
   int grid = (int)((words + kBlock - 1) / kBlock);
@@ -3176,13 +3339,22 @@ hipError_t launch_spmm2(const SpmvArgs &a, bool split, int mode, double *part, d
   // both columns of the rho-row staged in LDS when they fit
   const size_t lds = (size_t)a.N * 2 * sizeof(double2);
   const bool stage = a.N > 0 && lds <= kStageMaxBytes;
-#define QSW_L(SP, ST)                                                                       \
-  hipLaunchKernelGGL((spmm2_kernel<SP, ST>), dim3(grid), dim3(kBlock), ST ? lds : 0, s, a, mode, \
-                     part, sgn, h)
-  if (split && stage) QSW_L(true, true);
-  else if (split) QSW_L(true, false);
-  else if (stage) QSW_L(false, true);
-  else QSW_L(false, false);
+#define QSW_L(SP, ST, AD, G, A)                                                           \
+  hipLaunchKernelGGL((spmm2_kernel<SP, ST, AD>), dim3(G), dim3(kBlock), ST ? lds : 0, s, A, \
+                     mode, part, sgn, h)
+  if (a.adj_fwd) {
+    // L^dagger through the phase-split layout of L: `grid` workgroups for
+    // the blocks, then one wavefront per row (a, a)
+    if (!split || !a.trp || mode == 1 || a.N < 1) return hipErrorInvalidValue;
+    SpmvArgs b = a;
+    b.adj_grid = grid;
+    const int all = grid + (int)((a.N + kBlock / 64 - 1) / (kBlock / 64));
+    if (stage) QSW_L(true, true, true, all, b);
+    else QSW_L(true, false, true, all, b);
+  } else if (split && stage) QSW_L(true, true, false, grid, a);
+  else if (split) QSW_L(true, false, false, grid, a);
+  else if (stage) QSW_L(false, true, false, grid, a);
+  else QSW_L(false, false, false, grid, a);
 #undef QSW_L
   return hipGetLastError();
 }
@@ -3191,11 +3363,20 @@ hipError_t launch_spmm_wide(const SpmvArgs &a, bool split, int nr, const WideOut
                             hipStream_t s) {
   if (nr < 2 || nr > 2 * kEstChainsMax || (nr & 1) || o.ys < 0 || o.ys > nr) return hipErrorInvalidValue;
   if (o.ys != nr - 2 * (o.fin ? 1 : 0)) return hipErrorInvalidValue;
-#define QSW_L(SP, R) hipLaunchKernelGGL((spmm_wide_kernel<SP, R>), dim3(grid), dim3(kBlock), 0, s, a, o)
-#define QSW_W(R)            \
-  case R:                   \
-    if (split) QSW_L(true, R); \
-    else QSW_L(false, R);   \
+  if (a.adj_fwd && (!split || !a.trp || (o.fin && o.mode == 1) || a.N < 1))
+    return hipErrorInvalidValue;
+  // ADJ: L^dagger through the phase-split layout of L: `grid` workgroups for
+  // the blocks, then one wavefront per row (a, a)
+  SpmvArgs b = a;
+  b.adj_grid = grid;
+  const int all = grid + (int)((a.N + kBlock / 64 - 1) / (kBlock / 64));
+#define QSW_L(SP, R, AD, G, A) \
+  hipLaunchKernelGGL((spmm_wide_kernel<SP, R, AD>), dim3(G), dim3(kBlock), 0, s, A, o)
+#define QSW_W(R)                                \
+  case R:                                       \
+    if (a.adj_fwd) QSW_L(true, R, true, all, b); \
+    else if (split) QSW_L(true, R, false, grid, a); \
+    else QSW_L(false, R, false, grid, a);       \
     break;
   switch (nr) {
     QSW_W(2) QSW_W(4) QSW_W(6) QSW_W(8) QSW_W(10) QSW_W(12) QSW_W(14) QSW_W(16)

@@ -173,6 +173,17 @@ struct SpmvArgs {
   float2 *y32;
   const float2 *fin_hi, *fin_lo;
   float2 *fout_hi, *fout_lo;
+  // products with L^dagger through the phase-split layout of L (graph walks
+  // with a real H; the estimator's adjoint products): Hamiltonian entries
+  // negated, the diagonal conjugated, the real off-diagonal entries (the
+  // population transfers of the rows (a, a)) dropped and L^dagger's own
+  // added from the transposed rates: row a of trp / tcol / tval holds
+  // omega R_ja for rho_jj, ascending j
+  int32_t adj_fwd;
+  int32_t adj_grid;  // (set by the launch) workgroups taking blocks; the rest take the rows (a, a)
+  const int64_t *trp;
+  const int32_t *tcol;
+  const double *tval;
 };
 
 // ---- batched propagation (several walks advance together) ----
@@ -286,6 +297,13 @@ struct BatchArgs {
 hipError_t launch_assemble(const AssembleArgs &a, int64_t n, hipStream_t s);
 hipError_t launch_row_abs_max(int64_t n, const int64_t *rp, const double2 *val,
                               unsigned long long *out_bits, hipStream_t s);
+// The same maximum (||L||_1) from the CSR of L of a graph walk with a real
+// H, without the CSR of L^dagger: frp is the row pointer of L's rates, trp /
+// tval the transposed rates' (omega R_ja in row a); bit for bit the value of
+// launch_row_abs_max on L^dagger's CSR.
+hipError_t launch_adj_row_abs_max(int64_t n, int32_t N, const int64_t *rp, const double2 *val,
+                                  const int64_t *frp, const int64_t *trp, const double *tval,
+                                  unsigned long long *out_bits, hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_copy(double2 *dst, const double2 *src, int64_t n, hipStream_t s);
 hipError_t launch_to_c64(float2 *dst, const double2 *src, int64_t n, hipStream_t s);

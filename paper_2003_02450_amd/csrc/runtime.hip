@@ -1144,6 +1144,17 @@ struct qsw::Assembler {
   virtual int64_t max_row(double omega) const = 0;
   virtual qsw_status_t assemble(bool adjoint, double omega, hipStream_t s, int64_t **rp,
                                 int32_t **col, double2 **val, int64_t *nnz) const = 0;
+  // Walks whose L^dagger differs from L only as the adjoint products through
+  // L's layout assume (a real H; population transfers only in the rows
+  // (a, a)): frp, the row pointer of L's rates, and trp / tcol / tval, the
+  // transposed rates with the values L^dagger's assembly writes (row a:
+  // omega R_ja for rho_jj, ascending j).  False: L^dagger is assembled.
+  virtual bool adjoint_transfers(double omega, std::vector<int64_t> &frp,
+                                 std::vector<int64_t> &trp, std::vector<int32_t> &tcol,
+                                 std::vector<double> &tval) const {
+    (void)omega, (void)frp, (void)trp, (void)tcol, (void)tval;
+    return false;
+  }
 };
 
 namespace {
@@ -1159,6 +1170,20 @@ struct LocalAssembler : Assembler {
   qsw_status_t assemble(bool adjoint, double omega, hipStream_t s, int64_t **rp, int32_t **col,
                         double2 **val, int64_t *nnz) const override {
     return ::assemble(op, effective_rates(op, omega), adjoint, omega, s, rp, col, val, nnz);
+  }
+  bool adjoint_transfers(double omega, std::vector<int64_t> &frp, std::vector<int64_t> &trp,
+                         std::vector<int32_t> &tcol, std::vector<double> &tval) const override {
+    for (size_t i = 1; i < op.hv.size(); i += 2)
+      if (op.hv[i] != 0.0) return false;  // a complex H: its entries are not all imaginary in L
+    const Rates R = effective_rates(op, omega);
+    std::vector<double> rtv;
+    // as assemble(adjoint = true) transposes them, and each value as its
+    // kernel scales it
+    transpose_csr(op.N, R.rp, R.rc, R.rv, 1, trp, tcol, rtv);
+    tval.resize(rtv.size());
+    for (size_t e = 0; e < rtv.size(); ++e) tval[e] = R.scale * rtv[e];
+    frp = R.rp;
+    return true;
   }
 };
 
@@ -1444,13 +1469,26 @@ qsw_status_t build_common(std::shared_ptr<Assembler> src, double omega, hipStrea
       choose_vector_launch(h, eng);
     }
   }
-  // adjoint for ||L||_1 and the estimator
+  // L^dagger for ||L||_1 and the estimator: through the phase-split layout
+  // of L where the walk allows it (no CSR or layout of its own; the same
+  // values bit for bit, QSW_ADJ_LAYOUT=1 assembles it anyway), else
+  // assembled and laid out
+  std::vector<int64_t> hfrp, htrp;
+  std::vector<int32_t> htcol;
+  std::vector<double> htval;
+  const bool adj_fwd = h->split && env_int("QSW_ADJ_LAYOUT", 0) == 0 &&
+                       src->adjoint_transfers(omega, hfrp, htrp, htcol, htval);
   int64_t *arp = nullptr;
   int32_t *acol = nullptr;
   double2 *aval = nullptr;
   int64_t annz = 0;
-  st = src->assemble(true, omega, s, &arp, &acol, &aval, &annz);
-  if (st != QSW_OK) return fail(st);
+  if (!adj_fwd) {
+    st = src->assemble(true, omega, s, &arp, &acol, &aval, &annz);
+    if (st != QSW_OK) return fail(st);
+  }
+  int64_t *dfrp = nullptr, *dtrp = nullptr;
+  int32_t *dtcol = nullptr;
+  double *dtval = nullptr;
   unsigned long long *nbits = nullptr;
   Estimator E{};
   WaveLayout WA;
@@ -1459,7 +1497,27 @@ qsw_status_t build_common(std::shared_ptr<Assembler> src, double omega, hipStrea
   do {
     if ((e = dalloc(&nbits, 1)) != hipSuccess) break;
     if ((e = launch_zero(nbits, sizeof(unsigned long long), s)) != hipSuccess) break;
-    if ((e = launch_row_abs_max(n, arp, aval, nbits, s)) != hipSuccess) break;
+    if (adj_fwd) {
+      const size_t nt = std::max<size_t>(htcol.size(), 1);
+      if ((e = dalloc(&dfrp, hfrp.size())) != hipSuccess) break;
+      if ((e = dalloc(&dtrp, htrp.size())) != hipSuccess) break;
+      if ((e = dalloc(&dtcol, nt)) != hipSuccess) break;
+      if ((e = dalloc(&dtval, nt)) != hipSuccess) break;
+      // the host vectors outlive the copies (the stream is synchronised below)
+      if ((e = hipMemcpyAsync(dfrp, hfrp.data(), hfrp.size() * sizeof(int64_t),
+                              hipMemcpyHostToDevice, s)) != hipSuccess) break;
+      if ((e = hipMemcpyAsync(dtrp, htrp.data(), htrp.size() * sizeof(int64_t),
+                              hipMemcpyHostToDevice, s)) != hipSuccess) break;
+      if (!htcol.empty() &&
+          ((e = hipMemcpyAsync(dtcol, htcol.data(), htcol.size() * sizeof(int32_t),
+                               hipMemcpyHostToDevice, s)) != hipSuccess ||
+           (e = hipMemcpyAsync(dtval, htval.data(), htval.size() * sizeof(double),
+                               hipMemcpyHostToDevice, s)) != hipSuccess)) break;
+      if ((e = launch_adj_row_abs_max(n, N, h->row_ptr, h->val, dfrp, dtrp, dtval, nbits, s)) !=
+          hipSuccess) break;
+    } else if ((e = launch_row_abs_max(n, arp, aval, nbits, s)) != hipSuccess) {
+      break;
+    }
     unsigned long long bits = 0;
     if ((e = hipMemcpyAsync(&bits, nbits, sizeof(bits), hipMemcpyDeviceToHost, s)) != hipSuccess) break;
     if ((e = hipStreamSynchronize(s)) != hipSuccess) break;
@@ -1471,17 +1529,26 @@ qsw_status_t build_common(std::shared_ptr<Assembler> src, double omega, hipStrea
       h->info.d_probe[p] = 0;
     }
     if (!(norm1 > 0.0)) break;  // L = 0: every d_p is 0
-    // adjoint wave-jagged layout (transient)
-    if ((e = build_wave_layout(arp, acol, aval, n, annz, N, s, WA)) != hipSuccess) break;
     E.n = n;
     E.s = s;
     E.fwd.n = n; E.fwd.rp = h->row_ptr; E.fwd.col = h->col; E.fwd.val = h->val;
     set_wave(E.fwd, h);
-    E.adj.n = n; E.adj.rp = arp; E.adj.col = acol; E.adj.val = aval;
-    set_wave(E.adj, WA);
-    E.adj.N = N;
     E.fsplit = h->split;
-    E.asplit = WA.split;
+    if (adj_fwd) {
+      E.adj = E.fwd;
+      E.adj.adj_fwd = 1;
+      E.adj.trp = dtrp;
+      E.adj.tcol = dtcol;
+      E.adj.tval = dtval;
+      E.asplit = true;
+    } else {
+      // adjoint wave-jagged layout (transient)
+      if ((e = build_wave_layout(arp, acol, aval, n, annz, N, s, WA)) != hipSuccess) break;
+      E.adj.n = n; E.adj.rp = arp; E.adj.col = acol; E.adj.val = aval;
+      set_wave(E.adj, WA);
+      E.adj.N = N;
+      E.asplit = WA.split;
+    }
     E.grid = wave_grid(h->nwb, resident_workgroups(1));
     if ((e = dalloc(&E.X, 2 * (size_t)n)) != hipSuccess) break;
     if ((e = dalloc(&E.Y, 2 * (size_t)n)) != hipSuccess) break;
@@ -1576,6 +1643,7 @@ qsw_status_t build_common(std::shared_ptr<Assembler> src, double omega, hipStrea
   // back to the pool only with no post in flight (else it is left allocated)
   if (e == hipSuccess || hipStreamSynchronize(s) == hipSuccess) post_put(E.post_host, E.post_dev);
   dfree(arp); dfree(acol); dfree(aval);
+  dfree(dfrp); dfree(dtrp); dfree(dtcol); dfree(dtval);
   if (e != hipSuccess) return fail(status_of(e));
   if (!std::isfinite(norm1)) return fail(QSW_ERR_NONFINITE);
   h->info.N = N;
