@@ -96,8 +96,10 @@ typedef struct {
                                  the row) read one copy */
     int32_t engine;      /* product kernel of complex128 qsw_propagate calls: traversal (0
                             plain, 100 rho-row staged in LDS, 200 staged with XCD column
-                            bands) + 10 for phase-split values; 3: the CSR stream engine;
-                            4..64: the CSR vector engine with that many lanes per row */
+                            bands, 300 staged with wide position groups, taken for
+                            operators with long rows) + 10 for phase-split values; 3: the
+                            CSR stream engine; 4..64: the CSR vector engine with that many
+                            lanes per row */
 } qsw_info_t;
 
 typedef struct {
@@ -319,7 +321,8 @@ qsw_status_t qsw_superop_set_pacing(qsw_superop_t h, int32_t lookahead);
 typedef struct {
     int32_t staged;          /* 1: the rho-row is staged in LDS for the rho H gathers;
                                 2: staged, and each XCD takes one band of columns of rho
-                                (N = 512, 1024 or 2048) */
+                                (N = 512, 1024 or 2048); 3: staged, with wider groups of
+                                positions at fewer waves per SIMD (double values) */
     int32_t grid;            /* workgroups per product launch */
     double us_per_product;   /* measured time of one product in that configuration */
     int32_t from_cache;      /* 1: taken from an earlier tuning of the same key */
@@ -327,8 +330,9 @@ typedef struct {
 
 /*
  * Time the product kernel on this handle for each launch configuration
- * (rho-row staging off, on where N*16 bytes fit, and with XCD column bands
- * where N allows; grid of 1, 2, 4 and 8 times the resident workgroups),
+ * (rho-row staging off, on where N*16 bytes fit, with XCD column bands
+ * where N allows, and staged with wide position groups for double values;
+ * grid of 1, 2, 4 and 8 times the resident workgroups),
  * keep the fastest for later qsw_propagate /
  * qsw_apply calls and remember it for the key (N, entries per row, precision)
  * in the process, so that later handles with the same key take it without

@@ -134,13 +134,18 @@ struct qsw_superop_s {
 
 namespace qsw {
 
-inline bool is_wave_engine(int engine) { return engine == 0 || engine == 100 || engine == 200; }
+inline bool is_wave_engine(int engine) {
+  return engine == 0 || engine == 100 || engine == 200 || engine == 300;
+}
 
 // Kernel engine of a product launch: the handle's traversal plus its value
 // format (+10 phase-split, +1 single precision when `single`).
 inline int launch_engine(const qsw_superop_s *h, bool single) {
   if (!is_wave_engine(h->engine)) return h->engine;
-  return h->engine + (h->split ? 10 : 0) + (single ? 1 : 0);
+  // wide groups serve double values; single-precision values and products
+  // take the plain staged traversal
+  const int base = (single && h->engine == 300) ? 100 : h->engine;
+  return base + (h->split ? 10 : 0) + (single ? 1 : 0);
 }
 
 // Parameters and workspace layout of one qsw_propagate call.

@@ -425,8 +425,23 @@ __device__ __forceinline__ void stream_engine(const SpmvArgs &a, Epi &epi) {
 // Waves per SIMD of term_kernel<ENGINE>: the wave layouts with double values
 // QSW_TERM_WAVES; single-precision values (format 1 / 11), where five spill,
 // and the CSR engines four.
+// Wide groups (traversal 3: staged, double values): positions per group and
+// waves per SIMD for operators with long rows.  On the complete graph of 400
+// vertices (about 800 entries per row; a step to t = 10, 4008 products)
+// groups of 8 at four waves took 397.7 us per product, of 7 408.6, of 6
+// 419.5 and of 5 428.1, against 433 with the default five at five waves;
+// ten or more spill at four waves.
+#ifndef QSW_UNROLL1_WIDE
+#define QSW_UNROLL1_WIDE 8
+#endif
+#ifndef QSW_TERM_WIDE_WAVES
+#define QSW_TERM_WIDE_WAVES 4
+#endif
 constexpr int term_waves(int engine) {
-  return (engine % 10 == 1 || (engine % 100 != 0 && engine % 100 != 10)) ? 4 : QSW_TERM_WAVES;
+  return engine / 100 == 3
+             ? QSW_TERM_WIDE_WAVES
+             : ((engine % 10 == 1 || (engine % 100 != 0 && engine % 100 != 10)) ? 4
+                                                                                 : QSW_TERM_WAVES);
 }
 #ifndef QSW_SHARED_U1
 #define QSW_SHARED_U1 8  // block-shared positions per group, one right-hand side
@@ -614,7 +629,7 @@ __device__ __forceinline__ WaveHead wave_head(const SpmvArgs &a, int64_t k) {
 }
 
 template <int NRHS, bool F32, bool STAGE, class Epi, bool SOA = false, bool SPLIT = false,
-          bool X32 = false, bool ADJ = false>
+          bool X32 = false, bool ADJ = false, int UNR = 0>
 __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const WaveHead &hd,
                                              Epi &epi, const VecT<X32> *xs, int64_t base,
                                              bool staged = true, int64_t span = 0) {
@@ -626,7 +641,8 @@ __device__ __forceinline__ void wave_block_h(const SpmvArgs &a, int64_t k, const
   using R = RealT<X32>;
   // one right-hand side: xs holds x[base .. base + span) (span = N by default)
   const uint64_t lim = (uint64_t)(span ? span : a.N);
-  constexpr int kWaveUnroll = wave_unroll<NRHS, X32, F32>();
+  // positions per group (UNR: the caller's, else the default for the types)
+  constexpr int kWaveUnroll = UNR > 0 ? UNR : wave_unroll<NRHS, X32, F32>();
   const int lane = threadIdx.x & 63;
   const int64_t r0 = k * kWaveRows;
   const int nr = (int)min((int64_t)kWaveRows, a.n - r0);
@@ -955,7 +971,7 @@ __device__ __forceinline__ void stage_copy(T *xs, const T *src, int cnt) {
 
 // `grid`: the workgroups that take blocks (0: all of the launch).
 template <int NRHS, bool F32, bool STAGE, bool SPLIT, class Epi, bool X32 = false,
-          bool ADJ = false>
+          bool ADJ = false, int UNR = 0>
 __device__ __forceinline__ void wave_engine(const SpmvArgs &a, Epi &epi, int grid = 0) {
   constexpr int WPB = kBlock / 64;  // wavefronts per workgroup
   const int64_t nw = (int64_t)(grid > 0 ? grid : (int)gridDim.x) * WPB;
@@ -976,8 +992,8 @@ __device__ __forceinline__ void wave_engine(const SpmvArgs &a, Epi &epi, int gri
       __syncthreads();
     }
     if (k < a.nwb)
-      wave_block_h<NRHS, F32, STAGE, Epi, false, SPLIT, X32, ADJ>(a, k, wave_head_use(a, k, raw),
-                                                                  epi, xs, base);
+      wave_block_h<NRHS, F32, STAGE, Epi, false, SPLIT, X32, ADJ, UNR>(
+          a, k, wave_head_use(a, k, raw), epi, xs, base);
   }
 }
 
@@ -1047,8 +1063,9 @@ __device__ __forceinline__ void vector_engine(const SpmvArgs &a, Epi &epi) {
   }
 }
 
-// Engines: wave-jagged traversal 0 (plain), 100 (rho-row staged in LDS) or
-// 200 (staged and XCD-banded), plus 1 for single-precision values and 10 for
+// Engines: wave-jagged traversal 0 (plain), 100 (rho-row staged in LDS), 200
+// (staged and XCD-banded) or 300 (staged, wide groups at four waves per
+// SIMD, double values only), plus 1 for single-precision values and 10 for
 // phase-split values; 3 = CSR stream, 4..64 = vector with that many lanes per
 // row.
 template <int ENGINE>
@@ -1064,10 +1081,13 @@ __device__ __forceinline__ void run_engine(const SpmvArgs &a, Epi &epi) {
     vector_engine<ENGINE>(a, epi);
   } else {
     constexpr int trav = ENGINE / 100, fmt = ENGINE % 100;
-    static_assert(trav <= 2 && (fmt == 0 || fmt == 1 || fmt == 10 || fmt == 11), "engine");
+    static_assert(trav <= 3 && (fmt == 0 || fmt == 1 || fmt == 10 || fmt == 11), "engine");
+    static_assert(trav != 3 || fmt % 10 == 0, "wide groups: double values");
     constexpr bool f32 = (fmt % 10) == 1, split = fmt >= 10;
     if constexpr (trav == 2)
       wave_engine_banded<f32, split>(a, epi);
+    else if constexpr (trav == 3)
+      wave_engine<1, f32, true, split, Epi, false, false, QSW_UNROLL1_WIDE>(a, epi);
     else
       wave_engine<1, f32, trav == 1, split>(a, epi);
   }
@@ -3237,6 +3257,8 @@ hipError_t launch_to_c64(float2 *dst, const double2 *src, int64_t n, hipStream_t
     case 201: CALL(201); break;           \
     case 210: CALL(210); break;           \
     case 211: CALL(211); break;           \
+    case 300: CALL(300); break;           \
+    case 310: CALL(310); break;           \
     case 3: CALL(3); break;               \
     case 4: CALL(4); break;               \
     case 8: CALL(8); break;               \
@@ -3246,9 +3268,10 @@ hipError_t launch_to_c64(float2 *dst, const double2 *src, int64_t n, hipStream_t
     default: return hipErrorInvalidValue; \
   }
 
-// Dynamic LDS of a product launch: the staged rho-row for engines 100/101.
+// Dynamic LDS of a product launch: the staged rho-row for engines 1xx and
+// 3xx, the rows of an XCD band for 2xx.
 inline size_t stage_bytes(int engine, const SpmvArgs &a) {
-  if (engine >= 200) {
+  if (engine >= 200 && engine < 300) {
     const int bw = a.N / 64 / 8;
     return (size_t)(bw >= 4 ? 1 : 4 / bw) * a.N * sizeof(double2);
   }

@@ -88,6 +88,10 @@ constexpr int32_t kGlobDiagFirst = 1 << 30;
 constexpr int32_t kGlobMask = kGlobDiagFirst - 1;
 constexpr int kWavePad = 64;  // zero entries after the wave-jagged arrays (reads past a block's end)
 constexpr size_t kStageMaxBytes = 32768;  // largest LDS-staged rho-row (N <= 2048)
+// Stored entries per row (on average) from which a staged handle takes the
+// wide-group traversal (engine 300): the 1024-vertex benchmark operator has
+// 21, the complete graph of 400 vertices about 740.
+constexpr int64_t kWideRowEntries = 128;
 
 // The wave layout stores each entry's column as its offset from the entry's
 // row (column - row), so that blocks whose rows have the same pattern and

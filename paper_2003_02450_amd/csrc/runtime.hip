@@ -1462,6 +1462,12 @@ qsw_status_t build_common(std::shared_ptr<Assembler> src, double omega, hipStrea
       h->engine = 200;
       h->grid = banded_grid(h->grid);
     }
+    // long rows (at least kWideRowEntries stored entries per row on average)
+    // take wide groups at four waves per SIMD (QSW_WIDE=1 always, 0 never)
+    const int wide = env_int("QSW_WIDE", -1);
+    if (stage && h->engine == 100 &&
+        (wide > 0 || (wide < 0 && h->n > 0 && h->wentries >= kWideRowEntries * h->n)))
+      h->engine = 300;
     if (eng == 3) {
       h->engine = 3;
       h->grid = L.grid;
@@ -2497,7 +2503,7 @@ qsw_status_t qsw_superop_autotune(qsw_superop_t h, void *hip_stream, qsw_tuning_
     std::lock_guard<std::mutex> lk(mu);
     auto it = cache.find(key);
     if (it != cache.end()) {
-      h->engine = it->second.staged == 2 ? 200 : (it->second.staged ? 100 : 0);
+      h->engine = 100 * it->second.staged;
       h->grid = it->second.grid;
       if (out) {
         *out = it->second;
@@ -2527,7 +2533,14 @@ qsw_status_t qsw_superop_autotune(qsw_superop_t h, void *hip_stream, qsw_tuning_
   qsw_tuning_t best{};
   best.us_per_product = 1e300;
   hipError_t err = hipSuccess;
-  for (int st = can_stage ? (banded_ok(h->N) ? 2 : 1) : 0; st >= 0 && err == hipSuccess; --st) {
+  // traversals: wide groups (double values), XCD bands, staged, plain
+  std::vector<int> trav;
+  if (can_stage && h->prec == QSW_PREC_DOUBLE) trav.push_back(3);
+  if (can_stage && banded_ok(h->N)) trav.push_back(2);
+  if (can_stage) trav.push_back(1);
+  trav.push_back(0);
+  for (size_t ti = 0; ti < trav.size() && err == hipSuccess; ++ti) {
+    const int st = trav[ti];
     for (int mul : {1, 2, 4, 8}) {
       const int64_t wgs = (h->nwb + kBlockThreads / 64 - 1) / (kBlockThreads / 64);
       int grid = (int)std::max<int64_t>(1, std::min<int64_t>(wgs, (int64_t)mul * resident));
@@ -2541,8 +2554,7 @@ qsw_status_t qsw_superop_autotune(qsw_superop_t h, void *hip_stream, qsw_tuning_
       a.x = x;
       a.y = y;
       a.alpha = 1.0;
-      const int engine = (st == 2 ? 200 : (st ? 100 : 0)) + (h->split ? 10 : 0) +
-                         (h->prec != QSW_PREC_DOUBLE ? 1 : 0);
+      const int engine = 100 * st + (h->split ? 10 : 0) + (h->prec != QSW_PREC_DOUBLE ? 1 : 0);
       if ((err = launch_spmv(a, engine, grid, s)) != hipSuccess) break;  // warm-up
       if ((err = hipEventRecord(e0, s)) != hipSuccess) break;
       const int reps = 5;
@@ -2562,7 +2574,7 @@ qsw_status_t qsw_superop_autotune(qsw_superop_t h, void *hip_stream, qsw_tuning_
   }
   cleanup();
   if (err != hipSuccess) return status_of(err);
-  h->engine = best.staged == 2 ? 200 : (best.staged ? 100 : 0);
+  h->engine = 100 * best.staged;
   h->grid = best.grid;
   {
     std::lock_guard<std::mutex> lk(mu);

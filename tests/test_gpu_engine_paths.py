@@ -10,6 +10,9 @@ LDS) against it and against the oracle.
 * N = 2100 (beyond the LDS stage): the unstaged wave layout and the CSR
   stream engine, two independent product paths, agree to rounding; every
   point keeps the trace and is Hermitian.
+* Wide groups (QSW_WIDE=1, engine 300: more positions per group at fewer
+  waves per SIMD, taken by default for long rows): only the grouping of a
+  row's positions changes, so the results equal the default's bit for bit.
 """
 import numpy as np
 import pytest
@@ -74,3 +77,30 @@ def test_beyond_stage_two_engines_agree(monkeypatch):
         assert np.abs(wave[k] - wave[k].conj().T).max() <= 1e-14
     # the walk has left vertex 0
     assert wave[-1][0, 0].real < 1.0 - 1e-3
+
+
+@pytest.mark.parametrize("N,k,omega,dense", [(300, 4, 0.4, False), (1024, 3, 0.5, False),
+                                              (64, 0, 0.3, True)])
+def test_wide_groups_equal_default(monkeypatch, N, k, omega, dense):
+    if dense:
+        rng = np.random.Generator(np.random.PCG64(931))
+        g = workloads.complete_digraph(N, rng)
+        rho0 = workloads.random_density(N, rng, rank=2)
+        wl = workloads.Workload("complete64", g, omega, "laplacian", "transition", False, rho0,
+                                0.0, 0.05, 3)
+    else:
+        wl = random_workload(N, k, omega, 940 + N, n_steps=3, dt=0.6)
+    ref = _run_with(monkeypatch, wl, QSW_WIDE="0")
+    got = _run_with(monkeypatch, wl, QSW_WIDE="1")
+    assert np.isfinite(ref).all()
+    assert np.array_equal(ref, got)
+    # the engine each takes, and the default for long rows
+    monkeypatch.setenv("QSW_WIDE", "1")
+    op = build_gpu(wl)
+    monkeypatch.delenv("QSW_WIDE")
+    assert op.info()["engine"] == 310
+    op.close()
+    op = build_gpu(wl)
+    per_row = op.info()["stream_entries"] / op.info()["n"]
+    assert op.info()["engine"] == (310 if per_row >= 128 else 110)
+    op.close()
