@@ -3599,6 +3599,8 @@ int resident_workgroups(int which) {
   if (which == 1)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, spmm2_kernel<true, true>, kBlock,
                                                      kStageMaxBytes);
+  else if (which == 2)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, term_kernel<3>, kBlock, 0);
   else
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, term_kernel<0>, kBlock, 0);
   if (e != hipSuccess || per < 1) per = 1;

@@ -469,8 +469,9 @@ hipError_t launch_swap_pairs(double2 *dst, const double2 *src, int64_t n, hipStr
 hipError_t launch_topk(const double *h, int64_t n, int K, int grid, double *cand_v, int64_t *cand_i,
                        double *out_v, int64_t *out_i, hipStream_t s);
 
-// Workgroups of the stream kernels that fit on the device at once
-// (which = 0: single right-hand side, 1: two).
+// Workgroups of the product kernels that fit on the device at once
+// (which = 0: wave layout, single right-hand side, 1: two; 2: the CSR
+// stream engine).
 int resident_workgroups(int which);
 hipError_t launch_batch_control(const BatchArgs &a, hipStream_t s);
 // The work kernel of the walks with double (p32 false) or single-precision

@@ -138,9 +138,13 @@ namespace {
 
 // Row blocks of the stream engine for one CSR: block budget B entries so that
 // a block (whose rows start before the next multiple of B) never exceeds the
-// LDS stage of `cap` entries when the longest row is at most cap/2; workgroup count from the
-// device's resident capacity, a multiple of 8 so that runs of blocks map to
-// one XCD each.
+// LDS stage of `cap` entries when the longest row is at most cap/2.  The
+// workgroups, a multiple of 8 so that runs of blocks map to one XCD each,
+// take equal runs of blocks in at most two rounds of the stream kernel's own
+// resident workgroups (`resident`; QSW_CSR_GRID overrides the two rounds).
+// Rounds that end part-full leave a tail: on the 1024-vertex operator (21808
+// blocks, 1024 resident) a product took 295 us at 992 workgroups, 291 at
+// 1984, 365 at 1456, 328 at 1680, 333 at 2424 and 305-309 at 2728-7272.
 struct Layout {
   int32_t *blk = nullptr;
   int32_t nblk = 0;
@@ -156,8 +160,9 @@ hipError_t make_layout(const int64_t *rp, int64_t n, int64_t nnz, int64_t maxrow
   if (e != hipSuccess) return e;
   e = launch_row_blocks(rp, n, B, L.blk, nblk, s);
   if (e != hipSuccess) return e;
-  int64_t G = std::max(8, resident / 8 * 8);
+  int64_t G = std::max(8, 2 * resident / 8 * 8);
   G = std::min<int64_t>(G, env_int("QSW_GRID", (int)G));
+  G = std::max(1, env_int("QSW_CSR_GRID", (int)G));
   if (G > nblk) G = nblk;
   if (G < 1) G = 1;
   const int64_t bpw = (nblk + G - 1) / G;
@@ -1420,7 +1425,8 @@ qsw_status_t build_common(std::shared_ptr<Assembler> src, double omega, hipStrea
   const int resident1 = resident_workgroups(0);
   {
     Layout L;
-    hipError_t le = make_layout(h->row_ptr, n, h->nnz, maxrow, kCap, resident1, s, L);
+    hipError_t le =
+        make_layout(h->row_ptr, n, h->nnz, maxrow, kCap, resident_workgroups(2), s, L);
     if (le != hipSuccess) {
       dfree(L.blk);
       return fail(status_of(le));

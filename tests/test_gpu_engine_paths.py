@@ -13,6 +13,8 @@ LDS) against it and against the oracle.
 * Wide groups (QSW_WIDE=1, engine 300: more positions per group at fewer
   waves per SIMD, taken by default for long rows): only the grouping of a
   row's positions changes, so the results equal the default's bit for bit.
+* The CSR stream engine's workgroup count (QSW_CSR_GRID) only changes which
+  workgroup takes which run of row blocks: the same results bit for bit.
 """
 import numpy as np
 import pytest
@@ -104,3 +106,12 @@ def test_wide_groups_equal_default(monkeypatch, N, k, omega, dense):
     per_row = op.info()["stream_entries"] / op.info()["n"]
     assert op.info()["engine"] == (310 if per_row >= 128 else 110)
     op.close()
+
+
+@pytest.mark.parametrize("grid", ["1", "24"])
+def test_stream_engine_grid_changes_nothing(monkeypatch, grid):
+    wl = random_workload(300, 4, 0.25, 1210, dephasing=True, n_steps=3, dt=0.6)
+    ref = _run_with(monkeypatch, wl, QSW_ENGINE="3")
+    got = _run_with(monkeypatch, wl, QSW_ENGINE="3", QSW_CSR_GRID=grid)
+    assert np.isfinite(ref).all()
+    assert np.array_equal(ref, got)
