@@ -1065,6 +1065,8 @@ int wave_grid(int64_t nwb, int resident) {
   // (4096 quads) a pass took 104.7 ms at 2048 workgroups (two quads each),
   // 106.4 at 2560 (an uneven split), 111.5 at 3584 and 109.8 at 4096 (one
   // quad each); single-precision products 58.1, 59.2, 68.2 and 69.6 ms.
+  // Later kernels: 91.5 ms at 2048, 94.5 at 1024 (four quads each), 107.6
+  // at 1366 (three) and 101.6 at 4096, the same results bit for bit.
   int64_t cap = 2 * (int64_t)std::max(resident, 1);
   cap = std::max<int64_t>(1, env_int("QSW_GRID", (int)cap));
   const int64_t q = (wgs + cap - 1) / cap;
