@@ -12,7 +12,8 @@ LDS) against it and against the oracle.
   point keeps the trace and is Hermitian.
 * Wide groups (QSW_WIDE=1, engine 300: more positions per group at fewer
   waves per SIMD, taken by default for long rows): only the grouping of a
-  row's positions changes, so the results equal the default's bit for bit.
+  row's positions changes, so the results equal the default's bit for bit,
+  and both agree with the oracle within the FP64 bar.
 * The CSR stream engine's workgroup count (QSW_CSR_GRID) only changes which
   workgroup takes which run of row blocks: the same results bit for bit.
 """
@@ -96,6 +97,9 @@ def test_wide_groups_equal_default(monkeypatch, N, k, omega, dense):
     got = _run_with(monkeypatch, wl, QSW_WIDE="1")
     assert np.isfinite(ref).all()
     assert np.array_equal(ref, got)
+    A = oracle_superop(wl)
+    orc, _ = expmv.propagate(A, wl.rho0, wl.t0, wl.dt, wl.n_steps)
+    assert np.abs(got - orc).max() <= 1e-10
     # the engine each takes, and the default for long rows
     monkeypatch.setenv("QSW_WIDE", "1")
     op = build_gpu(wl)
